@@ -1,0 +1,197 @@
+"""Seeded synthetic inputs shaped like the paper's workloads.
+
+This module holds no arithmetic of the method itself: only a counter-based
+random generator (SplitMix64, Steele, Lea & Flood 2014), uniform random unit
+quaternions (Shoemake, Graphics Gems III, 1992), random sequential addition of
+non-overlapping particles, and the configuration dictionaries of the
+workloads.  Both the HIP path's tests and the CPU oracle's tests draw their
+inputs from here.
+
+A configuration is a plain dict (lattice units, dx = dt = 1) and a particle set
+a dict of numpy arrays: shape (n,) int32 0 sphere / 1 ellipsoid, semi (n,3),
+dens (n,) density ratio, pos (n,3), quat (n,4) w,x,y,z, vel (n,3),
+omega (n,3), fixed (n,) uint8.
+"""
+import math
+
+import numpy as np
+
+_GOLDEN = 0x9E3779B97F4A7C15
+_M1 = 0xBF58476D1CE4E5B9
+_M2 = 0x94D049BB133111EB
+_MASK = (1 << 64) - 1
+
+
+class SplitMix64:
+    """SplitMix64 stream; uniform doubles from the top 53 bits."""
+
+    def __init__(self, seed):
+        self.state = int(seed) & _MASK
+
+    def next_u64(self, n=None):
+        if n is None:
+            self.state = (self.state + _GOLDEN) & _MASK
+            z = self.state
+            z = ((z ^ (z >> 30)) * _M1) & _MASK
+            z = ((z ^ (z >> 27)) * _M2) & _MASK
+            return z ^ (z >> 31)
+        idx = np.arange(1, n + 1, dtype=np.uint64)
+        with np.errstate(over="ignore"):
+            z = np.uint64(self.state) + idx * np.uint64(_GOLDEN)
+            z = (z ^ (z >> np.uint64(30))) * np.uint64(_M1)
+            z = (z ^ (z >> np.uint64(27))) * np.uint64(_M2)
+            z = z ^ (z >> np.uint64(31))
+        self.state = (self.state + n * _GOLDEN) & _MASK
+        return z
+
+    def uniform(self, n=None):
+        if n is None:
+            return (self.next_u64() >> 11) * (1.0 / 9007199254740992.0)
+        return (self.next_u64(n) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+def shoemake_quaternions(rng, n):
+    """Uniform random unit quaternions (w, x, y, z), Shoemake's method."""
+    u = rng.uniform(3 * n).reshape(n, 3)
+    a = np.sqrt(1.0 - u[:, 0])
+    b = np.sqrt(u[:, 0])
+    t1 = 2.0 * math.pi * u[:, 1]
+    t2 = 2.0 * math.pi * u[:, 2]
+    return np.stack([b * np.cos(t2), a * np.sin(t1), a * np.cos(t1), b * np.sin(t2)], axis=1)
+
+
+# ---------------------------------------------------------------------------
+# contact-law parameter ratios at the paper's Poisson ratio 0.4999: the linear
+# law takes k_t/k_n = 3(1-nu)/(2-nu) and gamma_t/gamma_n = sqrt(2(1-nu)/(2-nu))
+# ---------------------------------------------------------------------------
+NU = 0.4999
+KT_RATIO = 3.0 * (1.0 - NU) / (2.0 - NU)
+GT_RATIO = math.sqrt(2.0 * (1.0 - NU) / (2.0 - NU))
+
+
+def rsa_spheres(rng, n, radii, box, periodic, region_lo=None, region_hi=None, gap=1.0,
+                wall_gap=1.0, max_attempts=1_000_000):
+    """Random sequential addition of spheres with a surface gap.
+
+    radii: (n,) array drawn beforehand; box: (3,) extents; periodic: 3 bools.
+    Centres are uniform in [region_lo, region_hi] shrunk by radius + wall_gap on
+    walled axes.  Returns (m, 3) positions for the first m <= n spheres placed.
+    """
+    box = np.asarray(box, dtype=np.float64)
+    lo = np.zeros(3) if region_lo is None else np.asarray(region_lo, np.float64)
+    hi = box.copy() if region_hi is None else np.asarray(region_hi, np.float64)
+    rmax = float(np.max(radii)) if len(radii) else 1.0
+    h = 2.0 * rmax + gap
+    ncell = np.maximum(1, np.floor(box / h).astype(int))
+    hcell = box / ncell
+    grid = {}
+    pos = np.zeros((n, 3))
+    placed = 0
+    attempts = 0
+    for k in range(n):
+        r = float(radii[k])
+        ok = False
+        while attempts < max_attempts:
+            attempts += 1
+            u = rng.uniform(3)
+            c = np.empty(3)
+            for a in range(3):
+                l, hh = lo[a], hi[a]
+                if not periodic[a]:
+                    l = max(l, r + wall_gap)
+                    hh = min(hh, box[a] - r - wall_gap)
+                c[a] = l + (hh - l) * u[a]
+            ci = np.floor(c / hcell).astype(int)
+            clash = False
+            for dz in (-1, 0, 1):
+                for dy in (-1, 0, 1):
+                    for dx in (-1, 0, 1):
+                        key = [ci[0] + dx, ci[1] + dy, ci[2] + dz]
+                        skip = False
+                        for a in range(3):
+                            if periodic[a]:
+                                key[a] %= ncell[a]
+                            elif key[a] < 0 or key[a] >= ncell[a]:
+                                skip = True
+                        if skip:
+                            continue
+                        for j in grid.get(tuple(key), ()):
+                            d = c - pos[j]
+                            for a in range(3):
+                                if periodic[a]:
+                                    d[a] -= box[a] * round(d[a] / box[a])
+                            if np.dot(d, d) < (r + radii[j] + gap) ** 2:
+                                clash = True
+                                break
+                        if clash:
+                            break
+                    if clash:
+                        break
+                if clash:
+                    break
+            if not clash:
+                ok = True
+                break
+        if not ok:
+            break
+        pos[k] = c
+        key = tuple(int(v) % int(m) for v, m in zip(np.floor(c / hcell).astype(int), ncell))
+        grid.setdefault(key, []).append(k)
+        placed += 1
+    return pos[:placed]
+
+
+def _periodic(bc):
+    return [bc[2 * a] == "periodic" for a in range(3)]
+
+
+def base_config(n, tau, **kw):
+    cfg = dict(n=tuple(n), tau=tau, rho0=1.0, bc=["periodic"] * 6, wall_u=[[0.0] * 3] * 6,
+               body_force=[0.0] * 3, kolm_amp=0.0, kolm_axis=1, kolm_dir=0,
+               gravity=[0.0] * 3, precision="fp64", sf_method="subdivision", sf_subdiv=10,
+               fluid_on=True, dem_on=True, n_sub=0, dem_cell=0.0, kn=1e3, restitution=0.8,
+               mu=0.3, kt_ratio=KT_RATIO, gt_ratio=GT_RATIO, max_solids=2)
+    cfg.update(kw)
+    return cfg
+
+
+def spheres(pos, radii, dens, vel=None, omega=None, fixed=None):
+    n = len(pos)
+    radii = np.broadcast_to(np.asarray(radii, np.float64), (n,))
+    return dict(shape=np.zeros(n, np.int32), semi=np.repeat(radii[:, None], 3, axis=1).copy(),
+                dens=np.broadcast_to(np.asarray(dens, np.float64), (n,)).copy(),
+                pos=np.asarray(pos, np.float64).reshape(n, 3).copy(),
+                quat=np.tile([1.0, 0.0, 0.0, 0.0], (n, 1)),
+                vel=np.zeros((n, 3)) if vel is None else np.asarray(vel, np.float64).reshape(n, 3),
+                omega=np.zeros((n, 3)) if omega is None else np.asarray(omega, np.float64).reshape(n, 3),
+                fixed=np.zeros(n, np.uint8) if fixed is None else np.asarray(fixed, np.uint8))
+
+
+# ---------------------------------------------------------------------------
+# workloads
+# ---------------------------------------------------------------------------
+def settling_sphere(precision="fp64", n=32, steps=200):
+    """Plain method, one sphere R=4 at the box centre, density ratio 2, settling
+    under gravity 1e-5 on a 32^3 periodic lattice, tau = 0.8, 200 steps."""
+    cfg = base_config((n, n, n), 0.8, gravity=[0.0, 0.0, -1e-5], precision=precision, n_sub=1)
+    c = n / 2.0
+    parts = spheres([[c, c, c]], 4.0, 2.0)
+    return cfg, parts, dict(workload="settling_sphere_32", steps=steps)
+
+
+def couette_suspension(precision="fp32", n=128, nsph=500, radius=5.0, seed=1001, steps=1000):
+    """Bounded Couette shear: n^3 lattice, moving walls beyond node layers 0 and
+    n-1 at -/+0.02 in x, periodic x,y, tau = 0.7; nsph spheres of radius 5 at
+    seeded non-overlapping positions, density ratio 1.5; linear spring-dashpot
+    k_n = 1e3, restitution 0.8, Coulomb mu = 0.3."""
+    bc = ["periodic", "periodic", "periodic", "periodic", "moving", "moving"]
+    wu = [[0.0] * 3 for _ in range(6)]
+    wu[4] = [-0.02, 0.0, 0.0]
+    wu[5] = [0.02, 0.0, 0.0]
+    cfg = base_config((n, n, n), 0.7, bc=bc, wall_u=wu, precision=precision, kn=1e3,
+                      restitution=0.8, mu=0.3)
+    rng = SplitMix64(seed)
+    radii = np.full(nsph, radius)
+    pos = rsa_spheres(rng, nsph, radii, (n, n, n), _periodic(bc))
+    parts = spheres(pos, radius, 1.5)
+    return cfg, parts, dict(workload=f"couette_{n}^3_{len(pos)}_spheres", steps=steps)
