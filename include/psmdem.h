@@ -1,0 +1,219 @@
+/*
+ * psmdem.h -- C ABI of the MI355X (gfx950) coupled LBM-PSM-DEM time step.
+ *
+ * The library advances a fully coupled lattice Boltzmann / discrete element
+ * system as formulated in arXiv 2512.04997 ("LEDDS"):
+ *   - D3Q19 BGK collide-and-stream (Sec. 2.3, Eqs. collAndStream, BGK,
+ *     equilibrium) with partially-saturated-method weighting (Sec. 2.4, Eqs.
+ *     psm1, lbePS, bk, btot), halfway and moving-wall bounce-back (Sec. 2.3);
+ *   - solid fractions of spheres and ellipsoids by subdivision or, for
+ *     spheres, by the distance formula (Sec. 2.4, Eq. naiveSolidFrac);
+ *   - hydrodynamic force and torque per particle (Sec. 2.4, Eqs. forceSF,
+ *     torqueSF);
+ *   - DEM: uniform-grid cell list and candidate pairs (Sec. 3.2.1), linear
+ *     spring-dashpot contacts with Coulomb friction and tangential history
+ *     (Sec. 2.1, Eqs. spring_dashpot_easy, fnScal, relative_velocity,
+ *     trangential-history, coulombCoeff, torque), walls as static particles,
+ *     ellipsoid contact by iterated equivalent spheres (Eq. local-curvature);
+ *   - Verlet integration of translation and rotation (Sec. 2.2, Eqs.
+ *     advance-r .. advance-omega) with DEM sub-stepping (Sec. 2.3);
+ *   in the coupled order of the workflow figure (Sec. 3.2).
+ *
+ * Units are lattice units (dx = dt = 1).  Node (x,y,z) has centre
+ * (x+1/2, y+1/2, z+1/2); the domain is [0,nx) x [0,ny) x [0,nz); walls lie on
+ * the planes 0 and n of walled axes.  D3Q19 order: 0 rest, 1..9 =
+ * (1,0,0),(0,1,0),(0,0,1),(1,1,0),(1,-1,0),(1,0,1),(1,0,-1),(0,1,1),(0,1,-1),
+ * 10..18 their negatives.  Cell index = x + nx*(y + ny*z).  Quaternions are
+ * (w,x,y,z) and rotate body-frame vectors into the world frame.
+ *
+ * Conventions of every call:
+ *   - all functions return psmdem_status (0 = OK, < 0 = error) and never
+ *     abort; psmdem_last_error() returns a thread-local message;
+ *   - host pointers are plain host memory owned by the caller; inputs are
+ *     copied before the call returns; outputs are written before it returns;
+ *   - device memory is owned by the library (allocated through the optional
+ *     allocator callback, else hipMalloc) and freed by psmdem_destroy;
+ *   - work is enqueued on the HIP stream given at creation (NULL = the
+ *     default stream); psmdem_step is asynchronous, every read_* call
+ *     synchronises the stream first.
+ */
+#ifndef PSMDEM_H
+#define PSMDEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PSMDEM_OK = 0,
+    PSMDEM_E_INVALID = -1,   /* bad argument or configuration */
+    PSMDEM_E_NOMEM = -2,     /* device allocation failed */
+    PSMDEM_E_CAPACITY = -3,  /* a device list outgrew its capacity; results of the step are invalid */
+    PSMDEM_E_UNSTABLE = -4,  /* non-finite or non-positive density detected (reserved) */
+    PSMDEM_E_HIP = -5,       /* a HIP runtime call failed */
+    PSMDEM_E_STATE = -6,     /* call not valid in the current state */
+    PSMDEM_E_NODEVICE = -7   /* no gfx950 device available */
+} psmdem_status;
+
+typedef enum { PSMDEM_BC_PERIODIC = 0, PSMDEM_BC_NOSLIP = 1, PSMDEM_BC_MOVING = 2 } psmdem_bc;
+
+/* Population storage.  All modes store shifted populations f_i - w_i.
+ * FP64: stored and computed in double.  FP32: float storage and arithmetic.
+ * BF16 / FP16: 16-bit storage (round to nearest even), float arithmetic.
+ * Particle kinematics and force/torque sums are double in every mode. */
+typedef enum {
+    PSMDEM_FP64 = 0,
+    PSMDEM_FP32 = 1,
+    PSMDEM_BF16_SHIFTED = 2,
+    PSMDEM_FP16_SHIFTED = 3
+} psmdem_precision;
+
+typedef enum { PSMDEM_SF_SUBDIVISION = 0, PSMDEM_SF_DISTANCE = 1 } psmdem_sf;
+typedef enum { PSMDEM_SPHERE = 0, PSMDEM_ELLIPSOID = 1 } psmdem_shape;
+
+typedef struct {
+    int32_t nx, ny, nz;         /* lattice extents (>= 1) */
+    double tau;                 /* BGK relaxation time, tau = 3 nu + 1/2 (Eq. tau), > 1/2 */
+    double rho0;                /* reference density (1): initial density, wall density */
+    int32_t bc[6];              /* faces -x,+x,-y,+y,-z,+z: psmdem_bc; both faces of an axis
+                                   periodic or neither */
+    double wall_u[6][3];        /* wall velocity of PSMDEM_BC_MOVING faces */
+    double body_force[3];       /* constant fluid force density (Guo forcing) */
+    double kolm_amp;            /* Kolmogorov forcing: component kolm_dir of the force
+                                   density gets kolm_amp sin(2 pi (c + 1/2) / n_axis),
+                                   c the coordinate along kolm_axis */
+    int32_t kolm_axis, kolm_dir;
+    double gravity[3];          /* acceleration on particles; F_ext = m (1 - rho0/rho_p) g */
+    int32_t precision;          /* psmdem_precision */
+    int32_t sf_method;          /* psmdem_sf (distance: spheres only) */
+    int32_t sf_subdiv;          /* subdivision samples per direction (10), 1..32 */
+    int32_t fluid_on, dem_on;   /* LBM and DEM usable independently or coupled */
+    int32_t n_sub;              /* DEM substeps per LBM step; 0 = automatic:
+                                   max(1, ceil(20 / t_c)) from the stiffest contact */
+    double dem_cell;            /* DEM grid spacing; 0 = automatic (>= 1.1 x largest diameter) */
+    double kn;                  /* normal stiffness of the linear law */
+    double restitution;         /* coefficient of restitution in (0, 1] */
+    double mu;                  /* Coulomb friction coefficient */
+    double kt_ratio, gt_ratio;  /* k_t / k_n and gamma_t / gamma_n */
+    int32_t max_solids;         /* solids kept per fluid cell (2), 1..4 */
+    int64_t pair_capacity;      /* candidate-pair capacity; 0 = automatic */
+} psmdem_desc;
+
+typedef struct {
+    int32_t n;                    /* number of particles (may be 0) */
+    const int32_t* shape;         /* [n] psmdem_shape */
+    const double* semi_axes;      /* [3n] radius (sphere: first entry) or semi-axes */
+    const double* density_ratio;  /* [n] rho_p / rho0 */
+    const double* pos;            /* [3n] centres */
+    const double* quat;           /* [4n] orientation (w,x,y,z); NULL = identity */
+    const double* vel;            /* [3n] NULL = 0 */
+    const double* omega;          /* [3n] world-frame angular velocity; NULL = 0 */
+    const uint8_t* fixed;         /* [n] 1 = velocities prescribed (not integrated); NULL = 0 */
+} psmdem_particles;
+
+/* Optional allocator: returns device memory of at least `bytes` bytes, or
+ * NULL.  Used for every device allocation of a domain. */
+typedef void* (*psmdem_alloc_fn)(size_t bytes, void* ctx);
+typedef void (*psmdem_free_fn)(void* ptr, size_t bytes, void* ctx);
+
+typedef struct psmdem_domain psmdem_domain;
+
+typedef struct {
+    int64_t n_pairs;         /* candidate pairs of the last substep */
+    int64_t n_contacts;      /* pairs with positive overlap */
+    int64_t n_registrations; /* DEM cell registrations */
+    int64_t n_entries;       /* (cell, particle) solid-fraction entries with beta > 0 */
+    int64_t n_dropped;       /* entries beyond max_solids in a cell (dropped, Sec. 3.2.3 limit) */
+    int64_t n_solid_tiles;   /* lattice tiles holding any particle */
+    int64_t step;            /* coupled steps taken */
+    int64_t flags;           /* bit 0 pair capacity, bit 1 tile particle list, bit 2 neighbour list */
+} psmdem_counters_t;
+
+typedef struct {
+    int32_t n_sub;          /* DEM substeps per coupled step */
+    int32_t dem_cells[3];   /* DEM grid */
+    double dem_h[3];        /* DEM cell size */
+    int64_t n_cells;        /* lattice cells */
+    int32_t n_particles;
+    int32_t precision;
+    int64_t device_bytes;   /* device memory held by the domain */
+    int32_t tile[3];        /* lattice tile used by the LBM and voxelisation kernels */
+} psmdem_info_t;
+
+/* --- life cycle ----------------------------------------------------------- */
+
+/* Creates a domain: validates the description, allocates device memory,
+ * initialises f = f^eq(rho0, 0) (Sec. 2.3), and evaluates the initial DEM
+ * forces (a(0) = (F_dem + F_ext)/m, zero tangential history).  stream is a
+ * hipStream_t (NULL: default stream).  alloc/free may be NULL. */
+psmdem_status psmdem_create(const psmdem_desc* desc, const psmdem_particles* parts, void* stream,
+                            psmdem_alloc_fn alloc, psmdem_free_fn free_fn, void* alloc_ctx,
+                            psmdem_domain** out);
+void psmdem_destroy(psmdem_domain* d);
+
+/* Enqueues n coupled steps (one LBM step with n_sub DEM substeps each). */
+psmdem_status psmdem_step(psmdem_domain* d, int64_t n);
+/* Waits for the stream and reports device-side flags (PSMDEM_E_CAPACITY). */
+psmdem_status psmdem_sync(psmdem_domain* d);
+
+/* --- stages (one stage on the current state; for per-stage checks) ------- */
+typedef enum {
+    PSMDEM_STAGE_LISTS = 0,     /* cell registrations and candidate pairs from current positions */
+    PSMDEM_STAGE_VOXELIZE = 1,  /* solid fractions and per-cell slots from current positions */
+    PSMDEM_STAGE_LBM = 2,       /* one LBM-PSM step with current slots and predicted velocities,
+                                   and the hydrodynamic force and torque */
+    PSMDEM_STAGE_CONTACTS = 3   /* contact forces with the current pair list and history as the
+                                   previous list, predicted velocities, one substep of history */
+} psmdem_stage_t;
+psmdem_status psmdem_stage(psmdem_domain* d, int32_t stage);
+
+/* --- state access (all synchronise the stream) ---------------------------- */
+/* f: [19 * n_cells] double, f[i * n_cells + cell], pre-collision populations at
+ * the current time in the canonical layout (the in-place storage is decoded). */
+psmdem_status psmdem_read_populations(psmdem_domain* d, double* f);
+psmdem_status psmdem_write_populations(psmdem_domain* d, const double* f);
+/* rho: [n_cells], u: [3 n_cells] (with forcing, u includes the half-force shift) */
+psmdem_status psmdem_read_fields(psmdem_domain* d, double* rho, double* u);
+/* particle arrays [3n] (quat [4n]); any pointer may be NULL */
+psmdem_status psmdem_read_particles(psmdem_domain* d, double* pos, double* quat, double* vel,
+                                   double* omega, double* acc, double* alpha, double* f_hyd,
+                                   double* m_hyd, double* f_dem, double* m_dem);
+psmdem_status psmdem_write_particles(psmdem_domain* d, const double* pos, const double* quat,
+                                    const double* vel, const double* omega, const double* acc,
+                                    const double* alpha, const double* f_hyd, const double* m_hyd);
+/* predicted velocities v^p, w^p of the last substep ([3n] each) */
+psmdem_status psmdem_read_predicted(psmdem_domain* d, double* vp, double* wp);
+psmdem_status psmdem_write_predicted(psmdem_domain* d, const double* vp, const double* wp);
+/* sorted candidate pairs (i << 32 | j; j >= n for wall face j - n) and their
+ * tangential history [3 cap]; *n receives the count (may exceed cap) */
+psmdem_status psmdem_read_pairs(psmdem_domain* d, int64_t cap, uint64_t* keys, double* hist,
+                               int64_t* n);
+psmdem_status psmdem_write_pairs(psmdem_domain* d, int64_t n, const uint64_t* keys,
+                                const double* hist);
+/* pairs in contact with force on i [3], torque on i [3], torque on j [3] */
+psmdem_status psmdem_read_contacts(psmdem_domain* d, int64_t cap, uint64_t* keys, double* force,
+                                  double* m_i, double* m_j, int64_t* n);
+/* sorted DEM cell registrations (cell << 32 | pid) */
+psmdem_status psmdem_read_cells(psmdem_domain* d, int64_t cap, uint64_t* keys, int64_t* n);
+/* kept solid slots sorted by (cell, pid) with their solid fraction beta */
+psmdem_status psmdem_read_solid(psmdem_domain* d, int64_t cap, uint32_t* cell, uint32_t* pid,
+                               double* beta, int64_t* n);
+psmdem_status psmdem_counters(psmdem_domain* d, psmdem_counters_t* out);
+psmdem_status psmdem_info(psmdem_domain* d, psmdem_info_t* out);
+
+/* Average device time per launch of each kernel family over the last
+ * psmdem_step call when timing is on (HIP events on the domain stream). */
+psmdem_status psmdem_set_timing(psmdem_domain* d, int32_t on);
+psmdem_status psmdem_timing(psmdem_domain* d, int32_t which, double* avg_ms, int64_t* launches);
+typedef enum { PSMDEM_T_LBM = 0, PSMDEM_T_VOXEL = 1, PSMDEM_T_DEM = 2, PSMDEM_T_HYDRO = 3 } psmdem_timer;
+
+const char* psmdem_last_error(void);
+const char* psmdem_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -57,6 +57,7 @@ struct or_domain {
     double *semi, *dens, *mass, *inertia, *rb;
     double *pos, *q, *qold, *v, *w, *vp, *wp, *a, *al;
     double *fh, *mh, *fd, *md;
+    double *fh1, *mh1, *fd1, *md1; /* per-component sums of |summand| (parity scale) */
     /* DEM lists */
     int64_t nreg, cap_reg;
     uint64_t* reg;
@@ -225,6 +226,7 @@ or_domain* or_create(const or_desc* d, int32_t np, const int32_t* shape, const d
     ALLOC3(D->semi); ALLOC3(D->inertia); ALLOC3(D->pos); ALLOC3(D->v); ALLOC3(D->w);
     ALLOC3(D->vp); ALLOC3(D->wp); ALLOC3(D->a); ALLOC3(D->al); ALLOC3(D->fh); ALLOC3(D->mh);
     ALLOC3(D->fd); ALLOC3(D->md);
+    ALLOC3(D->fh1); ALLOC3(D->mh1); ALLOC3(D->fd1); ALLOC3(D->md1);
 #undef ALLOC3
     D->dens = (double*)xcalloc(np, sizeof(double));
     D->mass = (double*)xcalloc(np, sizeof(double));
@@ -316,6 +318,7 @@ void or_destroy(or_domain* D) {
     free(D->mh); free(D->fd); free(D->md); free(D->reg); free(D->pairs); free(D->hist);
     free(D->cF); free(D->cMi); free(D->cMj); free(D->incontact); free(D->slot_pid);
     free(D->slot_beta);
+    free(D->fh1); free(D->mh1); free(D->fd1); free(D->md1);
     free(D);
 }
 
@@ -659,7 +662,7 @@ void or_stage_lbm(or_domain* D) {
             }
         }
     }
-    for (int k = 0; k < 3 * D->np; ++k) { D->fh[k] = 0.0; D->mh[k] = 0.0; }
+    for (int k = 0; k < 3 * D->np; ++k) { D->fh[k] = 0.0; D->mh[k] = 0.0; D->fh1[k] = 0.0; D->mh1[k] = 0.0; }
     for (int64_t c = 0; c < N; ++c) {
         int s = 0;
         for (int u = 0; u < ms; ++u) {
@@ -668,6 +671,8 @@ void or_stage_lbm(or_domain* D) {
             for (int k = 0; k < 3; ++k) {
                 D->fh[3 * p + k] -= Pcell[(c * ms + s) * 3 + k];
                 D->mh[3 * p + k] -= Tcell[(c * ms + s) * 3 + k];
+                D->fh1[3 * p + k] += fabs(Pcell[(c * ms + s) * 3 + k]);
+                D->mh1[3 * p + k] += fabs(Tcell[(c * ms + s) * 3 + k]);
             }
             ++s;
         }
@@ -1077,7 +1082,7 @@ static void dem_contacts(or_domain* D, const double* vv, const double* ww, doubl
     double kn = D->d.kn;
     double kt = D->d.kt_ratio * kn;
     D->ncontacts = 0;
-    for (int k = 0; k < 3 * np; ++k) { D->fd[k] = 0.0; D->md[k] = 0.0; }
+    for (int k = 0; k < 3 * np; ++k) { D->fd[k] = 0.0; D->md[k] = 0.0; D->fd1[k] = 0.0; D->md1[k] = 0.0; }
     for (int64_t p = 0; p < D->npairs; ++p) {
         uint64_t key = D->pairs[p];
         int i = (int)(key >> 32), j = (int)(key & 0xffffffffu);
@@ -1162,11 +1167,15 @@ static void dem_contacts(or_domain* D, const double* vv, const double* ww, doubl
         for (int k = 0; k < 3; ++k) {
             D->fd[3 * i + k] += D->cF[3 * p + k];
             D->md[3 * i + k] += D->cMi[3 * p + k];
+            D->fd1[3 * i + k] += fabs(D->cF[3 * p + k]);
+            D->md1[3 * i + k] += fabs(D->cMi[3 * p + k]);
         }
         if (j < np)
             for (int k = 0; k < 3; ++k) {
                 D->fd[3 * j + k] -= D->cF[3 * p + k];
                 D->md[3 * j + k] += D->cMj[3 * p + k];
+                D->fd1[3 * j + k] += fabs(D->cF[3 * p + k]);
+                D->md1[3 * j + k] += fabs(D->cMj[3 * p + k]);
             }
     }
 }
@@ -1318,6 +1327,19 @@ static void coupled_step(or_domain* D) {
     D->step++;
 }
 
+/* contact forces of the current pair list, with that list and its history as
+ * the previous substep's, predicted velocities and one substep of history */
+void or_stage_contacts(or_domain* D) {
+    int64_t pn = D->npairs;
+    uint64_t* pk = (uint64_t*)xcalloc(pn, sizeof(uint64_t));
+    double* ph = (double*)xcalloc(3 * pn, sizeof(double));
+    memcpy(pk, D->pairs, pn * sizeof(uint64_t));
+    memcpy(ph, D->hist, 3 * pn * sizeof(double));
+    dem_contacts(D, D->vp, D->wp, D->dt, pk, ph, pn);
+    free(pk);
+    free(ph);
+}
+
 void or_step(or_domain* D, int64_t n) {
     for (int64_t s = 0; s < n; ++s) coupled_step(D);
 }
@@ -1376,6 +1398,14 @@ void or_set_particles(or_domain* D, const double* pos, const double* quat, const
     if (alpha) memcpy(D->al, alpha, n3);
     if (fh) memcpy(D->fh, fh, n3);
     if (mh) memcpy(D->mh, mh, n3);
+}
+
+void or_get_scales(const or_domain* D, double* fh1, double* mh1, double* fd1, double* md1) {
+    size_t n3 = 3 * (size_t)D->np * sizeof(double);
+    if (fh1) memcpy(fh1, D->fh1, n3);
+    if (mh1) memcpy(mh1, D->mh1, n3);
+    if (fd1) memcpy(fd1, D->fd1, n3);
+    if (md1) memcpy(md1, D->md1, n3);
 }
 
 void or_get_predicted(const or_domain* D, double* vp, double* wp) {

@@ -70,6 +70,9 @@ void or_set_particles(or_domain* D, const double* pos, const double* quat,
                       const double* vel, const double* omega, const double* acc,
                       const double* alpha, const double* fh, const double* mh);
 void or_get_predicted(const or_domain* D, double* vp, double* wp);
+/* per-component sums of |summand| of the last hydrodynamic and DEM sums: the
+ * scale against which force parity is measured */
+void or_get_scales(const or_domain* D, double* fh1, double* mh1, double* fd1, double* md1);
 int64_t or_get_pairs(const or_domain* D, int64_t cap, uint64_t* keys, double* hist);
 void or_set_pairs(or_domain* D, int64_t n, const uint64_t* keys, const double* hist);
 int64_t or_get_cells(const or_domain* D, int64_t cap, uint64_t* keys);
@@ -82,6 +85,7 @@ void or_counters(const or_domain* D, int64_t out[6]); /* pairs, contacts, entrie
 void or_stage_lists(or_domain* D);      /* cell registrations + candidate pairs from current positions */
 void or_stage_voxelize(or_domain* D);   /* solid fractions and slots from current positions */
 void or_stage_lbm(or_domain* D);        /* one LBM-PSM step with the current slots and v^p, w^p */
+void or_stage_contacts(or_domain* D);   /* contacts of the current list, its history as the previous */
 void or_set_predicted(or_domain* D, const double* vp, const double* wp);
 
 /* brute-force candidate pairs (all i<j with intersecting registrations), sorted */

@@ -59,6 +59,7 @@ def lib():
     L.or_get_particles.argtypes = [P] + [P] * 10
     L.or_set_particles.argtypes = [P] + [P] * 8
     L.or_get_predicted.argtypes = [P, P, P]
+    L.or_get_scales.argtypes = [P, P, P, P, P]
     L.or_set_predicted.argtypes = [P, P, P]
     L.or_get_pairs.argtypes = [P, C.c_int64, P, P]
     L.or_get_pairs.restype = C.c_int64
@@ -70,7 +71,7 @@ def lib():
     L.or_get_contacts.argtypes = [P, C.c_int64, P, P, P, P]
     L.or_get_contacts.restype = C.c_int64
     L.or_counters.argtypes = [P, P]
-    for n in ("or_stage_lists", "or_stage_voxelize", "or_stage_lbm"):
+    for n in ("or_stage_lists", "or_stage_voxelize", "or_stage_lbm", "or_stage_contacts"):
         getattr(L, n).argtypes = [P]
     L.or_brute_pairs.argtypes = [P, C.c_int64, P]
     L.or_brute_pairs.restype = C.c_int64
@@ -199,6 +200,12 @@ class OracleDomain:
                 for k in keys]
         lib().or_set_particles(self.h, *[_ptr(a) for a in arrs])
 
+    def scales(self):
+        """Per-particle sums of |summand| of F_hyd, M_hyd, F_dem, M_dem."""
+        out = {k: np.zeros((self.np, 3)) for k in ("f_hyd", "m_hyd", "f_dem", "m_dem")}
+        lib().or_get_scales(self.h, *[_ptr(out[k]) for k in ("f_hyd", "m_hyd", "f_dem", "m_dem")])
+        return out
+
     def predicted(self):
         vp = np.zeros((self.np, 3))
         wp = np.zeros((self.np, 3))
@@ -260,6 +267,9 @@ class OracleDomain:
 
     def stage_lbm(self):
         lib().or_stage_lbm(self.h)
+
+    def stage_contacts(self):
+        lib().or_stage_contacts(self.h)
 
     def brute_pairs(self):
         n = lib().or_brute_pairs(self.h, 0, None)

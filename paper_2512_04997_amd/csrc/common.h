@@ -1,0 +1,116 @@
+// common.h -- internal definitions of the gfx950 coupled LBM-PSM-DEM library.
+//
+// Device data layout (lattice units):
+//   populations  f[i * N + cell], shifted g_i = f_i - w_i, storage type S
+//                (double / float / bf16 bits / half), updated in place with the
+//                AA pattern (even steps read and write the own cell, odd steps
+//                read from and write to the neighbours);
+//   lattice tiles of TX x TY x TZ = 64 x 4 x 4 cells; a workgroup of 256 lanes
+//                owns one tile, one wave per x-row (64 cells, coalesced), four
+//                z-planes per lane;
+//   per-cell solid slots in tile-major order (tile * 1024 + local cell);
+//   particles    interleaved xyz double arrays [3 n], quaternions [4 n].
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "psmdem.h"
+
+#define PSM_TX 64
+#define PSM_TY 4
+#define PSM_TZ 4
+#define PSM_TILE (PSM_TX * PSM_TY * PSM_TZ)
+#define PSM_PMAX 128          // particles registered in one tile (LBM-PSM / voxelisation)
+#define PSM_MAXNB 96          // unique neighbours j > i of one particle
+#define PSM_SLOTS_MAX 4
+
+// device-side flag bits (psmdem_counters_t.flags)
+#define PSM_FLAG_PAIRS 1
+#define PSM_FLAG_TILE 2
+#define PSM_FLAG_NEIGH 4
+#define PSM_FLAG_VREG 8
+
+// ---------------------------------------------------------------------------
+// D3Q19 (Sec. 2.3): velocities, weights, opposite directions
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int d3q19_cx(int i) {
+    constexpr int v[19] = {0, 1, 0, 0, 1, 1, 1, 1, 0, 0, -1, 0, 0, -1, -1, -1, -1, 0, 0};
+    return v[i];
+}
+__host__ __device__ constexpr int d3q19_cy(int i) {
+    constexpr int v[19] = {0, 0, 1, 0, 1, -1, 0, 0, 1, 1, 0, -1, 0, -1, 1, 0, 0, -1, -1};
+    return v[i];
+}
+__host__ __device__ constexpr int d3q19_cz(int i) {
+    constexpr int v[19] = {0, 0, 0, 1, 0, 0, 1, -1, 1, -1, 0, 0, -1, 0, 0, -1, 1, -1, 1};
+    return v[i];
+}
+__host__ __device__ constexpr int d3q19_opp(int i) { return i == 0 ? 0 : (i <= 9 ? i + 9 : i - 9); }
+__host__ __device__ constexpr double d3q19_w(int i) {
+    return i == 0 ? 1.0 / 3.0 : (((i - 1) % 9) < 3 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+// ---------------------------------------------------------------------------
+// kernel argument blocks
+// ---------------------------------------------------------------------------
+struct GeoArgs {
+    int nx, ny, nz;
+    long long N;
+    int ntx, nty, ntz;
+    long long ntiles;
+    int periodic[3];
+    int bc[6];
+};
+
+struct PartArgs {          // particle state, all double
+    int np;
+    const int* shape;
+    const unsigned char* fixed;
+    double *semi, *mass, *inertia, *rb, *dens;
+    double *pos, *q, *qold, *v, *w, *vp, *wp, *a, *al;
+    double *fh, *mh, *fd, *md;
+    double *kin;           // [9 np]: position, v^p, w^p (read by the LBM-PSM kernel)
+};
+
+// tile registrations of particles (solid fractions and hydrodynamic partial sums)
+struct TileArgs {
+    int* tile_start;       // [ntiles + 1] exclusive offsets into tile_list
+    unsigned long long* tile_list;  // (pid << 32 | emission index), sorted by pid per tile
+    int* vcount;           // [np] tiles per particle
+    int* voff;             // [np + 1] emission offsets
+    int* vinv;             // [cap] emission index -> position in tile_list
+    long long cap;         // capacity of tile_list / vinv / partial
+    unsigned int* slot_lp; // [ntiles * 1024] byte k = local particle index of slot k (0xff none)
+    void* slot_B;          // [ms][ntiles * 1024] B_k in the compute type
+    double* partial;       // [cap][6] per (tile, particle): force then torque
+    double* slot_beta;     // [ms][ntiles * 1024] beta of kept slots (double, for read-back)
+};
+
+// device error flags and counters (one 64-bit word each)
+struct DevCounters {
+    unsigned long long flags;
+    unsigned long long entries;
+    unsigned long long dropped;
+    unsigned long long contacts;
+};
+
+// host helpers
+#define PSM_CHECK(call)                                                      \
+    do {                                                                     \
+        hipError_t e__ = (call);                                             \
+        if (e__ != hipSuccess) return psm_hip_fail(e__, #call, __FILE__, __LINE__); \
+    } while (0)
+
+// error value usable as an int stage code or as a psmdem_status
+struct PsmErr {
+    int v;
+    operator int() const { return v; }
+    operator psmdem_status() const { return (psmdem_status)v; }
+};
+PsmErr psm_hip_fail(hipError_t e, const char* what, const char* file, int line);
+void psm_set_error(const char* fmt, ...);
+
+// exclusive scan of n ints into out[0..n], out[n] = total (device); tmp >= scan_tmp_size(n)
+size_t psm_scan_tmp_ints(long long n);
+hipError_t psm_scan(const int* in, int* out, long long n, int* tmp, hipStream_t s);
+hipError_t psm_fill_int(int* p, int v, long long n, hipStream_t s);

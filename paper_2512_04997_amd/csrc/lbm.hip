@@ -1,0 +1,487 @@
+// lbm.hip -- fused in-place (AA pattern) D3Q19 collide-and-stream with BGK
+// (Sec. 2.3, Eqs. collAndStream, BGK, equilibrium), partially saturated cells
+// (Sec. 2.4, Eqs. psm1, lbePS, bk, btot, forceSF, torqueSF), halfway and
+// moving-wall bounce-back and Guo forcing.
+//
+// Storage: one array of shifted populations g_i = f_i - w_i, [19][N], type S.
+//   even step: lane reads g_i at its own cell slot i and writes g*_i to its own
+//              slot opp(i);
+//   odd step : lane reads g_i from slot opp(i) of cell x - c_i and writes g*_i
+//              to slot i of cell x + c_i.
+//   A lane reads and writes the same set of addresses in both steps, so the
+//   update is race-free in place.  A link through a wall reads / writes the
+//   lane's own opposite slot with the moving-wall term (halfway bounce-back).
+// Tiles of 64 x 4 x 4 cells: a workgroup of 256 lanes, one x-row per wave
+// (coalesced 64-cell rows), four z-planes per lane.  Tiles with registered
+// particles run the PSM kernel: particle kinematics staged in LDS, per-cell
+// momentum exchange reduced per particle with wave shuffles into LDS (fixed
+// order, no floating-point atomics), one partial per (tile, particle).
+// The block -> tile mapping keeps consecutive tiles on one XCD.
+#include <hip/hip_fp16.h>
+
+#include "common.h"
+#include "lbm.h"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// storage conversions: double, float, bf16 (round to nearest even), fp16
+// ---------------------------------------------------------------------------
+struct bf16_t {
+    unsigned short u;
+};
+
+template <typename S, typename C>
+struct Conv;
+template <>
+struct Conv<double, double> {
+    __device__ static double ld(double v) { return v; }
+    __device__ static double st(double v) { return v; }
+};
+template <>
+struct Conv<float, float> {
+    __device__ static float ld(float v) { return v; }
+    __device__ static float st(float v) { return v; }
+};
+template <>
+struct Conv<bf16_t, float> {
+    __device__ static float ld(bf16_t v) { return __uint_as_float(((unsigned)v.u) << 16); }
+    __device__ static bf16_t st(float v) {
+        unsigned u = __float_as_uint(v);
+        bf16_t r;
+        if ((u & 0x7fffffffu) > 0x7f800000u) {
+            r.u = (unsigned short)((u >> 16) | 0x40u);
+        } else {
+            u += 0x7fffu + ((u >> 16) & 1u);
+            r.u = (unsigned short)(u >> 16);
+        }
+        return r;
+    }
+};
+template <>
+struct Conv<_Float16, float> {
+    __device__ static float ld(_Float16 v) { return (float)v; }
+    __device__ static _Float16 st(float v) { return (_Float16)v; }
+};
+
+// ---------------------------------------------------------------------------
+// collision of one cell in shifted form (g = f - w), compute type C
+// ---------------------------------------------------------------------------
+template <typename C, bool PSM>
+struct Cell {
+    C g[19];
+    C out[19];
+};
+
+template <typename C>
+__device__ inline C W(int i) {
+    return (C)d3q19_w(i);
+}
+
+// moments and equilibrium scalars
+template <typename C>
+__device__ inline void moments(const C* g, C& drho, C& jx, C& jy, C& jz) {
+    drho = (C)0;
+    jx = jy = jz = (C)0;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        drho += g[i];
+        if (d3q19_cx(i) > 0) jx += g[i];
+        if (d3q19_cx(i) < 0) jx -= g[i];
+        if (d3q19_cy(i) > 0) jy += g[i];
+        if (d3q19_cy(i) < 0) jy -= g[i];
+        if (d3q19_cz(i) > 0) jz += g[i];
+        if (d3q19_cz(i) < 0) jz -= g[i];
+    }
+}
+
+template <typename C>
+__device__ inline C cdot(int i, C x, C y, C z) {
+    C r = (C)0;
+    if (d3q19_cx(i) > 0) r += x;
+    if (d3q19_cx(i) < 0) r -= x;
+    if (d3q19_cy(i) > 0) r += y;
+    if (d3q19_cy(i) < 0) r -= y;
+    if (d3q19_cz(i) > 0) r += z;
+    if (d3q19_cz(i) < 0) r -= z;
+    return r;
+}
+
+// BGK (+ PSM, + Guo) collision; Pk[k] = sum_i Omega^s_ik c_i (before the B_k factor)
+template <typename C, bool PSM>
+__device__ inline void collide(const C* g, C* out, C omega, bool forcing, C Fx, C Fy, C Fz, int nk, const C* B,
+                               const C (*uk)[3], C (*Pk)[3]) {
+    C drho, jx, jy, jz;
+    moments(g, drho, jx, jy, jz);
+    const C rho = (C)1 + drho;
+    const C irho = (C)1 / rho;
+    C ux, uy, uz;
+    if (forcing) {
+        ux = (jx + (C)0.5 * Fx) * irho;
+        uy = (jy + (C)0.5 * Fy) * irho;
+        uz = (jz + (C)0.5 * Fz) * irho;
+    } else {
+        ux = jx * irho;
+        uy = jy * irho;
+        uz = jz * irho;
+    }
+    const C usq = ux * ux + uy * uy + uz * uz;
+    const C E = drho - (C)1.5 * rho * usq;
+    C Bt = (C)0;
+    if (PSM) {
+        for (int k = 0; k < nk; ++k) Bt += B[k];
+        Bt = Bt < (C)1 ? Bt : (C)1;
+    }
+    const C om = PSM ? ((C)1 - Bt) * omega : omega;
+    const C fpre = PSM ? ((C)1 - Bt) : (C)1;
+    const C gk = (C)1 - (C)0.5 * omega;  // Guo prefactor 1 - 1/(2 tau)
+    const C uF = ux * Fx + uy * Fy + uz * Fz;
+    // rest population
+    {
+        const C geq0 = W<C>(0) * E;
+        C o = g[0] - om * (g[0] - geq0);
+        if (forcing) o += fpre * gk * W<C>(0) * ((C)-3 * uF);
+        if (PSM) {
+            for (int k = 0; k < nk; ++k) {
+                const C uk2 = uk[k][0] * uk[k][0] + uk[k][1] * uk[k][1] + uk[k][2] * uk[k][2];
+                const C Ek = drho - (C)1.5 * rho * uk2;
+                o += B[k] * (W<C>(0) * (Ek - E));
+            }
+        }
+        out[0] = o;
+    }
+    if (PSM)
+        for (int k = 0; k < nk; ++k) Pk[k][0] = Pk[k][1] = Pk[k][2] = (C)0;
+#pragma unroll
+    for (int p = 1; p <= 9; ++p) {
+        const int q = p + 9;
+        const C w = W<C>(p);
+        const C cu = cdot<C>(p, ux, uy, uz);
+        const C sym = w * (E + (C)4.5 * rho * cu * cu);
+        const C anti = w * (C)3 * rho * cu;
+        const C geqp = sym + anti, geqq = sym - anti;
+        const C neqp = g[p] - geqp, neqq = g[q] - geqq;
+        C op = g[p] - om * neqp;
+        C oq = g[q] - om * neqq;
+        if (forcing) {
+            const C cF = cdot<C>(p, Fx, Fy, Fz);
+            const C t = (C)9 * cu * cF - (C)3 * uF;
+            op += fpre * gk * w * ((C)3 * cF + t);
+            oq += fpre * gk * w * ((C)-3 * cF + t);
+        }
+        if (PSM) {
+            for (int k = 0; k < nk; ++k) {
+                const C uk2 = uk[k][0] * uk[k][0] + uk[k][1] * uk[k][1] + uk[k][2] * uk[k][2];
+                const C Ek = drho - (C)1.5 * rho * uk2;
+                const C cuk = cdot<C>(p, uk[k][0], uk[k][1], uk[k][2]);
+                const C symk = w * (Ek + (C)4.5 * rho * cuk * cuk);
+                const C antik = w * (C)3 * rho * cuk;
+                const C Osp = neqq - (g[p] - (symk + antik));
+                const C Osq = neqp - (g[q] - (symk - antik));
+                op += B[k] * Osp;
+                oq += B[k] * Osq;
+                const C d = Osp - Osq;
+                if (d3q19_cx(p) > 0) Pk[k][0] += d;
+                if (d3q19_cx(p) < 0) Pk[k][0] -= d;
+                if (d3q19_cy(p) > 0) Pk[k][1] += d;
+                if (d3q19_cy(p) < 0) Pk[k][1] -= d;
+                if (d3q19_cz(p) > 0) Pk[k][2] += d;
+                if (d3q19_cz(p) < 0) Pk[k][2] -= d;
+            }
+        }
+        out[p] = op;
+        out[q] = oq;
+    }
+}
+
+// neighbour offsets and wall faces of a cell
+struct Nbr {
+    long long off[3][3];  // [axis][d + 1] index offset to the neighbour (wrapped)
+    int face[3][3];       // [axis][d + 1] walled face crossed, -1 none
+};
+
+__device__ inline void make_nbr(const GeoArgs& g, int x, int y, int z, Nbr& nb) {
+    const int c[3] = {x, y, z};
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const long long stride[3] = {1, (long long)g.nx, (long long)g.nx * g.ny};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        nb.off[a][1] = 0;
+        nb.face[a][1] = -1;
+        // minus
+        if (c[a] == 0) {
+            nb.off[a][0] = g.periodic[a] ? (long long)(n[a] - 1) * stride[a] : 0;
+            nb.face[a][0] = g.periodic[a] ? -1 : 2 * a;
+        } else {
+            nb.off[a][0] = -stride[a];
+            nb.face[a][0] = -1;
+        }
+        // plus
+        if (c[a] == n[a] - 1) {
+            nb.off[a][2] = g.periodic[a] ? -(long long)(n[a] - 1) * stride[a] : 0;
+            nb.face[a][2] = g.periodic[a] ? -1 : 2 * a + 1;
+        } else {
+            nb.off[a][2] = stride[a];
+            nb.face[a][2] = -1;
+        }
+    }
+}
+
+// cell offset and first walled face (lowest index) of direction (dx,dy,dz)
+__device__ inline long long nbr_at(const Nbr& nb, int dx, int dy, int dz, int* face) {
+    int f = nb.face[0][dx + 1];
+    if (f < 0) f = nb.face[1][dy + 1];
+    if (f < 0) f = nb.face[2][dz + 1];
+    *face = f;
+    return nb.off[0][dx + 1] + nb.off[1][dy + 1] + nb.off[2][dz + 1];
+}
+
+__device__ inline unsigned long long ballot64(bool p) { return __ballot(p); }
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <typename S, typename C, bool ODD, bool PSM>
+__global__ __launch_bounds__(256) void k_lbm(LbmArgs A) {
+    const long long ntiles = A.g.ntiles;
+    const long long per = (ntiles + 7) / 8;
+    const long long t = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (t >= ntiles) return;
+    long long s0 = A.t.tile_start[t], s1 = A.t.tile_start[t + 1];
+    if (s1 > A.t.cap) s1 = A.t.cap;
+    int count = (int)(s1 - s0);
+    if (PSM) {
+        if (count <= 0) return;
+        if (count > PSM_PMAX) count = PSM_PMAX;
+    } else {
+        if (count > 0) return;
+    }
+    __shared__ double kin_s[PSM ? PSM_PMAX * 9 : 1];
+    __shared__ double acc[PSM ? 4 * PSM_PMAX * 6 : 1];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
+    if (PSM) {
+        for (int u = tid; u < count * 9; u += 256) {
+            int k = (int)(A.t.tile_list[s0 + u / 9] >> 32);
+            kin_s[u] = A.kin[9 * k + u % 9];
+        }
+        for (int u = tid; u < 4 * count * 6; u += 256) acc[u] = 0.0;
+        __syncthreads();
+    }
+    const int tx = (int)(t % A.g.ntx), ty = (int)((t / A.g.ntx) % A.g.nty);
+    const int tz = (int)(t / ((long long)A.g.ntx * A.g.nty));
+    const int x = tx * PSM_TX + lane, y = ty * PSM_TY + wid;
+    const long long N = A.g.N;
+    S* f = (S*)A.f;
+    const C omega = (C)A.omega;
+    const bool forcing = A.forcing != 0;
+    const long long plane = ntiles * (long long)PSM_TILE;
+    const C* Bslot = (const C*)A.t.slot_B;
+
+#pragma unroll 1
+    for (int lz = 0; lz < PSM_TZ; ++lz) {
+        const int z = tz * PSM_TZ + lz;
+        const bool valid = x < A.g.nx && y < A.g.ny && z < A.g.nz;
+        const long long cell = (long long)x + (long long)A.g.nx * ((long long)y + (long long)A.g.ny * z);
+        C g[19], out[19];
+        Nbr nb;
+        int nk = 0;
+        C B[PSM_SLOTS_MAX];
+        C uk[PSM_SLOTS_MAX][3];
+        C Pk[PSM_SLOTS_MAX][3];
+        int lpk[PSM_SLOTS_MAX];
+        double dk[PSM_SLOTS_MAX][3];
+        C Fx = (C)0, Fy = (C)0, Fz = (C)0;
+        if (valid) {
+            if (ODD) make_nbr(A.g, x, y, z, nb);
+#pragma unroll
+            for (int i = 0; i < 19; ++i) {
+                if (!ODD) {
+                    g[i] = Conv<S, C>::ld(f[(long long)i * N + cell]);
+                } else {
+                    int face;
+                    long long o = nbr_at(nb, -d3q19_cx(i), -d3q19_cy(i), -d3q19_cz(i), &face);
+                    if (face >= 0)
+                        g[i] = Conv<S, C>::ld(f[(long long)i * N + cell]) + (C)A.wall_corr[face][i];
+                    else
+                        g[i] = Conv<S, C>::ld(f[(long long)d3q19_opp(i) * N + cell + o]);
+                }
+            }
+            if (forcing) {
+                Fx = (C)A.F[0];
+                Fy = (C)A.F[1];
+                Fz = (C)A.F[2];
+                if (A.kolm_prof) {
+                    int coord = A.kolm_axis == 0 ? x : (A.kolm_axis == 1 ? y : z);
+                    C add = (C)A.kolm_prof[coord];
+                    if (A.kolm_dir == 0) Fx += add;
+                    else if (A.kolm_dir == 1) Fy += add;
+                    else Fz += add;
+                }
+            }
+            if (PSM) {
+                const long long sl = t * (long long)PSM_TILE + lane + PSM_TX * (wid + PSM_TY * lz);
+                const unsigned lp = A.t.slot_lp[sl];
+                for (int k = 0; k < A.ms; ++k) {
+                    unsigned b = (lp >> (8 * k)) & 0xffu;
+                    if (b == 0xffu || (int)b >= count) break;
+                    lpk[nk] = (int)b;
+                    B[nk] = Bslot[k * plane + sl];
+                    const double* kn = kin_s + 9 * b;
+                    const double rj[3] = {x + 0.5, y + 0.5, z + 0.5};
+                    double d[3];
+                    for (int a = 0; a < 3; ++a) {
+                        double v = rj[a] - kn[a];
+                        if (A.g.periodic[a]) {
+                            if (v > 0.5 * A.L[a]) v -= A.L[a];
+                            else if (v < -0.5 * A.L[a]) v += A.L[a];
+                        }
+                        d[a] = v;
+                        dk[nk][a] = v;
+                    }
+                    // u_k = v_k + w_k x (r_j - r_k)
+                    uk[nk][0] = (C)(kn[3] + (kn[7] * d[2] - kn[8] * d[1]));
+                    uk[nk][1] = (C)(kn[4] + (kn[8] * d[0] - kn[6] * d[2]));
+                    uk[nk][2] = (C)(kn[5] + (kn[6] * d[1] - kn[7] * d[0]));
+                    ++nk;
+                }
+            }
+            collide<C, PSM>(g, out, omega, forcing, Fx, Fy, Fz, nk, B, uk, Pk);
+#pragma unroll
+            for (int i = 0; i < 19; ++i) {
+                if (!ODD) {
+                    f[(long long)d3q19_opp(i) * N + cell] = Conv<S, C>::st(out[i]);
+                } else {
+                    int face;
+                    long long o = nbr_at(nb, d3q19_cx(i), d3q19_cy(i), d3q19_cz(i), &face);
+                    if (face >= 0)
+                        f[(long long)d3q19_opp(i) * N + cell] = Conv<S, C>::st(out[i] - (C)A.wall_corr[face][i]);
+                    else
+                        f[(long long)i * N + cell + o] = Conv<S, C>::st(out[i]);
+                }
+            }
+        }
+        if (PSM) {
+            // per-particle momentum exchange of this plane: wave sums into LDS
+            for (int k = 0; k < A.ms; ++k) {
+                const bool has = k < nk;
+                const int my = has ? lpk[k] : -1;
+                double P[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
+                if (has) {
+                    const double Bd = (double)B[k];
+                    for (int a = 0; a < 3; ++a) P[a] = Bd * (double)Pk[k][a];
+                    T[0] = dk[k][1] * P[2] - dk[k][2] * P[1];
+                    T[1] = dk[k][2] * P[0] - dk[k][0] * P[2];
+                    T[2] = dk[k][0] * P[1] - dk[k][1] * P[0];
+                }
+                unsigned long long pending = ballot64(has);
+                while (pending) {
+                    const int leader = __ffsll((long long)pending) - 1;
+                    const int target = __shfl(my, leader, 64);
+                    const bool mine = has && my == target;
+                    double v[6];
+                    for (int a = 0; a < 3; ++a) {
+                        v[a] = mine ? P[a] : 0.0;
+                        v[3 + a] = mine ? T[a] : 0.0;
+                    }
+                    for (int a = 0; a < 6; ++a) v[a] = wave_sum(v[a]);
+                    if (lane == 0)
+                        for (int a = 0; a < 6; ++a) acc[(wid * PSM_PMAX + target) * 6 + a] += v[a];
+                    pending &= ~ballot64(mine);
+                }
+            }
+        }
+    }
+    if (PSM) {
+        __syncthreads();
+        for (int u = tid; u < count * 6; u += 256) {
+            const int p = u / 6, a = u % 6;
+            double s = 0.0;
+            for (int w = 0; w < 4; ++w) s += acc[(w * PSM_PMAX + p) * 6 + a];
+            A.t.partial[(s0 + p) * 6 + a] = s;
+        }
+    }
+}
+
+template <typename S, typename C>
+hipError_t launch_step(const LbmArgs& A, int odd, hipStream_t s) {
+    const unsigned nblk = (unsigned)(8 * ((A.g.ntiles + 7) / 8));
+    if (odd) {
+        k_lbm<S, C, true, false><<<nblk, 256, 0, s>>>(A);
+        k_lbm<S, C, true, true><<<nblk, 256, 0, s>>>(A);
+    } else {
+        k_lbm<S, C, false, false><<<nblk, 256, 0, s>>>(A);
+        k_lbm<S, C, false, true><<<nblk, 256, 0, s>>>(A);
+    }
+    return hipGetLastError();
+}
+
+template <typename S, typename C>
+__global__ void k_init(S* f, long long N, double rho0) {
+    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= N) return;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) f[(long long)i * N + c] = Conv<S, C>::st((C)(d3q19_w(i) * (rho0 - 1.0)));
+}
+
+template <typename S, typename C>
+__global__ void k_to_double(const S* f, long long n, double* out) {
+    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) out[c] = (double)Conv<S, C>::ld(f[c]);
+}
+
+template <typename S, typename C>
+__global__ void k_from_double(S* f, long long n, const double* in) {
+    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) f[c] = Conv<S, C>::st((C)in[c]);
+}
+
+inline unsigned nb256(long long n) { return (unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }
+
+}  // namespace
+
+hipError_t lbm_step(const LbmArgs& A, int precision, int odd, hipStream_t s) {
+    switch (precision) {
+        case 0: return launch_step<double, double>(A, odd, s);
+        case 1: return launch_step<float, float>(A, odd, s);
+        case 2: return launch_step<bf16_t, float>(A, odd, s);
+        case 3: return launch_step<_Float16, float>(A, odd, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t lbm_init(void* f, int precision, long long N, double rho0, hipStream_t s) {
+    switch (precision) {
+        case 0: k_init<double, double><<<nb256(N), 256, 0, s>>>((double*)f, N, rho0); break;
+        case 1: k_init<float, float><<<nb256(N), 256, 0, s>>>((float*)f, N, rho0); break;
+        case 2: k_init<bf16_t, float><<<nb256(N), 256, 0, s>>>((bf16_t*)f, N, rho0); break;
+        case 3: k_init<_Float16, float><<<nb256(N), 256, 0, s>>>((_Float16*)f, N, rho0); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t lbm_to_double(const void* f, int precision, long long n, double* out, hipStream_t s) {
+    switch (precision) {
+        case 0: k_to_double<double, double><<<nb256(n), 256, 0, s>>>((const double*)f, n, out); break;
+        case 1: k_to_double<float, float><<<nb256(n), 256, 0, s>>>((const float*)f, n, out); break;
+        case 2: k_to_double<bf16_t, float><<<nb256(n), 256, 0, s>>>((const bf16_t*)f, n, out); break;
+        case 3: k_to_double<_Float16, float><<<nb256(n), 256, 0, s>>>((const _Float16*)f, n, out); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t lbm_from_double(void* f, int precision, long long n, const double* in, hipStream_t s) {
+    switch (precision) {
+        case 0: k_from_double<double, double><<<nb256(n), 256, 0, s>>>((double*)f, n, in); break;
+        case 1: k_from_double<float, float><<<nb256(n), 256, 0, s>>>((float*)f, n, in); break;
+        case 2: k_from_double<bf16_t, float><<<nb256(n), 256, 0, s>>>((bf16_t*)f, n, in); break;
+        case 3: k_from_double<_Float16, float><<<nb256(n), 256, 0, s>>>((_Float16*)f, n, in); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}

@@ -1,0 +1,1094 @@
+// psmdem.hip -- domain object, coupled-step orchestration and the C ABI
+// declared in include/psmdem.h.
+//
+// Coupled step (workflow figure, Sec. 3.2; substeps per Sec. 2.3): for each of
+// n_sub DEM substeps: predictor, cell list, candidate pairs, contacts, DEM
+// sums; in the last substep, with the fluid on, solid fractions, the LBM-PSM
+// step and the hydrodynamic sums run before the corrector.  Every launch is
+// enqueued on the domain stream; nothing is copied back inside a step.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+#include "dem.h"
+#include "lbm.h"
+#include "voxel.h"
+
+static thread_local char g_err[512] = "";
+
+void psm_set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+PsmErr psm_hip_fail(hipError_t e, const char* what, const char* file, int line) {
+    psm_set_error("HIP error %s (%d) in %s at %s:%d", hipGetErrorString(e), (int)e, what, file, line);
+    return PsmErr{PSMDEM_E_HIP};
+}
+
+namespace {
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+__global__ void k_kin(PartArgs p, int copy_vw) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= p.np) return;
+    for (int c = 0; c < 3; ++c) {
+        if (copy_vw) {
+            p.vp[3 * k + c] = p.v[3 * k + c];
+            p.wp[3 * k + c] = p.w[3 * k + c];
+        }
+        p.kin[9 * k + c] = p.pos[3 * k + c];
+        p.kin[9 * k + 3 + c] = p.vp[3 * k + c];
+        p.kin[9 * k + 6 + c] = p.wp[3 * k + c];
+    }
+}
+
+inline unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
+
+const int CX[19] = {0, 1, 0, 0, 1, 1, 1, 1, 0, 0, -1, 0, 0, -1, -1, -1, -1, 0, 0};
+const int CY[19] = {0, 0, 1, 0, 1, -1, 0, 0, 1, 1, 0, -1, 0, -1, 1, 0, 0, -1, -1};
+const int CZ[19] = {0, 0, 0, 1, 0, 0, 1, -1, 1, -1, 0, 0, -1, 0, 0, -1, 1, -1, 1};
+inline int OPP(int i) { return i == 0 ? 0 : (i <= 9 ? i + 9 : i - 9); }
+inline double WT(int i) { return i == 0 ? 1.0 / 3.0 : (((i - 1) % 9) < 3 ? 1.0 / 18.0 : 1.0 / 36.0); }
+
+size_t storage_bytes(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
+
+double decode(const unsigned char* raw, int prec, long long idx) {
+    switch (prec) {
+        case 0: return ((const double*)raw)[idx];
+        case 1: return (double)((const float*)raw)[idx];
+        case 2: {
+            unsigned u = ((unsigned)((const unsigned short*)raw)[idx]) << 16;
+            float f;
+            memcpy(&f, &u, 4);
+            return (double)f;
+        }
+        default: return (double)((const _Float16*)raw)[idx];
+    }
+}
+
+void encode(unsigned char* raw, int prec, long long idx, double v) {
+    switch (prec) {
+        case 0: ((double*)raw)[idx] = v; break;
+        case 1: ((float*)raw)[idx] = (float)v; break;
+        case 2: {
+            float f = (float)v;
+            unsigned u;
+            memcpy(&u, &f, 4);
+            if ((u & 0x7fffffffu) > 0x7f800000u) u = (u >> 16) | 0x40u;
+            else u = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+            ((unsigned short*)raw)[idx] = (unsigned short)u;
+            break;
+        }
+        default: ((_Float16*)raw)[idx] = (_Float16)(float)v; break;
+    }
+}
+
+}  // namespace
+
+struct psmdem_domain {
+    psmdem_desc d;
+    hipStream_t s = nullptr;
+    psmdem_alloc_fn alloc = nullptr;
+    psmdem_free_fn freef = nullptr;
+    void* actx = nullptr;
+    std::vector<std::pair<void*, size_t>> blocks;
+    size_t bytes = 0;
+
+    int np = 0;
+    long long N = 0;
+    GeoArgs geo{};
+    double L[3];
+    int prec = 0;
+    void* f = nullptr;
+    double wall_corr[6][19];
+    double* kolm_prof = nullptr;
+
+    // particles
+    PartArgs p{};
+    std::vector<int> h_shape;
+    // DEM
+    int nsub = 1;
+    double dt = 1.0, beta_e = 0.0, Rc = 0.0;
+    int nc[3];
+    double h[3];
+    long long ncell = 1;
+    int *cell_count = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *cell_pid = nullptr;
+    long long reg_cap = 0;
+    int* pcount = nullptr;
+    int* prow[2] = {nullptr, nullptr};
+    unsigned long long* pairs[2] = {nullptr, nullptr};
+    double* hist[2] = {nullptr, nullptr};
+    double *cF = nullptr, *cMi = nullptr, *cMj = nullptr;
+    unsigned char* incontact = nullptr;
+    long long pair_cap = 0;
+    int cur = 0;
+    // voxel / tiles
+    TileArgs t{};
+    int* tile_count = nullptr;
+    int* tile_fill = nullptr;
+    int* scan_tmp = nullptr;
+    DevCounters* ctr = nullptr;
+
+    int64_t step = 0;
+    bool voxelized = false;
+
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    double t_ms[4] = {0, 0, 0, 0};
+    long long t_n[4] = {0, 0, 0, 0};
+
+    void* dalloc(size_t n) {
+        if (n == 0) n = 16;
+        n = (n + 255) & ~(size_t)255;
+        void* ptr = nullptr;
+        if (alloc) {
+            ptr = alloc(n, actx);
+        } else if (hipMalloc(&ptr, n) != hipSuccess) {
+            ptr = nullptr;
+        }
+        if (ptr) {
+            blocks.push_back({ptr, n});
+            bytes += n;
+        }
+        return ptr;
+    }
+    ~psmdem_domain() {
+        if (s) (void)hipStreamSynchronize(s);
+        else (void)hipDeviceSynchronize();
+        for (auto& b : blocks) {
+            if (freef) freef(b.first, b.second, actx);
+            else if (!alloc) (void)hipFree(b.first);
+        }
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+
+    DemArgs dem_args(int use_prev) {
+        DemArgs A{};
+        A.g = geo;
+        A.p = p;
+        for (int a = 0; a < 3; ++a) {
+            A.L[a] = L[a];
+            A.nc[a] = nc[a];
+            A.h[a] = h[a];
+            A.gravity[a] = d.gravity[a];
+        }
+        A.ncell = ncell;
+        A.cell_count = cell_count;
+        A.cell_start = cell_start;
+        A.cell_fill = cell_fill;
+        A.cell_pid = cell_pid;
+        A.reg_cap = reg_cap;
+        A.pcount = pcount;
+        A.prow = prow[cur];
+        A.pairs = pairs[cur];
+        A.hist = hist[cur];
+        A.cF = cF;
+        A.cMi = cMi;
+        A.cMj = cMj;
+        A.incontact = incontact;
+        A.pair_cap = pair_cap;
+        if (use_prev) {
+            A.prev_pairs = pairs[cur ^ 1];
+            A.prev_hist = hist[cur ^ 1];
+            A.prev_n = prow[cur ^ 1] + np;
+        } else {
+            A.prev_pairs = pairs[cur ^ 1];
+            A.prev_hist = hist[cur ^ 1];
+            A.prev_n = nullptr;
+        }
+        A.kn = d.kn;
+        A.beta_e = beta_e;
+        A.mu = d.mu;
+        A.kt_ratio = d.kt_ratio;
+        A.gt_ratio = d.gt_ratio;
+        for (int f_ = 0; f_ < 6; ++f_)
+            for (int c = 0; c < 3; ++c) A.wall_u[f_][c] = d.wall_u[f_][c];
+        A.ctr = ctr;
+        return A;
+    }
+
+    VoxArgs vox_args() {
+        VoxArgs A{};
+        A.g = geo;
+        A.p = p;
+        A.t = t;
+        A.tile_count = tile_count;
+        A.tile_fill = tile_fill;
+        A.sf_method = d.sf_method;
+        A.ns = d.sf_subdiv;
+        A.Rc = Rc;
+        A.tau = d.tau;
+        A.ms = d.max_solids;
+        A.ctr = ctr;
+        return A;
+    }
+
+    LbmArgs lbm_args() {
+        LbmArgs A{};
+        A.g = geo;
+        A.f = f;
+        A.omega = 1.0 / d.tau;
+        A.forcing = (d.body_force[0] != 0.0 || d.body_force[1] != 0.0 || d.body_force[2] != 0.0 ||
+                     d.kolm_amp != 0.0);
+        for (int a = 0; a < 3; ++a) {
+            A.F[a] = d.body_force[a];
+            A.L[a] = L[a];
+        }
+        A.kolm_axis = d.kolm_axis;
+        A.kolm_dir = d.kolm_dir;
+        A.kolm_prof = kolm_prof;
+        memcpy(A.wall_corr, wall_corr, sizeof wall_corr);
+        A.t = t;
+        A.kin = p.kin;
+        A.ms = d.max_solids;
+        return A;
+    }
+
+    int timed_begin(int which) {
+        if (!timing) return -1;
+        hipEvent_t a, b;
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+        ev.push_back(a);
+        ev.push_back(b);
+        (void)hipEventRecord(a, s);
+        pending.push_back({which, (int)ev.size() - 2});
+        return (int)ev.size() - 1;
+    }
+    void timed_end(int idx) {
+        if (idx >= 0) (void)hipEventRecord(ev[idx], s);
+    }
+    std::vector<std::pair<int, int>> pending;
+    void collect_timing() {
+        for (auto& pr : pending) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[pr.second], ev[pr.second + 1]) == hipSuccess) {
+                t_ms[pr.first] += ms;
+                t_n[pr.first] += 1;
+            }
+        }
+        pending.clear();
+        for (auto e : ev) (void)hipEventDestroy(e);
+        ev.clear();
+    }
+};
+
+// ---------------------------------------------------------------------------
+// stages
+// ---------------------------------------------------------------------------
+static int run_voxelize(psmdem_domain* D) {
+    VoxArgs V = D->vox_args();
+    int tk = D->timed_begin(PSMDEM_T_VOXEL);
+    k_zero_u64<<<1, 64, 0, D->s>>>(&D->ctr->entries, 2);
+    PSM_CHECK(vox_register(V, D->scan_tmp, D->s));
+    PSM_CHECK(vox_voxelize(V, D->prec == 0, D->s));
+    D->timed_end(tk);
+    D->voxelized = true;
+    return 0;
+}
+
+static int run_lbm(psmdem_domain* D) {
+    LbmArgs A = D->lbm_args();
+    int tk = D->timed_begin(PSMDEM_T_LBM);
+    PSM_CHECK(lbm_step(A, D->prec, (int)(D->step & 1), D->s));
+    D->timed_end(tk);
+    VoxArgs V = D->vox_args();
+    tk = D->timed_begin(PSMDEM_T_HYDRO);
+    PSM_CHECK(vox_reduce_hydro(V, D->s));
+    D->timed_end(tk);
+    return 0;
+}
+
+static int run_lists(psmdem_domain* D) {
+    DemArgs A = D->dem_args(1);
+    PSM_CHECK(dem_lists(A, D->scan_tmp, D->s));
+    return 0;
+}
+
+static int coupled_step(psmdem_domain* D) {
+    int rc;
+    if (D->d.dem_on && D->np > 0) {
+        for (int sub = 1; sub <= D->nsub; ++sub) {
+            const bool last = sub == D->nsub;
+            int tk = D->timed_begin(PSMDEM_T_DEM);
+            {
+                DemArgs A = D->dem_args(1);
+                PSM_CHECK(dem_predict(A, D->dt, last ? 1 : 0, D->s));
+            }
+            D->cur ^= 1;
+            {
+                DemArgs A = D->dem_args(1);
+                PSM_CHECK(dem_lists(A, D->scan_tmp, D->s));
+                PSM_CHECK(dem_contacts(A, D->p.vp, D->p.wp, D->dt, D->s));
+            }
+            D->timed_end(tk);
+            if (last && D->d.fluid_on) {
+                if ((rc = run_voxelize(D))) return rc;
+                if ((rc = run_lbm(D))) return rc;
+            }
+            tk = D->timed_begin(PSMDEM_T_DEM);
+            {
+                DemArgs A = D->dem_args(1);
+                PSM_CHECK(dem_correct(A, D->dt, D->s));
+            }
+            D->timed_end(tk);
+        }
+    } else if (D->d.fluid_on) {
+        if (D->np > 0) k_kin<<<nblk(D->np), 256, 0, D->s>>>(D->p, 1);
+        if ((rc = run_voxelize(D))) return rc;
+        if ((rc = run_lbm(D))) return rc;
+    }
+    D->step++;
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// creation
+// ---------------------------------------------------------------------------
+static int validate(const psmdem_desc* d, const psmdem_particles* P) {
+    if (!d) { psm_set_error("desc is NULL"); return 0; }
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1) { psm_set_error("lattice extents must be >= 1"); return 0; }
+    if (!(d->tau > 0.5)) { psm_set_error("tau must exceed 1/2"); return 0; }
+    for (int a = 0; a < 3; ++a) {
+        int p0 = d->bc[2 * a] == 0, p1 = d->bc[2 * a + 1] == 0;
+        if (p0 != p1) { psm_set_error("axis %d: periodic on one face only", a); return 0; }
+        for (int f = 0; f < 2; ++f)
+            if (d->bc[2 * a + f] < 0 || d->bc[2 * a + f] > 2) { psm_set_error("invalid boundary code"); return 0; }
+    }
+    if (d->precision < 0 || d->precision > 3) { psm_set_error("invalid precision"); return 0; }
+    if (d->sf_method < 0 || d->sf_method > 1) { psm_set_error("invalid sf_method"); return 0; }
+    if (d->sf_subdiv < 1 || d->sf_subdiv > 32) { psm_set_error("sf_subdiv must be in 1..32"); return 0; }
+    if (d->max_solids < 1 || d->max_solids > PSM_SLOTS_MAX) { psm_set_error("max_solids must be in 1..4"); return 0; }
+    if (d->kolm_amp != 0.0 && (d->kolm_axis < 0 || d->kolm_axis > 2 || d->kolm_dir < 0 || d->kolm_dir > 2)) {
+        psm_set_error("invalid Kolmogorov axis"); return 0;
+    }
+    if (P && P->n < 0) { psm_set_error("negative particle count"); return 0; }
+    if (P && P->n > 0) {
+        if (!P->shape || !P->semi_axes || !P->density_ratio || !P->pos) {
+            psm_set_error("particle arrays missing"); return 0;
+        }
+        if (!(d->restitution > 0.0 && d->restitution <= 1.0)) { psm_set_error("restitution must be in (0,1]"); return 0; }
+        if (d->kn < 0.0 || d->mu < 0.0) { psm_set_error("kn and mu must be >= 0"); return 0; }
+        for (int k = 0; k < P->n; ++k) {
+            if (P->shape[k] != 0 && P->shape[k] != 1) { psm_set_error("invalid shape of particle %d", k); return 0; }
+            if (P->shape[k] == 1 && d->sf_method == 1) {
+                psm_set_error("distance solid fraction is for spheres only"); return 0;
+            }
+            int na = P->shape[k] == 0 ? 1 : 3;
+            for (int a = 0; a < na; ++a)
+                if (!(P->semi_axes[3 * k + a] > 0.0)) { psm_set_error("semi-axes must be > 0"); return 0; }
+            if (!(P->density_ratio[k] > 0.0)) { psm_set_error("density ratio must be > 0"); return 0; }
+        }
+    }
+    return 1;
+}
+
+extern "C" psmdem_status psmdem_create(const psmdem_desc* desc, const psmdem_particles* parts, void* stream,
+                                       psmdem_alloc_fn alloc, psmdem_free_fn free_fn, void* alloc_ctx,
+                                       psmdem_domain** out) {
+    if (!out) { psm_set_error("out is NULL"); return PSMDEM_E_INVALID; }
+    *out = nullptr;
+    if (!validate(desc, parts)) return PSMDEM_E_INVALID;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+        psm_set_error("no HIP device");
+        return PSMDEM_E_NODEVICE;
+    }
+    psmdem_domain* D = new psmdem_domain();
+    D->d = *desc;
+    D->s = (hipStream_t)stream;
+    D->alloc = alloc;
+    D->freef = free_fn;
+    D->actx = alloc_ctx;
+    const psmdem_desc& d = D->d;
+    D->prec = d.precision;
+    D->np = parts ? parts->n : 0;
+    const int np = D->np;
+    D->N = (long long)d.nx * d.ny * d.nz;
+    GeoArgs& g = D->geo;
+    g.nx = d.nx; g.ny = d.ny; g.nz = d.nz; g.N = D->N;
+    g.ntx = (d.nx + PSM_TX - 1) / PSM_TX;
+    g.nty = (d.ny + PSM_TY - 1) / PSM_TY;
+    g.ntz = (d.nz + PSM_TZ - 1) / PSM_TZ;
+    g.ntiles = (long long)g.ntx * g.nty * g.ntz;
+    for (int a = 0; a < 3; ++a) g.periodic[a] = d.bc[2 * a] == 0;
+    for (int f = 0; f < 6; ++f) g.bc[f] = d.bc[f];
+    D->L[0] = d.nx; D->L[1] = d.ny; D->L[2] = d.nz;
+    for (int f = 0; f < 6; ++f)
+        for (int i = 0; i < 19; ++i) {
+            double cu = CX[i] * d.wall_u[f][0] + CY[i] * d.wall_u[f][1] + CZ[i] * d.wall_u[f][2];
+            D->wall_corr[f][i] = (d.bc[f] == 2) ? 6.0 * WT(i) * d.rho0 * cu : 0.0;
+        }
+    double e = d.restitution > 0 ? d.restitution : 1.0;
+    D->beta_e = log(e) / sqrt(log(e) * log(e) + M_PI * M_PI);
+    D->Rc = cbrt(3.0 / (4.0 * M_PI));
+
+    // host particle properties
+    std::vector<double> semi(3 * (size_t)np), mass(np), inertia(3 * (size_t)np), rb(np), dens(np);
+    std::vector<double> pos(3 * (size_t)np), q(4 * (size_t)np), v(3 * (size_t)np, 0.0), w(3 * (size_t)np, 0.0);
+    std::vector<unsigned char> fixed(np, 0);
+    D->h_shape.assign(np, 0);
+    double dmax = 0.0;
+    for (int k = 0; k < np; ++k) {
+        int sh = parts->shape[k];
+        D->h_shape[k] = sh;
+        for (int a = 0; a < 3; ++a) {
+            semi[3 * k + a] = sh == 0 ? parts->semi_axes[3 * k] : parts->semi_axes[3 * k + a];
+            pos[3 * k + a] = parts->pos[3 * k + a];
+            if (parts->vel) v[3 * k + a] = parts->vel[3 * k + a];
+            if (parts->omega) w[3 * k + a] = parts->omega[3 * k + a];
+        }
+        double qq[4] = {1.0, 0.0, 0.0, 0.0};
+        if (parts->quat)
+            for (int c = 0; c < 4; ++c) qq[c] = parts->quat[4 * k + c];
+        double qn = sqrt(qq[0] * qq[0] + qq[1] * qq[1] + qq[2] * qq[2] + qq[3] * qq[3]);
+        if (!(qn > 0.0)) { delete D; psm_set_error("zero quaternion for particle %d", k); return PSMDEM_E_INVALID; }
+        for (int c = 0; c < 4; ++c) q[4 * k + c] = qq[c] / qn;
+        dens[k] = parts->density_ratio[k];
+        fixed[k] = parts->fixed ? parts->fixed[k] : 0;
+        const double* s3 = &semi[3 * k];
+        double V = sh == 0 ? 4.0 / 3.0 * M_PI * s3[0] * s3[0] * s3[0] : 4.0 / 3.0 * M_PI * s3[0] * s3[1] * s3[2];
+        double m = dens[k] * d.rho0 * V;
+        mass[k] = m;
+        if (sh == 0) {
+            inertia[3 * k] = inertia[3 * k + 1] = inertia[3 * k + 2] = 0.4 * m * s3[0] * s3[0];
+            rb[k] = s3[0];
+        } else {
+            inertia[3 * k + 0] = m / 5.0 * (s3[1] * s3[1] + s3[2] * s3[2]);
+            inertia[3 * k + 1] = m / 5.0 * (s3[0] * s3[0] + s3[2] * s3[2]);
+            inertia[3 * k + 2] = m / 5.0 * (s3[0] * s3[0] + s3[1] * s3[1]);
+            rb[k] = std::max(s3[0], std::max(s3[1], s3[2]));
+        }
+        dmax = std::max(dmax, 2.0 * rb[k]);
+    }
+    double rbmax = dmax / 2.0;
+    for (int a = 0; a < 3; ++a)
+        if (g.periodic[a] && np > 0 && 2.0 * (rbmax + D->Rc + 1.0) + 1.0 > D->L[a]) {
+            delete D;
+            psm_set_error("periodic axis %d too short for the largest particle", a);
+            return PSMDEM_E_INVALID;
+        }
+    // tiles one particle box may touch per axis
+    {
+        const int T[3] = {PSM_TX, PSM_TY, PSM_TZ};
+        for (int a = 0; a < 3; ++a) {
+            int span = (int)ceil(2.0 * (rbmax + D->Rc + 1e-6)) + 2;
+            if (span / T[a] + 3 > VOX_AXIS_MAX) {
+                delete D;
+                psm_set_error("particles too large for the lattice tiles");
+                return PSMDEM_E_INVALID;
+            }
+        }
+    }
+    // DEM grid: n_c = floor(L / (1.1 d_max)), h = L / n_c
+    for (int a = 0; a < 3; ++a) {
+        int n;
+        if (d.dem_cell > 0.0) n = (int)floor(D->L[a] / d.dem_cell);
+        else n = dmax > 0.0 ? (int)floor(D->L[a] / (1.1 * dmax)) : 1;
+        if (n < 1) n = 1;
+        if (np > 0 && g.periodic[a] && n < 2) {
+            delete D;
+            psm_set_error("periodic axis %d has fewer than 2 DEM cells", a);
+            return PSMDEM_E_INVALID;
+        }
+        D->nc[a] = n;
+        D->h[a] = D->L[a] / (double)n;
+        if (n > 1 && !(D->h[a] > dmax)) {
+            delete D;
+            psm_set_error("DEM cell smaller than the largest diameter");
+            return PSMDEM_E_INVALID;
+        }
+    }
+    D->ncell = (long long)D->nc[0] * D->nc[1] * D->nc[2];
+    if (d.n_sub > 0) {
+        D->nsub = d.n_sub;
+    } else if (np == 0 || d.kn <= 0.0) {
+        D->nsub = 1;
+    } else {
+        std::vector<double> ms(mass);
+        std::sort(ms.begin(), ms.end());
+        double mst = np >= 2 ? ms[0] * ms[1] / (ms[0] + ms[1]) : ms[0];
+        double tc = M_PI * sqrt(mst / d.kn) / sqrt(1.0 - D->beta_e * D->beta_e);
+        D->nsub = std::max(1, (int)ceil(20.0 / tc));
+    }
+    D->dt = 1.0 / (double)D->nsub;
+
+    // ---- device allocation
+    bool ok = true;
+    auto A = [&](size_t n) {
+        void* p_ = D->dalloc(n);
+        ok = ok && p_ != nullptr;
+        return p_;
+    };
+    D->f = A(19 * (size_t)D->N * storage_bytes(D->prec));
+    PartArgs& P = D->p;
+    P.np = np;
+    P.shape = (int*)A(sizeof(int) * std::max(np, 1));
+    P.fixed = (unsigned char*)A(std::max(np, 1));
+    double** d3[] = {&P.semi, &P.inertia, &P.pos, &P.v, &P.w, &P.vp, &P.wp, &P.a, &P.al, &P.fh, &P.mh, &P.fd, &P.md};
+    for (double** pp : d3) *pp = (double*)A(sizeof(double) * 3 * std::max(np, 1));
+    P.mass = (double*)A(sizeof(double) * std::max(np, 1));
+    P.rb = (double*)A(sizeof(double) * std::max(np, 1));
+    P.dens = (double*)A(sizeof(double) * std::max(np, 1));
+    P.q = (double*)A(sizeof(double) * 4 * std::max(np, 1));
+    P.qold = (double*)A(sizeof(double) * 4 * std::max(np, 1));
+    P.kin = (double*)A(sizeof(double) * 9 * std::max(np, 1));
+    D->reg_cap = 8LL * std::max(np, 1);
+    D->cell_count = (int*)A(sizeof(int) * D->ncell);
+    D->cell_fill = (int*)A(sizeof(int) * D->ncell);
+    D->cell_start = (int*)A(sizeof(int) * (D->ncell + 1));
+    D->cell_pid = (int*)A(sizeof(int) * D->reg_cap);
+    D->pair_cap = d.pair_capacity > 0 ? d.pair_capacity : 32LL * np + 1024;
+    D->pcount = (int*)A(sizeof(int) * std::max(np, 1));
+    for (int b = 0; b < 2; ++b) {
+        D->prow[b] = (int*)A(sizeof(int) * (np + 1));
+        D->pairs[b] = (unsigned long long*)A(sizeof(unsigned long long) * D->pair_cap);
+        D->hist[b] = (double*)A(sizeof(double) * 3 * D->pair_cap);
+    }
+    D->cF = (double*)A(sizeof(double) * 3 * D->pair_cap);
+    D->cMi = (double*)A(sizeof(double) * 3 * D->pair_cap);
+    D->cMj = (double*)A(sizeof(double) * 3 * D->pair_cap);
+    D->incontact = (unsigned char*)A(D->pair_cap);
+    // tiles
+    long long per_particle = 1;
+    {
+        const int T[3] = {PSM_TX, PSM_TY, PSM_TZ};
+        for (int a = 0; a < 3; ++a) {
+            int span = (int)ceil(2.0 * (rbmax + D->Rc + 1e-6)) + 2;
+            per_particle *= std::min<long long>(span / T[a] + 3, VOX_AXIS_MAX);
+        }
+    }
+    TileArgs& t = D->t;
+    t.cap = std::max<long long>(1, per_particle * np);
+    t.tile_start = (int*)A(sizeof(int) * (g.ntiles + 1));
+    t.tile_list = (unsigned long long*)A(sizeof(unsigned long long) * t.cap);
+    t.vcount = (int*)A(sizeof(int) * std::max(np, 1));
+    t.voff = (int*)A(sizeof(int) * (np + 1));
+    t.vinv = (int*)A(sizeof(int) * t.cap);
+    const long long plane = g.ntiles * (long long)PSM_TILE;
+    t.slot_lp = (unsigned*)A(sizeof(unsigned) * plane);
+    t.slot_B = A((D->prec == 0 ? 8 : 4) * (size_t)plane * d.max_solids);
+    t.slot_beta = (double*)A(sizeof(double) * (size_t)plane * d.max_solids);
+    t.partial = (double*)A(sizeof(double) * 6 * t.cap);
+    D->tile_count = (int*)A(sizeof(int) * g.ntiles);
+    D->tile_fill = (int*)A(sizeof(int) * g.ntiles);
+    long long scan_n = std::max<long long>(std::max<long long>(D->ncell, g.ntiles), np + 1);
+    D->scan_tmp = (int*)A(sizeof(int) * psm_scan_tmp_ints(scan_n));
+    D->ctr = (DevCounters*)A(sizeof(DevCounters));
+    if (d.kolm_amp != 0.0) {
+        int n_ax = d.kolm_axis == 0 ? d.nx : (d.kolm_axis == 1 ? d.ny : d.nz);
+        std::vector<double> prof(n_ax);
+        for (int c = 0; c < n_ax; ++c) prof[c] = d.kolm_amp * sin(2.0 * M_PI * ((double)c + 0.5) / (double)n_ax);
+        D->kolm_prof = (double*)A(sizeof(double) * n_ax);
+        if (ok && hipMemcpy(D->kolm_prof, prof.data(), sizeof(double) * n_ax, hipMemcpyHostToDevice) != hipSuccess)
+            ok = false;
+    }
+    if (!ok) {
+        delete D;
+        psm_set_error("device allocation failed");
+        return PSMDEM_E_NOMEM;
+    }
+    int rc = 0;
+    auto H2D = [&](void* dst, const void* src, size_t n) {
+        if (n && hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, D->s) != hipSuccess) rc = PSMDEM_E_HIP;
+    };
+    if (np > 0) {
+        std::vector<int> shp(D->h_shape);
+        H2D((void*)P.shape, shp.data(), sizeof(int) * np);
+        H2D((void*)P.fixed, fixed.data(), np);
+        H2D(P.semi, semi.data(), sizeof(double) * 3 * np);
+        H2D(P.inertia, inertia.data(), sizeof(double) * 3 * np);
+        H2D(P.pos, pos.data(), sizeof(double) * 3 * np);
+        H2D(P.v, v.data(), sizeof(double) * 3 * np);
+        H2D(P.w, w.data(), sizeof(double) * 3 * np);
+        H2D(P.mass, mass.data(), sizeof(double) * np);
+        H2D(P.rb, rb.data(), sizeof(double) * np);
+        H2D(P.dens, dens.data(), sizeof(double) * np);
+        H2D(P.q, q.data(), sizeof(double) * 4 * np);
+        std::vector<double> zero(3 * (size_t)np, 0.0);
+        for (double* z : {P.a, P.al, P.fh, P.mh, P.fd, P.md, P.vp, P.wp}) H2D(z, zero.data(), sizeof(double) * 3 * np);
+    }
+    {
+        std::vector<int> z(np + 1, 0);
+        for (int b = 0; b < 2; ++b) H2D(D->prow[b], z.data(), sizeof(int) * (np + 1));
+        H2D(D->t.voff, z.data(), sizeof(int) * (np + 1));
+        std::vector<int> zt(g.ntiles + 1, 0);
+        H2D(D->t.tile_start, zt.data(), sizeof(int) * (g.ntiles + 1));
+        DevCounters c0{};
+        H2D(D->ctr, &c0, sizeof c0);
+    }
+    if (rc) {
+        delete D;
+        psm_set_error("initial copies failed");
+        return PSMDEM_E_HIP;
+    }
+    if (lbm_init(D->f, D->prec, D->N, d.rho0, D->s) != hipSuccess) {
+        delete D;
+        psm_set_error("init kernel failed");
+        return PSMDEM_E_HIP;
+    }
+    if (np > 0) {
+        // initial DEM forces: zero history, no increment (a(0) from F_dem(0) + F_ext)
+        D->cur = 0;
+        DemArgs A0 = D->dem_args(0);
+        if (dem_lists(A0, D->scan_tmp, D->s) != hipSuccess || dem_contacts(A0, P.v, P.w, 0.0, D->s) != hipSuccess ||
+            dem_initial_accel(A0, D->s) != hipSuccess || dem_zero(D->hist[0], 3 * D->pair_cap, D->s) != hipSuccess) {
+            delete D;
+            psm_set_error("initial DEM evaluation failed");
+            return PSMDEM_E_HIP;
+        }
+    }
+    if (hipStreamSynchronize(D->s) != hipSuccess) {
+        delete D;
+        psm_set_error("device error during creation: %s", hipGetErrorString(hipGetLastError()));
+        return PSMDEM_E_HIP;
+    }
+    *out = D;
+    return PSMDEM_OK;
+}
+
+extern "C" void psmdem_destroy(psmdem_domain* d) { delete d; }
+
+extern "C" psmdem_status psmdem_step(psmdem_domain* d, int64_t n) {
+    if (!d || n < 0) { psm_set_error("invalid arguments"); return PSMDEM_E_INVALID; }
+    if (d->timing) {
+        for (int k = 0; k < 4; ++k) { d->t_ms[k] = 0; d->t_n[k] = 0; }
+    }
+    for (int64_t k = 0; k < n; ++k) {
+        int rc = coupled_step(d);
+        if (rc) return (psmdem_status)rc;
+    }
+    if (d->timing) {
+        if (hipStreamSynchronize(d->s) != hipSuccess) return psm_hip_fail(hipGetLastError(), "sync", __FILE__, __LINE__);
+        d->collect_timing();
+    }
+    return PSMDEM_OK;
+}
+
+static psmdem_status sync_flags(psmdem_domain* d) {
+    PSM_CHECK(hipStreamSynchronize(d->s));
+    DevCounters c{};
+    PSM_CHECK(hipMemcpy(&c, d->ctr, sizeof c, hipMemcpyDeviceToHost));
+    if (c.flags) {
+        psm_set_error("device capacity exceeded (flags 0x%llx: 1 pairs, 2 tile list, 4 neighbours, 8 tile registrations)",
+                      (unsigned long long)c.flags);
+        return PSMDEM_E_CAPACITY;
+    }
+    return PSMDEM_OK;
+}
+
+extern "C" psmdem_status psmdem_sync(psmdem_domain* d) {
+    if (!d) return PSMDEM_E_INVALID;
+    return sync_flags(d);
+}
+
+extern "C" psmdem_status psmdem_stage(psmdem_domain* d, int32_t stage) {
+    if (!d) return PSMDEM_E_INVALID;
+    int rc = 0;
+    switch (stage) {
+        case PSMDEM_STAGE_LISTS:
+            d->cur ^= 1;
+            rc = run_lists(d);
+            break;
+        case PSMDEM_STAGE_VOXELIZE:
+            rc = run_voxelize(d);
+            break;
+        case PSMDEM_STAGE_LBM:
+            if (d->np > 0) k_kin<<<nblk(d->np), 256, 0, d->s>>>(d->p, 0);
+            rc = run_lbm(d);
+            if (!rc) d->step++;
+            break;
+        case PSMDEM_STAGE_CONTACTS: {
+            // the current list, with its own history as the previous list
+            int prev = d->cur;
+            d->cur ^= 1;
+            size_t nb = sizeof(unsigned long long) * d->pair_cap;
+            if (hipMemcpyAsync(d->pairs[d->cur], d->pairs[prev], nb, hipMemcpyDeviceToDevice, d->s) != hipSuccess ||
+                hipMemcpyAsync(d->prow[d->cur], d->prow[prev], sizeof(int) * (d->np + 1), hipMemcpyDeviceToDevice, d->s) != hipSuccess)
+                return psm_hip_fail(hipGetLastError(), "copy", __FILE__, __LINE__);
+            DemArgs A = d->dem_args(1);
+            if (dem_contacts(A, d->p.vp, d->p.wp, d->dt, d->s) != hipSuccess)
+                return psm_hip_fail(hipGetLastError(), "contacts", __FILE__, __LINE__);
+            break;
+        }
+        default:
+            psm_set_error("unknown stage %d", stage);
+            return PSMDEM_E_INVALID;
+    }
+    if (rc) return (psmdem_status)rc;
+    return sync_flags(d);
+}
+
+// ---------------------------------------------------------------------------
+// populations: decode the in-place storage on the host
+// ---------------------------------------------------------------------------
+static void host_face(const psmdem_domain* D, int x, int y, int z, int dx, int dy, int dz, long long* cell, int* face) {
+    const int c[3] = {x, y, z}, dd[3] = {dx, dy, dz};
+    const int n[3] = {D->d.nx, D->d.ny, D->d.nz};
+    int r[3];
+    *face = -1;
+    for (int a = 0; a < 3; ++a) {
+        int v = c[a] + dd[a];
+        if (v < 0 || v >= n[a]) {
+            if (D->geo.periodic[a]) v = (v + n[a]) % n[a];
+            else if (*face < 0) *face = v < 0 ? 2 * a : 2 * a + 1;
+        }
+        r[a] = v;
+    }
+    *cell = (long long)r[0] + (long long)n[0] * ((long long)r[1] + (long long)n[1] * r[2]);
+}
+
+extern "C" psmdem_status psmdem_read_populations(psmdem_domain* d, double* fout) {
+    if (!d || !fout) return PSMDEM_E_INVALID;
+    psmdem_status st = sync_flags(d);
+    if (st != PSMDEM_OK && st != PSMDEM_E_CAPACITY) return st;
+    const long long N = d->N;
+    const size_t sb = storage_bytes(d->prec);
+    std::vector<unsigned char> raw(19 * (size_t)N * sb);
+    PSM_CHECK(hipMemcpy(raw.data(), d->f, raw.size(), hipMemcpyDeviceToHost));
+    const bool odd = (d->step & 1) != 0;
+    for (long long c = 0; c < N; ++c) {
+        int x = (int)(c % d->d.nx), y = (int)((c / d->d.nx) % d->d.ny), z = (int)(c / ((long long)d->d.nx * d->d.ny));
+        for (int i = 0; i < 19; ++i) {
+            double gi;
+            if (!odd) {
+                gi = decode(raw.data(), d->prec, (long long)i * N + c);
+            } else {
+                long long src;
+                int face;
+                host_face(d, x, y, z, -CX[i], -CY[i], -CZ[i], &src, &face);
+                if (face >= 0) gi = decode(raw.data(), d->prec, (long long)i * N + c) + d->wall_corr[face][i];
+                else gi = decode(raw.data(), d->prec, (long long)OPP(i) * N + src);
+            }
+            fout[(long long)i * N + c] = gi + WT(i);
+        }
+    }
+    return PSMDEM_OK;
+}
+
+extern "C" psmdem_status psmdem_write_populations(psmdem_domain* d, const double* fin) {
+    if (!d || !fin) return PSMDEM_E_INVALID;
+    PSM_CHECK(hipStreamSynchronize(d->s));
+    const long long N = d->N;
+    const size_t sb = storage_bytes(d->prec);
+    std::vector<unsigned char> raw(19 * (size_t)N * sb);
+    const bool odd = (d->step & 1) != 0;
+    for (long long c = 0; c < N; ++c) {
+        int x = (int)(c % d->d.nx), y = (int)((c / d->d.nx) % d->d.ny), z = (int)(c / ((long long)d->d.nx * d->d.ny));
+        for (int i = 0; i < 19; ++i) {
+            double gi = fin[(long long)i * N + c] - WT(i);
+            if (!odd) {
+                encode(raw.data(), d->prec, (long long)i * N + c, gi);
+            } else {
+                long long src;
+                int face;
+                host_face(d, x, y, z, -CX[i], -CY[i], -CZ[i], &src, &face);
+                if (face >= 0) encode(raw.data(), d->prec, (long long)i * N + c, gi - d->wall_corr[face][i]);
+                else encode(raw.data(), d->prec, (long long)OPP(i) * N + src, gi);
+            }
+        }
+    }
+    PSM_CHECK(hipMemcpy(d->f, raw.data(), raw.size(), hipMemcpyHostToDevice));
+    return PSMDEM_OK;
+}
+
+extern "C" psmdem_status psmdem_read_fields(psmdem_domain* d, double* rho, double* u) {
+    if (!d) return PSMDEM_E_INVALID;
+    const long long N = d->N;
+    std::vector<double> f(19 * (size_t)N);
+    psmdem_status st = psmdem_read_populations(d, f.data());
+    if (st) return st;
+    for (long long c = 0; c < N; ++c) {
+        double r = 0, m[3] = {0, 0, 0};
+        for (int i = 0; i < 19; ++i) {
+            double fi = f[(long long)i * N + c];
+            r += fi;
+            m[0] += fi * CX[i];
+            m[1] += fi * CY[i];
+            m[2] += fi * CZ[i];
+        }
+        int x = (int)(c % d->d.nx), y = (int)((c / d->d.nx) % d->d.ny), z = (int)(c / ((long long)d->d.nx * d->d.ny));
+        double F[3] = {d->d.body_force[0], d->d.body_force[1], d->d.body_force[2]};
+        if (d->d.kolm_amp != 0.0) {
+            int ax = d->d.kolm_axis, coord = ax == 0 ? x : (ax == 1 ? y : z);
+            int n_ax = ax == 0 ? d->d.nx : (ax == 1 ? d->d.ny : d->d.nz);
+            F[d->d.kolm_dir] += d->d.kolm_amp * sin(2.0 * M_PI * ((double)coord + 0.5) / (double)n_ax);
+        }
+        if (rho) rho[c] = r;
+        if (u)
+            for (int k = 0; k < 3; ++k) u[3 * c + k] = (m[k] + 0.5 * F[k]) / r;
+    }
+    return PSMDEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// particles, pairs, cells, solid slots
+// ---------------------------------------------------------------------------
+extern "C" psmdem_status psmdem_read_particles(psmdem_domain* d, double* pos, double* quat, double* vel, double* omega,
+                                              double* acc, double* alpha, double* f_hyd, double* m_hyd, double* f_dem,
+                                              double* m_dem) {
+    if (!d) return PSMDEM_E_INVALID;
+    psmdem_status st = sync_flags(d);
+    if (st != PSMDEM_OK && st != PSMDEM_E_CAPACITY) return st;
+    size_t n3 = sizeof(double) * 3 * d->np;
+    if (d->np == 0) return PSMDEM_OK;
+    struct { double* h; double* dv; size_t n; } m[] = {
+        {pos, d->p.pos, n3}, {quat, d->p.q, sizeof(double) * 4 * d->np}, {vel, d->p.v, n3}, {omega, d->p.w, n3},
+        {acc, d->p.a, n3}, {alpha, d->p.al, n3}, {f_hyd, d->p.fh, n3}, {m_hyd, d->p.mh, n3},
+        {f_dem, d->p.fd, n3}, {m_dem, d->p.md, n3}};
+    for (auto& x : m)
+        if (x.h) PSM_CHECK(hipMemcpy(x.h, x.dv, x.n, hipMemcpyDeviceToHost));
+    return PSMDEM_OK;
+}
+
+extern "C" psmdem_status psmdem_write_particles(psmdem_domain* d, const double* pos, const double* quat,
+                                               const double* vel, const double* omega, const double* acc,
+                                               const double* alpha, const double* f_hyd, const double* m_hyd) {
+    if (!d) return PSMDEM_E_INVALID;
+    PSM_CHECK(hipStreamSynchronize(d->s));
+    if (d->np == 0) return PSMDEM_OK;
+    size_t n3 = sizeof(double) * 3 * d->np;
+    struct { const double* h; double* dv; size_t n; } m[] = {
+        {pos, d->p.pos, n3}, {quat, d->p.q, sizeof(double) * 4 * d->np}, {vel, d->p.v, n3}, {omega, d->p.w, n3},
+        {acc, d->p.a, n3}, {alpha, d->p.al, n3}, {f_hyd, d->p.fh, n3}, {m_hyd, d->p.mh, n3}};
+    for (auto& x : m)
+        if (x.h) PSM_CHECK(hipMemcpy(x.dv, x.h, x.n, hipMemcpyHostToDevice));
+    if (quat) PSM_CHECK(hipMemcpy(d->p.qold, quat, sizeof(double) * 4 * d->np, hipMemcpyHostToDevice));
+    return PSMDEM_OK;
+}
+
+extern "C" psmdem_status psmdem_read_predicted(psmdem_domain* d, double* vp, double* wp) {
+    if (!d) return PSMDEM_E_INVALID;
+    PSM_CHECK(hipStreamSynchronize(d->s));
+    if (d->np == 0) return PSMDEM_OK;
+    if (vp) PSM_CHECK(hipMemcpy(vp, d->p.vp, sizeof(double) * 3 * d->np, hipMemcpyDeviceToHost));
+    if (wp) PSM_CHECK(hipMemcpy(wp, d->p.wp, sizeof(double) * 3 * d->np, hipMemcpyDeviceToHost));
+    return PSMDEM_OK;
+}
+
+extern "C" psmdem_status psmdem_write_predicted(psmdem_domain* d, const double* vp, const double* wp) {
+    if (!d) return PSMDEM_E_INVALID;
+    PSM_CHECK(hipStreamSynchronize(d->s));
+    if (d->np == 0) return PSMDEM_OK;
+    if (vp) PSM_CHECK(hipMemcpy(d->p.vp, vp, sizeof(double) * 3 * d->np, hipMemcpyHostToDevice));
+    if (wp) PSM_CHECK(hipMemcpy(d->p.wp, wp, sizeof(double) * 3 * d->np, hipMemcpyHostToDevice));
+    return PSMDEM_OK;
+}
+
+static psmdem_status pair_count(psmdem_domain* d, int64_t* n) {
+    int v = 0;
+    if (d->np > 0) PSM_CHECK(hipMemcpy(&v, d->prow[d->cur] + d->np, sizeof(int), hipMemcpyDeviceToHost));
+    *n = v;
+    return PSMDEM_OK;
+}
+
+extern "C" psmdem_status psmdem_read_pairs(psmdem_domain* d, int64_t cap, uint64_t* keys, double* hist, int64_t* n) {
+    if (!d || !n) return PSMDEM_E_INVALID;
+    PSM_CHECK(hipStreamSynchronize(d->s));
+    int64_t np_ = 0;
+    psmdem_status st = pair_count(d, &np_);
+    if (st) return st;
+    *n = np_;
+    int64_t m = std::min<int64_t>(std::min<int64_t>(np_, cap), d->pair_cap);
+    if (m > 0 && keys) PSM_CHECK(hipMemcpy(keys, d->pairs[d->cur], sizeof(uint64_t) * m, hipMemcpyDeviceToHost));
+    if (m > 0 && hist) PSM_CHECK(hipMemcpy(hist, d->hist[d->cur], sizeof(double) * 3 * m, hipMemcpyDeviceToHost));
+    return PSMDEM_OK;
+}
+
+extern "C" psmdem_status psmdem_write_pairs(psmdem_domain* d, int64_t n, const uint64_t* keys, const double* hist) {
+    if (!d || n < 0 || (n > 0 && (!keys || !hist))) return PSMDEM_E_INVALID;
+    if (n > d->pair_cap) { psm_set_error("pair list exceeds the capacity"); return PSMDEM_E_CAPACITY; }
+    PSM_CHECK(hipStreamSynchronize(d->s));
+    // rebuild row offsets from the sorted keys
+    std::vector<int> row(d->np + 1, 0);
+    for (int64_t s = 0; s < n; ++s) {
+        uint64_t i = keys[s] >> 32;
+        if ((s > 0 && keys[s] <= keys[s - 1]) || i >= (uint64_t)d->np) {
+            psm_set_error("pair keys must be sorted, unique and index existing particles");
+            return PSMDEM_E_INVALID;
+        }
+        row[i + 1]++;
+    }
+    for (int k = 0; k < d->np; ++k) row[k + 1] += row[k];
+    if (d->np > 0) PSM_CHECK(hipMemcpy(d->prow[d->cur], row.data(), sizeof(int) * (d->np + 1), hipMemcpyHostToDevice));
+    if (n > 0) {
+        PSM_CHECK(hipMemcpy(d->pairs[d->cur], keys, sizeof(uint64_t) * n, hipMemcpyHostToDevice));
+        PSM_CHECK(hipMemcpy(d->hist[d->cur], hist, sizeof(double) * 3 * n, hipMemcpyHostToDevice));
+    }
+    return PSMDEM_OK;
+}
+
+extern "C" psmdem_status psmdem_read_contacts(psmdem_domain* d, int64_t cap, uint64_t* keys, double* force, double* m_i,
+                                             double* m_j, int64_t* n) {
+    if (!d || !n) return PSMDEM_E_INVALID;
+    PSM_CHECK(hipStreamSynchronize(d->s));
+    int64_t np_ = 0;
+    psmdem_status st = pair_count(d, &np_);
+    if (st) return st;
+    np_ = std::min<int64_t>(np_, d->pair_cap);
+    std::vector<uint64_t> k(np_);
+    std::vector<unsigned char> ic(np_);
+    std::vector<double> F(3 * np_), Mi(3 * np_), Mj(3 * np_);
+    if (np_ > 0) {
+        PSM_CHECK(hipMemcpy(k.data(), d->pairs[d->cur], sizeof(uint64_t) * np_, hipMemcpyDeviceToHost));
+        PSM_CHECK(hipMemcpy(ic.data(), d->incontact, np_, hipMemcpyDeviceToHost));
+        PSM_CHECK(hipMemcpy(F.data(), d->cF, sizeof(double) * 3 * np_, hipMemcpyDeviceToHost));
+        PSM_CHECK(hipMemcpy(Mi.data(), d->cMi, sizeof(double) * 3 * np_, hipMemcpyDeviceToHost));
+        PSM_CHECK(hipMemcpy(Mj.data(), d->cMj, sizeof(double) * 3 * np_, hipMemcpyDeviceToHost));
+    }
+    int64_t m = 0;
+    for (int64_t s = 0; s < np_; ++s) {
+        if (!ic[s]) continue;
+        if (m < cap) {
+            if (keys) keys[m] = k[s];
+            for (int c = 0; c < 3; ++c) {
+                if (force) force[3 * m + c] = F[3 * s + c];
+                if (m_i) m_i[3 * m + c] = Mi[3 * s + c];
+                if (m_j) m_j[3 * m + c] = Mj[3 * s + c];
+            }
+        }
+        ++m;
+    }
+    *n = m;
+    return PSMDEM_OK;
+}
+
+extern "C" psmdem_status psmdem_read_cells(psmdem_domain* d, int64_t cap, uint64_t* keys, int64_t* n) {
+    if (!d || !n) return PSMDEM_E_INVALID;
+    PSM_CHECK(hipStreamSynchronize(d->s));
+    *n = 0;
+    if (d->np == 0) return PSMDEM_OK;
+    std::vector<int> start(d->ncell + 1);
+    PSM_CHECK(hipMemcpy(start.data(), d->cell_start, sizeof(int) * (d->ncell + 1), hipMemcpyDeviceToHost));
+    long long tot = std::min<long long>(start[d->ncell], d->reg_cap);
+    std::vector<int> pid(std::max<long long>(tot, 1));
+    if (tot > 0) PSM_CHECK(hipMemcpy(pid.data(), d->cell_pid, sizeof(int) * tot, hipMemcpyDeviceToHost));
+    int64_t m = 0;
+    for (long long c = 0; c < d->ncell; ++c)
+        for (int s = start[c]; s < start[c + 1] && s < tot; ++s) {
+            if (m < cap && keys) keys[m] = ((uint64_t)c << 32) | (uint32_t)pid[s];
+            ++m;
+        }
+    *n = m;
+    return PSMDEM_OK;
+}
+
+extern "C" psmdem_status psmdem_read_solid(psmdem_domain* d, int64_t cap, uint32_t* cell, uint32_t* pid, double* beta,
+                                          int64_t* n) {
+    if (!d || !n) return PSMDEM_E_INVALID;
+    PSM_CHECK(hipStreamSynchronize(d->s));
+    *n = 0;
+    if (!d->voxelized) return PSMDEM_OK;
+    const GeoArgs& g = d->geo;
+    const long long plane = g.ntiles * (long long)PSM_TILE;
+    const int ms = d->d.max_solids;
+    std::vector<int> ts(g.ntiles + 1);
+    PSM_CHECK(hipMemcpy(ts.data(), d->t.tile_start, sizeof(int) * (g.ntiles + 1), hipMemcpyDeviceToHost));
+    long long tot = std::min<long long>(ts[g.ntiles], d->t.cap);
+    std::vector<unsigned long long> tl(std::max<long long>(tot, 1));
+    if (tot > 0) PSM_CHECK(hipMemcpy(tl.data(), d->t.tile_list, sizeof(unsigned long long) * tot, hipMemcpyDeviceToHost));
+    std::vector<unsigned> lp(plane);
+    std::vector<double> bt((size_t)plane * ms);
+    PSM_CHECK(hipMemcpy(lp.data(), d->t.slot_lp, sizeof(unsigned) * plane, hipMemcpyDeviceToHost));
+    PSM_CHECK(hipMemcpy(bt.data(), d->t.slot_beta, sizeof(double) * plane * ms, hipMemcpyDeviceToHost));
+    int64_t m = 0;
+    for (long long c = 0; c < d->N; ++c) {
+        int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny), z = (int)(c / ((long long)g.nx * g.ny));
+        long long t = x / PSM_TX + (long long)g.ntx * (y / PSM_TY + (long long)g.nty * (z / PSM_TZ));
+        if (ts[t + 1] <= ts[t]) continue;
+        long long l = (x % PSM_TX) + PSM_TX * ((y % PSM_TY) + PSM_TY * (z % PSM_TZ));
+        unsigned w = lp[t * PSM_TILE + l];
+        for (int k = 0; k < ms; ++k) {
+            unsigned b = (w >> (8 * k)) & 0xffu;
+            if (b == 0xffu) break;
+            long long at = ts[t] + b;
+            if (at >= tot) break;
+            if (m < cap) {
+                if (cell) cell[m] = (uint32_t)c;
+                if (pid) pid[m] = (uint32_t)(tl[at] >> 32);
+                if (beta) beta[m] = bt[(size_t)k * plane + t * PSM_TILE + l];
+            }
+            ++m;
+        }
+    }
+    *n = m;
+    return PSMDEM_OK;
+}
+
+extern "C" psmdem_status psmdem_counters(psmdem_domain* d, psmdem_counters_t* out) {
+    if (!d || !out) return PSMDEM_E_INVALID;
+    PSM_CHECK(hipStreamSynchronize(d->s));
+    DevCounters c{};
+    PSM_CHECK(hipMemcpy(&c, d->ctr, sizeof c, hipMemcpyDeviceToHost));
+    memset(out, 0, sizeof *out);
+    int64_t npairs = 0;
+    psmdem_status st = pair_count(d, &npairs);
+    if (st) return st;
+    out->n_pairs = npairs;
+    npairs = std::min<int64_t>(npairs, d->pair_cap);
+    if (npairs > 0) {
+        std::vector<unsigned char> ic(npairs);
+        PSM_CHECK(hipMemcpy(ic.data(), d->incontact, npairs, hipMemcpyDeviceToHost));
+        for (auto v : ic) out->n_contacts += v;
+    }
+    if (d->np > 0) {
+        int r = 0;
+        PSM_CHECK(hipMemcpy(&r, d->cell_start + d->ncell, sizeof(int), hipMemcpyDeviceToHost));
+        out->n_registrations = r;
+    }
+    std::vector<int> ts(d->geo.ntiles + 1);
+    PSM_CHECK(hipMemcpy(ts.data(), d->t.tile_start, sizeof(int) * ts.size(), hipMemcpyDeviceToHost));
+    for (long long t = 0; t < d->geo.ntiles; ++t) out->n_solid_tiles += ts[t + 1] > ts[t];
+    out->n_entries = (int64_t)c.entries;
+    out->n_dropped = (int64_t)c.dropped;
+    out->step = d->step;
+    out->flags = (int64_t)c.flags;
+    return PSMDEM_OK;
+}
+
+extern "C" psmdem_status psmdem_info(psmdem_domain* d, psmdem_info_t* out) {
+    if (!d || !out) return PSMDEM_E_INVALID;
+    out->n_sub = d->nsub;
+    for (int a = 0; a < 3; ++a) {
+        out->dem_cells[a] = d->nc[a];
+        out->dem_h[a] = d->h[a];
+    }
+    out->n_cells = d->N;
+    out->n_particles = d->np;
+    out->precision = d->prec;
+    out->device_bytes = (int64_t)d->bytes;
+    out->tile[0] = PSM_TX;
+    out->tile[1] = PSM_TY;
+    out->tile[2] = PSM_TZ;
+    return PSMDEM_OK;
+}
+
+extern "C" psmdem_status psmdem_set_timing(psmdem_domain* d, int32_t on) {
+    if (!d) return PSMDEM_E_INVALID;
+    d->timing = on != 0;
+    return PSMDEM_OK;
+}
+
+extern "C" psmdem_status psmdem_timing(psmdem_domain* d, int32_t which, double* avg_ms, int64_t* launches) {
+    if (!d || which < 0 || which > 3) return PSMDEM_E_INVALID;
+    if (avg_ms) *avg_ms = d->t_n[which] ? d->t_ms[which] / (double)d->t_n[which] : 0.0;
+    if (launches) *launches = d->t_n[which];
+    return PSMDEM_OK;
+}
+
+extern "C" const char* psmdem_last_error(void) { return g_err; }
+extern "C" const char* psmdem_version(void) { return "psmdem 0.1 gfx950"; }

@@ -1,0 +1,108 @@
+// scan.hip -- device-wide exclusive prefix sum of int32 counts and a fill
+// kernel.  Three launches: per-block scan of 1024 elements (256 lanes x 4),
+// a single-block scan of the block totals, and the block-offset add.
+#include "common.h"
+
+namespace {
+
+constexpr int SCAN_T = 256;
+constexpr int SCAN_PER = 4;
+constexpr int SCAN_BLOCK = SCAN_T * SCAN_PER;
+
+// block-wide exclusive scan of one int per lane (64-lane waves, LDS for the
+// wave totals); returns the block total through *total
+__device__ int block_excl_scan(int v, int* total) {
+    __shared__ int wsum[SCAN_T / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < SCAN_T / 64; ++w) {
+        if (w < wid) off += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return off + x - v;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_local(const int* __restrict__ in, int* __restrict__ out,
+                                                       long long n, int* __restrict__ bsum) {
+    long long base = (long long)blockIdx.x * SCAN_BLOCK + (long long)threadIdx.x * SCAN_PER;
+    int v[SCAN_PER];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_PER; ++k) {
+        v[k] = (base + k < n) ? in[base + k] : 0;
+        s += v[k];
+    }
+    int tot;
+    int off = block_excl_scan(s, &tot);
+#pragma unroll
+    for (int k = 0; k < SCAN_PER; ++k) {
+        if (base + k < n) out[base + k] = off;
+        off += v[k];
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// single block: exclusive scan of nb block totals, in place; total to out[n]
+__global__ __launch_bounds__(SCAN_T) void k_scan_bsum(int* __restrict__ bsum, int nb, int* __restrict__ out,
+                                                      long long n) {
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nb; base += SCAN_T) {
+        int i = base + threadIdx.x;
+        int v = i < nb ? bsum[i] : 0;
+        int tot;
+        int ex = block_excl_scan(v, &tot);
+        int c = carry;
+        if (i < nb) bsum[i] = c + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = c + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_add(int* __restrict__ out, long long n,
+                                                     const int* __restrict__ bsum) {
+    long long base = (long long)blockIdx.x * SCAN_BLOCK + (long long)threadIdx.x * SCAN_PER;
+    int add = bsum[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < SCAN_PER; ++k)
+        if (base + k < n) out[base + k] += add;
+}
+
+__global__ void k_fill_int(int* __restrict__ p, int v, long long n) {
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+size_t psm_scan_tmp_ints(long long n) { return (size_t)((n + SCAN_BLOCK - 1) / SCAN_BLOCK + 1); }
+
+hipError_t psm_scan(const int* in, int* out, long long n, int* tmp, hipStream_t s) {
+    int nb = (int)((n + SCAN_BLOCK - 1) / SCAN_BLOCK);
+    if (nb < 1) nb = 1;
+    k_scan_local<<<nb, SCAN_T, 0, s>>>(in, out, n, tmp);
+    k_scan_bsum<<<1, SCAN_T, 0, s>>>(tmp, nb, out, n);
+    k_scan_add<<<nb, SCAN_T, 0, s>>>(out, n, tmp);
+    return hipGetLastError();
+}
+
+hipError_t psm_fill_int(int* p, int v, long long n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    long long nb = (n + 255) / 256;
+    k_fill_int<<<(unsigned)nb, 256, 0, s>>>(p, v, n);
+    return hipGetLastError();
+}

@@ -1,0 +1,23 @@
+// voxel.h -- solid-fraction (voxelisation) arguments and launchers.
+#pragma once
+#include "common.h"
+
+#define VOX_AXIS_MAX 8   // distinct tiles one particle box may touch per axis
+
+struct VoxArgs {
+    GeoArgs g;
+    PartArgs p;
+    TileArgs t;
+    int* tile_count;     // [ntiles]
+    int* tile_fill;      // [ntiles]
+    int sf_method;       // 0 subdivision, 1 distance
+    int ns;              // samples per direction
+    double Rc;           // (3 / (4 pi))^(1/3)
+    double tau;
+    int ms;              // solids kept per cell
+    DevCounters* ctr;
+};
+
+hipError_t vox_register(const VoxArgs& A, int* scan_tmp, hipStream_t s);
+hipError_t vox_voxelize(const VoxArgs& A, int ctype_double, hipStream_t s);
+hipError_t vox_reduce_hydro(const VoxArgs& A, hipStream_t s);

@@ -1,0 +1,234 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle on
+the same seeded inputs.  Integer outputs (cell registrations, candidate
+pairs, solid-fraction slots) must match bit for bit; floating outputs within
+1e-12 (FP64) and 1e-5 (FP32) in the norms of the parity protocol."""
+import numpy as np
+import pytest
+
+from paper_2512_04997_amd import workloads as W
+from tests.parity import TOL, copy_state, force_err, pop_err, vec_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ps():
+    from paper_2512_04997_amd import psmdem
+    psmdem.lib()
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return psmdem
+
+
+def _pair(ps, oracle_mod, cfg, parts):
+    return ps.Domain(cfg, parts), oracle_mod.OracleDomain(cfg, parts)
+
+
+def _random_pops(N, seed, amp=0.02):
+    rng = np.random.default_rng(seed)
+    u = amp * (rng.random((N, 3)) - 0.5)
+    rho = 1.0 + 0.05 * (rng.random(N) - 0.5)
+    CI = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 0], [1, -1, 0], [1, 0, 1],
+                   [1, 0, -1], [0, 1, 1], [0, 1, -1]])
+    CI = np.concatenate([CI, -CI[1:]])
+    w = np.array([1 / 3] + [1 / 18] * 3 + [1 / 36] * 6 + [1 / 18] * 3 + [1 / 36] * 6)
+    cu = u @ CI.T
+    feq = w[None, :] * rho[:, None] * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * (u ** 2).sum(1)[:, None])
+    f = feq * (1 + 0.01 * (rng.random(feq.shape) - 0.5))
+    return f.T.copy()
+
+
+def _walled(n, tau, prec, **kw):
+    bc = ["periodic", "periodic", "noslip", "noslip", "moving", "moving"]
+    wu = [[0.0] * 3 for _ in range(6)]
+    wu[4] = [-0.02, 0.01, 0.0]
+    wu[5] = [0.02, 0.0, -0.005]
+    return W.base_config(n, tau, bc=bc, wall_u=wu, precision=prec, **kw)
+
+
+# --------------------------------------------------------------------------- LBM only
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("kind", ["periodic", "walls_forcing"])
+def test_lbm_matches_oracle(ps, oracle_mod, prec, kind):
+    """Ragged lattice (tiles of 64x4x4 cut in every axis), random near-equilibrium
+    populations; several steps cover both in-place parities."""
+    n = (70, 9, 6)
+    if kind == "periodic":
+        cfg = W.base_config(n, 0.63, precision=prec)
+    else:
+        cfg = _walled(n, 0.81, prec, body_force=[1e-5, -2e-6, 0.0], kolm_amp=3e-6, kolm_axis=2, kolm_dir=1)
+    G, O = _pair(ps, oracle_mod, cfg, None)
+    f0 = _random_pops(G.N, 11)
+    G.set_populations(f0)
+    O.set_populations(f0)
+    for steps in (1, 2, 3):
+        G.step(1)
+        O.step(1)
+        e = pop_err(G.populations(), O.populations())
+        assert e < TOL[prec], (steps, e)
+    rg, ug = G.fields()
+    ro, uo = O.fields()
+    assert vec_err(ug, uo) < 10 * TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_lbm_low_precision_storage_error_is_stated(ps, oracle_mod, prec):
+    """Shifted 16-bit storage with FP32 arithmetic: error stated, loose bound."""
+    cfg = _walled((70, 9, 6), 0.81, prec, body_force=[1e-5, 0, 0])
+    G, O = _pair(ps, oracle_mod, cfg, None)
+    f0 = _random_pops(G.N, 12)
+    G.set_populations(f0)
+    O.set_populations(f0)
+    G.step(4)
+    O.step(4)
+    e = pop_err(G.populations(), O.populations())
+    print(f"{prec} population error after 4 steps: {e:.3e}")
+    assert e < (1e-3 if prec == "bf16" else 1e-4)
+
+
+# --------------------------------------------------------------------------- stages
+def _mixed_particles(seed, n, box, periodic, ell_frac=0.5, gap=0.3):
+    rng = W.SplitMix64(seed)
+    radii = 2.0 + 2.0 * rng.uniform(n)
+    pos = W.rsa_spheres(rng, n, radii * 1.6, box, periodic, gap=gap)
+    m = len(pos)
+    shape = (rng.uniform(m) < ell_frac).astype(np.int32)
+    semi = np.stack([radii[:m] * 1.6, radii[:m], radii[:m] * 0.8], 1)
+    semi[shape == 0] = (radii[:m] * 1.2)[shape == 0, None]
+    return dict(shape=shape, semi=semi, dens=1.3 + rng.uniform(m), pos=pos,
+                quat=W.shoemake_quaternions(rng, m),
+                vel=0.01 * (rng.uniform(3 * m).reshape(m, 3) - 0.5),
+                omega=0.002 * (rng.uniform(3 * m).reshape(m, 3) - 0.5), fixed=np.zeros(m, np.uint8))
+
+
+@pytest.mark.parametrize("walls", [False, True])
+@pytest.mark.parametrize("method", ["subdivision", "distance"])
+def test_voxelize_bitexact(ps, oracle_mod, walls, method):
+    box = (72, 36, 32)
+    periodic = [True, True, not walls]
+    parts = _mixed_particles(101 + walls, 40, box, periodic, ell_frac=0.0 if method == "distance" else 0.5)
+    if walls:
+        cfg = _walled(box, 0.7, "fp64", sf_method=method, max_solids=2)
+    else:
+        cfg = W.base_config(box, 0.7, sf_method=method, max_solids=2)
+    G, O = _pair(ps, oracle_mod, cfg, parts)
+    G.stage("voxelize")
+    O.stage_voxelize()
+    cg, pg, bg = G.solid()
+    co, po, bo = O.solid()
+    assert len(co) > 1000
+    assert np.array_equal(cg, co) and np.array_equal(pg, po)
+    if method == "subdivision":
+        assert np.array_equal(bg, bo)
+    else:
+        assert np.max(np.abs(bg - bo)) < 1e-14
+    assert G.counters()["n_dropped"] == O.counters()["overflow"]
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_dem_lists_bitexact(ps, oracle_mod, walls):
+    box = (72, 60, 52)
+    periodic = [True, True, not walls]
+    parts = _mixed_particles(201 + walls, 120, box, periodic, gap=-1.0)
+    cfg = _walled(box, 0.7, "fp64", fluid_on=False) if walls else W.base_config(box, 0.7, fluid_on=False)
+    G, O = _pair(ps, oracle_mod, cfg, parts)
+    G.stage("lists")
+    O.stage_lists()
+    assert np.array_equal(G.cells(), O.cells())
+    kg, _ = G.pairs()
+    ko, _ = O.pairs()
+    assert len(ko) > 50
+    assert np.array_equal(kg, ko)
+    assert np.array_equal(ko, O.brute_pairs())
+
+
+def test_contacts_match(ps, oracle_mod):
+    """Overlapping spheres and ellipsoids with walls: contact forces, torques and
+    history from a shared state (pairs and history written to both)."""
+    box = (64, 48, 40)
+    parts = _mixed_particles(301, 90, box, [True, True, False], gap=-3.5)
+    cfg = _walled(box, 0.7, "fp64", fluid_on=False, mu=0.3, restitution=0.7, n_sub=8)
+    G, O = _pair(ps, oracle_mod, cfg, parts)
+    O.stage_lists()
+    k, _ = O.pairs()
+    rng = np.random.default_rng(3)
+    hist = 0.05 * (rng.random((len(k), 3)) - 0.5)
+    for D in (G, O):
+        D.set_pairs(k, hist)
+    vp = parts["vel"] * 1.1
+    wp = parts["omega"] * 0.9
+    G.set_predicted(vp, wp)
+    O.set_predicted(vp, wp)
+    G.stage("contacts")
+    O.stage_contacts()
+    kc, Fg, mig, mjg = G.contacts()
+    ko, Fo, mio, mjo = O.contacts()
+    assert len(ko) > 20
+    assert np.array_equal(kc, ko)
+    assert np.abs(Fg - Fo).max() <= 1e-12 * np.abs(Fo).max()
+    assert np.abs(mig - mio).max() <= 1e-12 * np.abs(mio).max()
+    assert np.abs(mjg - mjo).max() <= 1e-12 * np.abs(mjo).max()
+    _, hg = G.pairs()
+    _, ho = O.pairs()
+    assert np.abs(hg - ho).max() <= 1e-12 * max(np.abs(ho).max(), 1e-12)
+
+
+# --------------------------------------------------------------------------- coupled
+def test_settling_sphere_trajectory_fp64(ps, oracle_mod):
+    """Plain method, FP64: 32^3 periodic, tau = 0.8, one sphere R = 4 settling
+    with density ratio 2 under gravity 1e-5, 200 steps; the whole trajectory
+    holds the FP64 bar."""
+    cfg, parts, meta = W.settling_sphere()
+    G, O = _pair(ps, oracle_mod, cfg, parts)
+    worst = {"pop": 0.0, "pos": 0.0, "vel": 0.0, "f": 0.0}
+    for chunk in (1, 1, 8, 40, 150):
+        G.step(chunk)
+        O.step(chunk)
+        worst["pop"] = max(worst["pop"], pop_err(G.populations(), O.populations()))
+        Pg, Po = G.particles(), O.particles()
+        worst["pos"] = max(worst["pos"], vec_err(Pg["pos"], Po["pos"]))
+        worst["vel"] = max(worst["vel"], vec_err(Pg["vel"], Po["vel"], 1e-6))
+        sc = O.scales()
+        worst["f"] = max(worst["f"], force_err(Pg["f_hyd"], Po["f_hyd"], sc["f_hyd"]),
+                         force_err(Pg["m_hyd"], Po["m_hyd"], sc["m_hyd"]))
+    print("settling sphere worst errors over 200 steps:", worst)
+    assert worst["pop"] < 1e-12 and worst["pos"] < 1e-12 and worst["vel"] < 1e-12 and worst["f"] < 1e-12
+    assert O.counters()["step"] == 200
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_couette_suspension_steps(ps, oracle_mod, prec):
+    """Bounded Couette shear with spheres (48^3, moving walls, contacts and wall
+    contacts): three coupled steps from creation."""
+    cfg, parts, _ = W.couette_suspension(precision=prec, n=48, nsph=30, radius=4.0)
+    cfg["mu"] = 0.3
+    G, O = _pair(ps, oracle_mod, cfg, parts)
+    assert G.n_sub == O.n_sub
+    for _ in range(3):
+        G.step(1)
+        O.step(1)
+        assert np.array_equal(G.pairs()[0], O.pairs()[0])
+        cg, pg, bg = G.solid()
+        co, po, bo = O.solid()
+        assert np.array_equal(cg, co) and np.array_equal(pg, po)
+        assert pop_err(G.populations(), O.populations()) < TOL[prec]
+        Pg, Po = G.particles(), O.particles()
+        assert vec_err(Pg["pos"], Po["pos"]) < TOL[prec]
+        assert vec_err(Pg["vel"], Po["vel"], 1e-4) < TOL[prec]
+        sc = O.scales()
+        assert force_err(Pg["f_hyd"], Po["f_hyd"], sc["f_hyd"]) < TOL[prec]
+        assert force_err(Pg["f_dem"], Po["f_dem"], sc["f_dem"]) < TOL[prec]
+
+
+def test_determinism_bitwise(ps):
+    """No floating-point atomics: two runs are bitwise identical."""
+    cfg, parts, _ = W.couette_suspension(precision="fp32", n=48, nsph=30, radius=4.0)
+    out = []
+    for _ in range(2):
+        G = ps.Domain(cfg, parts)
+        G.step(4)
+        P = G.particles()
+        out.append((G.populations(), P["pos"], P["f_hyd"], P["m_hyd"]))
+        G.close()
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
