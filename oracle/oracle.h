@@ -70,8 +70,11 @@ void or_set_particles(or_domain* D, const double* pos, const double* quat,
                       const double* vel, const double* omega, const double* acc,
                       const double* alpha, const double* fh, const double* mh);
 void or_get_predicted(const or_domain* D, double* vp, double* wp);
-/* per-component sums of |summand| of the last hydrodynamic and DEM sums: the
- * scale against which force parity is measured */
+/* scales of the last hydrodynamic and DEM sums against which force parity is
+ * measured: for F_hyd / M_hyd the per-component L1 norm of the population-level
+ * summands of the momentum exchange (|f| and |f^eq| terms times |c_i|, times
+ * |r_j - r_k| for the torque), which bounds their rounding; for F_dem / M_dem
+ * the L1 norm of the pair forces and torques */
 void or_get_scales(const or_domain* D, double* fh1, double* mh1, double* fd1, double* md1);
 int64_t or_get_pairs(const or_domain* D, int64_t cap, uint64_t* keys, double* hist);
 void or_set_pairs(or_domain* D, int64_t n, const uint64_t* keys, const double* hist);

@@ -13,6 +13,7 @@ struct LbmArgs {
     double wall_corr[6][19];   // 6 w_i rho0 (c_i . u_w) per walled face (0 for no-slip)
     TileArgs t;
     const double* kin;         // [9 np] position, v^p, w^p
+    int np;
     int ms;
     double L[3];
 };

@@ -266,9 +266,13 @@ __global__ __launch_bounds__(256) void k_lbm(LbmArgs A) {
     if (PSM) {
         for (int u = tid; u < count * 9; u += 256) {
             int k = (int)(A.t.tile_list[s0 + u / 9] >> 32);
+            if (k >= A.np) k = 0;
             kin_s[u] = A.kin[9 * k + u % 9];
         }
-        for (int u = tid; u < 4 * count * 6; u += 256) acc[u] = 0.0;
+        for (int u = tid; u < 4 * count * 6; u += 256) {
+            const int w = u / (count * 6), r = u % (count * 6);
+            acc[w * PSM_PMAX * 6 + r] = 0.0;
+        }
         __syncthreads();
     }
     const int tx = (int)(t % A.g.ntx), ty = (int)((t / A.g.ntx) % A.g.nty);

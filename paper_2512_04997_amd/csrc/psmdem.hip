@@ -254,6 +254,7 @@ struct psmdem_domain {
         memcpy(A.wall_corr, wall_corr, sizeof wall_corr);
         A.t = t;
         A.kin = p.kin;
+        A.np = np;
         A.ms = d.max_solids;
         return A;
     }
@@ -604,7 +605,9 @@ extern "C" psmdem_status psmdem_create(const psmdem_desc* desc, const psmdem_par
     }
     int rc = 0;
     auto H2D = [&](void* dst, const void* src, size_t n) {
-        if (n && hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, D->s) != hipSuccess) rc = PSMDEM_E_HIP;
+        if (n && (hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, D->s) != hipSuccess ||
+                  hipStreamSynchronize(D->s) != hipSuccess))
+            rc = PSMDEM_E_HIP;
     };
     if (np > 0) {
         std::vector<int> shp(D->h_shape);
@@ -630,6 +633,13 @@ extern "C" psmdem_status psmdem_create(const psmdem_desc* desc, const psmdem_par
         H2D(D->t.tile_start, zt.data(), sizeof(int) * (g.ntiles + 1));
         DevCounters c0{};
         H2D(D->ctr, &c0, sizeof c0);
+        // registration lists start out valid (particle 0, entry 0)
+        if (hipMemsetAsync(D->t.tile_list, 0, sizeof(unsigned long long) * D->t.cap, D->s) != hipSuccess ||
+            hipMemsetAsync(D->t.vinv, 0, sizeof(int) * D->t.cap, D->s) != hipSuccess ||
+            hipMemsetAsync(D->t.slot_lp, 0xff, sizeof(unsigned) * g.ntiles * (size_t)PSM_TILE, D->s) != hipSuccess ||
+            hipMemsetAsync(D->cell_pid, 0, sizeof(int) * D->reg_cap, D->s) != hipSuccess ||
+            hipStreamSynchronize(D->s) != hipSuccess)
+            rc = PSMDEM_E_HIP;
     }
     if (rc) {
         delete D;

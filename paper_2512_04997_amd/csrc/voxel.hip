@@ -298,6 +298,7 @@ __global__ __launch_bounds__(256) void k_voxelize(VoxArgs A) {
     if (tid == 0) { cnt_e = 0; cnt_d = 0; }
     for (int u = tid; u < count; u += blockDim.x) {
         int k = (int)(A.t.tile_list[s0 + u] >> 32);
+        if (k >= A.p.np) k = 0;
         VoxPart& P = sp[u];
         P.pid = k;
         P.shape = A.p.shape[k];
@@ -378,6 +379,7 @@ __global__ void k_reduce_hydro(VoxArgs A) {
     int e0 = A.t.voff[k], e1 = A.t.voff[k + 1];
     for (int e = e0; e < e1 && e < A.t.cap; ++e) {
         long long s = A.t.vinv[e];
+        if (s < 0 || s >= A.t.cap) continue;
         const double* P = A.t.partial + 6 * s;
         for (int c = 0; c < 3; ++c) {
             F[c] -= P[c];

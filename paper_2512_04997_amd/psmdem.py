@@ -76,6 +76,10 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                            "(the HIP library is the only compute path)")
+    # torch first: the library's libamdhip64.so.7 then resolves to the HIP
+    # runtime torch already loaded, so one runtime owns the device, the streams
+    # and the memory of the process
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     P = C.c_void_p
     st = C.c_int

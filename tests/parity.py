@@ -18,15 +18,22 @@ def vec_err(a, b, floor=1e-3):
     return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)) if np.size(b) else 0.0, floor))
 
 
-def force_err(a, b, scale):
-    """Forces normalised per component by the L1 norm of their summands."""
+def force_floor(oracle_dom, accel=1e-6):
+    """Per-particle force floor: the force accelerating the particle's volume of
+    fluid by `accel` per step.  Summands that are pure round-off (a body at rest
+    in fluid at rest) are measured against it rather than against themselves."""
+    m = oracle_dom.mass()
+    dens = np.asarray(oracle_dom._keep["dens"], dtype=np.float64)
+    return (accel * m / dens)[:, None]
+
+
+def force_err(a, b, scale, floor=0.0):
+    """Forces normalised per component by the L1 norm of their summands (floored)."""
     a, b, scale = (np.asarray(x, dtype=np.float64) for x in (a, b, scale))
     if a.size == 0:
         return 0.0
-    s = np.maximum(scale, 1e-300)
-    err = np.abs(a - b) / s
-    err[scale == 0] = np.abs(a - b)[scale == 0] / 1e-30
-    return float(err.max())
+    s = np.maximum(np.maximum(scale, floor), 1e-300)
+    return float((np.abs(a - b) / s).max())
 
 
 def copy_state(src, dst, pairs=True):

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2512_04997_amd import workloads as W
-from tests.parity import TOL, copy_state, force_err, pop_err, vec_err
+from tests.parity import TOL, copy_state, force_err, force_floor, pop_err, vec_err
 
 pytestmark = pytest.mark.gpu
 
@@ -187,7 +187,7 @@ def test_settling_sphere_trajectory_fp64(ps, oracle_mod):
         worst["pop"] = max(worst["pop"], pop_err(G.populations(), O.populations()))
         Pg, Po = G.particles(), O.particles()
         worst["pos"] = max(worst["pos"], vec_err(Pg["pos"], Po["pos"]))
-        worst["vel"] = max(worst["vel"], vec_err(Pg["vel"], Po["vel"], 1e-6))
+        worst["vel"] = max(worst["vel"], vec_err(Pg["vel"], Po["vel"]))
         sc = O.scales()
         worst["f"] = max(worst["f"], force_err(Pg["f_hyd"], Po["f_hyd"], sc["f_hyd"]),
                          force_err(Pg["m_hyd"], Po["m_hyd"], sc["m_hyd"]))
@@ -214,10 +214,12 @@ def test_couette_suspension_steps(ps, oracle_mod, prec):
         assert pop_err(G.populations(), O.populations()) < TOL[prec]
         Pg, Po = G.particles(), O.particles()
         assert vec_err(Pg["pos"], Po["pos"]) < TOL[prec]
-        assert vec_err(Pg["vel"], Po["vel"], 1e-4) < TOL[prec]
+        assert vec_err(Pg["vel"], Po["vel"]) < TOL[prec]
         sc = O.scales()
+        fl = force_floor(O)
         assert force_err(Pg["f_hyd"], Po["f_hyd"], sc["f_hyd"]) < TOL[prec]
-        assert force_err(Pg["f_dem"], Po["f_dem"], sc["f_dem"]) < TOL[prec]
+        assert force_err(Pg["m_hyd"], Po["m_hyd"], sc["m_hyd"]) < TOL[prec]
+        assert force_err(Pg["f_dem"], Po["f_dem"], sc["f_dem"], fl) < TOL[prec]
 
 
 def test_determinism_bitwise(ps):
