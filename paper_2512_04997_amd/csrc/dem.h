@@ -2,6 +2,9 @@
 #pragma once
 #include "common.h"
 
+// particles up to this count take the fused single-workgroup substep kernel
+#define DEM_FUSED_MAX 2048
+
 struct DemArgs {
     GeoArgs g;
     PartArgs p;
@@ -9,29 +12,51 @@ struct DemArgs {
     int nc[3];
     double h[3];
     long long ncell;
+    int* pc;               // [8 np] per-axis registration cells of each particle
     int* cell_count;       // [ncell]
     int* cell_start;       // [ncell + 1]
     int* cell_fill;        // [ncell]
     int* cell_pid;         // [reg_cap] particle ids per cell, ascending
     long long reg_cap;
     int* pcount;           // [np] pairs per row
-    int* prow;             // [np + 1] row offsets; prow[np] = number of pairs
-    unsigned long long* pairs;  // [pair_cap] (i << 32 | j), ascending
-    double *hist, *cF, *cMi, *cMj;  // [3 pair_cap]
+    double *cF, *cMi, *cMj;         // [3 pair_cap] force on i, torque on i, torque on j
     unsigned char* incontact;       // [pair_cap]
+    int *col_count, *col_fill;      // [np]
+    int* col_start;                 // [np + 1]
+    int* col_list;                  // [pair_cap] pair indices by second member, ascending
     long long pair_cap;
-    const unsigned long long* prev_pairs;  // previous substep's list
-    const double* prev_hist;
-    const int* prev_n;     // device count of the previous list (NULL: empty)
     double kn, beta_e, mu, kt_ratio, gt_ratio;
     double wall_u[6][3];
     double gravity[3];
     DevCounters* ctr;
 };
 
+// the current and the previous substep's pair lists
+struct PairBufs {
+    unsigned long long* pairs;   // [pair_cap] (i << 32 | j), ascending
+    int* prow;                   // [np + 1] row offsets; prow[np] = number of pairs
+    double* hist;                // [3 pair_cap] tangential history
+    const unsigned long long* prev_pairs;
+    const double* prev_hist;
+    const int* prev_n;           // device count of the previous list (NULL: empty)
+};
+
+// both pair buffers for the fused kernel (substeps alternate between them)
+struct PairSet {
+    unsigned long long* pairs[2];
+    int* prow[2];
+    double* hist[2];
+};
+
 hipError_t dem_predict(const DemArgs& A, double dt, int write_kin, hipStream_t s);
-hipError_t dem_lists(const DemArgs& A, int* scan_tmp, hipStream_t s);
-hipError_t dem_contacts(const DemArgs& A, const double* vv, const double* ww, double dth, hipStream_t s);
+hipError_t dem_lists(const DemArgs& A, const PairBufs& B, int* scan_tmp, hipStream_t s);
+hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, const double* ww, double dth,
+                        int* scan_tmp, hipStream_t s);
 hipError_t dem_correct(const DemArgs& A, double dt, hipStream_t s);
 hipError_t dem_initial_accel(const DemArgs& A, hipStream_t s);
 hipError_t dem_zero(double* p, long long n, hipStream_t s);
+// nsub substeps in one workgroup starting from buffer `cur` (the first substep
+// writes buffer cur ^ 1); with stop_before_correct the last substep ends after
+// the DEM sums (the corrector then runs after the fluid coupling)
+hipError_t dem_fused(const DemArgs& A, const PairSet& P, int cur, int nsub, double dt, int stop_before_correct,
+                     hipStream_t s);

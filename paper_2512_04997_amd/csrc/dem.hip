@@ -2,20 +2,24 @@
 // that the predicates deciding integer results (cell indices, contact flags)
 // use separately rounded operations in a fixed order.
 //
-// Per substep (Sec. 3.2.1-3.2.2, Table 1):
-//   k_predict          Verlet predictor of position and orientation (Eqs. advance-r ...)
-//   k_reg_hist         DEM cells of each particle's axis-aligned box -> cell histogram
-//   (scan)             cell offsets
-//   k_reg_scatter      counting-sort scatter of particle ids into cells
-//   k_cell_sort        order each cell's ids (deterministic lists)
-//   k_pair_count/emit  per particle i the unique neighbours j > i sharing a cell,
-//                      then wall candidates: the sorted unique pair list built per
-//                      row, so no global sort or unique pass is needed
-//   k_contacts         spring-dashpot + Coulomb per pair, history by binary search
-//                      in the previous sorted list
-//   k_dem_sum          per particle: second-member pairs (k, i) then first-member
-//                      pairs (i, j), a fixed order
-//   k_correct          Verlet corrector
+// A substep (Sec. 3.2.1-3.2.2, Table 1), as per-index phases:
+//   predict      Verlet predictor of position and orientation (Eqs. advance-r ...)
+//                and the particle's DEM cells per axis (box of the particle)
+//   cell list    counting sort of (cell, pid) registrations: histogram, scan,
+//                scatter, per-cell order by pid
+//   pairs        per particle i the unique j > i sharing a cell (each j counted in
+//                the lowest shared cell), then wall candidates; rows emitted and
+//                ordered in place, so the list is sorted and unique without a
+//                global sort
+//   contacts     spring-dashpot + Coulomb per pair, history by binary search in the
+//                previous sorted list
+//   sums         per particle: pairs where it is the second member (counting-sorted
+//                columns, ascending pair index) then its own row, a fixed order
+//   correct      Verlet corrector
+// Large particle counts run each phase as a kernel.  Up to DEM_FUSED_MAX
+// particles, one workgroup runs every substep of a coupled step in a single
+// launch; there the candidate pairs come from testing all i < j for a shared
+// cell, the same set in the same order as the cell list gives.
 #include <math.h>
 
 #include "common.h"
@@ -72,39 +76,83 @@ __device__ inline void half_extents(const DemArgs& A, int k, double e[3]) {
     }
 }
 
-// DEM cells touched by particle k's box, sorted ascending; returns the count (<= 8)
-__device__ int dem_cells(const DemArgs& A, int k, long long out[8]) {
+// ---------------------------------------------------------------------------
+// registration cells: per axis the sorted DEM cells of the particle's box
+// lo = floor((x - e)/h) .. hi = floor((x + e)/h), wrapped on periodic axes and
+// clamped on walled ones (at most two per axis: h exceeds every diameter)
+// ---------------------------------------------------------------------------
+struct AxCells {
+    int c[3][2];
+    int n[3];
+};
+
+__device__ inline void axis_cells(const DemArgs& A, int k, AxCells& r) {
     double e[3];
     half_extents(A, k, e);
-    int list[3][2];
-    int nl[3];
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
         double x = A.p.pos[3 * k + a];
         int lo = (int)floor((x - e[a]) / A.h[a]);
         int hi = (int)floor((x + e[a]) / A.h[a]);
-        nl[a] = 0;
-        for (int c = lo; c <= hi && nl[a] < 2; ++c) {
-            int cw = c;
-            if (A.g.periodic[a]) cw = ((c % A.nc[a]) + A.nc[a]) % A.nc[a];
-            else cw = cw < 0 ? 0 : (cw > A.nc[a] - 1 ? A.nc[a] - 1 : cw);
-            bool dup = false;
-            for (int u = 0; u < nl[a]; ++u) dup |= (list[a][u] == cw);
-            if (!dup) list[a][nl[a]++] = cw;
+        int c0 = lo, c1 = lo + 1 <= hi ? lo + 1 : lo;
+        if (A.g.periodic[a]) {
+            c0 = ((c0 % A.nc[a]) + A.nc[a]) % A.nc[a];
+            c1 = ((c1 % A.nc[a]) + A.nc[a]) % A.nc[a];
+        } else {
+            c0 = c0 < 0 ? 0 : (c0 > A.nc[a] - 1 ? A.nc[a] - 1 : c0);
+            c1 = c1 < 0 ? 0 : (c1 > A.nc[a] - 1 ? A.nc[a] - 1 : c1);
         }
+        if (c1 < c0) {
+            int t = c0;
+            c0 = c1;
+            c1 = t;
+        }
+        r.c[a][0] = c0;
+        r.c[a][1] = c1;
+        r.n[a] = c1 == c0 ? 1 : 2;
     }
-    int n = 0;
-    for (int i = 0; i < nl[0]; ++i)
-        for (int j = 0; j < nl[1]; ++j)
-            for (int l = 0; l < nl[2]; ++l)
-                out[n++] = (long long)list[0][i] +
-                           (long long)A.nc[0] * ((long long)list[1][j] + (long long)A.nc[1] * list[2][l]);
-    for (int u = 1; u < n; ++u)
-        for (int v = u; v > 0 && out[v] < out[v - 1]; --v) {
-            long long t = out[v];
-            out[v] = out[v - 1];
-            out[v - 1] = t;
-        }
-    return n;
+}
+
+__device__ inline void store_cells(const DemArgs& A, int k, const AxCells& r) {
+    int* d = A.pc + 8 * k;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        d[2 * a] = r.c[a][0];
+        d[2 * a + 1] = r.c[a][1];
+    }
+    d[6] = r.n[0] | (r.n[1] << 2) | (r.n[2] << 4);
+}
+
+__device__ inline void load_cells(const DemArgs& A, int k, AxCells& r) {
+    const int* d = A.pc + 8 * k;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r.c[a][0] = d[2 * a];
+        r.c[a][1] = d[2 * a + 1];
+    }
+    r.n[0] = d[6] & 3;
+    r.n[1] = (d[6] >> 2) & 3;
+    r.n[2] = (d[6] >> 4) & 3;
+}
+
+__device__ inline long long cell_id(const DemArgs& A, int x, int y, int z) {
+    return (long long)x + (long long)A.nc[0] * ((long long)y + (long long)A.nc[1] * z);
+}
+
+// lowest common cell along one axis, -1 if none
+__device__ inline int axis_common(const AxCells& p, const AxCells& q, int a) {
+    int best = -1;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 2; ++v)
+            if (u < p.n[a] && v < q.n[a] && p.c[a][u] == q.c[a][v] && (best < 0 || p.c[a][u] < best))
+                best = p.c[a][u];
+    return best;
+}
+
+__device__ inline bool share_cell(const AxCells& p, const AxCells& q) {
+    return axis_common(p, q, 0) >= 0 && axis_common(p, q, 1) >= 0 && axis_common(p, q, 2) >= 0;
 }
 
 __device__ inline double wall_dist(const DemArgs& A, int k, int f) {
@@ -112,43 +160,10 @@ __device__ inline double wall_dist(const DemArgs& A, int k, int f) {
     return (f % 2 == 0) ? A.p.pos[3 * k + a] : A.L[a] - A.p.pos[3 * k + a];
 }
 
-// is pid in the (pid-sorted) list of cell c?
-__device__ inline bool cell_has(const DemArgs& A, long long c, int pid) {
-    int lo = A.cell_start[c], hi = A.cell_start[c + 1];
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (A.cell_pid[mid] < pid) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo < A.cell_start[c + 1] && A.cell_pid[lo] == pid;
-}
-
-// unique neighbours of i sharing a cell, j > i (upper) or j < i (lower), ascending.
-// Each j is taken from the first cell of i (ascending) that also holds j.
-__device__ int neighbours(const DemArgs& A, int i, bool upper, int* nb, bool* overflow) {
-    long long ci[8];
-    int nci = dem_cells(A, i, ci);
+__device__ inline int wall_count(const DemArgs& A, int i) {
     int n = 0;
-    for (int u = 0; u < nci; ++u) {
-        int s0 = A.cell_start[ci[u]], s1 = A.cell_start[ci[u] + 1];
-        for (int s = s0; s < s1; ++s) {
-            int j = A.cell_pid[s];
-            if (upper ? (j <= i) : (j >= i)) continue;
-            bool seen = false;
-            for (int v = 0; v < u && !seen; ++v) seen = cell_has(A, ci[v], j);
-            if (seen) continue;
-            if (n >= PSM_MAXNB) {
-                *overflow = true;
-                continue;
-            }
-            int t = n++;
-            while (t > 0 && nb[t - 1] > j) {
-                nb[t] = nb[t - 1];
-                --t;
-            }
-            nb[t] = j;
-        }
-    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) n += (A.g.bc[f] != 0 && wall_dist(A, i, f) < A.p.rb[i]);
     return n;
 }
 
@@ -331,32 +346,37 @@ __device__ void pair_geometry(const DemArgs& A, int i, int j, Geom& G) {
 }
 
 // ---------------------------------------------------------------------------
-// kernels
+// phases (one index each)
 // ---------------------------------------------------------------------------
-__global__ void k_reg_hist(DemArgs A) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= A.p.np) return;
-    long long c[8];
-    int n = dem_cells(A, k, c);
-    for (int u = 0; u < n; ++u) atomicAdd(&A.cell_count[c[u]], 1);
+__device__ void ph_cells(const DemArgs& A, int k) {
+    AxCells r;
+    axis_cells(A, k, r);
+    store_cells(A, k, r);
 }
 
-__global__ void k_reg_scatter(DemArgs A) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= A.p.np) return;
-    long long c[8];
-    int n = dem_cells(A, k, c);
-    for (int u = 0; u < n; ++u) {
-        int slot = atomicAdd(&A.cell_fill[c[u]], 1);
-        long long at = (long long)A.cell_start[c[u]] + slot;
-        if (at < A.reg_cap) A.cell_pid[at] = k;
-    }
+__device__ void ph_hist(const DemArgs& A, int k) {
+    AxCells r;
+    load_cells(A, k, r);
+    for (int z = 0; z < r.n[2]; ++z)
+        for (int y = 0; y < r.n[1]; ++y)
+            for (int x = 0; x < r.n[0]; ++x) atomicAdd(&A.cell_count[cell_id(A, r.c[0][x], r.c[1][y], r.c[2][z])], 1);
 }
 
-__global__ void k_cell_sort(DemArgs A) {
-    long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= A.ncell) return;
-    int s0 = A.cell_start[c], s1 = A.cell_start[c + 1];
+__device__ void ph_scatter(const DemArgs& A, int k) {
+    AxCells r;
+    load_cells(A, k, r);
+    for (int z = 0; z < r.n[2]; ++z)
+        for (int y = 0; y < r.n[1]; ++y)
+            for (int x = 0; x < r.n[0]; ++x) {
+                const long long c = cell_id(A, r.c[0][x], r.c[1][y], r.c[2][z]);
+                const int slot = atomicAdd(&A.cell_fill[c], 1);
+                const long long at = (long long)A.cell_start[c] + slot;
+                if (at < A.reg_cap) A.cell_pid[at] = k;
+            }
+}
+
+__device__ void ph_cellsort(const DemArgs& A, long long c) {
+    const int s0 = A.cell_start[c], s1 = A.cell_start[c + 1];
     for (int u = s0 + 1; u < s1; ++u)
         for (int v = u; v > s0 && A.cell_pid[v] < A.cell_pid[v - 1]; --v) {
             int t = A.cell_pid[v];
@@ -365,49 +385,96 @@ __global__ void k_cell_sort(DemArgs A) {
         }
 }
 
-__global__ void k_pair_count(DemArgs A) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.p.np) return;
-    int nb[PSM_MAXNB];
-    bool ovf = false;
-    int n = neighbours(A, i, true, nb, &ovf);
+// neighbours j > i through the cell lists; emit: write them (cell order) at out
+__device__ int pairs_by_cells(const DemArgs& A, int i, unsigned long long* out, long long room) {
+    AxCells ri;
+    load_cells(A, i, ri);
+    int n = 0;
+    for (int z = 0; z < ri.n[2]; ++z)
+        for (int y = 0; y < ri.n[1]; ++y)
+            for (int x = 0; x < ri.n[0]; ++x) {
+                const long long c = cell_id(A, ri.c[0][x], ri.c[1][y], ri.c[2][z]);
+                const int s0 = A.cell_start[c], s1 = A.cell_start[c + 1];
+                for (int s = s0; s < s1; ++s) {
+                    const int j = A.cell_pid[s];
+                    if (j <= i) continue;
+                    AxCells rj;
+                    load_cells(A, j, rj);
+                    // count j in the lowest cell the two share
+                    if (axis_common(ri, rj, 0) != ri.c[0][x] || axis_common(ri, rj, 1) != ri.c[1][y] ||
+                        axis_common(ri, rj, 2) != ri.c[2][z])
+                        continue;
+                    if (out && n < room) out[n] = ((unsigned long long)i << 32) | (unsigned)j;
+                    ++n;
+                }
+            }
+    return n;
+}
+
+// neighbours j > i by testing every j (small particle counts), ascending
+__device__ int pairs_all(const DemArgs& A, int i, unsigned long long* out, long long room) {
+    AxCells ri;
+    load_cells(A, i, ri);
+    int n = 0;
+    for (int j = i + 1; j < A.p.np; ++j) {
+        AxCells rj;
+        load_cells(A, j, rj);
+        if (!share_cell(ri, rj)) continue;
+        if (out && n < room) out[n] = ((unsigned long long)i << 32) | (unsigned)j;
+        ++n;
+    }
+    return n;
+}
+
+__device__ inline void emit_walls(const DemArgs& A, int i, unsigned long long* out, long long room, int n0) {
+    int n = n0;
+    const unsigned long long np = (unsigned long long)A.p.np;
     for (int f = 0; f < 6; ++f)
-        if (A.g.bc[f] != 0 && wall_dist(A, i, f) < A.p.rb[i]) ++n;
-    if (ovf) atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_NEIGH);
+        if (A.g.bc[f] != 0 && wall_dist(A, i, f) < A.p.rb[i]) {
+            if (n < room) out[n] = ((unsigned long long)i << 32) | (unsigned)(np + f);
+            ++n;
+        }
+}
+
+template <bool ALL>
+__device__ void ph_paircount(const DemArgs& A, int i) {
+    const int n = (ALL ? pairs_all(A, i, nullptr, 0) : pairs_by_cells(A, i, nullptr, 0)) + wall_count(A, i);
     A.pcount[i] = n;
 }
 
-__global__ void k_pair_emit(DemArgs A) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.p.np) return;
-    int nb[PSM_MAXNB];
-    bool ovf = false;
-    int n = neighbours(A, i, true, nb, &ovf);
-    long long at = A.prow[i];
-    const long long np = A.p.np;
-    bool full = false;
-    for (int u = 0; u < n; ++u) {
-        if (at < A.pair_cap) A.pairs[at] = ((unsigned long long)i << 32) | (unsigned)nb[u];
-        else full = true;
-        ++at;
+template <bool ALL>
+__device__ void ph_pairemit(const DemArgs& A, const PairBufs& B, int i) {
+    const long long at = B.prow[i];
+    const long long room = A.pair_cap - at;
+    if (room < (long long)(B.prow[i + 1] - B.prow[i])) atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_PAIRS);
+    if (room <= 0) return;
+    unsigned long long* out = B.pairs + at;
+    const int n = ALL ? pairs_all(A, i, out, room) : pairs_by_cells(A, i, out, room);
+    emit_walls(A, i, out, room, n);
+    if (!ALL) {
+        const int m = n < room ? n : (int)room;
+        for (int u = 1; u < m; ++u)
+            for (int v = u; v > 0 && out[v] < out[v - 1]; --v) {
+                unsigned long long t = out[v];
+                out[v] = out[v - 1];
+                out[v - 1] = t;
+            }
     }
-    for (int f = 0; f < 6; ++f)
-        if (A.g.bc[f] != 0 && wall_dist(A, i, f) < A.p.rb[i]) {
-            if (at < A.pair_cap) A.pairs[at] = ((unsigned long long)i << 32) | (unsigned)(np + f);
-            else full = true;
-            ++at;
-        }
-    if (full) atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_PAIRS);
 }
 
-__device__ inline long long find_prev(const DemArgs& A, unsigned long long key, long long n) {
+__device__ inline long long find_prev(const PairBufs& B, unsigned long long key, long long n) {
     long long lo = 0, hi = n;
     while (lo < hi) {
         long long mid = (lo + hi) >> 1;
-        if (A.prev_pairs[mid] < key) lo = mid + 1;
+        if (B.prev_pairs[mid] < key) lo = mid + 1;
         else hi = mid;
     }
-    return (lo < n && A.prev_pairs[lo] == key) ? lo : -1;
+    return (lo < n && B.prev_pairs[lo] == key) ? lo : -1;
+}
+
+__device__ inline long long n_pairs(const DemArgs& A, const PairBufs& B) {
+    long long n = B.prow[A.p.np];
+    return n < A.pair_cap ? n : A.pair_cap;
 }
 
 // linear spring-dashpot with Coulomb cap and tangential history (Sec. 2.1):
@@ -415,22 +482,17 @@ __device__ inline long long find_prev(const DemArgs& A, unsigned long long key, 
 // v_rel = (v_i - v_j) - (rho_i w_i + rho_j w_j) x e_n, v_t its tangential part;
 // history projected on the tangent plane then advanced by v_t dt;
 // F_t = -k_t d_t - gamma_t v_t capped at mu |F_n| with the history reset.
-__global__ void k_contacts(DemArgs A, const double* __restrict__ vv, const double* __restrict__ ww, double dth) {
-    long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    long long n = A.prow[A.p.np];
-    if (n > A.pair_cap) n = A.pair_cap;
-    if (s >= n) return;
-    long long nprev = A.prev_n ? *A.prev_n : 0;
-    if (nprev > A.pair_cap) nprev = A.pair_cap;
+__device__ void ph_contact(const DemArgs& A, const PairBufs& B, long long s, const double* __restrict__ vv,
+                           const double* __restrict__ ww, double dth, long long nprev) {
     const int np = A.p.np;
-    unsigned long long key = A.pairs[s];
+    unsigned long long key = B.pairs[s];
     int i = (int)(key >> 32), j = (int)(key & 0xffffffffu);
     Geom G;
     pair_geometry(A, i, j, G);
     double* F = A.cF + 3 * s;
     double* Mi = A.cMi + 3 * s;
     double* Mj = A.cMj + 3 * s;
-    double* h = A.hist + 3 * s;
+    double* h = B.hist + 3 * s;
     if (!(G.delta > 0.0)) {
         for (int k = 0; k < 3; ++k) F[k] = Mi[k] = Mj[k] = h[k] = 0.0;
         A.incontact[s] = 0;
@@ -468,9 +530,9 @@ __global__ void k_contacts(DemArgs A, const double* __restrict__ vv, const doubl
     double vrn = dot3(vrel, G.en);
     double vt[3] = {vrel[0] - vrn * G.en[0], vrel[1] - vrn * G.en[1], vrel[2] - vrn * G.en[2]};
     double ho[3] = {0.0, 0.0, 0.0};
-    long long ps = find_prev(A, key, nprev);
+    long long ps = find_prev(B, key, nprev);
     if (ps >= 0)
-        for (int k = 0; k < 3; ++k) ho[k] = A.prev_hist[3 * ps + k];
+        for (int k = 0; k < 3; ++k) ho[k] = B.prev_hist[3 * ps + k];
     double hp = dot3(ho, G.en);
     double ht[3];
     for (int k = 0; k < 3; ++k) ht[k] = (ho[k] - hp * G.en[k]) + vt[k] * dth;
@@ -503,42 +565,80 @@ __global__ void k_contacts(DemArgs A, const double* __restrict__ vv, const doubl
     }
 }
 
-__device__ inline long long find_pair(const DemArgs& A, unsigned long long key, long long lo, long long hi) {
-    long long end = hi;
-    while (lo < hi) {
-        long long mid = (lo + hi) >> 1;
-        if (A.pairs[mid] < key) lo = mid + 1;
-        else hi = mid;
-    }
-    return (lo < end && A.pairs[lo] == key) ? lo : -1;
+__device__ void ph_colhist(const DemArgs& A, const PairBufs& B, long long s) {
+    const unsigned j = (unsigned)(B.pairs[s] & 0xffffffffu);
+    if (j < (unsigned)A.p.np) atomicAdd(&A.col_count[j], 1);
 }
 
-__global__ void k_dem_sum(DemArgs A) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.p.np) return;
+__device__ void ph_colscatter(const DemArgs& A, const PairBufs& B, long long s) {
+    const unsigned j = (unsigned)(B.pairs[s] & 0xffffffffu);
+    if (j >= (unsigned)A.p.np) return;
+    const int slot = atomicAdd(&A.col_fill[j], 1);
+    A.col_list[A.col_start[j] + slot] = (int)s;
+}
+
+__device__ void ph_colsort(const DemArgs& A, int j) {
+    const int s0 = A.col_start[j], s1 = A.col_start[j + 1];
+    for (int u = s0 + 1; u < s1; ++u)
+        for (int v = u; v > s0 && A.col_list[v] < A.col_list[v - 1]; --v) {
+            int t = A.col_list[v];
+            A.col_list[v] = A.col_list[v - 1];
+            A.col_list[v - 1] = t;
+        }
+}
+
+__device__ inline long long find_pair(const PairBufs& B, unsigned long long key, long long lo, long long hi) {
+    const long long end = hi;
+    while (lo < hi) {
+        long long mid = (lo + hi) >> 1;
+        if (B.pairs[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < end && B.pairs[lo] == key) ? lo : -1;
+}
+
+// F_dem, M_dem of particle i: pairs (k, i) by ascending k (second member),
+// then its own row (first member), as the pairs are ordered
+template <bool ALL>
+__device__ void ph_sum(const DemArgs& A, const PairBufs& B, int i) {
     double F[3] = {0.0, 0.0, 0.0}, M[3] = {0.0, 0.0, 0.0};
-    int nb[PSM_MAXNB];
-    bool ovf = false;
-    int n = neighbours(A, i, false, nb, &ovf);
-    long long cap = A.pair_cap;
-    for (int u = 0; u < n; ++u) {
-        int k = nb[u];
-        long long lo = A.prow[k], hi = A.prow[k + 1];
-        if (hi > cap) hi = cap;
-        long long s = find_pair(A, ((unsigned long long)k << 32) | (unsigned)i, lo, hi);
-        if (s < 0) continue;
-        for (int c = 0; c < 3; ++c) {
-            F[c] -= A.cF[3 * s + c];
-            M[c] += A.cMj[3 * s + c];
+    const long long cap = A.pair_cap;
+    if (ALL) {
+        AxCells ri;
+        load_cells(A, i, ri);
+        for (int k = 0; k < i; ++k) {
+            AxCells rk;
+            load_cells(A, k, rk);
+            if (!share_cell(ri, rk)) continue;
+            long long lo = B.prow[k], hi = B.prow[k + 1];
+            hi = hi < cap ? hi : cap;
+            const long long s = find_pair(B, ((unsigned long long)k << 32) | (unsigned)i, lo, hi);
+            if (s < 0) continue;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                F[c] -= A.cF[3 * s + c];
+                M[c] += A.cMj[3 * s + c];
+            }
+        }
+    } else {
+        for (int u = A.col_start[i]; u < A.col_start[i + 1]; ++u) {
+            const long long s = A.col_list[u];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                F[c] -= A.cF[3 * s + c];
+                M[c] += A.cMj[3 * s + c];
+            }
         }
     }
-    long long s0 = A.prow[i], s1 = A.prow[i + 1];
-    if (s1 > cap) s1 = cap;
+    long long s0 = B.prow[i], s1 = B.prow[i + 1];
+    s1 = s1 < cap ? s1 : cap;
     for (long long s = s0; s < s1; ++s)
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
             F[c] += A.cF[3 * s + c];
             M[c] += A.cMi[3 * s + c];
         }
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
         A.p.fd[3 * i + c] = F[c];
         A.p.md[3 * i + c] = M[c];
@@ -555,9 +655,7 @@ __device__ inline void quat_rate(const double* w, const double* q, double* out) 
 
 // predictor: r += dt v + dt^2/2 a (wrapped), v^p = v + dt a, w^p = w + dt alpha,
 // orientation advanced with w(t) by the triad predictor-corrector
-__global__ void k_predict(DemArgs A, double dt, int write_kin) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= A.p.np) return;
+__device__ void ph_predict(const DemArgs& A, int k, double dt, int write_kin) {
     double hdt2 = 0.5 * dt * dt;
     double* x = A.p.pos + 3 * k;
     for (int c = 0; c < 3; ++c) {
@@ -611,9 +709,7 @@ __device__ void angular_accel(const DemArgs& A, int k, const double* qo, const d
 
 // corrector: a_new = (F_dem + F_hyd + F_ext)/m, F_ext = m (1 - rho0/rho_p) g;
 // v += dt/2 (a + a_new); w += dt/2 (alpha + alpha_new)
-__global__ void k_correct(DemArgs A, double dt) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= A.p.np) return;
+__device__ void ph_correct(const DemArgs& A, int k, double dt) {
     if (A.p.fixed[k]) {
         for (int c = 0; c < 3; ++c) A.p.a[3 * k + c] = A.p.al[3 * k + c] = 0.0;
         return;
@@ -636,9 +732,7 @@ __global__ void k_correct(DemArgs A, double dt) {
 }
 
 // initial accelerations a(0) = (F_dem(0) + F_ext)/m, alpha(0) from M_dem(0)
-__global__ void k_initial_accel(DemArgs A) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= A.p.np) return;
+__device__ void ph_initial_accel(const DemArgs& A, int k) {
     double m = A.p.mass[k];
     double fb = 1.0 - 1.0 / A.p.dens[k];
     if (A.p.fixed[k]) {
@@ -661,12 +755,235 @@ __global__ void k_initial_accel(DemArgs A) {
     for (int c = 0; c < 4; ++c) A.p.qold[4 * k + c] = A.p.q[4 * k + c];
 }
 
-__global__ void k_zero_d(double* p, long long n) {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0.0;
+
+// ---------------------------------------------------------------------------
+// kernels of the multi-launch path
+// ---------------------------------------------------------------------------
+#define GRID_LOOP(i, n) for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (long long)gridDim.x * blockDim.x)
+
+__global__ void k_predict(DemArgs A, double dt, int write_kin) {
+    GRID_LOOP(k, A.p.np) {
+        ph_predict(A, (int)k, dt, write_kin);
+        ph_cells(A, (int)k);
+    }
+}
+__global__ void k_cells(DemArgs A) { GRID_LOOP(k, A.p.np) ph_cells(A, (int)k); }
+__global__ void k_hist(DemArgs A) { GRID_LOOP(k, A.p.np) ph_hist(A, (int)k); }
+__global__ void k_scatter(DemArgs A) { GRID_LOOP(k, A.p.np) ph_scatter(A, (int)k); }
+__global__ void k_cellsort(DemArgs A) { GRID_LOOP(c, A.ncell) ph_cellsort(A, c); }
+__global__ void k_paircount(DemArgs A) { GRID_LOOP(i, A.p.np) ph_paircount<false>(A, (int)i); }
+__global__ void k_pairemit(DemArgs A, PairBufs B) { GRID_LOOP(i, A.p.np) ph_pairemit<false>(A, B, (int)i); }
+__global__ void k_contacts(DemArgs A, PairBufs B, const double* vv, const double* ww, double dth) {
+    long long nprev = B.prev_n ? *B.prev_n : 0;
+    nprev = nprev < A.pair_cap ? nprev : A.pair_cap;
+    const long long n = n_pairs(A, B);
+    GRID_LOOP(s, n) ph_contact(A, B, s, vv, ww, dth, nprev);
+}
+__global__ void k_colhist(DemArgs A, PairBufs B) {
+    const long long n = n_pairs(A, B);
+    GRID_LOOP(s, n) ph_colhist(A, B, s);
+}
+__global__ void k_colscatter(DemArgs A, PairBufs B) {
+    const long long n = n_pairs(A, B);
+    GRID_LOOP(s, n) ph_colscatter(A, B, s);
+}
+__global__ void k_colsort(DemArgs A) { GRID_LOOP(j, A.p.np) ph_colsort(A, (int)j); }
+__global__ void k_sum(DemArgs A, PairBufs B) { GRID_LOOP(i, A.p.np) ph_sum<false>(A, B, (int)i); }
+__global__ void k_correct(DemArgs A, double dt) { GRID_LOOP(k, A.p.np) ph_correct(A, (int)k, dt); }
+__global__ void k_initial_accel(DemArgs A) { GRID_LOOP(k, A.p.np) ph_initial_accel(A, (int)k); }
+
+__global__ void k_zero_d(double* p, long long n) { GRID_LOOP(i, n) p[i] = 0.0; }
+
+// ---------------------------------------------------------------------------
+// fused single-workgroup substeps
+// ---------------------------------------------------------------------------
+#define FUSED_T 1024
+
+// exclusive scan of in[0..n) into out[0..n], out[n] = total, by one workgroup
+__device__ void block_scan(const int* in, int* out, int n) {
+    __shared__ int wsum[FUSED_T / 64];
+    __shared__ int carry;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < n; base += FUSED_T) {
+        const int i = base + tid;
+        const int v = i < n ? in[i] : 0;
+        int x = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wid] = x;
+        __syncthreads();
+        int off = 0, tot = 0;
+        for (int w = 0; w < FUSED_T / 64; ++w) {
+            off += w < wid ? wsum[w] : 0;
+            tot += wsum[w];
+        }
+        const int c = carry;
+        if (i < n) out[i] = c + off + x - v;
+        __syncthreads();
+        if (tid == 0) carry = c + tot;
+        __syncthreads();
+    }
+    if (tid == 0) out[n] = carry;
+    __syncthreads();
 }
 
-inline unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
+#define FUSED_PREV_LDS 3072
+
+__device__ inline unsigned pack_axis(const AxCells& r, int a) {
+    return (unsigned)r.c[a][0] | ((unsigned)r.c[a][1] << 16);
+}
+
+// the two particles' cells meet along one axis (packed low/high cell pairs)
+__device__ inline bool axis_meet(unsigned p, unsigned q) {
+    const unsigned p0 = p & 0xffffu, p1 = p >> 16, q0 = q & 0xffffu, q1 = q >> 16;
+    return p0 == q0 || p0 == q1 || p1 == q0 || p1 == q1;
+}
+
+__device__ inline bool meet(const unsigned* cs, int i, int j) {
+    return axis_meet(cs[3 * i], cs[3 * j]) && axis_meet(cs[3 * i + 1], cs[3 * j + 1]) &&
+           axis_meet(cs[3 * i + 2], cs[3 * j + 2]);
+}
+
+__device__ inline long long find_key(const unsigned long long* keys, unsigned long long key, long long n) {
+    long long lo = 0, hi = n;
+    while (lo < hi) {
+        long long mid = (lo + hi) >> 1;
+        if (keys[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < n && keys[lo] == key) ? lo : -1;
+}
+
+// All substeps of a coupled step for up to DEM_FUSED_MAX particles in one
+// workgroup.  Per-axis cells of every particle sit in LDS; a row of candidate
+// pairs is built by one wave testing 64 partners per ballot, its emission order
+// (ascending j) given by the lanes' prefix counts.  The previous list's keys are
+// staged in LDS for the history search when they fit.
+__global__ __launch_bounds__(FUSED_T) void k_dem_fused(DemArgs A, PairSet P, int cur, int nsub, double dt,
+                                                       int stop_before_correct) {
+    __shared__ unsigned cells_s[3 * DEM_FUSED_MAX];
+    __shared__ int cnt_s[DEM_FUSED_MAX];
+    __shared__ unsigned long long prev_s[FUSED_PREV_LDS];
+    const int np = A.p.np, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int nw = FUSED_T / 64;
+    const unsigned long long lanes_below = (1ull << lane) - 1ull;
+    for (int sub = 0; sub < nsub; ++sub) {
+        const bool last = sub == nsub - 1;
+        const int c = cur ^ 1;
+        PairBufs B;
+        B.pairs = P.pairs[c];
+        B.prow = P.prow[c];
+        B.hist = P.hist[c];
+        B.prev_pairs = P.pairs[cur];
+        B.prev_hist = P.hist[cur];
+        B.prev_n = P.prow[cur] + np;
+        for (int k = tid; k < np; k += FUSED_T) {
+            ph_predict(A, k, dt, last ? 1 : 0);
+            AxCells r;
+            axis_cells(A, k, r);
+            store_cells(A, k, r);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) cells_s[3 * k + a] = pack_axis(r, a);
+        }
+        __syncthreads();
+        // row sizes: partners j > i sharing a cell, plus wall candidates
+        for (int i = wid; i < np; i += nw) {
+            int cnt = 0;
+            for (int j0 = i + 1; j0 < np; j0 += 64) {
+                const int j = j0 + lane;
+                cnt += __popcll(__ballot(j < np && meet(cells_s, i, j)));
+            }
+            if (lane == 0) {
+                cnt += wall_count(A, i);
+                cnt_s[i] = cnt;
+                A.pcount[i] = cnt;
+            }
+        }
+        __syncthreads();
+        block_scan(A.pcount, B.prow, np);
+        // rows, ascending j, then walls
+        for (int i = wid; i < np; i += nw) {
+            long long at = B.prow[i];
+            for (int j0 = i + 1; j0 < np; j0 += 64) {
+                const int j = j0 + lane;
+                const bool ok = j < np && meet(cells_s, i, j);
+                const unsigned long long m = __ballot(ok);
+                const long long pos = at + __popcll(m & lanes_below);
+                if (ok && pos < A.pair_cap) B.pairs[pos] = ((unsigned long long)i << 32) | (unsigned)j;
+                at += __popcll(m);
+            }
+            if (lane == 0) {
+                for (int f = 0; f < 6; ++f)
+                    if (A.g.bc[f] != 0 && wall_dist(A, i, f) < A.p.rb[i]) {
+                        if (at < A.pair_cap) B.pairs[at] = ((unsigned long long)i << 32) | (unsigned)(np + f);
+                        ++at;
+                    }
+                if (at > A.pair_cap) atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_PAIRS);
+            }
+        }
+        long long nprev = P.prow[cur][np];
+        nprev = nprev < A.pair_cap ? nprev : A.pair_cap;
+        const bool prev_in_lds = nprev <= FUSED_PREV_LDS;
+        if (prev_in_lds)
+            for (long long u = tid; u < nprev; u += FUSED_T) prev_s[u] = B.prev_pairs[u];
+        __syncthreads();
+        {
+            const long long n = n_pairs(A, B);
+            PairBufs BL = B;
+            if (prev_in_lds) BL.prev_pairs = prev_s;
+            for (long long s = tid; s < n; s += FUSED_T) ph_contact(A, BL, s, A.p.vp, A.p.wp, dt, nprev);
+        }
+        __syncthreads();
+        // DEM sums: (k, i) for ascending k, then the own row
+        for (int i = tid; i < np; i += FUSED_T) {
+            double F[3] = {0.0, 0.0, 0.0}, M[3] = {0.0, 0.0, 0.0};
+            for (int k = 0; k < i; ++k) {
+                if (!meet(cells_s, i, k)) continue;
+                const long long lo = B.prow[k];
+                long long hi = B.prow[k + 1];
+                hi = hi < A.pair_cap ? hi : A.pair_cap;
+                if (hi <= lo) continue;
+                const long long s = lo + find_key(B.pairs + lo, ((unsigned long long)k << 32) | (unsigned)i, hi - lo);
+                if (s < lo) continue;
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    F[q] -= A.cF[3 * s + q];
+                    M[q] += A.cMj[3 * s + q];
+                }
+            }
+            long long s0 = B.prow[i], s1 = B.prow[i + 1];
+            s1 = s1 < A.pair_cap ? s1 : A.pair_cap;
+            for (long long s = s0; s < s1; ++s)
+#pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    F[q] += A.cF[3 * s + q];
+                    M[q] += A.cMi[3 * s + q];
+                }
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                A.p.fd[3 * i + q] = F[q];
+                A.p.md[3 * i + q] = M[q];
+            }
+        }
+        __syncthreads();
+        if (!(last && stop_before_correct)) {
+            for (int k = tid; k < np; k += FUSED_T) ph_correct(A, k, dt);
+            __syncthreads();
+        }
+        cur = c;
+    }
+}
+
+inline unsigned nblk(long long n, int t = 256) {
+    long long b = (n + t - 1) / t;
+    b = b < 1 ? 1 : (b > 65535 ? 65535 : b);
+    return (unsigned)b;
+}
 
 }  // namespace
 
@@ -679,25 +996,34 @@ hipError_t dem_predict(const DemArgs& A, double dt, int write_kin, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t dem_lists(const DemArgs& A, int* scan_tmp, hipStream_t s) {
+hipError_t dem_lists(const DemArgs& A, const PairBufs& B, int* scan_tmp, hipStream_t s) {
     if (A.p.np == 0) return hipSuccess;
     hipError_t e;
+    k_cells<<<nblk(A.p.np), 256, 0, s>>>(A);
     if ((e = psm_fill_int(A.cell_count, 0, A.ncell, s)) != hipSuccess) return e;
     if ((e = psm_fill_int(A.cell_fill, 0, A.ncell, s)) != hipSuccess) return e;
-    k_reg_hist<<<nblk(A.p.np), 256, 0, s>>>(A);
+    k_hist<<<nblk(A.p.np), 256, 0, s>>>(A);
     if ((e = psm_scan(A.cell_count, A.cell_start, A.ncell, scan_tmp, s)) != hipSuccess) return e;
-    k_reg_scatter<<<nblk(A.p.np), 256, 0, s>>>(A);
-    k_cell_sort<<<nblk(A.ncell), 256, 0, s>>>(A);
-    k_pair_count<<<nblk(A.p.np), 128, 0, s>>>(A);
-    if ((e = psm_scan(A.pcount, A.prow, A.p.np, scan_tmp, s)) != hipSuccess) return e;
-    k_pair_emit<<<nblk(A.p.np), 128, 0, s>>>(A);
+    k_scatter<<<nblk(A.p.np), 256, 0, s>>>(A);
+    k_cellsort<<<nblk(A.ncell), 256, 0, s>>>(A);
+    k_paircount<<<nblk(A.p.np, 128), 128, 0, s>>>(A);
+    if ((e = psm_scan(A.pcount, B.prow, A.p.np, scan_tmp, s)) != hipSuccess) return e;
+    k_pairemit<<<nblk(A.p.np, 128), 128, 0, s>>>(A, B);
     return hipGetLastError();
 }
 
-hipError_t dem_contacts(const DemArgs& A, const double* vv, const double* ww, double dth, hipStream_t s) {
+hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, const double* ww, double dth,
+                        int* scan_tmp, hipStream_t s) {
     if (A.p.np == 0) return hipSuccess;
-    k_contacts<<<nblk(A.pair_cap, 128), 128, 0, s>>>(A, vv, ww, dth);
-    k_dem_sum<<<nblk(A.p.np, 128), 128, 0, s>>>(A);
+    hipError_t e;
+    k_contacts<<<nblk(A.pair_cap, 128), 128, 0, s>>>(A, B, vv, ww, dth);
+    if ((e = psm_fill_int(A.col_count, 0, A.p.np, s)) != hipSuccess) return e;
+    if ((e = psm_fill_int(A.col_fill, 0, A.p.np, s)) != hipSuccess) return e;
+    k_colhist<<<nblk(A.pair_cap), 256, 0, s>>>(A, B);
+    if ((e = psm_scan(A.col_count, A.col_start, A.p.np, scan_tmp, s)) != hipSuccess) return e;
+    k_colscatter<<<nblk(A.pair_cap), 256, 0, s>>>(A, B);
+    k_colsort<<<nblk(A.p.np), 256, 0, s>>>(A);
+    k_sum<<<nblk(A.p.np, 128), 128, 0, s>>>(A, B);
     return hipGetLastError();
 }
 
@@ -716,5 +1042,13 @@ hipError_t dem_initial_accel(const DemArgs& A, hipStream_t s) {
 hipError_t dem_zero(double* p, long long n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     k_zero_d<<<nblk(n), 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+hipError_t dem_fused(const DemArgs& A, const PairSet& P, int cur, int nsub, double dt, int stop_before_correct,
+                     hipStream_t s) {
+    if (A.p.np == 0 || nsub <= 0) return hipSuccess;
+    if (A.p.np > DEM_FUSED_MAX || A.nc[0] > 65535 || A.nc[1] > 65535 || A.nc[2] > 65535) return hipErrorInvalidValue;
+    k_dem_fused<<<1, FUSED_T, 0, s>>>(A, P, cur, nsub, dt, stop_before_correct);
     return hipGetLastError();
 }

@@ -10,7 +10,7 @@ struct LbmArgs {
     double F[3];               // constant force density
     int kolm_axis, kolm_dir;
     const double* kolm_prof;   // [n_axis] sine profile of the Kolmogorov forcing or NULL
-    double wall_corr[6][19];   // 6 w_i rho0 (c_i . u_w) per walled face (0 for no-slip)
+    const double* wall_corr;   // [6 * 19] 6 w_i rho0 (c_i . u_w) per walled face (0 for no-slip)
     TileArgs t;
     const double* kin;         // [9 np] position, v^p, w^p
     int np;

@@ -19,6 +19,8 @@
 // The block -> tile mapping keeps consecutive tiles on one XCD.
 #include <hip/hip_fp16.h>
 
+#include <utility>
+
 #include "common.h"
 #include "lbm.h"
 
@@ -107,10 +109,11 @@ __device__ inline C cdot(int i, C x, C y, C z) {
     return r;
 }
 
-// BGK (+ PSM, + Guo) collision; Pk[k] = sum_i Omega^s_ik c_i (before the B_k factor)
-template <typename C, bool PSM>
-__device__ inline void collide(const C* g, C* out, C omega, bool forcing, C Fx, C Fy, C Fz, int nk, const C* B,
-                               const C (*uk)[3], C (*Pk)[3]) {
+// BGK (+ PSM, + Guo) collision of one cell; MS = maximum solid slots (0: fluid
+// only).  Pk[k] = sum_i Omega^s_ik c_i (before the B_k factor).
+template <typename C, int MS>
+__device__ inline void collide(const C* g, C* out, C omega, bool forcing, C Fx, C Fy, C Fz, int nk,
+                               const C* B, const C (*uk)[3], C (*Pk)[3]) {
     C drho, jx, jy, jz;
     moments(g, drho, jx, jy, jz);
     const C rho = (C)1 + drho;
@@ -128,30 +131,30 @@ __device__ inline void collide(const C* g, C* out, C omega, bool forcing, C Fx, 
     const C usq = ux * ux + uy * uy + uz * uz;
     const C E = drho - (C)1.5 * rho * usq;
     C Bt = (C)0;
-    if (PSM) {
-        for (int k = 0; k < nk; ++k) Bt += B[k];
-        Bt = Bt < (C)1 ? Bt : (C)1;
+    C Ek[MS > 0 ? MS : 1];
+#pragma unroll
+    for (int k = 0; k < MS; ++k) {
+        if (k < nk) {
+            Bt += B[k];
+            const C uk2 = uk[k][0] * uk[k][0] + uk[k][1] * uk[k][1] + uk[k][2] * uk[k][2];
+            Ek[k] = drho - (C)1.5 * rho * uk2;
+        }
+        Pk[k][0] = Pk[k][1] = Pk[k][2] = (C)0;
     }
-    const C om = PSM ? ((C)1 - Bt) * omega : omega;
-    const C fpre = PSM ? ((C)1 - Bt) : (C)1;
+    Bt = Bt < (C)1 ? Bt : (C)1;
+    const C om = MS > 0 ? ((C)1 - Bt) * omega : omega;
+    const C fpre = MS > 0 ? ((C)1 - Bt) : (C)1;
     const C gk = (C)1 - (C)0.5 * omega;  // Guo prefactor 1 - 1/(2 tau)
     const C uF = ux * Fx + uy * Fy + uz * Fz;
-    // rest population
     {
         const C geq0 = W<C>(0) * E;
         C o = g[0] - om * (g[0] - geq0);
         if (forcing) o += fpre * gk * W<C>(0) * ((C)-3 * uF);
-        if (PSM) {
-            for (int k = 0; k < nk; ++k) {
-                const C uk2 = uk[k][0] * uk[k][0] + uk[k][1] * uk[k][1] + uk[k][2] * uk[k][2];
-                const C Ek = drho - (C)1.5 * rho * uk2;
-                o += B[k] * (W<C>(0) * (Ek - E));
-            }
-        }
+#pragma unroll
+        for (int k = 0; k < MS; ++k)
+            if (k < nk) o += B[k] * (W<C>(0) * (Ek[k] - E));
         out[0] = o;
     }
-    if (PSM)
-        for (int k = 0; k < nk; ++k) Pk[k][0] = Pk[k][1] = Pk[k][2] = (C)0;
 #pragma unroll
     for (int p = 1; p <= 9; ++p) {
         const int q = p + 9;
@@ -159,8 +162,7 @@ __device__ inline void collide(const C* g, C* out, C omega, bool forcing, C Fx, 
         const C cu = cdot<C>(p, ux, uy, uz);
         const C sym = w * (E + (C)4.5 * rho * cu * cu);
         const C anti = w * (C)3 * rho * cu;
-        const C geqp = sym + anti, geqq = sym - anti;
-        const C neqp = g[p] - geqp, neqq = g[q] - geqq;
+        const C neqp = g[p] - (sym + anti), neqq = g[q] - (sym - anti);
         C op = g[p] - om * neqp;
         C oq = g[q] - om * neqq;
         if (forcing) {
@@ -169,12 +171,11 @@ __device__ inline void collide(const C* g, C* out, C omega, bool forcing, C Fx, 
             op += fpre * gk * w * ((C)3 * cF + t);
             oq += fpre * gk * w * ((C)-3 * cF + t);
         }
-        if (PSM) {
-            for (int k = 0; k < nk; ++k) {
-                const C uk2 = uk[k][0] * uk[k][0] + uk[k][1] * uk[k][1] + uk[k][2] * uk[k][2];
-                const C Ek = drho - (C)1.5 * rho * uk2;
+#pragma unroll
+        for (int k = 0; k < MS; ++k) {
+            if (k < nk) {
                 const C cuk = cdot<C>(p, uk[k][0], uk[k][1], uk[k][2]);
-                const C symk = w * (Ek + (C)4.5 * rho * cuk * cuk);
+                const C symk = w * (Ek[k] + (C)4.5 * rho * cuk * cuk);
                 const C antik = w * (C)3 * rho * cuk;
                 const C Osp = neqq - (g[p] - (symk + antik));
                 const C Osq = neqp - (g[q] - (symk - antik));
@@ -194,46 +195,79 @@ __device__ inline void collide(const C* g, C* out, C omega, bool forcing, C Fx, 
     }
 }
 
-// neighbour offsets and wall faces of a cell
-struct Nbr {
-    long long off[3][3];  // [axis][d + 1] index offset to the neighbour (wrapped)
-    int face[3][3];       // [axis][d + 1] walled face crossed, -1 none
+// Per-axis neighbour offsets (wrapped on periodic axes) and wall flags of a
+// lane; a direction's source or destination and the walled face its link
+// crosses (lowest face index first) follow with a few selects.
+struct AxisNb {
+    int om, op;      // element offset of the -1 / +1 neighbour
+    bool wl, wh;     // the -1 / +1 neighbour lies beyond a wall
 };
 
-__device__ inline void make_nbr(const GeoArgs& g, int x, int y, int z, Nbr& nb) {
-    const int c[3] = {x, y, z};
-    const int n[3] = {g.nx, g.ny, g.nz};
-    const long long stride[3] = {1, (long long)g.nx, (long long)g.nx * g.ny};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        nb.off[a][1] = 0;
-        nb.face[a][1] = -1;
-        // minus
-        if (c[a] == 0) {
-            nb.off[a][0] = g.periodic[a] ? (long long)(n[a] - 1) * stride[a] : 0;
-            nb.face[a][0] = g.periodic[a] ? -1 : 2 * a;
-        } else {
-            nb.off[a][0] = -stride[a];
-            nb.face[a][0] = -1;
-        }
-        // plus
-        if (c[a] == n[a] - 1) {
-            nb.off[a][2] = g.periodic[a] ? -(long long)(n[a] - 1) * stride[a] : 0;
-            nb.face[a][2] = g.periodic[a] ? -1 : 2 * a + 1;
-        } else {
-            nb.off[a][2] = stride[a];
-            nb.face[a][2] = -1;
-        }
+__device__ inline AxisNb axis_nb(int c, int n, int periodic, int stride) {
+    AxisNb a;
+    a.wl = !periodic && c == 0;
+    a.wh = !periodic && c == n - 1;
+    a.om = c == 0 ? (periodic ? (n - 1) * stride : 0) : -stride;
+    a.op = c == n - 1 ? (periodic ? -(n - 1) * stride : 0) : stride;
+    return a;
+}
+
+template <int DX, int DY, int DZ>
+__device__ inline int dir_off(const AxisNb& ax, const AxisNb& ay, const AxisNb& az, int* face) {
+    int f = -1;
+    if (DX < 0 && ax.wl) f = 0;
+    if (DX > 0 && ax.wh) f = 1;
+    if (f < 0 && DY < 0 && ay.wl) f = 2;
+    if (f < 0 && DY > 0 && ay.wh) f = 3;
+    if (f < 0 && DZ < 0 && az.wl) f = 4;
+    if (f < 0 && DZ > 0 && az.wh) f = 5;
+    *face = f;
+    int o = 0;
+    if (DX < 0) o += ax.om;
+    if (DX > 0) o += ax.op;
+    if (DY < 0) o += ay.om;
+    if (DY > 0) o += ay.op;
+    if (DZ < 0) o += az.om;
+    if (DZ > 0) o += az.op;
+    return o;
+}
+
+template <typename S, typename C, bool ODD, int I>
+__device__ inline void load_dir(const LbmArgs& A, const S* f, long long N, long long cell, const AxisNb& ax,
+                                const AxisNb& ay, const AxisNb& az, C* g) {
+    if (!ODD) {
+        g[I] = Conv<S, C>::ld(f[(long long)I * N + cell]);
+    } else {
+        int face;
+        const int o = dir_off<-d3q19_cx(I), -d3q19_cy(I), -d3q19_cz(I)>(ax, ay, az, &face);
+        if (face >= 0) g[I] = Conv<S, C>::ld(f[(long long)I * N + cell]) + (C)A.wall_corr[face * 19 + I];
+        else g[I] = Conv<S, C>::ld(f[(long long)d3q19_opp(I) * N + cell + o]);
     }
 }
 
-// cell offset and first walled face (lowest index) of direction (dx,dy,dz)
-__device__ inline long long nbr_at(const Nbr& nb, int dx, int dy, int dz, int* face) {
-    int f = nb.face[0][dx + 1];
-    if (f < 0) f = nb.face[1][dy + 1];
-    if (f < 0) f = nb.face[2][dz + 1];
-    *face = f;
-    return nb.off[0][dx + 1] + nb.off[1][dy + 1] + nb.off[2][dz + 1];
+template <typename S, typename C, bool ODD, int I>
+__device__ inline void store_dir(const LbmArgs& A, S* f, long long N, long long cell, const AxisNb& ax,
+                                 const AxisNb& ay, const AxisNb& az, const C* out) {
+    if (!ODD) {
+        f[(long long)d3q19_opp(I) * N + cell] = Conv<S, C>::st(out[I]);
+    } else {
+        int face;
+        const int o = dir_off<d3q19_cx(I), d3q19_cy(I), d3q19_cz(I)>(ax, ay, az, &face);
+        if (face >= 0) f[(long long)d3q19_opp(I) * N + cell] = Conv<S, C>::st(out[I] - (C)A.wall_corr[face * 19 + I]);
+        else f[(long long)I * N + cell + o] = Conv<S, C>::st(out[I]);
+    }
+}
+
+template <typename S, typename C, bool ODD, int... Is>
+__device__ inline void load_all(const LbmArgs& A, const S* f, long long N, long long cell, const AxisNb& ax,
+                                const AxisNb& ay, const AxisNb& az, C* g, std::integer_sequence<int, Is...>) {
+    (load_dir<S, C, ODD, Is>(A, f, N, cell, ax, ay, az, g), ...);
+}
+
+template <typename S, typename C, bool ODD, int... Is>
+__device__ inline void store_all(const LbmArgs& A, S* f, long long N, long long cell, const AxisNb& ax,
+                                 const AxisNb& ay, const AxisNb& az, const C* out, std::integer_sequence<int, Is...>) {
+    (store_dir<S, C, ODD, Is>(A, f, N, cell, ax, ay, az, out), ...);
 }
 
 __device__ inline unsigned long long ballot64(bool p) { return __ballot(p); }
@@ -244,7 +278,8 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-template <typename S, typename C, bool ODD, bool PSM>
+// MS = 0: tiles without registered particles; MS > 0: tiles with particles
+template <typename S, typename C, bool ODD, int MS>
 __global__ __launch_bounds__(256) void k_lbm(LbmArgs A) {
     const long long ntiles = A.g.ntiles;
     const long long per = (ntiles + 7) / 8;
@@ -253,17 +288,17 @@ __global__ __launch_bounds__(256) void k_lbm(LbmArgs A) {
     long long s0 = A.t.tile_start[t], s1 = A.t.tile_start[t + 1];
     if (s1 > A.t.cap) s1 = A.t.cap;
     int count = (int)(s1 - s0);
-    if (PSM) {
+    if (MS > 0) {
         if (count <= 0) return;
         if (count > PSM_PMAX) count = PSM_PMAX;
     } else {
         if (count > 0) return;
     }
-    __shared__ double kin_s[PSM ? PSM_PMAX * 9 : 1];
-    __shared__ double acc[PSM ? 4 * PSM_PMAX * 6 : 1];
+    __shared__ double kin_s[MS > 0 ? PSM_PMAX * 9 : 1];
+    __shared__ double acc[MS > 0 ? 4 * PSM_PMAX * 6 : 1];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
-    if (PSM) {
+    if (MS > 0) {
         for (int u = tid; u < count * 9; u += 256) {
             int k = (int)(A.t.tile_list[s0 + u / 9] >> 32);
             if (k >= A.np) k = 0;
@@ -284,59 +319,84 @@ __global__ __launch_bounds__(256) void k_lbm(LbmArgs A) {
     const bool forcing = A.forcing != 0;
     const long long plane = ntiles * (long long)PSM_TILE;
     const C* Bslot = (const C*)A.t.slot_B;
+    const AxisNb ax = axis_nb(x, A.g.nx, A.g.periodic[0], 1);
+    const AxisNb ay = axis_nb(y, A.g.ny, A.g.periodic[1], A.g.nx);
+    const bool xy_ok = x < A.g.nx && y < A.g.ny;
 
 #pragma unroll 1
     for (int lz = 0; lz < PSM_TZ; ++lz) {
         const int z = tz * PSM_TZ + lz;
-        const bool valid = x < A.g.nx && y < A.g.ny && z < A.g.nz;
-        const long long cell = (long long)x + (long long)A.g.nx * ((long long)y + (long long)A.g.ny * z);
-        C g[19], out[19];
-        Nbr nb;
+        const bool valid = xy_ok && z < A.g.nz;
         int nk = 0;
-        C B[PSM_SLOTS_MAX];
-        C uk[PSM_SLOTS_MAX][3];
-        C Pk[PSM_SLOTS_MAX][3];
-        int lpk[PSM_SLOTS_MAX];
-        double dk[PSM_SLOTS_MAX][3];
-        C Fx = (C)0, Fy = (C)0, Fz = (C)0;
+        C B[MS > 0 ? MS : 1];
+        C Pk[MS > 0 ? MS : 1][3];
+        int lpk[MS > 0 ? MS : 1];
         if (valid) {
-            if (ODD) make_nbr(A.g, x, y, z, nb);
-#pragma unroll
-            for (int i = 0; i < 19; ++i) {
-                if (!ODD) {
-                    g[i] = Conv<S, C>::ld(f[(long long)i * N + cell]);
-                } else {
-                    int face;
-                    long long o = nbr_at(nb, -d3q19_cx(i), -d3q19_cy(i), -d3q19_cz(i), &face);
-                    if (face >= 0)
-                        g[i] = Conv<S, C>::ld(f[(long long)i * N + cell]) + (C)A.wall_corr[face][i];
-                    else
-                        g[i] = Conv<S, C>::ld(f[(long long)d3q19_opp(i) * N + cell + o]);
-                }
-            }
+            const AxisNb az = axis_nb(z, A.g.nz, A.g.periodic[2], A.g.nx * A.g.ny);
+            const long long cell = (long long)x + (long long)A.g.nx * ((long long)y + (long long)A.g.ny * z);
+            C g[19], out[19];
+            load_all<S, C, ODD>(A, f, N, cell, ax, ay, az, g, std::make_integer_sequence<int, 19>{});
+            C Fx = (C)0, Fy = (C)0, Fz = (C)0;
             if (forcing) {
                 Fx = (C)A.F[0];
                 Fy = (C)A.F[1];
                 Fz = (C)A.F[2];
                 if (A.kolm_prof) {
-                    int coord = A.kolm_axis == 0 ? x : (A.kolm_axis == 1 ? y : z);
-                    C add = (C)A.kolm_prof[coord];
+                    const int coord = A.kolm_axis == 0 ? x : (A.kolm_axis == 1 ? y : z);
+                    const C add = (C)A.kolm_prof[coord];
                     if (A.kolm_dir == 0) Fx += add;
                     else if (A.kolm_dir == 1) Fy += add;
                     else Fz += add;
                 }
             }
-            if (PSM) {
+            C uk[MS > 0 ? MS : 1][3];
+            if (MS > 0) {
                 const long long sl = t * (long long)PSM_TILE + lane + PSM_TX * (wid + PSM_TY * lz);
                 const unsigned lp = A.t.slot_lp[sl];
-                for (int k = 0; k < A.ms; ++k) {
-                    unsigned b = (lp >> (8 * k)) & 0xffu;
-                    if (b == 0xffu || (int)b >= count) break;
-                    lpk[nk] = (int)b;
-                    B[nk] = Bslot[k * plane + sl];
-                    const double* kn = kin_s + 9 * b;
-                    const double rj[3] = {x + 0.5, y + 0.5, z + 0.5};
+#pragma unroll
+                for (int k = 0; k < MS; ++k) {
+                    const unsigned b = (lp >> (8 * k)) & 0xffu;
+                    if (k == nk && k < A.ms && b != 0xffu && (int)b < count) {
+                        lpk[k] = (int)b;
+                        B[k] = Bslot[k * plane + sl];
+                        const double* kn = kin_s + 9 * b;
+                        const double rj[3] = {x + 0.5, y + 0.5, z + 0.5};
+                        double d[3];
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            double v = rj[a] - kn[a];
+                            if (A.g.periodic[a]) {
+                                if (v > 0.5 * A.L[a]) v -= A.L[a];
+                                else if (v < -0.5 * A.L[a]) v += A.L[a];
+                            }
+                            d[a] = v;
+                        }
+                        // u_k = v_k + w_k x (r_j - r_k)
+                        uk[k][0] = (C)(kn[3] + (kn[7] * d[2] - kn[8] * d[1]));
+                        uk[k][1] = (C)(kn[4] + (kn[8] * d[0] - kn[6] * d[2]));
+                        uk[k][2] = (C)(kn[5] + (kn[6] * d[1] - kn[7] * d[0]));
+                        ++nk;
+                    }
+                }
+            }
+            collide<C, MS>(g, out, omega, forcing, Fx, Fy, Fz, nk, B, uk, Pk);
+            store_all<S, C, ODD>(A, f, N, cell, ax, ay, az, out, std::make_integer_sequence<int, 19>{});
+        }
+        if (MS > 0) {
+            // per-particle momentum exchange of this plane: wave sums into LDS
+#pragma unroll
+            for (int k = 0; k < MS; ++k) {
+                const bool has = k < nk;
+                const int my = has ? lpk[k] : -1;
+                double P[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
+                if (has) {
+                    const double Bd = (double)B[k];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) P[a] = Bd * (double)Pk[k][a];
+                    const double* kn = kin_s + 9 * my;
+                    const double rj[3] = {x + 0.5, y + 0.5, tz * PSM_TZ + lz + 0.5};
                     double d[3];
+#pragma unroll
                     for (int a = 0; a < 3; ++a) {
                         double v = rj[a] - kn[a];
                         if (A.g.periodic[a]) {
@@ -344,42 +404,10 @@ __global__ __launch_bounds__(256) void k_lbm(LbmArgs A) {
                             else if (v < -0.5 * A.L[a]) v += A.L[a];
                         }
                         d[a] = v;
-                        dk[nk][a] = v;
                     }
-                    // u_k = v_k + w_k x (r_j - r_k)
-                    uk[nk][0] = (C)(kn[3] + (kn[7] * d[2] - kn[8] * d[1]));
-                    uk[nk][1] = (C)(kn[4] + (kn[8] * d[0] - kn[6] * d[2]));
-                    uk[nk][2] = (C)(kn[5] + (kn[6] * d[1] - kn[7] * d[0]));
-                    ++nk;
-                }
-            }
-            collide<C, PSM>(g, out, omega, forcing, Fx, Fy, Fz, nk, B, uk, Pk);
-#pragma unroll
-            for (int i = 0; i < 19; ++i) {
-                if (!ODD) {
-                    f[(long long)d3q19_opp(i) * N + cell] = Conv<S, C>::st(out[i]);
-                } else {
-                    int face;
-                    long long o = nbr_at(nb, d3q19_cx(i), d3q19_cy(i), d3q19_cz(i), &face);
-                    if (face >= 0)
-                        f[(long long)d3q19_opp(i) * N + cell] = Conv<S, C>::st(out[i] - (C)A.wall_corr[face][i]);
-                    else
-                        f[(long long)i * N + cell + o] = Conv<S, C>::st(out[i]);
-                }
-            }
-        }
-        if (PSM) {
-            // per-particle momentum exchange of this plane: wave sums into LDS
-            for (int k = 0; k < A.ms; ++k) {
-                const bool has = k < nk;
-                const int my = has ? lpk[k] : -1;
-                double P[3] = {0.0, 0.0, 0.0}, T[3] = {0.0, 0.0, 0.0};
-                if (has) {
-                    const double Bd = (double)B[k];
-                    for (int a = 0; a < 3; ++a) P[a] = Bd * (double)Pk[k][a];
-                    T[0] = dk[k][1] * P[2] - dk[k][2] * P[1];
-                    T[1] = dk[k][2] * P[0] - dk[k][0] * P[2];
-                    T[2] = dk[k][0] * P[1] - dk[k][1] * P[0];
+                    T[0] = d[1] * P[2] - d[2] * P[1];
+                    T[1] = d[2] * P[0] - d[0] * P[2];
+                    T[2] = d[0] * P[1] - d[1] * P[0];
                 }
                 unsigned long long pending = ballot64(has);
                 while (pending) {
@@ -387,19 +415,22 @@ __global__ __launch_bounds__(256) void k_lbm(LbmArgs A) {
                     const int target = __shfl(my, leader, 64);
                     const bool mine = has && my == target;
                     double v[6];
+#pragma unroll
                     for (int a = 0; a < 3; ++a) {
                         v[a] = mine ? P[a] : 0.0;
                         v[3 + a] = mine ? T[a] : 0.0;
                     }
+#pragma unroll
                     for (int a = 0; a < 6; ++a) v[a] = wave_sum(v[a]);
                     if (lane == 0)
+#pragma unroll
                         for (int a = 0; a < 6; ++a) acc[(wid * PSM_PMAX + target) * 6 + a] += v[a];
                     pending &= ~ballot64(mine);
                 }
             }
         }
     }
-    if (PSM) {
+    if (MS > 0) {
         __syncthreads();
         for (int u = tid; u < count * 6; u += 256) {
             const int p = u / 6, a = u % 6;
@@ -414,11 +445,13 @@ template <typename S, typename C>
 hipError_t launch_step(const LbmArgs& A, int odd, hipStream_t s) {
     const unsigned nblk = (unsigned)(8 * ((A.g.ntiles + 7) / 8));
     if (odd) {
-        k_lbm<S, C, true, false><<<nblk, 256, 0, s>>>(A);
-        k_lbm<S, C, true, true><<<nblk, 256, 0, s>>>(A);
+        k_lbm<S, C, true, 0><<<nblk, 256, 0, s>>>(A);
+        if (A.ms <= 2) k_lbm<S, C, true, 2><<<nblk, 256, 0, s>>>(A);
+        else k_lbm<S, C, true, 4><<<nblk, 256, 0, s>>>(A);
     } else {
-        k_lbm<S, C, false, false><<<nblk, 256, 0, s>>>(A);
-        k_lbm<S, C, false, true><<<nblk, 256, 0, s>>>(A);
+        k_lbm<S, C, false, 0><<<nblk, 256, 0, s>>>(A);
+        if (A.ms <= 2) k_lbm<S, C, false, 2><<<nblk, 256, 0, s>>>(A);
+        else k_lbm<S, C, false, 4><<<nblk, 256, 0, s>>>(A);
     }
     return hipGetLastError();
 }

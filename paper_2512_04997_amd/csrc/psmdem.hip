@@ -115,6 +115,7 @@ struct psmdem_domain {
     void* f = nullptr;
     double wall_corr[6][19];
     double* kolm_prof = nullptr;
+    double* wall_corr_d = nullptr;
 
     // particles
     PartArgs p{};
@@ -126,6 +127,8 @@ struct psmdem_domain {
     double h[3];
     long long ncell = 1;
     int *cell_count = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *cell_pid = nullptr;
+    int* pc = nullptr;
+    int *col_count = nullptr, *col_fill = nullptr, *col_start = nullptr, *col_list = nullptr;
     long long reg_cap = 0;
     int* pcount = nullptr;
     int* prow[2] = {nullptr, nullptr};
@@ -176,7 +179,7 @@ struct psmdem_domain {
         for (auto e : ev) (void)hipEventDestroy(e);
     }
 
-    DemArgs dem_args(int use_prev) {
+    DemArgs dem_args() {
         DemArgs A{};
         A.g = geo;
         A.p = p;
@@ -187,29 +190,22 @@ struct psmdem_domain {
             A.gravity[a] = d.gravity[a];
         }
         A.ncell = ncell;
+        A.pc = pc;
         A.cell_count = cell_count;
         A.cell_start = cell_start;
         A.cell_fill = cell_fill;
         A.cell_pid = cell_pid;
         A.reg_cap = reg_cap;
         A.pcount = pcount;
-        A.prow = prow[cur];
-        A.pairs = pairs[cur];
-        A.hist = hist[cur];
         A.cF = cF;
         A.cMi = cMi;
         A.cMj = cMj;
         A.incontact = incontact;
+        A.col_count = col_count;
+        A.col_fill = col_fill;
+        A.col_start = col_start;
+        A.col_list = col_list;
         A.pair_cap = pair_cap;
-        if (use_prev) {
-            A.prev_pairs = pairs[cur ^ 1];
-            A.prev_hist = hist[cur ^ 1];
-            A.prev_n = prow[cur ^ 1] + np;
-        } else {
-            A.prev_pairs = pairs[cur ^ 1];
-            A.prev_hist = hist[cur ^ 1];
-            A.prev_n = nullptr;
-        }
         A.kn = d.kn;
         A.beta_e = beta_e;
         A.mu = d.mu;
@@ -219,6 +215,28 @@ struct psmdem_domain {
             for (int c = 0; c < 3; ++c) A.wall_u[f_][c] = d.wall_u[f_][c];
         A.ctr = ctr;
         return A;
+    }
+
+    // current list = buffer cur, previous = the other one (or none)
+    PairBufs pair_bufs(int use_prev) {
+        PairBufs B{};
+        B.pairs = pairs[cur];
+        B.prow = prow[cur];
+        B.hist = hist[cur];
+        B.prev_pairs = pairs[cur ^ 1];
+        B.prev_hist = hist[cur ^ 1];
+        B.prev_n = use_prev ? prow[cur ^ 1] + np : nullptr;
+        return B;
+    }
+
+    PairSet pair_set() {
+        PairSet P{};
+        for (int b = 0; b < 2; ++b) {
+            P.pairs[b] = pairs[b];
+            P.prow[b] = prow[b];
+            P.hist[b] = hist[b];
+        }
+        return P;
     }
 
     VoxArgs vox_args() {
@@ -251,7 +269,7 @@ struct psmdem_domain {
         A.kolm_axis = d.kolm_axis;
         A.kolm_dir = d.kolm_dir;
         A.kolm_prof = kolm_prof;
-        memcpy(A.wall_corr, wall_corr, sizeof wall_corr);
+        A.wall_corr = wall_corr_d;
         A.t = t;
         A.kin = p.kin;
         A.np = np;
@@ -315,37 +333,48 @@ static int run_lbm(psmdem_domain* D) {
 }
 
 static int run_lists(psmdem_domain* D) {
-    DemArgs A = D->dem_args(1);
-    PSM_CHECK(dem_lists(A, D->scan_tmp, D->s));
+    DemArgs A = D->dem_args();
+    PairBufs B = D->pair_bufs(1);
+    PSM_CHECK(dem_lists(A, B, D->scan_tmp, D->s));
     return 0;
 }
 
 static int coupled_step(psmdem_domain* D) {
     int rc;
-    if (D->d.dem_on && D->np > 0) {
+    if (D->d.dem_on && D->np > 0 && D->np <= DEM_FUSED_MAX && D->nc[0] < 65536 && D->nc[1] < 65536 &&
+        D->nc[2] < 65536) {
+        // every DEM substep in one workgroup launch; with the fluid on, the last
+        // substep stops after the DEM sums and the corrector follows the coupling
+        const bool couple = D->d.fluid_on != 0;
+        DemArgs A = D->dem_args();
+        int tk = D->timed_begin(PSMDEM_T_DEM);
+        PSM_CHECK(dem_fused(A, D->pair_set(), D->cur, D->nsub, D->dt, couple ? 1 : 0, D->s));
+        D->timed_end(tk);
+        D->cur ^= (D->nsub & 1);
+        if (couple) {
+            if ((rc = run_voxelize(D))) return rc;
+            if ((rc = run_lbm(D))) return rc;
+            tk = D->timed_begin(PSMDEM_T_DEM);
+            PSM_CHECK(dem_correct(A, D->dt, D->s));
+            D->timed_end(tk);
+        }
+    } else if (D->d.dem_on && D->np > 0) {
         for (int sub = 1; sub <= D->nsub; ++sub) {
             const bool last = sub == D->nsub;
             int tk = D->timed_begin(PSMDEM_T_DEM);
-            {
-                DemArgs A = D->dem_args(1);
-                PSM_CHECK(dem_predict(A, D->dt, last ? 1 : 0, D->s));
-            }
+            DemArgs A = D->dem_args();
+            PSM_CHECK(dem_predict(A, D->dt, last ? 1 : 0, D->s));
             D->cur ^= 1;
-            {
-                DemArgs A = D->dem_args(1);
-                PSM_CHECK(dem_lists(A, D->scan_tmp, D->s));
-                PSM_CHECK(dem_contacts(A, D->p.vp, D->p.wp, D->dt, D->s));
-            }
+            PairBufs B = D->pair_bufs(1);
+            PSM_CHECK(dem_lists(A, B, D->scan_tmp, D->s));
+            PSM_CHECK(dem_contacts(A, B, D->p.vp, D->p.wp, D->dt, D->scan_tmp, D->s));
             D->timed_end(tk);
             if (last && D->d.fluid_on) {
                 if ((rc = run_voxelize(D))) return rc;
                 if ((rc = run_lbm(D))) return rc;
             }
             tk = D->timed_begin(PSMDEM_T_DEM);
-            {
-                DemArgs A = D->dem_args(1);
-                PSM_CHECK(dem_correct(A, D->dt, D->s));
-            }
+            PSM_CHECK(dem_correct(A, D->dt, D->s));
             D->timed_end(tk);
         }
     } else if (D->d.fluid_on) {
@@ -549,6 +578,7 @@ extern "C" psmdem_status psmdem_create(const psmdem_desc* desc, const psmdem_par
     P.qold = (double*)A(sizeof(double) * 4 * std::max(np, 1));
     P.kin = (double*)A(sizeof(double) * 9 * std::max(np, 1));
     D->reg_cap = 8LL * std::max(np, 1);
+    D->pc = (int*)A(sizeof(int) * 8 * std::max(np, 1));
     D->cell_count = (int*)A(sizeof(int) * D->ncell);
     D->cell_fill = (int*)A(sizeof(int) * D->ncell);
     D->cell_start = (int*)A(sizeof(int) * (D->ncell + 1));
@@ -564,6 +594,10 @@ extern "C" psmdem_status psmdem_create(const psmdem_desc* desc, const psmdem_par
     D->cMi = (double*)A(sizeof(double) * 3 * D->pair_cap);
     D->cMj = (double*)A(sizeof(double) * 3 * D->pair_cap);
     D->incontact = (unsigned char*)A(D->pair_cap);
+    D->col_count = (int*)A(sizeof(int) * std::max(np, 1));
+    D->col_fill = (int*)A(sizeof(int) * std::max(np, 1));
+    D->col_start = (int*)A(sizeof(int) * (np + 1));
+    D->col_list = (int*)A(sizeof(int) * D->pair_cap);
     // tiles
     long long per_particle = 1;
     {
@@ -590,6 +624,7 @@ extern "C" psmdem_status psmdem_create(const psmdem_desc* desc, const psmdem_par
     long long scan_n = std::max<long long>(std::max<long long>(D->ncell, g.ntiles), np + 1);
     D->scan_tmp = (int*)A(sizeof(int) * psm_scan_tmp_ints(scan_n));
     D->ctr = (DevCounters*)A(sizeof(DevCounters));
+    D->wall_corr_d = (double*)A(sizeof(double) * 6 * 19);
     if (d.kolm_amp != 0.0) {
         int n_ax = d.kolm_axis == 0 ? d.nx : (d.kolm_axis == 1 ? d.ny : d.nz);
         std::vector<double> prof(n_ax);
@@ -633,6 +668,7 @@ extern "C" psmdem_status psmdem_create(const psmdem_desc* desc, const psmdem_par
         H2D(D->t.tile_start, zt.data(), sizeof(int) * (g.ntiles + 1));
         DevCounters c0{};
         H2D(D->ctr, &c0, sizeof c0);
+        H2D(D->wall_corr_d, D->wall_corr, sizeof(double) * 6 * 19);
         // registration lists start out valid (particle 0, entry 0)
         if (hipMemsetAsync(D->t.tile_list, 0, sizeof(unsigned long long) * D->t.cap, D->s) != hipSuccess ||
             hipMemsetAsync(D->t.vinv, 0, sizeof(int) * D->t.cap, D->s) != hipSuccess ||
@@ -654,8 +690,10 @@ extern "C" psmdem_status psmdem_create(const psmdem_desc* desc, const psmdem_par
     if (np > 0) {
         // initial DEM forces: zero history, no increment (a(0) from F_dem(0) + F_ext)
         D->cur = 0;
-        DemArgs A0 = D->dem_args(0);
-        if (dem_lists(A0, D->scan_tmp, D->s) != hipSuccess || dem_contacts(A0, P.v, P.w, 0.0, D->s) != hipSuccess ||
+        DemArgs A0 = D->dem_args();
+        PairBufs B0 = D->pair_bufs(0);
+        if (dem_lists(A0, B0, D->scan_tmp, D->s) != hipSuccess ||
+            dem_contacts(A0, B0, P.v, P.w, 0.0, D->scan_tmp, D->s) != hipSuccess ||
             dem_initial_accel(A0, D->s) != hipSuccess || dem_zero(D->hist[0], 3 * D->pair_cap, D->s) != hipSuccess) {
             delete D;
             psm_set_error("initial DEM evaluation failed");
@@ -730,8 +768,9 @@ extern "C" psmdem_status psmdem_stage(psmdem_domain* d, int32_t stage) {
             if (hipMemcpyAsync(d->pairs[d->cur], d->pairs[prev], nb, hipMemcpyDeviceToDevice, d->s) != hipSuccess ||
                 hipMemcpyAsync(d->prow[d->cur], d->prow[prev], sizeof(int) * (d->np + 1), hipMemcpyDeviceToDevice, d->s) != hipSuccess)
                 return psm_hip_fail(hipGetLastError(), "copy", __FILE__, __LINE__);
-            DemArgs A = d->dem_args(1);
-            if (dem_contacts(A, d->p.vp, d->p.wp, d->dt, d->s) != hipSuccess)
+            DemArgs A = d->dem_args();
+            PairBufs B = d->pair_bufs(1);
+            if (dem_contacts(A, B, d->p.vp, d->p.wp, d->dt, d->scan_tmp, d->s) != hipSuccess)
                 return psm_hip_fail(hipGetLastError(), "contacts", __FILE__, __LINE__);
             break;
         }

@@ -177,63 +177,16 @@ __device__ inline bool in_box(const VoxPart& P, int x, int n, int axis, int peri
     int lo = P.lo[axis], hi = P.hi[axis];
     int v;
     if (periodic) {
+        // lo lies within one period below x: shift by whole periods without a division
         int d = x - lo;
-        d %= n;
-        if (d < 0) d += n;
+        while (d < 0) d += n;
+        while (d >= n) d -= n;
         v = lo + d;
     } else {
         v = x;
     }
     *X = v;
     return v >= lo && v <= hi;
-}
-
-__device__ double beta_sphere(const VoxPart& P, int X, int Y, int Z, int ns, int method, double Rc) {
-    const double R = P.ax[0];
-    if (method == 1) {
-        double dx = ((double)X + 0.5) - P.c[0], dy = ((double)Y + 0.5) - P.c[1], dz = ((double)Z + 0.5) - P.c[2];
-        double dist = sqrt((dx * dx + dy * dy) + dz * dz);
-        double delta = (R + Rc) - dist;
-        if (delta < 0.0) return 0.0;
-        if (delta > 2.0 * Rc) return 1.0;
-        return delta / (2.0 * Rc);
-    }
-    const double R2 = R * R;
-    // exact shortcuts: the cell box strictly inside / outside the sphere with a
-    // margin far above the rounding of any sample's squared distance
-    const int Xc[3] = {X, Y, Z};
-    double maxr2 = 0.0, minr2 = 0.0;
-    for (int a = 0; a < 3; ++a) {
-        double dl = (double)Xc[a] - P.c[a];
-        double dh = ((double)Xc[a] + 1.0) - P.c[a];
-        double l2 = dl * dl, h2 = dh * dh;
-        maxr2 += l2 > h2 ? l2 : h2;
-        minr2 += dl > 0.0 ? l2 : (dh < 0.0 ? h2 : 0.0);
-    }
-    const double m = 1e-8 * (1.0 + R2);
-    const int n3 = ns * ns * ns;
-    if (maxr2 < R2 - m) return 1.0;
-    if (minr2 > R2 + m) return 0.0;
-    int cnt = 0;
-    const double inv2ns = 1.0 / (double)(2 * ns);
-    (void)inv2ns;
-    for (int c = 0; c < ns; ++c) {
-        double oz = (double)(2 * c + 1) / (double)(2 * ns);
-        double dz = ((double)Z + oz) - P.c[2];
-        double dz2 = dz * dz;
-        for (int b = 0; b < ns; ++b) {
-            double oy = (double)(2 * b + 1) / (double)(2 * ns);
-            double dy = ((double)Y + oy) - P.c[1];
-            double dy2 = dy * dy;
-            for (int a = 0; a < ns; ++a) {
-                double ox = (double)(2 * a + 1) / (double)(2 * ns);
-                double dx = ((double)X + ox) - P.c[0];
-                double r2 = (dx * dx + dy2) + dz2;
-                cnt += (r2 < R2) ? 1 : 0;
-            }
-        }
-    }
-    return (double)cnt / (double)n3;
 }
 
 __device__ inline double ell_q(const VoxPart& P, double dx, double dy, double dz) {
@@ -243,60 +196,147 @@ __device__ inline double ell_q(const VoxPart& P, double dx, double dy, double dz
     return ((p0 * p0) * P.inv[0] + (p1 * p1) * P.inv[1]) + (p2 * p2) * P.inv[2];
 }
 
-__device__ double beta_ellipsoid(const VoxPart& P, int X, int Y, int Z, int ns) {
+// Classification of lattice cell (X,Y,Z) against particle P for the subdivision
+// method: 0 every sample outside, 1 every sample inside, 2 samples needed.
+// The shortcuts are exact: they only fire with a margin far above the rounding
+// of any sample's test value.
+__device__ int classify(const VoxPart& P, int X, int Y, int Z) {
     const int Xc[3] = {X, Y, Z};
-    double minr2 = 0.0;
-    double amax = P.ax[0] > P.ax[1] ? P.ax[0] : P.ax[1];
-    amax = amax > P.ax[2] ? amax : P.ax[2];
+    if (P.shape == 0) {
+        const double R2 = P.ax[0] * P.ax[0];
+        double maxr2 = 0.0, minr2 = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double dl = (double)Xc[a] - P.c[a];
+            double dh = ((double)Xc[a] + 1.0) - P.c[a];
+            double l2 = dl * dl, h2 = dh * dh;
+            maxr2 += l2 > h2 ? l2 : h2;
+            minr2 += dl > 0.0 ? l2 : (dh < 0.0 ? h2 : 0.0);
+        }
+        const double m = 1e-8 * (1.0 + R2);
+        if (maxr2 < R2 - m) return 1;
+        if (minr2 > R2 + m) return 0;
+        return 2;
+    }
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
         double dl = (double)Xc[a] - P.c[a];
         double dh = ((double)Xc[a] + 1.0) - P.c[a];
-        minr2 += dl > 0.0 ? dl * dl : (dh < 0.0 ? dh * dh : 0.0);
-        // outside the ellipsoid's axis-aligned box by a margin
-        if (dh < -P.e[a] - 1e-6 || dl > P.e[a] + 1e-6) return 0.0;
+        if (dh < -P.e[a] - 1e-6 || dl > P.e[a] + 1e-6) return 0;
     }
-    double rb = amax + 1e-6;
-    if (minr2 > rb * rb) return 0.0;
+    // |A^-1 R^T (p - c)| >= sqrt(q(centre)) - (sqrt(3)/2) / a_min for p in the cell
+    double amin = P.ax[0] < P.ax[1] ? P.ax[0] : P.ax[1];
+    amin = amin < P.ax[2] ? amin : P.ax[2];
+    double qc = ell_q(P, ((double)X + 0.5) - P.c[0], ((double)Y + 0.5) - P.c[1], ((double)Z + 0.5) - P.c[2]);
+    if (sqrt(qc) - 0.8660254037844387 / amin > 1.0 + 1e-6) return 0;
     bool all_in = true;
-    for (int corner = 0; corner < 8 && all_in; ++corner) {
+#pragma unroll
+    for (int corner = 0; corner < 8; ++corner) {
         double dx = ((double)X + (double)(corner & 1)) - P.c[0];
         double dy = ((double)Y + (double)((corner >> 1) & 1)) - P.c[1];
         double dz = ((double)Z + (double)((corner >> 2) & 1)) - P.c[2];
-        all_in = ell_q(P, dx, dy, dz) < 1.0 - 1e-9;
+        all_in = all_in && ell_q(P, dx, dy, dz) < 1.0 - 1e-9;
     }
-    if (all_in) return 1.0;
-    int cnt = 0;
-    for (int c = 0; c < ns; ++c) {
-        double dz = ((double)Z + (double)(2 * c + 1) / (double)(2 * ns)) - P.c[2];
-        for (int b = 0; b < ns; ++b) {
-            double dy = ((double)Y + (double)(2 * b + 1) / (double)(2 * ns)) - P.c[1];
-            for (int a = 0; a < ns; ++a) {
-                double dx = ((double)X + (double)(2 * a + 1) / (double)(2 * ns)) - P.c[0];
-                cnt += (ell_q(P, dx, dy, dz) < 1.0) ? 1 : 0;
-            }
+    return all_in ? 1 : 2;
+}
+
+#define VOX_MTAB 4096   // samples whose (a, b, c) indices are tabulated in LDS (ns <= 16)
+
+// one sample m (a fastest): inside test in the evaluation order of the definition
+__device__ inline bool sample_in(const VoxPart& P, int X, int Y, int Z, const double* off, int ns, int m,
+                                 const unsigned short* mtab) {
+    int a, b, c;
+    if (mtab) {
+        const unsigned t = mtab[m];
+        a = t & 31;
+        b = (t >> 5) & 31;
+        c = t >> 10;
+    } else {
+        a = m % ns;
+        b = (m / ns) % ns;
+        c = m / (ns * ns);
+    }
+    const double dz = ((double)Z + off[c]) - P.c[2];
+    const double dy = ((double)Y + off[b]) - P.c[1];
+    const double dx = ((double)X + off[a]) - P.c[0];
+    if (P.shape == 0) {
+        const double R2 = P.ax[0] * P.ax[0];
+        return ((dx * dx + dy * dy) + dz * dz) < R2;
+    }
+    return ell_q(P, dx, dy, dz) < 1.0;
+}
+
+__device__ inline double beta_distance(const VoxPart& P, int X, int Y, int Z, double Rc) {
+    const double R = P.ax[0];
+    double dx = ((double)X + 0.5) - P.c[0], dy = ((double)Y + 0.5) - P.c[1], dz = ((double)Z + 0.5) - P.c[2];
+    double dist = sqrt((dx * dx + dy * dy) + dz * dz);
+    double delta = (R + Rc) - dist;
+    if (delta < 0.0) return 0.0;
+    if (delta > 2.0 * Rc) return 1.0;
+    return delta / (2.0 * Rc);
+}
+
+#define VOX_QCAP 2048
+#define VOX_T 256
+
+// keep the ms largest beta (ties: the earlier, smaller pid wins); register-resident
+__device__ inline void keep_top(double (&bb)[PSM_SLOTS_MAX], int (&bl)[PSM_SLOTS_MAX], int& nk, int ms,
+                                double beta, int u, unsigned long long& dropped) {
+    int pos;
+    if (nk < ms) {
+        pos = nk++;
+    } else {
+        ++dropped;
+        double last = bb[0];
+#pragma unroll
+        for (int q = 1; q < PSM_SLOTS_MAX; ++q)
+            if (q == ms - 1) last = bb[q];
+        if (!(beta > last)) return;
+        pos = ms - 1;
+    }
+#pragma unroll
+    for (int q = 0; q < PSM_SLOTS_MAX; ++q)
+        if (q == pos) {
+            bb[q] = beta;
+            bl[q] = u;
         }
-    }
-    return (double)cnt / (double)(ns * ns * ns);
+#pragma unroll
+    for (int q = PSM_SLOTS_MAX - 1; q >= 1; --q)
+        if (q <= pos && bb[q - 1] < bb[q]) {
+            double tb = bb[q]; bb[q] = bb[q - 1]; bb[q - 1] = tb;
+            int ti = bl[q]; bl[q] = bl[q - 1]; bl[q - 1] = ti;
+        }
 }
 
 template <typename C>
-__global__ __launch_bounds__(256) void k_voxelize(VoxArgs A) {
+__global__ __launch_bounds__(VOX_T) void k_voxelize(VoxArgs A) {
     __shared__ VoxPart sp[PSM_PMAX];
+    __shared__ double off[32];
+    __shared__ unsigned qitem[VOX_QCAP];
+    __shared__ int qcnt[VOX_QCAP];
+    __shared__ int tcnt[VOX_T];
+    __shared__ unsigned short mtab_s[VOX_MTAB];
     __shared__ unsigned long long cnt_e, cnt_d;
     const long long t = blockIdx.x;
     if (t >= A.g.ntiles) return;
     long long s0 = A.t.tile_start[t], s1 = A.t.tile_start[t + 1];
     if (s1 > A.t.cap) s1 = A.t.cap;
     const int count = (int)(s1 - s0) < PSM_PMAX ? (int)(s1 - s0) : PSM_PMAX;
-    const int tid = threadIdx.x;
+    if (count <= 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int tx = (int)(t % A.g.ntx), ty = (int)((t / A.g.ntx) % A.g.nty), tz = (int)(t / ((long long)A.g.ntx * A.g.nty));
     const long long base = t * (long long)PSM_TILE;
-    const int ms = A.ms;
+    const int ms = A.ms, ns = A.ns, n3 = ns * ns * ns;
+    const bool subdiv = A.sf_method == 0;
     C* Bout = (C*)A.t.slot_B;
     const long long plane = A.g.ntiles * (long long)PSM_TILE;
-    if (count <= 0) return;
     if (tid == 0) { cnt_e = 0; cnt_d = 0; }
-    for (int u = tid; u < count; u += blockDim.x) {
+    if (tid < ns) off[tid] = (double)(2 * tid + 1) / (double)(2 * ns);
+    const unsigned short* mtab = n3 <= VOX_MTAB ? mtab_s : nullptr;
+    if (mtab)
+        for (int m = tid; m < n3; m += VOX_T)
+            mtab_s[m] = (unsigned short)((m % ns) | (((m / ns) % ns) << 5) | ((m / (ns * ns)) << 10));
+    for (int u = tid; u < count; u += VOX_T) {
         int k = (int)(A.t.tile_list[s0 + u] >> 32);
         if (k >= A.p.np) k = 0;
         VoxPart& P = sp[u];
@@ -312,55 +352,136 @@ __global__ __launch_bounds__(256) void k_voxelize(VoxArgs A) {
         lattice_box(A, k, P.lo, P.hi);
     }
     __syncthreads();
-    const int lx = tid & (PSM_TX - 1), ly = tid / PSM_TX;
-    const int x = tx * PSM_TX + lx, y = ty * PSM_TY + ly;
+    const int x = tx * PSM_TX + lane, y = ty * PSM_TY + wid;
+    const bool xy_ok = x < A.g.nx && y < A.g.ny;
+
+    // phase A: number of (cell, particle) items that need samples, per lane
+    int mine = 0;
+    if (subdiv && xy_ok)
+        for (int lz = 0; lz < PSM_TZ; ++lz) {
+            const int z = tz * PSM_TZ + lz;
+            if (z >= A.g.nz) break;
+            for (int u = 0; u < count; ++u) {
+                int X, Y, Z;
+                const VoxPart& P = sp[u];
+                if (!in_box(P, x, A.g.nx, 0, A.g.periodic[0], &X) || !in_box(P, y, A.g.ny, 1, A.g.periodic[1], &Y) ||
+                    !in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z))
+                    continue;
+                mine += classify(P, X, Y, Z) == 2;
+            }
+        }
+    tcnt[tid] = mine;
+    __syncthreads();
+    int my_off = 0, total = 0;
+    for (int w = 0; w < VOX_T; ++w) {
+        int c = tcnt[w];
+        if (w < tid) my_off += c;
+        total += c;
+    }
+    // queue the items (lane order, then plane, then particle)
+    if (mine) {
+        int j = my_off;
+        for (int lz = 0; lz < PSM_TZ && j < VOX_QCAP; ++lz) {
+            const int z = tz * PSM_TZ + lz;
+            if (z >= A.g.nz) break;
+            const unsigned l = lane + PSM_TX * (wid + PSM_TY * lz);
+            for (int u = 0; u < count && j < VOX_QCAP; ++u) {
+                int X, Y, Z;
+                const VoxPart& P = sp[u];
+                if (!in_box(P, x, A.g.nx, 0, A.g.periodic[0], &X) || !in_box(P, y, A.g.ny, 1, A.g.periodic[1], &Y) ||
+                    !in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z))
+                    continue;
+                if (classify(P, X, Y, Z) == 2) qitem[j++] = (l << 8) | (unsigned)u;
+            }
+        }
+    }
+    __syncthreads();
+    // phase B: each wave counts the inside samples of one item at a time (64 lanes
+    // per pass, the exact count from ballots)
+    const int nq = total < VOX_QCAP ? total : VOX_QCAP;
+    for (int it = wid; it < nq; it += VOX_T / 64) {
+        const unsigned item = qitem[it];
+        const int u = (int)(item & 0xffu), l = (int)(item >> 8);
+        const int cx = tx * PSM_TX + (l % PSM_TX), cy = ty * PSM_TY + (l / PSM_TX) % PSM_TY;
+        const int cz = tz * PSM_TZ + l / (PSM_TX * PSM_TY);
+        const VoxPart& P = sp[u];
+        int X, Y, Z;
+        in_box(P, cx, A.g.nx, 0, A.g.periodic[0], &X);
+        in_box(P, cy, A.g.ny, 1, A.g.periodic[1], &Y);
+        in_box(P, cz, A.g.nz, 2, A.g.periodic[2], &Z);
+        int cnt = 0;
+        for (int m0 = 0; m0 < n3; m0 += 64) {
+            const int m = m0 + lane;
+            const bool in = m < n3 && sample_in(P, X, Y, Z, off, ns, m, mtab);
+            cnt += __popcll(__ballot(in));
+        }
+        if (lane == 0) qcnt[it] = cnt;
+    }
+    __syncthreads();
+    // phase C: beta per (cell, particle) in pid order, keep the largest
     unsigned long long my_e = 0, my_d = 0;
+    int j = my_off;
     for (int lz = 0; lz < PSM_TZ; ++lz) {
         const int z = tz * PSM_TZ + lz;
-        const long long l = lx + PSM_TX * (ly + PSM_TY * lz);
-        double bb[PSM_SLOTS_MAX];
-        int bl[PSM_SLOTS_MAX];
+        const long long l = lane + PSM_TX * (wid + PSM_TY * lz);
+        double bb[PSM_SLOTS_MAX] = {0.0, 0.0, 0.0, 0.0};
+        int bl[PSM_SLOTS_MAX] = {0, 0, 0, 0};
         int nk = 0;
-        if (x < A.g.nx && y < A.g.ny && z < A.g.nz) {
+        if (xy_ok && z < A.g.nz) {
             for (int u = 0; u < count; ++u) {
                 const VoxPart& P = sp[u];
                 int X, Y, Z;
-                if (!in_box(P, x, A.g.nx, 0, A.g.periodic[0], &X)) continue;
-                if (!in_box(P, y, A.g.ny, 1, A.g.periodic[1], &Y)) continue;
-                if (!in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z)) continue;
-                double beta = (P.shape == 0) ? beta_sphere(P, X, Y, Z, A.ns, A.sf_method, A.Rc)
-                                             : beta_ellipsoid(P, X, Y, Z, A.ns);
+                if (!in_box(P, x, A.g.nx, 0, A.g.periodic[0], &X) || !in_box(P, y, A.g.ny, 1, A.g.periodic[1], &Y) ||
+                    !in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z))
+                    continue;
+                double beta;
+                if (!subdiv) {
+                    beta = beta_distance(P, X, Y, Z, A.Rc);
+                } else {
+                    const int cl = classify(P, X, Y, Z);
+                    if (cl == 0) continue;
+                    if (cl == 1) {
+                        beta = 1.0;
+                    } else {
+                        int cnt;
+                        if (j < VOX_QCAP) {
+                            cnt = qcnt[j];
+                        } else {
+                            cnt = 0;
+                            for (int m = 0; m < n3; ++m) cnt += sample_in(P, X, Y, Z, off, ns, m, mtab);
+                        }
+                        ++j;
+                        beta = (double)cnt / (double)n3;
+                    }
+                }
                 if (!(beta > 0.0)) continue;
                 ++my_e;
-                // keep the ms largest, ties to the earlier (smaller) pid
-                if (nk < ms) {
-                    int q = nk++;
-                    while (q > 0 && bb[q - 1] < beta) { bb[q] = bb[q - 1]; bl[q] = bl[q - 1]; --q; }
-                    bb[q] = beta; bl[q] = u;
-                } else if (beta > bb[ms - 1]) {
-                    ++my_d;
-                    int q = ms - 1;
-                    while (q > 0 && bb[q - 1] < beta) { bb[q] = bb[q - 1]; bl[q] = bl[q - 1]; --q; }
-                    bb[q] = beta; bl[q] = u;
-                } else {
-                    ++my_d;
-                }
+                keep_top(bb, bl, nk, ms, beta, u, my_d);
             }
         }
         // kept slots ordered by pid (local index order is pid order)
-        for (int u = 1; u < nk; ++u)
-            for (int v = u; v > 0 && bl[v] < bl[v - 1]; --v) {
-                int ti = bl[v]; bl[v] = bl[v - 1]; bl[v - 1] = ti;
-                double tb = bb[v]; bb[v] = bb[v - 1]; bb[v - 1] = tb;
-            }
+#pragma unroll
+        for (int pass = 0; pass < PSM_SLOTS_MAX - 1; ++pass)
+#pragma unroll
+            for (int q = 0; q < PSM_SLOTS_MAX - 1; ++q)
+                if (q + 1 < nk && bl[q + 1] < bl[q]) {
+                    int ti = bl[q]; bl[q] = bl[q + 1]; bl[q + 1] = ti;
+                    double tb = bb[q]; bb[q] = bb[q + 1]; bb[q + 1] = tb;
+                }
         unsigned int lp = 0xffffffffu;
-        for (int k = 0; k < nk; ++k) lp = (lp & ~(0xffu << (8 * k))) | ((unsigned)bl[k] << (8 * k));
-        A.t.slot_lp[base + l] = lp;
-        for (int k = 0; k < ms; ++k) {
-            double beta = k < nk ? bb[k] : 0.0;
-            double B = beta * (A.tau - 0.5) / ((1.0 - beta) + (A.tau - 0.5));
-            Bout[k * plane + base + l] = (C)B;
-            A.t.slot_beta[k * plane + base + l] = beta;
+#pragma unroll
+        for (int q = 0; q < PSM_SLOTS_MAX; ++q)
+            if (q < nk) lp = (lp & ~(0xffu << (8 * q))) | ((unsigned)bl[q] << (8 * q));
+        if (xy_ok && z < A.g.nz) {
+            A.t.slot_lp[base + l] = lp;
+#pragma unroll
+            for (int q = 0; q < PSM_SLOTS_MAX; ++q) {
+                if (q >= ms) break;
+                double beta = q < nk ? bb[q] : 0.0;
+                double B = beta * (A.tau - 0.5) / ((1.0 - beta) + (A.tau - 0.5));
+                Bout[q * plane + base + l] = (C)B;
+                A.t.slot_beta[q * plane + base + l] = beta;
+            }
         }
     }
     if (my_e) atomicAdd(&cnt_e, my_e);
@@ -409,8 +530,8 @@ hipError_t vox_register(const VoxArgs& A, int* scan_tmp, hipStream_t s) {
 }
 
 hipError_t vox_voxelize(const VoxArgs& A, int ctype_double, hipStream_t s) {
-    if (ctype_double) k_voxelize<double><<<(unsigned)A.g.ntiles, 256, 0, s>>>(A);
-    else k_voxelize<float><<<(unsigned)A.g.ntiles, 256, 0, s>>>(A);
+    if (ctype_double) k_voxelize<double><<<(unsigned)A.g.ntiles, VOX_T, 0, s>>>(A);
+    else k_voxelize<float><<<(unsigned)A.g.ntiles, VOX_T, 0, s>>>(A);
     return hipGetLastError();
 }
 

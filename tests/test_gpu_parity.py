@@ -234,3 +234,28 @@ def test_determinism_bitwise(ps):
         G.close()
     for a, b in zip(*out):
         assert np.array_equal(a, b)
+
+
+def test_dem_multi_launch_path(ps, oracle_mod):
+    """More particles than one workgroup takes: the per-phase kernels with the
+    counting-sort cell list (DEM only, walls, friction, contacts)."""
+    box = (72, 64, 60)
+    rng = W.SplitMix64(77)
+    n = 2300
+    radii = 1.2 + 0.6 * rng.uniform(n)
+    pos = W.rsa_spheres(rng, n, radii, box, [True, True, False], gap=-0.4)
+    m = len(pos)
+    assert m > 2048
+    parts = W.spheres(pos, radii[:m], 1.8, vel=0.01 * (rng.uniform(3 * m).reshape(m, 3) - 0.5))
+    cfg = _walled(box, 0.7, "fp64", fluid_on=False, mu=0.3, restitution=0.6, n_sub=6,
+                  gravity=[0.0, 0.0, -1e-4])
+    G, O = _pair(ps, oracle_mod, cfg, parts)
+    for _ in range(2):
+        G.step(1)
+        O.step(1)
+        assert np.array_equal(G.pairs()[0], O.pairs()[0])
+        Pg, Po = G.particles(), O.particles()
+        assert vec_err(Pg["pos"], Po["pos"]) < 1e-12
+        assert vec_err(Pg["vel"], Po["vel"]) < 1e-12
+        assert force_err(Pg["f_dem"], Po["f_dem"], O.scales()["f_dem"], force_floor(O)) < 1e-12
+    assert O.counters()["contacts"] > 50
