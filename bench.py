@@ -38,7 +38,107 @@ def parse():
     p.add_argument("--cpu-sample-steps", type=int, default=20,
                    help="coupled steps of the CPU oracle sample (0: skip the CPU baseline)")
     p.add_argument("--no-timing", action="store_true", help="skip the per-kernel event timing pass")
+    p.add_argument("--serve-jobs", type=int, default=32,
+                   help="jobs of the ensemble-serving sample (0: skip the serving measurement)")
+    p.add_argument("--serve-steps", type=int, default=100, help="coupled steps per served job")
+    p.add_argument("--serve-rate", type=float, default=50.0, help="mean arrival rate of served jobs (1/s)")
+    p.add_argument("--serve-slots", type=int, default=32, help="active slots of the server")
+    p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                   help="only run 20 plain device copies of MIB MiB (calibrates the HBM byte counters)")
     return p.parse_args()
+
+
+def copy_probe(mib):
+    """Plain device-to-device copies of a known size: the reference that scales
+    the FETCH_SIZE / WRITE_SIZE counters of the profiler into HBM bytes."""
+    import torch
+    n = mib * 2 ** 20 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(20):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4, "launches": 20}))
+
+
+def _pct(x, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(x), q)) if len(x) else None
+
+
+def serve_batched(stream, slots, precision):
+    """The job stream through the continuous-batching server: arrivals on the
+    wall clock, a done job released at once.  Latency = done - arrival."""
+    from paper_2512_04997_amd import psmdem
+    S = psmdem.Server(max_jobs=slots, hbm_budget=64 << 30, precision=precision)
+    t0 = psmdem.clock()
+    ids = {}
+    lat = []
+    k = 0
+    n_done = 0
+    while n_done < len(stream):
+        now = psmdem.clock() - t0
+        while k < len(stream) and stream[k][0] <= now:
+            arr, cfg, parts, steps = stream[k]
+            ids[S.submit(cfg, parts, steps)] = arr
+            k += 1
+        n_active, n_queued = S.iterate()
+        if n_active == 0 and n_queued == 0 and k < len(stream):
+            time.sleep(max(0.0, min(0.01, stream[k][0] - (psmdem.clock() - t0))))
+        for j in list(ids):
+            info = S.job(j)
+            if info["state"] == "done":
+                lat.append(info["t_done"] - t0 - ids.pop(j))
+                S.release(j)
+                n_done += 1
+            elif info["state"] == "failed":
+                raise RuntimeError(f"served job failed: {info}")
+    wall = psmdem.clock() - t0
+    S.close()
+    return wall, lat
+
+
+def serve_one_at_a_time(stream):
+    """The same stream, one job at a time in arrival order through the
+    single-domain API (create, step, synchronise)."""
+    from paper_2512_04997_amd import psmdem
+    import torch
+    t0 = psmdem.clock()
+    lat = []
+    for arr, cfg, parts, steps in stream:
+        wait = arr - (psmdem.clock() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        D = psmdem.Domain(cfg, parts)
+        D.step(steps)
+        D.sync()
+        torch.cuda.synchronize()
+        lat.append(psmdem.clock() - t0 - arr)
+        D.close()
+    return psmdem.clock() - t0, lat
+
+
+def serving(a):
+    from paper_2512_04997_amd import workloads
+    stream = workloads.serving_stream(njobs=a.serve_jobs, rate=a.serve_rate, steps=a.serve_steps,
+                                      precision="fp32")
+    lups = sum(c["n"][0] * c["n"][1] * c["n"][2] * st for _, c, _, st in stream)
+    # warm both paths (code objects, allocator pools) on a short prefix
+    warm = [(0.0, c, p, 2) for _, c, p, _ in stream[:4]]
+    serve_batched(warm, a.serve_slots, "fp32")
+    serve_one_at_a_time(warm)
+    wb, lb = serve_batched(stream, a.serve_slots, "fp32")
+    ws, ls = serve_one_at_a_time(stream)
+    res = {"jobs": len(stream), "steps_per_job": a.serve_steps, "arrival_rate_per_s": a.serve_rate,
+           "slots": a.serve_slots, "lattices": "uniform over 32^3, 64^3, 96^3, 128^3",
+           "lattice_updates": lups,
+           "batched": {"mlups": round(lups / wb / 1e6, 1), "jobs_per_s": round(len(stream) / wb, 3),
+                       "p50_s": round(_pct(lb, 50), 4), "p99_s": round(_pct(lb, 99), 4), "wall_s": round(wb, 3)},
+           "one_at_a_time": {"mlups": round(lups / ws / 1e6, 1), "jobs_per_s": round(len(stream) / ws, 3),
+                             "p50_s": round(_pct(ls, 50), 4), "p99_s": round(_pct(ls, 99), 4),
+                             "wall_s": round(ws, 3)}}
+    res["speedup"] = round(ws / wb, 3)
+    return res
 
 
 def cpu_baseline(cfg, parts, steps):
@@ -66,6 +166,9 @@ def main():
         sys.exit(2)
     import torch
 
+    if a.copy_probe:
+        copy_probe(a.copy_probe)
+        return
     from paper_2512_04997_amd import psmdem, workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -87,8 +190,10 @@ def main():
     D.sync()
     ms = elapsed / a.steps * 1e3
     mlups = N * a.steps / elapsed / 1e6
-    print(f"[bench] {a.steps} steps in {elapsed:.3f} s: {ms:.3f} ms/step, {mlups:.0f} MLUPS",
-          file=sys.stderr, flush=True)
+    ctr = D.counters()
+    print(f"[bench] {a.steps} steps in {elapsed:.3f} s: {ms:.3f} ms/step, {mlups:.0f} MLUPS; "
+          f"solid tiles {ctr['n_solid_tiles']}, entries {ctr['n_entries']}, pairs {ctr['n_pairs']}, "
+          f"contacts {ctr['n_contacts']}", file=sys.stderr, flush=True)
 
     roof = None
     if not a.no_timing:
@@ -111,6 +216,14 @@ def main():
               f"dem {dem_ms * dem_n / max(lbm_n, 1):.4f} ms ({dem_n // max(lbm_n, 1)} DEM launch groups)",
               file=sys.stderr, flush=True)
 
+    serve = None
+    if a.serve_jobs > 0:
+        serve = serving(a)
+        print(f"[bench] serving {serve['jobs']} jobs x {serve['steps_per_job']} steps: batched "
+              f"{serve['batched']['mlups']} MLUPS p50 {serve['batched']['p50_s']} s p99 {serve['batched']['p99_s']} s; "
+              f"one at a time {serve['one_at_a_time']['mlups']} MLUPS p50 {serve['one_at_a_time']['p50_s']} s "
+              f"p99 {serve['one_at_a_time']['p99_s']} s", file=sys.stderr, flush=True)
+
     cpu = None
     if a.cpu_sample_steps > 0:
         cpu = cpu_baseline(cfg, parts, a.cpu_sample_steps)
@@ -123,7 +236,7 @@ def main():
            "config": {"workload": meta["workload"], "lattice": [a.n] * 3, "particles": info["n_particles"],
                       "n_sub": info["n_sub"], "tau": cfg["tau"], "populations": a.precision,
                       "particles_dtype": "fp64"},
-           "roofline": roof, "cpu_baseline": cpu}
+           "roofline": roof, "cpu_baseline": cpu, "serving": serve}
     print(json.dumps(out), flush=True)
 
 

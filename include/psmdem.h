@@ -210,6 +210,90 @@ psmdem_status psmdem_set_timing(psmdem_domain* d, int32_t on);
 psmdem_status psmdem_timing(psmdem_domain* d, int32_t which, double* avg_ms, int64_t* launches);
 typedef enum { PSMDEM_T_LBM = 0, PSMDEM_T_VOXEL = 1, PSMDEM_T_DEM = 2, PSMDEM_T_HYDRO = 3 } psmdem_timer;
 
+/* Device bytes psmdem_create would allocate for this description and particle
+ * set (the memory model used for admission by the serving loop).  Touches no
+ * device. */
+psmdem_status psmdem_footprint(const psmdem_desc* desc, const psmdem_particles* parts, int64_t* bytes);
+
+/* --- ensemble serving: continuous batching of many domains ---------------- */
+/* A server advances many independent domains ("jobs") together.  Each
+ * psmdem_server_iterate call
+ *   1. marks jobs done whose last step the device has finished,
+ *   2. admits queued jobs in arrival order while a slot is free and the
+ *      footprints of the held jobs plus the next one fit hbm_budget (the job
+ *      is created on the admission stream, so the steps already enqueued keep
+ *      running meanwhile),
+ *   3. enqueues one coupled step of every active job as six batched launches
+ *      on the compute stream: fused DEM substeps (one workgroup per job), tile
+ *      registration (one workgroup per job), voxelisation and the two LBM-PSM
+ *      passes (one workgroup per lattice tile of every job), hydrodynamic sums
+ *      and the corrector (one workgroup per job),
+ *   4. retires the jobs that reached their step count (their memory stays
+ *      held, and readable, until psmdem_server_release).
+ * The host runs at most max_inflight steps ahead of the device.  A job's
+ * result is the one psmdem_step gives on the same domain, bit for bit: the
+ * batched launches run the single-domain device code on each job's own data,
+ * in the same order.  Jobs must have the fluid on, the server's precision, at
+ * most 2048 particles when the DEM is on, and at most 8192 lattice tiles of
+ * 64 x 4 x 4 cells.  Calls on one server are not thread-safe. */
+typedef struct psmdem_server psmdem_server;
+
+typedef struct {
+    int32_t max_jobs;       /* active slots, 1..128 */
+    int64_t hbm_budget;     /* device bytes the held jobs may occupy together (0: unlimited) */
+    int32_t max_inflight;   /* coupled steps enqueued ahead of the device (0: 2) */
+    int32_t precision;      /* psmdem_precision of every job */
+} psmdem_server_desc;
+
+typedef enum {
+    PSMDEM_JOB_QUEUED = 0,
+    PSMDEM_JOB_ACTIVE = 1,
+    PSMDEM_JOB_FINISHING = 2,   /* every step enqueued, device not finished yet */
+    PSMDEM_JOB_DONE = 3,        /* results readable */
+    PSMDEM_JOB_FAILED = 4       /* creation failed (psmdem_server_job reports the status) */
+} psmdem_job_state;
+
+typedef struct {
+    int32_t state;          /* psmdem_job_state */
+    int32_t slot;           /* active slot, -1 when not active */
+    int64_t steps;          /* requested coupled steps */
+    int64_t steps_done;     /* coupled steps enqueued so far */
+    int64_t footprint;      /* device bytes (psmdem_footprint) */
+    int32_t status;         /* creation status of a failed job */
+    double t_submit;        /* psmdem_clock() at submission */
+    double t_admit;         /* at admission (0 before) */
+    double t_done;          /* when the server saw the device finish the last step (0 before) */
+} psmdem_job_info_t;
+
+/* Seconds of a monotonic host clock (the clock of the job times). */
+double psmdem_clock(void);
+
+/* stream: compute stream; admit_stream: stream of job creation (NULL: the
+ * compute stream).  alloc/free as for psmdem_create, used for every job and
+ * for the server's tables (memory is allocated while admit_stream's work is
+ * the only work that may touch it). */
+psmdem_status psmdem_server_create(const psmdem_server_desc* desc, void* stream, void* admit_stream,
+                                   psmdem_alloc_fn alloc, psmdem_free_fn free_fn, void* alloc_ctx,
+                                   psmdem_server** out);
+/* Waits for the device and frees every job. */
+void psmdem_server_destroy(psmdem_server* s);
+/* Queues a job of `steps` coupled steps; inputs are copied.  *job receives
+ * its id (> 0).  Refuses jobs the server cannot run (PSMDEM_E_INVALID) or
+ * whose footprint alone exceeds the budget (PSMDEM_E_NOMEM). */
+psmdem_status psmdem_server_submit(psmdem_server* s, const psmdem_desc* desc, const psmdem_particles* parts,
+                                   int64_t steps, int64_t* job);
+/* One serving iteration (steps 1-4 above); either output may be NULL. */
+psmdem_status psmdem_server_iterate(psmdem_server* s, int32_t* n_active, int32_t* n_queued);
+/* Waits for the enqueued steps; finishing jobs become done. */
+psmdem_status psmdem_server_drain(psmdem_server* s);
+psmdem_status psmdem_server_job(psmdem_server* s, int64_t job, psmdem_job_info_t* out);
+/* The domain of a done job, for the psmdem_read_* calls (owned by the
+ * server; valid until the job is released; do not step it). */
+psmdem_status psmdem_server_domain(psmdem_server* s, int64_t job, psmdem_domain** out);
+/* Frees a job's memory; a queued job is dropped, an active one cancelled
+ * (waits for the device). */
+psmdem_status psmdem_server_release(psmdem_server* s, int64_t job);
+
 const char* psmdem_last_error(void);
 const char* psmdem_version(void);
 

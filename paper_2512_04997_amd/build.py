@@ -23,6 +23,7 @@ SOURCES = [
     ("voxel.hip", ["-ffp-contract=off"]),
     ("lbm.hip", []),
     ("psmdem.hip", []),
+    ("server.hip", []),
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -94,6 +94,64 @@ struct DevCounters {
     unsigned long long contacts;
 };
 
+// ---------------------------------------------------------------------------
+// device helpers shared by several kernels
+// ---------------------------------------------------------------------------
+// Exclusive scan of in[0..n) into out[0..n], out[n] = total, by one workgroup
+// of NT threads (every thread of the workgroup calls it).
+template <int NT>
+__device__ inline void psm_block_scan(const int* in, int* out, long long n) {
+    __shared__ int wsum[NT / 64];
+    __shared__ int carry;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (long long base = 0; base < n; base += NT) {
+        const long long i = base + tid;
+        const int v = i < n ? in[i] : 0;
+        int x = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wid] = x;
+        __syncthreads();
+        int off = 0, tot = 0;
+        for (int w = 0; w < NT / 64; ++w) {
+            off += w < wid ? wsum[w] : 0;
+            tot += wsum[w];
+        }
+        const int c = carry;
+        if (i < n) out[i] = c + off + x - v;
+        __syncthreads();
+        if (tid == 0) carry = c + tot;
+        __syncthreads();
+    }
+    if (tid == 0) out[n] = carry;
+    __syncthreads();
+}
+
+// hydrodynamic force and torque of particle k (Sec. 2.4, momentum exchange):
+// minus the sum of its per-tile partials, in emission order
+__device__ inline void psm_reduce_hydro(const TileArgs& t, const PartArgs& p, int k) {
+    double F[3] = {0.0, 0.0, 0.0}, M[3] = {0.0, 0.0, 0.0};
+    const int e0 = t.voff[k], e1 = t.voff[k + 1];
+    for (int e = e0; e < e1 && e < t.cap; ++e) {
+        const long long s = t.vinv[e];
+        if (s < 0 || s >= t.cap) continue;
+        const double* P = t.partial + 6 * s;
+        for (int c = 0; c < 3; ++c) {
+            F[c] -= P[c];
+            M[c] -= P[3 + c];
+        }
+    }
+    for (int c = 0; c < 3; ++c) {
+        p.fh[3 * k + c] = F[c];
+        p.mh[3 * k + c] = M[c];
+    }
+}
+
 // host helpers
 #define PSM_CHECK(call)                                                      \
     do {                                                                     \

@@ -24,6 +24,7 @@
 
 #include "common.h"
 #include "dem.h"
+#include "serve.h"
 
 namespace {
 
@@ -773,7 +774,7 @@ __global__ void k_scatter(DemArgs A) { GRID_LOOP(k, A.p.np) ph_scatter(A, (int)k
 __global__ void k_cellsort(DemArgs A) { GRID_LOOP(c, A.ncell) ph_cellsort(A, c); }
 __global__ void k_paircount(DemArgs A) { GRID_LOOP(i, A.p.np) ph_paircount<false>(A, (int)i); }
 __global__ void k_pairemit(DemArgs A, PairBufs B) { GRID_LOOP(i, A.p.np) ph_pairemit<false>(A, B, (int)i); }
-__global__ void k_contacts(DemArgs A, PairBufs B, const double* vv, const double* ww, double dth) {
+__global__ __launch_bounds__(256) void k_contacts(DemArgs A, PairBufs B, const double* vv, const double* ww, double dth) {
     long long nprev = B.prev_n ? *B.prev_n : 0;
     nprev = nprev < A.pair_cap ? nprev : A.pair_cap;
     const long long n = n_pairs(A, B);
@@ -797,42 +798,11 @@ __global__ void k_zero_d(double* p, long long n) { GRID_LOOP(i, n) p[i] = 0.0; }
 // ---------------------------------------------------------------------------
 // fused single-workgroup substeps
 // ---------------------------------------------------------------------------
-#define FUSED_T 1024
+#define FUSED_T 512
 
-// exclusive scan of in[0..n) into out[0..n], out[n] = total, by one workgroup
-__device__ void block_scan(const int* in, int* out, int n) {
-    __shared__ int wsum[FUSED_T / 64];
-    __shared__ int carry;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    if (tid == 0) carry = 0;
-    __syncthreads();
-    for (int base = 0; base < n; base += FUSED_T) {
-        const int i = base + tid;
-        const int v = i < n ? in[i] : 0;
-        int x = v;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            int y = __shfl_up(x, o, 64);
-            if (lane >= o) x += y;
-        }
-        if (lane == 63) wsum[wid] = x;
-        __syncthreads();
-        int off = 0, tot = 0;
-        for (int w = 0; w < FUSED_T / 64; ++w) {
-            off += w < wid ? wsum[w] : 0;
-            tot += wsum[w];
-        }
-        const int c = carry;
-        if (i < n) out[i] = c + off + x - v;
-        __syncthreads();
-        if (tid == 0) carry = c + tot;
-        __syncthreads();
-    }
-    if (tid == 0) out[n] = carry;
-    __syncthreads();
-}
-
-#define FUSED_PREV_LDS 3072
+#define FUSED_PREV_LDS 3072   // previous pair keys staged in LDS for the history search
+#define FUSED_CELLS 8192      // DEM grids up to this many cells keep their cell list in LDS
+#define FUSED_COLS 8192       // pair lists up to this length keep their column lists in LDS
 
 __device__ inline unsigned pack_axis(const AxCells& r, int a) {
     return (unsigned)r.c[a][0] | ((unsigned)r.c[a][1] << 16);
@@ -842,11 +812,6 @@ __device__ inline unsigned pack_axis(const AxCells& r, int a) {
 __device__ inline bool axis_meet(unsigned p, unsigned q) {
     const unsigned p0 = p & 0xffffu, p1 = p >> 16, q0 = q & 0xffffu, q1 = q >> 16;
     return p0 == q0 || p0 == q1 || p1 == q0 || p1 == q1;
-}
-
-__device__ inline bool meet(const unsigned* cs, int i, int j) {
-    return axis_meet(cs[3 * i], cs[3 * j]) && axis_meet(cs[3 * i + 1], cs[3 * j + 1]) &&
-           axis_meet(cs[3 * i + 2], cs[3 * j + 2]);
 }
 
 __device__ inline long long find_key(const unsigned long long* keys, unsigned long long key, long long n) {
@@ -859,19 +824,81 @@ __device__ inline long long find_key(const unsigned long long* keys, unsigned lo
     return (lo < n && keys[lo] == key) ? lo : -1;
 }
 
+// registration cell q (x bit 0, y bit 1, z bit 2) of a particle with packed
+// per-axis cells; -1 when that axis has one cell only.  Ascending q is
+// ascending cell id.
+__device__ inline int reg_cell(const DemArgs& A, unsigned px, unsigned py, unsigned pz, int q) {
+    const unsigned x0 = px & 0xffffu, x1 = px >> 16, y0 = py & 0xffffu, y1 = py >> 16, z0 = pz & 0xffffu,
+                   z1 = pz >> 16;
+    if (((q & 1) && x1 == x0) || ((q & 2) && y1 == y0) || ((q & 4) && z1 == z0)) return -1;
+    const int x = (int)((q & 1) ? x1 : x0), y = (int)((q & 2) ? y1 : y0), z = (int)((q & 4) ? z1 : z0);
+    return x + A.nc[0] * (y + A.nc[1] * z);
+}
+
+// Row of particle i from the LDS cell lists: the partners j > i registered in
+// any of i's cells, merged from the (ascending) per-cell lists in ascending j,
+// each once.  After the scatter, cst[c] holds the end of cell c's list and
+// cst[c - 1] its start.
+template <bool EMIT>
+__device__ int merged_row(const DemArgs& A, int i, const unsigned* cells_s, const int* cst,
+                          const unsigned short* cpid, unsigned long long* out, long long room) {
+    const unsigned px = cells_s[3 * i], py = cells_s[3 * i + 1], pz = cells_s[3 * i + 2];
+    int cur[8], end[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int c = reg_cell(A, px, py, pz, q);
+        int s0 = 0, s1 = 0;
+        if (c >= 0) {
+            s0 = c > 0 ? cst[c - 1] : 0;
+            s1 = cst[c];
+            while (s0 < s1 && (int)cpid[s0] <= i) ++s0;
+        }
+        cur[q] = s0;
+        end[q] = s1;
+    }
+    int n = 0;
+    for (;;) {
+        int best = 0x7fffffff;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (cur[q] < end[q]) {
+                const int j = cpid[cur[q]];
+                best = j < best ? j : best;
+            }
+        if (best == 0x7fffffff) break;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (cur[q] < end[q] && (int)cpid[cur[q]] == best) ++cur[q];
+        if (EMIT && n < room) out[n] = ((unsigned long long)i << 32) | (unsigned)best;
+        ++n;
+    }
+    return n;
+}
+
 // All substeps of a coupled step for up to DEM_FUSED_MAX particles in one
-// workgroup.  Per-axis cells of every particle sit in LDS; a row of candidate
-// pairs is built by one wave testing 64 partners per ballot, its emission order
-// (ascending j) given by the lanes' prefix counts.  The previous list's keys are
-// staged in LDS for the history search when they fit.
-__global__ __launch_bounds__(FUSED_T) void k_dem_fused(DemArgs A, PairSet P, int cur, int nsub, double dt,
-                                                       int stop_before_correct) {
+// workgroup, every list in LDS:
+//   cells    per-axis cells of each particle, a counting-sorted cell list
+//            (ids ascending per cell) when the grid has at most FUSED_CELLS cells;
+//   rows     partners j > i merged from i's cell lists (ascending, unique), then
+//            wall candidates; offsets by a workgroup scan;
+//   contacts the previous list's keys in LDS for the history search;
+//   sums     column lists (pairs by second member, ascending pair index) built in
+//            LDS, then each particle sums its column and its own row.
+// Larger grids test every i < j for a shared cell (64 partners per ballot);
+// longer pair lists search each (k, i) pair in row k.
+__device__ void dem_fused_body(const DemArgs& A, const PairSet& P, int cur, const int nsub, const double dt,
+                               const int stop_before_correct) {
     __shared__ unsigned cells_s[3 * DEM_FUSED_MAX];
-    __shared__ int cnt_s[DEM_FUSED_MAX];
+    __shared__ int cnt_s[DEM_FUSED_MAX + 1];
+    __shared__ int cst_s[FUSED_CELLS + 1];
+    __shared__ unsigned short cpid_s[8 * DEM_FUSED_MAX];
     __shared__ unsigned long long prev_s[FUSED_PREV_LDS];
+    __shared__ unsigned short col_s[FUSED_COLS];
     const int np = A.p.np, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int nw = FUSED_T / 64;
     const unsigned long long lanes_below = (1ull << lane) - 1ull;
+    const bool lds_cells = A.ncell <= FUSED_CELLS;
+    const int ncell = (int)A.ncell;
     for (int sub = 0; sub < nsub; ++sub) {
         const bool last = sub == nsub - 1;
         const int c = cur ^ 1;
@@ -882,6 +909,8 @@ __global__ __launch_bounds__(FUSED_T) void k_dem_fused(DemArgs A, PairSet P, int
         B.prev_pairs = P.pairs[cur];
         B.prev_hist = P.hist[cur];
         B.prev_n = P.prow[cur] + np;
+        if (lds_cells)
+            for (int u = tid; u <= ncell; u += FUSED_T) cst_s[u] = 0;
         for (int k = tid; k < np; k += FUSED_T) {
             ph_predict(A, k, dt, last ? 1 : 0);
             AxCells r;
@@ -891,39 +920,90 @@ __global__ __launch_bounds__(FUSED_T) void k_dem_fused(DemArgs A, PairSet P, int
             for (int a = 0; a < 3; ++a) cells_s[3 * k + a] = pack_axis(r, a);
         }
         __syncthreads();
-        // row sizes: partners j > i sharing a cell, plus wall candidates
-        for (int i = wid; i < np; i += nw) {
-            int cnt = 0;
-            for (int j0 = i + 1; j0 < np; j0 += 64) {
-                const int j = j0 + lane;
-                cnt += __popcll(__ballot(j < np && meet(cells_s, i, j)));
+        if (lds_cells) {
+            // counting sort of the registrations by cell
+            for (int k = tid; k < np; k += FUSED_T) {
+                const unsigned px = cells_s[3 * k], py = cells_s[3 * k + 1], pz = cells_s[3 * k + 2];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int cc = reg_cell(A, px, py, pz, q);
+                    if (cc >= 0) atomicAdd(&cst_s[cc], 1);
+                }
             }
-            if (lane == 0) {
-                cnt += wall_count(A, i);
-                cnt_s[i] = cnt;
-                A.pcount[i] = cnt;
+            __syncthreads();
+            psm_block_scan<FUSED_T>(cst_s, cst_s, ncell);
+            for (int k = tid; k < np; k += FUSED_T) {
+                const unsigned px = cells_s[3 * k], py = cells_s[3 * k + 1], pz = cells_s[3 * k + 2];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int cc = reg_cell(A, px, py, pz, q);
+                    if (cc >= 0) cpid_s[atomicAdd(&cst_s[cc], 1)] = (unsigned short)k;
+                }
+            }
+            __syncthreads();
+            for (int cc = tid; cc < ncell; cc += FUSED_T) {
+                const int s0 = cc > 0 ? cst_s[cc - 1] : 0, s1 = cst_s[cc];
+                for (int u = s0 + 1; u < s1; ++u)
+                    for (int v = u; v > s0 && cpid_s[v] < cpid_s[v - 1]; --v) {
+                        const unsigned short t = cpid_s[v];
+                        cpid_s[v] = cpid_s[v - 1];
+                        cpid_s[v - 1] = t;
+                    }
+            }
+            __syncthreads();
+            for (int i = tid; i < np; i += FUSED_T)
+                cnt_s[i] = merged_row<false>(A, i, cells_s, cst_s, cpid_s, nullptr, 0) + wall_count(A, i);
+        } else {
+            // row sizes: partners j > i sharing a cell (64 per ballot), plus walls
+            for (int i = wid; i < np; i += nw) {
+                const unsigned pi0 = cells_s[3 * i], pi1 = cells_s[3 * i + 1], pi2 = cells_s[3 * i + 2];
+                int cnt = 0;
+                for (int j0 = i + 1; j0 < np; j0 += 64) {
+                    const int j = j0 + lane;
+                    const bool ok = j < np && axis_meet(pi0, cells_s[3 * j]) && axis_meet(pi1, cells_s[3 * j + 1]) &&
+                                    axis_meet(pi2, cells_s[3 * j + 2]);
+                    cnt += __popcll(__ballot(ok));
+                }
+                if (lane == 0) cnt_s[i] = cnt + wall_count(A, i);
             }
         }
         __syncthreads();
-        block_scan(A.pcount, B.prow, np);
-        // rows, ascending j, then walls
-        for (int i = wid; i < np; i += nw) {
-            long long at = B.prow[i];
-            for (int j0 = i + 1; j0 < np; j0 += 64) {
-                const int j = j0 + lane;
-                const bool ok = j < np && meet(cells_s, i, j);
-                const unsigned long long m = __ballot(ok);
-                const long long pos = at + __popcll(m & lanes_below);
-                if (ok && pos < A.pair_cap) B.pairs[pos] = ((unsigned long long)i << 32) | (unsigned)j;
-                at += __popcll(m);
-            }
-            if (lane == 0) {
+        psm_block_scan<FUSED_T>(cnt_s, B.prow, np);
+        // rows: ascending j, then walls
+        if (lds_cells) {
+            for (int i = tid; i < np; i += FUSED_T) {
+                const long long at = B.prow[i];
+                const long long room = A.pair_cap - at;
+                long long e = at;
+                if (room > 0) e += merged_row<true>(A, i, cells_s, cst_s, cpid_s, B.pairs + at, room);
                 for (int f = 0; f < 6; ++f)
                     if (A.g.bc[f] != 0 && wall_dist(A, i, f) < A.p.rb[i]) {
-                        if (at < A.pair_cap) B.pairs[at] = ((unsigned long long)i << 32) | (unsigned)(np + f);
-                        ++at;
+                        if (e < A.pair_cap) B.pairs[e] = ((unsigned long long)i << 32) | (unsigned)(np + f);
+                        ++e;
                     }
-                if (at > A.pair_cap) atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_PAIRS);
+                if (e > A.pair_cap) atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_PAIRS);
+            }
+        } else {
+            for (int i = wid; i < np; i += nw) {
+                const unsigned pi0 = cells_s[3 * i], pi1 = cells_s[3 * i + 1], pi2 = cells_s[3 * i + 2];
+                long long at = B.prow[i];
+                for (int j0 = i + 1; j0 < np; j0 += 64) {
+                    const int j = j0 + lane;
+                    const bool ok = j < np && axis_meet(pi0, cells_s[3 * j]) && axis_meet(pi1, cells_s[3 * j + 1]) &&
+                                    axis_meet(pi2, cells_s[3 * j + 2]);
+                    const unsigned long long m = __ballot(ok);
+                    const long long pos = at + __popcll(m & lanes_below);
+                    if (ok && pos < A.pair_cap) B.pairs[pos] = ((unsigned long long)i << 32) | (unsigned)j;
+                    at += __popcll(m);
+                }
+                if (lane == 0) {
+                    for (int f = 0; f < 6; ++f)
+                        if (A.g.bc[f] != 0 && wall_dist(A, i, f) < A.p.rb[i]) {
+                            if (at < A.pair_cap) B.pairs[at] = ((unsigned long long)i << 32) | (unsigned)(np + f);
+                            ++at;
+                        }
+                    if (at > A.pair_cap) atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_PAIRS);
+                }
             }
         }
         long long nprev = P.prow[cur][np];
@@ -932,28 +1012,70 @@ __global__ __launch_bounds__(FUSED_T) void k_dem_fused(DemArgs A, PairSet P, int
         if (prev_in_lds)
             for (long long u = tid; u < nprev; u += FUSED_T) prev_s[u] = B.prev_pairs[u];
         __syncthreads();
+        const long long npairs = n_pairs(A, B);
         {
-            const long long n = n_pairs(A, B);
             PairBufs BL = B;
             if (prev_in_lds) BL.prev_pairs = prev_s;
-            for (long long s = tid; s < n; s += FUSED_T) ph_contact(A, BL, s, A.p.vp, A.p.wp, dt, nprev);
+            for (long long s = tid; s < npairs; s += FUSED_T) ph_contact(A, BL, s, A.p.vp, A.p.wp, dt, nprev);
+        }
+        const bool lds_cols = npairs <= FUSED_COLS;
+        if (lds_cols) {
+            // column lists: pairs by second member, ascending pair index
+            for (int k = tid; k <= np; k += FUSED_T) cnt_s[k] = 0;
+            __syncthreads();
+            for (int s = tid; s < (int)npairs; s += FUSED_T) {
+                const unsigned j = (unsigned)(B.pairs[s] & 0xffffffffu);
+                if (j < (unsigned)np) atomicAdd(&cnt_s[j], 1);
+            }
+            __syncthreads();
+            psm_block_scan<FUSED_T>(cnt_s, cnt_s, np);
+            for (int s = tid; s < (int)npairs; s += FUSED_T) {
+                const unsigned j = (unsigned)(B.pairs[s] & 0xffffffffu);
+                if (j < (unsigned)np) col_s[atomicAdd(&cnt_s[j], 1)] = (unsigned short)s;
+            }
+            __syncthreads();
+            for (int k = tid; k < np; k += FUSED_T) {
+                const int s0 = k > 0 ? cnt_s[k - 1] : 0, s1 = cnt_s[k];
+                for (int u = s0 + 1; u < s1; ++u)
+                    for (int v = u; v > s0 && col_s[v] < col_s[v - 1]; --v) {
+                        const unsigned short t = col_s[v];
+                        col_s[v] = col_s[v - 1];
+                        col_s[v - 1] = t;
+                    }
+            }
         }
         __syncthreads();
-        // DEM sums: (k, i) for ascending k, then the own row
+        // DEM sums: pairs (k, i) for ascending k, then the own row
         for (int i = tid; i < np; i += FUSED_T) {
             double F[3] = {0.0, 0.0, 0.0}, M[3] = {0.0, 0.0, 0.0};
-            for (int k = 0; k < i; ++k) {
-                if (!meet(cells_s, i, k)) continue;
-                const long long lo = B.prow[k];
-                long long hi = B.prow[k + 1];
-                hi = hi < A.pair_cap ? hi : A.pair_cap;
-                if (hi <= lo) continue;
-                const long long s = lo + find_key(B.pairs + lo, ((unsigned long long)k << 32) | (unsigned)i, hi - lo);
-                if (s < lo) continue;
+            if (lds_cols) {
+                const int s0 = i > 0 ? cnt_s[i - 1] : 0, s1 = cnt_s[i];
+                for (int u = s0; u < s1; ++u) {
+                    const long long s = col_s[u];
 #pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    F[q] -= A.cF[3 * s + q];
-                    M[q] += A.cMj[3 * s + q];
+                    for (int q = 0; q < 3; ++q) {
+                        F[q] -= A.cF[3 * s + q];
+                        M[q] += A.cMj[3 * s + q];
+                    }
+                }
+            } else {
+                const unsigned pi0 = cells_s[3 * i], pi1 = cells_s[3 * i + 1], pi2 = cells_s[3 * i + 2];
+                for (int k = 0; k < i; ++k) {
+                    if (!(axis_meet(pi0, cells_s[3 * k]) && axis_meet(pi1, cells_s[3 * k + 1]) &&
+                          axis_meet(pi2, cells_s[3 * k + 2])))
+                        continue;
+                    const long long lo = B.prow[k];
+                    long long hi = B.prow[k + 1];
+                    hi = hi < A.pair_cap ? hi : A.pair_cap;
+                    if (hi <= lo) continue;
+                    const long long s =
+                        lo + find_key(B.pairs + lo, ((unsigned long long)k << 32) | (unsigned)i, hi - lo);
+                    if (s < lo) continue;
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) {
+                        F[q] -= A.cF[3 * s + q];
+                        M[q] += A.cMj[3 * s + q];
+                    }
                 }
             }
             long long s0 = B.prow[i], s1 = B.prow[i + 1];
@@ -976,6 +1098,41 @@ __global__ __launch_bounds__(FUSED_T) void k_dem_fused(DemArgs A, PairSet P, int
             __syncthreads();
         }
         cur = c;
+    }
+}
+
+__global__ __launch_bounds__(FUSED_T) void k_dem_fused(DemArgs A, PairSet P, int cur, int nsub, double dt,
+                                                       int stop_before_correct) {
+    dem_fused_body(A, P, cur, nsub, dt, stop_before_correct);
+}
+
+// one workgroup per domain of a serving batch: the fused substeps (the last
+// one stops before the corrector when the fluid is coupled), or for a domain
+// without DEM the kinematics the LBM-PSM pass reads
+__global__ __launch_bounds__(FUSED_T) void k_dem_fused_batch(const DemJob* __restrict__ jobs, SrvDyn dyn) {
+    const DemJob& J = jobs[blockIdx.x];
+    if (J.dem) {
+        dem_fused_body(J.A, J.P, dyn.cur[blockIdx.x], J.nsub, J.dt, J.fluid);
+    } else if (J.fluid) {
+        const PartArgs& p = J.A.p;
+        for (int k = threadIdx.x; k < p.np; k += FUSED_T)
+            for (int c = 0; c < 3; ++c) {
+                p.vp[3 * k + c] = p.v[3 * k + c];
+                p.wp[3 * k + c] = p.w[3 * k + c];
+                p.kin[9 * k + c] = p.pos[3 * k + c];
+                p.kin[9 * k + 3 + c] = p.vp[3 * k + c];
+                p.kin[9 * k + 6 + c] = p.wp[3 * k + c];
+            }
+    }
+}
+
+// hydrodynamic sums, then the corrector, per particle of each domain
+__global__ __launch_bounds__(256) void k_dem_finish_batch(const DemJob* __restrict__ jobs) {
+    const DemJob& J = jobs[blockIdx.x];
+    if (!J.fluid) return;
+    for (int k = threadIdx.x; k < J.A.p.np; k += 256) {
+        psm_reduce_hydro(J.t, J.A.p, k);
+        if (J.dem) ph_correct(J.A, k, J.dt);
     }
 }
 
@@ -1042,6 +1199,18 @@ hipError_t dem_initial_accel(const DemArgs& A, hipStream_t s) {
 hipError_t dem_zero(double* p, long long n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     k_zero_d<<<nblk(n), 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+hipError_t dem_fused_batch(const DemJob* jobs, int njobs, const SrvDyn& dyn, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    k_dem_fused_batch<<<(unsigned)njobs, FUSED_T, 0, s>>>(jobs, dyn);
+    return hipGetLastError();
+}
+
+hipError_t dem_finish_batch(const DemJob* jobs, int njobs, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    k_dem_finish_batch<<<(unsigned)njobs, 256, 0, s>>>(jobs);
     return hipGetLastError();
 }
 

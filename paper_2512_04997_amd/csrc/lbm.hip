@@ -23,6 +23,7 @@
 
 #include "common.h"
 #include "lbm.h"
+#include "serve.h"
 
 namespace {
 
@@ -279,12 +280,10 @@ __device__ inline double wave_sum(double v) {
 }
 
 // MS = 0: tiles without registered particles; MS > 0: tiles with particles
+// one tile of one domain (the body shared by the single-domain and the batched kernels)
 template <typename S, typename C, bool ODD, int MS>
-__global__ __launch_bounds__(256) void k_lbm(LbmArgs A) {
+__device__ void lbm_tile(const LbmArgs& A, const long long t, double* kin_s, double* acc) {
     const long long ntiles = A.g.ntiles;
-    const long long per = (ntiles + 7) / 8;
-    const long long t = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
-    if (t >= ntiles) return;
     long long s0 = A.t.tile_start[t], s1 = A.t.tile_start[t + 1];
     if (s1 > A.t.cap) s1 = A.t.cap;
     int count = (int)(s1 - s0);
@@ -294,8 +293,6 @@ __global__ __launch_bounds__(256) void k_lbm(LbmArgs A) {
     } else {
         if (count > 0) return;
     }
-    __shared__ double kin_s[MS > 0 ? PSM_PMAX * 9 : 1];
-    __shared__ double acc[MS > 0 ? 4 * PSM_PMAX * 6 : 1];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
     if (MS > 0) {
@@ -441,6 +438,44 @@ __global__ __launch_bounds__(256) void k_lbm(LbmArgs A) {
     }
 }
 
+// the block -> tile mapping keeps consecutive tiles on one XCD
+__device__ inline long long xcd_block(long long nblocks) {
+    const long long per = (nblocks + 7) / 8;
+    return (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+
+template <typename S, typename C, bool ODD, int MS>
+__global__ __launch_bounds__(256) void k_lbm(LbmArgs A) {
+    __shared__ double kin_s[MS > 0 ? PSM_PMAX * 9 : 1];
+    __shared__ double acc[MS > 0 ? 4 * PSM_PMAX * 6 : 1];
+    const long long t = xcd_block(A.g.ntiles);
+    if (t >= A.g.ntiles) return;
+    lbm_tile<S, C, ODD, MS>(A, t, kin_s, acc);
+}
+
+// many domains in one launch: map[b] = (job, tile), the job's parity in dyn.odd
+template <typename S, typename C, int MS>
+__global__ __launch_bounds__(256) void k_lbm_batch(const LbmArgs* __restrict__ jobs, SrvDyn dyn,
+                                                   const int2* __restrict__ map, long long nmap) {
+    __shared__ double kin_s[MS > 0 ? PSM_PMAX * 9 : 1];
+    __shared__ double acc[MS > 0 ? 4 * PSM_PMAX * 6 : 1];
+    const long long b = xcd_block(nmap);
+    if (b >= nmap) return;
+    const int2 m = map[b];
+    if (dyn.odd[m.x]) lbm_tile<S, C, true, MS>(jobs[m.x], m.y, kin_s, acc);
+    else lbm_tile<S, C, false, MS>(jobs[m.x], m.y, kin_s, acc);
+}
+
+template <typename S, typename C>
+hipError_t launch_batch(const LbmArgs* jobs, const SrvDyn& dyn, const int2* map, long long nmap, int ms,
+                        hipStream_t s) {
+    const unsigned nb = (unsigned)(8 * ((nmap + 7) / 8));
+    if (ms == 0) k_lbm_batch<S, C, 0><<<nb, 256, 0, s>>>(jobs, dyn, map, nmap);
+    else if (ms <= 2) k_lbm_batch<S, C, 2><<<nb, 256, 0, s>>>(jobs, dyn, map, nmap);
+    else k_lbm_batch<S, C, 4><<<nb, 256, 0, s>>>(jobs, dyn, map, nmap);
+    return hipGetLastError();
+}
+
 template <typename S, typename C>
 hipError_t launch_step(const LbmArgs& A, int odd, hipStream_t s) {
     const unsigned nblk = (unsigned)(8 * ((A.g.ntiles + 7) / 8));
@@ -486,6 +521,18 @@ hipError_t lbm_step(const LbmArgs& A, int precision, int odd, hipStream_t s) {
         case 1: return launch_step<float, float>(A, odd, s);
         case 2: return launch_step<bf16_t, float>(A, odd, s);
         case 3: return launch_step<_Float16, float>(A, odd, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t lbm_step_batch(const LbmArgs* jobs, const SrvDyn& dyn, const int2* map, long long nmap, int ms,
+                          int precision, hipStream_t s) {
+    if (nmap <= 0) return hipSuccess;
+    switch (precision) {
+        case 0: return launch_batch<double, double>(jobs, dyn, map, nmap, ms, s);
+        case 1: return launch_batch<float, float>(jobs, dyn, map, nmap, ms, s);
+        case 2: return launch_batch<bf16_t, float>(jobs, dyn, map, nmap, ms, s);
+        case 3: return launch_batch<_Float16, float>(jobs, dyn, map, nmap, ms, s);
     }
     return hipErrorInvalidValue;
 }

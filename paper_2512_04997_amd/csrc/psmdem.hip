@@ -17,6 +17,7 @@
 
 #include "common.h"
 #include "dem.h"
+#include "domain.h"
 #include "lbm.h"
 #include "voxel.h"
 
@@ -97,214 +98,6 @@ void encode(unsigned char* raw, int prec, long long idx, double v) {
 }
 
 }  // namespace
-
-struct psmdem_domain {
-    psmdem_desc d;
-    hipStream_t s = nullptr;
-    psmdem_alloc_fn alloc = nullptr;
-    psmdem_free_fn freef = nullptr;
-    void* actx = nullptr;
-    std::vector<std::pair<void*, size_t>> blocks;
-    size_t bytes = 0;
-
-    int np = 0;
-    long long N = 0;
-    GeoArgs geo{};
-    double L[3];
-    int prec = 0;
-    void* f = nullptr;
-    double wall_corr[6][19];
-    double* kolm_prof = nullptr;
-    double* wall_corr_d = nullptr;
-
-    // particles
-    PartArgs p{};
-    std::vector<int> h_shape;
-    // DEM
-    int nsub = 1;
-    double dt = 1.0, beta_e = 0.0, Rc = 0.0;
-    int nc[3];
-    double h[3];
-    long long ncell = 1;
-    int *cell_count = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *cell_pid = nullptr;
-    int* pc = nullptr;
-    int *col_count = nullptr, *col_fill = nullptr, *col_start = nullptr, *col_list = nullptr;
-    long long reg_cap = 0;
-    int* pcount = nullptr;
-    int* prow[2] = {nullptr, nullptr};
-    unsigned long long* pairs[2] = {nullptr, nullptr};
-    double* hist[2] = {nullptr, nullptr};
-    double *cF = nullptr, *cMi = nullptr, *cMj = nullptr;
-    unsigned char* incontact = nullptr;
-    long long pair_cap = 0;
-    int cur = 0;
-    // voxel / tiles
-    TileArgs t{};
-    int* tile_count = nullptr;
-    int* tile_fill = nullptr;
-    int* scan_tmp = nullptr;
-    DevCounters* ctr = nullptr;
-
-    int64_t step = 0;
-    bool voxelized = false;
-
-    // timing
-    bool timing = false;
-    std::vector<hipEvent_t> ev;
-    double t_ms[4] = {0, 0, 0, 0};
-    long long t_n[4] = {0, 0, 0, 0};
-
-    void* dalloc(size_t n) {
-        if (n == 0) n = 16;
-        n = (n + 255) & ~(size_t)255;
-        void* ptr = nullptr;
-        if (alloc) {
-            ptr = alloc(n, actx);
-        } else if (hipMalloc(&ptr, n) != hipSuccess) {
-            ptr = nullptr;
-        }
-        if (ptr) {
-            blocks.push_back({ptr, n});
-            bytes += n;
-        }
-        return ptr;
-    }
-    ~psmdem_domain() {
-        if (s) (void)hipStreamSynchronize(s);
-        else (void)hipDeviceSynchronize();
-        for (auto& b : blocks) {
-            if (freef) freef(b.first, b.second, actx);
-            else if (!alloc) (void)hipFree(b.first);
-        }
-        for (auto e : ev) (void)hipEventDestroy(e);
-    }
-
-    DemArgs dem_args() {
-        DemArgs A{};
-        A.g = geo;
-        A.p = p;
-        for (int a = 0; a < 3; ++a) {
-            A.L[a] = L[a];
-            A.nc[a] = nc[a];
-            A.h[a] = h[a];
-            A.gravity[a] = d.gravity[a];
-        }
-        A.ncell = ncell;
-        A.pc = pc;
-        A.cell_count = cell_count;
-        A.cell_start = cell_start;
-        A.cell_fill = cell_fill;
-        A.cell_pid = cell_pid;
-        A.reg_cap = reg_cap;
-        A.pcount = pcount;
-        A.cF = cF;
-        A.cMi = cMi;
-        A.cMj = cMj;
-        A.incontact = incontact;
-        A.col_count = col_count;
-        A.col_fill = col_fill;
-        A.col_start = col_start;
-        A.col_list = col_list;
-        A.pair_cap = pair_cap;
-        A.kn = d.kn;
-        A.beta_e = beta_e;
-        A.mu = d.mu;
-        A.kt_ratio = d.kt_ratio;
-        A.gt_ratio = d.gt_ratio;
-        for (int f_ = 0; f_ < 6; ++f_)
-            for (int c = 0; c < 3; ++c) A.wall_u[f_][c] = d.wall_u[f_][c];
-        A.ctr = ctr;
-        return A;
-    }
-
-    // current list = buffer cur, previous = the other one (or none)
-    PairBufs pair_bufs(int use_prev) {
-        PairBufs B{};
-        B.pairs = pairs[cur];
-        B.prow = prow[cur];
-        B.hist = hist[cur];
-        B.prev_pairs = pairs[cur ^ 1];
-        B.prev_hist = hist[cur ^ 1];
-        B.prev_n = use_prev ? prow[cur ^ 1] + np : nullptr;
-        return B;
-    }
-
-    PairSet pair_set() {
-        PairSet P{};
-        for (int b = 0; b < 2; ++b) {
-            P.pairs[b] = pairs[b];
-            P.prow[b] = prow[b];
-            P.hist[b] = hist[b];
-        }
-        return P;
-    }
-
-    VoxArgs vox_args() {
-        VoxArgs A{};
-        A.g = geo;
-        A.p = p;
-        A.t = t;
-        A.tile_count = tile_count;
-        A.tile_fill = tile_fill;
-        A.sf_method = d.sf_method;
-        A.ns = d.sf_subdiv;
-        A.Rc = Rc;
-        A.tau = d.tau;
-        A.ms = d.max_solids;
-        A.ctr = ctr;
-        return A;
-    }
-
-    LbmArgs lbm_args() {
-        LbmArgs A{};
-        A.g = geo;
-        A.f = f;
-        A.omega = 1.0 / d.tau;
-        A.forcing = (d.body_force[0] != 0.0 || d.body_force[1] != 0.0 || d.body_force[2] != 0.0 ||
-                     d.kolm_amp != 0.0);
-        for (int a = 0; a < 3; ++a) {
-            A.F[a] = d.body_force[a];
-            A.L[a] = L[a];
-        }
-        A.kolm_axis = d.kolm_axis;
-        A.kolm_dir = d.kolm_dir;
-        A.kolm_prof = kolm_prof;
-        A.wall_corr = wall_corr_d;
-        A.t = t;
-        A.kin = p.kin;
-        A.np = np;
-        A.ms = d.max_solids;
-        return A;
-    }
-
-    int timed_begin(int which) {
-        if (!timing) return -1;
-        hipEvent_t a, b;
-        (void)hipEventCreate(&a);
-        (void)hipEventCreate(&b);
-        ev.push_back(a);
-        ev.push_back(b);
-        (void)hipEventRecord(a, s);
-        pending.push_back({which, (int)ev.size() - 2});
-        return (int)ev.size() - 1;
-    }
-    void timed_end(int idx) {
-        if (idx >= 0) (void)hipEventRecord(ev[idx], s);
-    }
-    std::vector<std::pair<int, int>> pending;
-    void collect_timing() {
-        for (auto& pr : pending) {
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, ev[pr.second], ev[pr.second + 1]) == hipSuccess) {
-                t_ms[pr.first] += ms;
-                t_n[pr.first] += 1;
-            }
-        }
-        pending.clear();
-        for (auto e : ev) (void)hipEventDestroy(e);
-        ev.clear();
-    }
-};
 
 // ---------------------------------------------------------------------------
 // stages
@@ -427,18 +220,19 @@ static int validate(const psmdem_desc* d, const psmdem_particles* P) {
     return 1;
 }
 
-extern "C" psmdem_status psmdem_create(const psmdem_desc* desc, const psmdem_particles* parts, void* stream,
-                                       psmdem_alloc_fn alloc, psmdem_free_fn free_fn, void* alloc_ctx,
-                                       psmdem_domain** out) {
-    if (!out) { psm_set_error("out is NULL"); return PSMDEM_E_INVALID; }
-    *out = nullptr;
+psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles* parts, void* stream,
+                                psmdem_alloc_fn alloc, psmdem_free_fn free_fn, void* alloc_ctx, bool dry,
+                                psmdem_domain** out, size_t* bytes) {
+    if (!out && !dry) { psm_set_error("out is NULL"); return PSMDEM_E_INVALID; }
+    if (out) *out = nullptr;
     if (!validate(desc, parts)) return PSMDEM_E_INVALID;
     int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    if (!dry && (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)) {
         psm_set_error("no HIP device");
         return PSMDEM_E_NODEVICE;
     }
     psmdem_domain* D = new psmdem_domain();
+    D->dry = dry;
     D->d = *desc;
     D->s = (hipStream_t)stream;
     D->alloc = alloc;
@@ -630,13 +424,19 @@ extern "C" psmdem_status psmdem_create(const psmdem_desc* desc, const psmdem_par
         std::vector<double> prof(n_ax);
         for (int c = 0; c < n_ax; ++c) prof[c] = d.kolm_amp * sin(2.0 * M_PI * ((double)c + 0.5) / (double)n_ax);
         D->kolm_prof = (double*)A(sizeof(double) * n_ax);
-        if (ok && hipMemcpy(D->kolm_prof, prof.data(), sizeof(double) * n_ax, hipMemcpyHostToDevice) != hipSuccess)
+        if (ok && !dry &&
+            hipMemcpy(D->kolm_prof, prof.data(), sizeof(double) * n_ax, hipMemcpyHostToDevice) != hipSuccess)
             ok = false;
     }
     if (!ok) {
         delete D;
         psm_set_error("device allocation failed");
         return PSMDEM_E_NOMEM;
+    }
+    if (dry) {
+        if (bytes) *bytes = D->bytes;
+        delete D;
+        return PSMDEM_OK;
     }
     int rc = 0;
     auto H2D = [&](void* dst, const void* src, size_t n) {
@@ -705,8 +505,23 @@ extern "C" psmdem_status psmdem_create(const psmdem_desc* desc, const psmdem_par
         psm_set_error("device error during creation: %s", hipGetErrorString(hipGetLastError()));
         return PSMDEM_E_HIP;
     }
+    if (bytes) *bytes = D->bytes;
     *out = D;
     return PSMDEM_OK;
+}
+
+extern "C" psmdem_status psmdem_create(const psmdem_desc* desc, const psmdem_particles* parts, void* stream,
+                                       psmdem_alloc_fn alloc, psmdem_free_fn free_fn, void* alloc_ctx,
+                                       psmdem_domain** out) {
+    return psm_domain_create(desc, parts, stream, alloc, free_fn, alloc_ctx, false, out, nullptr);
+}
+
+extern "C" psmdem_status psmdem_footprint(const psmdem_desc* desc, const psmdem_particles* parts, int64_t* bytes) {
+    if (!bytes) { psm_set_error("bytes is NULL"); return PSMDEM_E_INVALID; }
+    size_t b = 0;
+    psmdem_status rc = psm_domain_create(desc, parts, nullptr, nullptr, nullptr, nullptr, true, nullptr, &b);
+    *bytes = rc == PSMDEM_OK ? (int64_t)b : 0;
+    return rc;
 }
 
 extern "C" void psmdem_destroy(psmdem_domain* d) { delete d; }

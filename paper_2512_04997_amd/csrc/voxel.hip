@@ -15,6 +15,7 @@
 #include <math.h>
 
 #include "common.h"
+#include "serve.h"
 #include "voxel.h"
 
 namespace {
@@ -107,9 +108,8 @@ __device__ inline void particle_tiles(const VoxArgs& A, int k, TileSet& S) {
     S.nz = axis_tiles(lo[2], hi[2], A.g.nz, PSM_TZ, A.g.periodic[2], S.tz);
 }
 
-__global__ void k_vox_count(VoxArgs A) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= A.p.np) return;
+// tiles of particle k: count, and one tile-histogram increment each (through `hist`)
+__device__ inline void reg_count(const VoxArgs& A, int k, int* hist) {
     TileSet S;
     particle_tiles(A, k, S);
     A.t.vcount[k] = S.nx * S.ny * S.nz;
@@ -117,13 +117,12 @@ __global__ void k_vox_count(VoxArgs A) {
         for (int b = 0; b < S.ny; ++b)
             for (int a = 0; a < S.nx; ++a) {
                 long long t = S.tx[a] + (long long)A.g.ntx * (S.ty[b] + (long long)A.g.nty * S.tz[c]);
-                atomicAdd(&A.tile_count[t], 1);
+                atomicAdd(&hist[t], 1);
             }
 }
 
-__global__ void k_vox_scatter(VoxArgs A) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= A.p.np) return;
+// counting-sort scatter of particle k's (pid, emission) entries; `fill` counts per tile
+__device__ inline void reg_scatter(const VoxArgs& A, int k, int* fill) {
     TileSet S;
     particle_tiles(A, k, S);
     int e = A.t.voff[k];
@@ -132,7 +131,7 @@ __global__ void k_vox_scatter(VoxArgs A) {
         for (int b = 0; b < S.ny; ++b)
             for (int a = 0; a < S.nx; ++a) {
                 long long t = S.tx[a] + (long long)A.g.ntx * (S.ty[b] + (long long)A.g.nty * S.tz[c]);
-                int slot = atomicAdd(&A.tile_fill[t], 1);
+                int slot = atomicAdd(&fill[t], 1);
                 long long at = (long long)A.t.tile_start[t] + slot;
                 if (at < A.t.cap && e < A.t.cap)
                     A.t.tile_list[at] = ((unsigned long long)k << 32) | (unsigned)e;
@@ -143,9 +142,8 @@ __global__ void k_vox_scatter(VoxArgs A) {
     if (full) atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_VREG);
 }
 
-__global__ void k_tile_sort(VoxArgs A) {
-    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= A.g.ntiles) return;
+// order tile t's list by (pid, emission) and record where each emission landed
+__device__ inline void reg_sort(const VoxArgs& A, long long t) {
     long long s0 = A.t.tile_start[t], s1 = A.t.tile_start[t + 1];
     if (s1 > A.t.cap) s1 = A.t.cap;
     if (s0 >= s1) return;
@@ -159,6 +157,55 @@ __global__ void k_tile_sort(VoxArgs A) {
         unsigned e = (unsigned)(L[u] & 0xffffffffu);
         if (e < A.t.cap) A.t.vinv[e] = (int)u;
     }
+}
+
+__global__ void k_vox_count(VoxArgs A) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= A.p.np) return;
+    reg_count(A, k, A.tile_count);
+}
+
+__global__ void k_vox_scatter(VoxArgs A) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= A.p.np) return;
+    reg_scatter(A, k, A.tile_fill);
+}
+
+__global__ void k_tile_sort(VoxArgs A) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= A.g.ntiles) return;
+    reg_sort(A, t);
+}
+
+// Registration of one domain by one workgroup (serving batches): the tile
+// histogram and fill counters live in LDS, the lists and offsets are the ones
+// of the multi-launch path above.
+#define VOX_RT 1024
+#define VOX_REG_LDS_TILES 8192
+
+__global__ __launch_bounds__(VOX_RT) void k_vox_register_batch(const VoxArgs* __restrict__ jobs) {
+    __shared__ int hist_s[VOX_REG_LDS_TILES];
+    const VoxArgs& A = jobs[blockIdx.x];
+    const int tid = threadIdx.x;
+    if (A.g.ntiles > VOX_REG_LDS_TILES) return;  // refused on the host
+    const int nt = (int)A.g.ntiles, np = A.p.np;
+    if (tid == 0) {
+        A.ctr->entries = 0;
+        A.ctr->dropped = 0;
+    }
+    for (int t = tid; t < nt; t += VOX_RT) hist_s[t] = 0;
+    __syncthreads();
+    for (int k = tid; k < np; k += VOX_RT) reg_count(A, k, hist_s);
+    __syncthreads();
+    for (int t = tid; t < nt; t += VOX_RT) A.tile_count[t] = hist_s[t];
+    __syncthreads();
+    psm_block_scan<VOX_RT>(A.t.vcount, A.t.voff, np);
+    psm_block_scan<VOX_RT>(A.tile_count, A.t.tile_start, nt);
+    for (int t = tid; t < nt; t += VOX_RT) hist_s[t] = 0;
+    __syncthreads();
+    for (int k = tid; k < np; k += VOX_RT) reg_scatter(A, k, hist_s);
+    __syncthreads();
+    for (int t = tid; t < nt; t += VOX_RT) reg_sort(A, t);
 }
 
 // per-particle data staged in LDS for a tile
@@ -240,7 +287,7 @@ __device__ int classify(const VoxPart& P, int X, int Y, int Z) {
     return all_in ? 1 : 2;
 }
 
-#define VOX_MTAB 4096   // samples whose (a, b, c) indices are tabulated in LDS (ns <= 16)
+#define VOX_MTAB 1024   // samples whose (a, b, c) indices are tabulated in LDS (ns <= 10)
 
 // one sample m (a fastest): inside test in the evaluation order of the definition
 __device__ inline bool sample_in(const VoxPart& P, int X, int Y, int Z, const double* off, int ns, int m,
@@ -309,16 +356,15 @@ __device__ inline void keep_top(double (&bb)[PSM_SLOTS_MAX], int (&bl)[PSM_SLOTS
 }
 
 template <typename C>
-__global__ __launch_bounds__(VOX_T) void k_voxelize(VoxArgs A) {
+__device__ void voxelize_tile(const VoxArgs& A, const long long t) {
     __shared__ VoxPart sp[PSM_PMAX];
     __shared__ double off[32];
     __shared__ unsigned qitem[VOX_QCAP];
     __shared__ int qcnt[VOX_QCAP];
     __shared__ int tcnt[VOX_T];
     __shared__ unsigned short mtab_s[VOX_MTAB];
+    __shared__ double tab_s[(VOX_T / 64) * 9 * 32];
     __shared__ unsigned long long cnt_e, cnt_d;
-    const long long t = blockIdx.x;
-    if (t >= A.g.ntiles) return;
     long long s0 = A.t.tile_start[t], s1 = A.t.tile_start[t + 1];
     if (s1 > A.t.cap) s1 = A.t.cap;
     const int count = (int)(s1 - s0) < PSM_PMAX ? (int)(s1 - s0) : PSM_PMAX;
@@ -397,8 +443,12 @@ __global__ __launch_bounds__(VOX_T) void k_voxelize(VoxArgs A) {
     }
     __syncthreads();
     // phase B: each wave counts the inside samples of one item at a time (64 lanes
-    // per pass, the exact count from ballots)
+    // per pass, the exact count from ballots).  The per-axis terms of the sample
+    // test are formed once per item in wave-private LDS with the same rounding as
+    // the definition: squared offsets for spheres, rotated components for
+    // ellipsoids.
     const int nq = total < VOX_QCAP ? total : VOX_QCAP;
+    double* tab = tab_s + wid * (9 * 32);
     for (int it = wid; it < nq; it += VOX_T / 64) {
         const unsigned item = qitem[it];
         const int u = (int)(item & 0xffu), l = (int)(item >> 8);
@@ -409,13 +459,59 @@ __global__ __launch_bounds__(VOX_T) void k_voxelize(VoxArgs A) {
         in_box(P, cx, A.g.nx, 0, A.g.periodic[0], &X);
         in_box(P, cy, A.g.ny, 1, A.g.periodic[1], &Y);
         in_box(P, cz, A.g.nz, 2, A.g.periodic[2], &Z);
+        const bool sph = P.shape == 0;
+        if (lane < ns) {
+            const double dx = ((double)X + off[lane]) - P.c[0];
+            const double dy = ((double)Y + off[lane]) - P.c[1];
+            const double dz = ((double)Z + off[lane]) - P.c[2];
+            if (sph) {
+                tab[lane] = dx * dx;
+                tab[ns + lane] = dy * dy;
+                tab[2 * ns + lane] = dz * dz;
+            } else {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    tab[(3 * k + 0) * ns + lane] = P.R[0 + k] * dx;
+                    tab[(3 * k + 1) * ns + lane] = P.R[3 + k] * dy;
+                    tab[(3 * k + 2) * ns + lane] = P.R[6 + k] * dz;
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const double R2 = P.ax[0] * P.ax[0];
         int cnt = 0;
         for (int m0 = 0; m0 < n3; m0 += 64) {
             const int m = m0 + lane;
-            const bool in = m < n3 && sample_in(P, X, Y, Z, off, ns, m, mtab);
+            bool in = false;
+            if (m < n3) {
+                int a, b, c;
+                if (mtab) {
+                    const unsigned tw = mtab[m];
+                    a = tw & 31;
+                    b = (tw >> 5) & 31;
+                    c = tw >> 10;
+                } else {
+                    a = m % ns;
+                    b = (m / ns) % ns;
+                    c = m / (ns * ns);
+                }
+                if (sph) {
+                    in = ((tab[a] + tab[ns + b]) + tab[2 * ns + c]) < R2;
+                } else {
+                    const double p0 = (tab[a] + tab[ns + b]) + tab[2 * ns + c];
+                    const double p1 = (tab[3 * ns + a] + tab[4 * ns + b]) + tab[5 * ns + c];
+                    const double p2 = (tab[6 * ns + a] + tab[7 * ns + b]) + tab[8 * ns + c];
+                    in = (((p0 * p0) * P.inv[0] + (p1 * p1) * P.inv[1]) + (p2 * p2) * P.inv[2]) < 1.0;
+                }
+            }
             cnt += __popcll(__ballot(in));
         }
         if (lane == 0) qcnt[it] = cnt;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     __syncthreads();
     // phase C: beta per (cell, particle) in pid order, keep the largest
@@ -493,24 +589,32 @@ __global__ __launch_bounds__(VOX_T) void k_voxelize(VoxArgs A) {
     }
 }
 
+template <typename C>
+__global__ __launch_bounds__(VOX_T) void k_voxelize(VoxArgs A) {
+    if ((long long)blockIdx.x >= A.g.ntiles) return;
+    voxelize_tile<C>(A, blockIdx.x);
+}
+
+// consecutive blocks of the map stay on one XCD
+__device__ inline long long xcd_block(long long nblocks) {
+    const long long per = (nblocks + 7) / 8;
+    return (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
+}
+
+// many domains in one launch: map[b] = (job, tile)
+template <typename C>
+__global__ __launch_bounds__(VOX_T) void k_voxelize_batch(const VoxArgs* __restrict__ jobs,
+                                                          const int2* __restrict__ map, long long nmap) {
+    const long long b = xcd_block(nmap);
+    if (b >= nmap) return;
+    const int2 m = map[b];
+    voxelize_tile<C>(jobs[m.x], m.y);
+}
+
 __global__ void k_reduce_hydro(VoxArgs A) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= A.p.np) return;
-    double F[3] = {0.0, 0.0, 0.0}, M[3] = {0.0, 0.0, 0.0};
-    int e0 = A.t.voff[k], e1 = A.t.voff[k + 1];
-    for (int e = e0; e < e1 && e < A.t.cap; ++e) {
-        long long s = A.t.vinv[e];
-        if (s < 0 || s >= A.t.cap) continue;
-        const double* P = A.t.partial + 6 * s;
-        for (int c = 0; c < 3; ++c) {
-            F[c] -= P[c];
-            M[c] -= P[3 + c];
-        }
-    }
-    for (int c = 0; c < 3; ++c) {
-        A.p.fh[3 * k + c] = F[c];
-        A.p.mh[3 * k + c] = M[c];
-    }
+    psm_reduce_hydro(A.t, A.p, k);
 }
 
 inline unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
@@ -532,6 +636,21 @@ hipError_t vox_register(const VoxArgs& A, int* scan_tmp, hipStream_t s) {
 hipError_t vox_voxelize(const VoxArgs& A, int ctype_double, hipStream_t s) {
     if (ctype_double) k_voxelize<double><<<(unsigned)A.g.ntiles, VOX_T, 0, s>>>(A);
     else k_voxelize<float><<<(unsigned)A.g.ntiles, VOX_T, 0, s>>>(A);
+    return hipGetLastError();
+}
+
+hipError_t vox_register_batch(const VoxArgs* jobs, int njobs, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    k_vox_register_batch<<<(unsigned)njobs, VOX_RT, 0, s>>>(jobs);
+    return hipGetLastError();
+}
+
+hipError_t vox_voxelize_batch(const VoxArgs* jobs, const int2* map, long long nmap, int ctype_double,
+                              hipStream_t s) {
+    if (nmap <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)(8 * ((nmap + 7) / 8));
+    if (ctype_double) k_voxelize_batch<double><<<nb, VOX_T, 0, s>>>(jobs, map, nmap);
+    else k_voxelize_batch<float><<<nb, VOX_T, 0, s>>>(jobs, map, nmap);
     return hipGetLastError();
 }
 

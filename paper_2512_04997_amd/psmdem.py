@@ -64,6 +64,19 @@ class Info(C.Structure):
                 ("device_bytes", C.c_int64), ("tile", C.c_int32 * 3)]
 
 
+class ServerDesc(C.Structure):
+    _fields_ = [("max_jobs", C.c_int32), ("hbm_budget", C.c_int64), ("max_inflight", C.c_int32),
+                ("precision", C.c_int32)]
+
+
+class JobInfo(C.Structure):
+    _fields_ = [("state", C.c_int32), ("slot", C.c_int32), ("steps", C.c_int64), ("steps_done", C.c_int64),
+                ("footprint", C.c_int64), ("status", C.c_int32), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
+JOB_STATE = {0: "queued", 1: "active", 2: "finishing", 3: "done", 4: "failed"}
+
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p)
 
@@ -107,6 +120,19 @@ def lib():
     L.psmdem_info.argtypes = [P, C.POINTER(Info)]
     L.psmdem_set_timing.argtypes = [P, C.c_int32]
     L.psmdem_timing.argtypes = [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.psmdem_footprint.argtypes = [C.POINTER(Desc), C.POINTER(Particles), C.POINTER(C.c_int64)]
+    L.psmdem_clock.argtypes = []
+    L.psmdem_clock.restype = C.c_double
+    L.psmdem_server_create.argtypes = [C.POINTER(ServerDesc), P, P, ALLOC_FN, FREE_FN, P, C.POINTER(P)]
+    L.psmdem_server_destroy.argtypes = [P]
+    L.psmdem_server_destroy.restype = None
+    L.psmdem_server_submit.argtypes = [P, C.POINTER(Desc), C.POINTER(Particles), C.c_int64,
+                                       C.POINTER(C.c_int64)]
+    L.psmdem_server_iterate.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.psmdem_server_drain.argtypes = [P]
+    L.psmdem_server_job.argtypes = [P, C.c_int64, C.POINTER(JobInfo)]
+    L.psmdem_server_domain.argtypes = [P, C.c_int64, C.POINTER(P)]
+    L.psmdem_server_release.argtypes = [P, C.c_int64]
     L.psmdem_last_error.restype = C.c_char_p
     L.psmdem_last_error.argtypes = []
     L.psmdem_version.restype = C.c_char_p
@@ -116,7 +142,9 @@ def lib():
                  "psmdem_write_particles", "psmdem_read_predicted", "psmdem_write_predicted",
                  "psmdem_read_pairs", "psmdem_write_pairs", "psmdem_read_contacts",
                  "psmdem_read_cells", "psmdem_read_solid", "psmdem_counters", "psmdem_info",
-                 "psmdem_set_timing", "psmdem_timing"):
+                 "psmdem_set_timing", "psmdem_timing", "psmdem_footprint", "psmdem_server_create",
+                 "psmdem_server_submit", "psmdem_server_iterate", "psmdem_server_drain", "psmdem_server_job",
+                 "psmdem_server_domain", "psmdem_server_release"):
         getattr(L, name).restype = st
     _lib = L
     return L
@@ -241,9 +269,25 @@ class Domain:
         _check(code)
         self.h = h
 
+    @classmethod
+    def _attach(cls, handle, cfg, parts):
+        """A non-owning view of a domain held elsewhere (a served job)."""
+        self = cls.__new__(cls)
+        self.cfg = dict(cfg)
+        self.desc = make_desc(cfg)
+        self.n = tuple(int(v) for v in cfg["n"])
+        self.N = self.n[0] * self.n[1] * self.n[2]
+        _, self._keep, self.np = _particle_struct(parts)
+        self.stream = None
+        self._alloc = None
+        self.h = handle
+        self._owner = False
+        return self
+
     def close(self):
         if getattr(self, "h", None):
-            lib().psmdem_destroy(self.h)
+            if getattr(self, "_owner", True):
+                lib().psmdem_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -370,6 +414,92 @@ class Domain:
         b = np.zeros(m)
         _check(lib().psmdem_read_solid(self.h, m, _ptr(c), _ptr(p), _ptr(b), C.byref(n)))
         return c, p, b
+
+
+def footprint(cfg, parts=None):
+    """Device bytes a domain of this configuration allocates (no device needed)."""
+    d = make_desc(cfg)
+    ps, _keep, _ = _particle_struct(parts)
+    b = C.c_int64()
+    _check(lib().psmdem_footprint(C.byref(d), C.byref(ps), C.byref(b)))
+    return b.value
+
+
+def clock():
+    """The library's monotonic host clock in seconds (the clock of job times)."""
+    return lib().psmdem_clock()
+
+
+class Server:
+    """Continuous batching of many coupled domains (psmdem_server_*).
+
+    Jobs are created on a separate admission stream; every active job steps on
+    the compute stream in batched launches."""
+
+    def __init__(self, max_jobs=32, hbm_budget=0, max_inflight=2, precision="fp32", stream=None,
+                 admit_stream=None, allocator="torch"):
+        L = lib()
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the HIP library is the only compute path")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.admit_stream = admit_stream if admit_stream is not None else torch.cuda.Stream()
+        sp = C.c_void_p(self.stream.cuda_stream)
+        sa = C.c_void_p(self.admit_stream.cuda_stream)
+        self._alloc = _TorchAlloc(sa.value) if allocator == "torch" else None
+        d = ServerDesc(int(max_jobs), int(hbm_budget), int(max_inflight),
+                       PRECISION[precision] if isinstance(precision, str) else int(precision))
+        h = C.c_void_p()
+        _check(L.psmdem_server_create(C.byref(d), sp, sa, self._alloc.alloc if self._alloc else ALLOC_FN(),
+                                      self._alloc.free if self._alloc else FREE_FN(), None, C.byref(h)))
+        self.h = h
+        self._jobs = {}
+
+    def submit(self, cfg, parts, steps):
+        d = make_desc(cfg)
+        ps, keep, _ = _particle_struct(parts)
+        j = C.c_int64()
+        _check(lib().psmdem_server_submit(self.h, C.byref(d), C.byref(ps), int(steps), C.byref(j)))
+        self._jobs[j.value] = (dict(cfg), parts)
+        return j.value
+
+    def iterate(self):
+        a = C.c_int32()
+        q = C.c_int32()
+        _check(lib().psmdem_server_iterate(self.h, C.byref(a), C.byref(q)))
+        return a.value, q.value
+
+    def drain(self):
+        _check(lib().psmdem_server_drain(self.h))
+
+    def job(self, jid):
+        i = JobInfo()
+        _check(lib().psmdem_server_job(self.h, int(jid), C.byref(i)))
+        return dict(state=JOB_STATE.get(i.state, i.state), slot=i.slot, steps=i.steps, steps_done=i.steps_done,
+                    footprint=i.footprint, status=i.status, t_submit=i.t_submit, t_admit=i.t_admit,
+                    t_done=i.t_done)
+
+    def domain(self, jid):
+        """Read-only view of a done job's domain (valid until release)."""
+        h = C.c_void_p()
+        _check(lib().psmdem_server_domain(self.h, int(jid), C.byref(h)))
+        cfg, parts = self._jobs[jid]
+        return Domain._attach(h, cfg, parts)
+
+    def release(self, jid):
+        _check(lib().psmdem_server_release(self.h, int(jid)))
+        self._jobs.pop(jid, None)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().psmdem_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def version():

@@ -195,3 +195,52 @@ def couette_suspension(precision="fp32", n=128, nsph=500, radius=5.0, seed=1001,
     pos = rsa_spheres(rng, nsph, radii, (n, n, n), _periodic(bc))
     parts = spheres(pos, radius, 1.5)
     return cfg, parts, dict(workload=f"couette_{n}^3_{len(pos)}_spheres", steps=steps)
+
+
+def serving_job(rng, kind, n, tau, nsph, r_lo=3.0, r_hi=6.0, precision="fp32", max_fraction=0.15):
+    """One ensemble job on an n^3 lattice.
+
+    kind 'settle': periodic x, y, no-slip walls in z, gravity (0, 0, -1e-5),
+    density ratio 2.  kind 'shear': periodic x, y, walls in z moving at -/+0.02
+    in x, density ratio 1.5.  nsph sphere radii uniform in [r_lo, r_hi], capped
+    so that the solid volume fraction stays below max_fraction; positions by
+    random sequential addition (fewer spheres when the box is full)."""
+    radii = r_lo + (r_hi - r_lo) * rng.uniform(nsph) if nsph > 0 else np.zeros(0)
+    vol = np.cumsum(4.0 / 3.0 * np.pi * radii ** 3)
+    keep = int(np.searchsorted(vol, max_fraction * n ** 3, side="right"))
+    radii = radii[:max(keep, 1 if nsph > 0 else 0)]
+    bc = ["periodic", "periodic", "periodic", "periodic", "noslip", "noslip"]
+    wu = [[0.0] * 3 for _ in range(6)]
+    if kind == "shear":
+        bc[4] = bc[5] = "moving"
+        wu[4] = [-0.02, 0.0, 0.0]
+        wu[5] = [0.02, 0.0, 0.0]
+        cfg = base_config((n, n, n), tau, bc=bc, wall_u=wu, precision=precision)
+        dens = 1.5
+    else:
+        cfg = base_config((n, n, n), tau, bc=bc, gravity=[0.0, 0.0, -1e-5], precision=precision)
+        dens = 2.0
+    pos = rsa_spheres(rng, len(radii), radii, (n, n, n), _periodic(bc), max_attempts=200 * max(len(radii), 1))
+    parts = spheres(pos, radii[:len(pos)], dens)
+    return cfg, parts
+
+
+def serving_stream(njobs=512, rate=50.0, seed=2024, steps=1000, sizes=(32, 64, 96, 128), tau=(0.55, 0.9),
+                   nsph=(1, 500), r_lo=3.0, r_hi=6.0, precision="fp32"):
+    """A Poisson stream of independent settling / shear jobs: exponential gaps of
+    mean 1/rate seconds; per job a lattice edge drawn from `sizes`, tau uniform
+    in `tau`, a sphere count uniform in `nsph` (see serving_job for the cap),
+    and `steps` coupled steps.  Returns a list of (arrival_s, cfg, parts, steps)."""
+    rng = SplitMix64(seed)
+    out = []
+    t = 0.0
+    for k in range(njobs):
+        u = rng.uniform(5)
+        t += -math.log(1.0 - u[0]) / rate
+        n = int(sizes[min(int(u[1] * len(sizes)), len(sizes) - 1)])
+        ta = tau[0] + (tau[1] - tau[0]) * u[2]
+        m = nsph[0] + min(int(u[3] * (nsph[1] - nsph[0] + 1)), nsph[1] - nsph[0])
+        kind = "settle" if u[4] < 0.5 else "shear"
+        cfg, parts = serving_job(rng, kind, n, ta, m, r_lo, r_hi, precision)
+        out.append((t, cfg, parts, steps))
+    return out

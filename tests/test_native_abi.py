@@ -46,3 +46,31 @@ def test_invalid_description_is_rejected_without_a_device():
                                                     "periodic", "periodic"]))
     code = L.psmdem_create(ctypes.byref(d), None, None, P.ALLOC_FN(), P.FREE_FN(), None, ctypes.byref(h))
     assert code == P.E_INVALID
+
+
+def _r256(n):
+    return (n + 255) // 256 * 256
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpsmdem.so not built")
+def test_footprint_memory_model_without_a_device():
+    """The admission memory model is the allocation plan of creation: the
+    population array is 19 N storage bytes, the per-cell solid slots hold a
+    B_k in the compute type and a double beta per kept solid."""
+    from paper_2512_04997_amd import psmdem as P
+    from paper_2512_04997_amd import workloads as W
+    n = (70, 9, 6)
+    N = 70 * 9 * 6
+    plane = 2 * 3 * 2 * 1024          # tiles of 64 x 4 x 4 cells, 1024 slots each
+    fp = {p: P.footprint(W.base_config(n, 0.7, precision=p)) for p in ("fp64", "fp32", "bf16", "fp16")}
+    assert fp["bf16"] == fp["fp16"]
+    assert fp["fp32"] - fp["bf16"] == _r256(19 * N * 4) - _r256(19 * N * 2)
+    assert fp["fp64"] - fp["fp32"] == _r256(19 * N * 8) - _r256(19 * N * 4) + _r256(8 * plane * 2) - _r256(
+        4 * plane * 2)
+    ms3 = P.footprint(W.base_config(n, 0.7, precision="fp32", max_solids=3))
+    assert ms3 - fp["fp32"] == _r256(4 * plane * 3) - _r256(4 * plane * 2) + _r256(8 * plane * 3) - _r256(
+        8 * plane * 2)
+    cfg, parts, _ = W.couette_suspension(n=48, nsph=20, radius=4.0)
+    assert P.footprint(cfg, parts) > P.footprint(cfg, None)
+    with pytest.raises(P.PsmdemError):
+        P.footprint(W.base_config(n, 0.4))
