@@ -28,6 +28,7 @@ struct DemArgs {
     double kn, beta_e, mu, kt_ratio, gt_ratio;
     double wall_u[6][3];
     double gravity[3];
+    int ellipsoids;        // any particle is an ellipsoid (else the sphere-only kernels run)
     DevCounters* ctr;
 };
 

@@ -63,18 +63,28 @@ __device__ inline void min_image(const DemArgs& A, const double* a, const double
     }
 }
 
-__device__ inline void half_extents(const DemArgs& A, int k, double e[3]) {
-    const double* s = A.p.semi + 3 * k;
-    if (A.p.shape[k] == 0) {
+// half extents of the particle's axis-aligned box from its shape, semi-axes
+// and orientation
+__device__ inline void half_extents_of(int shape, const double s[3], const double q[4], double e[3]) {
+    if (shape == 0) {
         e[0] = e[1] = e[2] = s[0];
         return;
     }
     double R[9];
-    quat_rbw(A.p.q + 4 * k, R);
+    quat_rbw(q, R);
     for (int r = 0; r < 3; ++r) {
         double t0 = s[0] * R[3 * r + 0], t1 = s[1] * R[3 * r + 1], t2 = s[2] * R[3 * r + 2];
         e[r] = sqrt((t0 * t0 + t1 * t1) + t2 * t2);
     }
+}
+
+__device__ inline void half_extents(const DemArgs& A, int k, double e[3]) {
+    const int shape = A.p.shape[k];
+    const double s[3] = {A.p.semi[3 * k], A.p.semi[3 * k + 1], A.p.semi[3 * k + 2]};
+    double q[4] = {1.0, 0.0, 0.0, 0.0};
+    if (shape != 0)
+        for (int c = 0; c < 4; ++c) q[c] = A.p.q[4 * k + c];
+    half_extents_of(shape, s, q, e);
 }
 
 // ---------------------------------------------------------------------------
@@ -87,12 +97,10 @@ struct AxCells {
     int n[3];
 };
 
-__device__ inline void axis_cells(const DemArgs& A, int k, AxCells& r) {
-    double e[3];
-    half_extents(A, k, e);
+__device__ inline void axis_cells_at(const DemArgs& A, const double pos[3], const double e[3], AxCells& r) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        double x = A.p.pos[3 * k + a];
+        double x = pos[a];
         int lo = (int)floor((x - e[a]) / A.h[a]);
         int hi = (int)floor((x + e[a]) / A.h[a]);
         int c0 = lo, c1 = lo + 1 <= hi ? lo + 1 : lo;
@@ -112,6 +120,13 @@ __device__ inline void axis_cells(const DemArgs& A, int k, AxCells& r) {
         r.c[a][1] = c1;
         r.n[a] = c1 == c0 ? 1 : 2;
     }
+}
+
+__device__ inline void axis_cells(const DemArgs& A, int k, AxCells& r) {
+    double e[3];
+    half_extents(A, k, e);
+    const double pos[3] = {A.p.pos[3 * k], A.p.pos[3 * k + 1], A.p.pos[3 * k + 2]};
+    axis_cells_at(A, pos, e, r);
 }
 
 __device__ inline void store_cells(const DemArgs& A, int k, const AxCells& r) {
@@ -280,22 +295,31 @@ __device__ void ellipsoid_pair(const DemArgs& A, int i, int j, Geom& G) {
     }
 }
 
-__device__ void pair_geometry(const DemArgs& A, int i, int j, Geom& G) {
+// ci, cj: centres; shi, shj: shapes; ri, rj: first semi-axes (loaded by the
+// caller).  ELL = false compiles the sphere paths only (domains without
+// ellipsoids), which keeps the register budget of the contact kernels small.
+template <bool ELL>
+__device__ void pair_geometry(const DemArgs& A, int i, int j, const double* ci, const double* cj, int shi, int shj,
+                              double ri, double rj, Geom& G) {
     const int np = A.p.np;
     G.sphere_law = false;
     if (j >= np) {
         int f = j - np, a = f / 2;
-        double n[3] = {0.0, 0.0, 0.0};
-        n[a] = (f % 2 == 0) ? 1.0 : -1.0;
-        const double* c = A.p.pos + 3 * i;
-        double dist = (f % 2 == 0) ? c[a] : A.L[a] - c[a];
+        // the wall normal and the centre's coordinate along it, by selects
+        // (no indexing of register arrays)
+        const double sgn = (f % 2 == 0) ? 1.0 : -1.0;
+        const double n[3] = {a == 0 ? sgn : 0.0, a == 1 ? sgn : 0.0, a == 2 ? sgn : 0.0};
+        const double* c = ci;
+        const double ca = a == 0 ? c[0] : (a == 1 ? c[1] : c[2]);
+        const double La = a == 0 ? A.L[0] : (a == 1 ? A.L[1] : A.L[2]);
+        double dist = (f % 2 == 0) ? ca : La - ca;
         for (int k = 0; k < 3; ++k) {
             G.en[k] = n[k];
             G.rcj[k] = 0.0;
         }
         G.rhoj = 0.0;
-        if (A.p.shape[i] == 0) {
-            double R = A.p.semi[3 * i];
+        if (!ELL || shi == 0) {
+            double R = ri;
             G.delta = R - dist;
             for (int k = 0; k < 3; ++k) G.rci[k] = -R * n[k];
             G.rhoi = R;
@@ -322,10 +346,10 @@ __device__ void pair_geometry(const DemArgs& A, int i, int j, Geom& G) {
         return;
     }
     double d[3];
-    min_image(A, A.p.pos + 3 * i, A.p.pos + 3 * j, d);
+    min_image(A, ci, cj, d);
     double r2 = (d[0] * d[0] + d[1] * d[1]) + d[2] * d[2];
-    if (A.p.shape[i] == 0 && A.p.shape[j] == 0) {
-        double Ri = A.p.semi[3 * i], Rj = A.p.semi[3 * j];
+    if (!ELL || (shi == 0 && shj == 0)) {
+        double Ri = ri, Rj = rj;
         double dist = sqrt(r2);
         G.delta = (Ri + Rj) - dist;
         for (int k = 0; k < 3; ++k) {
@@ -483,13 +507,24 @@ __device__ inline long long n_pairs(const DemArgs& A, const PairBufs& B) {
 // v_rel = (v_i - v_j) - (rho_i w_i + rho_j w_j) x e_n, v_t its tangential part;
 // history projected on the tangent plane then advanced by v_t dt;
 // F_t = -k_t d_t - gamma_t v_t capped at mu |F_n| with the history reset.
+template <bool ELL>
 __device__ void ph_contact(const DemArgs& A, const PairBufs& B, long long s, const double* __restrict__ vv,
                            const double* __restrict__ ww, double dth, long long nprev) {
     const int np = A.p.np;
-    unsigned long long key = B.pairs[s];
-    int i = (int)(key >> 32), j = (int)(key & 0xffffffffu);
+    const unsigned long long key = B.pairs[s];
+    const int i = (int)(key >> 32), j = (int)(key & 0xffffffffu);
+    const bool wall = j >= np;
+    // the geometry's inputs first; the kinematics, masses and history only for
+    // pairs in contact (most candidate pairs are not)
+    double ci[3], cj[3] = {0.0, 0.0, 0.0};
+    const int shi = A.p.shape[i], shj = wall ? 0 : A.p.shape[j];
+    const double ri = A.p.semi[3 * i], rj = wall ? 0.0 : A.p.semi[3 * j];
+    for (int k = 0; k < 3; ++k) {
+        ci[k] = A.p.pos[3 * i + k];
+        if (!wall) cj[k] = A.p.pos[3 * j + k];
+    }
     Geom G;
-    pair_geometry(A, i, j, G);
+    pair_geometry<ELL>(A, i, j, ci, cj, shi, shj, ri, rj, G);
     double* F = A.cF + 3 * s;
     double* Mi = A.cMi + 3 * s;
     double* Mj = A.cMj + 3 * s;
@@ -499,25 +534,31 @@ __device__ void ph_contact(const DemArgs& A, const PairBufs& B, long long s, con
         A.incontact[s] = 0;
         return;
     }
-    A.incontact[s] = 1;
-    double vi[3], wi[3], vj[3], wj[3], mstar;
+    double vi[3], wi[3], vj[3], wj[3];
+    const double mi = A.p.mass[i], mj = wall ? 0.0 : A.p.mass[j];
     for (int k = 0; k < 3; ++k) {
         vi[k] = vv[3 * i + k];
         wi[k] = ww[3 * i + k];
-    }
-    if (j < np) {
-        for (int k = 0; k < 3; ++k) {
+        if (!wall) {
             vj[k] = vv[3 * j + k];
             wj[k] = ww[3 * j + k];
         }
-        mstar = A.p.mass[i] * A.p.mass[j] / (A.p.mass[i] + A.p.mass[j]);
+    }
+    const long long ps = find_prev(B, key, nprev);
+    double ho[3] = {0.0, 0.0, 0.0};
+    if (ps >= 0)
+        for (int k = 0; k < 3; ++k) ho[k] = B.prev_hist[3 * ps + k];
+    A.incontact[s] = 1;
+    double mstar;
+    if (!wall) {
+        mstar = mi * mj / (mi + mj);
     } else {
         int f = j - np;
         for (int k = 0; k < 3; ++k) {
             vj[k] = (A.g.bc[f] == 2) ? A.wall_u[f][k] : 0.0;
             wj[k] = 0.0;
         }
-        mstar = A.p.mass[i];
+        mstar = mi;
     }
     const double kn = A.kn, kt = A.kt_ratio * kn;
     double gn = -2.0 * A.beta_e * sqrt(kn * mstar);
@@ -530,10 +571,6 @@ __device__ void ph_contact(const DemArgs& A, const PairBufs& B, long long s, con
     double vrel[3] = {(vi[0] - vj[0]) - cr[0], (vi[1] - vj[1]) - cr[1], (vi[2] - vj[2]) - cr[2]};
     double vrn = dot3(vrel, G.en);
     double vt[3] = {vrel[0] - vrn * G.en[0], vrel[1] - vrn * G.en[1], vrel[2] - vrn * G.en[2]};
-    double ho[3] = {0.0, 0.0, 0.0};
-    long long ps = find_prev(B, key, nprev);
-    if (ps >= 0)
-        for (int k = 0; k < 3; ++k) ho[k] = B.prev_hist[3 * ps + k];
     double hp = dot3(ho, G.en);
     double ht[3];
     for (int k = 0; k < 3; ++k) ht[k] = (ho[k] - hp * G.en[k]) + vt[k] * dth;
@@ -656,39 +693,69 @@ __device__ inline void quat_rate(const double* w, const double* q, double* out) 
 
 // predictor: r += dt v + dt^2/2 a (wrapped), v^p = v + dt a, w^p = w + dt alpha,
 // orientation advanced with w(t) by the triad predictor-corrector
-__device__ void ph_predict(const DemArgs& A, int k, double dt, int write_kin) {
-    double hdt2 = 0.5 * dt * dt;
-    double* x = A.p.pos + 3 * k;
+// Verlet predictor (Sec. 2.2): x += v dt + a dt^2/2, v^p = v + a dt,
+// w^p = w + alpha dt, quaternion advanced by a midpoint step of q' = q (0, w)/2
+// and renormalised.  Every input is loaded before the first store; the new
+// position and orientation then give the particle's registration cells.
+__device__ void ph_predict(const DemArgs& A, int k, double dt, int write_kin, AxCells& cells) {
+    double x[3], v[3], a[3], w[3], al[3], q0[4], sm[3];
+    const int shape = A.p.shape[k];
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
-        double xn = (x[c] + dt * A.p.v[3 * k + c]) + hdt2 * A.p.a[3 * k + c];
+        x[c] = A.p.pos[3 * k + c];
+        v[c] = A.p.v[3 * k + c];
+        a[c] = A.p.a[3 * k + c];
+        w[c] = A.p.w[3 * k + c];
+        al[c] = A.p.al[3 * k + c];
+        sm[c] = A.p.semi[3 * k + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) q0[c] = A.p.q[4 * k + c];
+    const double hdt2 = 0.5 * dt * dt;
+    double xn[3], vp[3], wp[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double y = (x[c] + dt * v[c]) + hdt2 * a[c];
         if (A.g.periodic[c]) {
             double L = A.L[c];
-            if (xn >= L) xn -= L;
-            else if (xn < 0.0) xn += L;
-            if (xn == L) xn = 0.0;
+            if (y >= L) y -= L;
+            else if (y < 0.0) y += L;
+            if (y == L) y = 0.0;
         }
-        x[c] = xn;
-        A.p.vp[3 * k + c] = A.p.v[3 * k + c] + dt * A.p.a[3 * k + c];
-        A.p.wp[3 * k + c] = A.p.w[3 * k + c] + dt * A.p.al[3 * k + c];
+        xn[c] = y;
+        vp[c] = v[c] + dt * a[c];
+        wp[c] = w[c] + dt * al[c];
     }
-    double* q = A.p.q + 4 * k;
-    double q0[4] = {q[0], q[1], q[2], q[3]};
-    for (int c = 0; c < 4; ++c) A.p.qold[4 * k + c] = q0[c];
     double r1[4], qs[4], qm[4], r2[4], qn[4];
-    quat_rate(A.p.w + 3 * k, q0, r1);
+    quat_rate(w, q0, r1);
     for (int c = 0; c < 4; ++c) qs[c] = q0[c] + dt * r1[c];
     for (int c = 0; c < 4; ++c) qm[c] = 0.5 * (q0[c] + qs[c]);
-    quat_rate(A.p.w + 3 * k, qm, r2);
+    quat_rate(w, qm, r2);
     for (int c = 0; c < 4; ++c) qn[c] = q0[c] + dt * r2[c];
     double l = sqrt((qn[0] * qn[0] + qn[1] * qn[1]) + (qn[2] * qn[2] + qn[3] * qn[3]));
-    for (int c = 0; c < 4; ++c) q[c] = qn[c] / l;
+    for (int c = 0; c < 4; ++c) qn[c] = qn[c] / l;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        A.p.pos[3 * k + c] = xn[c];
+        A.p.vp[3 * k + c] = vp[c];
+        A.p.wp[3 * k + c] = wp[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        A.p.qold[4 * k + c] = q0[c];
+        A.p.q[4 * k + c] = qn[c];
+    }
     if (write_kin) {
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
-            A.p.kin[9 * k + c] = x[c];
-            A.p.kin[9 * k + 3 + c] = A.p.vp[3 * k + c];
-            A.p.kin[9 * k + 6 + c] = A.p.wp[3 * k + c];
+            A.p.kin[9 * k + c] = xn[c];
+            A.p.kin[9 * k + 3 + c] = vp[c];
+            A.p.kin[9 * k + 6 + c] = wp[c];
         }
     }
+    double e[3];
+    half_extents_of(shape, sm, qn, e);
+    axis_cells_at(A, xn, e, cells);
 }
 
 // alpha = Rbw I^-1 [Rbw^T M - (Rbw^T w) x (I Rbw^T w)] at the substep start (as printed)
@@ -715,19 +782,34 @@ __device__ void ph_correct(const DemArgs& A, int k, double dt) {
         for (int c = 0; c < 3; ++c) A.p.a[3 * k + c] = A.p.al[3 * k + c] = 0.0;
         return;
     }
-    double m = A.p.mass[k];
-    double fb = 1.0 - 1.0 / A.p.dens[k];
+    const double m = A.p.mass[k];
+    const double fb = 1.0 - 1.0 / A.p.dens[k];
+    double fd[3], fh[3], md[3], mh[3], a[3], al[3], v[3], w[3], qo[4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        fd[c] = A.p.fd[3 * k + c];
+        fh[c] = A.p.fh[3 * k + c];
+        md[c] = A.p.md[3 * k + c];
+        mh[c] = A.p.mh[3 * k + c];
+        a[c] = A.p.a[3 * k + c];
+        al[c] = A.p.al[3 * k + c];
+        v[c] = A.p.v[3 * k + c];
+        w[c] = A.p.w[3 * k + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) qo[c] = A.p.qold[4 * k + c];
     double M[3], an[3], aln[3];
     for (int c = 0; c < 3; ++c) {
         double fext = m * fb * A.gravity[c];
-        an[c] = ((A.p.fd[3 * k + c] + A.p.fh[3 * k + c]) + fext) / m;
-        M[c] = A.p.md[3 * k + c] + A.p.mh[3 * k + c];
+        an[c] = ((fd[c] + fh[c]) + fext) / m;
+        M[c] = md[c] + mh[c];
     }
-    angular_accel(A, k, A.p.qold + 4 * k, A.p.w + 3 * k, M, aln);
+    angular_accel(A, k, qo, w, M, aln);
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
-        A.p.v[3 * k + c] += 0.5 * dt * (A.p.a[3 * k + c] + an[c]);
+        A.p.v[3 * k + c] = v[c] + 0.5 * dt * (a[c] + an[c]);
         A.p.a[3 * k + c] = an[c];
-        A.p.w[3 * k + c] += 0.5 * dt * (A.p.al[3 * k + c] + aln[c]);
+        A.p.w[3 * k + c] = w[c] + 0.5 * dt * (al[c] + aln[c]);
         A.p.al[3 * k + c] = aln[c];
     }
 }
@@ -764,8 +846,9 @@ __device__ void ph_initial_accel(const DemArgs& A, int k) {
 
 __global__ void k_predict(DemArgs A, double dt, int write_kin) {
     GRID_LOOP(k, A.p.np) {
-        ph_predict(A, (int)k, dt, write_kin);
-        ph_cells(A, (int)k);
+        AxCells r;
+        ph_predict(A, (int)k, dt, write_kin, r);
+        store_cells(A, (int)k, r);
     }
 }
 __global__ void k_cells(DemArgs A) { GRID_LOOP(k, A.p.np) ph_cells(A, (int)k); }
@@ -774,11 +857,12 @@ __global__ void k_scatter(DemArgs A) { GRID_LOOP(k, A.p.np) ph_scatter(A, (int)k
 __global__ void k_cellsort(DemArgs A) { GRID_LOOP(c, A.ncell) ph_cellsort(A, c); }
 __global__ void k_paircount(DemArgs A) { GRID_LOOP(i, A.p.np) ph_paircount<false>(A, (int)i); }
 __global__ void k_pairemit(DemArgs A, PairBufs B) { GRID_LOOP(i, A.p.np) ph_pairemit<false>(A, B, (int)i); }
+template <bool ELL>
 __global__ __launch_bounds__(256) void k_contacts(DemArgs A, PairBufs B, const double* vv, const double* ww, double dth) {
     long long nprev = B.prev_n ? *B.prev_n : 0;
     nprev = nprev < A.pair_cap ? nprev : A.pair_cap;
     const long long n = n_pairs(A, B);
-    GRID_LOOP(s, n) ph_contact(A, B, s, vv, ww, dth, nprev);
+    GRID_LOOP(s, n) ph_contact<ELL>(A, B, s, vv, ww, dth, nprev);
 }
 __global__ void k_colhist(DemArgs A, PairBufs B) {
     const long long n = n_pairs(A, B);
@@ -837,40 +921,39 @@ __device__ inline int reg_cell(const DemArgs& A, unsigned px, unsigned py, unsig
 
 // Row of particle i from the LDS cell lists: the partners j > i registered in
 // any of i's cells, merged from the (ascending) per-cell lists in ascending j,
-// each once.  After the scatter, cst[c] holds the end of cell c's list and
-// cst[c - 1] its start.
+// each once.  The head of every cell's list stays in a register; a merge step
+// takes the smallest head and advances every list that holds it.  After the
+// scatter, cst[c] holds the end of cell c's list and cst[c - 1] its start.
 template <bool EMIT>
 __device__ int merged_row(const DemArgs& A, int i, const unsigned* cells_s, const int* cst,
                           const unsigned short* cpid, unsigned long long* out, long long room) {
     const unsigned px = cells_s[3 * i], py = cells_s[3 * i + 1], pz = cells_s[3 * i + 2];
-    int cur[8], end[8];
+    constexpr int NONE = 0x7fffffff;
+    int cur[8], end[8], head[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
         const int c = reg_cell(A, px, py, pz, q);
-        int s0 = 0, s1 = 0;
-        if (c >= 0) {
-            s0 = c > 0 ? cst[c - 1] : 0;
-            s1 = cst[c];
-            while (s0 < s1 && (int)cpid[s0] <= i) ++s0;
-        }
-        cur[q] = s0;
-        end[q] = s1;
+        cur[q] = c > 0 ? cst[c - 1] : 0;
+        end[q] = c >= 0 ? cst[c] : 0;
     }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) head[q] = cur[q] < end[q] ? (int)cpid[cur[q]] : NONE;
     int n = 0;
     for (;;) {
-        int best = 0x7fffffff;
+        int best = head[0];
+#pragma unroll
+        for (int q = 1; q < 8; ++q) best = head[q] < best ? head[q] : best;
+        if (best == NONE) break;
 #pragma unroll
         for (int q = 0; q < 8; ++q)
-            if (cur[q] < end[q]) {
-                const int j = cpid[cur[q]];
-                best = j < best ? j : best;
+            if (head[q] == best) {
+                ++cur[q];
+                head[q] = cur[q] < end[q] ? (int)cpid[cur[q]] : NONE;
             }
-        if (best == 0x7fffffff) break;
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (cur[q] < end[q] && (int)cpid[cur[q]] == best) ++cur[q];
-        if (EMIT && n < room) out[n] = ((unsigned long long)i << 32) | (unsigned)best;
-        ++n;
+        if (best > i) {
+            if (EMIT && n < room) out[n] = ((unsigned long long)i << 32) | (unsigned)best;
+            ++n;
+        }
     }
     return n;
 }
@@ -886,7 +969,8 @@ __device__ int merged_row(const DemArgs& A, int i, const unsigned* cells_s, cons
 //            LDS, then each particle sums its column and its own row.
 // Larger grids test every i < j for a shared cell (64 partners per ballot);
 // longer pair lists search each (k, i) pair in row k.
-__device__ void dem_fused_body(const DemArgs& A, const PairSet& P, int cur, const int nsub, const double dt,
+template <bool ELL>
+__device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, const PairSet& P, int cur, const int nsub, const double dt,
                                const int stop_before_correct) {
     __shared__ unsigned cells_s[3 * DEM_FUSED_MAX];
     __shared__ int cnt_s[DEM_FUSED_MAX + 1];
@@ -903,18 +987,18 @@ __device__ void dem_fused_body(const DemArgs& A, const PairSet& P, int cur, cons
         const bool last = sub == nsub - 1;
         const int c = cur ^ 1;
         PairBufs B;
-        B.pairs = P.pairs[c];
-        B.prow = P.prow[c];
-        B.hist = P.hist[c];
-        B.prev_pairs = P.pairs[cur];
-        B.prev_hist = P.hist[cur];
-        B.prev_n = P.prow[cur] + np;
+        // buffer pointers by selects (the pair set is not indexed)
+        B.pairs = c ? P.pairs[1] : P.pairs[0];
+        B.prow = c ? P.prow[1] : P.prow[0];
+        B.hist = c ? P.hist[1] : P.hist[0];
+        B.prev_pairs = c ? P.pairs[0] : P.pairs[1];
+        B.prev_hist = c ? P.hist[0] : P.hist[1];
+        B.prev_n = (c ? P.prow[0] : P.prow[1]) + np;
         if (lds_cells)
             for (int u = tid; u <= ncell; u += FUSED_T) cst_s[u] = 0;
         for (int k = tid; k < np; k += FUSED_T) {
-            ph_predict(A, k, dt, last ? 1 : 0);
             AxCells r;
-            axis_cells(A, k, r);
+            ph_predict(A, k, dt, last ? 1 : 0, r);
             store_cells(A, k, r);
 #pragma unroll
             for (int a = 0; a < 3; ++a) cells_s[3 * k + a] = pack_axis(r, a);
@@ -1006,7 +1090,7 @@ __device__ void dem_fused_body(const DemArgs& A, const PairSet& P, int cur, cons
                 }
             }
         }
-        long long nprev = P.prow[cur][np];
+        long long nprev = *B.prev_n;
         nprev = nprev < A.pair_cap ? nprev : A.pair_cap;
         const bool prev_in_lds = nprev <= FUSED_PREV_LDS;
         if (prev_in_lds)
@@ -1016,7 +1100,7 @@ __device__ void dem_fused_body(const DemArgs& A, const PairSet& P, int cur, cons
         {
             PairBufs BL = B;
             if (prev_in_lds) BL.prev_pairs = prev_s;
-            for (long long s = tid; s < npairs; s += FUSED_T) ph_contact(A, BL, s, A.p.vp, A.p.wp, dt, nprev);
+            for (long long s = tid; s < npairs; s += FUSED_T) ph_contact<ELL>(A, BL, s, A.p.vp, A.p.wp, dt, nprev);
         }
         const bool lds_cols = npairs <= FUSED_COLS;
         if (lds_cols) {
@@ -1101,18 +1185,20 @@ __device__ void dem_fused_body(const DemArgs& A, const PairSet& P, int cur, cons
     }
 }
 
+template <bool ELL>
 __global__ __launch_bounds__(FUSED_T) void k_dem_fused(DemArgs A, PairSet P, int cur, int nsub, double dt,
                                                        int stop_before_correct) {
-    dem_fused_body(A, P, cur, nsub, dt, stop_before_correct);
+    dem_fused_body<ELL>(A, P, cur, nsub, dt, stop_before_correct);
 }
 
 // one workgroup per domain of a serving batch: the fused substeps (the last
 // one stops before the corrector when the fluid is coupled), or for a domain
 // without DEM the kinematics the LBM-PSM pass reads
+template <bool ELL>
 __global__ __launch_bounds__(FUSED_T) void k_dem_fused_batch(const DemJob* __restrict__ jobs, SrvDyn dyn) {
     const DemJob& J = jobs[blockIdx.x];
     if (J.dem) {
-        dem_fused_body(J.A, J.P, dyn.cur[blockIdx.x], J.nsub, J.dt, J.fluid);
+        dem_fused_body<ELL>(J.A, J.P, srv_bit(dyn.cur, blockIdx.x), J.nsub, J.dt, J.fluid);
     } else if (J.fluid) {
         const PartArgs& p = J.A.p;
         for (int k = threadIdx.x; k < p.np; k += FUSED_T)
@@ -1173,7 +1259,8 @@ hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, c
                         int* scan_tmp, hipStream_t s) {
     if (A.p.np == 0) return hipSuccess;
     hipError_t e;
-    k_contacts<<<nblk(A.pair_cap, 128), 128, 0, s>>>(A, B, vv, ww, dth);
+    if (A.ellipsoids) k_contacts<true><<<nblk(A.pair_cap, 128), 128, 0, s>>>(A, B, vv, ww, dth);
+    else k_contacts<false><<<nblk(A.pair_cap, 128), 128, 0, s>>>(A, B, vv, ww, dth);
     if ((e = psm_fill_int(A.col_count, 0, A.p.np, s)) != hipSuccess) return e;
     if ((e = psm_fill_int(A.col_fill, 0, A.p.np, s)) != hipSuccess) return e;
     k_colhist<<<nblk(A.pair_cap), 256, 0, s>>>(A, B);
@@ -1202,9 +1289,10 @@ hipError_t dem_zero(double* p, long long n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t dem_fused_batch(const DemJob* jobs, int njobs, const SrvDyn& dyn, hipStream_t s) {
+hipError_t dem_fused_batch(const DemJob* jobs, int njobs, const SrvDyn& dyn, int ellipsoids, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
-    k_dem_fused_batch<<<(unsigned)njobs, FUSED_T, 0, s>>>(jobs, dyn);
+    if (ellipsoids) k_dem_fused_batch<true><<<(unsigned)njobs, FUSED_T, 0, s>>>(jobs, dyn);
+    else k_dem_fused_batch<false><<<(unsigned)njobs, FUSED_T, 0, s>>>(jobs, dyn);
     return hipGetLastError();
 }
 
@@ -1218,6 +1306,7 @@ hipError_t dem_fused(const DemArgs& A, const PairSet& P, int cur, int nsub, doub
                      hipStream_t s) {
     if (A.p.np == 0 || nsub <= 0) return hipSuccess;
     if (A.p.np > DEM_FUSED_MAX || A.nc[0] > 65535 || A.nc[1] > 65535 || A.nc[2] > 65535) return hipErrorInvalidValue;
-    k_dem_fused<<<1, FUSED_T, 0, s>>>(A, P, cur, nsub, dt, stop_before_correct);
+    if (A.ellipsoids) k_dem_fused<true><<<1, FUSED_T, 0, s>>>(A, P, cur, nsub, dt, stop_before_correct);
+    else k_dem_fused<false><<<1, FUSED_T, 0, s>>>(A, P, cur, nsub, dt, stop_before_correct);
     return hipGetLastError();
 }

@@ -132,6 +132,8 @@ struct psmdem_domain {
         A.gt_ratio = d.gt_ratio;
         for (int f_ = 0; f_ < 6; ++f_)
             for (int c = 0; c < 3; ++c) A.wall_u[f_][c] = d.wall_u[f_][c];
+        A.ellipsoids = 0;
+        for (int sh : h_shape) A.ellipsoids |= sh != 0;
         A.ctr = ctr;
         return A;
     }

@@ -271,6 +271,68 @@ __device__ inline void store_all(const LbmArgs& A, S* f, long long N, long long 
     (store_dir<S, C, ODD, Is>(A, f, N, cell, ax, ay, az, out), ...);
 }
 
+// Rows whose links cross no wall (every row of a periodic domain, and all but
+// the edge rows of a walled one): each direction reads and writes its own
+// population plane at a 32-bit byte offset from that plane's base, the
+// neighbour offsets being the per-axis wrap-aware steps.
+template <typename S>
+__device__ inline const S* plane_ptr(const S* f, long long N, int i, unsigned off_bytes) {
+    return (const S*)((const char*)(f + (long long)i * N) + off_bytes);
+}
+
+template <typename S>
+__device__ inline S* plane_ptr(S* f, long long N, int i, unsigned off_bytes) {
+    return (S*)((char*)(f + (long long)i * N) + off_bytes);
+}
+
+template <int DX, int DY, int DZ>
+__device__ inline int plain_off(const AxisNb& ax, const AxisNb& ay, const AxisNb& az) {
+    int o = 0;
+    if (DX < 0) o += ax.om;
+    if (DX > 0) o += ax.op;
+    if (DY < 0) o += ay.om;
+    if (DY > 0) o += ay.op;
+    if (DZ < 0) o += az.om;
+    if (DZ > 0) o += az.op;
+    return o;
+}
+
+template <typename S, typename C, bool ODD, int I>
+__device__ inline void load_plain(const S* f, long long N, unsigned cell, const AxisNb& ax, const AxisNb& ay,
+                                  const AxisNb& az, C* g) {
+    constexpr unsigned sz = sizeof(S);
+    if (!ODD) {
+        g[I] = Conv<S, C>::ld(*plane_ptr(f, N, I, cell * sz));
+    } else {
+        const int o = plain_off<-d3q19_cx(I), -d3q19_cy(I), -d3q19_cz(I)>(ax, ay, az);
+        g[I] = Conv<S, C>::ld(*plane_ptr(f, N, d3q19_opp(I), (unsigned)((int)cell + o) * sz));
+    }
+}
+
+template <typename S, typename C, bool ODD, int I>
+__device__ inline void store_plain(S* f, long long N, unsigned cell, const AxisNb& ax, const AxisNb& ay,
+                                   const AxisNb& az, const C* out) {
+    constexpr unsigned sz = sizeof(S);
+    if (!ODD) {
+        *plane_ptr(f, N, d3q19_opp(I), cell * sz) = Conv<S, C>::st(out[I]);
+    } else {
+        const int o = plain_off<d3q19_cx(I), d3q19_cy(I), d3q19_cz(I)>(ax, ay, az);
+        *plane_ptr(f, N, I, (unsigned)((int)cell + o) * sz) = Conv<S, C>::st(out[I]);
+    }
+}
+
+template <typename S, typename C, bool ODD, int... Is>
+__device__ inline void load_all_plain(const S* f, long long N, unsigned cell, const AxisNb& ax, const AxisNb& ay,
+                                      const AxisNb& az, C* g, std::integer_sequence<int, Is...>) {
+    (load_plain<S, C, ODD, Is>(f, N, cell, ax, ay, az, g), ...);
+}
+
+template <typename S, typename C, bool ODD, int... Is>
+__device__ inline void store_all_plain(S* f, long long N, unsigned cell, const AxisNb& ax, const AxisNb& ay,
+                                       const AxisNb& az, const C* out, std::integer_sequence<int, Is...>) {
+    (store_plain<S, C, ODD, Is>(f, N, cell, ax, ay, az, out), ...);
+}
+
 __device__ inline unsigned long long ballot64(bool p) { return __ballot(p); }
 
 __device__ inline double wave_sum(double v) {
@@ -319,6 +381,8 @@ __device__ void lbm_tile(const LbmArgs& A, const long long t, double* kin_s, dou
     const AxisNb ax = axis_nb(x, A.g.nx, A.g.periodic[0], 1);
     const AxisNb ay = axis_nb(y, A.g.ny, A.g.periodic[1], A.g.nx);
     const bool xy_ok = x < A.g.nx && y < A.g.ny;
+    // this wave's row has no lane next to a wall in x or y (wave-uniform)
+    const bool row_plain = __ballot(xy_ok && (ax.wl || ax.wh || ay.wl || ay.wh)) == 0ull;
 
 #pragma unroll 1
     for (int lz = 0; lz < PSM_TZ; ++lz) {
@@ -332,7 +396,11 @@ __device__ void lbm_tile(const LbmArgs& A, const long long t, double* kin_s, dou
             const AxisNb az = axis_nb(z, A.g.nz, A.g.periodic[2], A.g.nx * A.g.ny);
             const long long cell = (long long)x + (long long)A.g.nx * ((long long)y + (long long)A.g.ny * z);
             C g[19], out[19];
-            load_all<S, C, ODD>(A, f, N, cell, ax, ay, az, g, std::make_integer_sequence<int, 19>{});
+            const bool plain = row_plain && !az.wl && !az.wh;
+            if (plain)
+                load_all_plain<S, C, ODD>(f, N, (unsigned)cell, ax, ay, az, g, std::make_integer_sequence<int, 19>{});
+            else
+                load_all<S, C, ODD>(A, f, N, cell, ax, ay, az, g, std::make_integer_sequence<int, 19>{});
             C Fx = (C)0, Fy = (C)0, Fz = (C)0;
             if (forcing) {
                 Fx = (C)A.F[0];
@@ -377,7 +445,10 @@ __device__ void lbm_tile(const LbmArgs& A, const long long t, double* kin_s, dou
                 }
             }
             collide<C, MS>(g, out, omega, forcing, Fx, Fy, Fz, nk, B, uk, Pk);
-            store_all<S, C, ODD>(A, f, N, cell, ax, ay, az, out, std::make_integer_sequence<int, 19>{});
+            if (plain)
+                store_all_plain<S, C, ODD>(f, N, (unsigned)cell, ax, ay, az, out, std::make_integer_sequence<int, 19>{});
+            else
+                store_all<S, C, ODD>(A, f, N, cell, ax, ay, az, out, std::make_integer_sequence<int, 19>{});
         }
         if (MS > 0) {
             // per-particle momentum exchange of this plane: wave sums into LDS
@@ -462,7 +533,7 @@ __global__ __launch_bounds__(256) void k_lbm_batch(const LbmArgs* __restrict__ j
     const long long b = xcd_block(nmap);
     if (b >= nmap) return;
     const int2 m = map[b];
-    if (dyn.odd[m.x]) lbm_tile<S, C, true, MS>(jobs[m.x], m.y, kin_s, acc);
+    if (srv_bit(dyn.odd, m.x)) lbm_tile<S, C, true, MS>(jobs[m.x], m.y, kin_s, acc);
     else lbm_tile<S, C, false, MS>(jobs[m.x], m.y, kin_s, acc);
 }
 

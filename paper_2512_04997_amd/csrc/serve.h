@@ -16,11 +16,22 @@
 
 #define SRV_MAX_JOBS 128
 
-// per-step state of every slot, passed by value at each launch
+// per-step state of every slot, passed by value at each launch as bit sets
+// (read with selects: a kernel argument indexed by a lane-uniform value would
+// otherwise be copied to private memory)
 struct SrvDyn {
-    unsigned char cur[SRV_MAX_JOBS];   // DEM pair buffer holding the previous list
-    unsigned char odd[SRV_MAX_JOBS];   // AA parity of the LBM step
+    unsigned long long cur[2];   // bit i: DEM pair buffer of slot i holding the previous list
+    unsigned long long odd[2];   // bit i: AA parity of slot i's LBM step
 };
+
+__host__ __device__ inline int srv_bit(const unsigned long long (&w)[2], int i) {
+    const unsigned long long v = i < 64 ? w[0] : w[1];
+    return (int)((v >> (i & 63)) & 1ull);
+}
+
+__host__ inline void srv_set(unsigned long long (&w)[2], int i, int b) {
+    if (b) w[i >> 6] |= 1ull << (i & 63);
+}
 
 // the DEM and particle side of one domain
 struct DemJob {
@@ -33,7 +44,7 @@ struct DemJob {
     int fluid;    // fluid coupled (fluid_on)
 };
 
-hipError_t dem_fused_batch(const DemJob* jobs, int njobs, const SrvDyn& dyn, hipStream_t s);
+hipError_t dem_fused_batch(const DemJob* jobs, int njobs, const SrvDyn& dyn, int ellipsoids, hipStream_t s);
 hipError_t dem_finish_batch(const DemJob* jobs, int njobs, hipStream_t s);
 hipError_t vox_register_batch(const VoxArgs* jobs, int njobs, hipStream_t s);
 hipError_t vox_voxelize_batch(const VoxArgs* jobs, const int2* map, long long nmap, int ctype_double,

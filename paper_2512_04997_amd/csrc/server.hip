@@ -271,14 +271,16 @@ int enqueue_step(psmdem_server* S) {
     memset(&dyn, 0, sizeof dyn);
     for (int i = 0; i < na; ++i) {
         psmdem_domain* D = S->active[i]->D;
-        dyn.cur[i] = (unsigned char)D->cur;
-        dyn.odd[i] = (unsigned char)(D->step & 1);
+        srv_set(dyn.cur, i, D->cur);
+        srv_set(dyn.odd, i, (int)(D->step & 1));
     }
     const int prec = S->d.precision;
     const int2* m_all = S->map_d;
     const int2* m2 = S->map_d + S->n_all;
     const int2* m4 = m2 + S->n_ms2;
-    PSM_CHECK(dem_fused_batch(S->dem_tab, na, dyn, S->s));
+    int ell = 0;
+    for (int i = 0; i < na; ++i) ell |= S->active[i]->D->dem_args().ellipsoids;
+    PSM_CHECK(dem_fused_batch(S->dem_tab, na, dyn, ell, S->s));
     PSM_CHECK(vox_register_batch(S->vox_tab, na, S->s));
     PSM_CHECK(vox_voxelize_batch(S->vox_tab, m_all, S->n_all, prec == 0, S->s));
     PSM_CHECK(lbm_step_batch(S->lbm_tab, dyn, m_all, S->n_all, 0, prec, S->s));

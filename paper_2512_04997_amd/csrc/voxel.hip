@@ -287,22 +287,9 @@ __device__ int classify(const VoxPart& P, int X, int Y, int Z) {
     return all_in ? 1 : 2;
 }
 
-#define VOX_MTAB 1024   // samples whose (a, b, c) indices are tabulated in LDS (ns <= 10)
-
 // one sample m (a fastest): inside test in the evaluation order of the definition
-__device__ inline bool sample_in(const VoxPart& P, int X, int Y, int Z, const double* off, int ns, int m,
-                                 const unsigned short* mtab) {
-    int a, b, c;
-    if (mtab) {
-        const unsigned t = mtab[m];
-        a = t & 31;
-        b = (t >> 5) & 31;
-        c = t >> 10;
-    } else {
-        a = m % ns;
-        b = (m / ns) % ns;
-        c = m / (ns * ns);
-    }
+__device__ inline bool sample_in(const VoxPart& P, int X, int Y, int Z, const double* off, int ns, int m) {
+    const int a = m % ns, b = (m / ns) % ns, c = m / (ns * ns);
     const double dz = ((double)Z + off[c]) - P.c[2];
     const double dy = ((double)Y + off[b]) - P.c[1];
     const double dx = ((double)X + off[a]) - P.c[0];
@@ -324,35 +311,52 @@ __device__ inline double beta_distance(const VoxPart& P, int X, int Y, int Z, do
 }
 
 #define VOX_QCAP 2048
+#define VOX_NS_REG 12   // spheres with at most this many samples per direction keep the x terms in registers
 #define VOX_T 256
 
-// keep the ms largest beta (ties: the earlier, smaller pid wins); register-resident
-__device__ inline void keep_top(double (&bb)[PSM_SLOTS_MAX], int (&bl)[PSM_SLOTS_MAX], int& nk, int ms,
-                                double beta, int u, unsigned long long& dropped) {
+// the ms largest beta of a cell (ties: the earlier, smaller pid wins), kept in
+// four named registers in descending order
+struct Top4 {
+    double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
+    int l0 = 0, l1 = 0, l2 = 0, l3 = 0;
+    int n = 0;
+};
+
+__device__ inline void top_swap(double& a, double& b, int& i, int& j) {
+    const double t = a;
+    a = b;
+    b = t;
+    const int k = i;
+    i = j;
+    j = k;
+}
+
+__device__ inline void keep_top(Top4& T, int ms, double beta, int u, unsigned long long& dropped) {
     int pos;
-    if (nk < ms) {
-        pos = nk++;
+    if (T.n < ms) {
+        pos = T.n++;
     } else {
         ++dropped;
-        double last = bb[0];
-#pragma unroll
-        for (int q = 1; q < PSM_SLOTS_MAX; ++q)
-            if (q == ms - 1) last = bb[q];
+        const double last = ms == 1 ? T.b0 : (ms == 2 ? T.b1 : (ms == 3 ? T.b2 : T.b3));
         if (!(beta > last)) return;
         pos = ms - 1;
     }
-#pragma unroll
-    for (int q = 0; q < PSM_SLOTS_MAX; ++q)
-        if (q == pos) {
-            bb[q] = beta;
-            bl[q] = u;
-        }
-#pragma unroll
-    for (int q = PSM_SLOTS_MAX - 1; q >= 1; --q)
-        if (q <= pos && bb[q - 1] < bb[q]) {
-            double tb = bb[q]; bb[q] = bb[q - 1]; bb[q - 1] = tb;
-            int ti = bl[q]; bl[q] = bl[q - 1]; bl[q - 1] = ti;
-        }
+    if (pos == 0) { T.b0 = beta; T.l0 = u; }
+    else if (pos == 1) { T.b1 = beta; T.l1 = u; }
+    else if (pos == 2) { T.b2 = beta; T.l2 = u; }
+    else { T.b3 = beta; T.l3 = u; }
+    if (pos >= 3 && T.b2 < T.b3) top_swap(T.b2, T.b3, T.l2, T.l3);
+    if (pos >= 2 && T.b1 < T.b2) top_swap(T.b1, T.b2, T.l1, T.l2);
+    if (pos >= 1 && T.b0 < T.b1) top_swap(T.b0, T.b1, T.l0, T.l1);
+}
+
+// the kept slots reordered by pid (local index order is pid order)
+__device__ inline void top_by_pid(Top4& T) {
+    for (int pass = 0; pass < 3; ++pass) {
+        if (1 < T.n && T.l1 < T.l0) top_swap(T.b0, T.b1, T.l0, T.l1);
+        if (2 < T.n && T.l2 < T.l1) top_swap(T.b1, T.b2, T.l1, T.l2);
+        if (3 < T.n && T.l3 < T.l2) top_swap(T.b2, T.b3, T.l2, T.l3);
+    }
 }
 
 template <typename C>
@@ -362,7 +366,6 @@ __device__ void voxelize_tile(const VoxArgs& A, const long long t) {
     __shared__ unsigned qitem[VOX_QCAP];
     __shared__ int qcnt[VOX_QCAP];
     __shared__ int tcnt[VOX_T];
-    __shared__ unsigned short mtab_s[VOX_MTAB];
     __shared__ double tab_s[(VOX_T / 64) * 9 * 32];
     __shared__ unsigned long long cnt_e, cnt_d;
     long long s0 = A.t.tile_start[t], s1 = A.t.tile_start[t + 1];
@@ -378,10 +381,6 @@ __device__ void voxelize_tile(const VoxArgs& A, const long long t) {
     const long long plane = A.g.ntiles * (long long)PSM_TILE;
     if (tid == 0) { cnt_e = 0; cnt_d = 0; }
     if (tid < ns) off[tid] = (double)(2 * tid + 1) / (double)(2 * ns);
-    const unsigned short* mtab = n3 <= VOX_MTAB ? mtab_s : nullptr;
-    if (mtab)
-        for (int m = tid; m < n3; m += VOX_T)
-            mtab_s[m] = (unsigned short)((m % ns) | (((m / ns) % ns) << 5) | ((m / (ns * ns)) << 10));
     for (int u = tid; u < count; u += VOX_T) {
         int k = (int)(A.t.tile_list[s0 + u] >> 32);
         if (k >= A.p.np) k = 0;
@@ -400,28 +399,48 @@ __device__ void voxelize_tile(const VoxArgs& A, const long long t) {
     __syncthreads();
     const int x = tx * PSM_TX + lane, y = ty * PSM_TY + wid;
     const bool xy_ok = x < A.g.nx && y < A.g.ny;
+    // candidates of this lane's (x, y) column: bit u set when particle u's
+    // lattice box holds x and y (ascending u = ascending pid)
+    unsigned long long cm0 = 0, cm1 = 0;
+    if (xy_ok)
+        for (int u = 0; u < count; ++u) {
+            int X, Y;
+            if (in_box(sp[u], x, A.g.nx, 0, A.g.periodic[0], &X) && in_box(sp[u], y, A.g.ny, 1, A.g.periodic[1], &Y)) {
+                if (u < 64) cm0 |= 1ull << u;
+                else cm1 |= 1ull << (u - 64);
+            }
+        }
 
     // phase A: number of (cell, particle) items that need samples, per lane
     int mine = 0;
-    if (subdiv && xy_ok)
+    if (subdiv)
         for (int lz = 0; lz < PSM_TZ; ++lz) {
             const int z = tz * PSM_TZ + lz;
             if (z >= A.g.nz) break;
-            for (int u = 0; u < count; ++u) {
-                int X, Y, Z;
-                const VoxPart& P = sp[u];
-                if (!in_box(P, x, A.g.nx, 0, A.g.periodic[0], &X) || !in_box(P, y, A.g.ny, 1, A.g.periodic[1], &Y) ||
-                    !in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z))
-                    continue;
-                mine += classify(P, X, Y, Z) == 2;
-            }
+            for (int w = 0; w < 2; ++w)
+                for (unsigned long long bits = w ? cm1 : cm0; bits; bits &= bits - 1) {
+                    const int u = 64 * w + __ffsll((long long)bits) - 1;
+                    int X, Y, Z;
+                    const VoxPart& P = sp[u];
+                    in_box(P, x, A.g.nx, 0, A.g.periodic[0], &X);
+                    in_box(P, y, A.g.ny, 1, A.g.periodic[1], &Y);
+                    if (!in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z)) continue;
+                    mine += classify(P, X, Y, Z) == 2;
+                }
         }
-    tcnt[tid] = mine;
+    // exclusive prefix of the per-lane item counts over the workgroup
+    int incl = mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    if (lane == 63) tcnt[wid] = incl;
     __syncthreads();
-    int my_off = 0, total = 0;
-    for (int w = 0; w < VOX_T; ++w) {
-        int c = tcnt[w];
-        if (w < tid) my_off += c;
+    int my_off = incl - mine, total = 0;
+    for (int w = 0; w < VOX_T / 64; ++w) {
+        const int c = tcnt[w];
+        if (w < wid) my_off += c;
         total += c;
     }
     // queue the items (lane order, then plane, then particle)
@@ -431,24 +450,29 @@ __device__ void voxelize_tile(const VoxArgs& A, const long long t) {
             const int z = tz * PSM_TZ + lz;
             if (z >= A.g.nz) break;
             const unsigned l = lane + PSM_TX * (wid + PSM_TY * lz);
-            for (int u = 0; u < count && j < VOX_QCAP; ++u) {
-                int X, Y, Z;
-                const VoxPart& P = sp[u];
-                if (!in_box(P, x, A.g.nx, 0, A.g.periodic[0], &X) || !in_box(P, y, A.g.ny, 1, A.g.periodic[1], &Y) ||
-                    !in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z))
-                    continue;
-                if (classify(P, X, Y, Z) == 2) qitem[j++] = (l << 8) | (unsigned)u;
-            }
+            for (int w = 0; w < 2; ++w)
+                for (unsigned long long bits = w ? cm1 : cm0; bits && j < VOX_QCAP; bits &= bits - 1) {
+                    const int u = 64 * w + __ffsll((long long)bits) - 1;
+                    int X, Y, Z;
+                    const VoxPart& P = sp[u];
+                    in_box(P, x, A.g.nx, 0, A.g.periodic[0], &X);
+                    in_box(P, y, A.g.ny, 1, A.g.periodic[1], &Y);
+                    if (!in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z)) continue;
+                    if (classify(P, X, Y, Z) == 2) qitem[j++] = (l << 8) | (unsigned)u;
+                }
         }
     }
     __syncthreads();
-    // phase B: each wave counts the inside samples of one item at a time (64 lanes
-    // per pass, the exact count from ballots).  The per-axis terms of the sample
-    // test are formed once per item in wave-private LDS with the same rounding as
-    // the definition: squared offsets for spheres, rotated components for
-    // ellipsoids.
+    // phase B: each wave counts the inside samples of one item at a time.  The
+    // per-axis terms of the sample test are formed once per item in wave-private
+    // LDS with the same rounding as the definition (squared offsets for spheres,
+    // rotated components for ellipsoids); then each lane takes one row (b, c) of
+    // samples and walks its ns samples along x with the x terms read as LDS
+    // broadcasts, so the inner loop is register arithmetic only.  The count is
+    // the sum of exact per-row counts.
     const int nq = total < VOX_QCAP ? total : VOX_QCAP;
     double* tab = tab_s + wid * (9 * 32);
+    const int nrows = ns * ns;
     for (int it = wid; it < nq; it += VOX_T / 64) {
         const unsigned item = qitem[it];
         const int u = (int)(item & 0xffu), l = (int)(item >> 8);
@@ -480,34 +504,55 @@ __device__ void voxelize_tile(const VoxArgs& A, const long long t) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const double R2 = P.ax[0] * P.ax[0];
         int cnt = 0;
-        for (int m0 = 0; m0 < n3; m0 += 64) {
-            const int m = m0 + lane;
-            bool in = false;
-            if (m < n3) {
-                int a, b, c;
-                if (mtab) {
-                    const unsigned tw = mtab[m];
-                    a = tw & 31;
-                    b = (tw >> 5) & 31;
-                    c = tw >> 10;
-                } else {
-                    a = m % ns;
-                    b = (m / ns) % ns;
-                    c = m / (ns * ns);
-                }
-                if (sph) {
-                    in = ((tab[a] + tab[ns + b]) + tab[2 * ns + c]) < R2;
-                } else {
-                    const double p0 = (tab[a] + tab[ns + b]) + tab[2 * ns + c];
-                    const double p1 = (tab[3 * ns + a] + tab[4 * ns + b]) + tab[5 * ns + c];
-                    const double p2 = (tab[6 * ns + a] + tab[7 * ns + b]) + tab[8 * ns + c];
-                    in = (((p0 * p0) * P.inv[0] + (p1 * p1) * P.inv[1]) + (p2 * p2) * P.inv[2]) < 1.0;
-                }
+        if (sph && ns <= VOX_NS_REG) {
+            // x terms in registers (LDS broadcasts, once per item)
+            const double R2 = P.ax[0] * P.ax[0];
+            double x2[VOX_NS_REG];
+#pragma unroll
+            for (int a = 0; a < VOX_NS_REG; ++a) x2[a] = a < ns ? tab[a] : 0.0;
+            for (int r0 = 0; r0 < nrows; r0 += 64) {
+                const int r = r0 + lane;
+                const bool act = r < nrows;
+                const int b = act ? r % ns : 0, c = act ? r / ns : 0;
+                const double y2 = tab[ns + b], z2 = tab[2 * ns + c];
+                int rc = 0;
+#pragma unroll
+                for (int a = 0; a < VOX_NS_REG; ++a) rc += (a < ns && ((x2[a] + y2) + z2) < R2) ? 1 : 0;
+                cnt += act ? rc : 0;
             }
-            cnt += __popcll(__ballot(in));
+        } else if (sph) {
+            const double R2 = P.ax[0] * P.ax[0];
+            for (int r0 = 0; r0 < nrows; r0 += 64) {
+                const int r = r0 + lane;
+                const bool act = r < nrows;
+                const int b = act ? r % ns : 0, c = act ? r / ns : 0;
+                const double y2 = tab[ns + b], z2 = tab[2 * ns + c];
+                int rc = 0;
+                for (int a = 0; a < ns; ++a) rc += ((tab[a] + y2) + z2) < R2 ? 1 : 0;
+                cnt += act ? rc : 0;
+            }
+        } else {
+            const double i0 = P.inv[0], i1 = P.inv[1], i2 = P.inv[2];
+            for (int r0 = 0; r0 < nrows; r0 += 64) {
+                const int r = r0 + lane;
+                const bool act = r < nrows;
+                const int b = act ? r % ns : 0, c = act ? r / ns : 0;
+                const double y0 = tab[ns + b], z0 = tab[2 * ns + c];
+                const double y1 = tab[4 * ns + b], z1 = tab[5 * ns + c];
+                const double y2 = tab[7 * ns + b], z2 = tab[8 * ns + c];
+                int rc = 0;
+                for (int a = 0; a < ns; ++a) {
+                    const double p0 = (tab[a] + y0) + z0;
+                    const double p1 = (tab[3 * ns + a] + y1) + z1;
+                    const double p2 = (tab[6 * ns + a] + y2) + z2;
+                    rc += (((p0 * p0) * i0 + (p1 * p1) * i1) + (p2 * p2) * i2) < 1.0 ? 1 : 0;
+                }
+                cnt += act ? rc : 0;
+            }
         }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
         if (lane == 0) qcnt[it] = cnt;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -520,64 +565,59 @@ __device__ void voxelize_tile(const VoxArgs& A, const long long t) {
     for (int lz = 0; lz < PSM_TZ; ++lz) {
         const int z = tz * PSM_TZ + lz;
         const long long l = lane + PSM_TX * (wid + PSM_TY * lz);
-        double bb[PSM_SLOTS_MAX] = {0.0, 0.0, 0.0, 0.0};
-        int bl[PSM_SLOTS_MAX] = {0, 0, 0, 0};
-        int nk = 0;
+        Top4 T;
         if (xy_ok && z < A.g.nz) {
-            for (int u = 0; u < count; ++u) {
-                const VoxPart& P = sp[u];
-                int X, Y, Z;
-                if (!in_box(P, x, A.g.nx, 0, A.g.periodic[0], &X) || !in_box(P, y, A.g.ny, 1, A.g.periodic[1], &Y) ||
-                    !in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z))
-                    continue;
-                double beta;
-                if (!subdiv) {
-                    beta = beta_distance(P, X, Y, Z, A.Rc);
-                } else {
-                    const int cl = classify(P, X, Y, Z);
-                    if (cl == 0) continue;
-                    if (cl == 1) {
-                        beta = 1.0;
+            for (int w = 0; w < 2; ++w)
+                for (unsigned long long bits = w ? cm1 : cm0; bits; bits &= bits - 1) {
+                    const int u = 64 * w + __ffsll((long long)bits) - 1;
+                    const VoxPart& P = sp[u];
+                    int X, Y, Z;
+                    in_box(P, x, A.g.nx, 0, A.g.periodic[0], &X);
+                    in_box(P, y, A.g.ny, 1, A.g.periodic[1], &Y);
+                    if (!in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z)) continue;
+                    double beta;
+                    if (!subdiv) {
+                        beta = beta_distance(P, X, Y, Z, A.Rc);
                     } else {
-                        int cnt;
-                        if (j < VOX_QCAP) {
-                            cnt = qcnt[j];
+                        const int cl = classify(P, X, Y, Z);
+                        if (cl == 0) continue;
+                        if (cl == 1) {
+                            beta = 1.0;
                         } else {
-                            cnt = 0;
-                            for (int m = 0; m < n3; ++m) cnt += sample_in(P, X, Y, Z, off, ns, m, mtab);
+                            int cnt;
+                            if (j < VOX_QCAP) {
+                                cnt = qcnt[j];
+                            } else {
+                                cnt = 0;
+                                for (int m = 0; m < n3; ++m) cnt += sample_in(P, X, Y, Z, off, ns, m);
+                            }
+                            ++j;
+                            beta = (double)cnt / (double)n3;
                         }
-                        ++j;
-                        beta = (double)cnt / (double)n3;
                     }
+                    if (!(beta > 0.0)) continue;
+                    ++my_e;
+                    keep_top(T, ms, beta, u, my_d);
                 }
-                if (!(beta > 0.0)) continue;
-                ++my_e;
-                keep_top(bb, bl, nk, ms, beta, u, my_d);
             }
-        }
-        // kept slots ordered by pid (local index order is pid order)
-#pragma unroll
-        for (int pass = 0; pass < PSM_SLOTS_MAX - 1; ++pass)
-#pragma unroll
-            for (int q = 0; q < PSM_SLOTS_MAX - 1; ++q)
-                if (q + 1 < nk && bl[q + 1] < bl[q]) {
-                    int ti = bl[q]; bl[q] = bl[q + 1]; bl[q + 1] = ti;
-                    double tb = bb[q]; bb[q] = bb[q + 1]; bb[q + 1] = tb;
-                }
+        top_by_pid(T);
         unsigned int lp = 0xffffffffu;
-#pragma unroll
-        for (int q = 0; q < PSM_SLOTS_MAX; ++q)
-            if (q < nk) lp = (lp & ~(0xffu << (8 * q))) | ((unsigned)bl[q] << (8 * q));
+        if (T.n > 0) lp = (lp & ~0xffu) | (unsigned)T.l0;
+        if (T.n > 1) lp = (lp & ~0xff00u) | ((unsigned)T.l1 << 8);
+        if (T.n > 2) lp = (lp & ~0xff0000u) | ((unsigned)T.l2 << 16);
+        if (T.n > 3) lp = (lp & ~0xff000000u) | ((unsigned)T.l3 << 24);
         if (xy_ok && z < A.g.nz) {
             A.t.slot_lp[base + l] = lp;
+            const double bq[PSM_SLOTS_MAX] = {T.n > 0 ? T.b0 : 0.0, T.n > 1 ? T.b1 : 0.0, T.n > 2 ? T.b2 : 0.0,
+                                              T.n > 3 ? T.b3 : 0.0};
 #pragma unroll
-            for (int q = 0; q < PSM_SLOTS_MAX; ++q) {
-                if (q >= ms) break;
-                double beta = q < nk ? bb[q] : 0.0;
-                double B = beta * (A.tau - 0.5) / ((1.0 - beta) + (A.tau - 0.5));
-                Bout[q * plane + base + l] = (C)B;
-                A.t.slot_beta[q * plane + base + l] = beta;
-            }
+            for (int q = 0; q < PSM_SLOTS_MAX; ++q)
+                if (q < ms) {
+                    const double beta = bq[q];
+                    const double B = beta * (A.tau - 0.5) / ((1.0 - beta) + (A.tau - 0.5));
+                    Bout[q * plane + base + l] = (C)B;
+                    A.t.slot_beta[q * plane + base + l] = beta;
+                }
         }
     }
     if (my_e) atomicAdd(&cnt_e, my_e);
