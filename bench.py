@@ -45,7 +45,110 @@ def parse():
     p.add_argument("--serve-slots", type=int, default=32, help="active slots of the server")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only run 20 plain device copies of MIB MiB (calibrates the HBM byte counters)")
+    p.add_argument("--lbm-sweep", type=int, default=0, metavar="N",
+                   help="only time the LBM pass of a periodic fluid-only N^3 lattice in every precision")
+    p.add_argument("--summarize", nargs="+", metavar="DIR",
+                   help="print a per-kernel summary of rocprofv3 CSV output (no GPU): DIR of a --kernel-trace "
+                        "--stats run, or four DIRs of --pmc runs: FETCH_SIZE, WRITE_SIZE, and the same two "
+                        "counters over --copy-probe")
+    p.add_argument("--kernel", default="k_lbm<", help="kernel-name filter of the counter summary")
     return p.parse_args()
+
+
+def lbm_source_digest():
+    """Digest of the LBM kernel source: counter-derived traffic is reported only
+    while the kernel is the one the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "paper_2512_04997_amd", "csrc", "lbm.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lbm_couette128_fp32_traffic.txt")
+
+
+def measured_traffic(precision, n, spheres):
+    """HBM bytes per LBM pass from the committed counter summary, if it was
+    taken on this workload and on the current kernel source; else None."""
+    try:
+        rec = json.loads(open(TRAFFIC_FILE).read().split("JSON:", 1)[1].strip().splitlines()[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if (rec.get("lbm_source") != lbm_source_digest() or rec.get("precision") != precision or rec.get("n") != n
+            or rec.get("spheres") != spheres):
+        return None
+    return rec.get("bytes_per_pass")
+
+
+def _csv(path):
+    import csv
+    return list(csv.DictReader(open(path)))
+
+
+def summarize(dirs, kernel_filter):
+    """Per-kernel tables from rocprofv3 CSV output (host-only parsing)."""
+    import glob
+    if len(dirs) == 1:
+        f = glob.glob(os.path.join(dirs[0], "*kernel_stats.csv"))[0]
+        rows = sorted(_csv(f), key=lambda r: -float(r["TotalDurationNs"]))
+        tot = sum(float(r["TotalDurationNs"]) for r in rows)
+        print("| kernel | calls | avg us | total ms | % |")
+        print("|---|---|---|---|---|")
+        for r in rows[:25]:
+            print(f"| `{r['Name'][:100]}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                  f"{float(r['TotalDurationNs']) / 1e6:.3f} | {100 * float(r['TotalDurationNs']) / tot:.1f} |")
+        return
+    if len(dirs) != 4:
+        raise SystemExit("--summarize takes one kernel-trace directory or four counter directories")
+
+    def per_kernel(d, counter):
+        f = glob.glob(os.path.join(d, "*counter_collection.csv"))[0]
+        out = {}
+        for r in _csv(f):
+            if r["Counter_Name"] != counter:
+                continue
+            out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return out
+
+    fetch, write = per_kernel(dirs[0], "FETCH_SIZE"), per_kernel(dirs[1], "WRITE_SIZE")
+    cf, cw = per_kernel(dirs[2], "FETCH_SIZE"), per_kernel(dirs[3], "WRITE_SIZE")
+    # the copy probe: 20 copies of a known size; the counters' KiB against the bytes moved
+    probe_kib = max(max(v) for k, v in cw.items() if "copyBuffer" in k or "copy" in k.lower())
+    ck = [k for k in cf if "copyBuffer" in k][0]
+    f_fetch = probe_kib / (sum(cf[ck]) / len(cf[ck]))
+    f_write = probe_kib / (sum(cw[ck]) / len(cw[ck]))
+    print(f"copy probe: {probe_kib:.0f} KiB read and written per copy; FETCH_SIZE reads "
+          f"{sum(cf[ck]) / len(cf[ck]):.0f} KiB (factor {f_fetch:.3f}), WRITE_SIZE reads "
+          f"{sum(cw[ck]) / len(cw[ck]):.0f} KiB (factor {f_write:.3f})")
+    print("| kernel | dispatches | FETCH_SIZE KiB (avg) | WRITE_SIZE KiB (avg) | scaled MB per dispatch |")
+    print("|---|---|---|---|---|")
+    for k in sorted(set(fetch) | set(write)):
+        if kernel_filter not in k:
+            continue
+        fv, wv = fetch.get(k, [0.0]), write.get(k, [0.0])
+        mb = (f_fetch * sum(fv) / len(fv) + f_write * sum(wv) / len(wv)) * 1024 / 1e6
+        print(f"| `{k[:90]}` | {len(fv)} | {sum(fv) / len(fv):.0f} | {sum(wv) / len(wv):.0f} | {mb:.1f} |")
+    return f_fetch, f_write, fetch, write
+
+
+def lbm_sweep(n):
+    """LBM pass of a periodic fluid-only n^3 lattice (body force on), all precisions."""
+    import torch
+    from paper_2512_04997_amd import psmdem, workloads
+    torch.cuda.set_device(0)
+    for prec, sb in STORAGE_BYTES.items():
+        cfg = workloads.base_config((n, n, n), 0.7, precision=prec, body_force=[1e-6, 0.0, 0.0])
+        D = psmdem.Domain(cfg, None)
+        D.step(10)
+        D.sync()
+        D.set_timing(True)
+        D.step(50)
+        D.set_timing(False)
+        ms, _ = D.timing("lbm")
+        N = n ** 3
+        print(json.dumps({"lbm_sweep": prec, "n": n, "lbm_ms": round(ms, 4), "mlups": round(N / ms / 1e3, 1),
+                          "alg_GBs": round(N * 2 * 19 * sb / (ms * 1e-3) / 1e9, 1),
+                          "frac": round(N * 2 * 19 * sb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}), flush=True)
+        D.close()
 
 
 def copy_probe(mib):
@@ -160,6 +263,9 @@ def cpu_baseline(cfg, parts, steps):
 
 def main():
     a = parse()
+    if a.summarize:
+        summarize(a.summarize, a.kernel)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}): the coupled step of one "
               "domain is a single-GPU build; see the design notes for how it would shard.", file=sys.stderr)
@@ -168,6 +274,9 @@ def main():
 
     if a.copy_probe:
         copy_probe(a.copy_probe)
+        return
+    if a.lbm_sweep:
+        lbm_sweep(a.lbm_sweep)
         return
     from paper_2512_04997_amd import psmdem, workloads
 
@@ -209,7 +318,7 @@ def main():
         alg_bytes = N * 2 * 19 * sb
         achieved = alg_bytes / (lbm_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(a.precision, a.n, a.spheres),
                 "kernel": "LBM collide-stream pass (k_lbm fluid-tile + PSM-tile kernels of one step)",
                 "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": round(lbm_ms, 5)}
         print(f"[bench] per step: lbm {lbm_ms:.4f} ms, voxel {vox_ms:.4f} ms, hydro {hyd_ms:.4f} ms, "

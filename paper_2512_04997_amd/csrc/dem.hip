@@ -854,7 +854,14 @@ __global__ void k_predict(DemArgs A, double dt, int write_kin) {
 __global__ void k_cells(DemArgs A) { GRID_LOOP(k, A.p.np) ph_cells(A, (int)k); }
 __global__ void k_hist(DemArgs A) { GRID_LOOP(k, A.p.np) ph_hist(A, (int)k); }
 __global__ void k_scatter(DemArgs A) { GRID_LOOP(k, A.p.np) ph_scatter(A, (int)k); }
-__global__ void k_cellsort(DemArgs A) { GRID_LOOP(c, A.ncell) ph_cellsort(A, c); }
+// sorts each cell's list, then clears the cell's counters for the next list build
+__global__ void k_cellsort(DemArgs A) {
+    GRID_LOOP(c, A.ncell) {
+        ph_cellsort(A, c);
+        A.cell_count[c] = 0;
+        A.cell_fill[c] = 0;
+    }
+}
 __global__ void k_paircount(DemArgs A) { GRID_LOOP(i, A.p.np) ph_paircount<false>(A, (int)i); }
 __global__ void k_pairemit(DemArgs A, PairBufs B) { GRID_LOOP(i, A.p.np) ph_pairemit<false>(A, B, (int)i); }
 template <bool ELL>
@@ -872,7 +879,14 @@ __global__ void k_colscatter(DemArgs A, PairBufs B) {
     const long long n = n_pairs(A, B);
     GRID_LOOP(s, n) ph_colscatter(A, B, s);
 }
-__global__ void k_colsort(DemArgs A) { GRID_LOOP(j, A.p.np) ph_colsort(A, (int)j); }
+// sorts each column list, then clears the column's counters for the next build
+__global__ void k_colsort(DemArgs A) {
+    GRID_LOOP(j, A.p.np) {
+        ph_colsort(A, (int)j);
+        A.col_count[j] = 0;
+        A.col_fill[j] = 0;
+    }
+}
 __global__ void k_sum(DemArgs A, PairBufs B) { GRID_LOOP(i, A.p.np) ph_sum<false>(A, B, (int)i); }
 __global__ void k_correct(DemArgs A, double dt) { GRID_LOOP(k, A.p.np) ph_correct(A, (int)k, dt); }
 __global__ void k_initial_accel(DemArgs A) { GRID_LOOP(k, A.p.np) ph_initial_accel(A, (int)k); }
@@ -1242,9 +1256,8 @@ hipError_t dem_predict(const DemArgs& A, double dt, int write_kin, hipStream_t s
 hipError_t dem_lists(const DemArgs& A, const PairBufs& B, int* scan_tmp, hipStream_t s) {
     if (A.p.np == 0) return hipSuccess;
     hipError_t e;
+    // the cell and column counters start at zero (creation) and the sort kernels clear them again
     k_cells<<<nblk(A.p.np), 256, 0, s>>>(A);
-    if ((e = psm_fill_int(A.cell_count, 0, A.ncell, s)) != hipSuccess) return e;
-    if ((e = psm_fill_int(A.cell_fill, 0, A.ncell, s)) != hipSuccess) return e;
     k_hist<<<nblk(A.p.np), 256, 0, s>>>(A);
     if ((e = psm_scan(A.cell_count, A.cell_start, A.ncell, scan_tmp, s)) != hipSuccess) return e;
     k_scatter<<<nblk(A.p.np), 256, 0, s>>>(A);
@@ -1261,8 +1274,6 @@ hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, c
     hipError_t e;
     if (A.ellipsoids) k_contacts<true><<<nblk(A.pair_cap, 128), 128, 0, s>>>(A, B, vv, ww, dth);
     else k_contacts<false><<<nblk(A.pair_cap, 128), 128, 0, s>>>(A, B, vv, ww, dth);
-    if ((e = psm_fill_int(A.col_count, 0, A.p.np, s)) != hipSuccess) return e;
-    if ((e = psm_fill_int(A.col_fill, 0, A.p.np, s)) != hipSuccess) return e;
     k_colhist<<<nblk(A.pair_cap), 256, 0, s>>>(A, B);
     if ((e = psm_scan(A.col_count, A.col_start, A.p.np, scan_tmp, s)) != hipSuccess) return e;
     k_colscatter<<<nblk(A.pair_cap), 256, 0, s>>>(A, B);

@@ -37,11 +37,6 @@ PsmErr psm_hip_fail(hipError_t e, const char* what, const char* file, int line) 
 
 namespace {
 
-__global__ void k_zero_u64(unsigned long long* p, int n) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0ull;
-}
-
 __global__ void k_kin(PartArgs p, int copy_vw) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= p.np) return;
@@ -103,9 +98,13 @@ void encode(unsigned char* raw, int prec, long long idx, double v) {
 // stages
 // ---------------------------------------------------------------------------
 static int run_voxelize(psmdem_domain* D) {
+    // without particles the tile lists stay empty as created: every tile is fluid
+    if (D->np == 0) {
+        D->voxelized = true;
+        return 0;
+    }
     VoxArgs V = D->vox_args();
     int tk = D->timed_begin(PSMDEM_T_VOXEL);
-    k_zero_u64<<<1, 64, 0, D->s>>>(&D->ctr->entries, 2);
     PSM_CHECK(vox_register(V, D->scan_tmp, D->s));
     PSM_CHECK(vox_voxelize(V, D->prec == 0, D->s));
     D->timed_end(tk);
@@ -471,6 +470,12 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
         H2D(D->wall_corr_d, D->wall_corr, sizeof(double) * 6 * 19);
         // registration lists start out valid (particle 0, entry 0)
         if (hipMemsetAsync(D->t.tile_list, 0, sizeof(unsigned long long) * D->t.cap, D->s) != hipSuccess ||
+            hipMemsetAsync(D->tile_count, 0, sizeof(int) * g.ntiles, D->s) != hipSuccess ||
+            hipMemsetAsync(D->cell_count, 0, sizeof(int) * D->ncell, D->s) != hipSuccess ||
+            hipMemsetAsync(D->cell_fill, 0, sizeof(int) * D->ncell, D->s) != hipSuccess ||
+            hipMemsetAsync(D->col_count, 0, sizeof(int) * std::max(np, 1), D->s) != hipSuccess ||
+            hipMemsetAsync(D->col_fill, 0, sizeof(int) * std::max(np, 1), D->s) != hipSuccess ||
+            hipMemsetAsync(D->tile_fill, 0, sizeof(int) * g.ntiles, D->s) != hipSuccess ||
             hipMemsetAsync(D->t.vinv, 0, sizeof(int) * D->t.cap, D->s) != hipSuccess ||
             hipMemsetAsync(D->t.slot_lp, 0xff, sizeof(unsigned) * g.ntiles * (size_t)PSM_TILE, D->s) != hipSuccess ||
             hipMemsetAsync(D->cell_pid, 0, sizeof(int) * D->reg_cap, D->s) != hipSuccess ||

@@ -1,6 +1,8 @@
 // scan.hip -- device-wide exclusive prefix sum of int32 counts and a fill
-// kernel.  Three launches: per-block scan of 1024 elements (256 lanes x 4),
-// a single-block scan of the block totals, and the block-offset add.
+// kernel.  Up to SCAN_SMALL elements one workgroup of 1024 lanes scans in
+// chunks with a running carry (one launch); longer inputs take three
+// launches: per-block scan of 1024 elements (256 lanes x 4), a single-block
+// scan of the block totals, and the block-offset add.
 #include "common.h"
 
 namespace {
@@ -82,6 +84,12 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_add(int* __restrict__ out, long
         if (base + k < n) out[base + k] += add;
 }
 
+constexpr long long SCAN_SMALL = 32768;
+
+__global__ __launch_bounds__(1024) void k_scan_small(const int* in, int* out, long long n) {
+    psm_block_scan<1024>(in, out, n);
+}
+
 __global__ void k_fill_int(int* __restrict__ p, int v, long long n) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -92,6 +100,10 @@ __global__ void k_fill_int(int* __restrict__ p, int v, long long n) {
 size_t psm_scan_tmp_ints(long long n) { return (size_t)((n + SCAN_BLOCK - 1) / SCAN_BLOCK + 1); }
 
 hipError_t psm_scan(const int* in, int* out, long long n, int* tmp, hipStream_t s) {
+    if (n <= SCAN_SMALL) {
+        k_scan_small<<<1, 1024, 0, s>>>(in, out, n < 0 ? 0 : n);
+        return hipGetLastError();
+    }
     int nb = (int)((n + SCAN_BLOCK - 1) / SCAN_BLOCK);
     if (nb < 1) nb = 1;
     k_scan_local<<<nb, SCAN_T, 0, s>>>(in, out, n, tmp);

@@ -108,37 +108,40 @@ __device__ inline void particle_tiles(const VoxArgs& A, int k, TileSet& S) {
     S.nz = axis_tiles(lo[2], hi[2], A.g.nz, PSM_TZ, A.g.periodic[2], S.tz);
 }
 
-// tiles of particle k: count, and one tile-histogram increment each (through `hist`)
-__device__ inline void reg_count(const VoxArgs& A, int k, int* hist) {
+// Registration of particle k, one wave per particle: lane l takes the l-th
+// tile of the particle's box (x fastest, then y, then z), which is also the
+// order of its emission indices.
+__device__ inline long long tile_of(const VoxArgs& A, const TileSet& S, int l) {
+    const int a = l % S.nx, b = (l / S.nx) % S.ny, c = l / (S.nx * S.ny);
+    return S.tx[a] + (long long)A.g.ntx * (S.ty[b] + (long long)A.g.nty * S.tz[c]);
+}
+
+// tile count of particle k and one tile-histogram increment per tile (through `hist`)
+__device__ inline void reg_count_wave(const VoxArgs& A, int k, int lane, int* hist) {
     TileSet S;
     particle_tiles(A, k, S);
-    A.t.vcount[k] = S.nx * S.ny * S.nz;
-    for (int c = 0; c < S.nz; ++c)
-        for (int b = 0; b < S.ny; ++b)
-            for (int a = 0; a < S.nx; ++a) {
-                long long t = S.tx[a] + (long long)A.g.ntx * (S.ty[b] + (long long)A.g.nty * S.tz[c]);
-                atomicAdd(&hist[t], 1);
-            }
+    const int n = S.nx * S.ny * S.nz;
+    if (lane == 0) A.t.vcount[k] = n;
+    for (int l = lane; l < n; l += 64) atomicAdd(&hist[tile_of(A, S, l)], 1);
 }
 
 // counting-sort scatter of particle k's (pid, emission) entries; `fill` counts per tile
-__device__ inline void reg_scatter(const VoxArgs& A, int k, int* fill) {
+__device__ inline void reg_scatter_wave(const VoxArgs& A, int k, int lane, int* fill) {
     TileSet S;
     particle_tiles(A, k, S);
-    int e = A.t.voff[k];
+    const int n = S.nx * S.ny * S.nz;
+    const int e0 = A.t.voff[k];
     bool full = false;
-    for (int c = 0; c < S.nz; ++c)
-        for (int b = 0; b < S.ny; ++b)
-            for (int a = 0; a < S.nx; ++a) {
-                long long t = S.tx[a] + (long long)A.g.ntx * (S.ty[b] + (long long)A.g.nty * S.tz[c]);
-                int slot = atomicAdd(&fill[t], 1);
-                long long at = (long long)A.t.tile_start[t] + slot;
-                if (at < A.t.cap && e < A.t.cap)
-                    A.t.tile_list[at] = ((unsigned long long)k << 32) | (unsigned)e;
-                else
-                    full = true;
-                ++e;
-            }
+    for (int l = lane; l < n; l += 64) {
+        const long long t = tile_of(A, S, l);
+        const int e = e0 + l;
+        const int slot = atomicAdd(&fill[t], 1);
+        const long long at = (long long)A.t.tile_start[t] + slot;
+        if (at < A.t.cap && e < A.t.cap)
+            A.t.tile_list[at] = ((unsigned long long)k << 32) | (unsigned)e;
+        else
+            full = true;
+    }
     if (full) atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_VREG);
 }
 
@@ -159,22 +162,30 @@ __device__ inline void reg_sort(const VoxArgs& A, long long t) {
     }
 }
 
+// one wave per particle; block 0 also clears the step's entry counters
 __global__ void k_vox_count(VoxArgs A) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        A.ctr->entries = 0;
+        A.ctr->dropped = 0;
+    }
+    const int k = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     if (k >= A.p.np) return;
-    reg_count(A, k, A.tile_count);
+    reg_count_wave(A, k, threadIdx.x & 63, A.tile_count);
 }
 
 __global__ void k_vox_scatter(VoxArgs A) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     if (k >= A.p.np) return;
-    reg_scatter(A, k, A.tile_fill);
+    reg_scatter_wave(A, k, threadIdx.x & 63, A.tile_fill);
 }
 
+// sorts each tile's list, then clears the tile's counters for the next step
 __global__ void k_tile_sort(VoxArgs A) {
     long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= A.g.ntiles) return;
     reg_sort(A, t);
+    A.tile_count[t] = 0;
+    A.tile_fill[t] = 0;
 }
 
 // Registration of one domain by one workgroup (serving batches): the tile
@@ -195,7 +206,7 @@ __global__ __launch_bounds__(VOX_RT) void k_vox_register_batch(const VoxArgs* __
     }
     for (int t = tid; t < nt; t += VOX_RT) hist_s[t] = 0;
     __syncthreads();
-    for (int k = tid; k < np; k += VOX_RT) reg_count(A, k, hist_s);
+    for (int k = tid >> 6; k < np; k += VOX_RT / 64) reg_count_wave(A, k, tid & 63, hist_s);
     __syncthreads();
     for (int t = tid; t < nt; t += VOX_RT) A.tile_count[t] = hist_s[t];
     __syncthreads();
@@ -203,9 +214,12 @@ __global__ __launch_bounds__(VOX_RT) void k_vox_register_batch(const VoxArgs* __
     psm_block_scan<VOX_RT>(A.tile_count, A.t.tile_start, nt);
     for (int t = tid; t < nt; t += VOX_RT) hist_s[t] = 0;
     __syncthreads();
-    for (int k = tid; k < np; k += VOX_RT) reg_scatter(A, k, hist_s);
+    for (int k = tid >> 6; k < np; k += VOX_RT / 64) reg_scatter_wave(A, k, tid & 63, hist_s);
     __syncthreads();
-    for (int t = tid; t < nt; t += VOX_RT) reg_sort(A, t);
+    for (int t = tid; t < nt; t += VOX_RT) {
+        reg_sort(A, t);
+        A.tile_count[t] = 0;  // left cleared, as the multi-launch path leaves it
+    }
 }
 
 // per-particle data staged in LDS for a tile
@@ -651,24 +665,58 @@ __global__ __launch_bounds__(VOX_T) void k_voxelize_batch(const VoxArgs* __restr
     voxelize_tile<C>(jobs[m.x], m.y);
 }
 
+// one wave per particle: lanes fetch the particle's partials, lane 0 sums them
+// in emission order (the order of psm_reduce_hydro)
 __global__ void k_reduce_hydro(VoxArgs A) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
     if (k >= A.p.np) return;
-    psm_reduce_hydro(A.t, A.p, k);
+    const int e0 = A.t.voff[k], e1 = A.t.voff[k + 1];
+    double F[3] = {0.0, 0.0, 0.0}, M[3] = {0.0, 0.0, 0.0};
+    for (int b = e0; b < e1 && b < A.t.cap; b += 64) {
+        const int e = b + lane;
+        double P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        bool ok = false;
+        if (e < e1 && e < A.t.cap) {
+            const long long s = A.t.vinv[e];
+            ok = s >= 0 && s < A.t.cap;
+            if (ok)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) P[c] = A.t.partial[6 * s + c];
+        }
+        const unsigned long long okm = __ballot(ok);
+        const int m = (e1 - b < 64 ? e1 - b : 64);
+        for (int j = 0; j < m; ++j) {
+            double v[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) v[c] = __shfl(P[c], j, 64);
+            if ((okm >> j) & 1ull)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    F[c] -= v[c];
+                    M[c] -= v[3 + c];
+                }
+        }
+    }
+    if (lane == 0)
+        for (int c = 0; c < 3; ++c) {
+            A.p.fh[3 * k + c] = F[c];
+            A.p.mh[3 * k + c] = M[c];
+        }
 }
 
 inline unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
 
 }  // namespace
 
+// the tile counters start at zero (creation) and are cleared again by k_tile_sort
 hipError_t vox_register(const VoxArgs& A, int* scan_tmp, hipStream_t s) {
     hipError_t e;
-    if ((e = psm_fill_int(A.tile_count, 0, A.g.ntiles, s)) != hipSuccess) return e;
-    if ((e = psm_fill_int(A.tile_fill, 0, A.g.ntiles, s)) != hipSuccess) return e;
-    if (A.p.np > 0) k_vox_count<<<nblk(A.p.np), 256, 0, s>>>(A);
+    const unsigned nbw = nblk(64LL * (A.p.np > 0 ? A.p.np : 1));
+    k_vox_count<<<nbw, 256, 0, s>>>(A);
     if ((e = psm_scan(A.t.vcount, A.t.voff, A.p.np, scan_tmp, s)) != hipSuccess) return e;
     if ((e = psm_scan(A.tile_count, A.t.tile_start, A.g.ntiles, scan_tmp, s)) != hipSuccess) return e;
-    if (A.p.np > 0) k_vox_scatter<<<nblk(A.p.np), 256, 0, s>>>(A);
+    if (A.p.np > 0) k_vox_scatter<<<nbw, 256, 0, s>>>(A);
     k_tile_sort<<<nblk(A.g.ntiles), 256, 0, s>>>(A);
     return hipGetLastError();
 }
@@ -696,6 +744,6 @@ hipError_t vox_voxelize_batch(const VoxArgs* jobs, const int2* map, long long nm
 
 hipError_t vox_reduce_hydro(const VoxArgs& A, hipStream_t s) {
     if (A.p.np == 0) return hipSuccess;
-    k_reduce_hydro<<<nblk(A.p.np), 256, 0, s>>>(A);
+    k_reduce_hydro<<<nblk(64LL * A.p.np), 256, 0, s>>>(A);
     return hipGetLastError();
 }
