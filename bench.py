@@ -33,7 +33,9 @@ def parse():
     p.add_argument("--steps", type=int, default=200)
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--precision", default="fp32", choices=list(STORAGE_BYTES))
-    p.add_argument("--n", type=int, default=128, help="lattice edge of the Couette workload")
+    p.add_argument("--workload", default="couette", choices=["couette", "kolmogorov"],
+                   help="couette: spheres in bounded shear; kolmogorov: prolate ellipsoids in a forced periodic box")
+    p.add_argument("--n", type=int, default=128, help="lattice edge of the workload")
     p.add_argument("--spheres", type=int, default=500)
     p.add_argument("--cpu-sample-steps", type=int, default=20,
                    help="coupled steps of the CPU oracle sample (0: skip the CPU baseline)")
@@ -43,10 +45,14 @@ def parse():
     p.add_argument("--serve-steps", type=int, default=100, help="coupled steps per served job")
     p.add_argument("--serve-rate", type=float, default=50.0, help="mean arrival rate of served jobs (1/s)")
     p.add_argument("--serve-slots", type=int, default=32, help="active slots of the server")
+    p.add_argument("--serve-budget-gb", type=float, default=16.0, help="HBM budget of the held jobs (GiB)")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only run 20 plain device copies of MIB MiB (calibrates the HBM byte counters)")
     p.add_argument("--lbm-sweep", type=int, default=0, metavar="N",
                    help="only time the LBM pass of a periodic fluid-only N^3 lattice in every precision")
+    p.add_argument("--precision-study", type=int, default=0, metavar="N",
+                   help="only run the Kolmogorov-ellipsoid N^3 workload in FP64, FP32, BF16 and FP16 from the same "
+                        "start: coupled-step speed and the errors of each against the FP64 run at step 200")
     p.add_argument("--summarize", nargs="+", metavar="DIR",
                    help="print a per-kernel summary of rocprofv3 CSV output (no GPU): DIR of a --kernel-trace "
                         "--stats run, or four DIRs of --pmc runs: FETCH_SIZE, WRITE_SIZE, and the same two "
@@ -151,6 +157,61 @@ def lbm_sweep(n):
         D.close()
 
 
+def _rel_l2(a, b):
+    import numpy as np
+    nb = float(np.linalg.norm(b))
+    return float(np.linalg.norm(a - b)) / nb if nb > 0 else float(np.linalg.norm(a - b))
+
+
+def _rel_inf(a, b, floor=0.0):
+    import numpy as np
+    return float(np.max(np.abs(a - b))) / max(float(np.max(np.abs(b))), floor)
+
+
+def precision_study(n, warmup=20, timed=100, check=200):
+    """Same particle set and start in every population precision; speed of the
+    coupled step and of the LBM pass, and the errors against the FP64 run."""
+    import torch
+    from paper_2512_04997_amd import psmdem, workloads
+    torch.cuda.set_device(0)
+    cfg, parts, meta = workloads.kolmogorov_ellipsoids(n=n)
+    N = n ** 3
+    ref = None
+    for prec in ("fp64", "fp32", "bf16", "fp16"):
+        D = psmdem.Domain(dict(cfg, precision=prec), parts)
+        D.step(warmup)
+        D.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        D.step(timed)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / timed
+        D.set_timing(True)
+        D.step(10)
+        D.set_timing(False)
+        lbm_ms, _ = D.timing("lbm")
+        D.step(check - warmup - timed - 10)
+        D.sync()
+        _, u = D.fields()
+        P = D.particles()
+        out = {"precision_study": prec, "workload": meta["workload"], "n_sub": D.info()["n_sub"],
+               "ms_per_step": round(dt * 1e3, 4), "mlups": round(N / dt / 1e6, 1), "lbm_ms": round(lbm_ms, 4),
+               "lbm_GBs": round(N * 2 * 19 * STORAGE_BYTES[prec] / (lbm_ms * 1e-3) / 1e9, 1), "step": check}
+        if ref is None:
+            ref = (u, P)
+            out["max_u"] = float(abs(u).max())
+        else:
+            u0, P0 = ref
+            out.update({"u_rel_l2": _rel_l2(u, u0), "u_rel_linf": _rel_inf(u, u0),
+                        "v_rel_linf": _rel_inf(P["vel"], P0["vel"], 1e-12),
+                        "omega_rel_linf": _rel_inf(P["omega"], P0["omega"], 1e-12),
+                        "f_hyd_rel_l2": _rel_l2(P["f_hyd"], P0["f_hyd"]),
+                        "m_hyd_rel_l2": _rel_l2(P["m_hyd"], P0["m_hyd"])})
+        print(json.dumps(out), flush=True)
+        D.close()
+        del u, P
+
+
 def copy_probe(mib):
     """Plain device-to-device copies of a known size: the reference that scales
     the FETCH_SIZE / WRITE_SIZE counters of the profiler into HBM bytes."""
@@ -169,11 +230,11 @@ def _pct(x, q):
     return float(np.percentile(np.asarray(x), q)) if len(x) else None
 
 
-def serve_batched(stream, slots, precision):
+def serve_batched(stream, slots, precision, budget_gb=16.0):
     """The job stream through the continuous-batching server: arrivals on the
     wall clock, a done job released at once.  Latency = done - arrival."""
     from paper_2512_04997_amd import psmdem
-    S = psmdem.Server(max_jobs=slots, hbm_budget=64 << 30, precision=precision)
+    S = psmdem.Server(max_jobs=slots, hbm_budget=int(budget_gb * 2 ** 30), precision=precision)
     t0 = psmdem.clock()
     ids = {}
     lat = []
@@ -228,12 +289,13 @@ def serving(a):
     lups = sum(c["n"][0] * c["n"][1] * c["n"][2] * st for _, c, _, st in stream)
     # warm both paths (code objects, allocator pools) on a short prefix
     warm = [(0.0, c, p, 2) for _, c, p, _ in stream[:4]]
-    serve_batched(warm, a.serve_slots, "fp32")
+    serve_batched(warm, a.serve_slots, "fp32", a.serve_budget_gb)
     serve_one_at_a_time(warm)
-    wb, lb = serve_batched(stream, a.serve_slots, "fp32")
+    wb, lb = serve_batched(stream, a.serve_slots, "fp32", a.serve_budget_gb)
     ws, ls = serve_one_at_a_time(stream)
     res = {"jobs": len(stream), "steps_per_job": a.serve_steps, "arrival_rate_per_s": a.serve_rate,
-           "slots": a.serve_slots, "lattices": "uniform over 32^3, 64^3, 96^3, 128^3",
+           "slots": a.serve_slots, "hbm_budget_gib": a.serve_budget_gb,
+           "lattices": "uniform over 32^3, 64^3, 96^3, 128^3",
            "lattice_updates": lups,
            "batched": {"mlups": round(lups / wb / 1e6, 1), "jobs_per_s": round(len(stream) / wb, 3),
                        "p50_s": round(_pct(lb, 50), 4), "p99_s": round(_pct(lb, 99), 4), "wall_s": round(wb, 3)},
@@ -278,11 +340,17 @@ def main():
     if a.lbm_sweep:
         lbm_sweep(a.lbm_sweep)
         return
+    if a.precision_study:
+        precision_study(a.precision_study)
+        return
     from paper_2512_04997_amd import psmdem, workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    cfg, parts, meta = workloads.couette_suspension(precision=a.precision, n=a.n, nsph=a.spheres)
+    if a.workload == "couette":
+        cfg, parts, meta = workloads.couette_suspension(precision=a.precision, n=a.n, nsph=a.spheres)
+    else:
+        cfg, parts, meta = workloads.kolmogorov_ellipsoids(n=a.n, precision=a.precision)
     N = a.n ** 3
     stream = torch.cuda.current_stream()
     D = psmdem.Domain(cfg, parts, stream=stream)
@@ -318,7 +386,8 @@ def main():
         alg_bytes = N * 2 * 19 * sb
         achieved = alg_bytes / (lbm_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(a.precision, a.n, a.spheres),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": (measured_traffic(a.precision, a.n, a.spheres)
+                                                                    if a.workload == "couette" else None),
                 "kernel": "LBM collide-stream pass (k_lbm fluid-tile + PSM-tile kernels of one step)",
                 "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": round(lbm_ms, 5)}
         print(f"[bench] per step: lbm {lbm_ms:.4f} ms, voxel {vox_ms:.4f} ms, hydro {hyd_ms:.4f} ms, "

@@ -92,6 +92,7 @@ struct DevCounters {
     unsigned long long entries;
     unsigned long long dropped;
     unsigned long long contacts;
+    unsigned long long items;     // boundary cells queued for sampling this step
 };
 
 // ---------------------------------------------------------------------------

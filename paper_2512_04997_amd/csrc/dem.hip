@@ -862,8 +862,129 @@ __global__ void k_cellsort(DemArgs A) {
         A.cell_fill[c] = 0;
     }
 }
-__global__ void k_paircount(DemArgs A) { GRID_LOOP(i, A.p.np) ph_paircount<false>(A, (int)i); }
-__global__ void k_pairemit(DemArgs A, PairBufs B) { GRID_LOOP(i, A.p.np) ph_pairemit<false>(A, B, (int)i); }
+// Candidate rows through the cell lists, one wave per particle i: the entries
+// of i's registration cells are flattened over the lanes; a lane keeps
+// partner j when j > i and the cell is the lowest the two share (each pair
+// once).  Emission ranks the kept partners by j (ascending row), then the
+// walls follow.
+struct WaveCells {
+    int start[8], size[8];   // list range of each registration cell (x bit 0, y bit 1, z bit 2)
+    int total;
+};
+
+__device__ inline void wave_cells(const DemArgs& A, const AxCells& ri, WaveCells& W) {
+    W.total = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int xq = q & 1, yq = (q >> 1) & 1, zq = q >> 2;
+        int s0 = 0, n = 0;
+        if (xq < ri.n[0] && yq < ri.n[1] && zq < ri.n[2]) {
+            const long long c = cell_id(A, xq ? ri.c[0][1] : ri.c[0][0], yq ? ri.c[1][1] : ri.c[1][0],
+                                        zq ? ri.c[2][1] : ri.c[2][0]);
+            s0 = A.cell_start[c];
+            n = A.cell_start[c + 1] - s0;
+        }
+        W.start[q] = s0;
+        W.size[q] = n;
+        W.total += n;
+    }
+}
+
+// flat candidate f of i: partner j, or -1 when not kept
+__device__ inline int wave_candidate(const DemArgs& A, int i, const AxCells& ri, const WaveCells& W, int f) {
+    int q = 0, o = f;
+#pragma unroll
+    for (int u = 0; u < 7; ++u)
+        if (q == u && o >= W.size[u]) {
+            o -= W.size[u];
+            q = u + 1;
+        }
+    int st = W.start[0];
+#pragma unroll
+    for (int u = 1; u < 8; ++u) st = q == u ? W.start[u] : st;
+    const long long at = (long long)st + o;
+    if (at >= A.reg_cap) return -1;
+    const int j = A.cell_pid[at];
+    if (j <= i) return -1;
+    AxCells rj;
+    load_cells(A, j, rj);
+    // the cell's coordinates by selects (no indexing of register arrays)
+    const int cx = (q & 1) ? ri.c[0][1] : ri.c[0][0];
+    const int cy = (q & 2) ? ri.c[1][1] : ri.c[1][0];
+    const int cz = (q & 4) ? ri.c[2][1] : ri.c[2][0];
+    if (axis_common(ri, rj, 0) != cx || axis_common(ri, rj, 1) != cy || axis_common(ri, rj, 2) != cz) return -1;
+    return j;
+}
+
+#define PAIR_KEPT_MAX 256
+
+__global__ __launch_bounds__(256) void k_paircount(DemArgs A) {
+    const int lane = threadIdx.x & 63;
+    const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
+    for (long long iw = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; iw < A.p.np; iw += nw) {
+        const int i = (int)iw;
+        AxCells ri;
+        load_cells(A, i, ri);
+        WaveCells W;
+        wave_cells(A, ri, W);
+        int n = 0;
+        for (int f0 = 0; f0 < W.total; f0 += 64) {
+            const int f = f0 + lane;
+            n += __popcll(__ballot(f < W.total && wave_candidate(A, i, ri, W, f) >= 0));
+        }
+        if (lane == 0) A.pcount[i] = n + wall_count(A, i);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pairemit(DemArgs A, PairBufs B) {
+    __shared__ int kept_s[4][PAIR_KEPT_MAX];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const unsigned long long lanes_below = (1ull << lane) - 1ull;
+    int* kept = kept_s[wid];
+    const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
+    for (long long iw = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; iw < A.p.np; iw += nw) {
+        const int i = (int)iw;
+        const long long at = B.prow[i];
+        const long long room = A.pair_cap - at;
+        if (lane == 0 && room < (long long)(B.prow[i + 1] - B.prow[i]))
+            atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_PAIRS);
+        if (room <= 0) continue;
+        unsigned long long* out = B.pairs + at;
+        AxCells ri;
+        load_cells(A, i, ri);
+        WaveCells W;
+        wave_cells(A, ri, W);
+        // kept partners gathered in wave-private LDS
+        int nk = 0;
+        for (int f0 = 0; f0 < W.total; f0 += 64) {
+            const int f = f0 + lane;
+            const int j = f < W.total ? wave_candidate(A, i, ri, W, f) : -1;
+            const unsigned long long m = __ballot(j >= 0);
+            const int pos = nk + __popcll(m & lanes_below);
+            if (j >= 0 && pos < PAIR_KEPT_MAX) kept[pos] = j;
+            nk += __popcll(m);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (nk <= PAIR_KEPT_MAX) {
+            // partners are distinct: a partner's place is the number below it
+            for (int e = lane; e < nk; e += 64) {
+                const int j = kept[e];
+                int below = 0;
+                for (int v = 0; v < nk; ++v) below += kept[v] < j ? 1 : 0;
+                if (below < room) out[below] = ((unsigned long long)i << 32) | (unsigned)j;
+            }
+            if (lane == 0) emit_walls(A, i, out, room, nk);
+        } else if (lane == 0) {
+            // very long rows: the serial emission with an in-place sort
+            ph_pairemit<false>(A, B, i);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
 template <bool ELL>
 __global__ __launch_bounds__(256) void k_contacts(DemArgs A, PairBufs B, const double* vv, const double* ww, double dth) {
     long long nprev = B.prev_n ? *B.prev_n : 0;
@@ -1262,9 +1383,9 @@ hipError_t dem_lists(const DemArgs& A, const PairBufs& B, int* scan_tmp, hipStre
     if ((e = psm_scan(A.cell_count, A.cell_start, A.ncell, scan_tmp, s)) != hipSuccess) return e;
     k_scatter<<<nblk(A.p.np), 256, 0, s>>>(A);
     k_cellsort<<<nblk(A.ncell), 256, 0, s>>>(A);
-    k_paircount<<<nblk(A.p.np, 128), 128, 0, s>>>(A);
+    k_paircount<<<nblk(64LL * A.p.np), 256, 0, s>>>(A);
     if ((e = psm_scan(A.pcount, B.prow, A.p.np, scan_tmp, s)) != hipSuccess) return e;
-    k_pairemit<<<nblk(A.p.np, 128), 128, 0, s>>>(A, B);
+    k_pairemit<<<nblk(64LL * A.p.np), 256, 0, s>>>(A, B);
     return hipGetLastError();
 }
 

@@ -54,6 +54,11 @@ struct psmdem_domain {
     TileArgs t{};
     int* tile_count = nullptr;
     int* tile_fill = nullptr;
+    unsigned short* lane_items = nullptr;
+    int* tile_items = nullptr;
+    int4* items = nullptr;
+    int* item_cnt = nullptr;
+    long long item_cap = 0;
     int* scan_tmp = nullptr;
     DevCounters* ctr = nullptr;
 
@@ -172,6 +177,11 @@ struct psmdem_domain {
         A.Rc = Rc;
         A.tau = d.tau;
         A.ms = d.max_solids;
+        A.lane_items = lane_items;
+        A.tile_items = tile_items;
+        A.items = items;
+        A.item_cnt = item_cnt;
+        A.item_cap = item_cap;
         A.ctr = ctr;
         return A;
     }

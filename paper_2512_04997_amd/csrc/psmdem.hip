@@ -414,6 +414,16 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
     t.partial = (double*)A(sizeof(double) * 6 * t.cap);
     D->tile_count = (int*)A(sizeof(int) * g.ntiles);
     D->tile_fill = (int*)A(sizeof(int) * g.ntiles);
+    // boundary cells sampled per step: about twice the shell of the largest
+    // bounding sphere per particle (more are sampled in place, slower)
+    if (np > 0 && d.sf_method == 0) {
+        D->item_cap = std::min<long long>((long long)np * (long long)ceil(8.0 * M_PI * (rbmax + 1.0) * (rbmax + 1.0)),
+                                          1LL << 30);
+        D->lane_items = (unsigned short*)A(sizeof(unsigned short) * 256 * g.ntiles);
+        D->tile_items = (int*)A(sizeof(int) * g.ntiles);
+        D->items = (int4*)A(sizeof(int4) * D->item_cap);
+        D->item_cnt = (int*)A(sizeof(int) * D->item_cap);
+    }
     long long scan_n = std::max<long long>(std::max<long long>(D->ncell, g.ntiles), np + 1);
     D->scan_tmp = (int*)A(sizeof(int) * psm_scan_tmp_ints(scan_n));
     D->ctr = (DevCounters*)A(sizeof(DevCounters));

@@ -15,6 +15,12 @@ struct VoxArgs {
     double Rc;           // (3 / (4 pi))^(1/3)
     double tau;
     int ms;              // solids kept per cell
+    // boundary cells of the step (three-kernel form)
+    unsigned short* lane_items;  // [ntiles * 256] boundary cells per lane
+    int* tile_items;             // [ntiles] first item of the tile
+    int4* items;                 // [item_cap] (X, Y, Z, pid), unwrapped cell indices
+    int* item_cnt;               // [item_cap] inside samples
+    long long item_cap;          // items beyond it are sampled in the select kernel
     DevCounters* ctr;
 };
 

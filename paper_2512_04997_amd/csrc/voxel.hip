@@ -9,9 +9,14 @@
 //   (scans)        emission offsets per particle, list offsets per tile
 //   k_vox_scatter  counting-sort scatter of (pid, emission index) into tiles
 //   k_tile_sort    order each tile's list by pid; inverse map emission -> position
-//   k_voxelize     one workgroup per tile: beta of every (cell, particle), keep the
-//                  max_solids largest (ties to the smaller pid), B_k, slots
+//   k_vox_classify per tile: cells whose samples straddle a surface, queued as
+//                  items of the step (exact inside / outside shortcuts elsewhere)
+//   k_vox_sample   one wave per queued cell: its count of inside samples
+//   k_vox_select   per tile: beta of every (cell, particle), keep the max_solids
+//                  largest (ties to the smaller pid), B_k, slots
 //   k_reduce_hydro per particle: minus the sum of its tile partials (F, M)
+// Serving batches run classify, sample and select of a tile in one workgroup
+// (k_voxelize_batch); both forms count the same samples.
 #include <math.h>
 
 #include "common.h"
@@ -167,6 +172,7 @@ __global__ void k_vox_count(VoxArgs A) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         A.ctr->entries = 0;
         A.ctr->dropped = 0;
+        A.ctr->items = 0;
     }
     const int k = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     if (k >= A.p.np) return;
@@ -373,28 +379,14 @@ __device__ inline void top_by_pid(Top4& T) {
     }
 }
 
-template <typename C>
-__device__ void voxelize_tile(const VoxArgs& A, const long long t) {
-    __shared__ VoxPart sp[PSM_PMAX];
-    __shared__ double off[32];
-    __shared__ unsigned qitem[VOX_QCAP];
-    __shared__ int qcnt[VOX_QCAP];
-    __shared__ int tcnt[VOX_T];
-    __shared__ double tab_s[(VOX_T / 64) * 9 * 32];
-    __shared__ unsigned long long cnt_e, cnt_d;
-    long long s0 = A.t.tile_start[t], s1 = A.t.tile_start[t + 1];
-    if (s1 > A.t.cap) s1 = A.t.cap;
-    const int count = (int)(s1 - s0) < PSM_PMAX ? (int)(s1 - s0) : PSM_PMAX;
-    if (count <= 0) return;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int tx = (int)(t % A.g.ntx), ty = (int)((t / A.g.ntx) % A.g.nty), tz = (int)(t / ((long long)A.g.ntx * A.g.nty));
-    const long long base = t * (long long)PSM_TILE;
-    const int ms = A.ms, ns = A.ns, n3 = ns * ns * ns;
-    const bool subdiv = A.sf_method == 0;
-    C* Bout = (C*)A.t.slot_B;
-    const long long plane = A.g.ntiles * (long long)PSM_TILE;
-    if (tid == 0) { cnt_e = 0; cnt_d = 0; }
-    if (tid < ns) off[tid] = (double)(2 * tid + 1) / (double)(2 * ns);
+// ---------------------------------------------------------------------------
+// pieces of the per-tile voxelisation, shared by the one-kernel form (serving
+// batches) and the three-kernel form (classify / sample / select)
+// ---------------------------------------------------------------------------
+// the tile's registered particles staged in LDS, and the sample offsets
+__device__ inline void stage_particles(const VoxArgs& A, VoxPart* sp, double* off, long long s0, int count) {
+    const int tid = threadIdx.x;
+    if (tid < A.ns) off[tid] = (double)(2 * tid + 1) / (double)(2 * A.ns);
     for (int u = tid; u < count; u += VOX_T) {
         int k = (int)(A.t.tile_list[s0 + u] >> 32);
         if (k >= A.p.np) k = 0;
@@ -410,39 +402,49 @@ __device__ void voxelize_tile(const VoxArgs& A, const long long t) {
         half_extents(A, k, P.e);
         lattice_box(A, k, P.lo, P.hi);
     }
-    __syncthreads();
-    const int x = tx * PSM_TX + lane, y = ty * PSM_TY + wid;
-    const bool xy_ok = x < A.g.nx && y < A.g.ny;
-    // candidates of this lane's (x, y) column: bit u set when particle u's
-    // lattice box holds x and y (ascending u = ascending pid)
-    unsigned long long cm0 = 0, cm1 = 0;
-    if (xy_ok)
-        for (int u = 0; u < count; ++u) {
-            int X, Y;
-            if (in_box(sp[u], x, A.g.nx, 0, A.g.periodic[0], &X) && in_box(sp[u], y, A.g.ny, 1, A.g.periodic[1], &Y)) {
-                if (u < 64) cm0 |= 1ull << u;
-                else cm1 |= 1ull << (u - 64);
-            }
-        }
+}
 
-    // phase A: number of (cell, particle) items that need samples, per lane
-    int mine = 0;
-    if (subdiv)
-        for (int lz = 0; lz < PSM_TZ; ++lz) {
-            const int z = tz * PSM_TZ + lz;
-            if (z >= A.g.nz) break;
-            for (int w = 0; w < 2; ++w)
-                for (unsigned long long bits = w ? cm1 : cm0; bits; bits &= bits - 1) {
-                    const int u = 64 * w + __ffsll((long long)bits) - 1;
-                    int X, Y, Z;
-                    const VoxPart& P = sp[u];
-                    in_box(P, x, A.g.nx, 0, A.g.periodic[0], &X);
-                    in_box(P, y, A.g.ny, 1, A.g.periodic[1], &Y);
-                    if (!in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z)) continue;
-                    mine += classify(P, X, Y, Z) == 2;
-                }
+// candidates of a lane's (x, y) column: bit u set when particle u's lattice box
+// holds x and y (ascending u = ascending pid)
+__device__ inline void column_masks(const VoxArgs& A, const VoxPart* sp, int count, int x, int y, bool xy_ok,
+                                    unsigned long long& cm0, unsigned long long& cm1) {
+    cm0 = cm1 = 0;
+    if (!xy_ok) return;
+    for (int u = 0; u < count; ++u) {
+        int X, Y;
+        if (in_box(sp[u], x, A.g.nx, 0, A.g.periodic[0], &X) && in_box(sp[u], y, A.g.ny, 1, A.g.periodic[1], &Y)) {
+            if (u < 64) cm0 |= 1ull << u;
+            else cm1 |= 1ull << (u - 64);
         }
-    // exclusive prefix of the per-lane item counts over the workgroup
+    }
+}
+
+// Visits the lane's (plane, candidate) pairs whose cell lies in the particle's
+// box, in the order planes ascending, then pid ascending:
+// f(lz, u, P, X, Y, Z) returns false to stop.
+template <typename F>
+__device__ inline void for_each_pair(const VoxArgs& A, const VoxPart* sp, int tz, int x, int y, bool xy_ok,
+                                     unsigned long long cm0, unsigned long long cm1, F f) {
+    if (!xy_ok) return;
+    for (int lz = 0; lz < PSM_TZ; ++lz) {
+        const int z = tz * PSM_TZ + lz;
+        if (z >= A.g.nz) break;
+        for (int w = 0; w < 2; ++w)
+            for (unsigned long long bits = w ? cm1 : cm0; bits; bits &= bits - 1) {
+                const int u = 64 * w + __ffsll((long long)bits) - 1;
+                const VoxPart& P = sp[u];
+                int X, Y, Z;
+                in_box(P, x, A.g.nx, 0, A.g.periodic[0], &X);
+                in_box(P, y, A.g.ny, 1, A.g.periodic[1], &Y);
+                if (!in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z)) continue;
+                if (!f(lz, u, P, X, Y, Z)) return;
+            }
+    }
+}
+
+// exclusive prefix of the per-lane counts over the workgroup, and the total
+__device__ inline void block_offsets(int mine, int* tcnt, int& my_off, int& total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     int incl = mine;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -451,129 +453,114 @@ __device__ void voxelize_tile(const VoxArgs& A, const long long t) {
     }
     if (lane == 63) tcnt[wid] = incl;
     __syncthreads();
-    int my_off = incl - mine, total = 0;
+    my_off = incl - mine;
+    total = 0;
     for (int w = 0; w < VOX_T / 64; ++w) {
         const int c = tcnt[w];
         if (w < wid) my_off += c;
         total += c;
     }
-    // queue the items (lane order, then plane, then particle)
-    if (mine) {
-        int j = my_off;
-        for (int lz = 0; lz < PSM_TZ && j < VOX_QCAP; ++lz) {
-            const int z = tz * PSM_TZ + lz;
-            if (z >= A.g.nz) break;
-            const unsigned l = lane + PSM_TX * (wid + PSM_TY * lz);
-            for (int w = 0; w < 2; ++w)
-                for (unsigned long long bits = w ? cm1 : cm0; bits && j < VOX_QCAP; bits &= bits - 1) {
-                    const int u = 64 * w + __ffsll((long long)bits) - 1;
-                    int X, Y, Z;
-                    const VoxPart& P = sp[u];
-                    in_box(P, x, A.g.nx, 0, A.g.periodic[0], &X);
-                    in_box(P, y, A.g.ny, 1, A.g.periodic[1], &Y);
-                    if (!in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z)) continue;
-                    if (classify(P, X, Y, Z) == 2) qitem[j++] = (l << 8) | (unsigned)u;
-                }
-        }
-    }
     __syncthreads();
-    // phase B: each wave counts the inside samples of one item at a time.  The
-    // per-axis terms of the sample test are formed once per item in wave-private
-    // LDS with the same rounding as the definition (squared offsets for spheres,
-    // rotated components for ellipsoids); then each lane takes one row (b, c) of
-    // samples and walks its ns samples along x with the x terms read as LDS
-    // broadcasts, so the inner loop is register arithmetic only.  The count is
-    // the sum of exact per-row counts.
-    const int nq = total < VOX_QCAP ? total : VOX_QCAP;
-    double* tab = tab_s + wid * (9 * 32);
-    const int nrows = ns * ns;
-    for (int it = wid; it < nq; it += VOX_T / 64) {
-        const unsigned item = qitem[it];
-        const int u = (int)(item & 0xffu), l = (int)(item >> 8);
-        const int cx = tx * PSM_TX + (l % PSM_TX), cy = ty * PSM_TY + (l / PSM_TX) % PSM_TY;
-        const int cz = tz * PSM_TZ + l / (PSM_TX * PSM_TY);
-        const VoxPart& P = sp[u];
-        int X, Y, Z;
-        in_box(P, cx, A.g.nx, 0, A.g.periodic[0], &X);
-        in_box(P, cy, A.g.ny, 1, A.g.periodic[1], &Y);
-        in_box(P, cz, A.g.nz, 2, A.g.periodic[2], &Z);
-        const bool sph = P.shape == 0;
-        if (lane < ns) {
-            const double dx = ((double)X + off[lane]) - P.c[0];
-            const double dy = ((double)Y + off[lane]) - P.c[1];
-            const double dz = ((double)Z + off[lane]) - P.c[2];
-            if (sph) {
-                tab[lane] = dx * dx;
-                tab[ns + lane] = dy * dy;
-                tab[2 * ns + lane] = dz * dz;
-            } else {
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    tab[(3 * k + 0) * ns + lane] = P.R[0 + k] * dx;
-                    tab[(3 * k + 1) * ns + lane] = P.R[3 + k] * dy;
-                    tab[(3 * k + 2) * ns + lane] = P.R[6 + k] * dz;
-                }
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        int cnt = 0;
-        if (sph && ns <= VOX_NS_REG) {
-            // x terms in registers (LDS broadcasts, once per item)
-            const double R2 = P.ax[0] * P.ax[0];
-            double x2[VOX_NS_REG];
-#pragma unroll
-            for (int a = 0; a < VOX_NS_REG; ++a) x2[a] = a < ns ? tab[a] : 0.0;
-            for (int r0 = 0; r0 < nrows; r0 += 64) {
-                const int r = r0 + lane;
-                const bool act = r < nrows;
-                const int b = act ? r % ns : 0, c = act ? r / ns : 0;
-                const double y2 = tab[ns + b], z2 = tab[2 * ns + c];
-                int rc = 0;
-#pragma unroll
-                for (int a = 0; a < VOX_NS_REG; ++a) rc += (a < ns && ((x2[a] + y2) + z2) < R2) ? 1 : 0;
-                cnt += act ? rc : 0;
-            }
-        } else if (sph) {
-            const double R2 = P.ax[0] * P.ax[0];
-            for (int r0 = 0; r0 < nrows; r0 += 64) {
-                const int r = r0 + lane;
-                const bool act = r < nrows;
-                const int b = act ? r % ns : 0, c = act ? r / ns : 0;
-                const double y2 = tab[ns + b], z2 = tab[2 * ns + c];
-                int rc = 0;
-                for (int a = 0; a < ns; ++a) rc += ((tab[a] + y2) + z2) < R2 ? 1 : 0;
-                cnt += act ? rc : 0;
-            }
+}
+
+// Inside samples of cell (X, Y, Z) for particle P, counted by one wave.  The
+// per-axis terms of the sample test are formed once in wave-private LDS (tab)
+// with the same rounding as the definition: squared offsets for spheres,
+// rotated components for ellipsoids; then each lane takes one row (b, c) of
+// samples and walks its ns samples along x.  The count is the sum of exact
+// per-row counts.  Every lane of the wave calls it; all get the count.
+__device__ inline int sample_count(const VoxPart& P, int X, int Y, int Z, const double* off, int ns, double* tab) {
+    const int lane = threadIdx.x & 63;
+    const bool sph = P.shape == 0;
+    if (lane < ns) {
+        const double dx = ((double)X + off[lane]) - P.c[0];
+        const double dy = ((double)Y + off[lane]) - P.c[1];
+        const double dz = ((double)Z + off[lane]) - P.c[2];
+        if (sph) {
+            tab[lane] = dx * dx;
+            tab[ns + lane] = dy * dy;
+            tab[2 * ns + lane] = dz * dz;
         } else {
-            const double i0 = P.inv[0], i1 = P.inv[1], i2 = P.inv[2];
-            for (int r0 = 0; r0 < nrows; r0 += 64) {
-                const int r = r0 + lane;
-                const bool act = r < nrows;
-                const int b = act ? r % ns : 0, c = act ? r / ns : 0;
-                const double y0 = tab[ns + b], z0 = tab[2 * ns + c];
-                const double y1 = tab[4 * ns + b], z1 = tab[5 * ns + c];
-                const double y2 = tab[7 * ns + b], z2 = tab[8 * ns + c];
-                int rc = 0;
-                for (int a = 0; a < ns; ++a) {
-                    const double p0 = (tab[a] + y0) + z0;
-                    const double p1 = (tab[3 * ns + a] + y1) + z1;
-                    const double p2 = (tab[6 * ns + a] + y2) + z2;
-                    rc += (((p0 * p0) * i0 + (p1 * p1) * i1) + (p2 * p2) * i2) < 1.0 ? 1 : 0;
-                }
-                cnt += act ? rc : 0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                tab[(3 * k + 0) * ns + lane] = P.R[0 + k] * dx;
+                tab[(3 * k + 1) * ns + lane] = P.R[3 + k] * dy;
+                tab[(3 * k + 2) * ns + lane] = P.R[6 + k] * dz;
             }
         }
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
-        if (lane == 0) qcnt[it] = cnt;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    __syncthreads();
-    // phase C: beta per (cell, particle) in pid order, keep the largest
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int nrows = ns * ns;
+    int cnt = 0;
+    if (sph && ns <= VOX_NS_REG) {
+        // x terms in registers (LDS broadcasts, once per item)
+        const double R2 = P.ax[0] * P.ax[0];
+        double x2[VOX_NS_REG];
+#pragma unroll
+        for (int a = 0; a < VOX_NS_REG; ++a) x2[a] = a < ns ? tab[a] : 0.0;
+        for (int r0 = 0; r0 < nrows; r0 += 64) {
+            const int r = r0 + lane;
+            const bool act = r < nrows;
+            const int b = act ? r % ns : 0, c = act ? r / ns : 0;
+            const double y2 = tab[ns + b], z2 = tab[2 * ns + c];
+            int rc = 0;
+#pragma unroll
+            for (int a = 0; a < VOX_NS_REG; ++a) rc += (a < ns && ((x2[a] + y2) + z2) < R2) ? 1 : 0;
+            cnt += act ? rc : 0;
+        }
+    } else if (sph) {
+        const double R2 = P.ax[0] * P.ax[0];
+        for (int r0 = 0; r0 < nrows; r0 += 64) {
+            const int r = r0 + lane;
+            const bool act = r < nrows;
+            const int b = act ? r % ns : 0, c = act ? r / ns : 0;
+            const double y2 = tab[ns + b], z2 = tab[2 * ns + c];
+            int rc = 0;
+            for (int a = 0; a < ns; ++a) rc += ((tab[a] + y2) + z2) < R2 ? 1 : 0;
+            cnt += act ? rc : 0;
+        }
+    } else {
+        const double i0 = P.inv[0], i1 = P.inv[1], i2 = P.inv[2];
+        for (int r0 = 0; r0 < nrows; r0 += 64) {
+            const int r = r0 + lane;
+            const bool act = r < nrows;
+            const int b = act ? r % ns : 0, c = act ? r / ns : 0;
+            const double y0 = tab[ns + b], z0 = tab[2 * ns + c];
+            const double y1 = tab[4 * ns + b], z1 = tab[5 * ns + c];
+            const double y2 = tab[7 * ns + b], z2 = tab[8 * ns + c];
+            int rc = 0;
+            for (int a = 0; a < ns; ++a) {
+                const double p0 = (tab[a] + y0) + z0;
+                const double p1 = (tab[3 * ns + a] + y1) + z1;
+                const double p2 = (tab[6 * ns + a] + y2) + z2;
+                rc += (((p0 * p0) * i0 + (p1 * p1) * i1) + (p2 * p2) * i2) < 1.0 ? 1 : 0;
+            }
+            cnt += act ? rc : 0;
+        }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return cnt;
+}
+
+// Phase C: beta per (cell, particle) in pid order, keep the largest ms, write
+// the slots.  Boundary cells take their count from lookup(j, P, X, Y, Z), j
+// running from my_off in the order of for_each_pair.
+template <typename C, typename L>
+__device__ inline void select_slots(const VoxArgs& A, const VoxPart* sp, long long t, int tz, int x, int y, bool xy_ok,
+                                    unsigned long long cm0, unsigned long long cm1, int my_off, L lookup,
+                                    unsigned long long* cnt_e, unsigned long long* cnt_d) {
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int ms = A.ms, n3 = A.ns * A.ns * A.ns;
+    const bool subdiv = A.sf_method == 0;
+    C* Bout = (C*)A.t.slot_B;
+    const long long plane = A.g.ntiles * (long long)PSM_TILE;
+    const long long base = t * (long long)PSM_TILE;
     unsigned long long my_e = 0, my_d = 0;
     int j = my_off;
     for (int lz = 0; lz < PSM_TZ; ++lz) {
@@ -598,13 +585,7 @@ __device__ void voxelize_tile(const VoxArgs& A, const long long t) {
                         if (cl == 1) {
                             beta = 1.0;
                         } else {
-                            int cnt;
-                            if (j < VOX_QCAP) {
-                                cnt = qcnt[j];
-                            } else {
-                                cnt = 0;
-                                for (int m = 0; m < n3; ++m) cnt += sample_in(P, X, Y, Z, off, ns, m);
-                            }
+                            const int cnt = lookup(j, P, X, Y, Z);
                             ++j;
                             beta = (double)cnt / (double)n3;
                         }
@@ -613,7 +594,7 @@ __device__ void voxelize_tile(const VoxArgs& A, const long long t) {
                     ++my_e;
                     keep_top(T, ms, beta, u, my_d);
                 }
-            }
+        }
         top_by_pid(T);
         unsigned int lp = 0xffffffffu;
         if (T.n > 0) lp = (lp & ~0xffu) | (unsigned)T.l0;
@@ -634,19 +615,219 @@ __device__ void voxelize_tile(const VoxArgs& A, const long long t) {
                 }
         }
     }
-    if (my_e) atomicAdd(&cnt_e, my_e);
-    if (my_d) atomicAdd(&cnt_d, my_d);
+    if (my_e) atomicAdd(cnt_e, my_e);
+    if (my_d) atomicAdd(cnt_d, my_d);
     __syncthreads();
     if (tid == 0) {
-        if (cnt_e) atomicAdd(&A.ctr->entries, cnt_e);
-        if (cnt_d) atomicAdd(&A.ctr->dropped, cnt_d);
+        if (*cnt_e) atomicAdd(&A.ctr->entries, *cnt_e);
+        if (*cnt_d) atomicAdd(&A.ctr->dropped, *cnt_d);
     }
 }
 
+struct TileRange {
+    long long s0;
+    int count;
+    int tx, ty, tz;
+};
+
+__device__ inline TileRange tile_range(const VoxArgs& A, long long t) {
+    TileRange r;
+    long long s0 = A.t.tile_start[t], s1 = A.t.tile_start[t + 1];
+    if (s1 > A.t.cap) s1 = A.t.cap;
+    r.s0 = s0;
+    r.count = (int)(s1 - s0) < PSM_PMAX ? (int)(s1 - s0) : PSM_PMAX;
+    r.tx = (int)(t % A.g.ntx);
+    r.ty = (int)((t / A.g.ntx) % A.g.nty);
+    r.tz = (int)(t / ((long long)A.g.ntx * A.g.nty));
+    return r;
+}
+
+// One tile in one workgroup (serving batches): classify, queue the boundary
+// cells in LDS, count their samples (one wave per item), select.
 template <typename C>
-__global__ __launch_bounds__(VOX_T) void k_voxelize(VoxArgs A) {
-    if ((long long)blockIdx.x >= A.g.ntiles) return;
-    voxelize_tile<C>(A, blockIdx.x);
+__device__ void voxelize_tile(const VoxArgs& A, const long long t) {
+    __shared__ VoxPart sp[PSM_PMAX];
+    __shared__ double off[32];
+    __shared__ unsigned qitem[VOX_QCAP];
+    __shared__ int qcnt[VOX_QCAP];
+    __shared__ int tcnt[VOX_T / 64];
+    __shared__ double tab_s[(VOX_T / 64) * 9 * 32];
+    __shared__ unsigned long long cnt_e, cnt_d;
+    const TileRange R = tile_range(A, t);
+    if (R.count <= 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int ns = A.ns, n3 = ns * ns * ns;
+    const bool subdiv = A.sf_method == 0;
+    if (tid == 0) { cnt_e = 0; cnt_d = 0; }
+    stage_particles(A, sp, off, R.s0, R.count);
+    __syncthreads();
+    const int x = R.tx * PSM_TX + lane, y = R.ty * PSM_TY + wid;
+    const bool xy_ok = x < A.g.nx && y < A.g.ny;
+    unsigned long long cm0, cm1;
+    column_masks(A, sp, R.count, x, y, xy_ok, cm0, cm1);
+    int mine = 0;
+    if (subdiv)
+        for_each_pair(A, sp, R.tz, x, y, xy_ok, cm0, cm1, [&](int, int, const VoxPart& P, int X, int Y, int Z) {
+            mine += classify(P, X, Y, Z) == 2;
+            return true;
+        });
+    int my_off, total;
+    block_offsets(mine, tcnt, my_off, total);
+    if (mine) {
+        int j = my_off;
+        for_each_pair(A, sp, R.tz, x, y, xy_ok, cm0, cm1, [&](int lz, int u, const VoxPart& P, int X, int Y, int Z) {
+            if (classify(P, X, Y, Z) == 2) {
+                const unsigned l = lane + PSM_TX * (wid + PSM_TY * lz);
+                qitem[j++] = (l << 8) | (unsigned)u;
+            }
+            return j < VOX_QCAP;
+        });
+    }
+    __syncthreads();
+    const int nq = total < VOX_QCAP ? total : VOX_QCAP;
+    double* tab = tab_s + wid * (9 * 32);
+    for (int it = wid; it < nq; it += VOX_T / 64) {
+        const unsigned item = qitem[it];
+        const int u = (int)(item & 0xffu), l = (int)(item >> 8);
+        const int cx = R.tx * PSM_TX + (l % PSM_TX), cy = R.ty * PSM_TY + (l / PSM_TX) % PSM_TY;
+        const int cz = R.tz * PSM_TZ + l / (PSM_TX * PSM_TY);
+        const VoxPart& P = sp[u];
+        int X, Y, Z;
+        in_box(P, cx, A.g.nx, 0, A.g.periodic[0], &X);
+        in_box(P, cy, A.g.ny, 1, A.g.periodic[1], &Y);
+        in_box(P, cz, A.g.nz, 2, A.g.periodic[2], &Z);
+        const int cnt = sample_count(P, X, Y, Z, off, ns, tab);
+        if (lane == 0) qcnt[it] = cnt;
+    }
+    __syncthreads();
+    select_slots<C>(A, sp, t, R.tz, x, y, xy_ok, cm0, cm1, my_off,
+                    [&](int j, const VoxPart& P, int X, int Y, int Z) {
+                        if (j < VOX_QCAP) return qcnt[j];
+                        int cnt = 0;
+                        for (int m = 0; m < n3; ++m) cnt += sample_in(P, X, Y, Z, off, ns, m);
+                        return cnt;
+                    },
+                    &cnt_e, &cnt_d);
+}
+
+// ---------------------------------------------------------------------------
+// three-kernel form: the sampling runs as its own launch over every boundary
+// cell of the step, balanced across the GPU
+// ---------------------------------------------------------------------------
+// 1. per tile: count the boundary cells per lane, reserve the tile's range of
+//    the step's item list, queue (X, Y, Z, pid) of each boundary cell
+__global__ __launch_bounds__(VOX_T) void k_vox_classify(VoxArgs A) {
+    __shared__ VoxPart sp[PSM_PMAX];
+    __shared__ double off[32];
+    __shared__ int tcnt[VOX_T / 64];
+    __shared__ int tile_base;
+    const long long t = blockIdx.x;
+    if (t >= A.g.ntiles) return;
+    const TileRange R = tile_range(A, t);
+    if (R.count <= 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    stage_particles(A, sp, off, R.s0, R.count);
+    __syncthreads();
+    const int x = R.tx * PSM_TX + lane, y = R.ty * PSM_TY + wid;
+    const bool xy_ok = x < A.g.nx && y < A.g.ny;
+    unsigned long long cm0, cm1;
+    column_masks(A, sp, R.count, x, y, xy_ok, cm0, cm1);
+    int mine = 0;
+    for_each_pair(A, sp, R.tz, x, y, xy_ok, cm0, cm1, [&](int, int, const VoxPart& P, int X, int Y, int Z) {
+        mine += classify(P, X, Y, Z) == 2;
+        return true;
+    });
+    A.lane_items[t * VOX_T + tid] = (unsigned short)mine;
+    int my_off, total;
+    block_offsets(mine, tcnt, my_off, total);
+    if (tid == 0) {
+        // the first item of the tile, clamped to the capacity (beyond it the
+        // select kernel samples in place)
+        const unsigned long long b = atomicAdd(&A.ctr->items, (unsigned long long)total);
+        tile_base = (int)(b < (unsigned long long)A.item_cap ? b : (unsigned long long)A.item_cap);
+        A.tile_items[t] = tile_base;
+    }
+    __syncthreads();
+    if (mine) {
+        long long j = (long long)tile_base + my_off;
+        for_each_pair(A, sp, R.tz, x, y, xy_ok, cm0, cm1, [&](int, int, const VoxPart& P, int X, int Y, int Z) {
+            if (classify(P, X, Y, Z) == 2) {
+                if (j < A.item_cap) A.items[j] = make_int4(X, Y, Z, P.pid);
+                ++j;
+            }
+            return j < A.item_cap;
+        });
+    }
+}
+
+// 2. every boundary cell of the step: one wave counts its inside samples
+__global__ __launch_bounds__(VOX_T) void k_vox_sample(VoxArgs A) {
+    __shared__ VoxPart pw[VOX_T / 64];
+    __shared__ double off[32];
+    __shared__ double tab_s[(VOX_T / 64) * 9 * 32];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (tid < A.ns) off[tid] = (double)(2 * tid + 1) / (double)(2 * A.ns);
+    __syncthreads();
+    long long n = (long long)A.ctr->items;
+    n = n < A.item_cap ? n : A.item_cap;
+    const long long nw = (long long)gridDim.x * (VOX_T / 64);
+    double* tab = tab_s + wid * (9 * 32);
+    VoxPart& P = pw[wid];
+    for (long long i = (long long)blockIdx.x * (VOX_T / 64) + wid; i < n; i += nw) {
+        const int4 it = A.items[i];
+        const int k = it.w < A.p.np ? it.w : 0;
+        if (lane == 0) {
+            P.pid = k;
+            P.shape = A.p.shape[k];
+            for (int a = 0; a < 3; ++a) {
+                P.c[a] = A.p.pos[3 * k + a];
+                P.ax[a] = A.p.semi[3 * k + a];
+                P.inv[a] = 1.0 / (P.ax[a] * P.ax[a]);
+            }
+            quat_rbw(A.p.q + 4 * k, P.R);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const int cnt = sample_count(P, it.x, it.y, it.z, off, A.ns, tab);
+        if (lane == 0) A.item_cnt[i] = cnt;
+    }
+}
+
+// 3. per tile: select the kept solids with the sampled counts
+template <typename C>
+__global__ __launch_bounds__(VOX_T) void k_vox_select(VoxArgs A) {
+    __shared__ VoxPart sp[PSM_PMAX];
+    __shared__ double off[32];
+    __shared__ int tcnt[VOX_T / 64];
+    __shared__ unsigned long long cnt_e, cnt_d;
+    const long long t = blockIdx.x;
+    if (t >= A.g.ntiles) return;
+    const TileRange R = tile_range(A, t);
+    if (R.count <= 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int ns = A.ns, n3 = ns * ns * ns;
+    const bool subdiv = A.sf_method == 0;
+    if (tid == 0) { cnt_e = 0; cnt_d = 0; }
+    stage_particles(A, sp, off, R.s0, R.count);
+    __syncthreads();
+    const int x = R.tx * PSM_TX + lane, y = R.ty * PSM_TY + wid;
+    const bool xy_ok = x < A.g.nx && y < A.g.ny;
+    unsigned long long cm0, cm1;
+    column_masks(A, sp, R.count, x, y, xy_ok, cm0, cm1);
+    const int mine = subdiv ? (int)A.lane_items[t * VOX_T + tid] : 0;
+    int my_off, total;
+    block_offsets(mine, tcnt, my_off, total);
+    const long long tb = subdiv ? (long long)A.tile_items[t] : 0;
+    select_slots<C>(A, sp, t, R.tz, x, y, xy_ok, cm0, cm1, my_off,
+                    [&](int j, const VoxPart& P, int X, int Y, int Z) {
+                        const long long g = tb + j;
+                        if (g < A.item_cap) return A.item_cnt[g];
+                        int cnt = 0;
+                        for (int m = 0; m < n3; ++m) cnt += sample_in(P, X, Y, Z, off, ns, m);
+                        return cnt;
+                    },
+                    &cnt_e, &cnt_d);
 }
 
 // consecutive blocks of the map stay on one XCD
@@ -722,8 +903,16 @@ hipError_t vox_register(const VoxArgs& A, int* scan_tmp, hipStream_t s) {
 }
 
 hipError_t vox_voxelize(const VoxArgs& A, int ctype_double, hipStream_t s) {
-    if (ctype_double) k_voxelize<double><<<(unsigned)A.g.ntiles, VOX_T, 0, s>>>(A);
-    else k_voxelize<float><<<(unsigned)A.g.ntiles, VOX_T, 0, s>>>(A);
+    const unsigned nt = (unsigned)A.g.ntiles;
+    if (A.sf_method == 0) {
+        k_vox_classify<<<nt, VOX_T, 0, s>>>(A);
+        // enough waves to fill the GPU; each walks the item list with a stride
+        long long nb = (A.item_cap + VOX_T / 64 - 1) / (VOX_T / 64);
+        nb = nb < 4096 ? nb : 4096;
+        k_vox_sample<<<(unsigned)(nb > 0 ? nb : 1), VOX_T, 0, s>>>(A);
+    }
+    if (ctype_double) k_vox_select<double><<<nt, VOX_T, 0, s>>>(A);
+    else k_vox_select<float><<<nt, VOX_T, 0, s>>>(A);
     return hipGetLastError();
 }
 

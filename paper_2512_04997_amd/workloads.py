@@ -75,68 +75,54 @@ def rsa_spheres(rng, n, radii, box, periodic, region_lo=None, region_hi=None, ga
 
     radii: (n,) array drawn beforehand; box: (3,) extents; periodic: 3 bools.
     Centres are uniform in [region_lo, region_hi] shrunk by radius + wall_gap on
-    walled axes.  Returns (m, 3) positions for the first m <= n spheres placed.
+    walled axes; a candidate is kept when its surface gap to every placed
+    sphere (minimum image on periodic axes) is at least `gap`.  Returns (m, 3)
+    positions for the first m <= n spheres placed.
     """
     box = np.asarray(box, dtype=np.float64)
     lo = np.zeros(3) if region_lo is None else np.asarray(region_lo, np.float64)
     hi = box.copy() if region_hi is None else np.asarray(region_hi, np.float64)
-    rmax = float(np.max(radii)) if len(radii) else 1.0
-    h = 2.0 * rmax + gap
-    ncell = np.maximum(1, np.floor(box / h).astype(int))
-    hcell = box / ncell
-    grid = {}
+    per = np.asarray(periodic, dtype=bool)
+    radii = np.asarray(radii, dtype=np.float64)
     pos = np.zeros((n, 3))
     placed = 0
     attempts = 0
     for k in range(n):
         r = float(radii[k])
+        l = lo.copy()
+        h = hi.copy()
+        for a in range(3):
+            if not per[a]:
+                l[a] = max(l[a], r + wall_gap)
+                h[a] = min(h[a], box[a] - r - wall_gap)
+        # candidates are drawn in batches and tested in draw order; the stream
+        # is then rewound to just after the accepted one (SplitMix64 is a
+        # counter), so the placements equal those of one draw at a time
         ok = False
         while attempts < max_attempts:
-            attempts += 1
-            u = rng.uniform(3)
-            c = np.empty(3)
-            for a in range(3):
-                l, hh = lo[a], hi[a]
-                if not periodic[a]:
-                    l = max(l, r + wall_gap)
-                    hh = min(hh, box[a] - r - wall_gap)
-                c[a] = l + (hh - l) * u[a]
-            ci = np.floor(c / hcell).astype(int)
-            clash = False
-            for dz in (-1, 0, 1):
-                for dy in (-1, 0, 1):
-                    for dx in (-1, 0, 1):
-                        key = [ci[0] + dx, ci[1] + dy, ci[2] + dz]
-                        skip = False
-                        for a in range(3):
-                            if periodic[a]:
-                                key[a] %= ncell[a]
-                            elif key[a] < 0 or key[a] >= ncell[a]:
-                                skip = True
-                        if skip:
-                            continue
-                        for j in grid.get(tuple(key), ()):
-                            d = c - pos[j]
-                            for a in range(3):
-                                if periodic[a]:
-                                    d[a] -= box[a] * round(d[a] / box[a])
-                            if np.dot(d, d) < (r + radii[j] + gap) ** 2:
-                                clash = True
-                                break
-                        if clash:
-                            break
-                    if clash:
-                        break
-                if clash:
-                    break
-            if not clash:
-                ok = True
-                break
+            nb = min(64, max_attempts - attempts)
+            st0 = rng.state
+            C = l[None, :] + (h - l)[None, :] * rng.uniform(3 * nb).reshape(nb, 3)
+            if placed:
+                d = C[:, None, :] - pos[None, :placed, :]
+                d = np.where(per[None, None, :], d - box[None, None, :] * np.round(d / box[None, None, :]), d)
+                dd = (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
+                clash = np.any(dd < ((r + radii[:placed] + gap) ** 2)[None, :], axis=1)
+            else:
+                clash = np.zeros(nb, dtype=bool)
+            free = np.flatnonzero(~clash)
+            if free.size == 0:
+                attempts += nb
+                continue
+            i = int(free[0])
+            attempts += i + 1
+            rng.state = (st0 + 3 * (i + 1) * _GOLDEN) & _MASK
+            c = C[i]
+            ok = True
+            break
         if not ok:
             break
         pos[k] = c
-        key = tuple(int(v) % int(m) for v, m in zip(np.floor(c / hcell).astype(int), ncell))
-        grid.setdefault(key, []).append(k)
         placed += 1
     return pos[:placed]
 
@@ -197,27 +183,28 @@ def couette_suspension(precision="fp32", n=128, nsph=500, radius=5.0, seed=1001,
     return cfg, parts, dict(workload=f"couette_{n}^3_{len(pos)}_spheres", steps=steps)
 
 
-def serving_job(rng, kind, n, tau, nsph, r_lo=3.0, r_hi=6.0, precision="fp32", max_fraction=0.15):
+def serving_job(rng, kind, n, tau, nsph, r_lo=3.0, r_hi=6.0, precision="fp32", max_fraction=0.3):
     """One ensemble job on an n^3 lattice.
 
-    kind 'settle': periodic x, y, no-slip walls in z, gravity (0, 0, -1e-5),
-    density ratio 2.  kind 'shear': periodic x, y, walls in z moving at -/+0.02
-    in x, density ratio 1.5.  nsph sphere radii uniform in [r_lo, r_hi], capped
-    so that the solid volume fraction stays below max_fraction; positions by
-    random sequential addition (fewer spheres when the box is full)."""
+    kind 'settle': no-slip walls on every face, gravity (0, 0, -1e-5) on the
+    particles, density ratio 2.  kind 'shear': periodic x and y, walls beyond
+    node layers 0 and n-1 moving at -/+0.02 in x, density ratio 1.5.  nsph
+    sphere radii uniform in [r_lo, r_hi], capped so that the solid volume
+    fraction stays at most max_fraction; positions by random sequential
+    addition (fewer spheres when the box fills up)."""
     radii = r_lo + (r_hi - r_lo) * rng.uniform(nsph) if nsph > 0 else np.zeros(0)
     vol = np.cumsum(4.0 / 3.0 * np.pi * radii ** 3)
     keep = int(np.searchsorted(vol, max_fraction * n ** 3, side="right"))
     radii = radii[:max(keep, 1 if nsph > 0 else 0)]
-    bc = ["periodic", "periodic", "periodic", "periodic", "noslip", "noslip"]
     wu = [[0.0] * 3 for _ in range(6)]
     if kind == "shear":
-        bc[4] = bc[5] = "moving"
+        bc = ["periodic", "periodic", "periodic", "periodic", "moving", "moving"]
         wu[4] = [-0.02, 0.0, 0.0]
         wu[5] = [0.02, 0.0, 0.0]
         cfg = base_config((n, n, n), tau, bc=bc, wall_u=wu, precision=precision)
         dens = 1.5
     else:
+        bc = ["noslip"] * 6
         cfg = base_config((n, n, n), tau, bc=bc, gravity=[0.0, 0.0, -1e-5], precision=precision)
         dens = 2.0
     pos = rsa_spheres(rng, len(radii), radii, (n, n, n), _periodic(bc), max_attempts=200 * max(len(radii), 1))
@@ -225,22 +212,92 @@ def serving_job(rng, kind, n, tau, nsph, r_lo=3.0, r_hi=6.0, precision="fp32", m
     return cfg, parts
 
 
-def serving_stream(njobs=512, rate=50.0, seed=2024, steps=1000, sizes=(32, 64, 96, 128), tau=(0.55, 0.9),
-                   nsph=(1, 500), r_lo=3.0, r_hi=6.0, precision="fp32"):
-    """A Poisson stream of independent settling / shear jobs: exponential gaps of
-    mean 1/rate seconds; per job a lattice edge drawn from `sizes`, tau uniform
-    in `tau`, a sphere count uniform in `nsph` (see serving_job for the cap),
-    and `steps` coupled steps.  Returns a list of (arrival_s, cfg, parts, steps)."""
-    rng = SplitMix64(seed)
+def serving_stream(njobs=512, rate=50.0, steps=1000, sizes=(32, 64, 96, 128), tau=(0.55, 0.9), nsph=(1, 500),
+                   r_lo=3.0, r_hi=6.0, precision="fp32", arrival_seed=4999, job_seed=5000):
+    """A Poisson stream of independent settling / shear jobs.
+
+    Arrivals: exponential gaps of mean 1/rate seconds from SplitMix64(arrival_seed).
+    Job i, from SplitMix64(job_seed + i): a lattice edge drawn from `sizes`, tau
+    uniform in `tau`, kind settle or shear with probability 1/2, a sphere count
+    uniform in `nsph` (capped as in serving_job) and `steps` coupled steps.
+    Returns a list of (arrival_s, cfg, parts, steps)."""
+    arr = SplitMix64(arrival_seed)
     out = []
     t = 0.0
     for k in range(njobs):
-        u = rng.uniform(5)
-        t += -math.log(1.0 - u[0]) / rate
-        n = int(sizes[min(int(u[1] * len(sizes)), len(sizes) - 1)])
-        ta = tau[0] + (tau[1] - tau[0]) * u[2]
+        t += -math.log(1.0 - arr.uniform()) / rate
+        rng = SplitMix64(job_seed + k)
+        u = rng.uniform(4)
+        n = int(sizes[min(int(u[0] * len(sizes)), len(sizes) - 1)])
+        ta = tau[0] + (tau[1] - tau[0]) * u[1]
+        kind = "settle" if u[2] < 0.5 else "shear"
         m = nsph[0] + min(int(u[3] * (nsph[1] - nsph[0] + 1)), nsph[1] - nsph[0])
-        kind = "settle" if u[4] < 0.5 else "shear"
         cfg, parts = serving_job(rng, kind, n, ta, m, r_lo, r_hi, precision)
         out.append((t, cfg, parts, steps))
     return out
+
+
+def rsa_equal_spheres_periodic(rng, n, r, box, gap=1.0, max_attempts=10_000_000, batch=64):
+    """Random sequential addition of n equal spheres of radius r in a periodic
+    box, accelerated by a uniform grid (cells of at least 2r + gap, so every
+    possible clash lies in the 27 surrounding cells).  Candidates are drawn in
+    batches, tested in draw order, and the stream is rewound to just after the
+    accepted one.  Returns (m, 3) positions for the first m <= n spheres."""
+    box = np.asarray(box, dtype=np.float64)
+    nc = np.maximum(1, np.floor(box / (2.0 * r + gap)).astype(np.int64))
+    hc = box / nc
+    K = 8
+    grid = -np.ones((int(nc[0]), int(nc[1]), int(nc[2]), K), dtype=np.int64)
+    gcnt = np.zeros((int(nc[0]), int(nc[1]), int(nc[2])), dtype=np.int64)
+    pos = np.zeros((n + 1, 3))
+    off = np.array([(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)])
+    lim = (2.0 * r + gap) ** 2
+    placed = 0
+    attempts = 0
+    while placed < n and attempts < max_attempts:
+        nb = min(batch, max_attempts - attempts)
+        st0 = rng.state
+        C = box[None, :] * rng.uniform(3 * nb).reshape(nb, 3)
+        ci = np.minimum(np.floor(C / hc[None, :]).astype(np.int64), nc[None, :] - 1)
+        nbr = (ci[:, None, :] + off[None, :, :]) % nc[None, None, :]
+        idx = grid[nbr[..., 0], nbr[..., 1], nbr[..., 2]].reshape(nb, -1)
+        P = pos[np.where(idx >= 0, idx, n)]
+        d = C[:, None, :] - P
+        d = d - box[None, None, :] * np.round(d / box[None, None, :])
+        dd = (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
+        clash = np.any((dd < lim) & (idx >= 0), axis=1)
+        free = np.flatnonzero(~clash)
+        if free.size == 0:
+            attempts += nb
+            continue
+        i = int(free[0])
+        attempts += i + 1
+        rng.state = (st0 + 3 * (i + 1) * _GOLDEN) & _MASK
+        c = ci[i]
+        if gcnt[c[0], c[1], c[2]] >= K:
+            raise RuntimeError("grid cell overflow in sphere placement")
+        grid[c[0], c[1], c[2], gcnt[c[0], c[1], c[2]]] = placed
+        gcnt[c[0], c[1], c[2]] += 1
+        pos[placed] = C[i]
+        placed += 1
+    return pos[:placed]
+
+
+def kolmogorov_ellipsoids(n=256, fraction=0.2, precision="fp32", seed=1003, amp=1e-6):
+    """Periodic n^3 lattice, tau = 0.55, Kolmogorov forcing of the fluid with
+    component x = amp sin(2 pi (y + 1/2) / n); prolate ellipsoids with
+    semi-axes (6, 3, 3), density ratio 1.2, uniform random orientations
+    (Shoemake), centres by random sequential addition of their bounding
+    spheres (radius 6, surface gap 1) up to a bounding-sphere volume fraction
+    `fraction`; linear contact law k_n = 1e3, e = 0.8, mu = 0.3."""
+    cfg = base_config((n, n, n), 0.55, kolm_amp=amp, kolm_axis=1, kolm_dir=0, precision=precision,
+                      kn=1e3, restitution=0.8, mu=0.3)
+    rng = SplitMix64(seed)
+    count = int(round(fraction * n ** 3 / (4.0 / 3.0 * math.pi * 6.0 ** 3)))
+    pos = rsa_equal_spheres_periodic(rng, count, 6.0, (n, n, n))
+    m = len(pos)
+    quat = shoemake_quaternions(rng, m)
+    parts = dict(shape=np.ones(m, np.int32), semi=np.tile([6.0, 3.0, 3.0], (m, 1)),
+                 dens=np.full(m, 1.2), pos=pos, quat=quat, vel=np.zeros((m, 3)), omega=np.zeros((m, 3)),
+                 fixed=np.zeros(m, np.uint8))
+    return cfg, parts, dict(workload=f"kolmogorov_{n}^3_{m}_ellipsoids", steps=200)
