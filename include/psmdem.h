@@ -233,7 +233,8 @@ psmdem_status psmdem_footprint(const psmdem_desc* desc, const psmdem_particles* 
  * The host runs at most max_inflight steps ahead of the device.  A job's
  * result is the one psmdem_step gives on the same domain, bit for bit: the
  * batched launches run the single-domain device code on each job's own data,
- * in the same order.  Jobs must have the fluid on, the server's precision, at
+ * in the same order (the voxelisation in a one-workgroup form that counts the
+ * same samples).  Jobs must have the fluid on, the server's precision, at
  * most 2048 particles when the DEM is on, and at most 8192 lattice tiles of
  * 64 x 4 x 4 cells.  Calls on one server are not thread-safe. */
 typedef struct psmdem_server psmdem_server;

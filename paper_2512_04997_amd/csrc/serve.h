@@ -6,8 +6,9 @@
 // voxelisation and the two LBM passes over a (domain, tile) map of every
 // domain's tiles, and the hydrodynamic sums with the corrector (one workgroup
 // per domain).  Each domain's arithmetic is the one of its single-domain step:
-// the same device bodies on the same data, so a result does not depend on the
-// other domains of the batch.
+// the same device bodies on the same data (the voxelisation in a one-workgroup
+// form that counts the same samples), so a result does not depend on the other
+// domains of the batch.
 #pragma once
 #include "common.h"
 #include "dem.h"
