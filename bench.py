@@ -33,8 +33,9 @@ def parse():
     p.add_argument("--steps", type=int, default=200)
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--precision", default="fp32", choices=list(STORAGE_BYTES))
-    p.add_argument("--workload", default="couette", choices=["couette", "kolmogorov"],
-                   help="couette: spheres in bounded shear; kolmogorov: prolate ellipsoids in a forced periodic box")
+    p.add_argument("--workload", default="couette", choices=["couette", "kolmogorov", "bed"],
+                   help="couette: spheres in bounded shear; kolmogorov: prolate ellipsoids in a forced periodic "
+                        "box; bed: polydisperse spheres settling in a walled 256x256x128 box (n_sub 32)")
     p.add_argument("--n", type=int, default=128, help="lattice edge of the workload")
     p.add_argument("--spheres", type=int, default=500)
     p.add_argument("--cpu-sample-steps", type=int, default=20,
@@ -53,6 +54,8 @@ def parse():
     p.add_argument("--precision-study", type=int, default=0, metavar="N",
                    help="only run the Kolmogorov-ellipsoid N^3 workload in FP64, FP32, BF16 and FP16 from the same "
                         "start: coupled-step speed and the errors of each against the FP64 run at step 200")
+    p.add_argument("--study-fraction", type=float, default=0.2,
+                   help="bounding-sphere volume fraction of the precision-study ellipsoids")
     p.add_argument("--summarize", nargs="+", metavar="DIR",
                    help="print a per-kernel summary of rocprofv3 CSV output (no GPU): DIR of a --kernel-trace "
                         "--stats run, or four DIRs of --pmc runs: FETCH_SIZE, WRITE_SIZE, and the same two "
@@ -168,13 +171,13 @@ def _rel_inf(a, b, floor=0.0):
     return float(np.max(np.abs(a - b))) / max(float(np.max(np.abs(b))), floor)
 
 
-def precision_study(n, warmup=20, timed=100, check=200):
+def precision_study(n, fraction=0.2, warmup=20, timed=100, check=200):
     """Same particle set and start in every population precision; speed of the
     coupled step and of the LBM pass, and the errors against the FP64 run."""
     import torch
     from paper_2512_04997_amd import psmdem, workloads
     torch.cuda.set_device(0)
-    cfg, parts, meta = workloads.kolmogorov_ellipsoids(n=n)
+    cfg, parts, meta = workloads.kolmogorov_ellipsoids(n=n, fraction=fraction)
     N = n ** 3
     ref = None
     for prec in ("fp64", "fp32", "bf16", "fp16"):
@@ -341,7 +344,7 @@ def main():
         lbm_sweep(a.lbm_sweep)
         return
     if a.precision_study:
-        precision_study(a.precision_study)
+        precision_study(a.precision_study, a.study_fraction)
         return
     from paper_2512_04997_amd import psmdem, workloads
 
@@ -349,9 +352,11 @@ def main():
     torch.cuda.set_device(0)
     if a.workload == "couette":
         cfg, parts, meta = workloads.couette_suspension(precision=a.precision, n=a.n, nsph=a.spheres)
-    else:
+    elif a.workload == "kolmogorov":
         cfg, parts, meta = workloads.kolmogorov_ellipsoids(n=a.n, precision=a.precision)
-    N = a.n ** 3
+    else:
+        cfg, parts, meta = workloads.settling_bed(precision=a.precision)
+    N = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]
     stream = torch.cuda.current_stream()
     D = psmdem.Domain(cfg, parts, stream=stream)
     info = D.info()
@@ -411,7 +416,7 @@ def main():
     out = {"metric": METRIC, "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": a.steps,
            "warmup": a.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": a.precision, "data": "synthetic",
-           "config": {"workload": meta["workload"], "lattice": [a.n] * 3, "particles": info["n_particles"],
+           "config": {"workload": meta["workload"], "lattice": list(cfg["n"]), "particles": info["n_particles"],
                       "n_sub": info["n_sub"], "tau": cfg["tau"], "populations": a.precision,
                       "particles_dtype": "fp64"},
            "roofline": roof, "cpu_baseline": cpu, "serving": serve}

@@ -297,40 +297,58 @@ __device__ inline int plain_off(const AxisNb& ax, const AxisNb& ay, const AxisNb
     return o;
 }
 
+// x walls are handled per lane: a link leaving through the x face of a lane at
+// x = 0 or x = nx - 1 reads / writes the lane's own opposite slot with the
+// moving-wall term (faces 0 and 1 are the only ones such a row can cross)
 template <typename S, typename C, bool ODD, int I>
-__device__ inline void load_plain(const S* f, long long N, unsigned cell, const AxisNb& ax, const AxisNb& ay,
-                                  const AxisNb& az, C* g) {
+__device__ inline void load_plain(const LbmArgs& A, const S* f, long long N, unsigned cell, const AxisNb& ax,
+                                  const AxisNb& ay, const AxisNb& az, C* g) {
     constexpr unsigned sz = sizeof(S);
     if (!ODD) {
         g[I] = Conv<S, C>::ld(*plane_ptr(f, N, I, cell * sz));
     } else {
+        constexpr int cx = d3q19_cx(I);
         const int o = plain_off<-d3q19_cx(I), -d3q19_cy(I), -d3q19_cz(I)>(ax, ay, az);
-        g[I] = Conv<S, C>::ld(*plane_ptr(f, N, d3q19_opp(I), (unsigned)((int)cell + o) * sz));
+        const bool xw = (cx > 0 && ax.wl) || (cx < 0 && ax.wh);
+        if (cx != 0 && xw) {
+            const int face = cx > 0 ? 0 : 1;
+            g[I] = Conv<S, C>::ld(*plane_ptr(f, N, I, cell * sz)) + (C)A.wall_corr[face * 19 + I];
+        } else {
+            g[I] = Conv<S, C>::ld(*plane_ptr(f, N, d3q19_opp(I), (unsigned)((int)cell + o) * sz));
+        }
     }
 }
 
 template <typename S, typename C, bool ODD, int I>
-__device__ inline void store_plain(S* f, long long N, unsigned cell, const AxisNb& ax, const AxisNb& ay,
-                                   const AxisNb& az, const C* out) {
+__device__ inline void store_plain(const LbmArgs& A, S* f, long long N, unsigned cell, const AxisNb& ax,
+                                   const AxisNb& ay, const AxisNb& az, const C* out) {
     constexpr unsigned sz = sizeof(S);
     if (!ODD) {
         *plane_ptr(f, N, d3q19_opp(I), cell * sz) = Conv<S, C>::st(out[I]);
     } else {
+        constexpr int cx = d3q19_cx(I);
         const int o = plain_off<d3q19_cx(I), d3q19_cy(I), d3q19_cz(I)>(ax, ay, az);
-        *plane_ptr(f, N, I, (unsigned)((int)cell + o) * sz) = Conv<S, C>::st(out[I]);
+        const bool xw = (cx < 0 && ax.wl) || (cx > 0 && ax.wh);
+        if (cx != 0 && xw) {
+            const int face = cx < 0 ? 0 : 1;
+            *plane_ptr(f, N, d3q19_opp(I), cell * sz) = Conv<S, C>::st(out[I] - (C)A.wall_corr[face * 19 + I]);
+        } else {
+            *plane_ptr(f, N, I, (unsigned)((int)cell + o) * sz) = Conv<S, C>::st(out[I]);
+        }
     }
 }
 
 template <typename S, typename C, bool ODD, int... Is>
-__device__ inline void load_all_plain(const S* f, long long N, unsigned cell, const AxisNb& ax, const AxisNb& ay,
-                                      const AxisNb& az, C* g, std::integer_sequence<int, Is...>) {
-    (load_plain<S, C, ODD, Is>(f, N, cell, ax, ay, az, g), ...);
+__device__ inline void load_all_plain(const LbmArgs& A, const S* f, long long N, unsigned cell, const AxisNb& ax,
+                                      const AxisNb& ay, const AxisNb& az, C* g, std::integer_sequence<int, Is...>) {
+    (load_plain<S, C, ODD, Is>(A, f, N, cell, ax, ay, az, g), ...);
 }
 
 template <typename S, typename C, bool ODD, int... Is>
-__device__ inline void store_all_plain(S* f, long long N, unsigned cell, const AxisNb& ax, const AxisNb& ay,
-                                       const AxisNb& az, const C* out, std::integer_sequence<int, Is...>) {
-    (store_plain<S, C, ODD, Is>(f, N, cell, ax, ay, az, out), ...);
+__device__ inline void store_all_plain(const LbmArgs& A, S* f, long long N, unsigned cell, const AxisNb& ax,
+                                       const AxisNb& ay, const AxisNb& az, const C* out,
+                                       std::integer_sequence<int, Is...>) {
+    (store_plain<S, C, ODD, Is>(A, f, N, cell, ax, ay, az, out), ...);
 }
 
 __device__ inline unsigned long long ballot64(bool p) { return __ballot(p); }
@@ -381,8 +399,8 @@ __device__ void lbm_tile(const LbmArgs& A, const long long t, double* kin_s, dou
     const AxisNb ax = axis_nb(x, A.g.nx, A.g.periodic[0], 1);
     const AxisNb ay = axis_nb(y, A.g.ny, A.g.periodic[1], A.g.nx);
     const bool xy_ok = x < A.g.nx && y < A.g.ny;
-    // this wave's row has no lane next to a wall in x or y (wave-uniform)
-    const bool row_plain = __ballot(xy_ok && (ax.wl || ax.wh || ay.wl || ay.wh)) == 0ull;
+    // this wave's row lies next to no y wall (wave-uniform; x walls are handled per lane)
+    const bool row_plain = !ay.wl && !ay.wh;
 
 #pragma unroll 1
     for (int lz = 0; lz < PSM_TZ; ++lz) {
@@ -398,7 +416,7 @@ __device__ void lbm_tile(const LbmArgs& A, const long long t, double* kin_s, dou
             C g[19], out[19];
             const bool plain = row_plain && !az.wl && !az.wh;
             if (plain)
-                load_all_plain<S, C, ODD>(f, N, (unsigned)cell, ax, ay, az, g, std::make_integer_sequence<int, 19>{});
+                load_all_plain<S, C, ODD>(A, f, N, (unsigned)cell, ax, ay, az, g, std::make_integer_sequence<int, 19>{});
             else
                 load_all<S, C, ODD>(A, f, N, cell, ax, ay, az, g, std::make_integer_sequence<int, 19>{});
             C Fx = (C)0, Fy = (C)0, Fz = (C)0;
@@ -446,7 +464,8 @@ __device__ void lbm_tile(const LbmArgs& A, const long long t, double* kin_s, dou
             }
             collide<C, MS>(g, out, omega, forcing, Fx, Fy, Fz, nk, B, uk, Pk);
             if (plain)
-                store_all_plain<S, C, ODD>(f, N, (unsigned)cell, ax, ay, az, out, std::make_integer_sequence<int, 19>{});
+                store_all_plain<S, C, ODD>(A, f, N, (unsigned)cell, ax, ay, az, out,
+                                           std::make_integer_sequence<int, 19>{});
             else
                 store_all<S, C, ODD>(A, f, N, cell, ax, ay, az, out, std::make_integer_sequence<int, 19>{});
         }

@@ -237,50 +237,107 @@ def serving_stream(njobs=512, rate=50.0, steps=1000, sizes=(32, 64, 96, 128), ta
     return out
 
 
-def rsa_equal_spheres_periodic(rng, n, r, box, gap=1.0, max_attempts=10_000_000, batch=64):
-    """Random sequential addition of n equal spheres of radius r in a periodic
-    box, accelerated by a uniform grid (cells of at least 2r + gap, so every
-    possible clash lies in the 27 surrounding cells).  Candidates are drawn in
-    batches, tested in draw order, and the stream is rewound to just after the
-    accepted one.  Returns (m, 3) positions for the first m <= n spheres."""
+def rsa_grid(rng, n, radii, box, periodic, region_lo=None, region_hi=None, gap=1.0, wall_gap=1.0,
+             max_attempts=10_000_000, batch=64):
+    """Random sequential addition for many spheres, accelerated by a uniform
+    grid (cells of at least 2 max(r) + gap, so every possible clash lies in the
+    27 surrounding cells).  Same rules as rsa_spheres: centres uniform in
+    [region_lo, region_hi] shrunk by radius + wall_gap on walled axes, surface
+    gap at least `gap` (minimum image on periodic axes).  Candidates are drawn
+    in batches, tested in draw order, and the stream is rewound to just after
+    the accepted one.  Returns (m, 3) positions for the first m <= n spheres."""
     box = np.asarray(box, dtype=np.float64)
-    nc = np.maximum(1, np.floor(box / (2.0 * r + gap)).astype(np.int64))
+    per = np.asarray(periodic, dtype=bool)
+    radii = np.asarray(radii, dtype=np.float64)
+    lo = np.zeros(3) if region_lo is None else np.asarray(region_lo, np.float64)
+    hi = box.copy() if region_hi is None else np.asarray(region_hi, np.float64)
+    rmax = float(radii.max()) if n else 1.0
+    nc = np.maximum(1, np.floor(box / (2.0 * rmax + gap)).astype(np.int64))
     hc = box / nc
-    K = 8
+    K = 16
     grid = -np.ones((int(nc[0]), int(nc[1]), int(nc[2]), K), dtype=np.int64)
     gcnt = np.zeros((int(nc[0]), int(nc[1]), int(nc[2])), dtype=np.int64)
     pos = np.zeros((n + 1, 3))
+    rad = np.concatenate([radii[:n], [0.0]])
     off = np.array([(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)])
-    lim = (2.0 * r + gap) ** 2
     placed = 0
     attempts = 0
-    while placed < n and attempts < max_attempts:
-        nb = min(batch, max_attempts - attempts)
-        st0 = rng.state
-        C = box[None, :] * rng.uniform(3 * nb).reshape(nb, 3)
-        ci = np.minimum(np.floor(C / hc[None, :]).astype(np.int64), nc[None, :] - 1)
-        nbr = (ci[:, None, :] + off[None, :, :]) % nc[None, None, :]
-        idx = grid[nbr[..., 0], nbr[..., 1], nbr[..., 2]].reshape(nb, -1)
-        P = pos[np.where(idx >= 0, idx, n)]
-        d = C[:, None, :] - P
-        d = d - box[None, None, :] * np.round(d / box[None, None, :])
-        dd = (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
-        clash = np.any((dd < lim) & (idx >= 0), axis=1)
-        free = np.flatnonzero(~clash)
-        if free.size == 0:
-            attempts += nb
-            continue
-        i = int(free[0])
-        attempts += i + 1
-        rng.state = (st0 + 3 * (i + 1) * _GOLDEN) & _MASK
-        c = ci[i]
-        if gcnt[c[0], c[1], c[2]] >= K:
-            raise RuntimeError("grid cell overflow in sphere placement")
-        grid[c[0], c[1], c[2], gcnt[c[0], c[1], c[2]]] = placed
-        gcnt[c[0], c[1], c[2]] += 1
-        pos[placed] = C[i]
-        placed += 1
+    for k in range(n):
+        r = float(radii[k])
+        l = lo.copy()
+        h = hi.copy()
+        for a in range(3):
+            if not per[a]:
+                l[a] = max(l[a], r + wall_gap)
+                h[a] = min(h[a], box[a] - r - wall_gap)
+        ok = False
+        while attempts < max_attempts:
+            nb = min(batch, max_attempts - attempts)
+            st0 = rng.state
+            C = l[None, :] + (h - l)[None, :] * rng.uniform(3 * nb).reshape(nb, 3)
+            ci = np.minimum(np.floor(C / hc[None, :]).astype(np.int64), nc[None, :] - 1)
+            nbr = ci[:, None, :] + off[None, :, :]
+            inside = np.all(per[None, None, :] | ((nbr >= 0) & (nbr < nc[None, None, :])), axis=2)
+            nbr = nbr % nc[None, None, :]
+            idx = grid[nbr[..., 0], nbr[..., 1], nbr[..., 2]]
+            idx = np.where(inside[..., None], idx, -1).reshape(nb, -1)
+            P = pos[np.where(idx >= 0, idx, n)]
+            d = C[:, None, :] - P
+            d = np.where(per[None, None, :], d - box[None, None, :] * np.round(d / box[None, None, :]), d)
+            dd = (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
+            lim = (r + rad[np.where(idx >= 0, idx, n)] + gap) ** 2
+            clash = np.any((dd < lim) & (idx >= 0), axis=1)
+            free = np.flatnonzero(~clash)
+            if free.size == 0:
+                attempts += nb
+                continue
+            i = int(free[0])
+            attempts += i + 1
+            rng.state = (st0 + 3 * (i + 1) * _GOLDEN) & _MASK
+            c = ci[i]
+            if gcnt[c[0], c[1], c[2]] >= K:
+                raise RuntimeError("grid cell overflow in sphere placement")
+            grid[c[0], c[1], c[2], gcnt[c[0], c[1], c[2]]] = placed
+            gcnt[c[0], c[1], c[2]] += 1
+            pos[placed] = C[i]
+            placed += 1
+            ok = True
+            break
+        if not ok:
+            break
     return pos[:placed]
+
+
+def rsa_equal_spheres_periodic(rng, n, r, box, gap=1.0, max_attempts=10_000_000):
+    """rsa_grid for n equal spheres of radius r in a fully periodic box."""
+    return rsa_grid(rng, n, np.full(n, float(r)), box, [True, True, True], gap=gap, max_attempts=max_attempts)
+
+
+def settling_bed(precision="fp32", n=(256, 256, 128), fraction=0.15, seed=1002, steps=2000):
+    """Polydisperse spheres (radius uniform in [2, 3]) placed by random
+    sequential addition (surface gap 1) in the top 60 % of a box walled on
+    every face, up to a solid fraction `fraction` of that region (0.15: with
+    the unit gap the spheres' effective fraction is about 0.26, below the
+    addition's jamming limit); tau = 0.6, density ratio 2.5, gravity
+    (0, 0, -1e-5) on the particles, the linear contact law of the Couette
+    workload, n_sub = 32."""
+    bc = ["noslip"] * 6
+    cfg = base_config(tuple(n), 0.6, bc=bc, gravity=[0.0, 0.0, -1e-5], precision=precision, n_sub=32,
+                      kn=1e3, restitution=0.8, mu=0.3)
+    rng = SplitMix64(seed)
+    box = np.asarray(n, dtype=np.float64)
+    lo = np.array([0.0, 0.0, 0.4 * box[2]])
+    region = box[0] * box[1] * 0.6 * box[2]
+    # radii drawn first, enough to fill the region at the target fraction
+    mean_v = 4.0 / 3.0 * math.pi * 2.5 ** 3 * 1.05
+    nmax = int(fraction * region / mean_v) + 1
+    radii = 2.0 + rng.uniform(nmax)
+    vol = np.cumsum(4.0 / 3.0 * math.pi * radii ** 3)
+    m = int(np.searchsorted(vol, fraction * region, side="right"))
+    radii = radii[:m]
+    pos = rsa_grid(rng, m, radii, box, [False, False, False], region_lo=lo, max_attempts=50 * m)
+    parts = spheres(pos, radii[:len(pos)], 2.5)
+    return cfg, parts, dict(workload=f"settling_bed_{n[0]}x{n[1]}x{n[2]}_{len(pos)}_spheres", steps=steps)
 
 
 def kolmogorov_ellipsoids(n=256, fraction=0.2, precision="fp32", seed=1003, amp=1e-6):

@@ -48,15 +48,22 @@ def _walled(n, tau, prec, **kw):
 
 # --------------------------------------------------------------------------- LBM only
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("kind", ["periodic", "walls_forcing"])
+@pytest.mark.parametrize("kind", ["periodic", "walls_forcing", "walls_every_face"])
 def test_lbm_matches_oracle(ps, oracle_mod, prec, kind):
     """Ragged lattice (tiles of 64x4x4 cut in every axis), random near-equilibrium
     populations; several steps cover both in-place parities."""
     n = (70, 9, 6)
     if kind == "periodic":
         cfg = W.base_config(n, 0.63, precision=prec)
-    else:
+    elif kind == "walls_forcing":
         cfg = _walled(n, 0.81, prec, body_force=[1e-5, -2e-6, 0.0], kolm_amp=3e-6, kolm_axis=2, kolm_dir=1)
+    else:
+        wu = [[0.0] * 3 for _ in range(6)]
+        wu[0] = [0.0, 0.015, -0.01]
+        wu[1] = [0.0, -0.02, 0.0]
+        wu[5] = [0.01, 0.0, 0.0]
+        cfg = W.base_config(n, 0.74, precision=prec, bc=["moving", "moving", "noslip", "noslip", "noslip", "moving"],
+                            wall_u=wu, body_force=[0.0, 3e-6, 0.0])
     G, O = _pair(ps, oracle_mod, cfg, None)
     f0 = _random_pops(G.N, 11)
     G.set_populations(f0)
@@ -259,3 +266,46 @@ def test_dem_multi_launch_path(ps, oracle_mod):
         assert vec_err(Pg["vel"], Po["vel"]) < 1e-12
         assert force_err(Pg["f_dem"], Po["f_dem"], O.scales()["f_dem"], force_floor(O)) < 1e-12
     assert O.counters()["contacts"] > 50
+
+
+def test_couette_full_size_fp32(ps, oracle_mod):
+    """The bench workload at its full size (128^3, 500 spheres R = 5, moving
+    walls, n_sub = 11) in the bench's precision: two coupled steps from
+    creation against the FP64 oracle; pairs and solid slots bit for bit."""
+    cfg, parts, meta = W.couette_suspension(precision="fp32")
+    G, O = _pair(ps, oracle_mod, cfg, parts)
+    assert G.n_sub == O.n_sub == 11
+    for _ in range(2):
+        G.step(1)
+        O.step(1)
+    assert np.array_equal(G.pairs()[0], O.pairs()[0])
+    cg, pg, _ = G.solid()
+    co, po, _ = O.solid()
+    assert np.array_equal(cg, co) and np.array_equal(pg, po)
+    assert pop_err(G.populations(), O.populations()) < TOL["fp32"]
+    Pg, Po = G.particles(), O.particles()
+    sc = O.scales()
+    assert vec_err(Pg["pos"], Po["pos"]) < TOL["fp32"]
+    assert vec_err(Pg["vel"], Po["vel"]) < TOL["fp32"]
+    assert force_err(Pg["f_hyd"], Po["f_hyd"], sc["f_hyd"]) < TOL["fp32"]
+    assert force_err(Pg["m_hyd"], Po["m_hyd"], sc["m_hyd"]) < TOL["fp32"]
+
+
+def test_settling_bed_multi_launch_coupled(ps, oracle_mod):
+    """More particles than the single-workgroup DEM takes, coupled with the
+    fluid: polydisperse spheres settling in a box walled on every face
+    (n_sub = 32), FP64, two coupled steps against the oracle."""
+    cfg, parts, meta = W.settling_bed(precision="fp64", n=(128, 128, 96))
+    assert len(parts["pos"]) > 2048
+    G, O = _pair(ps, oracle_mod, cfg, parts)
+    for _ in range(2):
+        G.step(1)
+        O.step(1)
+    assert np.array_equal(G.pairs()[0], O.pairs()[0])
+    assert pop_err(G.populations(), O.populations()) < TOL["fp64"]
+    Pg, Po = G.particles(), O.particles()
+    sc = O.scales()
+    assert vec_err(Pg["pos"], Po["pos"]) < TOL["fp64"]
+    assert vec_err(Pg["vel"], Po["vel"]) < TOL["fp64"]
+    assert force_err(Pg["f_hyd"], Po["f_hyd"], sc["f_hyd"]) < TOL["fp64"]
+    assert force_err(Pg["f_dem"], Po["f_dem"], sc["f_dem"], force_floor(O)) < TOL["fp64"]
