@@ -1000,12 +1000,27 @@ __global__ void k_colscatter(DemArgs A, PairBufs B) {
     const long long n = n_pairs(A, B);
     GRID_LOOP(s, n) ph_colscatter(A, B, s);
 }
-// sorts each column list, then clears the column's counters for the next build
-__global__ void k_colsort(DemArgs A) {
-    GRID_LOOP(j, A.p.np) {
-        ph_colsort(A, (int)j);
-        A.col_count[j] = 0;
-        A.col_fill[j] = 0;
+// Orders each column list (pair indices with second member j) ascending, one
+// wave per column: entries are distinct, so an entry's place is the number of
+// entries below it; then clears the column's counters for the next build.
+__global__ __launch_bounds__(256) void k_colsort(DemArgs A) {
+    const int lane = threadIdx.x & 63;
+    const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
+    for (long long jw = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; jw < A.p.np; jw += nw) {
+        const int j = (int)jw;
+        const int s0 = A.col_start[j], n = A.col_start[j + 1] - s0;
+        if (n > 64) {
+            if (lane == 0) ph_colsort(A, j);
+        } else if (n > 1) {
+            const int v = lane < n ? A.col_list[s0 + lane] : 0x7fffffff;
+            int below = 0;
+            for (int u = 0; u < n; ++u) below += __shfl(v, u, 64) < v ? 1 : 0;
+            if (lane < n) A.col_list[s0 + below] = v;
+        }
+        if (lane == 0) {
+            A.col_count[j] = 0;
+            A.col_fill[j] = 0;
+        }
     }
 }
 __global__ void k_sum(DemArgs A, PairBufs B) { GRID_LOOP(i, A.p.np) ph_sum<false>(A, B, (int)i); }
@@ -1398,7 +1413,7 @@ hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, c
     k_colhist<<<nblk(A.pair_cap), 256, 0, s>>>(A, B);
     if ((e = psm_scan(A.col_count, A.col_start, A.p.np, scan_tmp, s)) != hipSuccess) return e;
     k_colscatter<<<nblk(A.pair_cap), 256, 0, s>>>(A, B);
-    k_colsort<<<nblk(A.p.np), 256, 0, s>>>(A);
+    k_colsort<<<nblk(64LL * A.p.np), 256, 0, s>>>(A);
     k_sum<<<nblk(A.p.np, 128), 128, 0, s>>>(A, B);
     return hipGetLastError();
 }

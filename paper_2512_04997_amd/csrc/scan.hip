@@ -86,8 +86,48 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_add(int* __restrict__ out, long
 
 constexpr long long SCAN_SMALL = 32768;
 
+// One workgroup of 1024 lanes walks the input in chunks of 4096 entries, four
+// consecutive entries per lane (coalesced), with a running carry (in place
+// allowed: a lane reads its entries before it writes them).
 __global__ __launch_bounds__(1024) void k_scan_small(const int* in, int* out, long long n) {
-    psm_block_scan<1024>(in, out, n);
+    __shared__ int wsum[16];
+    __shared__ int carry_s;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (tid == 0) carry_s = 0;
+    __syncthreads();
+    for (long long base = 0; base < n; base += 4096) {
+        const long long i0 = base + 4LL * tid;
+        int v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = i0 + k < n ? in[i0 + k] : 0;
+        const int sum = (v[0] + v[1]) + (v[2] + v[3]);
+        int x = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wid] = x;
+        __syncthreads();
+        const int carry = carry_s;
+        int off = carry, tot = 0;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) {
+            off += w < wid ? wsum[w] : 0;
+            tot += wsum[w];
+        }
+        int run = off + x - sum;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (i0 + k < n) {
+                out[i0 + k] = run;
+                run += v[k];
+            }
+        __syncthreads();
+        if (tid == 0) carry_s = carry + tot;
+        __syncthreads();
+    }
+    if (tid == 0) out[n] = carry_s;
 }
 
 __global__ void k_fill_int(int* __restrict__ p, int v, long long n) {
