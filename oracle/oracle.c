@@ -206,6 +206,10 @@ or_domain* or_create(const or_desc* d, int32_t np, const int32_t* shape, const d
         snprintf(g_err, sizeof g_err, "invalid max_solids or sf_subdiv");
         return NULL;
     }
+    if (d->collision < 0 || d->collision > 1 || d->trt_magic < 0.0) {
+        snprintf(g_err, sizeof g_err, "invalid collision operator");
+        return NULL;
+    }
     if (np > 0 && (d->restitution <= 0.0 || d->restitution > 1.0)) {
         snprintf(g_err, sizeof g_err, "restitution must be in (0,1]");
         return NULL;
@@ -533,7 +537,8 @@ static double b_weight(double beta, double tau) {
 }
 
 /* Collision of one cell with PSM, Eqs. (psm1), (lbePS) with the BGK fluid
- * operator Eq. (BGK) and the solid operator Omega^s; Guo forcing (G26) with the
+ * operator Eq. (BGK) or the TRT operator Eq. (TRT), and the solid operator
+ * Omega^s; Guo forcing (G26) with the
  * (1 - B_tot) factor.  Pk receives B_k sum_i Omega^s_{i,k} c_i per slot. */
 static void collide_cell(const or_domain* D, const double f[19], int32_t nslot, const double* B,
                          const double* uk, const double F[3], double fpost[19], double* Pk, double* Sk);
@@ -565,19 +570,44 @@ static void collide_cell(const or_domain* D, const double f[19], int32_t nslot, 
     double Bsum = 0.0;
     for (int s = 0; s < nslot; ++s) Bsum += B[s];
     double Btot = Bsum < 1.0 ? Bsum : 1.0; /* Eq. (btot) */
-    double S[19] = {0};
+    /* Guo source: w_i [3 (c_i - u) + 9 (c_i . u) c_i] . F, times its relaxation
+     * prefactor (BGK) or split below (TRT) */
+    double G[19] = {0};
     if (forcing) {
-        double cu_pref = 1.0 - 1.0 / (2.0 * tau);
         for (int i = 0; i < 19; ++i) {
             double cu = CX[i] * u[0] + CY[i] * u[1] + CZ[i] * u[2];
             double t0 = 3.0 * (CX[i] - u[0]) + 9.0 * cu * CX[i];
             double t1 = 3.0 * (CY[i] - u[1]) + 9.0 * cu * CY[i];
             double t2 = 3.0 * (CZ[i] - u[2]) + 9.0 * cu * CZ[i];
-            S[i] = cu_pref * W[i] * (t0 * F[0] + t1 * F[1] + t2 * F[2]);
+            G[i] = t0 * F[0] + t1 * F[1] + t2 * F[2];
         }
     }
-    for (int i = 0; i < 19; ++i)
-        fpost[i] = f[i] - (1.0 - Btot) * (f[i] - feq[i]) / tau + (1.0 - Btot) * S[i];
+    if (D->d.collision == 0) {
+        /* BGK, Eq. (BGK); Guo prefactor 1 - 1/(2 tau) */
+        double cu_pref = 1.0 - 1.0 / (2.0 * tau);
+        for (int i = 0; i < 19; ++i) {
+            double Si = cu_pref * W[i] * G[i];
+            fpost[i] = f[i] - (1.0 - Btot) * (f[i] - feq[i]) / tau + (1.0 - Btot) * Si;
+        }
+    } else {
+        double S[19];
+        for (int i = 0; i < 19; ++i) S[i] = W[i] * G[i];
+        /* TRT, Eqs. (trt_populations), (TRT): f+- = (f_i +- f_ibar)/2 and the same
+         * split of f^eq relax with dt/tau+ = 1/tau and dt/tau-; the Guo source is
+         * split the same way, each part with its own prefactor 1 - (dt/tau+-)/2 */
+        double wp = 1.0 / tau, wm;
+        if (D->d.trt_magic > 0.0) wm = 1.0 / (D->d.trt_magic / (tau - 0.5) + 0.5);
+        else wm = 8.0 * (2.0 - wp) / (8.0 - wp);
+        for (int i = 0; i < 19; ++i) {
+            int o = OPP[i];
+            double fp = 0.5 * (f[i] + f[o]), fm = 0.5 * (f[i] - f[o]);
+            double ep = 0.5 * (feq[i] + feq[o]), em = 0.5 * (feq[i] - feq[o]);
+            double Sp = 0.5 * (S[i] + S[o]), Sm = 0.5 * (S[i] - S[o]);
+            double omega = -wp * (fp - ep) - wm * (fm - em);
+            double src = (1.0 - 0.5 * wp) * Sp + (1.0 - 0.5 * wm) * Sm;
+            fpost[i] = f[i] + (1.0 - Btot) * omega + (1.0 - Btot) * src;
+        }
+    }
     for (int s = 0; s < nslot; ++s) {
         double feqk[19];
         or_feq(rho, uk + 3 * s, feqk);

@@ -41,6 +41,8 @@ typedef struct {
     double dem_cell;          /* 0: automatic DEM grid */
     double kn, restitution, mu, kt_ratio, gt_ratio;
     int32_t max_solids;       /* solids kept per fluid cell (2) */
+    int32_t collision;        /* fluid operator: 0 BGK, 1 TRT (Sec. 2.3, Eq. TRT) */
+    double trt_magic;         /* TRT: 0 = the paper's tau^- rule; > 0 = magic parameter Lambda */
 } or_desc;
 
 typedef struct or_domain or_domain;

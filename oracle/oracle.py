@@ -29,6 +29,7 @@ class OrDesc(C.Structure):
         ("kn", C.c_double), ("restitution", C.c_double), ("mu", C.c_double),
         ("kt_ratio", C.c_double), ("gt_ratio", C.c_double),
         ("max_solids", C.c_int32),
+        ("collision", C.c_int32), ("trt_magic", C.c_double),
     ]
 
 
@@ -124,6 +125,8 @@ def make_desc(cfg):
     d.kt_ratio = float(cfg.get("kt_ratio", 1.0))
     d.gt_ratio = float(cfg.get("gt_ratio", 1.0))
     d.max_solids = int(cfg.get("max_solids", 2))
+    d.collision = {"bgk": 0, "trt": 1}[cfg.get("collision", "bgk")]
+    d.trt_magic = float(cfg.get("trt_magic", 0.0))
     return d
 
 

@@ -2,7 +2,7 @@
 
 None of these compare the oracle with itself: each checks a conservation law,
 a closed form, a printed value, a limit that reduces to a textbook case, or a
-brute-force enumeration.  Labels P1..P19 name the pins in the design notes.
+brute-force enumeration.  Labels P1..P21 name the pins in the design notes.
 """
 import json
 import math
@@ -197,6 +197,98 @@ def test_p7_poiseuille_second_order(oracle_mod):
         ux = D.fields()[1][:, 0].reshape(N, 4).mean(1)
         errs.append(np.abs(ux - uex).max() / uex.max())
     assert 3.0 < errs[0] / errs[1] < 5.0
+
+
+def _trt_rates(tau, magic=None):
+    """omega+ = dt/tau+ = 1/tau; omega- from Lambda = (1/w+ - 1/2)(1/w- - 1/2)."""
+    wp = 1.0 / tau
+    lam = 3.0 / 16.0 if magic is None else magic
+    return wp, 1.0 / (lam / (tau - 0.5) + 0.5)
+
+
+def _split(f):
+    o = np.array([np.flatnonzero((CI == -CI[i]).all(1))[0] for i in range(19)])
+    return 0.5 * (f + f[o]), 0.5 * (f - f[o])
+
+
+def test_p20_trt_collision_relaxes_even_and_odd_parts(oracle_mod):
+    """TRT (Sec. 2.3): the even part of f - f^eq decays by (1 - w+), the odd
+    part by (1 - w-); with the paper's w- rule the magic parameter is 3/16.
+    Mass and momentum are conserved; a Guo force F adds exactly F to the
+    momentum of the cell (half-force velocity), mass unchanged."""
+    rng = np.random.default_rng(20)
+    for tau in (0.55, 0.8, 1.7):
+        D = _dom(oracle_mod, W.base_config((4, 4, 4), tau, collision="trt"))
+        wp, wm = _trt_rates(tau)
+        assert abs((1 / wp - 0.5) * (1 / wm - 0.5) - 3 / 16) < 1e-15
+        for _ in range(20):
+            f = oracle_mod.feq(1.0, 0.05 * (rng.random(3) - 0.5)) * (1 + 0.2 * rng.random(19))
+            fp, _ = D.collide_cell(f, np.zeros(0), np.zeros(0))
+            assert abs(fp.sum() - f.sum()) <= 20 * 2.2e-16 * f.sum()
+            np.testing.assert_allclose(CI.T @ fp, CI.T @ f, atol=1e-16 * 19)
+            feq = oracle_mod.feq(f.sum(), (CI.T @ f) / f.sum())
+            ep, em = _split(fp - feq)
+            np_, nm = _split(f - feq)
+            np.testing.assert_allclose(ep, (1 - wp) * np_, atol=1e-15)
+            np.testing.assert_allclose(em, (1 - wm) * nm, atol=1e-15)
+            F = 1e-4 * (rng.random(3) - 0.5)
+            fF, _ = D.collide_cell(f, np.zeros(0), np.zeros(0), F)
+            assert abs(fF.sum() - f.sum()) <= 20 * 2.2e-16 * f.sum()
+            np.testing.assert_allclose(CI.T @ (fF - f), F, atol=1e-16 * 19)
+
+
+def test_p20_trt_is_bgk_when_the_rates_coincide(oracle_mod):
+    """Lambda = (tau - 1/2)^2 makes w- = w+, and TRT reduces to BGK: the whole
+    coupled step (walls, body force, a settling sphere) agrees to round-off."""
+    tau = 0.74
+    cfg = W.base_config((24, 18, 14), tau, bc=["periodic"] * 4 + ["noslip", "moving"],
+                        wall_u=[[0.0] * 3] * 5 + [[0.01, 0.0, 0.0]], body_force=[1e-5, 0, 0],
+                        gravity=[0, 0, -1e-4], n_sub=2)
+    parts = W.spheres([[9.3, 8.1, 7.2]], 3.2, 1.8)
+    A = _dom(oracle_mod, cfg, parts)
+    B = _dom(oracle_mod, dict(cfg, collision="trt", trt_magic=(tau - 0.5) ** 2), parts)
+    A.step(6)
+    B.step(6)
+    np.testing.assert_allclose(B.populations(), A.populations(), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(B.particles()["vel"], A.particles()["vel"], rtol=1e-11, atol=1e-16)
+
+
+def _poiseuille_trt(oracle_mod, tau, magic, N=12, G=1e-6):
+    nu = (tau - 0.5) / 3
+    bc = ["periodic"] * 4 + ["noslip", "noslip"]
+    D = _dom(oracle_mod, W.base_config((2, 2, N), tau, bc=bc, body_force=[G, 0, 0], dem_on=False,
+                                       collision="trt", trt_magic=magic))
+    z = np.arange(N) + 0.5
+    uex = G * z * (N - z) / (2 * nu)
+    f = np.zeros((19, 4 * N))
+    for c in range(4 * N):
+        f[:, c] = oracle_mod.feq(1.0, [uex[c // 4], 0.0, 0.0])
+    D.set_populations(f)
+    D.step(int(60 * N * N / nu / np.pi ** 2) + 200)
+    ux = D.fields()[1][:, 0].reshape(N, 4).mean(1)
+    return np.abs(ux - uex).max() / uex.max()
+
+
+def test_p21_trt_poiseuille_exact_at_any_tau(oracle_mod):
+    """With Lambda = 3/16 (the paper's w- rule) the halfway bounce-back walls
+    sit exactly halfway and Guo-forced Poiseuille flow is exact for every tau,
+    not only at tau = 1/2 + sqrt(3)/4 as for BGK; another Lambda is not."""
+    for tau in (0.6, 0.9, 1.5):
+        assert _poiseuille_trt(oracle_mod, tau, 0.0) < 1e-10
+    assert _poiseuille_trt(oracle_mod, 0.9, 0.25) > 1e-4
+
+
+def test_p21_trt_couette(oracle_mod):
+    """The linear Couette profile is exact for TRT as for BGK."""
+    N, U, tau = 16, 0.02, 0.65
+    bc = ["periodic"] * 4 + ["moving", "moving"]
+    wu = [[0.0] * 3] * 4 + [[-U, 0.0, 0.0], [U, 0.0, 0.0]]
+    D = _dom(oracle_mod, W.base_config((4, 4, N), tau, bc=bc, wall_u=wu, dem_on=False, collision="trt"))
+    z = np.arange(N) + 0.5
+    uex = -U + 2 * U * z / N
+    D.step(int(60 * N * N / ((tau - 0.5) / 3) / np.pi ** 2 / 5) + 200)
+    ux = D.fields()[1][:, 0].reshape(N, 16).mean(1)
+    np.testing.assert_allclose(ux, uex, rtol=0, atol=1e-12 * U)
 
 
 # --------------------------------------------------------------------------- voxelisation
