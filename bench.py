@@ -37,6 +37,8 @@ def parse():
                    help="couette: spheres in bounded shear; kolmogorov: prolate ellipsoids in a forced periodic "
                         "box; bed: polydisperse spheres settling in a walled 256x256x128 box (n_sub 32)")
     p.add_argument("--n", type=int, default=128, help="lattice edge of the workload")
+    p.add_argument("--collision", default="bgk", choices=["bgk", "trt"],
+                   help="fluid operator inside the PSM collision (TRT: the paper's tau- rule)")
     p.add_argument("--spheres", type=int, default=500)
     p.add_argument("--cpu-sample-steps", type=int, default=20,
                    help="coupled steps of the CPU oracle sample (0: skip the CPU baseline)")
@@ -139,13 +141,14 @@ def summarize(dirs, kernel_filter):
     return f_fetch, f_write, fetch, write
 
 
-def lbm_sweep(n):
+def lbm_sweep(n, collision="bgk"):
     """LBM pass of a periodic fluid-only n^3 lattice (body force on), all precisions."""
     import torch
     from paper_2512_04997_amd import psmdem, workloads
     torch.cuda.set_device(0)
     for prec, sb in STORAGE_BYTES.items():
-        cfg = workloads.base_config((n, n, n), 0.7, precision=prec, body_force=[1e-6, 0.0, 0.0])
+        cfg = workloads.base_config((n, n, n), 0.7, precision=prec, body_force=[1e-6, 0.0, 0.0],
+                                    collision=collision)
         D = psmdem.Domain(cfg, None)
         D.step(10)
         D.sync()
@@ -154,7 +157,7 @@ def lbm_sweep(n):
         D.set_timing(False)
         ms, _ = D.timing("lbm")
         N = n ** 3
-        print(json.dumps({"lbm_sweep": prec, "n": n, "lbm_ms": round(ms, 4), "mlups": round(N / ms / 1e3, 1),
+        print(json.dumps({"lbm_sweep": prec, "collision": collision, "n": n, "lbm_ms": round(ms, 4), "mlups": round(N / ms / 1e3, 1),
                           "alg_GBs": round(N * 2 * 19 * sb / (ms * 1e-3) / 1e9, 1),
                           "frac": round(N * 2 * 19 * sb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}), flush=True)
         D.close()
@@ -341,7 +344,7 @@ def main():
         copy_probe(a.copy_probe)
         return
     if a.lbm_sweep:
-        lbm_sweep(a.lbm_sweep)
+        lbm_sweep(a.lbm_sweep, a.collision)
         return
     if a.precision_study:
         precision_study(a.precision_study, a.study_fraction)
@@ -356,6 +359,7 @@ def main():
         cfg, parts, meta = workloads.kolmogorov_ellipsoids(n=a.n, precision=a.precision)
     else:
         cfg, parts, meta = workloads.settling_bed(precision=a.precision)
+    cfg["collision"] = a.collision
     N = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]
     stream = torch.cuda.current_stream()
     D = psmdem.Domain(cfg, parts, stream=stream)
@@ -417,7 +421,8 @@ def main():
            "warmup": a.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": a.precision, "data": "synthetic",
            "config": {"workload": meta["workload"], "lattice": list(cfg["n"]), "particles": info["n_particles"],
-                      "n_sub": info["n_sub"], "tau": cfg["tau"], "populations": a.precision,
+                      "n_sub": info["n_sub"], "tau": cfg["tau"], "collision": a.collision,
+                      "populations": a.precision,
                       "particles_dtype": "fp64"},
            "roofline": roof, "cpu_baseline": cpu, "serving": serve}
     print(json.dumps(out), flush=True)

@@ -72,11 +72,17 @@ typedef enum {
 } psmdem_precision;
 
 typedef enum { PSMDEM_SF_SUBDIVISION = 0, PSMDEM_SF_DISTANCE = 1 } psmdem_sf;
+
+/* Fluid collision operator inside the PSM step, Eq. (lbePS).  BGK: Eq. (BGK).
+ * TRT, Eqs. (trt_populations), (TRT): the even and odd parts of f - f^eq relax
+ * with dt/tau+ = 1/tau and dt/tau-; the Guo source is split into its even and
+ * odd parts the same way, each scaled by 1 - (dt/tau+-)/2. */
+typedef enum { PSMDEM_BGK = 0, PSMDEM_TRT = 1 } psmdem_collision;
 typedef enum { PSMDEM_SPHERE = 0, PSMDEM_ELLIPSOID = 1 } psmdem_shape;
 
 typedef struct {
     int32_t nx, ny, nz;         /* lattice extents (>= 1) */
-    double tau;                 /* BGK relaxation time, tau = 3 nu + 1/2 (Eq. tau), > 1/2 */
+    double tau;                 /* relaxation time (tau+ of TRT), tau = 3 nu + 1/2 (Eq. tau), > 1/2 */
     double rho0;                /* reference density (1): initial density, wall density */
     int32_t bc[6];              /* faces -x,+x,-y,+y,-z,+z: psmdem_bc; both faces of an axis
                                    periodic or neither */
@@ -100,6 +106,10 @@ typedef struct {
     double kt_ratio, gt_ratio;  /* k_t / k_n and gamma_t / gamma_n */
     int32_t max_solids;         /* solids kept per fluid cell (2), 1..4 */
     int64_t pair_capacity;      /* candidate-pair capacity; 0 = automatic */
+    int32_t collision;          /* fluid operator: psmdem_collision (BGK, 0, when zeroed) */
+    double trt_magic;           /* TRT only: 0 = the paper's rule dt/tau- = 8 (2 - w) / (8 - w),
+                                   w = dt/tau+ (Sec. 2.3), which is the magic parameter
+                                   Lambda = (tau+ - 1/2)(tau- - 1/2) = 3/16; > 0 sets Lambda */
 } psmdem_desc;
 
 typedef struct {

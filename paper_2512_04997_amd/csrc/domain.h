@@ -191,6 +191,12 @@ struct psmdem_domain {
         A.g = geo;
         A.f = f;
         A.omega = 1.0 / d.tau;
+        A.omega_m = A.omega;
+        if (d.collision == PSMDEM_TRT) {
+            // Lambda = (1/w+ - 1/2)(1/w- - 1/2); the paper's rule is Lambda = 3/16
+            if (d.trt_magic > 0.0) A.omega_m = 1.0 / (d.trt_magic / (d.tau - 0.5) + 0.5);
+            else A.omega_m = 8.0 * (2.0 - A.omega) / (8.0 - A.omega);
+        }
         A.forcing = (d.body_force[0] != 0.0 || d.body_force[1] != 0.0 || d.body_force[2] != 0.0 ||
                      d.kolm_amp != 0.0);
         for (int a = 0; a < 3; ++a) {

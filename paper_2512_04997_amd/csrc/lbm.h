@@ -1,11 +1,12 @@
-// lbm.h -- fused in-place (AA pattern) D3Q19 BGK-PSM collide-and-stream.
+// lbm.h -- fused in-place (AA pattern) D3Q19 BGK/TRT-PSM collide-and-stream.
 #pragma once
 #include "common.h"
 
 struct LbmArgs {
     GeoArgs g;
     void* f;                   // populations [19][N], storage type S, shifted f - w_i
-    double omega;              // 1 / tau
+    double omega;              // dt / tau (tau+ of TRT)
+    double omega_m;            // dt / tau- of TRT; equal to omega for BGK
     int forcing;               // Guo forcing on
     double F[3];               // constant force density
     int kolm_axis, kolm_dir;

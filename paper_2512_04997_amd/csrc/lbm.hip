@@ -1,5 +1,6 @@
-// lbm.hip -- fused in-place (AA pattern) D3Q19 collide-and-stream with BGK
-// (Sec. 2.3, Eqs. collAndStream, BGK, equilibrium), partially saturated cells
+// lbm.hip -- fused in-place (AA pattern) D3Q19 collide-and-stream with BGK or
+// TRT (Sec. 2.3, Eqs. collAndStream, BGK, trt_populations, TRT, equilibrium),
+// partially saturated cells
 // (Sec. 2.4, Eqs. psm1, lbePS, bk, btot, forceSF, torqueSF), halfway and
 // moving-wall bounce-back and Guo forcing.
 //
@@ -110,10 +111,14 @@ __device__ inline C cdot(int i, C x, C y, C z) {
     return r;
 }
 
-// BGK (+ PSM, + Guo) collision of one cell; MS = maximum solid slots (0: fluid
-// only).  Pk[k] = sum_i Omega^s_ik c_i (before the B_k factor).
+// BGK or TRT (+ PSM, + Guo) collision of one cell; MS = maximum solid slots (0:
+// fluid only).  Pk[k] = sum_i Omega^s_ik c_i (before the B_k factor).
+// The pair (p, pbar) relaxes its even part at omega and its odd part at
+// omega_m: post_p = g_p - a neq_p - b neq_pbar with a = (omega + omega_m)/2,
+// b = (omega - omega_m)/2 (b = 0 for BGK, which leaves BGK's arithmetic).  The
+// Guo source's odd part w 3 c.F takes 1 - omega_m/2, its even part 1 - omega/2.
 template <typename C, int MS>
-__device__ inline void collide(const C* g, C* out, C omega, bool forcing, C Fx, C Fy, C Fz, int nk,
+__device__ inline void collide(const C* g, C* out, C omega, C omega_m, bool forcing, C Fx, C Fy, C Fz, int nk,
                                const C* B, const C (*uk)[3], C (*Pk)[3]) {
     C drho, jx, jy, jz;
     moments(g, drho, jx, jy, jz);
@@ -145,7 +150,11 @@ __device__ inline void collide(const C* g, C* out, C omega, bool forcing, C Fx, 
     Bt = Bt < (C)1 ? Bt : (C)1;
     const C om = MS > 0 ? ((C)1 - Bt) * omega : omega;
     const C fpre = MS > 0 ? ((C)1 - Bt) : (C)1;
-    const C gk = (C)1 - (C)0.5 * omega;  // Guo prefactor 1 - 1/(2 tau)
+    const C wa = (C)0.5 * (omega + omega_m), wb = (C)0.5 * (omega - omega_m);
+    const C oa = MS > 0 ? ((C)1 - Bt) * wa : wa;
+    const C ob = MS > 0 ? ((C)1 - Bt) * wb : wb;
+    const C gk = (C)1 - (C)0.5 * omega;     // even Guo prefactor 1 - (dt/tau+)/2
+    const C gkm = (C)1 - (C)0.5 * omega_m;  // odd Guo prefactor 1 - (dt/tau-)/2
     const C uF = ux * Fx + uy * Fy + uz * Fz;
     {
         const C geq0 = W<C>(0) * E;
@@ -164,13 +173,14 @@ __device__ inline void collide(const C* g, C* out, C omega, bool forcing, C Fx, 
         const C sym = w * (E + (C)4.5 * rho * cu * cu);
         const C anti = w * (C)3 * rho * cu;
         const C neqp = g[p] - (sym + anti), neqq = g[q] - (sym - anti);
-        C op = g[p] - om * neqp;
-        C oq = g[q] - om * neqq;
+        C op = (g[p] - oa * neqp) - ob * neqq;
+        C oq = (g[q] - oa * neqq) - ob * neqp;
         if (forcing) {
             const C cF = cdot<C>(p, Fx, Fy, Fz);
-            const C t = (C)9 * cu * cF - (C)3 * uF;
-            op += fpre * gk * w * ((C)3 * cF + t);
-            oq += fpre * gk * w * ((C)-3 * cF + t);
+            const C t = gk * ((C)9 * cu * cF - (C)3 * uF);
+            const C a3 = gkm * ((C)3 * cF);
+            op += fpre * w * (a3 + t);
+            oq += fpre * w * (t - a3);
         }
 #pragma unroll
         for (int k = 0; k < MS; ++k) {
@@ -297,10 +307,12 @@ __device__ inline int plain_off(const AxisNb& ax, const AxisNb& ay, const AxisNb
     return o;
 }
 
-// x walls are handled per lane: a link leaving through the x face of a lane at
-// x = 0 or x = nx - 1 reads / writes the lane's own opposite slot with the
-// moving-wall term (faces 0 and 1 are the only ones such a row can cross)
-template <typename S, typename C, bool ODD, int I>
+// XW: x walls are handled per lane: a link leaving through the x face of a lane
+// at x = 0 or x = nx - 1 reads / writes the lane's own opposite slot with the
+// moving-wall term (faces 0 and 1 are the only ones such a row can cross).
+// Waves with no lane at an x wall take XW = false and keep one unconditional
+// access per direction.
+template <typename S, typename C, bool ODD, bool XW, int I>
 __device__ inline void load_plain(const LbmArgs& A, const S* f, long long N, unsigned cell, const AxisNb& ax,
                                   const AxisNb& ay, const AxisNb& az, C* g) {
     constexpr unsigned sz = sizeof(S);
@@ -309,8 +321,8 @@ __device__ inline void load_plain(const LbmArgs& A, const S* f, long long N, uns
     } else {
         constexpr int cx = d3q19_cx(I);
         const int o = plain_off<-d3q19_cx(I), -d3q19_cy(I), -d3q19_cz(I)>(ax, ay, az);
-        const bool xw = (cx > 0 && ax.wl) || (cx < 0 && ax.wh);
-        if (cx != 0 && xw) {
+        const bool xw = XW && ((cx > 0 && ax.wl) || (cx < 0 && ax.wh));
+        if (XW && cx != 0 && xw) {
             const int face = cx > 0 ? 0 : 1;
             g[I] = Conv<S, C>::ld(*plane_ptr(f, N, I, cell * sz)) + (C)A.wall_corr[face * 19 + I];
         } else {
@@ -319,7 +331,7 @@ __device__ inline void load_plain(const LbmArgs& A, const S* f, long long N, uns
     }
 }
 
-template <typename S, typename C, bool ODD, int I>
+template <typename S, typename C, bool ODD, bool XW, int I>
 __device__ inline void store_plain(const LbmArgs& A, S* f, long long N, unsigned cell, const AxisNb& ax,
                                    const AxisNb& ay, const AxisNb& az, const C* out) {
     constexpr unsigned sz = sizeof(S);
@@ -328,8 +340,8 @@ __device__ inline void store_plain(const LbmArgs& A, S* f, long long N, unsigned
     } else {
         constexpr int cx = d3q19_cx(I);
         const int o = plain_off<d3q19_cx(I), d3q19_cy(I), d3q19_cz(I)>(ax, ay, az);
-        const bool xw = (cx < 0 && ax.wl) || (cx > 0 && ax.wh);
-        if (cx != 0 && xw) {
+        const bool xw = XW && ((cx < 0 && ax.wl) || (cx > 0 && ax.wh));
+        if (XW && cx != 0 && xw) {
             const int face = cx < 0 ? 0 : 1;
             *plane_ptr(f, N, d3q19_opp(I), cell * sz) = Conv<S, C>::st(out[I] - (C)A.wall_corr[face * 19 + I]);
         } else {
@@ -338,17 +350,17 @@ __device__ inline void store_plain(const LbmArgs& A, S* f, long long N, unsigned
     }
 }
 
-template <typename S, typename C, bool ODD, int... Is>
+template <typename S, typename C, bool ODD, bool XW, int... Is>
 __device__ inline void load_all_plain(const LbmArgs& A, const S* f, long long N, unsigned cell, const AxisNb& ax,
                                       const AxisNb& ay, const AxisNb& az, C* g, std::integer_sequence<int, Is...>) {
-    (load_plain<S, C, ODD, Is>(A, f, N, cell, ax, ay, az, g), ...);
+    (load_plain<S, C, ODD, XW, Is>(A, f, N, cell, ax, ay, az, g), ...);
 }
 
-template <typename S, typename C, bool ODD, int... Is>
+template <typename S, typename C, bool ODD, bool XW, int... Is>
 __device__ inline void store_all_plain(const LbmArgs& A, S* f, long long N, unsigned cell, const AxisNb& ax,
                                        const AxisNb& ay, const AxisNb& az, const C* out,
                                        std::integer_sequence<int, Is...>) {
-    (store_plain<S, C, ODD, Is>(A, f, N, cell, ax, ay, az, out), ...);
+    (store_plain<S, C, ODD, XW, Is>(A, f, N, cell, ax, ay, az, out), ...);
 }
 
 __device__ inline unsigned long long ballot64(bool p) { return __ballot(p); }
@@ -392,7 +404,7 @@ __device__ void lbm_tile(const LbmArgs& A, const long long t, double* kin_s, dou
     const int x = tx * PSM_TX + lane, y = ty * PSM_TY + wid;
     const long long N = A.g.N;
     S* f = (S*)A.f;
-    const C omega = (C)A.omega;
+    const C omega = (C)A.omega, omega_m = (C)A.omega_m;
     const bool forcing = A.forcing != 0;
     const long long plane = ntiles * (long long)PSM_TILE;
     const C* Bslot = (const C*)A.t.slot_B;
@@ -401,6 +413,8 @@ __device__ void lbm_tile(const LbmArgs& A, const long long t, double* kin_s, dou
     const bool xy_ok = x < A.g.nx && y < A.g.ny;
     // this wave's row lies next to no y wall (wave-uniform; x walls are handled per lane)
     const bool row_plain = !ay.wl && !ay.wh;
+    // some lane of this wave sits at an x wall (only the odd step's plain access differs)
+    const bool row_xw = ODD && __ballot(xy_ok && (ax.wl || ax.wh)) != 0ull;
 
 #pragma unroll 1
     for (int lz = 0; lz < PSM_TZ; ++lz) {
@@ -415,8 +429,12 @@ __device__ void lbm_tile(const LbmArgs& A, const long long t, double* kin_s, dou
             const long long cell = (long long)x + (long long)A.g.nx * ((long long)y + (long long)A.g.ny * z);
             C g[19], out[19];
             const bool plain = row_plain && !az.wl && !az.wh;
-            if (plain)
-                load_all_plain<S, C, ODD>(A, f, N, (unsigned)cell, ax, ay, az, g, std::make_integer_sequence<int, 19>{});
+            if (plain && !row_xw)
+                load_all_plain<S, C, ODD, false>(A, f, N, (unsigned)cell, ax, ay, az, g,
+                                                 std::make_integer_sequence<int, 19>{});
+            else if (plain)
+                load_all_plain<S, C, ODD, true>(A, f, N, (unsigned)cell, ax, ay, az, g,
+                                                std::make_integer_sequence<int, 19>{});
             else
                 load_all<S, C, ODD>(A, f, N, cell, ax, ay, az, g, std::make_integer_sequence<int, 19>{});
             C Fx = (C)0, Fy = (C)0, Fz = (C)0;
@@ -462,10 +480,13 @@ __device__ void lbm_tile(const LbmArgs& A, const long long t, double* kin_s, dou
                     }
                 }
             }
-            collide<C, MS>(g, out, omega, forcing, Fx, Fy, Fz, nk, B, uk, Pk);
-            if (plain)
-                store_all_plain<S, C, ODD>(A, f, N, (unsigned)cell, ax, ay, az, out,
-                                           std::make_integer_sequence<int, 19>{});
+            collide<C, MS>(g, out, omega, omega_m, forcing, Fx, Fy, Fz, nk, B, uk, Pk);
+            if (plain && !row_xw)
+                store_all_plain<S, C, ODD, false>(A, f, N, (unsigned)cell, ax, ay, az, out,
+                                                  std::make_integer_sequence<int, 19>{});
+            else if (plain)
+                store_all_plain<S, C, ODD, true>(A, f, N, (unsigned)cell, ax, ay, az, out,
+                                                 std::make_integer_sequence<int, 19>{});
             else
                 store_all<S, C, ODD>(A, f, N, cell, ax, ay, az, out, std::make_integer_sequence<int, 19>{});
         }
@@ -569,14 +590,16 @@ hipError_t launch_batch(const LbmArgs* jobs, const SrvDyn& dyn, const int2* map,
 template <typename S, typename C>
 hipError_t launch_step(const LbmArgs& A, int odd, hipStream_t s) {
     const unsigned nblk = (unsigned)(8 * ((A.g.ntiles + 7) / 8));
+    // without particles no tile holds a registration: the PSM launch is skipped
+    const bool psm = A.np > 0;
     if (odd) {
         k_lbm<S, C, true, 0><<<nblk, 256, 0, s>>>(A);
-        if (A.ms <= 2) k_lbm<S, C, true, 2><<<nblk, 256, 0, s>>>(A);
-        else k_lbm<S, C, true, 4><<<nblk, 256, 0, s>>>(A);
+        if (psm && A.ms <= 2) k_lbm<S, C, true, 2><<<nblk, 256, 0, s>>>(A);
+        else if (psm) k_lbm<S, C, true, 4><<<nblk, 256, 0, s>>>(A);
     } else {
         k_lbm<S, C, false, 0><<<nblk, 256, 0, s>>>(A);
-        if (A.ms <= 2) k_lbm<S, C, false, 2><<<nblk, 256, 0, s>>>(A);
-        else k_lbm<S, C, false, 4><<<nblk, 256, 0, s>>>(A);
+        if (psm && A.ms <= 2) k_lbm<S, C, false, 2><<<nblk, 256, 0, s>>>(A);
+        else if (psm) k_lbm<S, C, false, 4><<<nblk, 256, 0, s>>>(A);
     }
     return hipGetLastError();
 }

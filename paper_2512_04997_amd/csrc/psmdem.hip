@@ -195,6 +195,10 @@ static int validate(const psmdem_desc* d, const psmdem_particles* P) {
     if (d->sf_method < 0 || d->sf_method > 1) { psm_set_error("invalid sf_method"); return 0; }
     if (d->sf_subdiv < 1 || d->sf_subdiv > 32) { psm_set_error("sf_subdiv must be in 1..32"); return 0; }
     if (d->max_solids < 1 || d->max_solids > PSM_SLOTS_MAX) { psm_set_error("max_solids must be in 1..4"); return 0; }
+    if (d->collision < 0 || d->collision > 1) { psm_set_error("invalid collision operator"); return 0; }
+    if (d->collision == 1 && !(d->trt_magic >= 0.0 && d->trt_magic < 1e6)) {
+        psm_set_error("trt_magic must be 0 (the paper's rule) or a positive magic parameter"); return 0;
+    }
     if (d->kolm_amp != 0.0 && (d->kolm_axis < 0 || d->kolm_axis > 2 || d->kolm_dir < 0 || d->kolm_dir > 2)) {
         psm_set_error("invalid Kolmogorov axis"); return 0;
     }

@@ -20,6 +20,7 @@ _lib = None
 OK, E_INVALID, E_NOMEM, E_CAPACITY, E_UNSTABLE, E_HIP, E_STATE, E_NODEVICE = 0, -1, -2, -3, -4, -5, -6, -7
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
 BC = {"periodic": 0, "noslip": 1, "moving": 2}
+COLLISION = {"bgk": 0, "trt": 1}
 STAGE = {"lists": 0, "voxelize": 1, "lbm": 2, "contacts": 3}
 TIMER = {"lbm": 0, "voxel": 1, "dem": 2, "hydro": 3}
 
@@ -44,6 +45,7 @@ class Desc(C.Structure):
         ("kn", C.c_double), ("restitution", C.c_double), ("mu", C.c_double),
         ("kt_ratio", C.c_double), ("gt_ratio", C.c_double),
         ("max_solids", C.c_int32), ("pair_capacity", C.c_int64),
+        ("collision", C.c_int32), ("trt_magic", C.c_double),
     ]
 
 
@@ -191,6 +193,8 @@ def make_desc(cfg):
     d.gt_ratio = float(cfg.get("gt_ratio", 1.0))
     d.max_solids = int(cfg.get("max_solids", 2))
     d.pair_capacity = int(cfg.get("pair_capacity", 0))
+    d.collision = COLLISION[cfg.get("collision", "bgk")]
+    d.trt_magic = float(cfg.get("trt_magic", 0.0))
     return d
 
 

@@ -48,15 +48,24 @@ def _walled(n, tau, prec, **kw):
 
 # --------------------------------------------------------------------------- LBM only
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("kind", ["periodic", "walls_forcing", "walls_every_face"])
+@pytest.mark.parametrize("kind", ["periodic", "walls_forcing", "walls_every_face", "trt_walls_forcing",
+                                  "trt_magic_every_face"])
 def test_lbm_matches_oracle(ps, oracle_mod, prec, kind):
     """Ragged lattice (tiles of 64x4x4 cut in every axis), random near-equilibrium
-    populations; several steps cover both in-place parities."""
+    populations; several steps cover both in-place parities.  The TRT cases take
+    the paper's tau- rule and a free magic parameter."""
     n = (70, 9, 6)
     if kind == "periodic":
         cfg = W.base_config(n, 0.63, precision=prec)
-    elif kind == "walls_forcing":
-        cfg = _walled(n, 0.81, prec, body_force=[1e-5, -2e-6, 0.0], kolm_amp=3e-6, kolm_axis=2, kolm_dir=1)
+    elif kind in ("walls_forcing", "trt_walls_forcing"):
+        cfg = _walled(n, 0.81, prec, body_force=[1e-5, -2e-6, 0.0], kolm_amp=3e-6, kolm_axis=2, kolm_dir=1,
+                      collision="trt" if kind.startswith("trt") else "bgk")
+    elif kind == "trt_magic_every_face":
+        wu = [[0.0] * 3 for _ in range(6)]
+        wu[1] = [0.0, 0.01, 0.02]
+        wu[4] = [0.015, 0.0, 0.0]
+        cfg = W.base_config(n, 0.57, precision=prec, bc=["noslip", "moving", "noslip", "noslip", "moving", "noslip"],
+                            wall_u=wu, body_force=[2e-6, 0.0, -3e-6], collision="trt", trt_magic=0.07)
     else:
         wu = [[0.0] * 3 for _ in range(6)]
         wu[0] = [0.0, 0.015, -0.01]
@@ -203,12 +212,15 @@ def test_settling_sphere_trajectory_fp64(ps, oracle_mod):
     assert O.counters()["step"] == 200
 
 
+@pytest.mark.parametrize("collision", ["bgk", "trt"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_couette_suspension_steps(ps, oracle_mod, prec):
+def test_couette_suspension_steps(ps, oracle_mod, prec, collision):
     """Bounded Couette shear with spheres (48^3, moving walls, contacts and wall
-    contacts): three coupled steps from creation."""
+    contacts): three coupled steps from creation, with the BGK or the TRT
+    fluid operator inside the PSM collision."""
     cfg, parts, _ = W.couette_suspension(precision=prec, n=48, nsph=30, radius=4.0)
     cfg["mu"] = 0.3
+    cfg["collision"] = collision
     G, O = _pair(ps, oracle_mod, cfg, parts)
     assert G.n_sub == O.n_sub
     for _ in range(3):

@@ -25,7 +25,8 @@ def ps():
 
 def _jobs(prec="fp32"):
     """Uneven jobs: ragged tiles in every axis, settling and shear, a
-    fluid-only job, one with three solids per cell, and different step counts."""
+    fluid-only job with the TRT operator, one with three solids per cell, and
+    different step counts."""
     rng = W.SplitMix64(77)
     out = []
     cfg, parts = W.serving_job(rng, "settle", 32, 0.62, 12, precision=prec)
@@ -40,7 +41,7 @@ def _jobs(prec="fp32"):
     cfg = W.base_config(box, 0.85, bc=bc, wall_u=wu, precision=prec)
     out.append((cfg, W.spheres(pos, radii[:len(pos)], 1.5), 5))
     cfg = W.base_config((48, 22, 26), 0.7, precision=prec, bc=["periodic"] * 4 + ["noslip"] * 2,
-                        body_force=[2e-6, 0.0, 0.0])
+                        body_force=[2e-6, 0.0, 0.0], collision="trt")
     out.append((cfg, None, 6))
     cfg, parts = W.serving_job(rng, "shear", 32, 0.58, 10, precision=prec)
     cfg["max_solids"] = 3

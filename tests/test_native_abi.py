@@ -46,6 +46,13 @@ def test_invalid_description_is_rejected_without_a_device():
                                                     "periodic", "periodic"]))
     code = L.psmdem_create(ctypes.byref(d), None, None, P.ALLOC_FN(), P.FREE_FN(), None, ctypes.byref(h))
     assert code == P.E_INVALID
+    d = P.make_desc(dict(n=(8, 8, 8), tau=0.8, collision="trt"))
+    d.collision = 2
+    code = L.psmdem_create(ctypes.byref(d), None, None, P.ALLOC_FN(), P.FREE_FN(), None, ctypes.byref(h))
+    assert code == P.E_INVALID and b"collision" in L.psmdem_last_error()
+    d = P.make_desc(dict(n=(8, 8, 8), tau=0.8, collision="trt", trt_magic=-0.1))
+    code = L.psmdem_create(ctypes.byref(d), None, None, P.ALLOC_FN(), P.FREE_FN(), None, ctypes.byref(h))
+    assert code == P.E_INVALID and b"trt_magic" in L.psmdem_last_error()
 
 
 def _r256(n):
