@@ -507,9 +507,11 @@ __device__ inline long long n_pairs(const DemArgs& A, const PairBufs& B) {
 // v_rel = (v_i - v_j) - (rho_i w_i + rho_j w_j) x e_n, v_t its tangential part;
 // history projected on the tangent plane then advanced by v_t dt;
 // F_t = -k_t d_t - gamma_t v_t capped at mu |F_n| with the history reset.
+// same_list: the previous list holds the same keys in the same order, so the
+// history of pair s sits at index s.
 template <bool ELL>
 __device__ void ph_contact(const DemArgs& A, const PairBufs& B, long long s, const double* __restrict__ vv,
-                           const double* __restrict__ ww, double dth, long long nprev) {
+                           const double* __restrict__ ww, double dth, long long nprev, bool same_list = false) {
     const int np = A.p.np;
     const unsigned long long key = B.pairs[s];
     const int i = (int)(key >> 32), j = (int)(key & 0xffffffffu);
@@ -544,7 +546,7 @@ __device__ void ph_contact(const DemArgs& A, const PairBufs& B, long long s, con
             wj[k] = ww[3 * j + k];
         }
     }
-    const long long ps = find_prev(B, key, nprev);
+    const long long ps = same_list ? s : find_prev(B, key, nprev);
     double ho[3] = {0.0, 0.0, 0.0};
     if (ps >= 0)
         for (int k = 0; k < 3; ++k) ho[k] = B.prev_hist[3 * ps + k];
@@ -1119,6 +1121,11 @@ __device__ int merged_row(const DemArgs& A, int i, const unsigned* cells_s, cons
 //            LDS, then each particle sums its column and its own row.
 // Larger grids test every i < j for a shared cell (64 partners per ballot);
 // longer pair lists search each (k, i) pair in row k.
+// The pair list is a function of the particles' cells and wall candidates
+// alone: a substep in which none of them changed keeps the list (and the
+// column lists) of the last rebuild.  One substep after a rebuild the list is
+// copied into the other buffer; from then on both buffers hold it.  History
+// is then found at the pair's own index.
 template <bool ELL>
 __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, const PairSet& P, int cur, const int nsub, const double dt,
                                const int stop_before_correct) {
@@ -1128,11 +1135,15 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
     __shared__ unsigned short cpid_s[8 * DEM_FUSED_MAX];
     __shared__ unsigned long long prev_s[FUSED_PREV_LDS];
     __shared__ unsigned short col_s[FUSED_COLS];
+    __shared__ unsigned char wmask_s[DEM_FUSED_MAX];
     const int np = A.p.np, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int nw = FUSED_T / 64;
     const unsigned long long lanes_below = (1ull << lane) - 1ull;
     const bool lds_cells = A.ncell <= FUSED_CELLS;
     const int ncell = (int)A.ncell;
+    if (lds_cells)
+        for (int u = tid; u <= ncell; u += FUSED_T) cst_s[u] = 0;
+    int age = 0;  // substeps since the list was last rebuilt
     for (int sub = 0; sub < nsub; ++sub) {
         const bool last = sub == nsub - 1;
         const int c = cur ^ 1;
@@ -1143,18 +1154,37 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
         B.hist = c ? P.hist[1] : P.hist[0];
         B.prev_pairs = c ? P.pairs[0] : P.pairs[1];
         B.prev_hist = c ? P.hist[0] : P.hist[1];
-        B.prev_n = (c ? P.prow[0] : P.prow[1]) + np;
-        if (lds_cells)
-            for (int u = tid; u <= ncell; u += FUSED_T) cst_s[u] = 0;
+        const int* prev_prow = c ? P.prow[0] : P.prow[1];
+        B.prev_n = prev_prow + np;
+        int changed = sub == 0;
         for (int k = tid; k < np; k += FUSED_T) {
             AxCells r;
             ph_predict(A, k, dt, last ? 1 : 0, r);
             store_cells(A, k, r);
+            unsigned wm = 0;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) cells_s[3 * k + a] = pack_axis(r, a);
+            for (int f = 0; f < 6; ++f) wm |= (A.g.bc[f] != 0 && wall_dist(A, k, f) < A.p.rb[k]) ? 1u << f : 0u;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const unsigned pk = pack_axis(r, a);
+                changed |= pk != cells_s[3 * k + a];
+                cells_s[3 * k + a] = pk;
+            }
+            changed |= wm != wmask_s[k];
+            wmask_s[k] = (unsigned char)wm;
         }
-        __syncthreads();
-        if (lds_cells) {
+        const bool rebuild = __syncthreads_or(changed) != 0;
+        age = rebuild ? 0 : age + 1;
+        if (!rebuild) {
+            // the previous list is this list: one substep after the rebuild it
+            // is copied into this buffer, later this buffer already holds it
+            if (age == 1) {
+                long long n = *B.prev_n;
+                n = n < A.pair_cap ? n : A.pair_cap;
+                for (long long u = tid; u < n; u += FUSED_T) B.pairs[u] = B.prev_pairs[u];
+                for (int u = tid; u <= np; u += FUSED_T) B.prow[u] = prev_prow[u];
+            }
+        } else if (lds_cells) {
             // counting sort of the registrations by cell
             for (int k = tid; k < np; k += FUSED_T) {
                 const unsigned px = cells_s[3 * k], py = cells_s[3 * k + 1], pz = cells_s[3 * k + 2];
@@ -1201,59 +1231,65 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
                 if (lane == 0) cnt_s[i] = cnt + wall_count(A, i);
             }
         }
-        __syncthreads();
-        psm_block_scan<FUSED_T>(cnt_s, B.prow, np);
-        // rows: ascending j, then walls
-        if (lds_cells) {
-            for (int i = tid; i < np; i += FUSED_T) {
-                const long long at = B.prow[i];
-                const long long room = A.pair_cap - at;
-                long long e = at;
-                if (room > 0) e += merged_row<true>(A, i, cells_s, cst_s, cpid_s, B.pairs + at, room);
-                for (int f = 0; f < 6; ++f)
-                    if (A.g.bc[f] != 0 && wall_dist(A, i, f) < A.p.rb[i]) {
-                        if (e < A.pair_cap) B.pairs[e] = ((unsigned long long)i << 32) | (unsigned)(np + f);
-                        ++e;
-                    }
-                if (e > A.pair_cap) atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_PAIRS);
-            }
-        } else {
-            for (int i = wid; i < np; i += nw) {
-                const unsigned pi0 = cells_s[3 * i], pi1 = cells_s[3 * i + 1], pi2 = cells_s[3 * i + 2];
-                long long at = B.prow[i];
-                for (int j0 = i + 1; j0 < np; j0 += 64) {
-                    const int j = j0 + lane;
-                    const bool ok = j < np && axis_meet(pi0, cells_s[3 * j]) && axis_meet(pi1, cells_s[3 * j + 1]) &&
-                                    axis_meet(pi2, cells_s[3 * j + 2]);
-                    const unsigned long long m = __ballot(ok);
-                    const long long pos = at + __popcll(m & lanes_below);
-                    if (ok && pos < A.pair_cap) B.pairs[pos] = ((unsigned long long)i << 32) | (unsigned)j;
-                    at += __popcll(m);
-                }
-                if (lane == 0) {
+        if (rebuild) {
+            __syncthreads();
+            psm_block_scan<FUSED_T>(cnt_s, B.prow, np);
+            // rows: ascending j, then walls
+            if (lds_cells) {
+                for (int i = tid; i < np; i += FUSED_T) {
+                    const long long at = B.prow[i];
+                    const long long room = A.pair_cap - at;
+                    long long e = at;
+                    if (room > 0) e += merged_row<true>(A, i, cells_s, cst_s, cpid_s, B.pairs + at, room);
                     for (int f = 0; f < 6; ++f)
                         if (A.g.bc[f] != 0 && wall_dist(A, i, f) < A.p.rb[i]) {
-                            if (at < A.pair_cap) B.pairs[at] = ((unsigned long long)i << 32) | (unsigned)(np + f);
-                            ++at;
+                            if (e < A.pair_cap) B.pairs[e] = ((unsigned long long)i << 32) | (unsigned)(np + f);
+                            ++e;
                         }
-                    if (at > A.pair_cap) atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_PAIRS);
+                    if (e > A.pair_cap) atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_PAIRS);
+                }
+            } else {
+                for (int i = wid; i < np; i += nw) {
+                    const unsigned pi0 = cells_s[3 * i], pi1 = cells_s[3 * i + 1], pi2 = cells_s[3 * i + 2];
+                    long long at = B.prow[i];
+                    for (int j0 = i + 1; j0 < np; j0 += 64) {
+                        const int j = j0 + lane;
+                        const bool ok = j < np && axis_meet(pi0, cells_s[3 * j]) && axis_meet(pi1, cells_s[3 * j + 1]) &&
+                                        axis_meet(pi2, cells_s[3 * j + 2]);
+                        const unsigned long long m = __ballot(ok);
+                        const long long pos = at + __popcll(m & lanes_below);
+                        if (ok && pos < A.pair_cap) B.pairs[pos] = ((unsigned long long)i << 32) | (unsigned)j;
+                        at += __popcll(m);
+                    }
+                    if (lane == 0) {
+                        for (int f = 0; f < 6; ++f)
+                            if (A.g.bc[f] != 0 && wall_dist(A, i, f) < A.p.rb[i]) {
+                                if (at < A.pair_cap) B.pairs[at] = ((unsigned long long)i << 32) | (unsigned)(np + f);
+                                ++at;
+                            }
+                        if (at > A.pair_cap) atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_PAIRS);
+                    }
                 }
             }
         }
         long long nprev = *B.prev_n;
         nprev = nprev < A.pair_cap ? nprev : A.pair_cap;
-        const bool prev_in_lds = nprev <= FUSED_PREV_LDS;
+        const bool prev_in_lds = rebuild && nprev <= FUSED_PREV_LDS;
         if (prev_in_lds)
             for (long long u = tid; u < nprev; u += FUSED_T) prev_s[u] = B.prev_pairs[u];
         __syncthreads();
+        // the cell list is consumed: cleared for the next rebuild
+        if (rebuild && lds_cells)
+            for (int u = tid; u <= ncell; u += FUSED_T) cst_s[u] = 0;
         const long long npairs = n_pairs(A, B);
         {
             PairBufs BL = B;
             if (prev_in_lds) BL.prev_pairs = prev_s;
-            for (long long s = tid; s < npairs; s += FUSED_T) ph_contact<ELL>(A, BL, s, A.p.vp, A.p.wp, dt, nprev);
+            for (long long s = tid; s < npairs; s += FUSED_T)
+                ph_contact<ELL>(A, BL, s, A.p.vp, A.p.wp, dt, nprev, !rebuild);
         }
         const bool lds_cols = npairs <= FUSED_COLS;
-        if (lds_cols) {
+        if (rebuild && lds_cols) {
             // column lists: pairs by second member, ascending pair index
             for (int k = tid; k <= np; k += FUSED_T) cnt_s[k] = 0;
             __syncthreads();

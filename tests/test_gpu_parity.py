@@ -280,6 +280,38 @@ def test_dem_multi_launch_path(ps, oracle_mod):
     assert O.counters()["contacts"] > 50
 
 
+@pytest.mark.parametrize("kind", ["fast", "dense_slow"])
+def test_fused_dem_list_reuse(ps, oracle_mod, kind):
+    """The single-workgroup DEM keeps the pair list while no particle changes
+    its cells or wall candidates.  'fast': particles cross cells within a
+    launch, so rebuilt and kept lists alternate; 'dense_slow': overlapping,
+    slowly moving spheres keep their list for many substeps with contacts,
+    friction and wall contacts, so the history is carried at the kept index."""
+    box = (48, 40, 36)
+    rng = W.SplitMix64(4242 if kind == "fast" else 4343)
+    n = 400
+    radii = 1.4 + 0.6 * rng.uniform(n)
+    gap = 0.2 if kind == "fast" else -0.6
+    pos = W.rsa_spheres(rng, n, radii, box, [True, True, False], gap=gap)
+    m = len(pos)
+    amp = 0.05 if kind == "fast" else 0.004
+    vel = amp * (rng.uniform(3 * m).reshape(m, 3) - 0.5)
+    parts = W.spheres(pos, radii[:m], 1.6, vel=vel)
+    cfg = _walled(box, 0.7, "fp64", fluid_on=False, mu=0.3, restitution=0.7, n_sub=9,
+                  gravity=[0.0, 0.0, -2e-4])
+    G, O = _pair(ps, oracle_mod, cfg, parts)
+    for _ in range(4):
+        G.step(1)
+        O.step(1)
+        assert np.array_equal(G.pairs()[0], O.pairs()[0])
+        Pg, Po = G.particles(), O.particles()
+        assert vec_err(Pg["pos"], Po["pos"]) < 1e-12
+        assert vec_err(Pg["vel"], Po["vel"]) < 1e-12
+        assert force_err(Pg["f_dem"], Po["f_dem"], O.scales()["f_dem"], force_floor(O)) < 1e-12
+    if kind == "dense_slow":
+        assert O.counters()["contacts"] > 20
+
+
 def test_couette_full_size_fp32(ps, oracle_mod):
     """The bench workload at its full size (128^3, 500 spheres R = 5, moving
     walls, n_sub = 11) in the bench's precision: two coupled steps from
