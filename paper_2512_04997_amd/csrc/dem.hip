@@ -509,8 +509,9 @@ __device__ inline long long n_pairs(const DemArgs& A, const PairBufs& B) {
 // F_t = -k_t d_t - gamma_t v_t capped at mu |F_n| with the history reset.
 // same_list: the previous list holds the same keys in the same order, so the
 // history of pair s sits at index s.
+// Returns whether the pair is in contact.
 template <bool ELL>
-__device__ void ph_contact(const DemArgs& A, const PairBufs& B, long long s, const double* __restrict__ vv,
+__device__ bool ph_contact(const DemArgs& A, const PairBufs& B, long long s, const double* __restrict__ vv,
                            const double* __restrict__ ww, double dth, long long nprev, bool same_list = false) {
     const int np = A.p.np;
     const unsigned long long key = B.pairs[s];
@@ -534,7 +535,7 @@ __device__ void ph_contact(const DemArgs& A, const PairBufs& B, long long s, con
     if (!(G.delta > 0.0)) {
         for (int k = 0; k < 3; ++k) F[k] = Mi[k] = Mj[k] = h[k] = 0.0;
         A.incontact[s] = 0;
-        return;
+        return false;
     }
     double vi[3], wi[3], vj[3], wj[3];
     const double mi = A.p.mass[i], mj = wall ? 0.0 : A.p.mass[j];
@@ -603,6 +604,7 @@ __device__ void ph_contact(const DemArgs& A, const PairBufs& B, long long s, con
         if (j < np) cross3(G.rcj, mF, Mj);
         else Mj[0] = Mj[1] = Mj[2] = 0.0;
     }
+    return true;
 }
 
 __device__ void ph_colhist(const DemArgs& A, const PairBufs& B, long long s) {
@@ -1136,6 +1138,7 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
     __shared__ unsigned long long prev_s[FUSED_PREV_LDS];
     __shared__ unsigned short col_s[FUSED_COLS];
     __shared__ unsigned char wmask_s[DEM_FUSED_MAX];
+    __shared__ unsigned char inc_s[FUSED_COLS];  // pair in contact (lists up to FUSED_COLS)
     const int np = A.p.np, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int nw = FUSED_T / 64;
     const unsigned long long lanes_below = (1ull << lane) - 1ull;
@@ -1143,7 +1146,8 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
     const int ncell = (int)A.ncell;
     if (lds_cells)
         for (int u = tid; u <= ncell; u += FUSED_T) cst_s[u] = 0;
-    int age = 0;  // substeps since the list was last rebuilt
+    int age = 0;            // substeps since the list was last rebuilt
+    bool keys_lds = false;  // the kept list's keys are staged in prev_s
     for (int sub = 0; sub < nsub; ++sub) {
         const bool last = sub == nsub - 1;
         const int c = cur ^ 1;
@@ -1175,6 +1179,7 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
         }
         const bool rebuild = __syncthreads_or(changed) != 0;
         age = rebuild ? 0 : age + 1;
+        if (rebuild) keys_lds = false;
         if (!rebuild) {
             // the previous list is this list: one substep after the rebuild it
             // is copied into this buffer, later this buffer already holds it
@@ -1282,17 +1287,25 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
         if (rebuild && lds_cells)
             for (int u = tid; u <= ncell; u += FUSED_T) cst_s[u] = 0;
         const long long npairs = n_pairs(A, B);
+        const bool lds_cols = npairs <= FUSED_COLS;
         {
             PairBufs BL = B;
             if (prev_in_lds) BL.prev_pairs = prev_s;
-            for (long long s = tid; s < npairs; s += FUSED_T)
-                ph_contact<ELL>(A, BL, s, A.p.vp, A.p.wp, dt, nprev, !rebuild);
+            if (!rebuild && keys_lds) BL.pairs = prev_s;
+            for (long long s = tid; s < npairs; s += FUSED_T) {
+                const bool in = ph_contact<ELL>(A, BL, s, A.p.vp, A.p.wp, dt, nprev, !rebuild);
+                if (lds_cols) inc_s[s] = in ? 1 : 0;
+            }
         }
-        const bool lds_cols = npairs <= FUSED_COLS;
         if (rebuild && lds_cols) {
             // column lists: pairs by second member, ascending pair index
             for (int k = tid; k <= np; k += FUSED_T) cnt_s[k] = 0;
             __syncthreads();
+            // the history search is done: prev_s takes this list's keys for
+            // the substeps that keep it
+            keys_lds = npairs <= FUSED_PREV_LDS;
+            if (keys_lds)
+                for (int s = tid; s < (int)npairs; s += FUSED_T) prev_s[s] = B.pairs[s];
             for (int s = tid; s < (int)npairs; s += FUSED_T) {
                 const unsigned j = (unsigned)(B.pairs[s] & 0xffffffffu);
                 if (j < (unsigned)np) atomicAdd(&cnt_s[j], 1);
@@ -1322,6 +1335,7 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
                 const int s0 = i > 0 ? cnt_s[i - 1] : 0, s1 = cnt_s[i];
                 for (int u = s0; u < s1; ++u) {
                     const long long s = col_s[u];
+                    if (!inc_s[s]) continue;  // zero terms leave a sum unchanged
 #pragma unroll
                     for (int q = 0; q < 3; ++q) {
                         F[q] -= A.cF[3 * s + q];
@@ -1350,12 +1364,14 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
             }
             long long s0 = B.prow[i], s1 = B.prow[i + 1];
             s1 = s1 < A.pair_cap ? s1 : A.pair_cap;
-            for (long long s = s0; s < s1; ++s)
+            for (long long s = s0; s < s1; ++s) {
+                if (lds_cols && !inc_s[s]) continue;
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
                     F[q] += A.cF[3 * s + q];
                     M[q] += A.cMi[3 * s + q];
                 }
+            }
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 A.p.fd[3 * i + q] = F[q];

@@ -11,7 +11,7 @@
 //   k_tile_sort    order each tile's list by pid; inverse map emission -> position
 //   k_vox_classify per tile: cells whose samples straddle a surface, queued as
 //                  items of the step (exact inside / outside shortcuts elsewhere)
-//   k_vox_sample   one wave per queued cell: its count of inside samples
+//   k_vox_sample   a lane per queued sphere cell (a wave per other cell): its count of inside samples
 //   k_vox_select   per tile: beta of every (cell, particle), keep the max_solids
 //                  largest (ties to the smaller pid), B_k, slots
 //   k_reduce_hydro per particle: minus the sum of its tile partials (F, M)
@@ -760,7 +760,59 @@ __global__ __launch_bounds__(VOX_T) void k_vox_classify(VoxArgs A) {
     }
 }
 
-// 2. every boundary cell of the step: one wave counts its inside samples
+// Inside samples of a sphere in cell (X, Y, Z), counted by ONE LANE: the
+// squared x offsets stay in registers, the y and z ones are formed per row
+// and layer; every sample is tested with the rounding and evaluation order of
+// the definition.  No cross-lane traffic, so a wave counts 64 cells at once
+// and its loads overlap freely.
+template <int NS>
+__device__ inline int sphere_count_lane(double c0, double c1, double c2, double R, int X, int Y, int Z,
+                                        const double* off) {
+    double x2[NS];
+#pragma unroll
+    for (int a = 0; a < NS; ++a) {
+        const double dx = ((double)X + off[a]) - c0;
+        x2[a] = dx * dx;
+    }
+    const double R2 = R * R;
+    int cnt = 0;
+#pragma unroll 1
+    for (int c = 0; c < NS; ++c) {
+        const double dz = ((double)Z + off[c]) - c2;
+        const double z2 = dz * dz;
+#pragma unroll 1
+        for (int b = 0; b < NS; ++b) {
+            const double dy = ((double)Y + off[b]) - c1;
+            const double y2 = dy * dy;
+#pragma unroll
+            for (int a = 0; a < NS; ++a) cnt += ((x2[a] + y2) + z2) < R2 ? 1 : 0;
+        }
+    }
+    return cnt;
+}
+
+__device__ inline int sphere_count_lane_ns(int ns, double c0, double c1, double c2, double R, int X, int Y, int Z,
+                                           const double* off) {
+    switch (ns) {
+        case 1: return sphere_count_lane<1>(c0, c1, c2, R, X, Y, Z, off);
+        case 2: return sphere_count_lane<2>(c0, c1, c2, R, X, Y, Z, off);
+        case 3: return sphere_count_lane<3>(c0, c1, c2, R, X, Y, Z, off);
+        case 4: return sphere_count_lane<4>(c0, c1, c2, R, X, Y, Z, off);
+        case 5: return sphere_count_lane<5>(c0, c1, c2, R, X, Y, Z, off);
+        case 6: return sphere_count_lane<6>(c0, c1, c2, R, X, Y, Z, off);
+        case 7: return sphere_count_lane<7>(c0, c1, c2, R, X, Y, Z, off);
+        case 8: return sphere_count_lane<8>(c0, c1, c2, R, X, Y, Z, off);
+        case 9: return sphere_count_lane<9>(c0, c1, c2, R, X, Y, Z, off);
+        case 10: return sphere_count_lane<10>(c0, c1, c2, R, X, Y, Z, off);
+        case 11: return sphere_count_lane<11>(c0, c1, c2, R, X, Y, Z, off);
+        default: return sphere_count_lane<12>(c0, c1, c2, R, X, Y, Z, off);
+    }
+}
+
+// 2. every boundary cell of the step.  Each wave takes 64 consecutive items,
+// one per lane: sphere cells (up to VOX_NS_REG samples per direction) are
+// counted by their own lane; the wave then counts the remaining cells of its
+// chunk (ellipsoids, finer sampling) one after the other, all lanes together.
 __global__ __launch_bounds__(VOX_T) void k_vox_sample(VoxArgs A) {
     __shared__ VoxPart pw[VOX_T / 64];
     __shared__ double off[32];
@@ -770,27 +822,46 @@ __global__ __launch_bounds__(VOX_T) void k_vox_sample(VoxArgs A) {
     __syncthreads();
     long long n = (long long)A.ctr->items;
     n = n < A.item_cap ? n : A.item_cap;
-    const long long nw = (long long)gridDim.x * (VOX_T / 64);
+    if (n <= 0) return;
+    const int ns = A.ns;
+    const long long nchunk = (long long)gridDim.x * (VOX_T / 64);
     double* tab = tab_s + wid * (9 * 32);
     VoxPart& P = pw[wid];
-    for (long long i = (long long)blockIdx.x * (VOX_T / 64) + wid; i < n; i += nw) {
-        const int4 it = A.items[i];
+    for (long long base = ((long long)blockIdx.x * (VOX_T / 64) + wid) * 64; base < n; base += nchunk * 64) {
+        const long long i = base + lane;
+        const bool valid = i < n;
+        // lanes past the end re-read the last item (never stored)
+        const int4 it = A.items[valid ? i : n - 1];
         const int k = it.w < A.p.np ? it.w : 0;
-        if (lane == 0) {
-            P.pid = k;
-            P.shape = A.p.shape[k];
-            for (int a = 0; a < 3; ++a) {
-                P.c[a] = A.p.pos[3 * k + a];
-                P.ax[a] = A.p.semi[3 * k + a];
-                P.inv[a] = 1.0 / (P.ax[a] * P.ax[a]);
-            }
-            quat_rbw(A.p.q + 4 * k, P.R);
+        const int shape = A.p.shape[k];
+        const bool lane_sph = valid && shape == 0 && ns <= VOX_NS_REG;
+        if (lane_sph) {
+            const int cnt = sphere_count_lane_ns(ns, A.p.pos[3 * k], A.p.pos[3 * k + 1], A.p.pos[3 * k + 2],
+                                                 A.p.semi[3 * k], it.x, it.y, it.z, off);
+            A.item_cnt[i] = cnt;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int cnt = sample_count(P, it.x, it.y, it.z, off, A.ns, tab);
-        if (lane == 0) A.item_cnt[i] = cnt;
+        unsigned long long rest = __ballot(valid && !lane_sph);
+        while (rest) {
+            const int l = __ffsll((long long)rest) - 1;
+            rest &= rest - 1;
+            const int X = __shfl(it.x, l, 64), Y = __shfl(it.y, l, 64), Z = __shfl(it.z, l, 64);
+            const int kk = __shfl(k, l, 64);
+            if (lane == 0) {
+                P.pid = kk;
+                P.shape = A.p.shape[kk];
+                for (int a = 0; a < 3; ++a) {
+                    P.c[a] = A.p.pos[3 * kk + a];
+                    P.ax[a] = A.p.semi[3 * kk + a];
+                    P.inv[a] = 1.0 / (P.ax[a] * P.ax[a]);
+                }
+                quat_rbw(A.p.q + 4 * kk, P.R);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const int cnt = sample_count(P, X, Y, Z, off, ns, tab);
+            if (lane == 0) A.item_cnt[base + l] = cnt;
+        }
     }
 }
 
@@ -906,8 +977,8 @@ hipError_t vox_voxelize(const VoxArgs& A, int ctype_double, hipStream_t s) {
     const unsigned nt = (unsigned)A.g.ntiles;
     if (A.sf_method == 0) {
         k_vox_classify<<<nt, VOX_T, 0, s>>>(A);
-        // enough waves to fill the GPU; each walks the item list with a stride
-        long long nb = (A.item_cap + VOX_T / 64 - 1) / (VOX_T / 64);
+        // one wave per 64 items, up to 4096 workgroups; the waves stride over the rest
+        long long nb = (A.item_cap + VOX_T - 1) / VOX_T;
         nb = nb < 4096 ? nb : 4096;
         k_vox_sample<<<(unsigned)(nb > 0 ? nb : 1), VOX_T, 0, s>>>(A);
     }
