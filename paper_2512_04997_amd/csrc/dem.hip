@@ -509,10 +509,12 @@ __device__ inline long long n_pairs(const DemArgs& A, const PairBufs& B) {
 // F_t = -k_t d_t - gamma_t v_t capped at mu |F_n| with the history reset.
 // same_list: the previous list holds the same keys in the same order, so the
 // history of pair s sits at index s.
-// Returns whether the pair is in contact.
+// Returns whether the pair is in contact; out of contact, *gap (when given)
+// receives the separation -delta.
 template <bool ELL>
 __device__ bool ph_contact(const DemArgs& A, const PairBufs& B, long long s, const double* __restrict__ vv,
-                           const double* __restrict__ ww, double dth, long long nprev, bool same_list = false) {
+                           const double* __restrict__ ww, double dth, long long nprev, bool same_list = false,
+                           double* gap = nullptr) {
     const int np = A.p.np;
     const unsigned long long key = B.pairs[s];
     const int i = (int)(key >> 32), j = (int)(key & 0xffffffffu);
@@ -535,6 +537,7 @@ __device__ bool ph_contact(const DemArgs& A, const PairBufs& B, long long s, con
     if (!(G.delta > 0.0)) {
         for (int k = 0; k < 3; ++k) F[k] = Mi[k] = Mj[k] = h[k] = 0.0;
         A.incontact[s] = 0;
+        if (gap) *gap = -G.delta;
         return false;
     }
     double vi[3], wi[3], vj[3], wj[3];
@@ -701,7 +704,8 @@ __device__ inline void quat_rate(const double* w, const double* q, double* out) 
 // w^p = w + alpha dt, quaternion advanced by a midpoint step of q' = q (0, w)/2
 // and renormalised.  Every input is loaded before the first store; the new
 // position and orientation then give the particle's registration cells.
-__device__ void ph_predict(const DemArgs& A, int k, double dt, int write_kin, AxCells& cells) {
+__device__ void ph_predict(const DemArgs& A, int k, double dt, int write_kin, AxCells& cells,
+                           double* disp = nullptr) {
     double x[3], v[3], a[3], w[3], al[3], q0[4], sm[3];
     const int shape = A.p.shape[k];
 #pragma unroll
@@ -760,6 +764,13 @@ __device__ void ph_predict(const DemArgs& A, int k, double dt, int write_kin, Ax
     double e[3];
     half_extents_of(shape, sm, qn, e);
     axis_cells_at(A, xn, e, cells);
+    // an upper bound of the distance moved (L1 norm of the exact step)
+    if (disp) {
+        double d = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) d += fabs(dt * v[c]) + fabs(hdt2 * a[c]);
+        *disp = d;
+    }
 }
 
 // alpha = Rbw I^-1 [Rbw^T M - (Rbw^T w) x (I Rbw^T w)] at the substep start (as printed)
@@ -1041,6 +1052,7 @@ __global__ void k_zero_d(double* p, long long n) { GRID_LOOP(i, n) p[i] = 0.0; }
 #define FUSED_PREV_LDS 3072   // previous pair keys staged in LDS for the history search
 #define FUSED_CELLS 8192      // DEM grids up to this many cells keep their cell list in LDS
 #define FUSED_COLS 8192       // pair lists up to this length keep their column lists in LDS
+#define FUSED_SKIP_EPS 1e-9   // separation margin above the rounding of positions and distances
 
 __device__ inline unsigned pack_axis(const AxCells& r, int a) {
     return (unsigned)r.c[a][0] | ((unsigned)r.c[a][1] << 16);
@@ -1128,13 +1140,20 @@ __device__ int merged_row(const DemArgs& A, int i, const unsigned* cells_s, cons
 // column lists) of the last rebuild.  One substep after a rebuild the list is
 // copied into the other buffer; from then on both buffers hold it.  History
 // is then found at the pair's own index.
+// Sphere pairs of a kept list (up to FUSED_PREV_LDS) also carry their last
+// separation and each particle the distance it has moved since (an upper
+// bound): a pair out of contact at its last two evaluations whose separation
+// exceeds the two particles' movement since by FUSED_SKIP_EPS is still out of
+// contact, and its outputs and both history buffers already hold zeros, so it
+// is not evaluated again.  These live in the cell-list space, which a kept
+// list does not use.
 template <bool ELL>
 __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, const PairSet& P, int cur, const int nsub, const double dt,
                                const int stop_before_correct) {
     __shared__ unsigned cells_s[3 * DEM_FUSED_MAX];
     __shared__ int cnt_s[DEM_FUSED_MAX + 1];
-    __shared__ int cst_s[FUSED_CELLS + 1];
-    __shared__ unsigned short cpid_s[8 * DEM_FUSED_MAX];
+    __shared__ __align__(16) int cst_s[FUSED_CELLS + 1];
+    __shared__ __align__(16) unsigned short cpid_s[8 * DEM_FUSED_MAX];
     __shared__ unsigned long long prev_s[FUSED_PREV_LDS];
     __shared__ unsigned short col_s[FUSED_COLS];
     __shared__ unsigned char wmask_s[DEM_FUSED_MAX];
@@ -1144,8 +1163,13 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
     const unsigned long long lanes_below = (1ull << lane) - 1ull;
     const bool lds_cells = A.ncell <= FUSED_CELLS;
     const int ncell = (int)A.ncell;
-    if (lds_cells)
-        for (int u = tid; u <= ncell; u += FUSED_T) cst_s[u] = 0;
+    // kept-list state in the cell-list space
+    double* gapb_s = reinterpret_cast<double*>(cst_s);                                // [FUSED_PREV_LDS]
+    unsigned char* quiet_s = reinterpret_cast<unsigned char*>(cpid_s);                // [FUSED_PREV_LDS]
+    double* dacc_s = reinterpret_cast<double*>(reinterpret_cast<unsigned char*>(cpid_s) + 4096);  // [np]
+    static_assert(FUSED_PREV_LDS * 8 <= (FUSED_CELLS + 1) * 4, "separations exceed the cell-list space");
+    static_assert(FUSED_PREV_LDS <= 4096 && 4096 + DEM_FUSED_MAX * 8 <= 8 * DEM_FUSED_MAX * 2,
+                  "movement bounds exceed the cell-list space");
     int age = 0;            // substeps since the list was last rebuilt
     bool keys_lds = false;  // the kept list's keys are staged in prev_s
     for (int sub = 0; sub < nsub; ++sub) {
@@ -1163,7 +1187,9 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
         int changed = sub == 0;
         for (int k = tid; k < np; k += FUSED_T) {
             AxCells r;
-            ph_predict(A, k, dt, last ? 1 : 0, r);
+            double dsp;
+            ph_predict(A, k, dt, last ? 1 : 0, r, &dsp);
+            if (!ELL) dacc_s[k] += dsp;  // reset by the rebuild that follows a first substep
             store_cells(A, k, r);
             unsigned wm = 0;
 #pragma unroll
@@ -1191,6 +1217,8 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
             }
         } else if (lds_cells) {
             // counting sort of the registrations by cell
+            for (int u = tid; u <= ncell; u += FUSED_T) cst_s[u] = 0;
+            __syncthreads();
             for (int k = tid; k < np; k += FUSED_T) {
                 const unsigned px = cells_s[3 * k], py = cells_s[3 * k + 1], pz = cells_s[3 * k + 2];
 #pragma unroll
@@ -1283,18 +1311,49 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
         if (prev_in_lds)
             for (long long u = tid; u < nprev; u += FUSED_T) prev_s[u] = B.prev_pairs[u];
         __syncthreads();
-        // the cell list is consumed: cleared for the next rebuild
-        if (rebuild && lds_cells)
-            for (int u = tid; u <= ncell; u += FUSED_T) cst_s[u] = 0;
         const long long npairs = n_pairs(A, B);
         const bool lds_cols = npairs <= FUSED_COLS;
         {
             PairBufs BL = B;
             if (prev_in_lds) BL.prev_pairs = prev_s;
             if (!rebuild && keys_lds) BL.pairs = prev_s;
+            // separations tracked for sphere lists whose keys LDS holds when kept
+            const bool track = !ELL && npairs <= FUSED_PREV_LDS;
+            const bool skip_ok = track && !rebuild && age >= 2 && keys_lds;
+            if (rebuild && track)
+                for (int k = tid; k < np; k += FUSED_T) dacc_s[k] = 0.0;
             for (long long s = tid; s < npairs; s += FUSED_T) {
-                const bool in = ph_contact<ELL>(A, BL, s, A.p.vp, A.p.wp, dt, nprev, !rebuild);
+                int pi = 0, pj = 0;
+                if (skip_ok) {
+                    const unsigned long long key = prev_s[s];
+                    pi = (int)(key >> 32);
+                    pj = (int)(key & 0xffffffffu);
+                    if (quiet_s[s] >= 2) {
+                        const double mv = dacc_s[pi] + (pj < np ? dacc_s[pj] : 0.0);
+                        if (gapb_s[s] - mv > FUSED_SKIP_EPS) {
+                            if (lds_cols) inc_s[s] = 0;
+                            continue;
+                        }
+                    }
+                }
+                double gp = 0.0;
+                const bool in = ph_contact<ELL>(A, BL, s, A.p.vp, A.p.wp, dt, nprev, !rebuild, track ? &gp : nullptr);
                 if (lds_cols) inc_s[s] = in ? 1 : 0;
+                if (track) {
+                    if (rebuild) {
+                        quiet_s[s] = in ? 0 : 1;
+                        gapb_s[s] = gp;
+                    } else {
+                        if (!skip_ok) {
+                            const unsigned long long key = prev_s[s];
+                            pi = (int)(key >> 32);
+                            pj = (int)(key & 0xffffffffu);
+                        }
+                        const int q = quiet_s[s];
+                        quiet_s[s] = in ? 0 : (q < 2 ? q + 1 : 2);
+                        gapb_s[s] = gp + (dacc_s[pi] + (pj < np ? dacc_s[pj] : 0.0));
+                    }
+                }
             }
         }
         if (rebuild && lds_cols) {
