@@ -29,6 +29,8 @@ struct DemArgs {
     double wall_u[6][3];
     double gravity[3];
     int ellipsoids;        // any particle is an ellipsoid (else the sphere-only kernels run)
+    int* fused_age;        // [1] substeps the single-workgroup DEM's list had been kept when its last
+                           // launch ended (pc holds the cells it was built from); -1: rebuild
     DevCounters* ctr;
 };
 

@@ -705,7 +705,7 @@ __device__ inline void quat_rate(const double* w, const double* q, double* out) 
 // and renormalised.  Every input is loaded before the first store; the new
 // position and orientation then give the particle's registration cells.
 __device__ void ph_predict(const DemArgs& A, int k, double dt, int write_kin, AxCells& cells,
-                           double* disp = nullptr) {
+                           double* disp = nullptr, double* xo = nullptr) {
     double x[3], v[3], a[3], w[3], al[3], q0[4], sm[3];
     const int shape = A.p.shape[k];
 #pragma unroll
@@ -764,6 +764,9 @@ __device__ void ph_predict(const DemArgs& A, int k, double dt, int write_kin, Ax
     double e[3];
     half_extents_of(shape, sm, qn, e);
     axis_cells_at(A, xn, e, cells);
+    if (xo)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xo[c] = xn[c];
     // an upper bound of the distance moved (L1 norm of the exact step)
     if (disp) {
         double d = 0.0;
@@ -1147,6 +1150,11 @@ __device__ int merged_row(const DemArgs& A, int i, const unsigned* cells_s, cons
 // contact, and its outputs and both history buffers already hold zeros, so it
 // is not evaluated again.  These live in the cell-list space, which a kept
 // list does not use.
+// The list also outlives the launch: A.fused_age records how long it had been
+// kept when the launch ended (pc holds the cells, with the wall candidates in
+// its last word); the next launch keeps it when nothing changed and rebuilds
+// only its LDS state (column lists, staged keys, separations).  Every other
+// writer of the lists or particles resets A.fused_age to -1.
 template <bool ELL>
 __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, const PairSet& P, int cur, const int nsub, const double dt,
                                const int stop_before_correct) {
@@ -1170,8 +1178,9 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
     static_assert(FUSED_PREV_LDS * 8 <= (FUSED_CELLS + 1) * 4, "separations exceed the cell-list space");
     static_assert(FUSED_PREV_LDS <= 4096 && 4096 + DEM_FUSED_MAX * 8 <= 8 * DEM_FUSED_MAX * 2,
                   "movement bounds exceed the cell-list space");
-    int age = 0;            // substeps since the list was last rebuilt
-    bool keys_lds = false;  // the kept list's keys are staged in prev_s
+    const int age0 = *A.fused_age;  // the last launch's list age, -1: none
+    int age = 0;                     // substeps since the list was last rebuilt
+    bool keys_lds = false;           // the kept list's keys are staged in prev_s
     for (int sub = 0; sub < nsub; ++sub) {
         const bool last = sub == nsub - 1;
         const int c = cur ^ 1;
@@ -1184,28 +1193,49 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
         B.prev_hist = c ? P.hist[0] : P.hist[1];
         const int* prev_prow = c ? P.prow[0] : P.prow[1];
         B.prev_n = prev_prow + np;
-        int changed = sub == 0;
+        int changed = sub == 0 && age0 < 0;
         for (int k = tid; k < np; k += FUSED_T) {
+            // the cells and wall candidates the kept list was built from
+            unsigned old[4];
+            if (sub == 0) {
+                const int* d = A.pc + 8 * k;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) old[a] = (unsigned)d[2 * a] | ((unsigned)d[2 * a + 1] << 16);
+                old[3] = (unsigned)d[7];
+            } else {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) old[a] = cells_s[3 * k + a];
+                old[3] = wmask_s[k];
+            }
+            const double rbk = A.p.rb[k];
             AxCells r;
-            double dsp;
-            ph_predict(A, k, dt, last ? 1 : 0, r, &dsp);
-            if (!ELL) dacc_s[k] += dsp;  // reset by the rebuild that follows a first substep
+            double dsp, xk[3];
+            ph_predict(A, k, dt, last ? 1 : 0, r, &dsp, xk);
+            if (!ELL) dacc_s[k] += dsp;  // reset by the first substep, which starts fresh
             store_cells(A, k, r);
             unsigned wm = 0;
 #pragma unroll
-            for (int f = 0; f < 6; ++f) wm |= (A.g.bc[f] != 0 && wall_dist(A, k, f) < A.p.rb[k]) ? 1u << f : 0u;
+            for (int f = 0; f < 6; ++f) {
+                const int a = f / 2;
+                const double wd = (f % 2 == 0) ? xk[a] : A.L[a] - xk[a];
+                wm |= (A.g.bc[f] != 0 && wd < rbk) ? 1u << f : 0u;
+            }
+            A.pc[8 * k + 7] = (int)wm;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const unsigned pk = pack_axis(r, a);
-                changed |= pk != cells_s[3 * k + a];
+                changed |= pk != old[a];
                 cells_s[3 * k + a] = pk;
             }
-            changed |= wm != wmask_s[k];
+            changed |= wm != old[3];
             wmask_s[k] = (unsigned char)wm;
         }
         const bool rebuild = __syncthreads_or(changed) != 0;
-        age = rebuild ? 0 : age + 1;
-        if (rebuild) keys_lds = false;
+        age = rebuild ? 0 : (sub == 0 ? age0 + 1 : age + 1);
+        // LDS state (column lists, staged keys, separations) is built afresh
+        // with a new list and at the start of a launch
+        const bool fresh = rebuild || sub == 0;
+        if (fresh) keys_lds = false;
         if (!rebuild) {
             // the previous list is this list: one substep after the rebuild it
             // is copied into this buffer, later this buffer already holds it
@@ -1319,8 +1349,8 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
             if (!rebuild && keys_lds) BL.pairs = prev_s;
             // separations tracked for sphere lists whose keys LDS holds when kept
             const bool track = !ELL && npairs <= FUSED_PREV_LDS;
-            const bool skip_ok = track && !rebuild && age >= 2 && keys_lds;
-            if (rebuild && track)
+            const bool skip_ok = track && !fresh && age >= 2 && keys_lds;
+            if (fresh && track)
                 for (int k = tid; k < np; k += FUSED_T) dacc_s[k] = 0.0;
             for (long long s = tid; s < npairs; s += FUSED_T) {
                 int pi = 0, pj = 0;
@@ -1340,7 +1370,7 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
                 const bool in = ph_contact<ELL>(A, BL, s, A.p.vp, A.p.wp, dt, nprev, !rebuild, track ? &gp : nullptr);
                 if (lds_cols) inc_s[s] = in ? 1 : 0;
                 if (track) {
-                    if (rebuild) {
+                    if (fresh) {
                         quiet_s[s] = in ? 0 : 1;
                         gapb_s[s] = gp;
                     } else {
@@ -1356,7 +1386,7 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
                 }
             }
         }
-        if (rebuild && lds_cols) {
+        if (fresh && lds_cols) {
             // column lists: pairs by second member, ascending pair index
             for (int k = tid; k <= np; k += FUSED_T) cnt_s[k] = 0;
             __syncthreads();
@@ -1444,6 +1474,7 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
         }
         cur = c;
     }
+    if (tid == 0 && nsub > 0) *A.fused_age = age;
 }
 
 template <bool ELL>

@@ -40,6 +40,7 @@ struct psmdem_domain {
     long long ncell = 1;
     int *cell_count = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *cell_pid = nullptr;
     int* pc = nullptr;
+    int* fused_age = nullptr;
     int *col_count = nullptr, *col_fill = nullptr, *col_start = nullptr, *col_list = nullptr;
     long long reg_cap = 0;
     int* pcount = nullptr;
@@ -115,6 +116,7 @@ struct psmdem_domain {
         }
         A.ncell = ncell;
         A.pc = pc;
+        A.fused_age = fused_age;
         A.cell_count = cell_count;
         A.cell_start = cell_start;
         A.cell_fill = cell_fill;

@@ -124,7 +124,15 @@ static int run_lbm(psmdem_domain* D) {
     return 0;
 }
 
+// the single-workgroup DEM may keep its pair list across launches; any other
+// writer of the lists, cells or particle state makes its next launch rebuild
+static int forget_fused_list(psmdem_domain* D) {
+    if (D->np > 0) PSM_CHECK(hipMemsetAsync(D->fused_age, 0xff, sizeof(int), D->s));
+    return 0;
+}
+
 static int run_lists(psmdem_domain* D) {
+    if (int rc = forget_fused_list(D)) return rc;
     DemArgs A = D->dem_args();
     PairBufs B = D->pair_bufs(1);
     PSM_CHECK(dem_lists(A, B, D->scan_tmp, D->s));
@@ -376,6 +384,7 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
     P.kin = (double*)A(sizeof(double) * 9 * std::max(np, 1));
     D->reg_cap = 8LL * std::max(np, 1);
     D->pc = (int*)A(sizeof(int) * 8 * std::max(np, 1));
+    D->fused_age = (int*)A(sizeof(int));
     D->cell_count = (int*)A(sizeof(int) * D->ncell);
     D->cell_fill = (int*)A(sizeof(int) * D->ncell);
     D->cell_start = (int*)A(sizeof(int) * (D->ncell + 1));
@@ -493,6 +502,7 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
             hipMemsetAsync(D->t.vinv, 0, sizeof(int) * D->t.cap, D->s) != hipSuccess ||
             hipMemsetAsync(D->t.slot_lp, 0xff, sizeof(unsigned) * g.ntiles * (size_t)PSM_TILE, D->s) != hipSuccess ||
             hipMemsetAsync(D->cell_pid, 0, sizeof(int) * D->reg_cap, D->s) != hipSuccess ||
+            hipMemsetAsync(D->fused_age, 0xff, sizeof(int), D->s) != hipSuccess ||
             hipStreamSynchronize(D->s) != hipSuccess)
             rc = PSMDEM_E_HIP;
     }
@@ -580,7 +590,8 @@ extern "C" psmdem_status psmdem_sync(psmdem_domain* d) {
 
 extern "C" psmdem_status psmdem_stage(psmdem_domain* d, int32_t stage) {
     if (!d) return PSMDEM_E_INVALID;
-    int rc = 0;
+    int rc = forget_fused_list(d);
+    if (rc) return (psmdem_status)rc;
     switch (stage) {
         case PSMDEM_STAGE_LISTS:
             d->cur ^= 1;
@@ -742,6 +753,7 @@ extern "C" psmdem_status psmdem_write_particles(psmdem_domain* d, const double* 
                                                const double* vel, const double* omega, const double* acc,
                                                const double* alpha, const double* f_hyd, const double* m_hyd) {
     if (!d) return PSMDEM_E_INVALID;
+    if (int rc = forget_fused_list(d)) return (psmdem_status)rc;
     PSM_CHECK(hipStreamSynchronize(d->s));
     if (d->np == 0) return PSMDEM_OK;
     size_t n3 = sizeof(double) * 3 * d->np;
@@ -765,6 +777,7 @@ extern "C" psmdem_status psmdem_read_predicted(psmdem_domain* d, double* vp, dou
 
 extern "C" psmdem_status psmdem_write_predicted(psmdem_domain* d, const double* vp, const double* wp) {
     if (!d) return PSMDEM_E_INVALID;
+    if (int rc = forget_fused_list(d)) return (psmdem_status)rc;
     PSM_CHECK(hipStreamSynchronize(d->s));
     if (d->np == 0) return PSMDEM_OK;
     if (vp) PSM_CHECK(hipMemcpy(d->p.vp, vp, sizeof(double) * 3 * d->np, hipMemcpyHostToDevice));
@@ -795,6 +808,7 @@ extern "C" psmdem_status psmdem_read_pairs(psmdem_domain* d, int64_t cap, uint64
 extern "C" psmdem_status psmdem_write_pairs(psmdem_domain* d, int64_t n, const uint64_t* keys, const double* hist) {
     if (!d || n < 0 || (n > 0 && (!keys || !hist))) return PSMDEM_E_INVALID;
     if (n > d->pair_cap) { psm_set_error("pair list exceeds the capacity"); return PSMDEM_E_CAPACITY; }
+    if (int rc = forget_fused_list(d)) return (psmdem_status)rc;
     PSM_CHECK(hipStreamSynchronize(d->s));
     // rebuild row offsets from the sorted keys
     std::vector<int> row(d->np + 1, 0);

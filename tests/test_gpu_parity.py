@@ -312,6 +312,41 @@ def test_fused_dem_list_reuse(ps, oracle_mod, kind):
         assert O.counters()["contacts"] > 20
 
 
+def test_fused_dem_state_written_between_steps(ps, oracle_mod):
+    """A list kept across launches is dropped when the host writes particles
+    or pairs: both sides take the same moved positions and scaled history
+    after two steps and must agree again after three more."""
+    box = (48, 40, 36)
+    rng = W.SplitMix64(4545)
+    n = 300
+    radii = 1.4 + 0.6 * rng.uniform(n)
+    pos = W.rsa_spheres(rng, n, radii, box, [True, True, False], gap=-0.5)
+    m = len(pos)
+    vel = 0.004 * (rng.uniform(3 * m).reshape(m, 3) - 0.5)
+    parts = W.spheres(pos, radii[:m], 1.6, vel=vel)
+    cfg = _walled(box, 0.7, "fp64", fluid_on=False, mu=0.3, restitution=0.7, n_sub=7)
+    G, O = _pair(ps, oracle_mod, cfg, parts)
+    G.step(2)
+    O.step(2)
+    P = O.particles()
+    moved = P["pos"].copy()
+    moved[::3, 0] = (moved[::3, 0] + 0.6) % box[0]
+    for D in (G, O):
+        D.set_particles(pos=moved, quat=P["quat"], vel=P["vel"], omega=P["omega"], acc=P["acc"],
+                        alpha=P["alpha"], f_hyd=P["f_hyd"], m_hyd=P["m_hyd"])
+    k, h = O.pairs()
+    for D in (G, O):
+        D.set_pairs(k, 0.5 * h)
+    for _ in range(3):
+        G.step(1)
+        O.step(1)
+        assert np.array_equal(G.pairs()[0], O.pairs()[0])
+        Pg, Po = G.particles(), O.particles()
+        assert vec_err(Pg["pos"], Po["pos"]) < 1e-12
+        assert vec_err(Pg["vel"], Po["vel"]) < 1e-12
+        assert force_err(Pg["f_dem"], Po["f_dem"], O.scales()["f_dem"], force_floor(O)) < 1e-12
+
+
 def test_couette_full_size_fp32(ps, oracle_mod):
     """The bench workload at its full size (128^3, 500 spheres R = 5, moving
     walls, n_sub = 11) in the bench's precision: two coupled steps from
