@@ -40,7 +40,7 @@ def parse():
     p.add_argument("--collision", default="bgk", choices=["bgk", "trt"],
                    help="fluid operator inside the PSM collision (TRT: the paper's tau- rule)")
     p.add_argument("--spheres", type=int, default=500)
-    p.add_argument("--cpu-sample-steps", type=int, default=20,
+    p.add_argument("--cpu-sample-steps", type=int, default=120,
                    help="coupled steps of the CPU oracle sample (0: skip the CPU baseline)")
     p.add_argument("--no-timing", action="store_true", help="skip the per-kernel event timing pass")
     p.add_argument("--serve-jobs", type=int, default=32,

@@ -105,8 +105,13 @@ __device__ inline void axis_cells_at(const DemArgs& A, const double pos[3], cons
         int hi = (int)floor((x + e[a]) / A.h[a]);
         int c0 = lo, c1 = lo + 1 <= hi ? lo + 1 : lo;
         if (A.g.periodic[a]) {
-            c0 = ((c0 % A.nc[a]) + A.nc[a]) % A.nc[a];
-            c1 = ((c1 % A.nc[a]) + A.nc[a]) % A.nc[a];
+            // one period off at most for a wrapped position (selects); any
+            // other offset takes the integer remainder
+            const int n = A.nc[a];
+            c0 = c0 < 0 && c0 >= -n ? c0 + n : (c0 >= n && c0 < 2 * n ? c0 - n : c0);
+            c1 = c1 < 0 && c1 >= -n ? c1 + n : (c1 >= n && c1 < 2 * n ? c1 - n : c1);
+            if (c0 < 0 || c0 >= n) c0 = ((c0 % n) + n) % n;
+            if (c1 < 0 || c1 >= n) c1 = ((c1 % n) + n) % n;
         } else {
             c0 = c0 < 0 ? 0 : (c0 > A.nc[a] - 1 ? A.nc[a] - 1 : c0);
             c1 = c1 < 0 ? 0 : (c1 > A.nc[a] - 1 ? A.nc[a] - 1 : c1);
@@ -704,26 +709,37 @@ __device__ inline void quat_rate(const double* w, const double* q, double* out) 
 // w^p = w + alpha dt, quaternion advanced by a midpoint step of q' = q (0, w)/2
 // and renormalised.  Every input is loaded before the first store; the new
 // position and orientation then give the particle's registration cells.
-__device__ void ph_predict(const DemArgs& A, int k, double dt, int write_kin, AxCells& cells,
-                           double* disp = nullptr, double* xo = nullptr) {
-    double x[3], v[3], a[3], w[3], al[3], q0[4], sm[3];
-    const int shape = A.p.shape[k];
+// one particle's integration state as the predictor reads it
+struct PredIn {
+    double x[3], v[3], a[3], w[3], al[3], q[4], sm[3];
+    int shape;
+};
+
+__device__ inline void pred_load(const DemArgs& A, int k, PredIn& s) {
+    s.shape = A.p.shape[k];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        x[c] = A.p.pos[3 * k + c];
-        v[c] = A.p.v[3 * k + c];
-        a[c] = A.p.a[3 * k + c];
-        w[c] = A.p.w[3 * k + c];
-        al[c] = A.p.al[3 * k + c];
-        sm[c] = A.p.semi[3 * k + c];
+        s.x[c] = A.p.pos[3 * k + c];
+        s.v[c] = A.p.v[3 * k + c];
+        s.a[c] = A.p.a[3 * k + c];
+        s.w[c] = A.p.w[3 * k + c];
+        s.al[c] = A.p.al[3 * k + c];
+        s.sm[c] = A.p.semi[3 * k + c];
     }
 #pragma unroll
-    for (int c = 0; c < 4; ++c) q0[c] = A.p.q[4 * k + c];
+    for (int c = 0; c < 4; ++c) s.q[c] = A.p.q[4 * k + c];
+}
+
+// The predictor on a loaded state: stores the new position, predicted
+// velocities and orientation (and the previous one), and leaves the new
+// position and orientation in s; q0 receives the orientation it started from.
+__device__ inline void pred_core(const DemArgs& A, int k, double dt, int write_kin, PredIn& s, AxCells& cells,
+                                 double* disp, double* q0) {
     const double hdt2 = 0.5 * dt * dt;
     double xn[3], vp[3], wp[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        double y = (x[c] + dt * v[c]) + hdt2 * a[c];
+        double y = (s.x[c] + dt * s.v[c]) + hdt2 * s.a[c];
         if (A.g.periodic[c]) {
             double L = A.L[c];
             if (y >= L) y -= L;
@@ -731,14 +747,16 @@ __device__ void ph_predict(const DemArgs& A, int k, double dt, int write_kin, Ax
             if (y == L) y = 0.0;
         }
         xn[c] = y;
-        vp[c] = v[c] + dt * a[c];
-        wp[c] = w[c] + dt * al[c];
+        vp[c] = s.v[c] + dt * s.a[c];
+        wp[c] = s.w[c] + dt * s.al[c];
     }
     double r1[4], qs[4], qm[4], r2[4], qn[4];
-    quat_rate(w, q0, r1);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) q0[c] = s.q[c];
+    quat_rate(s.w, q0, r1);
     for (int c = 0; c < 4; ++c) qs[c] = q0[c] + dt * r1[c];
     for (int c = 0; c < 4; ++c) qm[c] = 0.5 * (q0[c] + qs[c]);
-    quat_rate(w, qm, r2);
+    quat_rate(s.w, qm, r2);
     for (int c = 0; c < 4; ++c) qn[c] = q0[c] + dt * r2[c];
     double l = sqrt((qn[0] * qn[0] + qn[1] * qn[1]) + (qn[2] * qn[2] + qn[3] * qn[3]));
     for (int c = 0; c < 4; ++c) qn[c] = qn[c] / l;
@@ -762,26 +780,36 @@ __device__ void ph_predict(const DemArgs& A, int k, double dt, int write_kin, Ax
         }
     }
     double e[3];
-    half_extents_of(shape, sm, qn, e);
+    half_extents_of(s.shape, s.sm, qn, e);
     axis_cells_at(A, xn, e, cells);
-    if (xo)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) xo[c] = xn[c];
     // an upper bound of the distance moved (L1 norm of the exact step)
     if (disp) {
         double d = 0.0;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) d += fabs(dt * v[c]) + fabs(hdt2 * a[c]);
+        for (int c = 0; c < 3; ++c) d += fabs(dt * s.v[c]) + fabs(hdt2 * s.a[c]);
         *disp = d;
     }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s.x[c] = xn[c];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s.q[c] = qn[c];
+}
+
+__device__ void ph_predict(const DemArgs& A, int k, double dt, int write_kin, AxCells& cells,
+                           double* disp = nullptr, double* xo = nullptr) {
+    PredIn s;
+    pred_load(A, k, s);
+    double q0[4];
+    pred_core(A, k, dt, write_kin, s, cells, disp, q0);
+    if (xo)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xo[c] = s.x[c];
 }
 
 // alpha = Rbw I^-1 [Rbw^T M - (Rbw^T w) x (I Rbw^T w)] at the substep start (as printed)
-__device__ void angular_accel(const DemArgs& A, int k, const double* qo, const double* w, const double* M,
-                              double* al) {
+__device__ void angular_accel_I(const double* I, const double* qo, const double* w, const double* M, double* al) {
     double R[9];
     quat_rbw(qo, R);
-    const double* I = A.p.inertia + 3 * k;
     double Mb[3], wb[3], Iw[3], g[3], ab[3];
     for (int c = 0; c < 3; ++c) {
         Mb[c] = (R[0 + c] * M[0] + R[3 + c] * M[1]) + R[6 + c] * M[2];
@@ -793,22 +821,74 @@ __device__ void angular_accel(const DemArgs& A, int k, const double* qo, const d
     for (int r = 0; r < 3; ++r) al[r] = (R[3 * r] * ab[0] + R[3 * r + 1] * ab[1]) + R[3 * r + 2] * ab[2];
 }
 
+__device__ inline void angular_accel(const DemArgs& A, int k, const double* qo, const double* w, const double* M,
+                                     double* al) {
+    angular_accel_I(A.p.inertia + 3 * k, qo, w, M, al);
+}
+
 // corrector: a_new = (F_dem + F_hyd + F_ext)/m, F_ext = m (1 - rho0/rho_p) g;
 // v += dt/2 (a + a_new); w += dt/2 (alpha + alpha_new)
-__device__ void ph_correct(const DemArgs& A, int k, double dt) {
-    if (A.p.fixed[k]) {
-        for (int c = 0; c < 3; ++c) A.p.a[3 * k + c] = A.p.al[3 * k + c] = 0.0;
+// the corrector's inputs that stay fixed over the substeps of a step
+struct CorrConst {
+    double fh[3], mh[3], I[3];
+    double m, dens;
+    int fixed;
+};
+
+__device__ inline void corr_load_const(const DemArgs& A, int k, CorrConst& c) {
+    c.fixed = A.p.fixed[k];
+    c.m = A.p.mass[k];
+    c.dens = A.p.dens[k];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        c.fh[q] = A.p.fh[3 * k + q];
+        c.mh[q] = A.p.mh[3 * k + q];
+        c.I[q] = A.p.inertia[3 * k + q];
+    }
+}
+
+// The corrector on loaded values: v, a, w, al are read and replaced by the
+// corrected ones, which are also stored.
+__device__ inline void corr_core(const DemArgs& A, int k, double dt, const CorrConst& cc, const double* fd,
+                                 const double* md, const double* qo, double* v, double* a, double* w, double* al) {
+    if (cc.fixed) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            A.p.a[3 * k + c] = A.p.al[3 * k + c] = 0.0;
+            a[c] = al[c] = 0.0;
+        }
         return;
     }
-    const double m = A.p.mass[k];
-    const double fb = 1.0 - 1.0 / A.p.dens[k];
-    double fd[3], fh[3], md[3], mh[3], a[3], al[3], v[3], w[3], qo[4];
+    const double m = cc.m;
+    const double fb = 1.0 - 1.0 / cc.dens;
+    double M[3], an[3], aln[3];
+    for (int c = 0; c < 3; ++c) {
+        double fext = m * fb * A.gravity[c];
+        an[c] = ((fd[c] + cc.fh[c]) + fext) / m;
+        M[c] = md[c] + cc.mh[c];
+    }
+    angular_accel_I(cc.I, qo, w, M, aln);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        v[c] = v[c] + 0.5 * dt * (a[c] + an[c]);
+        a[c] = an[c];
+        w[c] = w[c] + 0.5 * dt * (al[c] + aln[c]);
+        al[c] = aln[c];
+        A.p.v[3 * k + c] = v[c];
+        A.p.a[3 * k + c] = a[c];
+        A.p.w[3 * k + c] = w[c];
+        A.p.al[3 * k + c] = al[c];
+    }
+}
+
+__device__ void ph_correct(const DemArgs& A, int k, double dt) {
+    CorrConst cc;
+    corr_load_const(A, k, cc);
+    double fd[3], md[3], a[3], al[3], v[3], w[3], qo[4];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         fd[c] = A.p.fd[3 * k + c];
-        fh[c] = A.p.fh[3 * k + c];
         md[c] = A.p.md[3 * k + c];
-        mh[c] = A.p.mh[3 * k + c];
         a[c] = A.p.a[3 * k + c];
         al[c] = A.p.al[3 * k + c];
         v[c] = A.p.v[3 * k + c];
@@ -816,20 +896,7 @@ __device__ void ph_correct(const DemArgs& A, int k, double dt) {
     }
 #pragma unroll
     for (int c = 0; c < 4; ++c) qo[c] = A.p.qold[4 * k + c];
-    double M[3], an[3], aln[3];
-    for (int c = 0; c < 3; ++c) {
-        double fext = m * fb * A.gravity[c];
-        an[c] = ((fd[c] + fh[c]) + fext) / m;
-        M[c] = md[c] + mh[c];
-    }
-    angular_accel(A, k, qo, w, M, aln);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        A.p.v[3 * k + c] = v[c] + 0.5 * dt * (a[c] + an[c]);
-        A.p.a[3 * k + c] = an[c];
-        A.p.w[3 * k + c] = w[c] + 0.5 * dt * (al[c] + aln[c]);
-        A.p.al[3 * k + c] = aln[c];
-    }
+    corr_core(A, k, dt, cc, fd, md, qo, v, a, w, al);
 }
 
 // initial accelerations a(0) = (F_dem(0) + F_ext)/m, alpha(0) from M_dem(0)
@@ -1181,6 +1248,54 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
     const int age0 = *A.fused_age;  // the last launch's list age, -1: none
     int age = 0;                     // substeps since the list was last rebuilt
     bool keys_lds = false;           // the kept list's keys are staged in prev_s
+    // With at most one particle per thread (and LDS column lists) each thread
+    // runs its particle's sums, corrector and next predictor back to back,
+    // every state load issued before the sums' own loads: no barrier and no
+    // further load latency between them (the same arithmetic as the
+    // stored-state path).
+    // Predictor of particle k for substep psub on its loaded state; returns
+    // whether its cells or wall candidates differ from those the kept list
+    // was built from.
+    auto predict_k = [&](int k, int psub, PredIn& st, double rbk) __attribute__((always_inline)) -> int {
+        unsigned old[4];
+        if (psub == 0) {
+            const int* d = A.pc + 8 * k;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) old[a] = (unsigned)d[2 * a] | ((unsigned)d[2 * a + 1] << 16);
+            old[3] = (unsigned)d[7];
+        } else {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) old[a] = cells_s[3 * k + a];
+            old[3] = wmask_s[k];
+        }
+        const int pl = psub == nsub - 1 ? 1 : 0;
+        AxCells r;
+        double dsp, q0[4];
+        pred_core(A, k, dt, pl, st, r, &dsp, q0);
+        const double xk[3] = {st.x[0], st.x[1], st.x[2]};
+        if (!ELL) dacc_s[k] += dsp;  // reset by the first substep, which starts fresh
+        store_cells(A, k, r);
+        unsigned wm = 0;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            const int a = f / 2;
+            const double wd = (f % 2 == 0) ? xk[a] : A.L[a] - xk[a];
+            wm |= (A.g.bc[f] != 0 && wd < rbk) ? 1u << f : 0u;
+        }
+        A.pc[8 * k + 7] = (int)wm;
+        int ch = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const unsigned pk = pack_axis(r, a);
+            ch |= pk != old[a];
+            cells_s[3 * k + a] = pk;
+        }
+        ch |= wm != old[3];
+        wmask_s[k] = (unsigned char)wm;
+        return ch;
+    };
+    int changed_next = 0;  // predictors of the next substep run after the sums
+    bool tail_done = false;  // ... in the previous substep
     for (int sub = 0; sub < nsub; ++sub) {
         const bool last = sub == nsub - 1;
         const int c = cur ^ 1;
@@ -1194,41 +1309,14 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
         const int* prev_prow = c ? P.prow[0] : P.prow[1];
         B.prev_n = prev_prow + np;
         int changed = sub == 0 && age0 < 0;
-        for (int k = tid; k < np; k += FUSED_T) {
-            // the cells and wall candidates the kept list was built from
-            unsigned old[4];
-            if (sub == 0) {
-                const int* d = A.pc + 8 * k;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) old[a] = (unsigned)d[2 * a] | ((unsigned)d[2 * a + 1] << 16);
-                old[3] = (unsigned)d[7];
-            } else {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) old[a] = cells_s[3 * k + a];
-                old[3] = wmask_s[k];
+        if (!tail_done) {
+            for (int k = tid; k < np; k += FUSED_T) {
+                PredIn st;
+                pred_load(A, k, st);
+                changed |= predict_k(k, sub, st, A.p.rb[k]);
             }
-            const double rbk = A.p.rb[k];
-            AxCells r;
-            double dsp, xk[3];
-            ph_predict(A, k, dt, last ? 1 : 0, r, &dsp, xk);
-            if (!ELL) dacc_s[k] += dsp;  // reset by the first substep, which starts fresh
-            store_cells(A, k, r);
-            unsigned wm = 0;
-#pragma unroll
-            for (int f = 0; f < 6; ++f) {
-                const int a = f / 2;
-                const double wd = (f % 2 == 0) ? xk[a] : A.L[a] - xk[a];
-                wm |= (A.g.bc[f] != 0 && wd < rbk) ? 1u << f : 0u;
-            }
-            A.pc[8 * k + 7] = (int)wm;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const unsigned pk = pack_axis(r, a);
-                changed |= pk != old[a];
-                cells_s[3 * k + a] = pk;
-            }
-            changed |= wm != old[3];
-            wmask_s[k] = (unsigned char)wm;
+        } else {
+            changed = changed_next;
         }
         const bool rebuild = __syncthreads_or(changed) != 0;
         age = rebuild ? 0 : (sub == 0 ? age0 + 1 : age + 1);
@@ -1418,7 +1506,18 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
         }
         __syncthreads();
         // DEM sums: pairs (k, i) for ascending k, then the own row
+        const bool tail = !ELL && np <= FUSED_T && lds_cols;  // ellipsoids: registers go to the contacts
         for (int i = tid; i < np; i += FUSED_T) {
+            PredIn ps;
+            CorrConst cs;
+            double qo[4], rbk = 0.0;
+            if (tail) {
+                pred_load(A, i, ps);
+                corr_load_const(A, i, cs);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) qo[q] = A.p.qold[4 * i + q];
+                rbk = A.p.rb[i];
+            }
             double F[3] = {0.0, 0.0, 0.0}, M[3] = {0.0, 0.0, 0.0};
             if (lds_cols) {
                 const int s0 = i > 0 ? cnt_s[i - 1] : 0, s1 = cnt_s[i];
@@ -1466,12 +1565,21 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
                 A.p.fd[3 * i + q] = F[q];
                 A.p.md[3 * i + q] = M[q];
             }
+            if (tail) {
+                // this thread's particle: corrector, then the next predictor
+                if (!(last && stop_before_correct))
+                    corr_core(A, i, dt, cs, F, M, qo, ps.v, ps.a, ps.w, ps.al);
+                if (!last) changed_next = predict_k(i, sub + 1, ps, rbk);
+            }
         }
-        __syncthreads();
-        if (!(last && stop_before_correct)) {
-            for (int k = tid; k < np; k += FUSED_T) ph_correct(A, k, dt);
+        if (!tail) {
             __syncthreads();
+            if (!(last && stop_before_correct)) {
+                for (int k = tid; k < np; k += FUSED_T) ph_correct(A, k, dt);
+                __syncthreads();
+            }
         }
+        tail_done = tail && !last;
         cur = c;
     }
     if (tid == 0 && nsub > 0) *A.fused_age = age;
