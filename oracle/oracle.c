@@ -76,6 +76,7 @@ struct or_domain {
     double h[3];
     int32_t nsub;
     double dt, beta_e, Rc;
+    double ystar, gstar;      /* Hertz: Y* and G* of a contact (App. A), one material */
     int64_t step;
 };
 
@@ -210,6 +211,15 @@ or_domain* or_create(const or_desc* d, int32_t np, const int32_t* shape, const d
         snprintf(g_err, sizeof g_err, "invalid collision operator");
         return NULL;
     }
+    if (d->contact_law < 0 || d->contact_law > 1 ||
+        (d->contact_law == 1 && (!(d->young > 0.0) || !(d->poisson >= 0.0 && d->poisson < 0.5)))) {
+        snprintf(g_err, sizeof g_err, "invalid contact law or material");
+        return NULL;
+    }
+    if (d->contact_law == 1 && np > 0 && d->dem_on && d->n_sub < 1) {
+        snprintf(g_err, sizeof g_err, "the Hertz law needs n_sub >= 1");
+        return NULL;
+    }
     if (np > 0 && (d->restitution <= 0.0 || d->restitution > 1.0)) {
         snprintf(g_err, sizeof g_err, "restitution must be in (0,1]");
         return NULL;
@@ -239,6 +249,14 @@ or_domain* or_create(const or_desc* d, int32_t np, const int32_t* shape, const d
     D->qold = (double*)xcalloc(4 * (size_t)np, sizeof(double));
     double e = d->restitution > 0 ? d->restitution : 1.0;
     D->beta_e = log(e) / sqrt(log(e) * log(e) + M_PI * M_PI); /* App. A */
+    if (d->contact_law == 1) {
+        /* App. A with both bodies of the one material:
+         * Y* = ((1 - nu_i^2)/E_i + (1 - nu_j^2)/E_j)^-1,
+         * G* = (2 (2 - nu_i)(1 + nu_i)/E_i + 2 (2 - nu_j)(1 + nu_j)/E_j)^-1 */
+        double E = d->young, nu = d->poisson;
+        D->ystar = 1.0 / ((1.0 - nu * nu) / E + (1.0 - nu * nu) / E);
+        D->gstar = 1.0 / (2.0 * (2.0 - nu) * (1.0 + nu) / E + 2.0 * (2.0 - nu) * (1.0 + nu) / E);
+    }
     D->Rc = cbrt(3.0 / (4.0 * M_PI));                          /* Sec. 2.4 distance method */
     double dmax = 0.0;
     for (int k = 0; k < np; ++k) {
@@ -1136,8 +1154,6 @@ static void dem_contacts(or_domain* D, const double* vv, const double* ww, doubl
     g_prev_keys = (uint64_t*)prev_keys;
     g_prev_hist = (double*)prev_hist;
     g_prev_n = prev_n;
-    double kn = D->d.kn;
-    double kt = D->d.kt_ratio * kn;
     D->ncontacts = 0;
     for (int k = 0; k < 3 * np; ++k) { D->fd[k] = 0.0; D->md[k] = 0.0; D->fd1[k] = 0.0; D->md1[k] = 0.0; }
     for (int64_t p = 0; p < D->npairs; ++p) {
@@ -1145,6 +1161,7 @@ static void dem_contacts(or_domain* D, const double* vv, const double* ww, doubl
         int i = (int)(key >> 32), j = (int)(key & 0xffffffffu);
         double delta, en[3], rci[3], rcj[3], rhoi, rhoj;
         int sphere_law;
+        double kn = D->d.kn, kt = D->d.kt_ratio * D->d.kn;  /* linear law; Hertz below */
         pair_geometry(D, i, j, &delta, en, rci, rcj, &rhoi, &rhoj, &sphere_law, NULL);
         double *F = D->cF + 3 * p, *Mi = D->cMi + 3 * p, *Mj = D->cMj + 3 * p, *h = D->hist + 3 * p;
         if (!(delta > 0.0)) {
@@ -1167,8 +1184,23 @@ static void dem_contacts(or_domain* D, const double* vv, const double* ww, doubl
             }
             mstar = D->mass[i];
         }
-        double gn = -2.0 * D->beta_e * sqrt(kn * mstar);
-        double gt = D->d.gt_ratio * gn;
+        double gn, gt;
+        if (D->d.contact_law == 1) {
+            /* Hertz (App. A): k_n = 4/3 Y* sqrt(R* d), k_t = 8 G* sqrt(R* d),
+             * gamma = -2 sqrt(5/6) beta sqrt(S m*), S_n = 2 Y* sqrt(R* d),
+             * S_t = 8 G* sqrt(R* d); R* = (1/R_i + 1/R_j)^-1 with the local
+             * equivalent-sphere radii; a wall has infinite radius and mass */
+            double Rs = (j < np) ? 1.0 / (1.0 / rhoi + 1.0 / rhoj) : rhoi;
+            double sq = sqrt(Rs * delta);
+            kn = 4.0 / 3.0 * D->ystar * sq;
+            kt = 8.0 * D->gstar * sq;
+            double Sn = 2.0 * D->ystar * sq, St = 8.0 * D->gstar * sq;
+            gn = -2.0 * sqrt(5.0 / 6.0) * D->beta_e * sqrt(Sn * mstar);
+            gt = -2.0 * sqrt(5.0 / 6.0) * D->beta_e * sqrt(St * mstar);
+        } else {
+            gn = -2.0 * D->beta_e * sqrt(kn * mstar);
+            gt = D->d.gt_ratio * gn;
+        }
         /* normal: F_n = [k_n delta + gamma_n (v_j - v_i).e_n] e_n (G2) */
         double dv[3] = {vj[0] - vi[0], vj[1] - vi[1], vj[2] - vi[2]};
         double fn = kn * delta + gn * dot3(dv, en);

@@ -43,6 +43,8 @@ typedef struct {
     int32_t max_solids;       /* solids kept per fluid cell (2) */
     int32_t collision;        /* fluid operator: 0 BGK, 1 TRT (Sec. 2.3, Eq. TRT) */
     double trt_magic;         /* TRT: 0 = the paper's tau^- rule; > 0 = magic parameter Lambda */
+    int32_t contact_law;      /* 0 linear spring-dashpot (k_n given), 1 Hertz from the material (App. A) */
+    double young, poisson;    /* Hertz: Young's modulus and Poisson's ratio of particles and walls */
 } or_desc;
 
 typedef struct or_domain or_domain;

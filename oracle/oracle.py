@@ -30,6 +30,7 @@ class OrDesc(C.Structure):
         ("kt_ratio", C.c_double), ("gt_ratio", C.c_double),
         ("max_solids", C.c_int32),
         ("collision", C.c_int32), ("trt_magic", C.c_double),
+        ("contact_law", C.c_int32), ("young", C.c_double), ("poisson", C.c_double),
     ]
 
 
@@ -127,6 +128,9 @@ def make_desc(cfg):
     d.max_solids = int(cfg.get("max_solids", 2))
     d.collision = {"bgk": 0, "trt": 1}[cfg.get("collision", "bgk")]
     d.trt_magic = float(cfg.get("trt_magic", 0.0))
+    d.contact_law = {"linear": 0, "hertz": 1}[cfg.get("contact_law", "linear")]
+    d.young = float(cfg.get("young", 0.0))
+    d.poisson = float(cfg.get("poisson", 0.0))
     return d
 
 

@@ -2,7 +2,7 @@
 
 None of these compare the oracle with itself: each checks a conservation law,
 a closed form, a printed value, a limit that reduces to a textbook case, or a
-brute-force enumeration.  Labels P1..P21 name the pins in the design notes.
+brute-force enumeration.  Labels P1..P22 name the pins in the design notes.
 """
 import json
 import math
@@ -421,6 +421,144 @@ def test_p10_energy_elastic(oracle_mod):
         delta = max(0.0, 10.0 - d)
         Es.append(0.5 * (m * (P["vel"] ** 2).sum(1)).sum() + 0.5 * 1e3 * delta ** 2)
     assert max(abs(E - E0) for E in Es) / E0 < 1e-3
+
+
+# Hertz law (App. A) with one material: Y* = E / (2 (1 - nu^2)) for two
+# bodies of it; the head-on closed forms follow from the elastic energy
+# 8/15 Y* sqrt(R*) delta^(5/2): maximum overlap (15 m* v^2 / (16 Y* sqrt(R*)))^(2/5)
+# and contact duration 2 * (2/5) B(2/5, 1/2) delta_max / v for approach speed v.
+HERTZ_T = 0.8 * math.sqrt(math.pi) * math.gamma(0.4) / math.gamma(0.9)
+
+
+def _hertz_pair(oracle_mod, e, v, E=2.0, nu=0.3, R=5.0, dens=1.5, nsub=4, wall=False):
+    bc = ["periodic"] * 6
+    if wall:
+        bc = ["periodic"] * 4 + ["noslip", "noslip"]
+    cfg = W.base_config((64, 64, 64), 0.8, fluid_on=False, restitution=e, mu=0.0, n_sub=nsub, bc=bc,
+                        contact_law="hertz", young=E, poisson=nu)
+    gap = 0.05
+    if wall:
+        parts = W.spheres([[32.0, 32.0, R + gap]], R, dens, vel=[[0, 0, -v]])
+    else:
+        parts = W.spheres([[32 - R - gap / 2, 32.0, 32.0], [32 + R + gap / 2, 32.0, 32.0]], R, dens,
+                          vel=[[v, 0, 0], [-v, 0, 0]])
+    return _dom(oracle_mod, cfg, parts)
+
+
+def _hertz_run(D, steps, overlap):
+    m = D.mass()
+    p0 = (m[:, None] * D.particles()["vel"]).sum(0)
+    E0 = 0.5 * (m * (D.particles()["vel"] ** 2).sum(1)).sum()
+    out = dict(maxd=0.0, tin=0, dev=0.0, p0=p0, m=m)
+    for _ in range(steps):
+        D.step(1)
+        P = D.particles()
+        d, el = overlap(P["pos"])
+        out["tin"] += d > 0
+        out["maxd"] = max(out["maxd"], d)
+        Ek = 0.5 * (m * (P["vel"] ** 2).sum(1)).sum()
+        out["dev"] = max(out["dev"], abs(Ek + el - E0) / E0)
+    out["P"] = P
+    return out
+
+
+@pytest.mark.parametrize("v", [0.05, 0.02])
+def test_p22_hertz_head_on_elastic(oracle_mod, v):
+    """Two equal spheres, e = 1, mu = 0: kinetic plus Hertz elastic energy is
+    constant, the spheres separate with their approach speed, momentum is
+    conserved, and the maximum overlap and contact duration take their
+    closed-form values (sampled once per step: 4 substeps of 1/4)."""
+    E, nu, R = 2.0, 0.3, 5.0
+    ys = E / (2 * (1 - nu * nu))
+    Rs = R / 2
+    D = _hertz_pair(oracle_mod, 1.0, v, E, nu, R)
+
+    def ov(pos):
+        d = max(0.0, 2 * R - np.linalg.norm(pos[0] - pos[1]))
+        return d, 8.0 / 15.0 * ys * math.sqrt(Rs) * d ** 2.5
+
+    # one collision: the spheres meet again across the periodic box only later
+    r = _hertz_run(D, 400 if v > 0.03 else 800, ov)
+    ms = r["m"][0] / 2
+    dmax = (15 * ms * (2 * v) ** 2 / (16 * ys * math.sqrt(Rs))) ** 0.4
+    assert r["dev"] < 1e-3
+    assert dmax * (1 - 2e-3) < r["maxd"] <= dmax * (1 + 1e-6)
+    assert abs(r["tin"] - HERTZ_T * dmax / (2 * v)) <= 1.5
+    vel = r["P"]["vel"]
+    assert abs((vel[1, 0] - vel[0, 0]) / (2 * v) - 1.0) < 1e-5
+    np.testing.assert_allclose((r["m"][:, None] * vel).sum(0), r["p0"], atol=1e-15 * r["m"][0])
+
+
+def test_p22_hertz_wall(oracle_mod):
+    """A sphere hitting a wall of the same material: R* = R, m* = m."""
+    E, nu, R, v = 2.0, 0.3, 5.0, 0.03
+    ys = E / (2 * (1 - nu * nu))
+    D = _hertz_pair(oracle_mod, 1.0, v, E, nu, R, wall=True)
+
+    def ov(pos):
+        d = max(0.0, R - pos[0, 2])
+        return d, 8.0 / 15.0 * ys * math.sqrt(R) * d ** 2.5
+
+    r = _hertz_run(D, 600, ov)
+    dmax = (15 * r["m"][0] * v ** 2 / (16 * ys * math.sqrt(R))) ** 0.4
+    assert r["dev"] < 1e-3
+    assert dmax * (1 - 2e-3) < r["maxd"] <= dmax * (1 + 1e-6)
+    assert abs(r["tin"] - HERTZ_T * dmax / v) <= 1.5
+    assert abs(r["P"]["vel"][0, 2] / v - 1.0) < 1e-5
+
+
+def test_p22_hertz_restitution(oracle_mod):
+    """Hertz damping with gamma = -2 sqrt(5/6) beta sqrt(S m*) grows with
+    delta^(1/4), which makes the restitution independent of the impact speed;
+    with beta from e it returns e."""
+    es = []
+    for v in (0.05, 0.02):
+        D = _hertz_pair(oracle_mod, 0.7, v)
+        D.step(800 if v < 0.03 else 400)
+        vel = D.particles()["vel"]
+        es.append((vel[1, 0] - vel[0, 0]) / (2 * v))
+    assert abs(es[0] - es[1]) < 1e-3
+    assert all(abs(x - 0.7) < 5e-3 for x in es)
+
+
+@pytest.mark.parametrize("e", [1.0, 0.5])
+def test_p22_hertz_tangential_oscillation(oracle_mod, e):
+    """A sphere resting on a wall at its static Hertz overlap
+    (4/3 Y* sqrt(R) d0^(3/2) = buoyant weight), kicked tangentially with
+    friction high enough to stick: its contact point oscillates like a mass
+    2m/7 on the spring k_t = 8 G* sqrt(R d0) with the dashpot
+    gamma_t = -2 sqrt(5/6) beta sqrt(8 G* sqrt(R d0) m), G* = E/(4 (2 - nu)(1 + nu))."""
+    E, nu, R, dens, g, nsub = 2.0, 0.3, 5.0, 1.5, 1e-3, 8
+    ys = E / (2 * (1 - nu * nu))
+    gs = E / (4 * (2 - nu) * (1 + nu))
+    m = dens * 4 / 3 * math.pi * R ** 3
+    d0 = (m * (1 - 1 / dens) * g / (4 / 3 * ys * math.sqrt(R))) ** (2 / 3)
+    kt = 8 * gs * math.sqrt(R * d0)
+    meff = 2 * m / 7
+    w0 = math.sqrt(kt / meff)
+    le = math.log(e)
+    beta = le / math.sqrt(le * le + math.pi ** 2)
+    gt = -2 * math.sqrt(5 / 6) * beta * math.sqrt(kt * m)
+    zeta = gt / (2 * math.sqrt(kt * meff))
+    Td = 2 * math.pi / (w0 * math.sqrt(1 - zeta * zeta))
+    cfg = W.base_config((32, 32, 32), 0.8, fluid_on=False, restitution=e, mu=1.0, n_sub=nsub,
+                        bc=["periodic"] * 4 + ["noslip", "noslip"], contact_law="hertz", young=E, poisson=nu,
+                        gravity=[0, 0, -g])
+    D = _dom(oracle_mod, cfg, W.spheres([[16.0, 16.0, R - d0]], R, dens, vel=[[1e-4, 0, 0]]))
+    vc = []
+    for _ in range(int(4 * Td)):
+        D.step(1)
+        P = D.particles()
+        vc.append(P["vel"][0, 0] - R * P["omega"][0, 1])  # contact-point velocity
+    vc = np.array(vc)
+    t = np.arange(1, len(vc) + 1)
+    down = [t[i] + vc[i] / (vc[i] - vc[i + 1]) for i in range(len(vc) - 1) if vc[i] > 0 >= vc[i + 1]]
+    peaks = [vc[i] for i in range(1, len(vc) - 1) if vc[i - 1] < vc[i] >= vc[i + 1] and vc[i] > 0]
+    assert len(down) >= 3 and len(peaks) >= 2
+    assert abs(np.diff(down).mean() / Td - 1) < (1e-3 if e == 1.0 else 1e-2)
+    # the rotation update is first order in the step: about 2 % amplitude drift per period here
+    assert abs(peaks[1] / peaks[0] - math.exp(-zeta * w0 * Td)) < 0.03
+    assert D.counters()["contacts"] == 1
 
 
 @pytest.mark.parametrize("mu", [0.0, 0.1, 0.3, 0.5])
