@@ -78,6 +78,16 @@ typedef enum { PSMDEM_SF_SUBDIVISION = 0, PSMDEM_SF_DISTANCE = 1 } psmdem_sf;
  * with dt/tau+ = 1/tau and dt/tau-; the Guo source is split into its even and
  * odd parts the same way, each scaled by 1 - (dt/tau+-)/2. */
 typedef enum { PSMDEM_BGK = 0, PSMDEM_TRT = 1 } psmdem_collision;
+
+/* Contact law, Sec. 2.1 and App. A.  LINEAR: F_n = [k_n d + gamma_n (v_j - v_i).e_n] e_n
+ * with the given k_n, gamma_n = -2 beta sqrt(k_n m*), beta = ln e / sqrt(ln^2 e + pi^2),
+ * k_t = kt_ratio k_n, gamma_t = gt_ratio gamma_n.  HERTZ: the same force form with
+ * k_n = 4/3 Y* sqrt(R* d), k_t = 8 G* sqrt(R* d), gamma = -2 sqrt(5/6) beta sqrt(S m*),
+ * S_n = 2 Y* sqrt(R* d), S_t = 8 G* sqrt(R* d), R* = (1/R_i + 1/R_j)^-1 (local equivalent
+ * sphere radii for ellipsoids), Y* and G* from one material (young, poisson) shared by the
+ * particles and the walls; a wall has infinite radius and mass.  The contact time then
+ * depends on the impact speed, so n_sub must be given (> 0). */
+typedef enum { PSMDEM_LINEAR = 0, PSMDEM_HERTZ = 1 } psmdem_contact_law;
 typedef enum { PSMDEM_SPHERE = 0, PSMDEM_ELLIPSOID = 1 } psmdem_shape;
 
 typedef struct {
@@ -110,6 +120,9 @@ typedef struct {
     double trt_magic;           /* TRT only: 0 = the paper's rule dt/tau- = 8 (2 - w) / (8 - w),
                                    w = dt/tau+ (Sec. 2.3), which is the magic parameter
                                    Lambda = (tau+ - 1/2)(tau- - 1/2) = 3/16; > 0 sets Lambda */
+    int32_t contact_law;        /* psmdem_contact_law (linear, 0, when zeroed) */
+    double young, poisson;      /* Hertz: Young's modulus (> 0) and Poisson's ratio (in [0, 1/2)) of the
+                                   particles and the walls, in lattice units */
 } psmdem_desc;
 
 typedef struct {

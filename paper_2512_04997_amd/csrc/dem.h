@@ -26,6 +26,8 @@ struct DemArgs {
     int* col_list;                  // [pair_cap] pair indices by second member, ascending
     long long pair_cap;
     double kn, beta_e, mu, kt_ratio, gt_ratio;
+    int hertz;             // Hertz law from the material, else the linear law
+    double ystar, gstar;   // Hertz: Y*, G*
     double wall_u[6][3];
     double gravity[3];
     int ellipsoids;        // any particle is an ellipsoid (else the sphere-only kernels run)

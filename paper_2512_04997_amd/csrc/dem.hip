@@ -507,8 +507,9 @@ __device__ inline long long n_pairs(const DemArgs& A, const PairBufs& B) {
     return n < A.pair_cap ? n : A.pair_cap;
 }
 
-// linear spring-dashpot with Coulomb cap and tangential history (Sec. 2.1):
-// F_n = [k_n delta + gamma_n (v_j - v_i).e_n] e_n, gamma_n = -2 beta sqrt(k_n m*);
+// spring-dashpot with Coulomb cap and tangential history (Sec. 2.1), linear or
+// Hertz (App. A) stiffness and damping:
+// F_n = [k_n delta + gamma_n (v_j - v_i).e_n] e_n, linear gamma_n = -2 beta sqrt(k_n m*);
 // v_rel = (v_i - v_j) - (rho_i w_i + rho_j w_j) x e_n, v_t its tangential part;
 // history projected on the tangent plane then advanced by v_t dt;
 // F_t = -k_t d_t - gamma_t v_t capped at mu |F_n| with the history reset.
@@ -571,9 +572,20 @@ __device__ bool ph_contact(const DemArgs& A, const PairBufs& B, long long s, con
         }
         mstar = mi;
     }
-    const double kn = A.kn, kt = A.kt_ratio * kn;
-    double gn = -2.0 * A.beta_e * sqrt(kn * mstar);
-    double gt = A.gt_ratio * gn;
+    double kn = A.kn, kt = A.kt_ratio * A.kn, gn, gt;
+    if (A.hertz) {
+        // Hertz (App. A): stiffness and damping from the material and the overlap
+        const double Rs = wall ? G.rhoi : 1.0 / (1.0 / G.rhoi + 1.0 / G.rhoj);
+        const double sq = sqrt(Rs * G.delta);
+        kn = 4.0 / 3.0 * A.ystar * sq;
+        kt = 8.0 * A.gstar * sq;
+        const double Sn = 2.0 * A.ystar * sq, St = 8.0 * A.gstar * sq;
+        gn = -2.0 * sqrt(5.0 / 6.0) * A.beta_e * sqrt(Sn * mstar);
+        gt = -2.0 * sqrt(5.0 / 6.0) * A.beta_e * sqrt(St * mstar);
+    } else {
+        gn = -2.0 * A.beta_e * sqrt(kn * mstar);
+        gt = A.gt_ratio * gn;
+    }
     double dv[3] = {vj[0] - vi[0], vj[1] - vi[1], vj[2] - vi[2]};
     double fn = kn * G.delta + gn * dot3(dv, G.en);
     double rw[3] = {G.rhoi * wi[0] + G.rhoj * wj[0], G.rhoi * wi[1] + G.rhoj * wj[1], G.rhoi * wi[2] + G.rhoj * wj[2]};

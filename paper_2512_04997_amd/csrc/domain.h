@@ -35,6 +35,7 @@ struct psmdem_domain {
     // DEM
     int nsub = 1;
     double dt = 1.0, beta_e = 0.0, Rc = 0.0;
+    double ystar = 0.0, gstar = 0.0;  // Hertz: Y*, G*
     int nc[3];
     double h[3];
     long long ncell = 1;
@@ -137,6 +138,9 @@ struct psmdem_domain {
         A.mu = d.mu;
         A.kt_ratio = d.kt_ratio;
         A.gt_ratio = d.gt_ratio;
+        A.hertz = d.contact_law == PSMDEM_HERTZ;
+        A.ystar = ystar;
+        A.gstar = gstar;
         for (int f_ = 0; f_ < 6; ++f_)
             for (int c = 0; c < 3; ++c) A.wall_u[f_][c] = d.wall_u[f_][c];
         A.ellipsoids = 0;

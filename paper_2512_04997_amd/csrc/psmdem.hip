@@ -210,6 +210,13 @@ static int validate(const psmdem_desc* d, const psmdem_particles* P) {
     if (d->kolm_amp != 0.0 && (d->kolm_axis < 0 || d->kolm_axis > 2 || d->kolm_dir < 0 || d->kolm_dir > 2)) {
         psm_set_error("invalid Kolmogorov axis"); return 0;
     }
+    if (d->contact_law < 0 || d->contact_law > 1) { psm_set_error("invalid contact_law"); return 0; }
+    if (d->contact_law == 1 && (!(d->young > 0.0) || !(d->poisson >= 0.0 && d->poisson < 0.5))) {
+        psm_set_error("the Hertz law needs young > 0 and poisson in [0, 1/2)"); return 0;
+    }
+    if (d->contact_law == 1 && P && P->n > 0 && d->dem_on && d->n_sub < 1) {
+        psm_set_error("the Hertz law needs n_sub >= 1 (its contact time depends on the impact speed)"); return 0;
+    }
     if (P && P->n < 0) { psm_set_error("negative particle count"); return 0; }
     if (P && P->n > 0) {
         if (!P->shape || !P->semi_axes || !P->density_ratio || !P->pos) {
@@ -270,6 +277,12 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
         }
     double e = d.restitution > 0 ? d.restitution : 1.0;
     D->beta_e = log(e) / sqrt(log(e) * log(e) + M_PI * M_PI);
+    if (d.contact_law == 1) {
+        // App. A with both bodies of the one material
+        const double E = d.young, nu = d.poisson;
+        D->ystar = 1.0 / ((1.0 - nu * nu) / E + (1.0 - nu * nu) / E);
+        D->gstar = 1.0 / (2.0 * (2.0 - nu) * (1.0 + nu) / E + 2.0 * (2.0 - nu) * (1.0 + nu) / E);
+    }
     D->Rc = cbrt(3.0 / (4.0 * M_PI));
 
     // host particle properties

@@ -21,6 +21,7 @@ OK, E_INVALID, E_NOMEM, E_CAPACITY, E_UNSTABLE, E_HIP, E_STATE, E_NODEVICE = 0, 
 PRECISION = {"fp64": 0, "fp32": 1, "bf16": 2, "fp16": 3}
 BC = {"periodic": 0, "noslip": 1, "moving": 2}
 COLLISION = {"bgk": 0, "trt": 1}
+CONTACT_LAW = {"linear": 0, "hertz": 1}
 STAGE = {"lists": 0, "voxelize": 1, "lbm": 2, "contacts": 3}
 TIMER = {"lbm": 0, "voxel": 1, "dem": 2, "hydro": 3}
 
@@ -46,6 +47,7 @@ class Desc(C.Structure):
         ("kt_ratio", C.c_double), ("gt_ratio", C.c_double),
         ("max_solids", C.c_int32), ("pair_capacity", C.c_int64),
         ("collision", C.c_int32), ("trt_magic", C.c_double),
+        ("contact_law", C.c_int32), ("young", C.c_double), ("poisson", C.c_double),
     ]
 
 
@@ -195,6 +197,9 @@ def make_desc(cfg):
     d.pair_capacity = int(cfg.get("pair_capacity", 0))
     d.collision = COLLISION[cfg.get("collision", "bgk")]
     d.trt_magic = float(cfg.get("trt_magic", 0.0))
+    d.contact_law = CONTACT_LAW[cfg.get("contact_law", "linear")]
+    d.young = float(cfg.get("young", 0.0))
+    d.poisson = float(cfg.get("poisson", 0.0))
     return d
 
 

@@ -158,12 +158,15 @@ def test_dem_lists_bitexact(ps, oracle_mod, walls):
     assert np.array_equal(ko, O.brute_pairs())
 
 
-def test_contacts_match(ps, oracle_mod):
+@pytest.mark.parametrize("law", ["linear", "hertz"])
+def test_contacts_match(ps, oracle_mod, law):
     """Overlapping spheres and ellipsoids with walls: contact forces, torques and
-    history from a shared state (pairs and history written to both)."""
+    history from a shared state (pairs and history written to both), with the
+    linear law and with the Hertz law from the material."""
     box = (64, 48, 40)
     parts = _mixed_particles(301, 90, box, [True, True, False], gap=-3.5)
-    cfg = _walled(box, 0.7, "fp64", fluid_on=False, mu=0.3, restitution=0.7, n_sub=8)
+    cfg = _walled(box, 0.7, "fp64", fluid_on=False, mu=0.3, restitution=0.7, n_sub=8, contact_law=law,
+                  young=800.0, poisson=0.3)
     G, O = _pair(ps, oracle_mod, cfg, parts)
     O.stage_lists()
     k, _ = O.pairs()
@@ -345,6 +348,50 @@ def test_fused_dem_state_written_between_steps(ps, oracle_mod):
         assert vec_err(Pg["pos"], Po["pos"]) < 1e-12
         assert vec_err(Pg["vel"], Po["vel"]) < 1e-12
         assert force_err(Pg["f_dem"], Po["f_dem"], O.scales()["f_dem"], force_floor(O)) < 1e-12
+
+
+@pytest.mark.parametrize("n", [600, 2300])
+def test_hertz_dem_steps(ps, oracle_mod, n):
+    """Hertz law through whole DEM steps: overlapping polydisperse spheres with
+    walls, friction and gravity; 600 particles take the single-workgroup
+    substeps, 2300 the multi-launch path."""
+    box = (40, 36, 30) if n < 1000 else (72, 64, 60)
+    rng = W.SplitMix64(88 + n)
+    radii = 1.2 + 0.6 * rng.uniform(n)
+    pos = W.rsa_spheres(rng, n, radii, box, [True, True, False], gap=-0.4)
+    m = len(pos)
+    parts = W.spheres(pos, radii[:m], 1.8, vel=0.01 * (rng.uniform(3 * m).reshape(m, 3) - 0.5))
+    cfg = _walled(box, 0.7, "fp64", fluid_on=False, mu=0.3, restitution=0.6, n_sub=6,
+                  gravity=[0.0, 0.0, -1e-4], contact_law="hertz", young=600.0, poisson=0.25)
+    G, O = _pair(ps, oracle_mod, cfg, parts)
+    for _ in range(3):
+        G.step(1)
+        O.step(1)
+        assert np.array_equal(G.pairs()[0], O.pairs()[0])
+        Pg, Po = G.particles(), O.particles()
+        assert vec_err(Pg["pos"], Po["pos"]) < 1e-12
+        assert vec_err(Pg["vel"], Po["vel"]) < 1e-12
+        assert force_err(Pg["f_dem"], Po["f_dem"], O.scales()["f_dem"], force_floor(O)) < 1e-12
+    assert O.counters()["contacts"] > 20
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_couette_hertz_steps(ps, oracle_mod, prec):
+    """The coupled step with the Hertz law and TRT: Couette shear with spheres
+    (48^3), three steps from creation against the oracle."""
+    cfg, parts, _ = W.couette_suspension(precision=prec, n=48, nsph=30, radius=4.0)
+    cfg.update(mu=0.3, contact_law="hertz", young=2e3, poisson=0.3, n_sub=10, collision="trt")
+    G, O = _pair(ps, oracle_mod, cfg, parts)
+    for _ in range(3):
+        G.step(1)
+        O.step(1)
+        assert np.array_equal(G.pairs()[0], O.pairs()[0])
+        assert pop_err(G.populations(), O.populations()) < TOL[prec]
+        Pg, Po = G.particles(), O.particles()
+        assert vec_err(Pg["pos"], Po["pos"]) < TOL[prec]
+        assert vec_err(Pg["vel"], Po["vel"]) < TOL[prec]
+        sc = O.scales()
+        assert force_err(Pg["f_hyd"], Po["f_hyd"], sc["f_hyd"]) < TOL[prec]
 
 
 def test_couette_full_size_fp32(ps, oracle_mod):
