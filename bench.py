@@ -33,10 +33,14 @@ def parse():
     p.add_argument("--steps", type=int, default=200)
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--precision", default="fp32", choices=list(STORAGE_BYTES))
-    p.add_argument("--workload", default="couette", choices=["couette", "kolmogorov", "bed"],
+    p.add_argument("--workload", default="couette", choices=["couette", "kolmogorov", "bed", "fluidized"],
                    help="couette: spheres in bounded shear; kolmogorov: prolate ellipsoids in a forced periodic "
                         "box; bed: polydisperse spheres settling in a walled 256x256x128 box (n_sub 32)")
     p.add_argument("--n", type=int, default=128, help="lattice edge of the workload")
+    p.add_argument("--phi", type=float, default=0.15, help="solid volume fraction of the fluidized bed")
+    p.add_argument("--fluidized-sweep", action="store_true",
+                   help="the paper's performance study: fluidized bed 500x200x800 at phi = 0, 0.15, 0.30, "
+                        "0.45 in FP32 and FP64, one JSON line per point")
     p.add_argument("--collision", default="bgk", choices=["bgk", "trt"],
                    help="fluid operator inside the PSM collision (TRT: the paper's tau- rule)")
     p.add_argument("--spheres", type=int, default=500)
@@ -161,6 +165,44 @@ def lbm_sweep(n, collision="bgk"):
                           "alg_GBs": round(N * 2 * 19 * sb / (ms * 1e-3) / 1e9, 1),
                           "frac": round(N * 2 * 19 * sb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}), flush=True)
         D.close()
+
+
+def fluidized_sweep(warmup, steps, collision):
+    """Coupled-step throughput of the paper's fluidized bed (500 x 200 x 800,
+    D = 20, 10 substeps, distance solid fraction) against the solid fraction,
+    in FP32 and FP64: one JSON line per point."""
+    import torch
+    from paper_2512_04997_amd import psmdem, workloads
+    torch.cuda.set_device(0)
+    for phi in (0.0, 0.15, 0.30, 0.45):
+        cfg, parts, meta = workloads.fluidized_bed(phi=phi)
+        for prec in ("fp32", "fp64"):
+            cfg = dict(cfg, precision=prec, collision=collision)
+            N = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]
+            D = psmdem.Domain(cfg, parts, stream=torch.cuda.current_stream())
+            D.step(warmup)
+            D.sync()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            D.step(steps)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            D.sync()
+            D.set_timing(True)
+            D.step(min(steps, 20))
+            D.set_timing(False)
+            parts_ms = {k: round(D.timing(k)[0], 4) for k in ("lbm", "voxel", "dem", "hydro")}
+            dem_n = D.timing("dem")[1] // max(D.timing("lbm")[1], 1)
+            parts_ms["dem"] = round(parts_ms["dem"] * dem_n, 4)
+            ctr = D.counters()
+            print(json.dumps({"fluidized_bed": meta["workload"], "phi": phi, "precision": prec,
+                              "particles": 0 if parts is None else len(parts["pos"]), "steps": steps,
+                              "ms_per_step": round(el / steps * 1e3, 4), "mlups": round(N * steps / el / 1e6, 1),
+                              "per_step_ms": parts_ms, "contacts": ctr["n_contacts"], "pairs": ctr["n_pairs"]}),
+                  flush=True)
+            D.close()
+            del D
+            torch.cuda.empty_cache()
 
 
 def _rel_l2(a, b):
@@ -349,6 +391,9 @@ def main():
     if a.precision_study:
         precision_study(a.precision_study, a.study_fraction)
         return
+    if a.fluidized_sweep:
+        fluidized_sweep(a.warmup, a.steps, a.collision)
+        return
     from paper_2512_04997_amd import psmdem, workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -357,6 +402,8 @@ def main():
         cfg, parts, meta = workloads.couette_suspension(precision=a.precision, n=a.n, nsph=a.spheres)
     elif a.workload == "kolmogorov":
         cfg, parts, meta = workloads.kolmogorov_ellipsoids(n=a.n, precision=a.precision)
+    elif a.workload == "fluidized":
+        cfg, parts, meta = workloads.fluidized_bed(precision=a.precision, phi=a.phi)
     else:
         cfg, parts, meta = workloads.settling_bed(precision=a.precision)
     cfg["collision"] = a.collision

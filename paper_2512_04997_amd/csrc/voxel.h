@@ -2,7 +2,7 @@
 #pragma once
 #include "common.h"
 
-#define VOX_AXIS_MAX 8   // distinct tiles one particle box may touch per axis
+#define VOX_AXIS_MAX 12  // distinct tiles one particle box may touch per axis (radius up to about 15 cells)
 
 struct VoxArgs {
     GeoArgs g;

@@ -340,6 +340,86 @@ def settling_bed(precision="fp32", n=(256, 256, 128), fraction=0.15, seed=1002, 
     return cfg, parts, dict(workload=f"settling_bed_{n[0]}x{n[1]}x{n[2]}_{len(pos)}_spheres", steps=steps)
 
 
+# sphere counts of the fluidized-bed benchmark at the fractions the paper lists
+FLUIDIZED_COUNTS = {0.0: 0, 0.15: 2866, 0.30: 5731, 0.45: 8596}
+
+
+def fluidized_bed(precision="fp32", phi=0.15, n=(500, 200, 800), radius=10.0, seed=1004, steps=200):
+    """The paper's performance configuration (Sec. 5): a lattice of
+    500 x 200 x 800 cells, periodic in x and z, no-slip walls in y, gravity
+    along -y, spheres of diameter 20 cells at density ratio 1.1, 10 DEM
+    substeps per step, the distance-based solid fraction, at a solid volume
+    fraction phi of the whole box (2866, 5731, 8596 spheres at 0.15, 0.30,
+    0.45; other fractions in proportion).  Lattice units: tau = 0.8
+    (nu = 0.1) and g = 2.25e-4 make the Stokes settling Reynolds number
+    u_s D / nu = 1 (u_s = 0.005); Hertz contacts (Y* = 100, nu = 0.3,
+    e = 0.9, mu = 0.3), whose contact time spans well over 10 substeps.
+    Placement: up to phi = 0.25 random sequential addition over the whole
+    box (surface gap 1, wall gap 1); above it a settled bed, the stand-in for
+    the paper's sedimentation-relaxation packing: a face-centred cubic
+    lattice (cubic cell 31.25 x 31.25 x 32, nearest centres 22.1 apart)
+    filled layer by layer from the y = 0 wall, the top layer in random order,
+    every centre jittered by up to 0.5 per axis.  A smaller n keeps the
+    recipe (count in proportion to the volume)."""
+    nx, ny, nz = (int(v) for v in n)
+    nu_p = 0.3
+    young = 100.0 * 2.0 * (1.0 - nu_p * nu_p)
+    cfg = base_config((nx, ny, nz), 0.8, bc=["periodic", "periodic", "noslip", "noslip", "periodic", "periodic"],
+                      gravity=[0.0, -2.25e-4, 0.0], precision=precision, n_sub=10, sf_method="distance",
+                      contact_law="hertz", young=young, poisson=nu_p, restitution=0.9, mu=0.3, kn=0.0)
+    vol = nx * ny * nz
+    vs = 4.0 / 3.0 * math.pi * radius ** 3
+    key = round(phi, 2)
+    if (nx, ny, nz) == (500, 200, 800) and key in FLUIDIZED_COUNTS:
+        count = FLUIDIZED_COUNTS[key]
+    else:
+        count = int(round(phi / 0.45 * 8596 * vol / (500 * 200 * 800)))
+    rng = SplitMix64(seed)
+    if count == 0:
+        pos = np.zeros((0, 3))
+    elif phi <= 0.25:
+        radii = np.full(count, radius)
+        pos = rsa_spheres(rng, count, radii, (nx, ny, nz), [True, False, True], gap=1.0)
+    else:
+        ax, az = nx / max(1, int(nx // 31.25)), nz / max(1, int(nz // 32.0))
+        ay = 31.25
+        cx, cz = int(round(nx / ax)), int(round(nz / az))
+        layers = []
+        k = 0
+        while True:
+            y = radius + 1.0 + k * ay / 2
+            if y + radius + 1.0 > ny:
+                break
+            off = k % 2
+            layer = []
+            for i in range(cx):
+                for j in range(cz):
+                    # FCC: layer A holds (0, 0) and (1/2, 1/2), layer B (1/2, 0) and (0, 1/2)
+                    for (u, w) in (((0.0, 0.0), (0.5, 0.5)) if off == 0 else ((0.5, 0.0), (0.0, 0.5))):
+                        layer.append(((i + u + 0.25) * ax, y, (j + w + 0.25) * az))
+            layers.append(np.array(layer))
+            k += 1
+        pts = []
+        for L in layers:
+            need = count - sum(len(p) for p in pts)
+            if need <= 0:
+                break
+            if need < len(L):
+                order = np.argsort(rng.uniform(len(L)), kind="stable")
+                L = L[np.sort(order[:need])]
+            pts.append(L)
+        pos = np.concatenate(pts)
+        if len(pos) < count:
+            raise ValueError("the settled bed holds %d of %d spheres" % (len(pos), count))
+        pos = pos + (rng.uniform(3 * len(pos)).reshape(-1, 3) - 0.5)
+        pos[:, 0] %= nx
+        pos[:, 2] %= nz
+    m = len(pos)
+    parts = spheres(pos, radius, 1.1) if m else None
+    name = f"fluidized_bed_{nx}x{ny}x{nz}_phi{phi:.2f}_{m}_spheres"
+    return cfg, parts, dict(workload=name, steps=steps, phi=phi)
+
+
 def kolmogorov_ellipsoids(n=256, fraction=0.2, precision="fp32", seed=1003, amp=1e-6):
     """Periodic n^3 lattice, tau = 0.55, Kolmogorov forcing of the fluid with
     component x = amp sin(2 pi (y + 1/2) / n); prolate ellipsoids with

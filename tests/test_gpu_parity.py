@@ -394,6 +394,35 @@ def test_couette_hertz_steps(ps, oracle_mod, prec):
         assert force_err(Pg["f_hyd"], Po["f_hyd"], sc["f_hyd"]) < TOL[prec]
 
 
+@pytest.mark.parametrize("phi", [0.15, 0.45])
+def test_fluidized_bed_reduced(ps, oracle_mod, phi):
+    """The paper's fluidized-bed recipe (D = 20, y walls, gravity -y, density
+    1.1, 10 substeps, distance solid fraction, Hertz contacts) on a 128 x 104
+    x 128 lattice: 61 spheres by random addition at 0.15, a settled bed of
+    183 at 0.45 (the single-workgroup DEM; the full-size bed's 2866-8596
+    spheres take the multi-launch path, covered by the settling-bed test);
+    two coupled steps against the FP64 oracle, registrations and pairs bit
+    for bit."""
+    cfg, parts, meta = W.fluidized_bed(precision="fp64", phi=phi, n=(128, 104, 128))
+    cfg["collision"] = "trt"
+    G, O = _pair(ps, oracle_mod, cfg, parts)
+    for _ in range(2):
+        G.step(1)
+        O.step(1)
+    assert np.array_equal(G.pairs()[0], O.pairs()[0])
+    cg, pg, bg = G.solid()
+    co, po, bo = O.solid()
+    assert np.array_equal(cg, co) and np.array_equal(pg, po)
+    assert np.abs(bg - bo).max() < 1e-12
+    assert pop_err(G.populations(), O.populations()) < TOL["fp64"]
+    Pg, Po = G.particles(), O.particles()
+    sc = O.scales()
+    assert vec_err(Pg["pos"], Po["pos"]) < TOL["fp64"]
+    assert vec_err(Pg["vel"], Po["vel"]) < TOL["fp64"]
+    assert force_err(Pg["f_hyd"], Po["f_hyd"], sc["f_hyd"]) < TOL["fp64"]
+    assert force_err(Pg["m_hyd"], Po["m_hyd"], sc["m_hyd"]) < TOL["fp64"]
+
+
 def test_couette_full_size_fp32(ps, oracle_mod):
     """The bench workload at its full size (128^3, 500 spheres R = 5, moving
     walls, n_sub = 11) in the bench's precision: two coupled steps from
