@@ -41,8 +41,9 @@ def parse():
     p.add_argument("--fluidized-sweep", action="store_true",
                    help="the paper's performance study: fluidized bed 500x200x800 at phi = 0, 0.15, 0.30, "
                         "0.45 in FP32 and FP64, one JSON line per point")
-    p.add_argument("--collision", default="bgk", choices=["bgk", "trt"],
-                   help="fluid operator inside the PSM collision (TRT: the paper's tau- rule)")
+    p.add_argument("--collision", default=None, choices=["bgk", "trt"],
+                   help="fluid operator inside the PSM collision (TRT: the paper's tau- rule); default: the "
+                        "workload's own (TRT for the fluidized bed, as in the paper's studies, else BGK)")
     p.add_argument("--spheres", type=int, default=500)
     p.add_argument("--cpu-sample-steps", type=int, default=120,
                    help="coupled steps of the CPU oracle sample (0: skip the CPU baseline)")
@@ -177,7 +178,9 @@ def fluidized_sweep(warmup, steps, collision):
     for phi in (0.0, 0.15, 0.30, 0.45):
         cfg, parts, meta = workloads.fluidized_bed(phi=phi)
         for prec in ("fp32", "fp64"):
-            cfg = dict(cfg, precision=prec, collision=collision)
+            cfg = dict(cfg, precision=prec)
+            if collision:
+                cfg["collision"] = collision
             N = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]
             D = psmdem.Domain(cfg, parts, stream=torch.cuda.current_stream())
             D.step(warmup)
@@ -386,7 +389,7 @@ def main():
         copy_probe(a.copy_probe)
         return
     if a.lbm_sweep:
-        lbm_sweep(a.lbm_sweep, a.collision)
+        lbm_sweep(a.lbm_sweep, a.collision or "bgk")
         return
     if a.precision_study:
         precision_study(a.precision_study, a.study_fraction)
@@ -406,7 +409,8 @@ def main():
         cfg, parts, meta = workloads.fluidized_bed(precision=a.precision, phi=a.phi)
     else:
         cfg, parts, meta = workloads.settling_bed(precision=a.precision)
-    cfg["collision"] = a.collision
+    if a.collision:
+        cfg["collision"] = a.collision
     N = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]
     stream = torch.cuda.current_stream()
     D = psmdem.Domain(cfg, parts, stream=stream)
@@ -468,7 +472,7 @@ def main():
            "warmup": a.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": a.precision, "data": "synthetic",
            "config": {"workload": meta["workload"], "lattice": list(cfg["n"]), "particles": info["n_particles"],
-                      "n_sub": info["n_sub"], "tau": cfg["tau"], "collision": a.collision,
+                      "n_sub": info["n_sub"], "tau": cfg["tau"], "collision": cfg.get("collision", "bgk"),
                       "populations": a.precision,
                       "particles_dtype": "fp64"},
            "roofline": roof, "cpu_baseline": cpu, "serving": serve}

@@ -371,6 +371,31 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
+// Adds, for every distinct particle id among the lanes with has set, the wave
+// sum of those lanes' (P, T) into acc[wid][id] (lane 0 writes; a fixed
+// butterfly order, no atomics).
+__device__ inline void wave_add_by_id(bool has, int my, const double* P, const double* T, double* acc, int wid,
+                                      int lane) {
+    unsigned long long pending = ballot64(has);
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int target = __shfl(my, leader, 64);
+        const bool mine = has && my == target;
+        double v[6];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            v[a] = mine ? P[a] : 0.0;
+            v[3 + a] = mine ? T[a] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 6; ++a) v[a] = wave_sum(v[a]);
+        if (lane == 0)
+#pragma unroll
+            for (int a = 0; a < 6; ++a) acc[(wid * PSM_PMAX + target) * 6 + a] += v[a];
+        pending &= ~ballot64(mine);
+    }
+}
+
 // MS = 0: tiles without registered particles; MS > 0: tiles with particles
 // one tile of one domain (the body shared by the single-domain and the batched kernels)
 template <typename S, typename C, bool ODD, int MS>
@@ -416,6 +441,19 @@ __device__ void lbm_tile(const LbmArgs& A, const long long t, double* kin_s, dou
     // some lane of this wave sits at an x wall (only the odd step's plain access differs)
     const bool row_xw = ODD && __ballot(xy_ok && (ax.wl || ax.wh)) != 0ull;
 
+    // Momentum exchange: each lane accumulates its cells' (P, T) over the
+    // tile's planes in MS register slots, one per particle id; the wave sums
+    // run once per tile (a lane meeting more ids than slots sends the extra
+    // term through the wave sum of its plane).
+    int aid[MS > 0 ? MS : 1];
+    double aP[MS > 0 ? MS : 1][3], aT[MS > 0 ? MS : 1][3];
+#pragma unroll
+    for (int s = 0; s < MS; ++s) {
+        aid[s] = -1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) aP[s][a] = aT[s][a] = 0.0;
+    }
+
 #pragma unroll 1
     for (int lz = 0; lz < PSM_TZ; ++lz) {
         const int z = tz * PSM_TZ + lz;
@@ -425,6 +463,15 @@ __device__ void lbm_tile(const LbmArgs& A, const long long t, double* kin_s, dou
         C Pk[MS > 0 ? MS : 1][3];
         int lpk[MS > 0 ? MS : 1];
         if (valid) {
+            // the cell's solid slots are loaded with its populations: one round trip
+            unsigned lp = 0xffffffffu;
+            C Braw[MS > 0 ? MS : 1];
+            const long long sl = t * (long long)PSM_TILE + lane + PSM_TX * (wid + PSM_TY * lz);
+            if (MS > 0) {
+                lp = A.t.slot_lp[sl];
+#pragma unroll
+                for (int k = 0; k < MS; ++k) Braw[k] = k < A.ms ? Bslot[k * plane + sl] : (C)0;
+            }
             const AxisNb az = axis_nb(z, A.g.nz, A.g.periodic[2], A.g.nx * A.g.ny);
             const long long cell = (long long)x + (long long)A.g.nx * ((long long)y + (long long)A.g.ny * z);
             C g[19], out[19];
@@ -452,14 +499,12 @@ __device__ void lbm_tile(const LbmArgs& A, const long long t, double* kin_s, dou
             }
             C uk[MS > 0 ? MS : 1][3];
             if (MS > 0) {
-                const long long sl = t * (long long)PSM_TILE + lane + PSM_TX * (wid + PSM_TY * lz);
-                const unsigned lp = A.t.slot_lp[sl];
 #pragma unroll
                 for (int k = 0; k < MS; ++k) {
                     const unsigned b = (lp >> (8 * k)) & 0xffu;
                     if (k == nk && k < A.ms && b != 0xffu && (int)b < count) {
                         lpk[k] = (int)b;
-                        B[k] = Bslot[k * plane + sl];
+                        B[k] = Braw[k];
                         const double* kn = kin_s + 9 * b;
                         const double rj[3] = {x + 0.5, y + 0.5, z + 0.5};
                         double d[3];
@@ -517,28 +562,29 @@ __device__ void lbm_tile(const LbmArgs& A, const long long t, double* kin_s, dou
                     T[1] = d[2] * P[0] - d[0] * P[2];
                     T[2] = d[0] * P[1] - d[1] * P[0];
                 }
-                unsigned long long pending = ballot64(has);
-                while (pending) {
-                    const int leader = __ffsll((long long)pending) - 1;
-                    const int target = __shfl(my, leader, 64);
-                    const bool mine = has && my == target;
-                    double v[6];
+                // the lane's slot for this id: a matching one, else the first free one
+                bool placed = false;
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        v[a] = mine ? P[a] : 0.0;
-                        v[3 + a] = mine ? T[a] : 0.0;
+                for (int s = 0; s < MS; ++s) {
+                    const bool take = has && !placed && (aid[s] == my || aid[s] < 0);
+                    if (take) {
+                        aid[s] = my;
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            aP[s][a] += P[a];
+                            aT[s][a] += T[a];
+                        }
                     }
-#pragma unroll
-                    for (int a = 0; a < 6; ++a) v[a] = wave_sum(v[a]);
-                    if (lane == 0)
-#pragma unroll
-                        for (int a = 0; a < 6; ++a) acc[(wid * PSM_PMAX + target) * 6 + a] += v[a];
-                    pending &= ~ballot64(mine);
+                    placed = placed || take;
                 }
+                if (__ballot(has && !placed)) wave_add_by_id(has && !placed, my, P, T, acc, wid, lane);
             }
         }
     }
     if (MS > 0) {
+#pragma unroll
+        for (int s = 0; s < MS; ++s)
+            if (__ballot(aid[s] >= 0)) wave_add_by_id(aid[s] >= 0, aid[s], aP[s], aT[s], acc, wid, lane);
         __syncthreads();
         for (int u = tid; u < count * 6; u += 256) {
             const int p = u / 6, a = u % 6;
@@ -555,8 +601,16 @@ __device__ inline long long xcd_block(long long nblocks) {
     return (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
 }
 
+// PSM tiles (two slots): four workgroups per CU within 128 registers where it
+// measures faster than the natural allocation (three): 16-bit storage (some
+// spilled on the odd step) and the float even step (no spill)
+template <typename S, bool ODD, int MS>
+struct LbmMinBlocks {
+    static constexpr int value = (MS == 2 && (sizeof(S) == 2 || (sizeof(S) == 4 && !ODD))) ? 4 : 1;
+};
+
 template <typename S, typename C, bool ODD, int MS>
-__global__ __launch_bounds__(256) void k_lbm(LbmArgs A) {
+__global__ __launch_bounds__(256, (LbmMinBlocks<S, ODD, MS>::value)) void k_lbm(LbmArgs A) {
     __shared__ double kin_s[MS > 0 ? PSM_PMAX * 9 : 1];
     __shared__ double acc[MS > 0 ? 4 * PSM_PMAX * 6 : 1];
     const long long t = xcd_block(A.g.ntiles);

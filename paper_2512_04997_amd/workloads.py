@@ -348,7 +348,8 @@ def fluidized_bed(precision="fp32", phi=0.15, n=(500, 200, 800), radius=10.0, se
     """The paper's performance configuration (Sec. 5): a lattice of
     500 x 200 x 800 cells, periodic in x and z, no-slip walls in y, gravity
     along -y, spheres of diameter 20 cells at density ratio 1.1, 10 DEM
-    substeps per step, the distance-based solid fraction, at a solid volume
+    substeps per step, the distance-based solid fraction, the TRT operator
+    (the paper's choice for its studies), at a solid volume
     fraction phi of the whole box (2866, 5731, 8596 spheres at 0.15, 0.30,
     0.45; other fractions in proportion).  Lattice units: tau = 0.8
     (nu = 0.1) and g = 2.25e-4 make the Stokes settling Reynolds number
@@ -366,7 +367,8 @@ def fluidized_bed(precision="fp32", phi=0.15, n=(500, 200, 800), radius=10.0, se
     young = 100.0 * 2.0 * (1.0 - nu_p * nu_p)
     cfg = base_config((nx, ny, nz), 0.8, bc=["periodic", "periodic", "noslip", "noslip", "periodic", "periodic"],
                       gravity=[0.0, -2.25e-4, 0.0], precision=precision, n_sub=10, sf_method="distance",
-                      contact_law="hertz", young=young, poisson=nu_p, restitution=0.9, mu=0.3, kn=0.0)
+                      contact_law="hertz", young=young, poisson=nu_p, restitution=0.9, mu=0.3, kn=0.0,
+                      collision="trt")
     vol = nx * ny * nz
     vs = 4.0 / 3.0 * math.pi * radius ** 3
     key = round(phi, 2)
