@@ -40,7 +40,7 @@ def parse():
     p.add_argument("--phi", type=float, default=0.15, help="solid volume fraction of the fluidized bed")
     p.add_argument("--fluidized-sweep", action="store_true",
                    help="the paper's performance study: fluidized bed 500x200x800 at phi = 0, 0.15, 0.30, "
-                        "0.45 in FP32 and FP64, one JSON line per point")
+                        "0.45 in FP32, FP64 and BF16 storage, one JSON line per point")
     p.add_argument("--collision", default=None, choices=["bgk", "trt"],
                    help="fluid operator inside the PSM collision (TRT: the paper's tau- rule); default: the "
                         "workload's own (TRT for the fluidized bed, as in the paper's studies, else BGK)")
@@ -171,13 +171,13 @@ def lbm_sweep(n, collision="bgk"):
 def fluidized_sweep(warmup, steps, collision):
     """Coupled-step throughput of the paper's fluidized bed (500 x 200 x 800,
     D = 20, 10 substeps, distance solid fraction) against the solid fraction,
-    in FP32 and FP64: one JSON line per point."""
+    in FP32, FP64 and BF16 storage: one JSON line per point."""
     import torch
     from paper_2512_04997_amd import psmdem, workloads
     torch.cuda.set_device(0)
     for phi in (0.0, 0.15, 0.30, 0.45):
         cfg, parts, meta = workloads.fluidized_bed(phi=phi)
-        for prec in ("fp32", "fp64"):
+        for prec in ("fp32", "fp64", "bf16"):
             cfg = dict(cfg, precision=prec)
             if collision:
                 cfg["collision"] = collision

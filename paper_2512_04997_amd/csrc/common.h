@@ -171,5 +171,6 @@ void psm_set_error(const char* fmt, ...);
 
 // exclusive scan of n ints into out[0..n], out[n] = total (device); tmp >= scan_tmp_size(n)
 size_t psm_scan_tmp_ints(long long n);
-hipError_t psm_scan(const int* in, int* out, long long n, int* tmp, hipStream_t s);
+// exclusive scan of in[0..n) into out[0..n], out[n] = total; with run, only if *run != 0
+hipError_t psm_scan(const int* in, int* out, long long n, int* tmp, hipStream_t s, const int* run = nullptr);
 hipError_t psm_fill_int(int* p, int v, long long n, hipStream_t s);

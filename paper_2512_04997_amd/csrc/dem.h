@@ -31,8 +31,10 @@ struct DemArgs {
     double wall_u[6][3];
     double gravity[3];
     int ellipsoids;        // any particle is an ellipsoid (else the sphere-only kernels run)
-    int* fused_age;        // [1] substeps the single-workgroup DEM's list had been kept when its last
-                           // launch ended (pc holds the cells it was built from); -1: rebuild
+    int* fused_age;        // [1] substeps the pair list has been kept (pc holds the cells it was built
+                           // from, the wall candidates in pc's last word); -1: rebuild
+    int* list_flag;        // [2] multi-launch path: the list changed in this substep (by substep parity)
+    const int* list_run;   // multi-launch path: list_flag of this substep, or null (always build)
     DevCounters* ctr;
 };
 
@@ -55,6 +57,9 @@ struct PairSet {
 
 hipError_t dem_predict(const DemArgs& A, double dt, int write_kin, hipStream_t s);
 hipError_t dem_lists(const DemArgs& A, const PairBufs& B, int* scan_tmp, hipStream_t s);
+// multi-launch substeps that keep an unchanged list (A.list_run = A.list_flag + par)
+hipError_t dem_predict_keep(const DemArgs& A, double dt, int write_kin, int par, hipStream_t s);
+hipError_t dem_lists_kept(const DemArgs& A, const PairBufs& B, int par, int* scan_tmp, hipStream_t s);
 hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, const double* ww, double dth,
                         int* scan_tmp, hipStream_t s);
 hipError_t dem_correct(const DemArgs& A, double dt, hipStream_t s);

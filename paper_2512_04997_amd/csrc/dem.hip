@@ -948,11 +948,69 @@ __global__ void k_predict(DemArgs A, double dt, int write_kin) {
         store_cells(A, (int)k, r);
     }
 }
+
+// Multi-launch substeps keep the pair list while it is unchanged: the
+// predictor also compares each particle's new cells and wall candidates with
+// the stored ones (those of the last substep, so of the list) and raises
+// list_flag[par]; it clears the other parity's flag for the next substep.
+__global__ void k_predict_keep(DemArgs A, double dt, int write_kin, int par) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) A.list_flag[par ^ 1] = 0;
+    GRID_LOOP(k, A.p.np) {
+        const int kk = (int)k;
+        const int* d = A.pc + 8 * kk;
+        unsigned old[4];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) old[a] = (unsigned)d[2 * a] | ((unsigned)d[2 * a + 1] << 16);
+        old[3] = (unsigned)d[7];
+        const double rbk = A.p.rb[kk];
+        AxCells r;
+        double xk[3];
+        ph_predict(A, kk, dt, write_kin, r, nullptr, xk);
+        store_cells(A, kk, r);
+        unsigned wm = 0;
+#pragma unroll
+        for (int f = 0; f < 6; ++f) {
+            const int a = f / 2;
+            const double wd = (f % 2 == 0) ? xk[a] : A.L[a] - xk[a];
+            wm |= (A.g.bc[f] != 0 && wd < rbk) ? 1u << f : 0u;
+        }
+        A.pc[8 * kk + 7] = (int)wm;
+        bool ch = wm != old[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) ch |= ((unsigned)r.c[a][0] | ((unsigned)r.c[a][1] << 16)) != old[a];
+        if (ch) atomicOr(&A.list_flag[par], 1);
+    }
+}
+
+// the substep's decision: rebuild when something changed or no list is kept
+__global__ void k_list_age(DemArgs A, int par) {
+    const int age = *A.fused_age;
+    const int ch = A.list_flag[par] != 0 || age < 0;
+    A.list_flag[par] = ch;
+    *A.fused_age = ch ? 0 : age + 1;
+}
+
+// one substep after a rebuild the kept list is copied into this buffer
+__global__ void k_list_copy(DemArgs A, PairBufs B, int par) {
+    if (A.list_flag[par] || *A.fused_age != 1) return;
+    long long n = *B.prev_n;
+    n = n < A.pair_cap ? n : A.pair_cap;
+    const int* prev_prow = B.prev_n - A.p.np;
+    GRID_LOOP(u, n) B.pairs[u] = B.prev_pairs[u];
+    GRID_LOOP(u, (long long)A.p.np + 1) B.prow[u] = prev_prow[u];
+}
 __global__ void k_cells(DemArgs A) { GRID_LOOP(k, A.p.np) ph_cells(A, (int)k); }
-__global__ void k_hist(DemArgs A) { GRID_LOOP(k, A.p.np) ph_hist(A, (int)k); }
-__global__ void k_scatter(DemArgs A) { GRID_LOOP(k, A.p.np) ph_scatter(A, (int)k); }
+__global__ void k_hist(DemArgs A) {
+    if (A.list_run && !*A.list_run) return;
+    GRID_LOOP(k, A.p.np) ph_hist(A, (int)k);
+}
+__global__ void k_scatter(DemArgs A) {
+    if (A.list_run && !*A.list_run) return;
+    GRID_LOOP(k, A.p.np) ph_scatter(A, (int)k);
+}
 // sorts each cell's list, then clears the cell's counters for the next list build
 __global__ void k_cellsort(DemArgs A) {
+    if (A.list_run && !*A.list_run) return;
     GRID_LOOP(c, A.ncell) {
         ph_cellsort(A, c);
         A.cell_count[c] = 0;
@@ -1016,6 +1074,7 @@ __device__ inline int wave_candidate(const DemArgs& A, int i, const AxCells& ri,
 #define PAIR_KEPT_MAX 256
 
 __global__ __launch_bounds__(256) void k_paircount(DemArgs A) {
+    if (A.list_run && !*A.list_run) return;
     const int lane = threadIdx.x & 63;
     const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
     for (long long iw = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; iw < A.p.np; iw += nw) {
@@ -1034,6 +1093,7 @@ __global__ __launch_bounds__(256) void k_paircount(DemArgs A) {
 }
 
 __global__ __launch_bounds__(256) void k_pairemit(DemArgs A, PairBufs B) {
+    if (A.list_run && !*A.list_run) return;
     __shared__ int kept_s[4][PAIR_KEPT_MAX];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const unsigned long long lanes_below = (1ull << lane) - 1ull;
@@ -1087,13 +1147,16 @@ __global__ __launch_bounds__(256) void k_contacts(DemArgs A, PairBufs B, const d
     long long nprev = B.prev_n ? *B.prev_n : 0;
     nprev = nprev < A.pair_cap ? nprev : A.pair_cap;
     const long long n = n_pairs(A, B);
-    GRID_LOOP(s, n) ph_contact<ELL>(A, B, s, vv, ww, dth, nprev);
+    const bool same = A.list_run && !*A.list_run;  // a kept list: history at the pair's own index
+    GRID_LOOP(s, n) ph_contact<ELL>(A, B, s, vv, ww, dth, nprev, same);
 }
 __global__ void k_colhist(DemArgs A, PairBufs B) {
+    if (A.list_run && !*A.list_run) return;
     const long long n = n_pairs(A, B);
     GRID_LOOP(s, n) ph_colhist(A, B, s);
 }
 __global__ void k_colscatter(DemArgs A, PairBufs B) {
+    if (A.list_run && !*A.list_run) return;
     const long long n = n_pairs(A, B);
     GRID_LOOP(s, n) ph_colscatter(A, B, s);
 }
@@ -1101,6 +1164,7 @@ __global__ void k_colscatter(DemArgs A, PairBufs B) {
 // wave per column: entries are distinct, so an entry's place is the number of
 // entries below it; then clears the column's counters for the next build.
 __global__ __launch_bounds__(256) void k_colsort(DemArgs A) {
+    if (A.list_run && !*A.list_run) return;
     const int lane = threadIdx.x & 63;
     const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
     for (long long jw = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; jw < A.p.np; jw += nw) {
@@ -1651,6 +1715,29 @@ hipError_t dem_predict(const DemArgs& A, double dt, int write_kin, hipStream_t s
     return hipGetLastError();
 }
 
+hipError_t dem_predict_keep(const DemArgs& A, double dt, int write_kin, int par, hipStream_t s) {
+    if (A.p.np == 0) return hipSuccess;
+    k_predict_keep<<<nblk(A.p.np), 256, 0, s>>>(A, dt, write_kin, par);
+    return hipGetLastError();
+}
+
+// the multi-launch list build of a substep, its kernels skipped (on the
+// device) when the list is kept; A.list_run is list_flag + par
+hipError_t dem_lists_kept(const DemArgs& A, const PairBufs& B, int par, int* scan_tmp, hipStream_t s) {
+    if (A.p.np == 0) return hipSuccess;
+    hipError_t e;
+    k_list_age<<<1, 1, 0, s>>>(A, par);
+    k_list_copy<<<nblk(A.pair_cap), 256, 0, s>>>(A, B, par);
+    k_hist<<<nblk(A.p.np), 256, 0, s>>>(A);
+    if ((e = psm_scan(A.cell_count, A.cell_start, A.ncell, scan_tmp, s, A.list_run)) != hipSuccess) return e;
+    k_scatter<<<nblk(A.p.np), 256, 0, s>>>(A);
+    k_cellsort<<<nblk(A.ncell), 256, 0, s>>>(A);
+    k_paircount<<<nblk(64LL * A.p.np), 256, 0, s>>>(A);
+    if ((e = psm_scan(A.pcount, B.prow, A.p.np, scan_tmp, s, A.list_run)) != hipSuccess) return e;
+    k_pairemit<<<nblk(64LL * A.p.np), 256, 0, s>>>(A, B);
+    return hipGetLastError();
+}
+
 hipError_t dem_lists(const DemArgs& A, const PairBufs& B, int* scan_tmp, hipStream_t s) {
     if (A.p.np == 0) return hipSuccess;
     hipError_t e;
@@ -1673,7 +1760,7 @@ hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, c
     if (A.ellipsoids) k_contacts<true><<<nblk(A.pair_cap, 128), 128, 0, s>>>(A, B, vv, ww, dth);
     else k_contacts<false><<<nblk(A.pair_cap, 128), 128, 0, s>>>(A, B, vv, ww, dth);
     k_colhist<<<nblk(A.pair_cap), 256, 0, s>>>(A, B);
-    if ((e = psm_scan(A.col_count, A.col_start, A.p.np, scan_tmp, s)) != hipSuccess) return e;
+    if ((e = psm_scan(A.col_count, A.col_start, A.p.np, scan_tmp, s, A.list_run)) != hipSuccess) return e;
     k_colscatter<<<nblk(A.pair_cap), 256, 0, s>>>(A, B);
     k_colsort<<<nblk(64LL * A.p.np), 256, 0, s>>>(A);
     k_sum<<<nblk(A.p.np, 128), 128, 0, s>>>(A, B);

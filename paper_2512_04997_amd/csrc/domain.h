@@ -42,6 +42,8 @@ struct psmdem_domain {
     int *cell_count = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *cell_pid = nullptr;
     int* pc = nullptr;
     int* fused_age = nullptr;
+    int* list_flag = nullptr;
+    long long dem_sub = 0;  // multi-launch substeps run (their parity indexes list_flag)
     int *col_count = nullptr, *col_fill = nullptr, *col_start = nullptr, *col_list = nullptr;
     long long reg_cap = 0;
     int* pcount = nullptr;
@@ -118,6 +120,8 @@ struct psmdem_domain {
         A.ncell = ncell;
         A.pc = pc;
         A.fused_age = fused_age;
+        A.list_flag = list_flag;
+        A.list_run = nullptr;
         A.cell_count = cell_count;
         A.cell_start = cell_start;
         A.cell_fill = cell_fill;

@@ -162,11 +162,15 @@ static int coupled_step(psmdem_domain* D) {
         for (int sub = 1; sub <= D->nsub; ++sub) {
             const bool last = sub == D->nsub;
             int tk = D->timed_begin(PSMDEM_T_DEM);
+            // the list is rebuilt only when some particle's cells or wall
+            // candidates changed (decided on the device, list_flag[par])
+            const int par = (int)(D->dem_sub++ & 1);
             DemArgs A = D->dem_args();
-            PSM_CHECK(dem_predict(A, D->dt, last ? 1 : 0, D->s));
+            A.list_run = A.list_flag + par;
+            PSM_CHECK(dem_predict_keep(A, D->dt, last ? 1 : 0, par, D->s));
             D->cur ^= 1;
             PairBufs B = D->pair_bufs(1);
-            PSM_CHECK(dem_lists(A, B, D->scan_tmp, D->s));
+            PSM_CHECK(dem_lists_kept(A, B, par, D->scan_tmp, D->s));
             PSM_CHECK(dem_contacts(A, B, D->p.vp, D->p.wp, D->dt, D->scan_tmp, D->s));
             D->timed_end(tk);
             if (last && D->d.fluid_on) {
@@ -398,6 +402,7 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
     D->reg_cap = 8LL * std::max(np, 1);
     D->pc = (int*)A(sizeof(int) * 8 * std::max(np, 1));
     D->fused_age = (int*)A(sizeof(int));
+    D->list_flag = (int*)A(2 * sizeof(int));
     D->cell_count = (int*)A(sizeof(int) * D->ncell);
     D->cell_fill = (int*)A(sizeof(int) * D->ncell);
     D->cell_start = (int*)A(sizeof(int) * (D->ncell + 1));
@@ -516,6 +521,7 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
             hipMemsetAsync(D->t.slot_lp, 0xff, sizeof(unsigned) * g.ntiles * (size_t)PSM_TILE, D->s) != hipSuccess ||
             hipMemsetAsync(D->cell_pid, 0, sizeof(int) * D->reg_cap, D->s) != hipSuccess ||
             hipMemsetAsync(D->fused_age, 0xff, sizeof(int), D->s) != hipSuccess ||
+            hipMemsetAsync(D->list_flag, 0, 2 * sizeof(int), D->s) != hipSuccess ||
             hipStreamSynchronize(D->s) != hipSuccess)
             rc = PSMDEM_E_HIP;
     }

@@ -36,7 +36,8 @@ __device__ int block_excl_scan(int v, int* total) {
 }
 
 __global__ __launch_bounds__(SCAN_T) void k_scan_local(const int* __restrict__ in, int* __restrict__ out,
-                                                       long long n, int* __restrict__ bsum) {
+                                                       long long n, int* __restrict__ bsum, const int* run) {
+    if (run && !*run) return;
     long long base = (long long)blockIdx.x * SCAN_BLOCK + (long long)threadIdx.x * SCAN_PER;
     int v[SCAN_PER];
     int s = 0;
@@ -57,7 +58,8 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_local(const int* __restrict__ i
 
 // single block: exclusive scan of nb block totals, in place; total to out[n]
 __global__ __launch_bounds__(SCAN_T) void k_scan_bsum(int* __restrict__ bsum, int nb, int* __restrict__ out,
-                                                      long long n) {
+                                                      long long n, const int* run) {
+    if (run && !*run) return;
     __shared__ int carry;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
@@ -76,7 +78,8 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_bsum(int* __restrict__ bsum, in
 }
 
 __global__ __launch_bounds__(SCAN_T) void k_scan_add(int* __restrict__ out, long long n,
-                                                     const int* __restrict__ bsum) {
+                                                     const int* __restrict__ bsum, const int* run) {
+    if (run && !*run) return;
     long long base = (long long)blockIdx.x * SCAN_BLOCK + (long long)threadIdx.x * SCAN_PER;
     int add = bsum[blockIdx.x];
 #pragma unroll
@@ -89,7 +92,8 @@ constexpr long long SCAN_SMALL = 32768;
 // One workgroup of 1024 lanes walks the input in chunks of 4096 entries, four
 // consecutive entries per lane (coalesced), with a running carry (in place
 // allowed: a lane reads its entries before it writes them).
-__global__ __launch_bounds__(1024) void k_scan_small(const int* in, int* out, long long n) {
+__global__ __launch_bounds__(1024) void k_scan_small(const int* in, int* out, long long n, const int* run) {
+    if (run && !*run) return;
     __shared__ int wsum[16];
     __shared__ int carry_s;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -139,16 +143,16 @@ __global__ void k_fill_int(int* __restrict__ p, int v, long long n) {
 
 size_t psm_scan_tmp_ints(long long n) { return (size_t)((n + SCAN_BLOCK - 1) / SCAN_BLOCK + 1); }
 
-hipError_t psm_scan(const int* in, int* out, long long n, int* tmp, hipStream_t s) {
+hipError_t psm_scan(const int* in, int* out, long long n, int* tmp, hipStream_t s, const int* run) {
     if (n <= SCAN_SMALL) {
-        k_scan_small<<<1, 1024, 0, s>>>(in, out, n < 0 ? 0 : n);
+        k_scan_small<<<1, 1024, 0, s>>>(in, out, n < 0 ? 0 : n, run);
         return hipGetLastError();
     }
     int nb = (int)((n + SCAN_BLOCK - 1) / SCAN_BLOCK);
     if (nb < 1) nb = 1;
-    k_scan_local<<<nb, SCAN_T, 0, s>>>(in, out, n, tmp);
-    k_scan_bsum<<<1, SCAN_T, 0, s>>>(tmp, nb, out, n);
-    k_scan_add<<<nb, SCAN_T, 0, s>>>(out, n, tmp);
+    k_scan_local<<<nb, SCAN_T, 0, s>>>(in, out, n, tmp, run);
+    k_scan_bsum<<<1, SCAN_T, 0, s>>>(tmp, nb, out, n, run);
+    k_scan_add<<<nb, SCAN_T, 0, s>>>(out, n, tmp, run);
     return hipGetLastError();
 }
 
