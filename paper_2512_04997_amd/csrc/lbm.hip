@@ -618,6 +618,23 @@ __global__ __launch_bounds__(256, (LbmMinBlocks<S, ODD, MS>::value)) void k_lbm(
     lbm_tile<S, C, ODD, MS>(A, t, kin_s, acc);
 }
 
+// Both tile kinds in one launch: the branch is uniform over the workgroup (a
+// tile's registration count decides it), so a pass is one kernel and the few
+// particle-free tiles of a dense suspension share the rounds of the PSM tiles
+// instead of a launch of their own.
+template <typename S, typename C, bool ODD, int MS>
+__global__ __launch_bounds__(256, (LbmMinBlocks<S, ODD, MS>::value)) void k_lbm_mixed(LbmArgs A) {
+    __shared__ double kin_s[PSM_PMAX * 9];
+    __shared__ double acc[4 * PSM_PMAX * 6];
+    const long long t = xcd_block(A.g.ntiles);
+    if (t >= A.g.ntiles) return;
+    const long long s0 = A.t.tile_start[t];
+    long long s1 = A.t.tile_start[t + 1];
+    if (s1 > A.t.cap) s1 = A.t.cap;
+    if (s1 > s0) lbm_tile<S, C, ODD, MS>(A, t, kin_s, acc);
+    else lbm_tile<S, C, ODD, 0>(A, t, kin_s, acc);
+}
+
 // many domains in one launch: map[b] = (job, tile), the job's parity in dyn.odd
 template <typename S, typename C, int MS>
 __global__ __launch_bounds__(256) void k_lbm_batch(const LbmArgs* __restrict__ jobs, SrvDyn dyn,
@@ -645,15 +662,18 @@ template <typename S, typename C>
 hipError_t launch_step(const LbmArgs& A, int odd, hipStream_t s) {
     const unsigned nblk = (unsigned)(8 * ((A.g.ntiles + 7) / 8));
     // without particles no tile holds a registration: the PSM launch is skipped
+    // (two slots: one launch for both tile kinds; four slots keep two launches,
+    // whose PSM kernel alone already fills the register file)
     const bool psm = A.np > 0;
-    if (odd) {
+    if (psm && A.ms <= 2) {
+        if (odd) k_lbm_mixed<S, C, true, 2><<<nblk, 256, 0, s>>>(A);
+        else k_lbm_mixed<S, C, false, 2><<<nblk, 256, 0, s>>>(A);
+    } else if (odd) {
         k_lbm<S, C, true, 0><<<nblk, 256, 0, s>>>(A);
-        if (psm && A.ms <= 2) k_lbm<S, C, true, 2><<<nblk, 256, 0, s>>>(A);
-        else if (psm) k_lbm<S, C, true, 4><<<nblk, 256, 0, s>>>(A);
+        if (psm) k_lbm<S, C, true, 4><<<nblk, 256, 0, s>>>(A);
     } else {
         k_lbm<S, C, false, 0><<<nblk, 256, 0, s>>>(A);
-        if (psm && A.ms <= 2) k_lbm<S, C, false, 2><<<nblk, 256, 0, s>>>(A);
-        else if (psm) k_lbm<S, C, false, 4><<<nblk, 256, 0, s>>>(A);
+        if (psm) k_lbm<S, C, false, 4><<<nblk, 256, 0, s>>>(A);
     }
     return hipGetLastError();
 }
