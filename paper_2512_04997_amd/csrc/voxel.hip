@@ -307,6 +307,79 @@ __device__ int classify(const VoxPart& P, int X, int Y, int Z) {
     return all_in ? 1 : 2;
 }
 
+// The sphere branch of classify split at its axis loop: the x and y terms of a
+// column once, then the z term per plane; the sums round in the same order,
+// so the result is classify's.
+struct SphCol {
+    double maxr2, minr2, R2, m;
+};
+
+__device__ inline SphCol sphere_column(const VoxPart& P, int X, int Y) {
+    SphCol s;
+    s.R2 = P.ax[0] * P.ax[0];
+    s.maxr2 = 0.0;
+    s.minr2 = 0.0;
+    const int Xc[2] = {X, Y};
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const double dl = (double)Xc[a] - P.c[a];
+        const double dh = ((double)Xc[a] + 1.0) - P.c[a];
+        const double l2 = dl * dl, h2 = dh * dh;
+        s.maxr2 += l2 > h2 ? l2 : h2;
+        s.minr2 += dl > 0.0 ? l2 : (dh < 0.0 ? h2 : 0.0);
+    }
+    s.m = 1e-8 * (1.0 + s.R2);
+    return s;
+}
+
+__device__ inline int sphere_class_z(const SphCol& s, double cz, int Z) {
+    const double dl = (double)Z - cz;
+    const double dh = ((double)Z + 1.0) - cz;
+    const double l2 = dl * dl, h2 = dh * dh;
+    const double maxr2 = s.maxr2 + (l2 > h2 ? l2 : h2);
+    const double minr2 = s.minr2 + (dl > 0.0 ? l2 : (dh < 0.0 ? h2 : 0.0));
+    if (maxr2 < s.R2 - s.m) return 1;
+    if (minr2 > s.R2 + s.m) return 0;
+    return 2;
+}
+
+// Boundary cells (class 2) of a lane's column, visited candidate by candidate
+// (ascending pid) with the tile's planes unrolled: f(lz, u, P, X, Y, Z) for
+// each.  The per-plane visit order (pid ascending) is that of for_each_pair.
+template <typename F>
+__device__ inline void for_each_boundary_by_candidate(const VoxArgs& A, const VoxPart* sp, int tz, int x, int y,
+                                                      bool xy_ok, unsigned long long cm0, unsigned long long cm1,
+                                                      F f) {
+    if (!xy_ok) return;
+    for (int w = 0; w < 2; ++w)
+        for (unsigned long long bits = w ? cm1 : cm0; bits; bits &= bits - 1) {
+            const int u = 64 * w + __ffsll((long long)bits) - 1;
+            const VoxPart& P = sp[u];
+            int X, Y;
+            in_box(P, x, A.g.nx, 0, A.g.periodic[0], &X);
+            in_box(P, y, A.g.ny, 1, A.g.periodic[1], &Y);
+            if (P.shape == 0) {
+                const SphCol s = sphere_column(P, X, Y);
+                const double cz = P.c[2];
+#pragma unroll
+                for (int lz = 0; lz < PSM_TZ; ++lz) {
+                    const int z = tz * PSM_TZ + lz;
+                    int Z;
+                    if (z < A.g.nz && in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z) && sphere_class_z(s, cz, Z) == 2)
+                        f(lz, u, P, X, Y, Z);
+                }
+            } else {
+#pragma unroll 1
+                for (int lz = 0; lz < PSM_TZ; ++lz) {
+                    const int z = tz * PSM_TZ + lz;
+                    int Z;
+                    if (z < A.g.nz && in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z) && classify(P, X, Y, Z) == 2)
+                        f(lz, u, P, X, Y, Z);
+                }
+            }
+        }
+}
+
 // one sample m (a fastest): inside test in the evaluation order of the definition
 __device__ inline bool sample_in(const VoxPart& P, int X, int Y, int Z, const double* off, int ns, int m) {
     const int a = m % ns, b = (m / ns) % ns, c = m / (ns * ns);
@@ -732,11 +805,17 @@ __global__ __launch_bounds__(VOX_T) void k_vox_classify(VoxArgs A) {
     const bool xy_ok = x < A.g.nx && y < A.g.ny;
     unsigned long long cm0, cm1;
     column_masks(A, sp, R.count, x, y, xy_ok, cm0, cm1);
+    int pc[PSM_TZ];
+#pragma unroll
+    for (int lz = 0; lz < PSM_TZ; ++lz) pc[lz] = 0;
+    for_each_boundary_by_candidate(A, sp, R.tz, x, y, xy_ok, cm0, cm1,
+                                   [&](int lz, int, const VoxPart&, int, int, int) {
+#pragma unroll
+                                       for (int l = 0; l < PSM_TZ; ++l) pc[l] += l == lz ? 1 : 0;
+                                   });
     int mine = 0;
-    for_each_pair(A, sp, R.tz, x, y, xy_ok, cm0, cm1, [&](int, int, const VoxPart& P, int X, int Y, int Z) {
-        mine += classify(P, X, Y, Z) == 2;
-        return true;
-    });
+#pragma unroll
+    for (int lz = 0; lz < PSM_TZ; ++lz) mine += pc[lz];
     A.lane_items[t * VOX_T + tid] = (unsigned short)mine;
     int my_off, total;
     block_offsets(mine, tcnt, my_off, total);
@@ -749,14 +828,20 @@ __global__ __launch_bounds__(VOX_T) void k_vox_classify(VoxArgs A) {
     }
     __syncthreads();
     if (mine) {
-        long long j = (long long)tile_base + my_off;
-        for_each_pair(A, sp, R.tz, x, y, xy_ok, cm0, cm1, [&](int, int, const VoxPart& P, int X, int Y, int Z) {
-            if (classify(P, X, Y, Z) == 2) {
-                if (j < A.item_cap) A.items[j] = make_int4(X, Y, Z, P.pid);
-                ++j;
-            }
-            return j < A.item_cap;
-        });
+        // item index of (plane lz, candidate u): the lane's plane-major order,
+        // pid ascending within a plane
+        int j[PSM_TZ];
+        j[0] = tile_base + my_off;
+#pragma unroll
+        for (int lz = 1; lz < PSM_TZ; ++lz) j[lz] = j[lz - 1] + pc[lz - 1];
+        for_each_boundary_by_candidate(A, sp, R.tz, x, y, xy_ok, cm0, cm1,
+                                       [&](int lz, int, const VoxPart& P, int X, int Y, int Z) {
+                                           int g = 0;
+#pragma unroll
+                                           for (int l = 0; l < PSM_TZ; ++l)
+                                               if (l == lz) g = j[l]++;
+                                           if (g < A.item_cap) A.items[g] = make_int4(X, Y, Z, P.pid);
+                                       });
     }
 }
 
@@ -865,12 +950,16 @@ __global__ __launch_bounds__(VOX_T) void k_vox_sample(VoxArgs A) {
     }
 }
 
-// 3. per tile: select the kept solids with the sampled counts
+// 3. per tile: select the kept solids with the sampled counts (the tile's
+//    counts are staged in LDS first: one coalesced load instead of a dependent
+//    global load per boundary cell inside the selection loop)
+#define VOX_SEL_Q 1024
 template <typename C>
 __global__ __launch_bounds__(VOX_T) void k_vox_select(VoxArgs A) {
     __shared__ VoxPart sp[PSM_PMAX];
     __shared__ double off[32];
     __shared__ int tcnt[VOX_T / 64];
+    __shared__ int qc_s[VOX_SEL_Q];
     __shared__ unsigned long long cnt_e, cnt_d;
     const long long t = blockIdx.x;
     if (t >= A.g.ntiles) return;
@@ -890,9 +979,13 @@ __global__ __launch_bounds__(VOX_T) void k_vox_select(VoxArgs A) {
     int my_off, total;
     block_offsets(mine, tcnt, my_off, total);
     const long long tb = subdiv ? (long long)A.tile_items[t] : 0;
+    const int nq = total < VOX_SEL_Q ? total : VOX_SEL_Q;
+    for (int u = tid; u < nq; u += VOX_T) qc_s[u] = tb + u < A.item_cap ? A.item_cnt[tb + u] : 0;
+    __syncthreads();
     select_slots<C>(A, sp, t, R.tz, x, y, xy_ok, cm0, cm1, my_off,
                     [&](int j, const VoxPart& P, int X, int Y, int Z) {
                         const long long g = tb + j;
+                        if (j < nq && g < A.item_cap) return qc_s[j];
                         if (g < A.item_cap) return A.item_cnt[g];
                         int cnt = 0;
                         for (int m = 0; m < n3; ++m) cnt += sample_in(P, X, Y, Z, off, ns, m);
