@@ -678,9 +678,11 @@ __device__ inline void select_slots(const VoxArgs& A, const VoxPart* sp, long lo
             A.t.slot_lp[base + l] = lp;
             const double bq[PSM_SLOTS_MAX] = {T.n > 0 ? T.b0 : 0.0, T.n > 1 ? T.b1 : 0.0, T.n > 2 ? T.b2 : 0.0,
                                               T.n > 3 ? T.b3 : 0.0};
+            // only the kept slots are written: readers stop at the first
+            // empty index of slot_lp
 #pragma unroll
             for (int q = 0; q < PSM_SLOTS_MAX; ++q)
-                if (q < ms) {
+                if (q < ms && q < T.n) {
                     const double beta = bq[q];
                     const double B = beta * (A.tau - 0.5) / ((1.0 - beta) + (A.tau - 0.5));
                     Bout[q * plane + base + l] = (C)B;
