@@ -266,16 +266,18 @@ __device__ inline double ell_q(const VoxPart& P, double dx, double dy, double dz
 // Classification of lattice cell (X,Y,Z) against particle P for the subdivision
 // method: 0 every sample outside, 1 every sample inside, 2 samples needed.
 // The shortcuts are exact: they only fire with a margin far above the rounding
-// of any sample's test value.
-__device__ int classify(const VoxPart& P, int X, int Y, int Z) {
+// of any sample's test value.  Spheres are bounded over the box the samples
+// span, offsets slo..shi from the cell corner (the first and last sample
+// offset), not over the whole cell.
+__device__ int classify(const VoxPart& P, int X, int Y, int Z, double slo, double shi) {
     const int Xc[3] = {X, Y, Z};
     if (P.shape == 0) {
         const double R2 = P.ax[0] * P.ax[0];
         double maxr2 = 0.0, minr2 = 0.0;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            double dl = (double)Xc[a] - P.c[a];
-            double dh = ((double)Xc[a] + 1.0) - P.c[a];
+            double dl = ((double)Xc[a] + slo) - P.c[a];
+            double dh = ((double)Xc[a] + shi) - P.c[a];
             double l2 = dl * dl, h2 = dh * dh;
             maxr2 += l2 > h2 ? l2 : h2;
             minr2 += dl > 0.0 ? l2 : (dh < 0.0 ? h2 : 0.0);
@@ -314,7 +316,7 @@ struct SphCol {
     double maxr2, minr2, R2, m;
 };
 
-__device__ inline SphCol sphere_column(const VoxPart& P, int X, int Y) {
+__device__ inline SphCol sphere_column(const VoxPart& P, int X, int Y, double slo, double shi) {
     SphCol s;
     s.R2 = P.ax[0] * P.ax[0];
     s.maxr2 = 0.0;
@@ -322,8 +324,8 @@ __device__ inline SphCol sphere_column(const VoxPart& P, int X, int Y) {
     const int Xc[2] = {X, Y};
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-        const double dl = (double)Xc[a] - P.c[a];
-        const double dh = ((double)Xc[a] + 1.0) - P.c[a];
+        const double dl = ((double)Xc[a] + slo) - P.c[a];
+        const double dh = ((double)Xc[a] + shi) - P.c[a];
         const double l2 = dl * dl, h2 = dh * dh;
         s.maxr2 += l2 > h2 ? l2 : h2;
         s.minr2 += dl > 0.0 ? l2 : (dh < 0.0 ? h2 : 0.0);
@@ -332,9 +334,9 @@ __device__ inline SphCol sphere_column(const VoxPart& P, int X, int Y) {
     return s;
 }
 
-__device__ inline int sphere_class_z(const SphCol& s, double cz, int Z) {
-    const double dl = (double)Z - cz;
-    const double dh = ((double)Z + 1.0) - cz;
+__device__ inline int sphere_class_z(const SphCol& s, double cz, int Z, double slo, double shi) {
+    const double dl = ((double)Z + slo) - cz;
+    const double dh = ((double)Z + shi) - cz;
     const double l2 = dl * dl, h2 = dh * dh;
     const double maxr2 = s.maxr2 + (l2 > h2 ? l2 : h2);
     const double minr2 = s.minr2 + (dl > 0.0 ? l2 : (dh < 0.0 ? h2 : 0.0));
@@ -349,7 +351,7 @@ __device__ inline int sphere_class_z(const SphCol& s, double cz, int Z) {
 template <typename F>
 __device__ inline void for_each_boundary_by_candidate(const VoxArgs& A, const VoxPart* sp, int tz, int x, int y,
                                                       bool xy_ok, unsigned long long cm0, unsigned long long cm1,
-                                                      F f) {
+                                                      double slo, double shi, F f) {
     if (!xy_ok) return;
     for (int w = 0; w < 2; ++w)
         for (unsigned long long bits = w ? cm1 : cm0; bits; bits &= bits - 1) {
@@ -359,13 +361,13 @@ __device__ inline void for_each_boundary_by_candidate(const VoxArgs& A, const Vo
             in_box(P, x, A.g.nx, 0, A.g.periodic[0], &X);
             in_box(P, y, A.g.ny, 1, A.g.periodic[1], &Y);
             if (P.shape == 0) {
-                const SphCol s = sphere_column(P, X, Y);
+                const SphCol s = sphere_column(P, X, Y, slo, shi);
                 const double cz = P.c[2];
 #pragma unroll
                 for (int lz = 0; lz < PSM_TZ; ++lz) {
                     const int z = tz * PSM_TZ + lz;
                     int Z;
-                    if (z < A.g.nz && in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z) && sphere_class_z(s, cz, Z) == 2)
+                    if (z < A.g.nz && in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z) && sphere_class_z(s, cz, Z, slo, shi) == 2)
                         f(lz, u, P, X, Y, Z);
                 }
             } else {
@@ -373,7 +375,7 @@ __device__ inline void for_each_boundary_by_candidate(const VoxArgs& A, const Vo
                 for (int lz = 0; lz < PSM_TZ; ++lz) {
                     const int z = tz * PSM_TZ + lz;
                     int Z;
-                    if (z < A.g.nz && in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z) && classify(P, X, Y, Z) == 2)
+                    if (z < A.g.nz && in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z) && classify(P, X, Y, Z, slo, shi) == 2)
                         f(lz, u, P, X, Y, Z);
                 }
             }
@@ -626,8 +628,8 @@ __device__ inline int sample_count(const VoxPart& P, int X, int Y, int Z, const 
 // running from my_off in the order of for_each_pair.
 template <typename C, typename L>
 __device__ inline void select_slots(const VoxArgs& A, const VoxPart* sp, long long t, int tz, int x, int y, bool xy_ok,
-                                    unsigned long long cm0, unsigned long long cm1, int my_off, L lookup,
-                                    unsigned long long* cnt_e, unsigned long long* cnt_d) {
+                                    unsigned long long cm0, unsigned long long cm1, double slo, double shi,
+                                    int my_off, L lookup, unsigned long long* cnt_e, unsigned long long* cnt_d) {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int ms = A.ms, n3 = A.ns * A.ns * A.ns;
     const bool subdiv = A.sf_method == 0;
@@ -653,7 +655,7 @@ __device__ inline void select_slots(const VoxArgs& A, const VoxPart* sp, long lo
                     if (!subdiv) {
                         beta = beta_distance(P, X, Y, Z, A.Rc);
                     } else {
-                        const int cl = classify(P, X, Y, Z);
+                        const int cl = classify(P, X, Y, Z, slo, shi);
                         if (cl == 0) continue;
                         if (cl == 1) {
                             beta = 1.0;
@@ -736,6 +738,7 @@ __device__ void voxelize_tile(const VoxArgs& A, const long long t) {
     if (tid == 0) { cnt_e = 0; cnt_d = 0; }
     stage_particles(A, sp, off, R.s0, R.count);
     __syncthreads();
+    const double slo = off[0], shi = off[A.ns - 1];  // first and last sample offset
     const int x = R.tx * PSM_TX + lane, y = R.ty * PSM_TY + wid;
     const bool xy_ok = x < A.g.nx && y < A.g.ny;
     unsigned long long cm0, cm1;
@@ -743,7 +746,7 @@ __device__ void voxelize_tile(const VoxArgs& A, const long long t) {
     int mine = 0;
     if (subdiv)
         for_each_pair(A, sp, R.tz, x, y, xy_ok, cm0, cm1, [&](int, int, const VoxPart& P, int X, int Y, int Z) {
-            mine += classify(P, X, Y, Z) == 2;
+            mine += classify(P, X, Y, Z, slo, shi) == 2;
             return true;
         });
     int my_off, total;
@@ -751,7 +754,7 @@ __device__ void voxelize_tile(const VoxArgs& A, const long long t) {
     if (mine) {
         int j = my_off;
         for_each_pair(A, sp, R.tz, x, y, xy_ok, cm0, cm1, [&](int lz, int u, const VoxPart& P, int X, int Y, int Z) {
-            if (classify(P, X, Y, Z) == 2) {
+            if (classify(P, X, Y, Z, slo, shi) == 2) {
                 const unsigned l = lane + PSM_TX * (wid + PSM_TY * lz);
                 qitem[j++] = (l << 8) | (unsigned)u;
             }
@@ -775,7 +778,7 @@ __device__ void voxelize_tile(const VoxArgs& A, const long long t) {
         if (lane == 0) qcnt[it] = cnt;
     }
     __syncthreads();
-    select_slots<C>(A, sp, t, R.tz, x, y, xy_ok, cm0, cm1, my_off,
+    select_slots<C>(A, sp, t, R.tz, x, y, xy_ok, cm0, cm1, slo, shi, my_off,
                     [&](int j, const VoxPart& P, int X, int Y, int Z) {
                         if (j < VOX_QCAP) return qcnt[j];
                         int cnt = 0;
@@ -803,6 +806,7 @@ __global__ __launch_bounds__(VOX_T) void k_vox_classify(VoxArgs A) {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     stage_particles(A, sp, off, R.s0, R.count);
     __syncthreads();
+    const double slo = off[0], shi = off[A.ns - 1];  // first and last sample offset
     const int x = R.tx * PSM_TX + lane, y = R.ty * PSM_TY + wid;
     const bool xy_ok = x < A.g.nx && y < A.g.ny;
     unsigned long long cm0, cm1;
@@ -810,7 +814,7 @@ __global__ __launch_bounds__(VOX_T) void k_vox_classify(VoxArgs A) {
     int pc[PSM_TZ];
 #pragma unroll
     for (int lz = 0; lz < PSM_TZ; ++lz) pc[lz] = 0;
-    for_each_boundary_by_candidate(A, sp, R.tz, x, y, xy_ok, cm0, cm1,
+    for_each_boundary_by_candidate(A, sp, R.tz, x, y, xy_ok, cm0, cm1, slo, shi,
                                    [&](int lz, int, const VoxPart&, int, int, int) {
 #pragma unroll
                                        for (int l = 0; l < PSM_TZ; ++l) pc[l] += l == lz ? 1 : 0;
@@ -836,7 +840,7 @@ __global__ __launch_bounds__(VOX_T) void k_vox_classify(VoxArgs A) {
         j[0] = tile_base + my_off;
 #pragma unroll
         for (int lz = 1; lz < PSM_TZ; ++lz) j[lz] = j[lz - 1] + pc[lz - 1];
-        for_each_boundary_by_candidate(A, sp, R.tz, x, y, xy_ok, cm0, cm1,
+        for_each_boundary_by_candidate(A, sp, R.tz, x, y, xy_ok, cm0, cm1, slo, shi,
                                        [&](int lz, int, const VoxPart& P, int X, int Y, int Z) {
                                            int g = 0;
 #pragma unroll
@@ -973,6 +977,7 @@ __global__ __launch_bounds__(VOX_T) void k_vox_select(VoxArgs A) {
     if (tid == 0) { cnt_e = 0; cnt_d = 0; }
     stage_particles(A, sp, off, R.s0, R.count);
     __syncthreads();
+    const double slo = off[0], shi = off[A.ns - 1];  // first and last sample offset
     const int x = R.tx * PSM_TX + lane, y = R.ty * PSM_TY + wid;
     const bool xy_ok = x < A.g.nx && y < A.g.ny;
     unsigned long long cm0, cm1;
@@ -984,7 +989,7 @@ __global__ __launch_bounds__(VOX_T) void k_vox_select(VoxArgs A) {
     const int nq = total < VOX_SEL_Q ? total : VOX_SEL_Q;
     for (int u = tid; u < nq; u += VOX_T) qc_s[u] = tb + u < A.item_cap ? A.item_cnt[tb + u] : 0;
     __syncthreads();
-    select_slots<C>(A, sp, t, R.tz, x, y, xy_ok, cm0, cm1, my_off,
+    select_slots<C>(A, sp, t, R.tz, x, y, xy_ok, cm0, cm1, slo, shi, my_off,
                     [&](int j, const VoxPart& P, int X, int Y, int Z) {
                         const long long g = tb + j;
                         if (j < nq && g < A.item_cap) return qc_s[j];
