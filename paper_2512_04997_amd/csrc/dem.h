@@ -33,6 +33,8 @@ struct DemArgs {
     int ellipsoids;        // any particle is an ellipsoid (else the sphere-only kernels run)
     int* fused_age;        // [1] substeps the pair list has been kept (pc holds the cells it was built
                            // from, the wall candidates in pc's last word); -1: rebuild
+    unsigned char* fz;     // [dem_fused_save_bytes()] the fused kernel's skip state of its kept list,
+                           // saved at the end of a launch for the next one (null: not kept)
     int* list_flag;        // [2] multi-launch path: the list changed in this substep (by substep parity)
     const int* list_run;   // multi-launch path: list_flag of this substep, or null (always build)
     DevCounters* ctr;
@@ -68,5 +70,7 @@ hipError_t dem_zero(double* p, long long n, hipStream_t s);
 // nsub substeps in one workgroup starting from buffer `cur` (the first substep
 // writes buffer cur ^ 1); with stop_before_correct the last substep ends after
 // the DEM sums (the corrector then runs after the fluid coupling)
+// bytes of DemArgs::fz; its first int is -1 while it holds no state
+size_t dem_fused_save_bytes();
 hipError_t dem_fused(const DemArgs& A, const PairSet& P, int cur, int nsub, double dt, int stop_before_correct,
                      hipStream_t s);

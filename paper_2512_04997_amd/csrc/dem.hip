@@ -1198,6 +1198,14 @@ __global__ void k_zero_d(double* p, long long n) { GRID_LOOP(i, n) p[i] = 0.0; }
 #define FUSED_PREV_LDS 3072   // previous pair keys staged in LDS for the history search
 #define FUSED_CELLS 8192      // DEM grids up to this many cells keep their cell list in LDS
 #define FUSED_COLS 8192       // pair lists up to this length keep their column lists in LDS
+// the saved skip state (bytes): a header (pairs, list age), the column ends,
+// separations, movement bounds, column lists and quiet counters
+#define FZ_CNT 16
+#define FZ_GAP (FZ_CNT + 4 * (DEM_FUSED_MAX + 2))
+#define FZ_DACC (FZ_GAP + 8 * FUSED_PREV_LDS)
+#define FZ_COL (FZ_DACC + 8 * DEM_FUSED_MAX)
+#define FZ_QUIET (FZ_COL + 2 * FUSED_COLS)
+#define FZ_BYTES (FZ_QUIET + FUSED_PREV_LDS)
 #define FUSED_SKIP_EPS 1e-9   // separation margin above the rounding of positions and distances
 
 __device__ inline unsigned pack_axis(const AxCells& r, int a) {
@@ -1297,7 +1305,10 @@ __device__ int merged_row(const DemArgs& A, int i, const unsigned* cells_s, cons
 // kept when the launch ended (pc holds the cells, with the wall candidates in
 // its last word); the next launch keeps it when nothing changed and rebuilds
 // only its LDS state (column lists, staged keys, separations).  Every other
-// writer of the lists or particles resets A.fused_age to -1.
+// writer of the lists or particles resets A.fused_age to -1.  For sphere
+// lists the launch also saves that LDS state (A.fz, with the list's length and
+// age) and the next launch restores it when its list is that one: its first
+// substeps then skip quiet pairs and keep the column lists like any later one.
 template <bool ELL>
 __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, const PairSet& P, int cur, const int nsub, const double dt,
                                const int stop_before_correct) {
@@ -1324,6 +1335,32 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
     const int age0 = *A.fused_age;  // the last launch's list age, -1: none
     int age = 0;                     // substeps since the list was last rebuilt
     bool keys_lds = false;           // the kept list's keys are staged in prev_s
+    // the last launch's skip state, when it belongs to the list of buffer cur
+    bool restored = false;
+    if (!ELL && A.fz && age0 >= 0) {
+        const int* hdr = reinterpret_cast<const int*>(A.fz);
+        long long nk = (cur ? P.prow[1] : P.prow[0])[np];
+        nk = nk < A.pair_cap ? nk : A.pair_cap;
+        restored = hdr[0] >= 0 && hdr[0] == nk && hdr[1] == age0 && nk <= FUSED_PREV_LDS && nk <= FUSED_COLS;
+        if (restored) {
+            const unsigned long long* keys = cur ? P.pairs[1] : P.pairs[0];
+            const int* zc = reinterpret_cast<const int*>(A.fz + FZ_CNT);
+            const double* zg = reinterpret_cast<const double*>(A.fz + FZ_GAP);
+            const double* zd = reinterpret_cast<const double*>(A.fz + FZ_DACC);
+            const unsigned short* zl = reinterpret_cast<const unsigned short*>(A.fz + FZ_COL);
+            const unsigned char* zq = A.fz + FZ_QUIET;
+            for (int k = tid; k <= np; k += FUSED_T) cnt_s[k] = zc[k];
+            for (int k = tid; k < np; k += FUSED_T) dacc_s[k] = zd[k];
+            for (int s = tid; s < (int)nk; s += FUSED_T) {
+                prev_s[s] = keys[s];
+                gapb_s[s] = zg[s];
+                quiet_s[s] = zq[s];
+                col_s[s] = zl[s];
+            }
+            keys_lds = true;
+        }
+    }
+    long long save_n = -1;  // the last substep's list length when its skip state is complete
     // With at most one particle per thread (and LDS column lists) each thread
     // runs its particle's sums, corrector and next predictor back to back,
     // every state load issued before the sums' own loads: no barrier and no
@@ -1397,8 +1434,8 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
         const bool rebuild = __syncthreads_or(changed) != 0;
         age = rebuild ? 0 : (sub == 0 ? age0 + 1 : age + 1);
         // LDS state (column lists, staged keys, separations) is built afresh
-        // with a new list and at the start of a launch
-        const bool fresh = rebuild || sub == 0;
+        // with a new list and at the start of a launch that restored none
+        const bool fresh = rebuild || (sub == 0 && !restored);
         if (fresh) keys_lds = false;
         if (!rebuild) {
             // the previous list is this list: one substep after the rebuild it
@@ -1580,6 +1617,7 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
                     }
             }
         }
+        save_n = (!ELL && lds_cols && keys_lds && npairs <= FUSED_PREV_LDS) ? npairs : -1;
         __syncthreads();
         // DEM sums: pairs (k, i) for ascending k, then the own row
         const bool tail = !ELL && np <= FUSED_T && lds_cols;  // ellipsoids: registers go to the contacts
@@ -1659,6 +1697,29 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
         cur = c;
     }
     if (tid == 0 && nsub > 0) *A.fused_age = age;
+    if (!ELL && A.fz && nsub > 0) {
+        // the kept list's skip state for the next launch
+        __syncthreads();
+        if (save_n >= 0) {
+            int* zc = reinterpret_cast<int*>(A.fz + FZ_CNT);
+            double* zg = reinterpret_cast<double*>(A.fz + FZ_GAP);
+            double* zd = reinterpret_cast<double*>(A.fz + FZ_DACC);
+            unsigned short* zl = reinterpret_cast<unsigned short*>(A.fz + FZ_COL);
+            unsigned char* zq = A.fz + FZ_QUIET;
+            for (int k = tid; k <= np; k += FUSED_T) zc[k] = cnt_s[k];
+            for (int k = tid; k < np; k += FUSED_T) zd[k] = dacc_s[k];
+            for (int s = tid; s < (int)save_n; s += FUSED_T) {
+                zg[s] = gapb_s[s];
+                zq[s] = quiet_s[s];
+                zl[s] = col_s[s];
+            }
+        }
+        if (tid == 0) {
+            int* hdr = reinterpret_cast<int*>(A.fz);
+            hdr[0] = (int)save_n;
+            hdr[1] = age;
+        }
+    }
 }
 
 template <bool ELL>
@@ -1797,6 +1858,8 @@ hipError_t dem_finish_batch(const DemJob* jobs, int njobs, hipStream_t s) {
     k_dem_finish_batch<<<(unsigned)njobs, 256, 0, s>>>(jobs);
     return hipGetLastError();
 }
+
+size_t dem_fused_save_bytes() { return FZ_BYTES; }
 
 hipError_t dem_fused(const DemArgs& A, const PairSet& P, int cur, int nsub, double dt, int stop_before_correct,
                      hipStream_t s) {

@@ -42,6 +42,7 @@ struct psmdem_domain {
     int *cell_count = nullptr, *cell_start = nullptr, *cell_fill = nullptr, *cell_pid = nullptr;
     int* pc = nullptr;
     int* fused_age = nullptr;
+    unsigned char* fz = nullptr;
     int* list_flag = nullptr;
     long long dem_sub = 0;  // multi-launch substeps run (their parity indexes list_flag)
     int *col_count = nullptr, *col_fill = nullptr, *col_start = nullptr, *col_list = nullptr;
@@ -120,6 +121,7 @@ struct psmdem_domain {
         A.ncell = ncell;
         A.pc = pc;
         A.fused_age = fused_age;
+        A.fz = fz;
         A.list_flag = list_flag;
         A.list_run = nullptr;
         A.cell_count = cell_count;

@@ -128,6 +128,7 @@ static int run_lbm(psmdem_domain* D) {
 // writer of the lists, cells or particle state makes its next launch rebuild
 static int forget_fused_list(psmdem_domain* D) {
     if (D->np > 0) PSM_CHECK(hipMemsetAsync(D->fused_age, 0xff, sizeof(int), D->s));
+    if (D->fz) PSM_CHECK(hipMemsetAsync(D->fz, 0xff, sizeof(int), D->s));
     return 0;
 }
 
@@ -402,6 +403,8 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
     D->reg_cap = 8LL * std::max(np, 1);
     D->pc = (int*)A(sizeof(int) * 8 * std::max(np, 1));
     D->fused_age = (int*)A(sizeof(int));
+    // the fused DEM kernel's saved skip state (domains it runs)
+    D->fz = np > 0 && np <= DEM_FUSED_MAX ? (unsigned char*)A(dem_fused_save_bytes()) : nullptr;
     D->list_flag = (int*)A(2 * sizeof(int));
     D->cell_count = (int*)A(sizeof(int) * D->ncell);
     D->cell_fill = (int*)A(sizeof(int) * D->ncell);
@@ -521,6 +524,7 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
             hipMemsetAsync(D->t.slot_lp, 0xff, sizeof(unsigned) * g.ntiles * (size_t)PSM_TILE, D->s) != hipSuccess ||
             hipMemsetAsync(D->cell_pid, 0, sizeof(int) * D->reg_cap, D->s) != hipSuccess ||
             hipMemsetAsync(D->fused_age, 0xff, sizeof(int), D->s) != hipSuccess ||
+            (D->fz && hipMemsetAsync(D->fz, 0xff, sizeof(int), D->s) != hipSuccess) ||
             hipMemsetAsync(D->list_flag, 0, 2 * sizeof(int), D->s) != hipSuccess ||
             hipStreamSynchronize(D->s) != hipSuccess)
             rc = PSMDEM_E_HIP;

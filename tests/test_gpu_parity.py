@@ -315,6 +315,38 @@ def test_fused_dem_list_reuse(ps, oracle_mod, kind):
         assert O.counters()["contacts"] > 20
 
 
+def test_fused_dem_skip_state_across_launches(ps, oracle_mod):
+    """Two substeps per launch: a kept list's quiet pairs are skipped from the
+    first substep of a launch only through the state the previous launch
+    saved.  Slow, nearly touching spheres keep their lists while contacts
+    form and break, so a wrongly skipped pair would show in the forces (a soft
+    spring, k_n = 10, keeps the contact resolved at dt = 1/2)."""
+    box = (48, 40, 36)
+    rng = W.SplitMix64(4646)
+    n = 350
+    radii = 1.4 + 0.6 * rng.uniform(n)
+    pos = W.rsa_spheres(rng, n, radii, box, [True, True, False], gap=0.03)
+    m = len(pos)
+    vel = 0.01 * (rng.uniform(3 * m).reshape(m, 3) - 0.5)
+    parts = W.spheres(pos, radii[:m], 1.6, vel=vel)
+    cfg = _walled(box, 0.7, "fp64", fluid_on=False, mu=0.3, restitution=0.7, n_sub=2,
+                  gravity=[0.0, 0.0, -2e-4], kn=10.0)
+    G, O = _pair(ps, oracle_mod, cfg, parts)
+    contacts, lengths = 0, set()
+    for _ in range(12):
+        G.step(1)
+        O.step(1)
+        pg = G.pairs()[0]
+        assert np.array_equal(pg, O.pairs()[0])
+        Pg, Po = G.particles(), O.particles()
+        assert vec_err(Pg["pos"], Po["pos"]) < 1e-12
+        assert vec_err(Pg["vel"], Po["vel"]) < 1e-12
+        assert force_err(Pg["f_dem"], Po["f_dem"], O.scales()["f_dem"], force_floor(O)) < 1e-12
+        contacts += O.counters()["contacts"]
+        lengths.add(len(pg))
+    assert contacts > 60 and len(lengths) > 3
+
+
 def test_fused_dem_state_written_between_steps(ps, oracle_mod):
     """A list kept across launches is dropped when the host writes particles
     or pairs: both sides take the same moved positions and scaled history
