@@ -173,4 +173,7 @@ void psm_set_error(const char* fmt, ...);
 size_t psm_scan_tmp_ints(long long n);
 // exclusive scan of in[0..n) into out[0..n], out[n] = total; with run, only if *run != 0
 hipError_t psm_scan(const int* in, int* out, long long n, int* tmp, hipStream_t s, const int* run = nullptr);
+// two independent scans; one launch when both are short
+hipError_t psm_scan2(const int* in0, int* out0, long long n0, const int* in1, int* out1, long long n1, int* tmp,
+                     hipStream_t s);
 hipError_t psm_fill_int(int* p, int v, long long n, hipStream_t s);

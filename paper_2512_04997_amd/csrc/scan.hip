@@ -92,8 +92,7 @@ constexpr long long SCAN_SMALL = 32768;
 // One workgroup of 1024 lanes walks the input in chunks of 4096 entries, four
 // consecutive entries per lane (coalesced), with a running carry (in place
 // allowed: a lane reads its entries before it writes them).
-__global__ __launch_bounds__(1024) void k_scan_small(const int* in, int* out, long long n, const int* run) {
-    if (run && !*run) return;
+__device__ inline void scan_small_body(const int* in, int* out, long long n) {
     __shared__ int wsum[16];
     __shared__ int carry_s;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -134,6 +133,18 @@ __global__ __launch_bounds__(1024) void k_scan_small(const int* in, int* out, lo
     if (tid == 0) out[n] = carry_s;
 }
 
+__global__ __launch_bounds__(1024) void k_scan_small(const int* in, int* out, long long n, const int* run) {
+    if (run && !*run) return;
+    scan_small_body(in, out, n);
+}
+
+// two short scans, one per workgroup
+__global__ __launch_bounds__(1024) void k_scan_small2(const int* in0, int* out0, long long n0, const int* in1,
+                                                      int* out1, long long n1) {
+    if (blockIdx.x == 0) scan_small_body(in0, out0, n0);
+    else scan_small_body(in1, out1, n1);
+}
+
 __global__ void k_fill_int(int* __restrict__ p, int v, long long n) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -154,6 +165,16 @@ hipError_t psm_scan(const int* in, int* out, long long n, int* tmp, hipStream_t 
     k_scan_bsum<<<1, SCAN_T, 0, s>>>(tmp, nb, out, n, run);
     k_scan_add<<<nb, SCAN_T, 0, s>>>(out, n, tmp, run);
     return hipGetLastError();
+}
+
+hipError_t psm_scan2(const int* in0, int* out0, long long n0, const int* in1, int* out1, long long n1, int* tmp,
+                     hipStream_t s) {
+    if (n0 <= SCAN_SMALL && n1 <= SCAN_SMALL) {
+        k_scan_small2<<<2, 1024, 0, s>>>(in0, out0, n0 < 0 ? 0 : n0, in1, out1, n1 < 0 ? 0 : n1);
+        return hipGetLastError();
+    }
+    hipError_t e = psm_scan(in0, out0, n0, tmp, s);
+    return e != hipSuccess ? e : psm_scan(in1, out1, n1, tmp, s);
 }
 
 hipError_t psm_fill_int(int* p, int v, long long n, hipStream_t s) {

@@ -24,6 +24,10 @@ struct VoxArgs {
     DevCounters* ctr;
 };
 
+// registration: the tile lists (on lattices of up to 8192 tiles left in
+// arbitrary order within a tile, which vox_voxelize's first per-tile kernel
+// then sets, clearing the registration counters: it follows every vox_register)
 hipError_t vox_register(const VoxArgs& A, int* scan_tmp, hipStream_t s);
+// voxelisation of registered tiles
 hipError_t vox_voxelize(const VoxArgs& A, int ctype_double, hipStream_t s);
 hipError_t vox_reduce_hydro(const VoxArgs& A, hipStream_t s);

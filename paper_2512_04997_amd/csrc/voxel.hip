@@ -8,7 +8,9 @@
 //   k_vox_count    tiles touched by each particle's lattice box (count + tile histogram)
 //   (scans)        emission offsets per particle, list offsets per tile
 //   k_vox_scatter  counting-sort scatter of (pid, emission index) into tiles
-//   k_tile_sort    order each tile's list by pid; inverse map emission -> position
+//   (k_tile_sort)  order each tile's list by pid; inverse map emission -> position
+//                  (lattices of up to VOX_SORT_IN_TILE_MAX tiles do this in the
+//                  first per-tile kernel below instead)
 //   k_vox_classify per tile: cells whose samples straddle a surface, queued as
 //                  items of the step (exact inside / outside shortcuts elsewhere)
 //   k_vox_sample   a lane per queued sphere cell (a wave per other cell): its count of inside samples
@@ -185,13 +187,59 @@ __global__ void k_vox_scatter(VoxArgs A) {
     reg_scatter_wave(A, k, threadIdx.x & 63, A.tile_fill);
 }
 
-// sorts each tile's list, then clears the tile's counters for the next step
+#define VOX_T 256  // lanes of the per-tile voxelisation workgroups
+// Up to this many tiles the lists are ordered inside the first per-tile
+// voxelisation kernel (saving a launch); larger lattices order them in a
+// kernel of their own, one thread per tile, which costs less than the added
+// latency in every tile workgroup.
+#define VOX_SORT_IN_TILE_MAX 8192
+
+// orders each tile's list, then clears the tile's counters for the next step
 __global__ void k_tile_sort(VoxArgs A) {
     long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= A.g.ntiles) return;
     reg_sort(A, t);
     A.tile_count[t] = 0;
     A.tile_fill[t] = 0;
+}
+
+// Tile t's list ordered by (pid, emission) by the tile's workgroup, the
+// emission -> position map, and the tile's counters cleared for the next step.
+// Up to VOX_T entries rank-sort through LDS (keys are unique); longer lists
+// (beyond the tile capacity, flagged) take the serial sort.  Every thread of
+// the workgroup calls it; the list is ordered when it returns.  Returns ks,
+// which then holds the ordered list, or null (the list is in global memory only).
+__device__ inline const unsigned long long* sort_tile_list(const VoxArgs& A, long long t, unsigned long long* ks) {
+    const int tid = threadIdx.x;
+    long long s0 = A.t.tile_start[t], s1 = A.t.tile_start[t + 1];
+    if (s1 > A.t.cap) s1 = A.t.cap;
+    if (tid == 0) {
+        A.tile_count[t] = 0;
+        A.tile_fill[t] = 0;
+    }
+    const long long n = s1 - s0;
+    if (n <= 0) return nullptr;
+    unsigned long long* L = A.t.tile_list + s0;
+    if (n <= VOX_T) {
+        if (n > PSM_PMAX && tid == 0) atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_TILE);
+        const unsigned long long key = tid < n ? L[tid] : 0ull;
+        if (tid < n) ks[tid] = key;
+        __syncthreads();
+        int r = 0;
+        if (tid < n)
+            for (int v = 0; v < (int)n; ++v) r += ks[v] < key ? 1 : 0;
+        __syncthreads();
+        if (tid < n) {
+            ks[r] = key;
+            L[r] = key;
+            const unsigned e = (unsigned)(key & 0xffffffffu);
+            if (e < A.t.cap) A.t.vinv[e] = (int)(s0 + r);
+        }
+    } else if (tid == 0) {
+        reg_sort(A, t);
+    }
+    __syncthreads();
+    return n <= VOX_T ? ks : nullptr;
 }
 
 // Registration of one domain by one workgroup (serving batches): the tile
@@ -407,7 +455,6 @@ __device__ inline double beta_distance(const VoxPart& P, int X, int Y, int Z, do
 
 #define VOX_QCAP 2048
 #define VOX_NS_REG 12   // spheres with at most this many samples per direction keep the x terms in registers
-#define VOX_T 256
 
 // the ms largest beta of a cell (ties: the earlier, smaller pid wins), kept in
 // four named registers in descending order
@@ -458,12 +505,14 @@ __device__ inline void top_by_pid(Top4& T) {
 // pieces of the per-tile voxelisation, shared by the one-kernel form (serving
 // batches) and the three-kernel form (classify / sample / select)
 // ---------------------------------------------------------------------------
-// the tile's registered particles staged in LDS, and the sample offsets
-__device__ inline void stage_particles(const VoxArgs& A, VoxPart* sp, double* off, long long s0, int count) {
+// the tile's registered particles staged in LDS, and the sample offsets (the
+// list from keys when given, else from global memory)
+__device__ inline void stage_particles(const VoxArgs& A, VoxPart* sp, double* off, long long s0, int count,
+                                       const unsigned long long* keys = nullptr) {
     const int tid = threadIdx.x;
     if (tid < A.ns) off[tid] = (double)(2 * tid + 1) / (double)(2 * A.ns);
     for (int u = tid; u < count; u += VOX_T) {
-        int k = (int)(A.t.tile_list[s0 + u] >> 32);
+        int k = (int)((keys ? keys[u] : A.t.tile_list[s0 + u]) >> 32);
         if (k >= A.p.np) k = 0;
         VoxPart& P = sp[u];
         P.pid = k;
@@ -794,17 +843,20 @@ __device__ void voxelize_tile(const VoxArgs& A, const long long t) {
 // ---------------------------------------------------------------------------
 // 1. per tile: count the boundary cells per lane, reserve the tile's range of
 //    the step's item list, queue (X, Y, Z, pid) of each boundary cell
+template <bool SORT>
 __global__ __launch_bounds__(VOX_T) void k_vox_classify(VoxArgs A) {
     __shared__ VoxPart sp[PSM_PMAX];
     __shared__ double off[32];
     __shared__ int tcnt[VOX_T / 64];
     __shared__ int tile_base;
+    __shared__ unsigned long long ks[SORT ? VOX_T : 1];
     const long long t = blockIdx.x;
     if (t >= A.g.ntiles) return;
+    const unsigned long long* keys = SORT ? sort_tile_list(A, t, ks) : nullptr;
     const TileRange R = tile_range(A, t);
     if (R.count <= 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    stage_particles(A, sp, off, R.s0, R.count);
+    stage_particles(A, sp, off, R.s0, R.count, keys);
     __syncthreads();
     const double slo = off[0], shi = off[A.ns - 1];  // first and last sample offset
     const int x = R.tx * PSM_TX + lane, y = R.ty * PSM_TY + wid;
@@ -960,22 +1012,24 @@ __global__ __launch_bounds__(VOX_T) void k_vox_sample(VoxArgs A) {
 //    counts are staged in LDS first: one coalesced load instead of a dependent
 //    global load per boundary cell inside the selection loop)
 #define VOX_SEL_Q 1024
-template <typename C>
+template <typename C, bool SORT>
 __global__ __launch_bounds__(VOX_T) void k_vox_select(VoxArgs A) {
     __shared__ VoxPart sp[PSM_PMAX];
     __shared__ double off[32];
     __shared__ int tcnt[VOX_T / 64];
     __shared__ int qc_s[VOX_SEL_Q];
+    __shared__ unsigned long long ks[SORT ? VOX_T : 1];
     __shared__ unsigned long long cnt_e, cnt_d;
     const long long t = blockIdx.x;
     if (t >= A.g.ntiles) return;
+    const bool subdiv = A.sf_method == 0;
+    const unsigned long long* keys = SORT ? sort_tile_list(A, t, ks) : nullptr;
     const TileRange R = tile_range(A, t);
     if (R.count <= 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int ns = A.ns, n3 = ns * ns * ns;
-    const bool subdiv = A.sf_method == 0;
     if (tid == 0) { cnt_e = 0; cnt_d = 0; }
-    stage_particles(A, sp, off, R.s0, R.count);
+    stage_particles(A, sp, off, R.s0, R.count, keys);
     __syncthreads();
     const double slo = off[0], shi = off[A.ns - 1];  // first and last sample offset
     const int x = R.tx * PSM_TX + lane, y = R.ty * PSM_TY + wid;
@@ -1061,29 +1115,41 @@ inline unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) /
 
 }  // namespace
 
-// the tile counters start at zero (creation) and are cleared again by k_tile_sort
+// the tile counters start at zero (creation) and are cleared again where the lists are ordered
 hipError_t vox_register(const VoxArgs& A, int* scan_tmp, hipStream_t s) {
     hipError_t e;
     const unsigned nbw = nblk(64LL * (A.p.np > 0 ? A.p.np : 1));
     k_vox_count<<<nbw, 256, 0, s>>>(A);
-    if ((e = psm_scan(A.t.vcount, A.t.voff, A.p.np, scan_tmp, s)) != hipSuccess) return e;
-    if ((e = psm_scan(A.tile_count, A.t.tile_start, A.g.ntiles, scan_tmp, s)) != hipSuccess) return e;
+    if ((e = psm_scan2(A.t.vcount, A.t.voff, A.p.np, A.tile_count, A.t.tile_start, A.g.ntiles, scan_tmp, s)) !=
+        hipSuccess)
+        return e;
     if (A.p.np > 0) k_vox_scatter<<<nbw, 256, 0, s>>>(A);
-    k_tile_sort<<<nblk(A.g.ntiles), 256, 0, s>>>(A);
+    // small lattices: each tile's list is ordered by the first per-tile kernel
+    // of vox_voxelize
+    if (A.g.ntiles > VOX_SORT_IN_TILE_MAX) k_tile_sort<<<nblk(A.g.ntiles), 256, 0, s>>>(A);
     return hipGetLastError();
 }
 
 hipError_t vox_voxelize(const VoxArgs& A, int ctype_double, hipStream_t s) {
     const unsigned nt = (unsigned)A.g.ntiles;
+    const bool sort = A.g.ntiles <= VOX_SORT_IN_TILE_MAX;
     if (A.sf_method == 0) {
-        k_vox_classify<<<nt, VOX_T, 0, s>>>(A);
+        if (sort) k_vox_classify<true><<<nt, VOX_T, 0, s>>>(A);
+        else k_vox_classify<false><<<nt, VOX_T, 0, s>>>(A);
         // one wave per 64 items, up to 4096 workgroups; the waves stride over the rest
         long long nb = (A.item_cap + VOX_T - 1) / VOX_T;
         nb = nb < 4096 ? nb : 4096;
         k_vox_sample<<<(unsigned)(nb > 0 ? nb : 1), VOX_T, 0, s>>>(A);
     }
-    if (ctype_double) k_vox_select<double><<<nt, VOX_T, 0, s>>>(A);
-    else k_vox_select<float><<<nt, VOX_T, 0, s>>>(A);
+    // (the subdivision method's lists were ordered by the classify kernel)
+    const bool sort_sel = A.sf_method != 0 && sort;
+    if (ctype_double) {
+        if (sort_sel) k_vox_select<double, true><<<nt, VOX_T, 0, s>>>(A);
+        else k_vox_select<double, false><<<nt, VOX_T, 0, s>>>(A);
+    } else {
+        if (sort_sel) k_vox_select<float, true><<<nt, VOX_T, 0, s>>>(A);
+        else k_vox_select<float, false><<<nt, VOX_T, 0, s>>>(A);
+    }
     return hipGetLastError();
 }
 
