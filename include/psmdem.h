@@ -228,7 +228,10 @@ psmdem_status psmdem_counters(psmdem_domain* d, psmdem_counters_t* out);
 psmdem_status psmdem_info(psmdem_domain* d, psmdem_info_t* out);
 
 /* Average device time per launch of each kernel family over the last
- * psmdem_step call when timing is on (HIP events on the domain stream). */
+ * psmdem_step call when timing is on (HIP events on the domain stream).
+ * PSMDEM_T_HYDRO covers the per-particle hydrodynamic sums after the LBM-PSM
+ * pass, which with the DEM on run in one launch with the step's final
+ * corrector; PSMDEM_T_DEM covers the substeps before it. */
 psmdem_status psmdem_set_timing(psmdem_domain* d, int32_t on);
 psmdem_status psmdem_timing(psmdem_domain* d, int32_t which, double* avg_ms, int64_t* launches);
 typedef enum { PSMDEM_T_LBM = 0, PSMDEM_T_VOXEL = 1, PSMDEM_T_DEM = 2, PSMDEM_T_HYDRO = 3 } psmdem_timer;

@@ -65,6 +65,8 @@ hipError_t dem_lists_kept(const DemArgs& A, const PairBufs& B, int par, int* sca
 hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, const double* ww, double dth,
                         int* scan_tmp, hipStream_t s);
 hipError_t dem_correct(const DemArgs& A, double dt, hipStream_t s);
+// hydrodynamic sums of the tile partials (T) and the corrector, one launch
+hipError_t dem_hydro_correct(const DemArgs& A, const TileArgs& T, double dt, hipStream_t s);
 hipError_t dem_initial_accel(const DemArgs& A, hipStream_t s);
 hipError_t dem_zero(double* p, long long n, hipStream_t s);
 // nsub substeps in one workgroup starting from buffer `cur` (the first substep

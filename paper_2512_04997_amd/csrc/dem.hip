@@ -1186,6 +1186,16 @@ __global__ __launch_bounds__(256) void k_colsort(DemArgs A) {
 }
 __global__ void k_sum(DemArgs A, PairBufs B) { GRID_LOOP(i, A.p.np) ph_sum<false>(A, B, (int)i); }
 __global__ void k_correct(DemArgs A, double dt) { GRID_LOOP(k, A.p.np) ph_correct(A, (int)k, dt); }
+
+// after the LBM-PSM pass: each particle's hydrodynamic sums (one wave), then
+// its corrector (lane 0, which stored the sums)
+__global__ void k_hydro_correct(DemArgs A, TileArgs T, double dt) {
+    const int k = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (k >= A.p.np) return;
+    psm_reduce_hydro_wave(T, A.p, k, lane);
+    if (lane == 0) ph_correct(A, k, dt);
+}
 __global__ void k_initial_accel(DemArgs A) { GRID_LOOP(k, A.p.np) ph_initial_accel(A, (int)k); }
 
 __global__ void k_zero_d(double* p, long long n) { GRID_LOOP(i, n) p[i] = 0.0; }
@@ -1825,6 +1835,12 @@ hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, c
     k_colscatter<<<nblk(A.pair_cap), 256, 0, s>>>(A, B);
     k_colsort<<<nblk(64LL * A.p.np), 256, 0, s>>>(A);
     k_sum<<<nblk(A.p.np, 128), 128, 0, s>>>(A, B);
+    return hipGetLastError();
+}
+
+hipError_t dem_hydro_correct(const DemArgs& A, const TileArgs& T, double dt, hipStream_t s) {
+    if (A.p.np == 0) return hipSuccess;
+    k_hydro_correct<<<(unsigned)((64LL * A.p.np + 255) / 256), 256, 0, s>>>(A, T, dt);
     return hipGetLastError();
 }
 

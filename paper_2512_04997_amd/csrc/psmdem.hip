@@ -112,11 +112,14 @@ static int run_voxelize(psmdem_domain* D) {
     return 0;
 }
 
-static int run_lbm(psmdem_domain* D) {
+// the LBM-PSM pass, then the hydrodynamic sums unless the caller runs them
+// with the DEM corrector (dem_hydro_correct)
+static int run_lbm(psmdem_domain* D, bool hydro = true) {
     LbmArgs A = D->lbm_args();
     int tk = D->timed_begin(PSMDEM_T_LBM);
     PSM_CHECK(lbm_step(A, D->prec, (int)(D->step & 1), D->s));
     D->timed_end(tk);
+    if (!hydro) return 0;
     VoxArgs V = D->vox_args();
     tk = D->timed_begin(PSMDEM_T_HYDRO);
     PSM_CHECK(vox_reduce_hydro(V, D->s));
@@ -154,9 +157,9 @@ static int coupled_step(psmdem_domain* D) {
         D->cur ^= (D->nsub & 1);
         if (couple) {
             if ((rc = run_voxelize(D))) return rc;
-            if ((rc = run_lbm(D))) return rc;
-            tk = D->timed_begin(PSMDEM_T_DEM);
-            PSM_CHECK(dem_correct(A, D->dt, D->s));
+            if ((rc = run_lbm(D, false))) return rc;
+            tk = D->timed_begin(PSMDEM_T_HYDRO);
+            PSM_CHECK(dem_hydro_correct(A, D->t, D->dt, D->s));
             D->timed_end(tk);
         }
     } else if (D->d.dem_on && D->np > 0) {
@@ -176,10 +179,13 @@ static int coupled_step(psmdem_domain* D) {
             D->timed_end(tk);
             if (last && D->d.fluid_on) {
                 if ((rc = run_voxelize(D))) return rc;
-                if ((rc = run_lbm(D))) return rc;
+                if ((rc = run_lbm(D, false))) return rc;
+                tk = D->timed_begin(PSMDEM_T_HYDRO);
+                PSM_CHECK(dem_hydro_correct(A, D->t, D->dt, D->s));
+            } else {
+                tk = D->timed_begin(PSMDEM_T_DEM);
+                PSM_CHECK(dem_correct(A, D->dt, D->s));
             }
-            tk = D->timed_begin(PSMDEM_T_DEM);
-            PSM_CHECK(dem_correct(A, D->dt, D->s));
             D->timed_end(tk);
         }
     } else if (D->d.fluid_on) {

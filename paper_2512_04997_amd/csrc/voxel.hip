@@ -1071,44 +1071,11 @@ __global__ __launch_bounds__(VOX_T) void k_voxelize_batch(const VoxArgs* __restr
     voxelize_tile<C>(jobs[m.x], m.y);
 }
 
-// one wave per particle: lanes fetch the particle's partials, lane 0 sums them
-// in emission order (the order of psm_reduce_hydro)
+// one wave per particle
 __global__ void k_reduce_hydro(VoxArgs A) {
     const int k = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    const int lane = threadIdx.x & 63;
     if (k >= A.p.np) return;
-    const int e0 = A.t.voff[k], e1 = A.t.voff[k + 1];
-    double F[3] = {0.0, 0.0, 0.0}, M[3] = {0.0, 0.0, 0.0};
-    for (int b = e0; b < e1 && b < A.t.cap; b += 64) {
-        const int e = b + lane;
-        double P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        bool ok = false;
-        if (e < e1 && e < A.t.cap) {
-            const long long s = A.t.vinv[e];
-            ok = s >= 0 && s < A.t.cap;
-            if (ok)
-#pragma unroll
-                for (int c = 0; c < 6; ++c) P[c] = A.t.partial[6 * s + c];
-        }
-        const unsigned long long okm = __ballot(ok);
-        const int m = (e1 - b < 64 ? e1 - b : 64);
-        for (int j = 0; j < m; ++j) {
-            double v[6];
-#pragma unroll
-            for (int c = 0; c < 6; ++c) v[c] = __shfl(P[c], j, 64);
-            if ((okm >> j) & 1ull)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    F[c] -= v[c];
-                    M[c] -= v[3 + c];
-                }
-        }
-    }
-    if (lane == 0)
-        for (int c = 0; c < 3; ++c) {
-            A.p.fh[3 * k + c] = F[c];
-            A.p.mh[3 * k + c] = M[c];
-        }
+    psm_reduce_hydro_wave(A.t, A.p, k, threadIdx.x & 63);
 }
 
 inline unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
