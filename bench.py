@@ -67,7 +67,7 @@ def parse():
                    help="print a per-kernel summary of rocprofv3 CSV output (no GPU): DIR of a --kernel-trace "
                         "--stats run, or four DIRs of --pmc runs: FETCH_SIZE, WRITE_SIZE, and the same two "
                         "counters over --copy-probe")
-    p.add_argument("--kernel", default="k_lbm<", help="kernel-name filter of the counter summary")
+    p.add_argument("--kernel", default="k_lbm", help="kernel-name filter of the counter summary")
     return p.parse_args()
 
 
