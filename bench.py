@@ -54,6 +54,8 @@ def parse():
     p.add_argument("--serve-rate", type=float, default=50.0, help="mean arrival rate of served jobs (1/s)")
     p.add_argument("--serve-slots", type=int, default=32, help="active slots of the server")
     p.add_argument("--serve-budget-gb", type=float, default=16.0, help="HBM budget of the held jobs (GiB)")
+    p.add_argument("--stream-probe", type=int, default=0, metavar="MIB",
+                   help="attainable streaming bandwidth: copy / read / write kernels over MIB-sized buffers")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                    help="only run 20 plain device copies of MIB MiB (calibrates the HBM byte counters)")
     p.add_argument("--lbm-sweep", type=int, default=0, metavar="N",
@@ -263,6 +265,24 @@ def precision_study(n, fraction=0.2, warmup=20, timed=100, check=200):
         del u, P
 
 
+def stream_probe(mib):
+    """The device's attainable streaming rates (plain copy, read, write kernels
+    of the library), the ceiling beside the roofline's 8 TB/s."""
+    import torch
+    from paper_2512_04997_amd import psmdem
+    torch.cuda.set_device(0)
+    nbytes = mib << 20
+    a = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    for grid in (1024, 4096, 16384):
+        for kind, moved in (("copy", 2 * nbytes), ("read", nbytes), ("write", nbytes)):
+            ms = psmdem.stream_probe(kind, a.data_ptr(), b.data_ptr(), nbytes, grid)
+            print(json.dumps({"stream_probe": kind, "grid": grid, "bytes_moved": moved, "ms": round(ms, 4),
+                              "TB_s": round(moved / (ms * 1e-3) / 1e12, 3),
+                              "frac_of_peak": round(moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}), flush=True)
+
+
 def copy_probe(mib):
     """Plain device-to-device copies of a known size: the reference that scales
     the FETCH_SIZE / WRITE_SIZE counters of the profiler into HBM bytes."""
@@ -385,6 +405,9 @@ def main():
         sys.exit(2)
     import torch
 
+    if a.stream_probe:
+        stream_probe(a.stream_probe)
+        return
     if a.copy_probe:
         copy_probe(a.copy_probe)
         return

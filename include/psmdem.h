@@ -241,6 +241,18 @@ typedef enum { PSMDEM_T_LBM = 0, PSMDEM_T_VOXEL = 1, PSMDEM_T_DEM = 2, PSMDEM_T_
  * device. */
 psmdem_status psmdem_footprint(const psmdem_desc* desc, const psmdem_particles* parts, int64_t* bytes);
 
+/* Measurement utility, not part of the method: the device's attainable
+ * streaming bandwidth, stated beside the roofline figures.  Streams `bytes`
+ * (rounded down to 16-byte elements) through a plain grid-stride kernel of
+ * `grid` workgroups of 256 lanes on the null stream: kind 0 copies src to dst,
+ * kind 1 reads src (dst: at least 4 bytes, written only in a case that zero
+ * input never reaches), kind 2 writes dst.  Two untimed launches, then `reps`
+ * timed ones; *ms_per_launch receives their average duration (HIP events).
+ * Device pointers owned by the caller.  PSMDEM_E_INVALID on a null or short
+ * argument. */
+psmdem_status psmdem_stream_probe(int32_t kind, const void* src, void* dst, int64_t bytes, int32_t grid,
+                                  int32_t reps, double* ms_per_launch);
+
 /* --- ensemble serving: continuous batching of many domains ---------------- */
 /* A server advances many independent domains ("jobs") together.  Each
  * psmdem_server_iterate call

@@ -24,6 +24,7 @@ SOURCES = [
     ("lbm.hip", []),
     ("psmdem.hip", []),
     ("server.hip", []),
+    ("probe.hip", []),
 ]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -1,0 +1,78 @@
+// probe.hip -- attainable streaming bandwidth of the device (a measurement
+// utility beside the roofline figures, not part of the method): plain
+// grid-stride copy, read and write kernels over 16-byte elements, four
+// independent accesses per lane per iteration.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace {
+
+constexpr int PU = 4;
+
+__global__ __launch_bounds__(256) void k_probe_copy(const float4* __restrict__ a, float4* __restrict__ b, long long n) {
+    const long long stride = (long long)gridDim.x * 256 * PU;
+    for (long long i = (long long)blockIdx.x * 256 * PU + threadIdx.x; i < n; i += stride) {
+        float4 v[PU];
+#pragma unroll
+        for (int u = 0; u < PU; ++u) v[u] = i + u * 256 < n ? a[i + u * 256] : float4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int u = 0; u < PU; ++u)
+            if (i + u * 256 < n) b[i + u * 256] = v[u];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_probe_read(const float4* __restrict__ a, float* __restrict__ sink, long long n) {
+    const long long stride = (long long)gridDim.x * 256 * PU;
+    float s = 0.f;
+    for (long long i = (long long)blockIdx.x * 256 * PU + threadIdx.x; i < n; i += stride)
+#pragma unroll
+        for (int u = 0; u < PU; ++u)
+            if (i + u * 256 < n) {
+                const float4 v = a[i + u * 256];
+                s += (v.x + v.y) + (v.z + v.w);
+            }
+    // keeps the loads; the sum of zero-filled input never equals this
+    if (s == 1234.5f) sink[0] = s;
+}
+
+__global__ __launch_bounds__(256) void k_probe_write(float4* __restrict__ b, long long n) {
+    const long long stride = (long long)gridDim.x * 256 * PU;
+    for (long long i = (long long)blockIdx.x * 256 * PU + threadIdx.x; i < n; i += stride)
+#pragma unroll
+        for (int u = 0; u < PU; ++u)
+            if (i + u * 256 < n) b[i + u * 256] = float4{1.f, 2.f, 3.f, 4.f};
+}
+
+}  // namespace
+
+extern "C" psmdem_status psmdem_stream_probe(int32_t kind, const void* src, void* dst, int64_t bytes, int32_t grid,
+                                             int32_t reps, double* ms_per_launch) {
+    if (!ms_per_launch || bytes < 16 || grid < 1 || reps < 1 || kind < 0 || kind > 2 || !dst || (kind != 2 && !src)) {
+        psm_set_error("stream probe: invalid arguments");
+        return PSMDEM_E_INVALID;
+    }
+    const long long n = bytes / 16;
+    const float4* a = (const float4*)src;
+    float4* b = (float4*)dst;
+    auto launch = [&]() {
+        if (kind == 0) k_probe_copy<<<grid, 256>>>(a, b, n);
+        else if (kind == 1) k_probe_read<<<grid, 256>>>(a, (float*)dst, n);
+        else k_probe_write<<<grid, 256>>>(b, n);
+    };
+    hipEvent_t e0, e1;
+    PSM_CHECK(hipEventCreate(&e0));
+    PSM_CHECK(hipEventCreate(&e1));
+    for (int w = 0; w < 2; ++w) launch();
+    PSM_CHECK(hipGetLastError());
+    PSM_CHECK(hipEventRecord(e0, 0));
+    for (int r = 0; r < reps; ++r) launch();
+    PSM_CHECK(hipEventRecord(e1, 0));
+    PSM_CHECK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    PSM_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    PSM_CHECK(hipEventDestroy(e0));
+    PSM_CHECK(hipEventDestroy(e1));
+    *ms_per_launch = (double)ms / reps;
+    return PSMDEM_OK;
+}

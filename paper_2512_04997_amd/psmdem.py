@@ -125,6 +125,7 @@ def lib():
     L.psmdem_set_timing.argtypes = [P, C.c_int32]
     L.psmdem_timing.argtypes = [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.psmdem_footprint.argtypes = [C.POINTER(Desc), C.POINTER(Particles), C.POINTER(C.c_int64)]
+    L.psmdem_stream_probe.argtypes = [C.c_int32, P, P, C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_double)]
     L.psmdem_clock.argtypes = []
     L.psmdem_clock.restype = C.c_double
     L.psmdem_server_create.argtypes = [C.POINTER(ServerDesc), P, P, ALLOC_FN, FREE_FN, P, C.POINTER(P)]
@@ -146,7 +147,8 @@ def lib():
                  "psmdem_write_particles", "psmdem_read_predicted", "psmdem_write_predicted",
                  "psmdem_read_pairs", "psmdem_write_pairs", "psmdem_read_contacts",
                  "psmdem_read_cells", "psmdem_read_solid", "psmdem_counters", "psmdem_info",
-                 "psmdem_set_timing", "psmdem_timing", "psmdem_footprint", "psmdem_server_create",
+                 "psmdem_set_timing", "psmdem_timing", "psmdem_footprint", "psmdem_stream_probe",
+                 "psmdem_server_create",
                  "psmdem_server_submit", "psmdem_server_iterate", "psmdem_server_drain", "psmdem_server_job",
                  "psmdem_server_domain", "psmdem_server_release"):
         getattr(L, name).restype = st
@@ -513,3 +515,15 @@ class Server:
 
 def version():
     return lib().psmdem_version().decode()
+
+
+STREAM_KINDS = {"copy": 0, "read": 1, "write": 2}
+
+
+def stream_probe(kind, src, dst, nbytes, grid=16384, reps=10):
+    """Average milliseconds of one plain streaming pass (a measurement of the
+    device, not part of the method) over device buffers src, dst (addresses)."""
+    ms = C.c_double()
+    _check(lib().psmdem_stream_probe(STREAM_KINDS[kind], C.c_void_p(src), C.c_void_p(dst), int(nbytes), int(grid),
+                                     int(reps), C.byref(ms)))
+    return ms.value

@@ -55,6 +55,19 @@ def test_invalid_description_is_rejected_without_a_device():
     assert code == P.E_INVALID and b"trt_magic" in L.psmdem_last_error()
 
 
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpsmdem.so not built")
+def test_stream_probe_rejects_bad_arguments_without_a_device():
+    from paper_2512_04997_amd import psmdem as P
+    L = P.lib()
+    ms = ctypes.c_double()
+    for kind, src, dst, nbytes, grid, reps, out in ((3, 16, 16, 1 << 20, 8, 1, True), (0, None, 16, 1 << 20, 8, 1, True),
+                                                   (2, None, None, 1 << 20, 8, 1, True), (0, 16, 16, 8, 8, 1, True),
+                                                   (0, 16, 16, 1 << 20, 0, 1, True), (0, 16, 16, 1 << 20, 8, 0, True),
+                                                   (1, 16, 16, 1 << 20, 8, 1, False)):
+        code = L.psmdem_stream_probe(kind, src, dst, nbytes, grid, reps, ctypes.byref(ms) if out else None)
+        assert code == P.E_INVALID and b"stream probe" in L.psmdem_last_error()
+
+
 def _r256(n):
     return (n + 255) // 256 * 256
 
