@@ -471,7 +471,7 @@ def main():
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": (measured_traffic(a.precision, a.n, a.spheres)
                                                                     if a.workload == "couette" else None),
-                "kernel": "LBM collide-stream pass (k_lbm fluid-tile + PSM-tile kernels of one step)",
+                "kernel": "LBM collide-stream pass (one k_lbm_mixed launch over fluid and PSM tiles per step)",
                 "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": round(lbm_ms, 5)}
         print(f"[bench] per step: lbm {lbm_ms:.4f} ms, voxel {vox_ms:.4f} ms, hydro {hyd_ms:.4f} ms, "
               f"dem {dem_ms * dem_n / max(lbm_n, 1):.4f} ms ({dem_n // max(lbm_n, 1)} DEM launch groups)",
