@@ -649,63 +649,6 @@ __device__ void ph_colsort(const DemArgs& A, int j) {
         }
 }
 
-__device__ inline long long find_pair(const PairBufs& B, unsigned long long key, long long lo, long long hi) {
-    const long long end = hi;
-    while (lo < hi) {
-        long long mid = (lo + hi) >> 1;
-        if (B.pairs[mid] < key) lo = mid + 1;
-        else hi = mid;
-    }
-    return (lo < end && B.pairs[lo] == key) ? lo : -1;
-}
-
-// F_dem, M_dem of particle i: pairs (k, i) by ascending k (second member),
-// then its own row (first member), as the pairs are ordered
-template <bool ALL>
-__device__ void ph_sum(const DemArgs& A, const PairBufs& B, int i) {
-    double F[3] = {0.0, 0.0, 0.0}, M[3] = {0.0, 0.0, 0.0};
-    const long long cap = A.pair_cap;
-    if (ALL) {
-        AxCells ri;
-        load_cells(A, i, ri);
-        for (int k = 0; k < i; ++k) {
-            AxCells rk;
-            load_cells(A, k, rk);
-            if (!share_cell(ri, rk)) continue;
-            long long lo = B.prow[k], hi = B.prow[k + 1];
-            hi = hi < cap ? hi : cap;
-            const long long s = find_pair(B, ((unsigned long long)k << 32) | (unsigned)i, lo, hi);
-            if (s < 0) continue;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                F[c] -= A.cF[3 * s + c];
-                M[c] += A.cMj[3 * s + c];
-            }
-        }
-    } else {
-        for (int u = A.col_start[i]; u < A.col_start[i + 1]; ++u) {
-            const long long s = A.col_list[u];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                F[c] -= A.cF[3 * s + c];
-                M[c] += A.cMj[3 * s + c];
-            }
-        }
-    }
-    long long s0 = B.prow[i], s1 = B.prow[i + 1];
-    s1 = s1 < cap ? s1 : cap;
-    for (long long s = s0; s < s1; ++s)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            F[c] += A.cF[3 * s + c];
-            M[c] += A.cMi[3 * s + c];
-        }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        A.p.fd[3 * i + c] = F[c];
-        A.p.md[3 * i + c] = M[c];
-    }
-}
 
 // q' = (1/2) [0, w] (x) q
 __device__ inline void quat_rate(const double* w, const double* q, double* out) {
@@ -1184,7 +1127,69 @@ __global__ __launch_bounds__(256) void k_colsort(DemArgs A) {
         }
     }
 }
-__global__ void k_sum(DemArgs A, PairBufs B) { GRID_LOOP(i, A.p.np) ph_sum<false>(A, B, (int)i); }
+// F_dem, M_dem of particle i, one wave per particle: pairs (k, i) by ascending
+// k (its column list), then its own row, as the pairs are ordered.  The lanes
+// fetch the particle's entries
+// with their in-contact flags and forces at once; lane 0 adds the terms of
+// the pairs in contact in that order.  A pair out of contact holds zero forces,
+// whose terms leave a sum unchanged.
+__global__ __launch_bounds__(256) void k_sum_wave(DemArgs A, PairBufs B) {
+    const int lane = threadIdx.x & 63;
+    const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
+    const long long cap = A.pair_cap;
+    for (long long w = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < A.p.np; w += nw) {
+        const int i = (int)w;
+        const long long c0 = A.col_start[i], nc = A.col_start[i + 1] - c0;
+        const long long s0 = B.prow[i];
+        long long s1 = B.prow[i + 1];
+        s1 = s1 < cap ? s1 : cap;
+        const long long ne = nc + (s1 > s0 ? s1 - s0 : 0);
+        double F[3] = {0.0, 0.0, 0.0}, M[3] = {0.0, 0.0, 0.0};
+        for (long long b = 0; b < ne; b += 64) {
+            const long long e = b + lane;
+            double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            bool in = false;
+            if (e < ne) {
+                const bool col = e < nc;
+                const long long s = col ? (long long)A.col_list[c0 + e] : s0 + (e - nc);
+                in = A.incontact[s] != 0;
+                if (in) {
+                    const double* Mo = col ? A.cMj : A.cMi;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        v[c] = A.cF[3 * s + c];
+                        v[3 + c] = Mo[3 * s + c];
+                    }
+                }
+            }
+            for (unsigned long long m = __ballot(in); m; m &= m - 1) {
+                const int j = __ffsll((long long)m) - 1;
+                double t[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) t[c] = __shfl(v[c], j, 64);
+                if (b + j < nc) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        F[c] -= t[c];
+                        M[c] += t[3 + c];
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        F[c] += t[c];
+                        M[c] += t[3 + c];
+                    }
+                }
+            }
+        }
+        if (lane == 0)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                A.p.fd[3 * i + c] = F[c];
+                A.p.md[3 * i + c] = M[c];
+            }
+    }
+}
 __global__ void k_correct(DemArgs A, double dt) { GRID_LOOP(k, A.p.np) ph_correct(A, (int)k, dt); }
 
 // after the LBM-PSM pass: each particle's hydrodynamic sums (one wave), then
@@ -1834,7 +1839,7 @@ hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, c
     if ((e = psm_scan(A.col_count, A.col_start, A.p.np, scan_tmp, s, A.list_run)) != hipSuccess) return e;
     k_colscatter<<<nblk(A.pair_cap), 256, 0, s>>>(A, B);
     k_colsort<<<nblk(64LL * A.p.np), 256, 0, s>>>(A);
-    k_sum<<<nblk(A.p.np, 128), 128, 0, s>>>(A, B);
+    k_sum_wave<<<nblk(64LL * A.p.np), 256, 0, s>>>(A, B);
     return hipGetLastError();
 }
 
