@@ -154,34 +154,39 @@ __device__ inline void psm_reduce_hydro(const TileArgs& t, const PartArgs& p, in
 }
 
 // The same sums by one wave (every lane calls it): lanes fetch the
-// particle's partials, lane 0 adds them in emission order and stores fh, mh.
-__device__ inline void psm_reduce_hydro_wave(const TileArgs& t, const PartArgs& p, int k, int lane) {
+// particle's partials into the wave's LDS buffer buf[64 * 6], lane 0 adds
+// them in emission order and stores fh, mh.
+__device__ inline void psm_reduce_hydro_wave(const TileArgs& t, const PartArgs& p, int k, int lane, double* buf) {
     const int e0 = t.voff[k], e1 = t.voff[k + 1];
     double F[3] = {0.0, 0.0, 0.0}, M[3] = {0.0, 0.0, 0.0};
     for (int b = e0; b < e1 && b < t.cap; b += 64) {
         const int e = b + lane;
-        double P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         bool ok = false;
         if (e < e1 && e < t.cap) {
             const long long s = t.vinv[e];
             ok = s >= 0 && s < t.cap;
             if (ok)
 #pragma unroll
-                for (int c = 0; c < 6; ++c) P[c] = t.partial[6 * s + c];
+                for (int c = 0; c < 6; ++c) buf[6 * lane + c] = t.partial[6 * s + c];
         }
         const unsigned long long okm = __ballot(ok);
-        const int m = (e1 - b < 64 ? e1 - b : 64);
-        for (int j = 0; j < m; ++j) {
-            double v[6];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (lane == 0) {
+            const int m = (e1 - b < 64 ? e1 - b : 64);
+            for (int j = 0; j < m; ++j)
+                if ((okm >> j) & 1ull)
 #pragma unroll
-            for (int c = 0; c < 6; ++c) v[c] = __shfl(P[c], j, 64);
-            if ((okm >> j) & 1ull)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    F[c] -= v[c];
-                    M[c] -= v[3 + c];
-                }
+                    for (int c = 0; c < 3; ++c) {
+                        F[c] -= buf[6 * j + c];
+                        M[c] -= buf[6 * j + 3 + c];
+                    }
         }
+        // the buffer is refilled only after lane 0 has read it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     if (lane == 0)
         for (int c = 0; c < 3; ++c) {

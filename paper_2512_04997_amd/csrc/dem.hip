@@ -1194,11 +1194,12 @@ __global__ void k_correct(DemArgs A, double dt) { GRID_LOOP(k, A.p.np) ph_correc
 
 // after the LBM-PSM pass: each particle's hydrodynamic sums (one wave), then
 // its corrector (lane 0, which stored the sums)
-__global__ void k_hydro_correct(DemArgs A, TileArgs T, double dt) {
+__global__ __launch_bounds__(256) void k_hydro_correct(DemArgs A, TileArgs T, double dt) {
+    __shared__ double buf[4][64 * 6];
     const int k = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const int lane = threadIdx.x & 63;
     if (k >= A.p.np) return;
-    psm_reduce_hydro_wave(T, A.p, k, lane);
+    psm_reduce_hydro_wave(T, A.p, k, lane, buf[threadIdx.x >> 6]);
     if (lane == 0) ph_correct(A, k, dt);
 }
 __global__ void k_initial_accel(DemArgs A) { GRID_LOOP(k, A.p.np) ph_initial_accel(A, (int)k); }

@@ -1072,10 +1072,11 @@ __global__ __launch_bounds__(VOX_T) void k_voxelize_batch(const VoxArgs* __restr
 }
 
 // one wave per particle
-__global__ void k_reduce_hydro(VoxArgs A) {
+__global__ __launch_bounds__(256) void k_reduce_hydro(VoxArgs A) {
+    __shared__ double buf[4][64 * 6];
     const int k = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     if (k >= A.p.np) return;
-    psm_reduce_hydro_wave(A.t, A.p, k, threadIdx.x & 63);
+    psm_reduce_hydro_wave(A.t, A.p, k, threadIdx.x & 63, buf[threadIdx.x >> 6]);
 }
 
 inline unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) / t > 0 ? (n + t - 1) / t : 1); }
