@@ -602,11 +602,13 @@ __device__ inline long long xcd_block(long long nblocks) {
 }
 
 // PSM tiles (two slots): four workgroups per CU within 128 registers where it
-// measures faster than the natural allocation (three): 16-bit storage (some
-// spilled on the odd step) and the float even step (no spill)
+// measures faster than the natural allocation: the even step of 16-bit and
+// float storage (no spill).  The odd step keeps its natural allocation (three
+// workgroups; four would spill, slower for float, and for 16-bit storage on
+// lattices of many PSM tiles).
 template <typename S, bool ODD, int MS>
 struct LbmMinBlocks {
-    static constexpr int value = (MS == 2 && (sizeof(S) == 2 || (sizeof(S) == 4 && !ODD))) ? 4 : 1;
+    static constexpr int value = (MS == 2 && !ODD && (sizeof(S) == 2 || sizeof(S) == 4)) ? 4 : 1;
 };
 
 template <typename S, typename C, bool ODD, int MS>
