@@ -245,8 +245,8 @@ psmdem_status psmdem_footprint(const psmdem_desc* desc, const psmdem_particles* 
  * streaming bandwidth, stated beside the roofline figures.  Streams `bytes`
  * (rounded down to 16-byte elements) through a plain grid-stride kernel of
  * `grid` workgroups of 256 lanes on the null stream: kind 0 copies src to dst,
- * kind 1 reads src (dst: at least 4 bytes, written only in a case that zero
- * input never reaches), kind 2 writes dst.  Two untimed launches, then `reps`
+ * kind 1 reads src (dst: at least 4 bytes; its first float is written only by
+ * a lane whose partial sum equals 1234.5), kind 2 writes dst.  Two untimed launches, then `reps`
  * timed ones; *ms_per_launch receives their average duration (HIP events).
  * Device pointers owned by the caller.  PSMDEM_E_INVALID on a null or short
  * argument. */

@@ -32,7 +32,8 @@ __global__ __launch_bounds__(256) void k_probe_read(const float4* __restrict__ a
                 const float4 v = a[i + u * 256];
                 s += (v.x + v.y) + (v.z + v.w);
             }
-    // keeps the loads; the sum of zero-filled input never equals this
+    // the compare keeps the loads live: sink[0] is written only by a lane
+    // whose sum is exactly this value
     if (s == 1234.5f) sink[0] = s;
 }
 
