@@ -1781,6 +1781,15 @@ inline unsigned nblk(long long n, int t = 256) {
     return (unsigned)b;
 }
 
+// The list kernels loop over their items with a grid stride; on the substeps
+// that keep the list they return at once, so their grids stay small (a launch
+// dispatches every workgroup even when each returns at once).
+constexpr unsigned DEM_LIST_GRID_MAX = 512;
+inline unsigned nblk_list(long long n) {
+    const unsigned b = nblk(n);
+    return b < DEM_LIST_GRID_MAX ? b : DEM_LIST_GRID_MAX;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1804,14 +1813,14 @@ hipError_t dem_lists_kept(const DemArgs& A, const PairBufs& B, int par, int* sca
     if (A.p.np == 0) return hipSuccess;
     hipError_t e;
     k_list_age<<<1, 1, 0, s>>>(A, par);
-    k_list_copy<<<nblk(A.pair_cap), 256, 0, s>>>(A, B, par);
-    k_hist<<<nblk(A.p.np), 256, 0, s>>>(A);
+    k_list_copy<<<nblk_list(A.pair_cap), 256, 0, s>>>(A, B, par);
+    k_hist<<<nblk_list(A.p.np), 256, 0, s>>>(A);
     if ((e = psm_scan(A.cell_count, A.cell_start, A.ncell, scan_tmp, s, A.list_run)) != hipSuccess) return e;
-    k_scatter<<<nblk(A.p.np), 256, 0, s>>>(A);
-    k_cellsort<<<nblk(A.ncell), 256, 0, s>>>(A);
-    k_paircount<<<nblk(64LL * A.p.np), 256, 0, s>>>(A);
+    k_scatter<<<nblk_list(A.p.np), 256, 0, s>>>(A);
+    k_cellsort<<<nblk_list(A.ncell), 256, 0, s>>>(A);
+    k_paircount<<<nblk_list(64LL * A.p.np), 256, 0, s>>>(A);
     if ((e = psm_scan(A.pcount, B.prow, A.p.np, scan_tmp, s, A.list_run)) != hipSuccess) return e;
-    k_pairemit<<<nblk(64LL * A.p.np), 256, 0, s>>>(A, B);
+    k_pairemit<<<nblk_list(64LL * A.p.np), 256, 0, s>>>(A, B);
     return hipGetLastError();
 }
 
@@ -1822,11 +1831,11 @@ hipError_t dem_lists(const DemArgs& A, const PairBufs& B, int* scan_tmp, hipStre
     k_cells<<<nblk(A.p.np), 256, 0, s>>>(A);
     k_hist<<<nblk(A.p.np), 256, 0, s>>>(A);
     if ((e = psm_scan(A.cell_count, A.cell_start, A.ncell, scan_tmp, s)) != hipSuccess) return e;
-    k_scatter<<<nblk(A.p.np), 256, 0, s>>>(A);
-    k_cellsort<<<nblk(A.ncell), 256, 0, s>>>(A);
-    k_paircount<<<nblk(64LL * A.p.np), 256, 0, s>>>(A);
+    k_scatter<<<nblk_list(A.p.np), 256, 0, s>>>(A);
+    k_cellsort<<<nblk_list(A.ncell), 256, 0, s>>>(A);
+    k_paircount<<<nblk_list(64LL * A.p.np), 256, 0, s>>>(A);
     if ((e = psm_scan(A.pcount, B.prow, A.p.np, scan_tmp, s)) != hipSuccess) return e;
-    k_pairemit<<<nblk(64LL * A.p.np), 256, 0, s>>>(A, B);
+    k_pairemit<<<nblk_list(64LL * A.p.np), 256, 0, s>>>(A, B);
     return hipGetLastError();
 }
 
@@ -1836,10 +1845,10 @@ hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, c
     hipError_t e;
     if (A.ellipsoids) k_contacts<true><<<nblk(A.pair_cap, 128), 128, 0, s>>>(A, B, vv, ww, dth);
     else k_contacts<false><<<nblk(A.pair_cap, 128), 128, 0, s>>>(A, B, vv, ww, dth);
-    k_colhist<<<nblk(A.pair_cap), 256, 0, s>>>(A, B);
+    k_colhist<<<nblk_list(A.pair_cap), 256, 0, s>>>(A, B);
     if ((e = psm_scan(A.col_count, A.col_start, A.p.np, scan_tmp, s, A.list_run)) != hipSuccess) return e;
-    k_colscatter<<<nblk(A.pair_cap), 256, 0, s>>>(A, B);
-    k_colsort<<<nblk(64LL * A.p.np), 256, 0, s>>>(A);
+    k_colscatter<<<nblk_list(A.pair_cap), 256, 0, s>>>(A, B);
+    k_colsort<<<nblk_list(64LL * A.p.np), 256, 0, s>>>(A);
     k_sum_wave<<<nblk(64LL * A.p.np), 256, 0, s>>>(A, B);
     return hipGetLastError();
 }
