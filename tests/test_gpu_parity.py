@@ -117,6 +117,29 @@ def _mixed_particles(seed, n, box, periodic, ell_frac=0.5, gap=0.3):
                 omega=0.002 * (rng.uniform(3 * m).reshape(m, 3) - 0.5), fixed=np.zeros(m, np.uint8))
 
 
+@pytest.mark.parametrize("method", ["subdivision", "distance"])
+def test_voxelize_bitexact_many_tiles(ps, oracle_mod, method):
+    """A lattice of 8320 tiles (64 x 256 x 520), beyond the size whose tile
+    lists are ordered inside the per-tile voxelisation kernels: the lists are
+    ordered by their own kernel there.  Kept slots bit for bit."""
+    box = (64, 256, 520)
+    parts = _mixed_particles(131, 200, box, [True, True, True], ell_frac=0.0 if method == "distance" else 0.5)
+    cfg = W.base_config(box, 0.7, sf_method=method, max_solids=2)
+    assert (box[0] // 64) * (box[1] // 4) * (box[2] // 4) > 8192
+    G, O = _pair(ps, oracle_mod, cfg, parts)
+    G.stage("voxelize")
+    O.stage_voxelize()
+    cg, pg, bg = G.solid()
+    co, po, bo = O.solid()
+    assert len(co) > 50000
+    assert np.array_equal(cg, co) and np.array_equal(pg, po)
+    if method == "subdivision":
+        assert np.array_equal(bg, bo)
+    else:
+        assert np.max(np.abs(bg - bo)) < 1e-14
+    G.close()
+
+
 @pytest.mark.parametrize("walls", [False, True])
 @pytest.mark.parametrize("method", ["subdivision", "distance"])
 def test_voxelize_bitexact(ps, oracle_mod, walls, method):
