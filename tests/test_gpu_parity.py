@@ -117,6 +117,50 @@ def _mixed_particles(seed, n, box, periodic, ell_frac=0.5, gap=0.3):
                 omega=0.002 * (rng.uniform(3 * m).reshape(m, 3) - 0.5), fixed=np.zeros(m, np.uint8))
 
 
+def _fcc_cluster(lo, hi, d):
+    """Face-centred cubic points with nearest distance d inside the box lo..hi."""
+    a = d * np.sqrt(2.0)
+    base = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]]) * a
+    n = [int((hi[c] - lo[c]) / a) + 1 for c in range(3)]
+    pts = [np.array(lo) + np.array([i, j, k]) * a + b
+           for i in range(n[0]) for j in range(n[1]) for k in range(n[2]) for b in base]
+    return np.array([p for p in pts if np.all(p <= np.array(hi))])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("ms", [2, 4])
+def test_coupled_steps_three_solids_per_cell(ps, oracle_mod, ms, prec):
+    """A face-centred cluster of 70 spheres (R = 3, nearest centres 6.05
+    apart) with the distance solid fraction: cells near the triangle centroids
+    see three solids.  Four slots run the four-slot LBM-PSM kernels and keep
+    all three; two slots drop the smallest.  Two coupled steps against the
+    FP64 oracle."""
+    box = (48, 40, 36)
+    pos = _fcc_cluster((10.3, 9.7, 9.1), (37.0, 30.0, 26.0), 6.05)
+    parts = W.spheres(pos, 3.0, 1.5)
+    cfg = W.base_config(box, 0.7, max_solids=ms, n_sub=4, precision=prec, sf_method="distance")
+    G, O = _pair(ps, oracle_mod, cfg, parts)
+    for _ in range(2):
+        G.step(1)
+        O.step(1)
+    cg, pg, bg = G.solid()
+    co, po, bo = O.solid()
+    assert np.array_equal(cg, co) and np.array_equal(pg, po)
+    assert np.abs(bg - bo).max() < 1e-12
+    u, cnt = np.unique(co, return_counts=True)
+    if ms == 4:
+        assert (cnt >= 3).sum() > 10
+    else:
+        assert G.counters()["n_dropped"] > 0
+    assert pop_err(G.populations(), O.populations()) < TOL[prec]
+    Pg, Po = G.particles(), O.particles()
+    sc = O.scales()
+    assert vec_err(Pg["vel"], Po["vel"]) < TOL[prec]
+    assert force_err(Pg["f_hyd"], Po["f_hyd"], sc["f_hyd"]) < TOL[prec]
+    assert force_err(Pg["m_hyd"], Po["m_hyd"], sc["m_hyd"]) < TOL[prec]
+    G.close()
+
+
 @pytest.mark.parametrize("method", ["subdivision", "distance"])
 def test_voxelize_bitexact_many_tiles(ps, oracle_mod, method):
     """A lattice of 8320 tiles (64 x 256 x 520), beyond the size whose tile
