@@ -444,6 +444,16 @@ void or_stage_voxelize(or_domain* D) {
         double R[9];
         quat_to_rbw(D->q + 4 * k, R);
         int32_t lo[3], hi[3];
+        /* a centre more than one box length outside the domain (a state that
+         * has blown up) or not finite has no entries */
+        int far = 0;
+        for (int a = 0; a < 3; ++a)
+            far |= !(c[a] >= -(double)dims[a] && c[a] < 2.0 * (double)dims[a]);
+        if (far) {
+            per[k] = NULL;
+            cnt[k] = 0;
+            continue;
+        }
         for (int a = 0; a < 3; ++a) {
             double E = e[a] + 1e-6;
             if (D->d.sf_method == 1) E += D->Rc;
@@ -486,7 +496,7 @@ void or_stage_voxelize(or_domain* D) {
     entry_t* all = (entry_t*)xcalloc(tot, sizeof(entry_t));
     int64_t o = 0;
     for (int k = 0; k < np; ++k) {
-        memcpy(all + o, per[k], cnt[k] * sizeof(entry_t));
+        if (cnt[k]) memcpy(all + o, per[k], cnt[k] * sizeof(entry_t));
         o += cnt[k];
         free(per[k]);
     }
@@ -768,9 +778,27 @@ static int u64_cmp(const void* A, const void* B) {
     return a < b ? -1 : (a > b);
 }
 
+/* Cell index t (an integer-valued double, floor of a coordinate over h) wrapped
+ * on a periodic axis (remainder mod n, exact in double) or clamped to
+ * [0, n-1] on a walled one.  Done in double so that a position of any finite
+ * magnitude maps to a cell without an out-of-range integer conversion; a NaN
+ * coordinate maps to cell 0. */
+static int32_t wrap_cell(double t, int32_t n, int periodic) {
+    if (t != t) return 0;
+    if (periodic) {
+        double r = fmod(t, (double)n);
+        if (r < 0.0) r += (double)n;
+        return (int32_t)r;
+    }
+    if (t < 0.0) return 0;
+    if (t > (double)(n - 1)) return n - 1;
+    return (int32_t)t;
+}
+
 /* DEM cells touched by particle k's axis-aligned box: per axis
- * lo = floor((x - e)/h) .. hi = floor((x + e)/h), wrapped on periodic axes and
- * clamped on walled ones.  Returns the number of cells (<= 27) in out[]. */
+ * lo = floor((x - e)/h) .. hi = floor((x + e)/h) (at most two cells, as h
+ * exceeds every diameter), wrapped on periodic axes and clamped on walled
+ * ones.  Returns the number of cells (<= 8) in out[]. */
 static int registrations(const or_domain* D, int k, int64_t* out) {
     double e[3];
     half_extents(D, k, e);
@@ -778,18 +806,15 @@ static int registrations(const or_domain* D, int k, int64_t* out) {
     int nl[3];
     for (int a = 0; a < 3; ++a) {
         double x = D->pos[3 * k + a];
-        int32_t lo = (int32_t)floor((x - e[a]) / D->h[a]);
-        int32_t hi = (int32_t)floor((x + e[a]) / D->h[a]);
+        double lo = floor((x - e[a]) / D->h[a]);
+        double hi = floor((x + e[a]) / D->h[a]);
+        double cand[2] = {lo, lo + 1.0};
+        int nc = hi > lo ? 2 : 1;
         nl[a] = 0;
-        for (int32_t c = lo; c <= hi && nl[a] < 2; ++c) {
-            int32_t cw = c;
-            if (periodic_axis(D, a)) cw = ((c % D->nc[a]) + D->nc[a]) % D->nc[a];
-            else {
-                if (cw < 0) cw = 0;
-                if (cw > D->nc[a] - 1) cw = D->nc[a] - 1;
-            }
+        for (int u = 0; u < nc; ++u) {
+            int32_t cw = wrap_cell(cand[u], D->nc[a], periodic_axis(D, a));
             int dup = 0;
-            for (int u = 0; u < nl[a]; ++u) dup |= (list[a][u] == cw);
+            for (int v = 0; v < nl[a]; ++v) dup |= (list[a][v] == cw);
             if (!dup) list[a][nl[a]++] = cw;
         }
     }

@@ -780,3 +780,251 @@ def test_golden_jeffery_period():
     a, b, gd = g["a"], g["b"], g["shear_rate"]
     TJ = math.pi * (a * a + b * b) / (a * b * gd)
     assert abs(TJ - g["T_J"]) < g["abs_tol"]
+
+
+# --------------------------------------------------------------------------- orientation convention
+# q = (1/2, 1/2, 1/2, 1/2) is the rotation by 120 degrees about (1,1,1): its
+# matrix is an exact permutation (body x -> world y, body y -> world z,
+# body z -> world x) and is not symmetric, so reading R where R^T is meant
+# (or the reverse) sends the body axes elsewhere (body x -> world z).
+Q120 = np.array([[0.5, 0.5, 0.5, 0.5]])
+
+
+def _ellipsoid(semi, pos, quat=None, dens=2.0, vel=None):
+    n = len(pos)
+    return dict(shape=np.ones(n, np.int32), semi=np.array(semi, float).reshape(n, 3), dens=np.full(n, dens),
+                pos=np.array(pos, float).reshape(n, 3),
+                quat=np.tile([1.0, 0, 0, 0], (n, 1)) if quat is None else np.array(quat, float).reshape(n, 4),
+                vel=np.zeros((n, 3)) if vel is None else np.array(vel, float).reshape(n, 3),
+                omega=np.zeros((n, 3)), fixed=np.zeros(n, np.uint8))
+
+
+def _beta_field(oracle_mod, parts, n=(28, 28, 28)):
+    D = _dom(oracle_mod, W.base_config(n, 0.8, dem_on=False), parts)
+    D.stage_voxelize()
+    c, _, b = D.solid()
+    f = np.zeros(n[0] * n[1] * n[2])
+    f[c] = b
+    return f
+
+
+def test_orientation_convention_solid_fraction(oracle_mod):
+    """Semi-axes (6, 3, 2) turned by Q120 occupy the cells of semi-axes (2, 6, 3)
+    with no rotation (the samples are the same points; only the order of the
+    three squared terms differs, so at most a sample or two on the surface may
+    flip).  The transposed reading would give (3, 2, 6)."""
+    c = [14.3, 13.6, 14.45]
+    turned = _beta_field(oracle_mod, _ellipsoid([6.0, 3.0, 2.0], [c], Q120))
+    plain = _beta_field(oracle_mod, _ellipsoid([2.0, 6.0, 3.0], [c]))
+    wrong = _beta_field(oracle_mod, _ellipsoid([3.0, 2.0, 6.0], [c]))
+    diff = np.abs(turned - plain)
+    assert np.count_nonzero(diff) <= 3 and diff.max() <= 0.002
+    assert np.abs(turned - wrong).sum() > 50.0
+
+
+def test_orientation_convention_wall_contact(oracle_mod):
+    """Ellipsoid-wall overlap: delta = sqrt(n^T A n) - distance, the world extent
+    along the wall normal.  Q120 puts semi-axis 3 along z and 6 along y."""
+    bc = ["periodic"] * 2 + ["noslip"] * 4
+    cfg = W.base_config((32, 32, 32), 0.8, bc=bc, fluid_on=False)
+    D = _dom(oracle_mod, cfg, _ellipsoid([6.0, 3.0, 2.0], [[16.0, 5.5, 2.5]], Q120))
+    gz = D.contact_geometry(0, 1 + 4)       # wall -z (face 4)
+    assert abs(gz["delta"] - 0.5) < 1e-14
+    np.testing.assert_allclose(gz["en"], [0, 0, 1], atol=0)
+    np.testing.assert_allclose(gz["rci"], [0, 0, -3.0], atol=1e-14)
+    gy = D.contact_geometry(0, 1 + 2)       # wall -y (face 2)
+    assert abs(gy["delta"] - 0.5) < 1e-14
+    np.testing.assert_allclose(gy["rci"], [0, -6.0, 0], atol=1e-14)
+    gx = D.contact_geometry(0, 1 + 5)       # wall +z at distance 29.5: far
+    assert gx["delta"] < -20
+
+
+def test_orientation_convention_pair_contact(oracle_mod):
+    """Two Q120 ellipsoids stacked along z (world extent 3 each) with centres 5.5
+    apart overlap by 0.5 tip to tip; side by side along y (extent 6 each) with
+    centres 11.6 apart they overlap by 0.4."""
+    cfg = W.base_config((48, 48, 48), 0.8, fluid_on=False)
+    q = np.vstack([Q120, Q120])
+    D = _dom(oracle_mod, cfg, _ellipsoid([[6.0, 3.0, 2.0]] * 2, [[20.0, 20.0, 20.0], [20.0, 20.0, 25.5]], q))
+    g = D.contact_geometry(0, 1)
+    assert abs(g["delta"] - 0.5) < 1e-12
+    np.testing.assert_allclose(g["en"], [0, 0, -1], atol=1e-12)
+    np.testing.assert_allclose(g["rci"], [0, 0, 3.0], atol=1e-12)
+    np.testing.assert_allclose(g["rcj"], [0, 0, -3.0], atol=1e-12)
+    D = _dom(oracle_mod, cfg, _ellipsoid([[6.0, 3.0, 2.0]] * 2, [[20.0, 20.0, 20.0], [20.0, 31.6, 20.0]], q))
+    g = D.contact_geometry(0, 1)
+    assert abs(g["delta"] - 0.4) < 1e-12
+    np.testing.assert_allclose(g["en"], [0, -1, 0], atol=1e-12)
+
+
+# --------------------------------------------------------------------------- Kolmogorov forcing
+def test_kolmogorov_profile_second_order(oracle_mod):
+    """Fluid force (A sin(2 pi (y + 1/2) / N), 0, 0) in a periodic box: the steady
+    flow is u_x = A N^2 / (4 pi^2 nu) sin(2 pi (y + 1/2) / N), u_y = u_z = 0,
+    to second order in 1/N (the error falls by 4 per doubling).  A phase
+    without the half cell, a wrong axis or sign fail at N = 16 already."""
+    tau, A = 0.8, 1e-6
+    nu = (tau - 0.5) / 3.0
+    errs = []
+    for N in (16, 32, 64):
+        cfg = W.base_config((2, N, 2), tau, kolm_amp=A, kolm_axis=1, kolm_dir=0)
+        D = _dom(oracle_mod, cfg)
+        k = 2 * math.pi / N
+        D.step(int(14 / (nu * k * k)) + 1)
+        _, u = D.fields()
+        u = u.reshape(2, N, 2, 3)
+        ux = u[0, :, 0, 0]
+        ex = A * N * N / (4 * math.pi ** 2 * nu) * np.sin(k * (np.arange(N) + 0.5))
+        assert np.abs(u[..., 1:]).max() < 1e-8 * np.abs(ex).max()
+        assert np.abs(ux[None, :, None] - u[..., 0]).max() < 1e-8 * np.abs(ex).max()
+        errs.append(np.abs(ux - ex).max() / np.abs(ex).max())
+    assert errs[0] < 0.02
+    assert 3.7 < errs[0] / errs[1] < 4.3 and 3.7 < errs[1] / errs[2] < 4.3
+
+
+# --------------------------------------------------------------------------- slot selection
+def _counts_bruteforce(centres, radii, n, ns=10):
+    """Per (cell, particle) sample counts by direct enumeration of the sample
+    predicate: d = fl(X + o) - c, fl(fl(dx^2 + dy^2) + dz^2) < R^2 (periodic box,
+    unwrapped cell indices over each sphere's box)."""
+    o = (2 * np.arange(ns) + 1) / (2.0 * ns)
+    out = {}
+    for k, (c, R) in enumerate(zip(centres, radii)):
+        lo = np.floor(np.asarray(c) - R - 1e-6).astype(int)
+        hi = np.floor(np.asarray(c) + R + 1e-6).astype(int)
+        for X in range(lo[0], hi[0] + 1):
+            for Y in range(lo[1], hi[1] + 1):
+                for Z in range(lo[2], hi[2] + 1):
+                    dx = (X + o) - c[0]
+                    dy = (Y + o) - c[1]
+                    dz = (Z + o) - c[2]
+                    s = (dx[:, None, None] * dx[:, None, None] + dy[None, :, None] * dy[None, :, None]) \
+                        + dz[None, None, :] * dz[None, None, :]
+                    m = int(np.count_nonzero(s < R * R))
+                    if m:
+                        cell = (X % n) + n * ((Y % n) + n * (Z % n))
+                        out.setdefault(cell, []).append((m, k))
+    return out
+
+
+@pytest.mark.parametrize("ms", [1, 2, 3])
+def test_slot_selection_bruteforce(oracle_mod, ms):
+    """Per cell the max_solids entries with the largest count are kept, ties to
+    the smaller particle index, ordered by index; the rest are counted as
+    dropped.  Spheres 1 and 2 mirror each other about the centre plane of cell
+    column x = 8, so they tie there; the random spheres overlap heavily."""
+    n = 16
+    rng = np.random.default_rng(5)
+    centres = [[8.5, 8.45, 8.3], [6.2, 8.5, 8.5], [10.8, 8.5, 8.5]]
+    radii = [2.7, 3.1, 3.1]
+    for _ in range(5):
+        centres.append(list(6.0 + 5.0 * rng.random(3)))
+        radii.append(1.5 + 2.0 * rng.random())
+    D = _dom(oracle_mod, W.base_config((n, n, n), 0.8, dem_on=False, max_solids=ms),
+             W.spheres(centres, radii, 2.0))
+    D.stage_voxelize()
+    c, p, b = D.solid()
+    exp_c, exp_p, exp_b, dropped, ties = [], [], [], 0, 0
+    for cell, ents in sorted(_counts_bruteforce(centres, radii, n).items()):
+        ents.sort(key=lambda e: (-e[0], e[1]))
+        kept = sorted(ents[:ms], key=lambda e: e[1])
+        dropped += len(ents) - len(kept)
+        ties += len(ents) > ms and ents[ms - 1][0] == ents[ms][0]
+        for m, k in kept:
+            exp_c.append(cell)
+            exp_p.append(k)
+            exp_b.append(m / 1000.0)
+    assert np.array_equal(c, exp_c) and np.array_equal(p, exp_p) and np.array_equal(b, exp_b)
+    assert D.counters()["overflow"] == dropped and dropped > 0
+    if ms == 2:
+        assert ties > 0
+
+
+# --------------------------------------------------------------------------- far positions
+def test_p17_cells_of_far_positions(oracle_mod):
+    """A position of any finite size maps to its cells by the definition: per
+    axis floor((x -+ e)/h) wrapped mod n_c (periodic) or clamped (walls),
+    evaluated without integer overflow (positions of a blown-up state reach
+    1e15 and beyond)."""
+    box = (48, 40, 36)
+    bc = ["periodic"] * 4 + ["noslip"] * 2
+    pos = np.array([[5.0, 6.0, 7.0], [3.1e15, -2.7e13, 9.9e11], [-4.4e12, 8.8e10, -1.3e16],
+                    [47.9, 39.95, 35.5], [-1.0, 40.5, 18.0]])
+    radii = np.array([1.5, 1.8, 1.2, 1.9, 1.6])
+    D = _dom(oracle_mod, W.base_config(box, 0.8, bc=bc, fluid_on=False), W.spheres(pos, radii, 2.0))
+    D.set_particles(pos=pos)
+    D.stage_lists()
+    nc, h = D.dem_grid()
+    nc = [int(v) for v in nc]
+    per = [True, True, False]
+    exp = []
+    for k in range(len(pos)):
+        axes = []
+        for a in range(3):
+            lo = math.floor((pos[k, a] - radii[k]) / h[a])
+            hi = math.floor((pos[k, a] + radii[k]) / h[a])
+            cs = []
+            for t in ([lo, lo + 1.0] if hi > lo else [lo]):
+                cw = int(math.fmod(t, nc[a]) % nc[a]) if per[a] else int(min(max(t, 0), nc[a] - 1))
+                if cw not in cs:
+                    cs.append(cw)
+            axes.append(cs)
+        for x in axes[0]:
+            for y in axes[1]:
+                for z in axes[2]:
+                    exp.append(((x + nc[0] * (y + nc[1] * z)) << 32) | k)
+    assert np.array_equal(D.cells(), np.sort(np.array(exp, np.uint64)))
+
+
+# --------------------------------------------------------------------------- Jeffery orbit
+def jeffery_setup(a=8.0, b=4.0, L=80, U=0.04, tau=1.4, dens=2.0):
+    """Prolate ellipsoid (a, b, b) at the centre of an L/2 x L x L/2 channel,
+    major axis along y (Jeffery angle 0), top wall moving at U in x (shear rate
+    U/L), x and z periodic, fluid started on the linear profile.  Density ratio
+    2: with the explicit coupling of the step a neutrally buoyant body is
+    unstable (the fluid in its cells carries as much inertia as the body)."""
+    n = (L // 2, L, L // 2)
+    bc = ["periodic", "periodic", "noslip", "moving", "periodic", "periodic"]
+    wu = [[0.0] * 3 for _ in range(6)]
+    wu[3] = [U, 0.0, 0.0]
+    cfg = W.base_config(n, tau, bc=bc, wall_u=wu, n_sub=1)
+    s = math.sqrt(0.5)
+    parts = _ellipsoid([[a, b, b]], [[n[0] / 2, n[1] / 2, n[2] / 2]], [[s, 0, 0, s]], dens=dens)
+    N = n[0] * n[1] * n[2]
+    y = np.arange(N) // n[0] % n[1]
+    u = np.zeros((N, 3))
+    u[:, 0] = U / L * (y + 0.5)
+    cu = u @ CI.T
+    Wt = np.array([1 / 3] + [1 / 18] * 3 + [1 / 36] * 6 + [1 / 18] * 3 + [1 / 36] * 6)
+    f = Wt[None, :] * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * (u ** 2).sum(1)[:, None])
+    return cfg, parts, f.T.copy(), U / L
+
+
+def jeffery_angle(q):
+    """Angle of the major (body x) axis from +y towards +x in the flow plane."""
+    w, x, y, z = q
+    return math.atan2(1 - 2 * (y * y + z * z), 2 * (x * y + w * z))
+
+
+@pytest.mark.slow
+def test_p13_jeffery_rotation_rate(oracle_mod):
+    """Ellipsoid in Couette shear (Sec. 4.7): once the flow round it has formed,
+    its spin follows Jeffery's law omega_z = -gd (a^2 cos^2 th + b^2 sin^2 th) /
+    (a^2 + b^2) at its current angle th (negative: the shear turns it from +y
+    towards +x), within 5 %, at Re = gd a^2 / nu = 0.11."""
+    oracle_mod.set_threads(8)
+    a, b = 8.0, 4.0
+    cfg, parts, f0, gd = jeffery_setup(a, b)
+    D = _dom(oracle_mod, cfg, parts)
+    D.set_populations(f0)
+    D.step(200)
+    ratios = []
+    for _ in range(4):
+        D.step(50)
+        P = D.particles()
+        th = jeffery_angle(P["quat"][0])
+        wj = -gd * (a * a * math.cos(th) ** 2 + b * b * math.sin(th) ** 2) / (a * a + b * b)
+        ratios.append(P["omega"][0, 2] / wj)
+        assert abs(P["omega"][0, 0]) < 1e-6 * abs(wj) and abs(P["omega"][0, 1]) < 1e-6 * abs(wj)
+    assert 0.1 < th < 0.2
+    assert all(0.95 < r < 1.05 for r in ratios), ratios
