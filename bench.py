@@ -267,9 +267,9 @@ def precision_study(n, fraction=0.2, warmup=20, timed=100, check=200):
 
 def stream_probe(mib):
     """The device's attainable streaming rates (plain copy, read, write kernels
-    of the library), the ceiling beside the roofline's 8 TB/s."""
+    of the measurement library), the ceiling beside the roofline's 8 TB/s."""
     import torch
-    from paper_2512_04997_amd import psmdem
+    from paper_2512_04997_amd import probe
     torch.cuda.set_device(0)
     nbytes = mib << 20
     a = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -277,7 +277,7 @@ def stream_probe(mib):
     torch.cuda.synchronize()
     for grid in (1024, 4096, 16384):
         for kind, moved in (("copy", 2 * nbytes), ("read", nbytes), ("write", nbytes)):
-            ms = psmdem.stream_probe(kind, a.data_ptr(), b.data_ptr(), nbytes, grid)
+            ms = probe.stream(kind, a.data_ptr(), b.data_ptr(), nbytes, grid)
             print(json.dumps({"stream_probe": kind, "grid": grid, "bytes_moved": moved, "ms": round(ms, 4),
                               "TB_s": round(moved / (ms * 1e-3) / 1e12, 3),
                               "frac_of_peak": round(moved / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}), flush=True)

@@ -35,7 +35,11 @@
  *     allocator callback, else hipMalloc) and freed by psmdem_destroy;
  *   - work is enqueued on the HIP stream given at creation (NULL = the
  *     default stream); psmdem_step is asynchronous, every read_* call
- *     synchronises the stream first.
+ *     synchronises the stream first;
+ *   - device flags (PSMDEM_E_UNSTABLE, PSMDEM_E_CAPACITY) are raised by the
+ *     kernels and reported by psmdem_sync and by every read_* call, which
+ *     still writes its outputs (for inspection) and then returns the flag;
+ *     they stay set until a write_* call rewrites the state.
  */
 #ifndef PSMDEM_H
 #define PSMDEM_H
@@ -52,7 +56,11 @@ typedef enum {
     PSMDEM_E_INVALID = -1,   /* bad argument or configuration */
     PSMDEM_E_NOMEM = -2,     /* device allocation failed */
     PSMDEM_E_CAPACITY = -3,  /* a device list outgrew its capacity; results of the step are invalid */
-    PSMDEM_E_UNSTABLE = -4,  /* non-finite or non-positive density detected (reserved) */
+    PSMDEM_E_UNSTABLE = -4,  /* the state has blown up: a cell density that is not a positive finite
+                                number (checked by every LBM-PSM pass), or a particle centre that is not
+                                finite or lies more than one box length outside the domain (checked by
+                                every DEM predictor and every voxelisation, which then gives that
+                                particle no solid fractions) */
     PSMDEM_E_HIP = -5,       /* a HIP runtime call failed */
     PSMDEM_E_STATE = -6,     /* call not valid in the current state */
     PSMDEM_E_NODEVICE = -7   /* no gfx950 device available */
@@ -152,7 +160,8 @@ typedef struct {
     int64_t n_dropped;       /* entries beyond max_solids in a cell (dropped, Sec. 3.2.3 limit) */
     int64_t n_solid_tiles;   /* lattice tiles holding any particle */
     int64_t step;            /* coupled steps taken */
-    int64_t flags;           /* bit 0 pair capacity, bit 1 tile particle list, bit 2 neighbour list */
+    int64_t flags;           /* bit 0 pair capacity, bit 1 tile particle list, bit 2 neighbour list,
+                                bit 3 tile registrations, bit 4 unstable */
 } psmdem_counters_t;
 
 typedef struct {
@@ -179,7 +188,8 @@ void psmdem_destroy(psmdem_domain* d);
 
 /* Enqueues n coupled steps (one LBM step with n_sub DEM substeps each). */
 psmdem_status psmdem_step(psmdem_domain* d, int64_t n);
-/* Waits for the stream and reports device-side flags (PSMDEM_E_CAPACITY). */
+/* Waits for the stream and reports the device flags: PSMDEM_E_UNSTABLE, else
+ * PSMDEM_E_CAPACITY, else PSMDEM_OK. */
 psmdem_status psmdem_sync(psmdem_domain* d);
 
 /* --- stages (one stage on the current state; for per-stage checks) ------- */
@@ -236,22 +246,29 @@ psmdem_status psmdem_set_timing(psmdem_domain* d, int32_t on);
 psmdem_status psmdem_timing(psmdem_domain* d, int32_t which, double* avg_ms, int64_t* launches);
 typedef enum { PSMDEM_T_LBM = 0, PSMDEM_T_VOXEL = 1, PSMDEM_T_DEM = 2, PSMDEM_T_HYDRO = 3 } psmdem_timer;
 
+/* --- checkpoint and restore ------------------------------------------------ */
+/* The whole state of a domain as one host byte image: a header (step, AA
+ * parity, DEM buffer index) and every device block of the domain (in-place
+ * populations, particle state, both pair lists with their tangential history,
+ * the kept-list and skip state of the DEM substeps, tile lists, solid slots,
+ * counters and device flags).  A domain created from the same description and
+ * particle count that receives the image continues bit for bit as the saved
+ * one would have: n steps, a checkpoint, n more steps equal 2n steps.
+ * psmdem_read_state: *used receives the image size; with buf NULL only the
+ * size is reported (PSMDEM_OK); a buffer shorter than the image gives
+ * PSMDEM_E_INVALID.  Otherwise the image is written to buf (caller-owned host
+ * memory) and the device flags are returned as by the read_* calls.
+ * psmdem_write_state: n must be the image size and the image must come from a
+ * domain of the same layout (description and particle count), else
+ * PSMDEM_E_INVALID with nothing changed; the device flags are restored with
+ * the image. */
+psmdem_status psmdem_read_state(psmdem_domain* d, void* buf, size_t cap, size_t* used);
+psmdem_status psmdem_write_state(psmdem_domain* d, const void* buf, size_t n);
+
 /* Device bytes psmdem_create would allocate for this description and particle
  * set (the memory model used for admission by the serving loop).  Touches no
  * device. */
 psmdem_status psmdem_footprint(const psmdem_desc* desc, const psmdem_particles* parts, int64_t* bytes);
-
-/* Measurement utility, not part of the method: the device's attainable
- * streaming bandwidth, stated beside the roofline figures.  Streams `bytes`
- * (rounded down to 16-byte elements) through a plain grid-stride kernel of
- * `grid` workgroups of 256 lanes on the null stream: kind 0 copies src to dst,
- * kind 1 reads src (dst: at least 4 bytes; its first float is written only by
- * a lane whose partial sum equals 1234.5), kind 2 writes dst.  Two untimed launches, then `reps`
- * timed ones; *ms_per_launch receives their average duration (HIP events).
- * Device pointers owned by the caller.  PSMDEM_E_INVALID on a null or short
- * argument. */
-psmdem_status psmdem_stream_probe(int32_t kind, const void* src, void* dst, int64_t bytes, int32_t grid,
-                                  int32_t reps, double* ms_per_launch);
 
 /* --- ensemble serving: continuous batching of many domains ---------------- */
 /* A server advances many independent domains ("jobs") together.  Each

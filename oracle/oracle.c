@@ -57,7 +57,8 @@ struct or_domain {
     double *semi, *dens, *mass, *inertia, *rb;
     double *pos, *q, *qold, *v, *w, *vp, *wp, *a, *al;
     double *fh, *mh, *fd, *md;
-    double *fh1, *mh1, *fd1, *md1; /* per-component sums of |summand| (parity scale) */
+    double *fh1, *mh1, *fd1, *md1; /* per-component L1 norms of the summands (parity scale): per-cell
+                                      momentum-exchange terms for F_hyd, M_hyd; pair terms for F_dem, M_dem */
     /* DEM lists */
     int64_t nreg, cap_reg;
     uint64_t* reg;
@@ -569,18 +570,15 @@ static double b_weight(double beta, double tau) {
  * Omega^s; Guo forcing (G26) with the
  * (1 - B_tot) factor.  Pk receives B_k sum_i Omega^s_{i,k} c_i per slot. */
 static void collide_cell(const or_domain* D, const double f[19], int32_t nslot, const double* B,
-                         const double* uk, const double F[3], double fpost[19], double* Pk, double* Sk);
+                         const double* uk, const double F[3], double fpost[19], double* Pk);
 
 void or_collide_cell(const or_domain* D, const double f[19], int32_t nslot, const double* B,
                      const double* uk, const double F[3], double fpost[19], double* Pk) {
-    collide_cell(D, f, nslot, B, uk, F, fpost, Pk, NULL);
+    collide_cell(D, f, nslot, B, uk, F, fpost, Pk);
 }
 
-/* Sk (optional) receives per slot B_k sum_i (|f_ibar| + |feq_ibar| + |f_i| + |feq_i(u_k)|) |c_i|:
- * the magnitude of the population-level summands of the momentum exchange,
- * the scale of its floating-point rounding */
 static void collide_cell(const or_domain* D, const double f[19], int32_t nslot, const double* B,
-                         const double* uk, const double F[3], double fpost[19], double* Pk, double* Sk) {
+                         const double* uk, const double F[3], double fpost[19], double* Pk) {
     if (W[0] == 0.0) lattice_init();
     double tau = D->d.tau;
     double rho = 0.0, m[3] = {0, 0, 0};
@@ -639,7 +637,7 @@ static void collide_cell(const or_domain* D, const double f[19], int32_t nslot, 
     for (int s = 0; s < nslot; ++s) {
         double feqk[19];
         or_feq(rho, uk + 3 * s, feqk);
-        double P[3] = {0, 0, 0}, A[3] = {0, 0, 0};
+        double P[3] = {0, 0, 0};
         for (int i = 0; i < 19; ++i) {
             int o = OPP[i];
             double Os = (f[o] - feq[o]) - (f[i] - feqk[i]);
@@ -647,14 +645,8 @@ static void collide_cell(const or_domain* D, const double f[19], int32_t nslot, 
             P[0] += Os * CX[i];
             P[1] += Os * CY[i];
             P[2] += Os * CZ[i];
-            double mag = fabs(f[o]) + fabs(feq[o]) + fabs(f[i]) + fabs(feqk[i]);
-            A[0] += mag * abs(CX[i]);
-            A[1] += mag * abs(CY[i]);
-            A[2] += mag * abs(CZ[i]);
         }
         for (int k = 0; k < 3; ++k) Pk[3 * s + k] = B[s] * P[k];
-        if (Sk)
-            for (int k = 0; k < 3; ++k) Sk[3 * s + k] = B[s] * A[k];
     }
 }
 
@@ -682,8 +674,6 @@ void or_stage_lbm(or_domain* D) {
     const int ms = D->d.max_solids;
     double* Pcell = (double*)xcalloc((size_t)(N * ms * 3), sizeof(double));
     double* Tcell = (double*)xcalloc((size_t)(N * ms * 3), sizeof(double));
-    double* Scell = (double*)xcalloc((size_t)(N * ms * 3), sizeof(double));
-    double* Ucell = (double*)xcalloc((size_t)(N * ms * 3), sizeof(double));
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < N; ++c) {
         int x = (int)(c % nx), y = (int)((c / nx) % ny), z = (int)(c / ((int64_t)nx * ny));
@@ -706,20 +696,15 @@ void or_stage_lbm(or_domain* D) {
             }
             ++nsl;
         }
-        double P[12], Sc[12];
-        collide_cell(D, f, nsl, B, uk, F, fp, P, Sc);
+        double P[12];
+        collide_cell(D, f, nsl, B, uk, F, fp, P);
         for (int s = 0; s < nsl; ++s) {
             double T[3];
             const double* d = rjk + 3 * s;
-            const double* a = Sc + 3 * s;
             cross3(d, P + 3 * s, T);
-            double U[3] = {fabs(d[1]) * a[2] + fabs(d[2]) * a[1], fabs(d[2]) * a[0] + fabs(d[0]) * a[2],
-                           fabs(d[0]) * a[1] + fabs(d[1]) * a[0]};
             for (int k = 0; k < 3; ++k) {
                 Pcell[(c * ms + s) * 3 + k] = P[3 * s + k];
                 Tcell[(c * ms + s) * 3 + k] = T[k];
-                Scell[(c * ms + s) * 3 + k] = a[k];
-                Ucell[(c * ms + s) * 3 + k] = U[k];
             }
         }
         for (int i = 0; i < 19; ++i) {
@@ -754,16 +739,14 @@ void or_stage_lbm(or_domain* D) {
             for (int k = 0; k < 3; ++k) {
                 D->fh[3 * p + k] -= Pcell[(c * ms + s) * 3 + k];
                 D->mh[3 * p + k] -= Tcell[(c * ms + s) * 3 + k];
-                D->fh1[3 * p + k] += Scell[(c * ms + s) * 3 + k];
-                D->mh1[3 * p + k] += Ucell[(c * ms + s) * 3 + k];
+                D->fh1[3 * p + k] += fabs(Pcell[(c * ms + s) * 3 + k]);
+                D->mh1[3 * p + k] += fabs(Tcell[(c * ms + s) * 3 + k]);
             }
             ++s;
         }
     }
     free(Pcell);
     free(Tcell);
-    free(Scell);
-    free(Ucell);
     double* t = D->f;
     D->f = D->fn;
     D->fn = t;

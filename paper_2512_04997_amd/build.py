@@ -1,4 +1,5 @@
-"""Builds libpsmdem.so (HIP, gfx950) in-tree with hipcc.
+"""Builds libpsmdem.so (HIP, gfx950) in-tree with hipcc, and libpsmprobe.so,
+the streaming-bandwidth measurement utility kept apart from the method.
 
 Every HIP source is compiled for gfx950 only, with packed-FP32 instruction
 generation disabled.  The DEM and voxelisation sources are compiled without
@@ -15,6 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libpsmdem.so")
+PROBE_LIB = os.path.join(PKG, "libpsmprobe.so")
 ARCH = "gfx950"
 
 SOURCES = [
@@ -24,8 +26,8 @@ SOURCES = [
     ("lbm.hip", []),
     ("psmdem.hip", []),
     ("server.hip", []),
-    ("probe.hip", []),
 ]
+PROBE_SOURCES = [("probe.hip", [])]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -50,19 +52,25 @@ def _compile(src, extra, verbose):
     return obj
 
 
-def build(verbose=False, jobs=None):
-    os.makedirs(BUILD, exist_ok=True)
-    jobs = jobs or min(len(SOURCES), os.cpu_count() or 4, 8)
-    with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s[0], s[1], verbose), SOURCES))
-    tmp = LIB + ".tmp"
+def _link(objs, lib, verbose):
+    tmp = lib + ".tmp"
     cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(verbose=False, jobs=None):
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = SOURCES + PROBE_SOURCES
+    jobs = jobs or min(len(srcs), os.cpu_count() or 4, 8)
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s[0], s[1], verbose), srcs))
+    _link(objs[:len(SOURCES)], LIB, verbose)
+    _link(objs[len(SOURCES):], PROBE_LIB, verbose)
     return LIB
 
 

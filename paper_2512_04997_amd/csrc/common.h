@@ -29,6 +29,11 @@
 #define PSM_FLAG_TILE 2
 #define PSM_FLAG_NEIGH 4
 #define PSM_FLAG_VREG 8
+#define PSM_FLAG_CAPACITY_MASK 15ull
+// a cell density that is not a positive finite number (LBM), or a particle
+// centre that is not finite or lies more than one box length outside the
+// domain (DEM predictor, voxelisation): the state has blown up
+#define PSM_FLAG_UNSTABLE 16
 
 // ---------------------------------------------------------------------------
 // D3Q19 (Sec. 2.3): velocities, weights, opposite directions

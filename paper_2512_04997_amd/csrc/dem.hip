@@ -97,25 +97,35 @@ struct AxCells {
     int n[3];
 };
 
+// Cell t (an integer-valued double: the floor of a coordinate over h) wrapped
+// mod n on a periodic axis or clamped to [0, n-1] on a walled one.  The
+// arithmetic stays in double until the result is in range, so a position of
+// any finite size (a blown-up state) maps to a cell; NaN maps to cell 0.
+__device__ inline int wrap_cell(double t, int n, int periodic) {
+    if (t != t) return 0;
+    const double dn = (double)n;
+    if (periodic) {
+        // one period off at most for a wrapped position (selects, exact);
+        // any other offset takes the remainder
+        double r = t < 0.0 ? t + dn : (t >= dn ? t - dn : t);
+        if (r < 0.0 || r >= dn) {
+            r = fmod(t, dn);
+            if (r < 0.0) r += dn;
+        }
+        return (int)r;
+    }
+    return t < 0.0 ? 0 : (t > dn - 1.0 ? n - 1 : (int)t);
+}
+
 __device__ inline void axis_cells_at(const DemArgs& A, const double pos[3], const double e[3], AxCells& r) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         double x = pos[a];
-        int lo = (int)floor((x - e[a]) / A.h[a]);
-        int hi = (int)floor((x + e[a]) / A.h[a]);
-        int c0 = lo, c1 = lo + 1 <= hi ? lo + 1 : lo;
-        if (A.g.periodic[a]) {
-            // one period off at most for a wrapped position (selects); any
-            // other offset takes the integer remainder
-            const int n = A.nc[a];
-            c0 = c0 < 0 && c0 >= -n ? c0 + n : (c0 >= n && c0 < 2 * n ? c0 - n : c0);
-            c1 = c1 < 0 && c1 >= -n ? c1 + n : (c1 >= n && c1 < 2 * n ? c1 - n : c1);
-            if (c0 < 0 || c0 >= n) c0 = ((c0 % n) + n) % n;
-            if (c1 < 0 || c1 >= n) c1 = ((c1 % n) + n) % n;
-        } else {
-            c0 = c0 < 0 ? 0 : (c0 > A.nc[a] - 1 ? A.nc[a] - 1 : c0);
-            c1 = c1 < 0 ? 0 : (c1 > A.nc[a] - 1 ? A.nc[a] - 1 : c1);
-        }
+        const double lo = floor((x - e[a]) / A.h[a]);
+        const double hi = floor((x + e[a]) / A.h[a]);
+        const int per = A.g.periodic[a];
+        int c0 = wrap_cell(lo, A.nc[a], per);
+        int c1 = hi > lo ? wrap_cell(lo + 1.0, A.nc[a], per) : c0;
         if (c1 < c0) {
             int t = c0;
             c0 = c1;
@@ -705,6 +715,10 @@ __device__ inline void pred_core(const DemArgs& A, int k, double dt, int write_k
         vp[c] = s.v[c] + dt * s.a[c];
         wp[c] = s.w[c] + dt * s.al[c];
     }
+    // a centre that is not finite or more than a box length outside: blown up
+    if (!(xn[0] >= -A.L[0] && xn[0] < 2.0 * A.L[0] && xn[1] >= -A.L[1] && xn[1] < 2.0 * A.L[1] &&
+          xn[2] >= -A.L[2] && xn[2] < 2.0 * A.L[2]))
+        atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_UNSTABLE);
     double r1[4], qs[4], qm[4], r2[4], qn[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) q0[c] = s.q[c];

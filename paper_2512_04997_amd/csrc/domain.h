@@ -223,6 +223,7 @@ struct psmdem_domain {
         A.kin = p.kin;
         A.np = np;
         A.ms = d.max_solids;
+        A.flags = &ctr->flags;
         return A;
     }
 

@@ -17,6 +17,7 @@ struct LbmArgs {
     int np;
     int ms;
     double L[3];
+    unsigned long long* flags;  // device flags word (PSM_FLAG_UNSTABLE raised on a non-positive density)
 };
 
 // storage: 0 double, 1 float, 2 bf16, 3 fp16 (psmdem_precision)

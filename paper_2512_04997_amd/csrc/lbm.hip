@@ -117,9 +117,10 @@ __device__ inline C cdot(int i, C x, C y, C z) {
 // omega_m: post_p = g_p - a neq_p - b neq_pbar with a = (omega + omega_m)/2,
 // b = (omega - omega_m)/2 (b = 0 for BGK, which leaves BGK's arithmetic).  The
 // Guo source's odd part w 3 c.F takes 1 - omega_m/2, its even part 1 - omega/2.
+// Returns the cell density.
 template <typename C, int MS>
-__device__ inline void collide(const C* g, C* out, C omega, C omega_m, bool forcing, C Fx, C Fy, C Fz, int nk,
-                               const C* B, const C (*uk)[3], C (*Pk)[3]) {
+__device__ inline C collide(const C* g, C* out, C omega, C omega_m, bool forcing, C Fx, C Fy, C Fz, int nk,
+                            const C* B, const C (*uk)[3], C (*Pk)[3]) {
     C drho, jx, jy, jz;
     moments(g, drho, jx, jy, jz);
     const C rho = (C)1 + drho;
@@ -204,6 +205,7 @@ __device__ inline void collide(const C* g, C* out, C omega, C omega_m, bool forc
         out[p] = op;
         out[q] = oq;
     }
+    return rho;
 }
 
 // Per-axis neighbour offsets (wrapped on periodic axes) and wall flags of a
@@ -454,6 +456,7 @@ __device__ void lbm_tile(const LbmArgs& A, const long long t, double* kin_s, dou
         for (int a = 0; a < 3; ++a) aP[s][a] = aT[s][a] = 0.0;
     }
 
+    bool bad = false;  // a density of this lane's cells is not a positive finite number
 #pragma unroll 1
     for (int lz = 0; lz < PSM_TZ; ++lz) {
         const int z = tz * PSM_TZ + lz;
@@ -525,7 +528,8 @@ __device__ void lbm_tile(const LbmArgs& A, const long long t, double* kin_s, dou
                     }
                 }
             }
-            collide<C, MS>(g, out, omega, omega_m, forcing, Fx, Fy, Fz, nk, B, uk, Pk);
+            const C rho = collide<C, MS>(g, out, omega, omega_m, forcing, Fx, Fy, Fz, nk, B, uk, Pk);
+            bad = bad || !(rho > (C)0 && rho < (C)1e30);
             if (plain && !row_xw)
                 store_all_plain<S, C, ODD, false>(A, f, N, (unsigned)cell, ax, ay, az, out,
                                                   std::make_integer_sequence<int, 19>{});
@@ -581,6 +585,7 @@ __device__ void lbm_tile(const LbmArgs& A, const long long t, double* kin_s, dou
             }
         }
     }
+    if (__ballot(bad) && lane == 0 && A.flags) atomicOr(A.flags, (unsigned long long)PSM_FLAG_UNSTABLE);
     if (MS > 0) {
 #pragma unroll
         for (int s = 0; s < MS; ++s)

@@ -1,10 +1,11 @@
-// probe.hip -- attainable streaming bandwidth of the device (a measurement
-// utility beside the roofline figures, not part of the method): plain
-// grid-stride copy, read and write kernels over 16-byte elements, four
-// independent accesses per lane per iteration.
+// probe.hip -- libpsmprobe.so (include/psmprobe.h): attainable streaming
+// bandwidth of the device, a measurement utility beside the roofline figures
+// and kept out of the method's library: plain grid-stride copy, read and write
+// kernels over 16-byte elements, four independent accesses per lane per
+// iteration.
 #include <hip/hip_runtime.h>
 
-#include "common.h"
+#include "psmprobe.h"
 
 namespace {
 
@@ -47,12 +48,15 @@ __global__ __launch_bounds__(256) void k_probe_write(float4* __restrict__ b, lon
 
 }  // namespace
 
-extern "C" psmdem_status psmdem_stream_probe(int32_t kind, const void* src, void* dst, int64_t bytes, int32_t grid,
-                                             int32_t reps, double* ms_per_launch) {
-    if (!ms_per_launch || bytes < 16 || grid < 1 || reps < 1 || kind < 0 || kind > 2 || !dst || (kind != 2 && !src)) {
-        psm_set_error("stream probe: invalid arguments");
-        return PSMDEM_E_INVALID;
-    }
+#define PROBE_CHECK(call)                      \
+    do {                                       \
+        if ((call) != hipSuccess) return -5;   \
+    } while (0)
+
+extern "C" int32_t psmprobe_stream(int32_t kind, const void* src, void* dst, int64_t bytes, int32_t grid,
+                                   int32_t reps, double* ms_per_launch) {
+    if (!ms_per_launch || bytes < 16 || grid < 1 || reps < 1 || kind < 0 || kind > 2 || !dst || (kind != 2 && !src))
+        return -1;
     const long long n = bytes / 16;
     const float4* a = (const float4*)src;
     float4* b = (float4*)dst;
@@ -62,18 +66,18 @@ extern "C" psmdem_status psmdem_stream_probe(int32_t kind, const void* src, void
         else k_probe_write<<<grid, 256>>>(b, n);
     };
     hipEvent_t e0, e1;
-    PSM_CHECK(hipEventCreate(&e0));
-    PSM_CHECK(hipEventCreate(&e1));
+    PROBE_CHECK(hipEventCreate(&e0));
+    PROBE_CHECK(hipEventCreate(&e1));
     for (int w = 0; w < 2; ++w) launch();
-    PSM_CHECK(hipGetLastError());
-    PSM_CHECK(hipEventRecord(e0, 0));
+    PROBE_CHECK(hipGetLastError());
+    PROBE_CHECK(hipEventRecord(e0, 0));
     for (int r = 0; r < reps; ++r) launch();
-    PSM_CHECK(hipEventRecord(e1, 0));
-    PSM_CHECK(hipEventSynchronize(e1));
+    PROBE_CHECK(hipEventRecord(e1, 0));
+    PROBE_CHECK(hipEventSynchronize(e1));
     float ms = 0.f;
-    PSM_CHECK(hipEventElapsedTime(&ms, e0, e1));
-    PSM_CHECK(hipEventDestroy(e0));
-    PSM_CHECK(hipEventDestroy(e1));
+    PROBE_CHECK(hipEventElapsedTime(&ms, e0, e1));
+    PROBE_CHECK(hipEventDestroy(e0));
+    PROBE_CHECK(hipEventDestroy(e1));
     *ms_per_launch = (double)ms / reps;
-    return PSMDEM_OK;
+    return 0;
 }

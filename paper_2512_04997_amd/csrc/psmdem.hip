@@ -600,15 +600,36 @@ extern "C" psmdem_status psmdem_step(psmdem_domain* d, int64_t n) {
     return PSMDEM_OK;
 }
 
+// Waits for the stream and reports the device flags: PSMDEM_E_UNSTABLE when
+// the state has blown up, else PSMDEM_E_CAPACITY when a device list outgrew
+// its capacity.  The flags stay set until a write_* call rewrites the state.
 static psmdem_status sync_flags(psmdem_domain* d) {
     PSM_CHECK(hipStreamSynchronize(d->s));
     DevCounters c{};
     PSM_CHECK(hipMemcpy(&c, d->ctr, sizeof c, hipMemcpyDeviceToHost));
-    if (c.flags) {
+    if (c.flags & PSM_FLAG_UNSTABLE) {
+        psm_set_error("unstable: a cell density is not a positive finite number or a particle centre is not finite "
+                      "or lies more than one box length outside the domain (flags 0x%llx)",
+                      (unsigned long long)c.flags);
+        return PSMDEM_E_UNSTABLE;
+    }
+    if (c.flags & PSM_FLAG_CAPACITY_MASK) {
         psm_set_error("device capacity exceeded (flags 0x%llx: 1 pairs, 2 tile list, 4 neighbours, 8 tile registrations)",
                       (unsigned long long)c.flags);
         return PSMDEM_E_CAPACITY;
     }
+    return PSMDEM_OK;
+}
+
+// a status of sync_flags that stops a read (the device flags do not: the
+// outputs are still written and the flag is returned)
+static bool read_fails(psmdem_status st) { return st != PSMDEM_OK && st != PSMDEM_E_CAPACITY && st != PSMDEM_E_UNSTABLE; }
+
+// the state is being rewritten: the device flags of the old one are dropped
+static psmdem_status clear_flags(psmdem_domain* d) {
+    PSM_CHECK(hipStreamSynchronize(d->s));
+    const unsigned long long z = 0;
+    PSM_CHECK(hipMemcpy(&d->ctr->flags, &z, sizeof z, hipMemcpyHostToDevice));
     return PSMDEM_OK;
 }
 
@@ -677,8 +698,8 @@ static void host_face(const psmdem_domain* D, int x, int y, int z, int dx, int d
 
 extern "C" psmdem_status psmdem_read_populations(psmdem_domain* d, double* fout) {
     if (!d || !fout) return PSMDEM_E_INVALID;
-    psmdem_status st = sync_flags(d);
-    if (st != PSMDEM_OK && st != PSMDEM_E_CAPACITY) return st;
+    const psmdem_status st = sync_flags(d);
+    if (read_fails(st)) return st;
     const long long N = d->N;
     const size_t sb = storage_bytes(d->prec);
     std::vector<unsigned char> raw(19 * (size_t)N * sb);
@@ -700,12 +721,12 @@ extern "C" psmdem_status psmdem_read_populations(psmdem_domain* d, double* fout)
             fout[(long long)i * N + c] = gi + WT(i);
         }
     }
-    return PSMDEM_OK;
+    return st;
 }
 
 extern "C" psmdem_status psmdem_write_populations(psmdem_domain* d, const double* fin) {
     if (!d || !fin) return PSMDEM_E_INVALID;
-    PSM_CHECK(hipStreamSynchronize(d->s));
+    if (psmdem_status cs = clear_flags(d)) return cs;
     const long long N = d->N;
     const size_t sb = storage_bytes(d->prec);
     std::vector<unsigned char> raw(19 * (size_t)N * sb);
@@ -733,8 +754,8 @@ extern "C" psmdem_status psmdem_read_fields(psmdem_domain* d, double* rho, doubl
     if (!d) return PSMDEM_E_INVALID;
     const long long N = d->N;
     std::vector<double> f(19 * (size_t)N);
-    psmdem_status st = psmdem_read_populations(d, f.data());
-    if (st) return st;
+    const psmdem_status st = psmdem_read_populations(d, f.data());
+    if (read_fails(st)) return st;
     for (long long c = 0; c < N; ++c) {
         double r = 0, m[3] = {0, 0, 0};
         for (int i = 0; i < 19; ++i) {
@@ -755,7 +776,7 @@ extern "C" psmdem_status psmdem_read_fields(psmdem_domain* d, double* rho, doubl
         if (u)
             for (int k = 0; k < 3; ++k) u[3 * c + k] = (m[k] + 0.5 * F[k]) / r;
     }
-    return PSMDEM_OK;
+    return st;
 }
 
 // ---------------------------------------------------------------------------
@@ -765,17 +786,17 @@ extern "C" psmdem_status psmdem_read_particles(psmdem_domain* d, double* pos, do
                                               double* acc, double* alpha, double* f_hyd, double* m_hyd, double* f_dem,
                                               double* m_dem) {
     if (!d) return PSMDEM_E_INVALID;
-    psmdem_status st = sync_flags(d);
-    if (st != PSMDEM_OK && st != PSMDEM_E_CAPACITY) return st;
+    const psmdem_status st = sync_flags(d);
+    if (read_fails(st)) return st;
     size_t n3 = sizeof(double) * 3 * d->np;
-    if (d->np == 0) return PSMDEM_OK;
+    if (d->np == 0) return st;
     struct { double* h; double* dv; size_t n; } m[] = {
         {pos, d->p.pos, n3}, {quat, d->p.q, sizeof(double) * 4 * d->np}, {vel, d->p.v, n3}, {omega, d->p.w, n3},
         {acc, d->p.a, n3}, {alpha, d->p.al, n3}, {f_hyd, d->p.fh, n3}, {m_hyd, d->p.mh, n3},
         {f_dem, d->p.fd, n3}, {m_dem, d->p.md, n3}};
     for (auto& x : m)
         if (x.h) PSM_CHECK(hipMemcpy(x.h, x.dv, x.n, hipMemcpyDeviceToHost));
-    return PSMDEM_OK;
+    return st;
 }
 
 extern "C" psmdem_status psmdem_write_particles(psmdem_domain* d, const double* pos, const double* quat,
@@ -783,7 +804,7 @@ extern "C" psmdem_status psmdem_write_particles(psmdem_domain* d, const double* 
                                                const double* alpha, const double* f_hyd, const double* m_hyd) {
     if (!d) return PSMDEM_E_INVALID;
     if (int rc = forget_fused_list(d)) return (psmdem_status)rc;
-    PSM_CHECK(hipStreamSynchronize(d->s));
+    if (psmdem_status cs = clear_flags(d)) return cs;
     if (d->np == 0) return PSMDEM_OK;
     size_t n3 = sizeof(double) * 3 * d->np;
     struct { const double* h; double* dv; size_t n; } m[] = {
@@ -797,11 +818,12 @@ extern "C" psmdem_status psmdem_write_particles(psmdem_domain* d, const double* 
 
 extern "C" psmdem_status psmdem_read_predicted(psmdem_domain* d, double* vp, double* wp) {
     if (!d) return PSMDEM_E_INVALID;
-    PSM_CHECK(hipStreamSynchronize(d->s));
-    if (d->np == 0) return PSMDEM_OK;
+    const psmdem_status st = sync_flags(d);
+    if (read_fails(st)) return st;
+    if (d->np == 0) return st;
     if (vp) PSM_CHECK(hipMemcpy(vp, d->p.vp, sizeof(double) * 3 * d->np, hipMemcpyDeviceToHost));
     if (wp) PSM_CHECK(hipMemcpy(wp, d->p.wp, sizeof(double) * 3 * d->np, hipMemcpyDeviceToHost));
-    return PSMDEM_OK;
+    return st;
 }
 
 extern "C" psmdem_status psmdem_write_predicted(psmdem_domain* d, const double* vp, const double* wp) {
@@ -823,22 +845,22 @@ static psmdem_status pair_count(psmdem_domain* d, int64_t* n) {
 
 extern "C" psmdem_status psmdem_read_pairs(psmdem_domain* d, int64_t cap, uint64_t* keys, double* hist, int64_t* n) {
     if (!d || !n) return PSMDEM_E_INVALID;
-    PSM_CHECK(hipStreamSynchronize(d->s));
+    const psmdem_status st = sync_flags(d);
+    if (read_fails(st)) return st;
     int64_t np_ = 0;
-    psmdem_status st = pair_count(d, &np_);
-    if (st) return st;
+    if (psmdem_status pc = pair_count(d, &np_)) return pc;
     *n = np_;
     int64_t m = std::min<int64_t>(std::min<int64_t>(np_, cap), d->pair_cap);
     if (m > 0 && keys) PSM_CHECK(hipMemcpy(keys, d->pairs[d->cur], sizeof(uint64_t) * m, hipMemcpyDeviceToHost));
     if (m > 0 && hist) PSM_CHECK(hipMemcpy(hist, d->hist[d->cur], sizeof(double) * 3 * m, hipMemcpyDeviceToHost));
-    return PSMDEM_OK;
+    return st;
 }
 
 extern "C" psmdem_status psmdem_write_pairs(psmdem_domain* d, int64_t n, const uint64_t* keys, const double* hist) {
     if (!d || n < 0 || (n > 0 && (!keys || !hist))) return PSMDEM_E_INVALID;
     if (n > d->pair_cap) { psm_set_error("pair list exceeds the capacity"); return PSMDEM_E_CAPACITY; }
     if (int rc = forget_fused_list(d)) return (psmdem_status)rc;
-    PSM_CHECK(hipStreamSynchronize(d->s));
+    if (psmdem_status cs = clear_flags(d)) return cs;
     // rebuild row offsets from the sorted keys
     std::vector<int> row(d->np + 1, 0);
     for (int64_t s = 0; s < n; ++s) {
@@ -861,10 +883,10 @@ extern "C" psmdem_status psmdem_write_pairs(psmdem_domain* d, int64_t n, const u
 extern "C" psmdem_status psmdem_read_contacts(psmdem_domain* d, int64_t cap, uint64_t* keys, double* force, double* m_i,
                                              double* m_j, int64_t* n) {
     if (!d || !n) return PSMDEM_E_INVALID;
-    PSM_CHECK(hipStreamSynchronize(d->s));
+    const psmdem_status st = sync_flags(d);
+    if (read_fails(st)) return st;
     int64_t np_ = 0;
-    psmdem_status st = pair_count(d, &np_);
-    if (st) return st;
+    if (psmdem_status pc = pair_count(d, &np_)) return pc;
     np_ = std::min<int64_t>(np_, d->pair_cap);
     std::vector<uint64_t> k(np_);
     std::vector<unsigned char> ic(np_);
@@ -890,14 +912,15 @@ extern "C" psmdem_status psmdem_read_contacts(psmdem_domain* d, int64_t cap, uin
         ++m;
     }
     *n = m;
-    return PSMDEM_OK;
+    return st;
 }
 
 extern "C" psmdem_status psmdem_read_cells(psmdem_domain* d, int64_t cap, uint64_t* keys, int64_t* n) {
     if (!d || !n) return PSMDEM_E_INVALID;
-    PSM_CHECK(hipStreamSynchronize(d->s));
+    const psmdem_status st = sync_flags(d);
+    if (read_fails(st)) return st;
     *n = 0;
-    if (d->np == 0) return PSMDEM_OK;
+    if (d->np == 0) return st;
     std::vector<int> start(d->ncell + 1);
     PSM_CHECK(hipMemcpy(start.data(), d->cell_start, sizeof(int) * (d->ncell + 1), hipMemcpyDeviceToHost));
     long long tot = std::min<long long>(start[d->ncell], d->reg_cap);
@@ -910,15 +933,16 @@ extern "C" psmdem_status psmdem_read_cells(psmdem_domain* d, int64_t cap, uint64
             ++m;
         }
     *n = m;
-    return PSMDEM_OK;
+    return st;
 }
 
 extern "C" psmdem_status psmdem_read_solid(psmdem_domain* d, int64_t cap, uint32_t* cell, uint32_t* pid, double* beta,
                                           int64_t* n) {
     if (!d || !n) return PSMDEM_E_INVALID;
-    PSM_CHECK(hipStreamSynchronize(d->s));
+    const psmdem_status st = sync_flags(d);
+    if (read_fails(st)) return st;
     *n = 0;
-    if (!d->voxelized) return PSMDEM_OK;
+    if (!d->voxelized) return st;
     const GeoArgs& g = d->geo;
     const long long plane = g.ntiles * (long long)PSM_TILE;
     const int ms = d->d.max_solids;
@@ -952,7 +976,7 @@ extern "C" psmdem_status psmdem_read_solid(psmdem_domain* d, int64_t cap, uint32
         }
     }
     *n = m;
-    return PSMDEM_OK;
+    return st;
 }
 
 extern "C" psmdem_status psmdem_counters(psmdem_domain* d, psmdem_counters_t* out) {
@@ -1000,6 +1024,98 @@ extern "C" psmdem_status psmdem_info(psmdem_domain* d, psmdem_info_t* out) {
     out->tile[0] = PSM_TX;
     out->tile[1] = PSM_TY;
     out->tile[2] = PSM_TZ;
+    return PSMDEM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// checkpoint: a header, then every device block of the domain in allocation
+// order (the in-place populations with their parity, particle state, both
+// pair lists and histories, the kept-list and skip state, tile lists, slots,
+// counters and flags), so a restored domain continues bit for bit
+// ---------------------------------------------------------------------------
+namespace {
+struct StateHeader {
+    char magic[8];          // "PSMDEMS1"
+    uint64_t layout;        // FNV-1a of the block sizes and the domain shape
+    uint64_t nblocks;
+    uint64_t payload;       // bytes of the blocks after the header
+    int64_t step;
+    int64_t dem_sub;
+    int32_t cur;
+    int32_t voxelized;
+};
+const char kStateMagic[8] = {'P', 'S', 'M', 'D', 'E', 'M', 'S', '1'};
+
+uint64_t fnv(uint64_t h, const void* p, size_t n) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    return h;
+}
+
+uint64_t state_layout(const psmdem_domain* d) {
+    uint64_t h = 14695981039346656037ull;
+    const int64_t shape[8] = {d->d.nx, d->d.ny, d->d.nz, d->np, d->prec, d->nsub, d->d.max_solids,
+                              (int64_t)d->blocks.size()};
+    h = fnv(h, shape, sizeof shape);
+    for (const auto& b : d->blocks) {
+        const uint64_t n = b.second;
+        h = fnv(h, &n, sizeof n);
+    }
+    return h;
+}
+}  // namespace
+
+extern "C" psmdem_status psmdem_read_state(psmdem_domain* d, void* buf, size_t cap, size_t* used) {
+    if (!d || !used) { psm_set_error("invalid arguments"); return PSMDEM_E_INVALID; }
+    const size_t need = sizeof(StateHeader) + d->bytes;
+    *used = need;
+    if (!buf) return PSMDEM_OK;
+    if (cap < need) {
+        psm_set_error("state buffer holds %zu bytes, %zu needed", cap, need);
+        return PSMDEM_E_INVALID;
+    }
+    const psmdem_status st = sync_flags(d);
+    if (read_fails(st)) return st;
+    StateHeader h{};
+    memcpy(h.magic, kStateMagic, 8);
+    h.layout = state_layout(d);
+    h.nblocks = d->blocks.size();
+    h.payload = d->bytes;
+    h.step = d->step;
+    h.dem_sub = d->dem_sub;
+    h.cur = d->cur;
+    h.voxelized = d->voxelized ? 1 : 0;
+    unsigned char* o = (unsigned char*)buf;
+    memcpy(o, &h, sizeof h);
+    o += sizeof h;
+    for (const auto& b : d->blocks) {
+        PSM_CHECK(hipMemcpy(o, b.first, b.second, hipMemcpyDeviceToHost));
+        o += b.second;
+    }
+    return st;
+}
+
+extern "C" psmdem_status psmdem_write_state(psmdem_domain* d, const void* buf, size_t n) {
+    if (!d || !buf) { psm_set_error("invalid arguments"); return PSMDEM_E_INVALID; }
+    StateHeader h{};
+    if (n < sizeof h) { psm_set_error("state buffer too short"); return PSMDEM_E_INVALID; }
+    memcpy(&h, buf, sizeof h);
+    if (memcmp(h.magic, kStateMagic, 8) != 0) { psm_set_error("not a psmdem state"); return PSMDEM_E_INVALID; }
+    if (h.layout != state_layout(d) || h.nblocks != d->blocks.size() || h.payload != d->bytes ||
+        n != sizeof h + d->bytes) {
+        psm_set_error("the state was saved from a domain of another description or particle count");
+        return PSMDEM_E_INVALID;
+    }
+    PSM_CHECK(hipStreamSynchronize(d->s));
+    const unsigned char* in = (const unsigned char*)buf + sizeof h;
+    for (const auto& b : d->blocks) {
+        PSM_CHECK(hipMemcpy(b.first, in, b.second, hipMemcpyHostToDevice));
+        in += b.second;
+    }
+    d->step = h.step;
+    d->dem_sub = h.dem_sub;
+    d->cur = h.cur;
+    d->voxelized = h.voxelized != 0;
     return PSMDEM_OK;
 }
 

@@ -54,11 +54,27 @@ __device__ inline void half_extents(const VoxArgs& A, int k, double e[3]) {
     }
 }
 
-// lattice box of particle k: unwrapped lo..hi per axis, clamped on walled axes
-__device__ inline void lattice_box(const VoxArgs& A, int k, int lo[3], int hi[3]) {
+// lattice box of particle k: unwrapped lo..hi per axis, clamped on walled
+// axes.  A centre that is not finite or lies more than one box length outside
+// the domain (a blown-up state) gets an empty box (hi < lo on every axis) and
+// returns true; every other box lies within [-1.5 n - 1, 2.5 n + 1) per axis
+// (the half extent stays below n / 2, checked at creation).
+__device__ inline bool lattice_box(const VoxArgs& A, int k, int lo[3], int hi[3]) {
     double e[3];
     half_extents(A, k, e);
     const int n[3] = {A.g.nx, A.g.ny, A.g.nz};
+    bool far = false;
+    for (int a = 0; a < 3; ++a) {
+        const double c = A.p.pos[3 * k + a];
+        far = far || !(c >= -(double)n[a] && c < 2.0 * (double)n[a]);
+    }
+    if (far) {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = 0;
+            hi[a] = -1;
+        }
+        return true;
+    }
     for (int a = 0; a < 3; ++a) {
         double E = e[a] + 1e-6;
         if (A.sf_method == 1) E += A.Rc;
@@ -70,31 +86,29 @@ __device__ inline void lattice_box(const VoxArgs& A, int k, int lo[3], int hi[3]
             hi[a] = hi[a] > n[a] - 1 ? n[a] - 1 : hi[a];
         }
     }
+    return false;
 }
 
-// distinct tile indices along one axis for the wrapped cell range lo..hi
+// distinct tile indices along one axis for the cell range lo..hi (unwrapped
+// on a periodic axis: walked tile by tile in wrapped coordinates)
 __device__ inline int axis_tiles(int lo, int hi, int n, int T, int periodic, int* out) {
     int cnt = 0;
-    int seg[2][2];
-    int ns = 0;
     if (hi < lo) return 0;
     if (!periodic) {
-        seg[ns][0] = lo; seg[ns][1] = hi; ++ns;
-    } else if (lo < 0) {
-        seg[ns][0] = lo + n; seg[ns][1] = n - 1; ++ns;
-        seg[ns][0] = 0; seg[ns][1] = hi; ++ns;
-    } else if (hi >= n) {
-        seg[ns][0] = lo; seg[ns][1] = n - 1; ++ns;
-        seg[ns][0] = 0; seg[ns][1] = hi - n; ++ns;
-    } else {
-        seg[ns][0] = lo; seg[ns][1] = hi; ++ns;
+        for (int t = lo / T; t <= hi / T && cnt < VOX_AXIS_MAX; ++t) out[cnt++] = t;
+        return cnt;
     }
-    for (int s = 0; s < ns; ++s)
-        for (int t = seg[s][0] / T; t <= seg[s][1] / T && cnt < VOX_AXIS_MAX; ++t) {
-            bool dup = false;
-            for (int u = 0; u < cnt; ++u) dup |= out[u] == t;
-            if (!dup) out[cnt++] = t;
-        }
+    for (int c = lo; c <= hi && cnt < VOX_AXIS_MAX;) {
+        int w = c % n;
+        w = w < 0 ? w + n : w;
+        const int t = w / T;
+        bool dup = false;
+        for (int u = 0; u < cnt; ++u) dup |= out[u] == t;
+        if (!dup) out[cnt++] = t;
+        int step = T - w % T;          // to the start of the next tile
+        step = w + step > n ? n - w : step;  // or to the wrap
+        c += step;
+    }
     for (int u = 1; u < cnt; ++u)
         for (int v = u; v > 0 && out[v] < out[v - 1]; --v) {
             int t = out[v]; out[v] = out[v - 1]; out[v - 1] = t;
@@ -107,12 +121,14 @@ struct TileSet {
     int nx, ny, nz;
 };
 
-__device__ inline void particle_tiles(const VoxArgs& A, int k, TileSet& S) {
+// returns true for a blown-up particle (no tiles)
+__device__ inline bool particle_tiles(const VoxArgs& A, int k, TileSet& S) {
     int lo[3], hi[3];
-    lattice_box(A, k, lo, hi);
+    const bool far = lattice_box(A, k, lo, hi);
     S.nx = axis_tiles(lo[0], hi[0], A.g.nx, PSM_TX, A.g.periodic[0], S.tx);
     S.ny = axis_tiles(lo[1], hi[1], A.g.ny, PSM_TY, A.g.periodic[1], S.ty);
     S.nz = axis_tiles(lo[2], hi[2], A.g.nz, PSM_TZ, A.g.periodic[2], S.tz);
+    return far;
 }
 
 // Registration of particle k, one wave per particle: lane l takes the l-th
@@ -126,9 +142,10 @@ __device__ inline long long tile_of(const VoxArgs& A, const TileSet& S, int l) {
 // tile count of particle k and one tile-histogram increment per tile (through `hist`)
 __device__ inline void reg_count_wave(const VoxArgs& A, int k, int lane, int* hist) {
     TileSet S;
-    particle_tiles(A, k, S);
+    const bool far = particle_tiles(A, k, S);
     const int n = S.nx * S.ny * S.nz;
     if (lane == 0) A.t.vcount[k] = n;
+    if (lane == 0 && far) atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_UNSTABLE);
     for (int l = lane; l < n; l += 64) atomicAdd(&hist[tile_of(A, S, l)], 1);
 }
 

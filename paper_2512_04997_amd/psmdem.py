@@ -8,8 +8,10 @@ no fallback: if the library is missing or no GPU is present, the calls raise.
 A configuration is a plain dict and a particle set a dict of numpy arrays; see
 paper_2512_04997_amd.workloads for the keys.
 """
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -125,7 +127,8 @@ def lib():
     L.psmdem_set_timing.argtypes = [P, C.c_int32]
     L.psmdem_timing.argtypes = [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.psmdem_footprint.argtypes = [C.POINTER(Desc), C.POINTER(Particles), C.POINTER(C.c_int64)]
-    L.psmdem_stream_probe.argtypes = [C.c_int32, P, P, C.c_int64, C.c_int32, C.c_int32, C.POINTER(C.c_double)]
+    L.psmdem_read_state.argtypes = [P, P, C.c_size_t, C.POINTER(C.c_size_t)]
+    L.psmdem_write_state.argtypes = [P, P, C.c_size_t]
     L.psmdem_clock.argtypes = []
     L.psmdem_clock.restype = C.c_double
     L.psmdem_server_create.argtypes = [C.POINTER(ServerDesc), P, P, ALLOC_FN, FREE_FN, P, C.POINTER(P)]
@@ -147,7 +150,8 @@ def lib():
                  "psmdem_write_particles", "psmdem_read_predicted", "psmdem_write_predicted",
                  "psmdem_read_pairs", "psmdem_write_pairs", "psmdem_read_contacts",
                  "psmdem_read_cells", "psmdem_read_solid", "psmdem_counters", "psmdem_info",
-                 "psmdem_set_timing", "psmdem_timing", "psmdem_footprint", "psmdem_stream_probe",
+                 "psmdem_set_timing", "psmdem_timing", "psmdem_footprint", "psmdem_read_state",
+                 "psmdem_write_state",
                  "psmdem_server_create",
                  "psmdem_server_submit", "psmdem_server_iterate", "psmdem_server_drain", "psmdem_server_job",
                  "psmdem_server_domain", "psmdem_server_release"):
@@ -159,6 +163,20 @@ def lib():
 def _check(code):
     if code != OK:
         raise PsmdemError(code, lib().psmdem_last_error().decode())
+
+
+# live domains and servers, closed at interpreter exit while torch (whose
+# caching allocator takes their device memory back) is still up
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live():
+    for obj in list(_LIVE):
+        try:
+            obj.close()
+        except Exception:
+            pass
 
 
 def _ptr(a):
@@ -249,7 +267,10 @@ class _TorchAlloc:
         def _free(p, n, ctx):
             if p in self.live:
                 del self.live[p]
-                torch.cuda.caching_allocator_delete(p)
+                try:
+                    torch.cuda.caching_allocator_delete(p)
+                except Exception:  # the interpreter is shutting down: the process frees the device
+                    pass
 
         self.alloc = ALLOC_FN(_alloc)
         self.free = FREE_FN(_free)
@@ -258,11 +279,15 @@ class _TorchAlloc:
 class Domain:
     """One coupled LBM-PSM-DEM domain on the current GPU (psmdem_create)."""
 
-    def __init__(self, cfg, parts=None, stream=None, allocator="torch"):
+    def __init__(self, cfg, parts=None, stream=None, allocator="torch", strict=True):
+        """strict: reads raise on the device flags (E_UNSTABLE, E_CAPACITY);
+        otherwise they return the outputs and leave the flag in self.flag."""
         L = lib()
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the HIP library is the only compute path")
+        self.strict = strict
+        self.flag = OK
         self.cfg = dict(cfg)
         self.desc = make_desc(cfg)
         self.n = tuple(int(v) for v in cfg["n"])
@@ -279,6 +304,7 @@ class Domain:
                                self._alloc.free if self._alloc else FREE_FN(), None, C.byref(h))
         _check(code)
         self.h = h
+        _LIVE.add(self)
 
     @classmethod
     def _attach(cls, handle, cfg, parts):
@@ -293,6 +319,8 @@ class Domain:
         self._alloc = None
         self.h = handle
         self._owner = False
+        self.strict = True
+        self.flag = OK
         return self
 
     def close(self):
@@ -311,8 +339,19 @@ class Domain:
     def step(self, n=1):
         _check(lib().psmdem_step(self.h, int(n)))
 
+    def _rd(self, code):
+        """Status of a read: the device flags raise only in strict mode."""
+        if code in (E_CAPACITY, E_UNSTABLE):
+            self.flag = code
+            if not self.strict:
+                return
+        _check(code)
+
     def sync(self):
-        _check(lib().psmdem_sync(self.h))
+        """Waits for the device; returns the device flag status (0 OK)."""
+        code = lib().psmdem_sync(self.h)
+        self._rd(code)
+        return code
 
     def stage(self, name):
         _check(lib().psmdem_stage(self.h, STAGE[name]))
@@ -345,7 +384,7 @@ class Domain:
     # ---- state ----------------------------------------------------------------
     def populations(self):
         f = np.zeros(19 * self.N)
-        _check(lib().psmdem_read_populations(self.h, _ptr(f)))
+        self._rd(lib().psmdem_read_populations(self.h, _ptr(f)))
         return f.reshape(19, self.N)
 
     def set_populations(self, f):
@@ -357,7 +396,7 @@ class Domain:
     def fields(self):
         rho = np.zeros(self.N)
         u = np.zeros(3 * self.N)
-        _check(lib().psmdem_read_fields(self.h, _ptr(rho), _ptr(u)))
+        self._rd(lib().psmdem_read_fields(self.h, _ptr(rho), _ptr(u)))
         return rho, u.reshape(self.N, 3)
 
     def particles(self):
@@ -365,7 +404,7 @@ class Domain:
         out = {k: np.zeros((n, 3)) for k in ("pos", "vel", "omega", "acc", "alpha",
                                              "f_hyd", "m_hyd", "f_dem", "m_dem")}
         out["quat"] = np.zeros((n, 4))
-        _check(lib().psmdem_read_particles(self.h, *[_ptr(out[k]) for k in (
+        self._rd(lib().psmdem_read_particles(self.h, *[_ptr(out[k]) for k in (
             "pos", "quat", "vel", "omega", "acc", "alpha", "f_hyd", "m_hyd", "f_dem", "m_dem")]))
         return out
 
@@ -378,7 +417,7 @@ class Domain:
     def predicted(self):
         vp = np.zeros((self.np, 3))
         wp = np.zeros((self.np, 3))
-        _check(lib().psmdem_read_predicted(self.h, _ptr(vp), _ptr(wp)))
+        self._rd(lib().psmdem_read_predicted(self.h, _ptr(vp), _ptr(wp)))
         return vp, wp
 
     def set_predicted(self, vp, wp):
@@ -387,10 +426,10 @@ class Domain:
 
     def pairs(self):
         n = C.c_int64()
-        _check(lib().psmdem_read_pairs(self.h, 0, None, None, C.byref(n)))
+        self._rd(lib().psmdem_read_pairs(self.h, 0, None, None, C.byref(n)))
         k = np.zeros(n.value, np.uint64)
         hst = np.zeros((n.value, 3))
-        _check(lib().psmdem_read_pairs(self.h, n.value, _ptr(k), _ptr(hst), C.byref(n)))
+        self._rd(lib().psmdem_read_pairs(self.h, n.value, _ptr(k), _ptr(hst), C.byref(n)))
         return k, hst
 
     def set_pairs(self, keys, hist):
@@ -400,30 +439,44 @@ class Domain:
 
     def contacts(self):
         n = C.c_int64()
-        _check(lib().psmdem_read_contacts(self.h, 0, None, None, None, None, C.byref(n)))
+        self._rd(lib().psmdem_read_contacts(self.h, 0, None, None, None, None, C.byref(n)))
         m = n.value
         k = np.zeros(m, np.uint64)
         F = np.zeros((m, 3))
         mi = np.zeros((m, 3))
         mj = np.zeros((m, 3))
-        _check(lib().psmdem_read_contacts(self.h, m, _ptr(k), _ptr(F), _ptr(mi), _ptr(mj), C.byref(n)))
+        self._rd(lib().psmdem_read_contacts(self.h, m, _ptr(k), _ptr(F), _ptr(mi), _ptr(mj), C.byref(n)))
         return k, F, mi, mj
 
     def cells(self):
         n = C.c_int64()
-        _check(lib().psmdem_read_cells(self.h, 0, None, C.byref(n)))
+        self._rd(lib().psmdem_read_cells(self.h, 0, None, C.byref(n)))
         k = np.zeros(n.value, np.uint64)
-        _check(lib().psmdem_read_cells(self.h, n.value, _ptr(k), C.byref(n)))
+        self._rd(lib().psmdem_read_cells(self.h, n.value, _ptr(k), C.byref(n)))
         return k
+
+    def state(self):
+        """The whole domain state as a host byte image (psmdem_read_state)."""
+        n = C.c_size_t()
+        _check(lib().psmdem_read_state(self.h, None, 0, C.byref(n)))
+        buf = np.empty(n.value, np.uint8)
+        self._rd(lib().psmdem_read_state(self.h, _ptr(buf), buf.size, C.byref(n)))
+        return buf
+
+    def set_state(self, buf):
+        """Restores an image of state() from a domain of the same layout."""
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(lib().psmdem_write_state(self.h, _ptr(buf), buf.size))
+        self.flag = OK
 
     def solid(self):
         n = C.c_int64()
-        _check(lib().psmdem_read_solid(self.h, 0, None, None, None, C.byref(n)))
+        self._rd(lib().psmdem_read_solid(self.h, 0, None, None, None, C.byref(n)))
         m = n.value
         c = np.zeros(m, np.uint32)
         p = np.zeros(m, np.uint32)
         b = np.zeros(m)
-        _check(lib().psmdem_read_solid(self.h, m, _ptr(c), _ptr(p), _ptr(b), C.byref(n)))
+        self._rd(lib().psmdem_read_solid(self.h, m, _ptr(c), _ptr(p), _ptr(b), C.byref(n)))
         return c, p, b
 
 
@@ -461,6 +514,7 @@ class Server:
         d = ServerDesc(int(max_jobs), int(hbm_budget), int(max_inflight),
                        PRECISION[precision] if isinstance(precision, str) else int(precision))
         h = C.c_void_p()
+        _LIVE.add(self)
         _check(L.psmdem_server_create(C.byref(d), sp, sa, self._alloc.alloc if self._alloc else ALLOC_FN(),
                                       self._alloc.free if self._alloc else FREE_FN(), None, C.byref(h)))
         self.h = h
@@ -515,15 +569,3 @@ class Server:
 
 def version():
     return lib().psmdem_version().decode()
-
-
-STREAM_KINDS = {"copy": 0, "read": 1, "write": 2}
-
-
-def stream_probe(kind, src, dst, nbytes, grid=16384, reps=10):
-    """Average milliseconds of one plain streaming pass (a measurement of the
-    device, not part of the method) over device buffers src, dst (addresses)."""
-    ms = C.c_double()
-    _check(lib().psmdem_stream_probe(STREAM_KINDS[kind], C.c_void_p(src), C.c_void_p(dst), int(nbytes), int(grid),
-                                     int(reps), C.byref(ms)))
-    return ms.value

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2512_04997_amd import workloads as W
-from tests.parity import TOL, copy_state, force_err, force_floor, pop_err, vec_err
+from tests.parity import TOL, copy_state, force_err, linear_shear_populations, pop_err, vec_err
 
 pytestmark = pytest.mark.gpu
 
@@ -137,10 +137,15 @@ def test_coupled_steps_three_solids_per_cell(ps, oracle_mod, ms, prec):
     FP64 oracle."""
     box = (48, 40, 36)
     pos = _fcc_cluster((10.3, 9.7, 9.1), (37.0, 30.0, 26.0), 6.05)
-    parts = W.spheres(pos, 3.0, 1.5)
-    cfg = W.base_config(box, 0.7, max_solids=ms, n_sub=4, precision=prec, sf_method="distance")
+    rng = np.random.default_rng(17)
+    m = len(pos)
+    parts = W.spheres(pos, 3.0, 1.5, vel=0.004 * (rng.random((m, 3)) - 0.5),
+                      omega=0.001 * (rng.random((m, 3)) - 0.5))
+    # the fluid is driven too, so every three-solid cell carries a real exchange
+    cfg = W.base_config(box, 0.7, max_solids=ms, n_sub=4, precision=prec, sf_method="distance",
+                        body_force=[2e-6, -1e-6, 0.5e-6], kn=50.0)
     G, O = _pair(ps, oracle_mod, cfg, parts)
-    for _ in range(2):
+    for _ in range(6):
         G.step(1)
         O.step(1)
     cg, pg, bg = G.solid()
@@ -152,12 +157,14 @@ def test_coupled_steps_three_solids_per_cell(ps, oracle_mod, ms, prec):
         assert (cnt >= 3).sum() > 10
     else:
         assert G.counters()["n_dropped"] > 0
-    assert pop_err(G.populations(), O.populations()) < TOL[prec]
     Pg, Po = G.particles(), O.particles()
     sc = O.scales()
-    assert vec_err(Pg["vel"], Po["vel"]) < TOL[prec]
-    assert force_err(Pg["f_hyd"], Po["f_hyd"], sc["f_hyd"]) < TOL[prec]
-    assert force_err(Pg["m_hyd"], Po["m_hyd"], sc["m_hyd"]) < TOL[prec]
+    assert np.abs(Po["f_hyd"]).min(axis=1).min() > 0 and np.abs(Po["m_hyd"]).max() > 0
+    errs = dict(pop=pop_err(G.populations(), O.populations()), vel=vec_err(Pg["vel"], Po["vel"]),
+                omega=vec_err(Pg["omega"], Po["omega"]), f_hyd=force_err(Pg["f_hyd"], Po["f_hyd"], sc["f_hyd"]),
+                m_hyd=force_err(Pg["m_hyd"], Po["m_hyd"], sc["m_hyd"]))
+    print(f"three solids per cell ({ms} slots, {prec}) after 6 steps:", errs)
+    assert max(errs.values()) < TOL[prec]
     G.close()
 
 
@@ -293,22 +300,31 @@ def test_couette_suspension_steps(ps, oracle_mod, prec, collision):
     cfg["collision"] = collision
     G, O = _pair(ps, oracle_mod, cfg, parts)
     assert G.n_sub == O.n_sub
-    for _ in range(3):
-        G.step(1)
-        O.step(1)
+    # the fluid starts on the Couette profile of the walls, so every particle
+    # is sheared (and pushed into contacts) from the first step
+    f0 = linear_shear_populations(oracle_mod, cfg["n"], 0, 2, cfg["wall_u"][4][0], cfg["wall_u"][5][0])
+    G.set_populations(f0)
+    O.set_populations(f0)
+    worst = {}
+    for chunk in (1, 1, 48, 50):
+        G.step(chunk)
+        O.step(chunk)
         assert np.array_equal(G.pairs()[0], O.pairs()[0])
         cg, pg, bg = G.solid()
         co, po, bo = O.solid()
         assert np.array_equal(cg, co) and np.array_equal(pg, po)
-        assert pop_err(G.populations(), O.populations()) < TOL[prec]
         Pg, Po = G.particles(), O.particles()
-        assert vec_err(Pg["pos"], Po["pos"]) < TOL[prec]
-        assert vec_err(Pg["vel"], Po["vel"]) < TOL[prec]
         sc = O.scales()
-        fl = force_floor(O)
-        assert force_err(Pg["f_hyd"], Po["f_hyd"], sc["f_hyd"]) < TOL[prec]
-        assert force_err(Pg["m_hyd"], Po["m_hyd"], sc["m_hyd"]) < TOL[prec]
-        assert force_err(Pg["f_dem"], Po["f_dem"], sc["f_dem"], fl) < TOL[prec]
+        e = dict(pop=pop_err(G.populations(), O.populations()), pos=vec_err(Pg["pos"], Po["pos"]),
+                 vel=vec_err(Pg["vel"], Po["vel"]), omega=vec_err(Pg["omega"], Po["omega"]),
+                 f_hyd=force_err(Pg["f_hyd"], Po["f_hyd"], sc["f_hyd"]),
+                 m_hyd=force_err(Pg["m_hyd"], Po["m_hyd"], sc["m_hyd"]),
+                 f_dem=force_err(Pg["f_dem"], Po["f_dem"], sc["f_dem"]))
+        worst = {k: max(worst.get(k, 0.0), v) for k, v in e.items()}
+    print(f"Couette {prec} {collision}, worst errors over 100 steps:", worst,
+          "max |v| %.2e, contacts %d" % (np.abs(Po["vel"]).max(), O.counters()["contacts"]))
+    assert np.abs(Po["vel"]).max() > 1e-3
+    assert max(worst.values()) < TOL[prec]
 
 
 def test_determinism_bitwise(ps):
@@ -346,7 +362,7 @@ def test_dem_multi_launch_path(ps, oracle_mod):
         Pg, Po = G.particles(), O.particles()
         assert vec_err(Pg["pos"], Po["pos"]) < 1e-12
         assert vec_err(Pg["vel"], Po["vel"]) < 1e-12
-        assert force_err(Pg["f_dem"], Po["f_dem"], O.scales()["f_dem"], force_floor(O)) < 1e-12
+        assert force_err(Pg["f_dem"], Po["f_dem"], O.scales()["f_dem"]) < 1e-12
     assert O.counters()["contacts"] > 50
 
 
@@ -377,7 +393,7 @@ def test_fused_dem_list_reuse(ps, oracle_mod, kind):
         Pg, Po = G.particles(), O.particles()
         assert vec_err(Pg["pos"], Po["pos"]) < 1e-12
         assert vec_err(Pg["vel"], Po["vel"]) < 1e-12
-        assert force_err(Pg["f_dem"], Po["f_dem"], O.scales()["f_dem"], force_floor(O)) < 1e-12
+        assert force_err(Pg["f_dem"], Po["f_dem"], O.scales()["f_dem"]) < 1e-12
     if kind == "dense_slow":
         assert O.counters()["contacts"] > 20
 
@@ -408,7 +424,7 @@ def test_fused_dem_skip_state_across_launches(ps, oracle_mod):
         Pg, Po = G.particles(), O.particles()
         assert vec_err(Pg["pos"], Po["pos"]) < 1e-12
         assert vec_err(Pg["vel"], Po["vel"]) < 1e-12
-        assert force_err(Pg["f_dem"], Po["f_dem"], O.scales()["f_dem"], force_floor(O)) < 1e-12
+        assert force_err(Pg["f_dem"], Po["f_dem"], O.scales()["f_dem"]) < 1e-12
         contacts += O.counters()["contacts"]
         lengths.add(len(pg))
     assert contacts > 60 and len(lengths) > 3
@@ -446,7 +462,7 @@ def test_fused_dem_state_written_between_steps(ps, oracle_mod):
         Pg, Po = G.particles(), O.particles()
         assert vec_err(Pg["pos"], Po["pos"]) < 1e-12
         assert vec_err(Pg["vel"], Po["vel"]) < 1e-12
-        assert force_err(Pg["f_dem"], Po["f_dem"], O.scales()["f_dem"], force_floor(O)) < 1e-12
+        assert force_err(Pg["f_dem"], Po["f_dem"], O.scales()["f_dem"]) < 1e-12
 
 
 @pytest.mark.parametrize("n", [600, 2300])
@@ -470,7 +486,7 @@ def test_hertz_dem_steps(ps, oracle_mod, n):
         Pg, Po = G.particles(), O.particles()
         assert vec_err(Pg["pos"], Po["pos"]) < 1e-12
         assert vec_err(Pg["vel"], Po["vel"]) < 1e-12
-        assert force_err(Pg["f_dem"], Po["f_dem"], O.scales()["f_dem"], force_floor(O)) < 1e-12
+        assert force_err(Pg["f_dem"], Po["f_dem"], O.scales()["f_dem"]) < 1e-12
     assert O.counters()["contacts"] > 20
 
 
@@ -562,4 +578,4 @@ def test_settling_bed_multi_launch_coupled(ps, oracle_mod):
     assert vec_err(Pg["pos"], Po["pos"]) < TOL["fp64"]
     assert vec_err(Pg["vel"], Po["vel"]) < TOL["fp64"]
     assert force_err(Pg["f_hyd"], Po["f_hyd"], sc["f_hyd"]) < TOL["fp64"]
-    assert force_err(Pg["f_dem"], Po["f_dem"], sc["f_dem"], force_floor(O)) < TOL["fp64"]
+    assert force_err(Pg["f_dem"], Po["f_dem"], sc["f_dem"]) < TOL["fp64"]

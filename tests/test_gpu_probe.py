@@ -12,19 +12,19 @@ PEAK = 8e12
 
 def test_stream_probe_kinds():
     import torch
-    from paper_2512_04997_amd import psmdem
+    from paper_2512_04997_amd import probe
     assert torch.cuda.is_available(), "GPU tests need a visible GPU"
     torch.cuda.set_device(0)
     nbytes = 1 << 30
     a = torch.arange(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.zeros_like(a)
     torch.cuda.synchronize()
-    ms = psmdem.stream_probe("copy", a.data_ptr(), b.data_ptr(), nbytes, grid=4096, reps=3)
+    ms = probe.stream("copy", a.data_ptr(), b.data_ptr(), nbytes, grid=4096, reps=3)
     assert ms > 0 and 2 * nbytes / (ms * 1e-3) < PEAK
     assert torch.equal(a, b)
-    ms = psmdem.stream_probe("read", a.data_ptr(), b.data_ptr(), nbytes, grid=4096, reps=3)
+    ms = probe.stream("read", a.data_ptr(), b.data_ptr(), nbytes, grid=4096, reps=3)
     assert ms > 0 and nbytes / (ms * 1e-3) < PEAK
-    ms = psmdem.stream_probe("write", a.data_ptr(), b.data_ptr(), nbytes, grid=4096, reps=3)
+    ms = probe.stream("write", a.data_ptr(), b.data_ptr(), nbytes, grid=4096, reps=3)
     assert ms > 0 and nbytes / (ms * 1e-3) < PEAK
     q = b.view(-1, 4)
     assert bool((q[:, 0] == 1).all()) and bool((q[:, 3] == 4).all())

@@ -55,17 +55,37 @@ def test_invalid_description_is_rejected_without_a_device():
     assert code == P.E_INVALID and b"trt_magic" in L.psmdem_last_error()
 
 
-@pytest.mark.skipif(not os.path.exists(LIB), reason="libpsmdem.so not built")
-def test_stream_probe_rejects_bad_arguments_without_a_device():
-    from paper_2512_04997_amd import psmdem as P
-    L = P.lib()
+PROBE_HEADER = os.path.join(ROOT, "include", "psmprobe.h")
+PROBE_LIB = os.path.join(ROOT, "paper_2512_04997_amd", "libpsmprobe.so")
+
+
+@pytest.mark.skipif(not os.path.exists(PROBE_LIB), reason="libpsmprobe.so not built")
+def test_stream_probe_is_its_own_library_and_rejects_bad_arguments_without_a_device():
+    """The measurement probe lives in libpsmprobe.so, not in the method's ABI."""
+    assert "stream" not in " ".join(declared_functions())
+    text = re.sub(r"/\*.*?\*/", "", open(PROBE_HEADER).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(psmprobe_[a-z_]+)\s*\(", text)))
+    L = ctypes.CDLL(PROBE_LIB)
+    assert names and all(hasattr(L, n) for n in names)
+    assert not hasattr(ctypes.CDLL(LIB), "psmdem_stream_probe")
+    from paper_2512_04997_amd import probe
+    L = probe.lib()
     ms = ctypes.c_double()
     for kind, src, dst, nbytes, grid, reps, out in ((3, 16, 16, 1 << 20, 8, 1, True), (0, None, 16, 1 << 20, 8, 1, True),
                                                    (2, None, None, 1 << 20, 8, 1, True), (0, 16, 16, 8, 8, 1, True),
                                                    (0, 16, 16, 1 << 20, 0, 1, True), (0, 16, 16, 1 << 20, 8, 0, True),
                                                    (1, 16, 16, 1 << 20, 8, 1, False)):
-        code = L.psmdem_stream_probe(kind, src, dst, nbytes, grid, reps, ctypes.byref(ms) if out else None)
-        assert code == P.E_INVALID and b"stream probe" in L.psmdem_last_error()
+        code = L.psmprobe_stream(kind, src, dst, nbytes, grid, reps, ctypes.byref(ms) if out else None)
+        assert code == -1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libpsmdem.so not built")
+def test_state_calls_reject_bad_arguments_without_a_device():
+    from paper_2512_04997_amd import psmdem as P
+    L = P.lib()
+    n = ctypes.c_size_t()
+    assert L.psmdem_read_state(None, None, 0, ctypes.byref(n)) == P.E_INVALID
+    assert L.psmdem_write_state(None, None, 0) == P.E_INVALID
 
 
 def _r256(n):

@@ -977,12 +977,14 @@ def test_p17_cells_of_far_positions(oracle_mod):
 
 
 # --------------------------------------------------------------------------- Jeffery orbit
-def jeffery_setup(a=8.0, b=4.0, L=80, U=0.04, tau=1.4, dens=2.0):
+def jeffery_setup(oracle_mod, a=8.0, b=4.0, L=80, U=0.04, tau=1.4, dens=2.0):
     """Prolate ellipsoid (a, b, b) at the centre of an L/2 x L x L/2 channel,
     major axis along y (Jeffery angle 0), top wall moving at U in x (shear rate
-    U/L), x and z periodic, fluid started on the linear profile.  Density ratio
-    2: with the explicit coupling of the step a neutrally buoyant body is
-    unstable (the fluid in its cells carries as much inertia as the body)."""
+    U/L), x and z periodic, fluid started on the linear profile (the oracle's
+    equilibria).  Density ratio 2: with the explicit coupling of the step a
+    neutrally buoyant body is unstable (the fluid in its cells carries as much
+    inertia as the body)."""
+    from tests.parity import linear_shear_populations
     n = (L // 2, L, L // 2)
     bc = ["periodic", "periodic", "noslip", "moving", "periodic", "periodic"]
     wu = [[0.0] * 3 for _ in range(6)]
@@ -990,14 +992,8 @@ def jeffery_setup(a=8.0, b=4.0, L=80, U=0.04, tau=1.4, dens=2.0):
     cfg = W.base_config(n, tau, bc=bc, wall_u=wu, n_sub=1)
     s = math.sqrt(0.5)
     parts = _ellipsoid([[a, b, b]], [[n[0] / 2, n[1] / 2, n[2] / 2]], [[s, 0, 0, s]], dens=dens)
-    N = n[0] * n[1] * n[2]
-    y = np.arange(N) // n[0] % n[1]
-    u = np.zeros((N, 3))
-    u[:, 0] = U / L * (y + 0.5)
-    cu = u @ CI.T
-    Wt = np.array([1 / 3] + [1 / 18] * 3 + [1 / 36] * 6 + [1 / 18] * 3 + [1 / 36] * 6)
-    f = Wt[None, :] * (1 + 3 * cu + 4.5 * cu ** 2 - 1.5 * (u ** 2).sum(1)[:, None])
-    return cfg, parts, f.T.copy(), U / L
+    f = linear_shear_populations(oracle_mod, n, 0, 1, 0.0, U)
+    return cfg, parts, f, U / L
 
 
 def jeffery_angle(q):
@@ -1014,7 +1010,7 @@ def test_p13_jeffery_rotation_rate(oracle_mod):
     towards +x), within 5 %, at Re = gd a^2 / nu = 0.11."""
     oracle_mod.set_threads(8)
     a, b = 8.0, 4.0
-    cfg, parts, f0, gd = jeffery_setup(a, b)
+    cfg, parts, f0, gd = jeffery_setup(oracle_mod, a, b)
     D = _dom(oracle_mod, cfg, parts)
     D.set_populations(f0)
     D.step(200)
