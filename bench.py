@@ -1,16 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark of the coupled LBM-PSM-DEM time step on one MI355X.
 
-Workload (default): bounded Couette shear, 128^3 lattice, walls beyond node
-layers 0 and 127 moving at -/+0.02, periodic in x and y, tau = 0.7; 500
-spheres of radius 5 at seeded non-overlapping positions, density ratio 1.5;
-linear spring-dashpot k_n = 1e3, restitution 0.8, Coulomb mu = 0.3; FP32
-populations (shifted storage), FP64 particles.  Synthetic seeded data.
+Workload (default): the precision form's lattice, 512^3 periodic, tau = 0.55,
+Kolmogorov forcing of amplitude 1e-6; 50,000 prolate ellipsoids (6, 3, 3) at
+seeded non-overlapping positions with uniform random orientations, density
+ratio 1.2; linear spring-dashpot k_n = 1e3, restitution 0.8, Coulomb mu = 0.3,
+18 DEM substeps; FP32 populations (shifted storage), FP64 particles; 50 warm-up
+and 500 timed coupled steps.  Synthetic seeded data.  --workload couette runs
+the bounded Couette suspension (128^3, 500 spheres of radius 5).
 
 Prints one JSON line: coupled-step MLUPS (lattice updates per second of whole
-coupled steps, every phase included), the roofline of the dominant kernel (the
-LBM collide-stream pass, measured with HIP events on the domain stream), and
-the FP64 CPU oracle timed on a bounded sample of the same workload.
+coupled steps, every phase included), the roofline of the dominant kernel
+(measured with HIP events on the domain stream), the roofline of the whole
+coupled step (its algorithmic bytes over the step time), and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -30,13 +33,14 @@ STORAGE_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2, "fp16": 2}
 def parse():
     p = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=200)
-    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--steps", type=int, default=500)
+    p.add_argument("--warmup", type=int, default=50)
     p.add_argument("--precision", default="fp32", choices=list(STORAGE_BYTES))
-    p.add_argument("--workload", default="couette", choices=["couette", "kolmogorov", "bed", "fluidized"],
-                   help="couette: spheres in bounded shear; kolmogorov: prolate ellipsoids in a forced periodic "
-                        "box; bed: polydisperse spheres settling in a walled 256x256x128 box (n_sub 32)")
-    p.add_argument("--n", type=int, default=128, help="lattice edge of the workload")
+    p.add_argument("--workload", default="kolmogorov", choices=["couette", "kolmogorov", "bed", "fluidized"],
+                   help="kolmogorov: prolate ellipsoids in a forced periodic box (512^3, 50,000 ellipsoids); "
+                        "couette: spheres in bounded shear (128^3, 500 spheres); bed: polydisperse spheres "
+                        "settling in a walled 256x256x128 box (n_sub 32); fluidized: the paper's fluidized bed")
+    p.add_argument("--n", type=int, default=0, help="lattice edge of the workload (0: 512 kolmogorov, 128 couette)")
     p.add_argument("--phi", type=float, default=0.15, help="solid volume fraction of the fluidized bed")
     p.add_argument("--fluidized-sweep", action="store_true",
                    help="the paper's performance study: fluidized bed 500x200x800 at phi = 0, 0.15, 0.30, "
@@ -45,15 +49,16 @@ def parse():
                    help="fluid operator inside the PSM collision (TRT: the paper's tau- rule); default: the "
                         "workload's own (TRT for the fluidized bed, as in the paper's studies, else BGK)")
     p.add_argument("--spheres", type=int, default=500)
-    p.add_argument("--cpu-sample-steps", type=int, default=120,
-                   help="coupled steps of the CPU oracle sample (0: skip the CPU baseline)")
+    p.add_argument("--cpu-sample-steps", type=int, default=-1,
+                   help="coupled steps of the CPU oracle sample (0: skip the CPU baseline; -1: the workload's "
+                        "default, 200 on the 64^3 ellipsoid box of the same recipe, 120 on the Couette workload)")
     p.add_argument("--no-timing", action="store_true", help="skip the per-kernel event timing pass")
     p.add_argument("--serve-jobs", type=int, default=32,
                    help="jobs of the ensemble-serving sample (0: skip the serving measurement)")
     p.add_argument("--serve-steps", type=int, default=100, help="coupled steps per served job")
     p.add_argument("--serve-rate", type=float, default=50.0, help="mean arrival rate of served jobs (1/s)")
     p.add_argument("--serve-slots", type=int, default=32, help="active slots of the server")
-    p.add_argument("--serve-budget-gb", type=float, default=16.0, help="HBM budget of the held jobs (GiB)")
+    p.add_argument("--serve-budget-gb", type=float, default=2.0, help="HBM budget of the held jobs (GiB)")
     p.add_argument("--stream-probe", type=int, default=0, metavar="MIB",
                    help="attainable streaming bandwidth: copy / read / write kernels over MIB-sized buffers")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -63,8 +68,6 @@ def parse():
     p.add_argument("--precision-study", type=int, default=0, metavar="N",
                    help="only run the Kolmogorov-ellipsoid N^3 workload in FP64, FP32, BF16 and FP16 from the same "
                         "start: coupled-step speed and the errors of each against the FP64 run at step 200")
-    p.add_argument("--study-fraction", type=float, default=0.2,
-                   help="bounding-sphere volume fraction of the precision-study ellipsoids")
     p.add_argument("--summarize", nargs="+", metavar="DIR",
                    help="print a per-kernel summary of rocprofv3 CSV output (no GPU): DIR of a --kernel-trace "
                         "--stats run, or four DIRs of --pmc runs: FETCH_SIZE, WRITE_SIZE, and the same two "
@@ -221,13 +224,13 @@ def _rel_inf(a, b, floor=0.0):
     return float(np.max(np.abs(a - b))) / max(float(np.max(np.abs(b))), floor)
 
 
-def precision_study(n, fraction=0.2, warmup=20, timed=100, check=200):
+def precision_study(n, warmup=20, timed=100, check=200):
     """Same particle set and start in every population precision; speed of the
     coupled step and of the LBM pass, and the errors against the FP64 run."""
     import torch
     from paper_2512_04997_amd import psmdem, workloads
     torch.cuda.set_device(0)
-    cfg, parts, meta = workloads.kolmogorov_ellipsoids(n=n, fraction=fraction)
+    cfg, parts, meta = workloads.kolmogorov_ellipsoids(n=n)
     N = n ** 3
     ref = None
     for prec in ("fp64", "fp32", "bf16", "fp16"):
@@ -377,8 +380,9 @@ def serving(a):
     return res
 
 
-def cpu_baseline(cfg, parts, steps):
-    """FP64 CPU oracle on the same workload for a bounded number of coupled steps."""
+def cpu_baseline(cfg, parts, steps, name):
+    """FP64 CPU oracle on a bounded sample of the workload (coupled steps of
+    `cfg`, which the caller names)."""
     from oracle import oracle
     threads = min(os.cpu_count() or 1, 16)
     oracle.set_threads(threads)
@@ -390,8 +394,7 @@ def cpu_baseline(cfg, parts, steps):
     N = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]
     return {"value": N * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.get_threads(),
             "kind": "oracle",
-            "sample": f"{steps} coupled steps of the same workload (after one untimed step), FP64, "
-                      f"{dt:.1f} s"}
+            "sample": f"{steps} coupled steps of {name} (after one untimed step), FP64, {dt:.1f} s"}
 
 
 def main():
@@ -415,7 +418,7 @@ def main():
         lbm_sweep(a.lbm_sweep, a.collision or "bgk")
         return
     if a.precision_study:
-        precision_study(a.precision_study, a.study_fraction)
+        precision_study(a.precision_study)
         return
     if a.fluidized_sweep:
         fluidized_sweep(a.warmup, a.steps, a.collision)
@@ -424,10 +427,11 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    n = a.n or (512 if a.workload == "kolmogorov" else 128)
     if a.workload == "couette":
-        cfg, parts, meta = workloads.couette_suspension(precision=a.precision, n=a.n, nsph=a.spheres)
+        cfg, parts, meta = workloads.couette_suspension(precision=a.precision, n=n, nsph=a.spheres)
     elif a.workload == "kolmogorov":
-        cfg, parts, meta = workloads.kolmogorov_ellipsoids(n=a.n, precision=a.precision)
+        cfg, parts, meta = workloads.kolmogorov_ellipsoids(n=n, precision=a.precision)
     elif a.workload == "fluidized":
         cfg, parts, meta = workloads.fluidized_bed(precision=a.precision, phi=a.phi)
     else:
@@ -452,10 +456,30 @@ def main():
     mlups = N * a.steps / elapsed / 1e6
     ctr = D.counters()
     print(f"[bench] {a.steps} steps in {elapsed:.3f} s: {ms:.3f} ms/step, {mlups:.0f} MLUPS; "
-          f"solid tiles {ctr['n_solid_tiles']}, entries {ctr['n_entries']}, pairs {ctr['n_pairs']}, "
-          f"contacts {ctr['n_contacts']}", file=sys.stderr, flush=True)
+          f"solid tiles {ctr['n_solid_tiles']}, entries {ctr['n_entries']}, registrations {ctr['n_registrations']}, "
+          f"pairs {ctr['n_pairs']}, contacts {ctr['n_contacts']}", file=sys.stderr, flush=True)
+
+    sb = STORAGE_BYTES[a.precision]
+    np_ = info["n_particles"]
+    # algorithmic bytes of one coupled step: populations read and written once,
+    # a solid-presence bit per cell, solid-fraction entries written and read,
+    # hydrodynamic force and torque out, and per substep the particle state,
+    # the cell-list keys and the pair list with history and contact outputs
+    step_terms = {
+        "populations": N * 2 * 19 * sb,
+        "solid_presence": N / 8.0,
+        "solid_entries": ctr["n_entries"] * (4 + 4 + (8 if a.precision == "fp64" else 4)) * 2,
+        "hydro_out": np_ * 48,
+        "dem": info["n_sub"] * (np_ * 500 + ctr["n_registrations"] * 16 + ctr["n_pairs"] * (8 + 24 * 2 + 72)),
+    }
+    step_bytes = sum(step_terms.values())
+    step_gbs = step_bytes / (ms * 1e-3) / 1e9
+    step_roof = {"bound": "hbm", "achieved": round(step_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": round(step_gbs / HBM_PEAK_GBS, 4), "algorithmic_bytes_per_step": int(step_bytes),
+                 "terms": {k: int(v) for k, v in step_terms.items()}}
 
     roof = None
+    parts_ms = None
     if not a.no_timing:
         # a separate pass with HIP events around every kernel family on the domain stream
         D.set_timing(True)
@@ -465,17 +489,18 @@ def main():
         vox_ms, _ = D.timing("voxel")
         dem_ms, dem_n = D.timing("dem")
         hyd_ms, _ = D.timing("hydro")
-        sb = STORAGE_BYTES[a.precision]
+        groups = dem_n / max(lbm_n, 1)
+        parts_ms = {"lbm": round(lbm_ms, 4), "voxel": round(vox_ms, 4), "dem": round(dem_ms * groups, 4),
+                    "hydro_and_corrector": round(hyd_ms, 4)}
         alg_bytes = N * 2 * 19 * sb
         achieved = alg_bytes / (lbm_ms * 1e-3) / 1e9
+        traffic = measured_traffic(a.precision, n, a.spheres) if a.workload == "couette" else None
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": (measured_traffic(a.precision, a.n, a.spheres)
-                                                                    if a.workload == "couette" else None),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "LBM collide-stream pass (one k_lbm_mixed launch over fluid and PSM tiles per step)",
                 "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": round(lbm_ms, 5)}
         print(f"[bench] per step: lbm {lbm_ms:.4f} ms, voxel {vox_ms:.4f} ms, hydro {hyd_ms:.4f} ms, "
-              f"dem {dem_ms * dem_n / max(lbm_n, 1):.4f} ms ({dem_n // max(lbm_n, 1)} DEM launch groups)",
-              file=sys.stderr, flush=True)
+              f"dem {dem_ms * groups:.4f} ms ({groups:.0f} DEM launch groups)", file=sys.stderr, flush=True)
 
     serve = None
     if a.serve_jobs > 0:
@@ -486,8 +511,18 @@ def main():
               f"p99 {serve['one_at_a_time']['p99_s']} s", file=sys.stderr, flush=True)
 
     cpu = None
-    if a.cpu_sample_steps > 0:
-        cpu = cpu_baseline(cfg, parts, a.cpu_sample_steps)
+    cpu_steps = a.cpu_sample_steps
+    if cpu_steps < 0:
+        cpu_steps = 200 if a.workload == "kolmogorov" else 120
+    if cpu_steps > 0:
+        if a.workload == "kolmogorov" and n > 64:
+            # the oracle's two FP64 population arrays of 512^3 would not finish in a
+            # bounded sample: it runs the 64^3 box of the same recipe (same forcing
+            # amplitude, number density of ellipsoids, contact law)
+            ccfg, cparts, cmeta = workloads.kolmogorov_ellipsoids(n=64, precision="fp64")
+            cpu = cpu_baseline(ccfg, cparts, cpu_steps, cmeta["workload"])
+        else:
+            cpu = cpu_baseline(cfg, parts, cpu_steps, meta["workload"])
         print(f"[bench] cpu oracle: {cpu['value']:.2f} MLUPS on {cpu['cores']} threads", file=sys.stderr,
               flush=True)
 
@@ -496,9 +531,9 @@ def main():
            "vs_baseline": None, "dtype": a.precision, "data": "synthetic",
            "config": {"workload": meta["workload"], "lattice": list(cfg["n"]), "particles": info["n_particles"],
                       "n_sub": info["n_sub"], "tau": cfg["tau"], "collision": cfg.get("collision", "bgk"),
-                      "populations": a.precision,
-                      "particles_dtype": "fp64"},
-           "roofline": roof, "cpu_baseline": cpu, "serving": serve}
+                      "populations": a.precision, "particles_dtype": "fp64"},
+           "roofline": roof, "coupled_step_roofline": step_roof, "per_step_ms": parts_ms,
+           "cpu_baseline": cpu, "serving": serve}
     print(json.dumps(out), flush=True)
 
 

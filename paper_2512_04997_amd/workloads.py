@@ -127,6 +127,167 @@ def rsa_spheres(rng, n, radii, box, periodic, region_lo=None, region_hi=None, ga
     return pos[:placed]
 
 
+# ---------------------------------------------------------------------------
+# exact placement of ellipsoids
+# ---------------------------------------------------------------------------
+def _rotation(q):
+    """Rotation matrices (body to world) of unit quaternions (w, x, y, z)."""
+    w, x, y, z = q[:, 0], q[:, 1], q[:, 2], q[:, 3]
+    R = np.empty((len(q), 3, 3))
+    R[:, 0, 0] = 1 - 2 * (y * y + z * z)
+    R[:, 0, 1] = 2 * (x * y - w * z)
+    R[:, 0, 2] = 2 * (x * z + w * y)
+    R[:, 1, 0] = 2 * (x * y + w * z)
+    R[:, 1, 1] = 1 - 2 * (x * x + z * z)
+    R[:, 1, 2] = 2 * (y * z - w * x)
+    R[:, 2, 0] = 2 * (x * z - w * y)
+    R[:, 2, 1] = 2 * (y * z + w * x)
+    R[:, 2, 2] = 1 - 2 * (x * x + y * y)
+    return R
+
+
+def ellipsoid_shape_matrices(semi, quat):
+    """A = R diag(a^2) R^T: the ellipsoid is {x : x^T A^-1 x <= 1} about its centre."""
+    R = _rotation(np.asarray(quat, np.float64))
+    s = np.asarray(semi, np.float64)
+    return np.einsum("nij,nj,nkj->nik", R, s * s, R)
+
+
+def _r_inv_r(C, r):
+    """r^T C^-1 r for symmetric positive definite 3x3 matrices (adjugate form)."""
+    a, b, c = C[:, 0, 0], C[:, 0, 1], C[:, 0, 2]
+    d, e, f = C[:, 1, 1], C[:, 1, 2], C[:, 2, 2]
+    A00, A01, A02 = d * f - e * e, c * e - b * f, b * e - c * d
+    A11, A12, A22 = a * f - c * c, b * c - a * e, a * d - b * b
+    det = a * A00 + b * A01 + c * A02
+    x, y, z = r[:, 0], r[:, 1], r[:, 2]
+    return (A00 * x * x + A11 * y * y + A22 * z * z + 2.0 * (A01 * x * y + A02 * x * z + A12 * y * z)) / det
+
+
+def ellipsoids_overlap(r, A, B, iters=40):
+    """Overlap test of ellipsoid pairs (Perram & Wertheim, J. Comput. Phys. 58,
+    1985): with shape matrices A, B and centre offset r, the two overlap exactly
+    when max over 0 < l < 1 of S(l) = l (1 - l) r^T [(1 - l) A + l B]^-1 r is
+    below 1 (S is concave in l).  The maximum is searched by golden sections;
+    every evaluated S is a lower bound of it, so touching or nearly touching
+    pairs are reported as overlapping (conservative for placement)."""
+    g = (math.sqrt(5.0) - 1.0) / 2.0
+
+    def S(l):
+        C = (1.0 - l)[:, None, None] * A + l[:, None, None] * B
+        return l * (1.0 - l) * _r_inv_r(C, r)
+
+    lo = np.zeros(len(r))
+    hi = np.ones(len(r))
+    c = hi - g * (hi - lo)
+    d = lo + g * (hi - lo)
+    fc, fd = S(c), S(d)
+    best = np.maximum(fc, fd)
+    for _ in range(iters):
+        left = fc > fd
+        hi = np.where(left, d, hi)
+        lo = np.where(left, lo, c)
+        nc = np.where(left, hi - g * (hi - lo), d)
+        nd = np.where(left, c, lo + g * (hi - lo))
+        fx = S(np.where(left, nc, nd))
+        fc, fd = np.where(left, fx, fd), np.where(left, fc, fx)
+        c, d = nc, nd
+        best = np.maximum(best, fx)
+    return best < 1.0
+
+
+def rsa_ellipsoids_periodic(rng, n, semi, box, gap=1.0, batch=None, max_attempts=50_000_000):
+    """Random sequential addition of equal ellipsoids in a periodic box with
+    an exact overlap test.  Candidates come in batches: `batch` centres
+    uniform in the box (3 batch uniforms), then `batch` Shoemake orientations
+    (3 batch uniforms).  A candidate is kept when its ellipsoid with every
+    semi-axis enlarged by gap/2 overlaps (ellipsoids_overlap, minimum image) no
+    kept one's; candidates are tested in draw order against every earlier kept
+    one, including those of their own batch, so the result is that of one
+    candidate at a time.  Returns (pos (m, 3), quat (m, 4)), m <= n."""
+    box = np.asarray(box, np.float64)
+    infl = np.asarray(semi, np.float64) + 0.5 * gap
+    bound, inner = float(infl.max()), float(infl.min())
+    batch = batch or int(min(4096, max(128, n)))
+    nc = np.maximum(1, np.floor(box / (2.0 * bound)).astype(np.int64))
+    hc = box / nc
+    ncell = int(np.prod(nc))
+    K = 16
+    grid = -np.ones((ncell, K), np.int64)
+    gcnt = np.zeros(ncell, np.int64)
+    pos = np.zeros((n + 1, 3))
+    quat = np.zeros((n, 4))
+    Am = np.zeros((n + 1, 3, 3))
+    Am[n] = np.eye(3)
+    off = np.array([(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)])
+
+    def image(d):
+        return d - box * np.round(d / box)
+
+    def cell_id(c):
+        return (c[..., 2] * nc[1] + c[..., 1]) * nc[0] + c[..., 0]
+
+    placed = attempts = 0
+    while placed < n and attempts < max_attempts:
+        nb = min(batch, max_attempts - attempts)
+        C = box[None, :] * rng.uniform(3 * nb).reshape(nb, 3)
+        Q = shoemake_quaternions(rng, nb)
+        attempts += nb
+        Ab = ellipsoid_shape_matrices(np.tile(infl, (nb, 1)), Q)
+        ci = np.minimum(np.floor(C / hc).astype(np.int64), nc - 1)
+        # against the ellipsoids kept before this batch
+        nbr = cell_id((ci[:, None, :] + off[None]) % nc)
+        idx = grid[nbr].reshape(nb, -1)
+        d = image(pos[np.where(idx >= 0, idx, n)] - C[:, None, :])
+        dist = np.sqrt(np.sum(d * d, axis=2))
+        valid = idx >= 0
+        clash = np.any(valid & (dist < 2.0 * inner), axis=1)
+        ii, jj = np.nonzero(valid & (dist >= 2.0 * inner) & (dist < 2.0 * bound) & ~clash[:, None])
+        if len(ii):
+            clash[ii[ellipsoids_overlap(d[ii, jj], Ab[ii], Am[idx[ii, jj]])]] = True
+        # overlaps among the batch's survivors (earlier survivor jj, later ii)
+        surv = np.flatnonzero(~clash)
+        S = len(surv)
+        if S == 0:
+            continue
+        cid = cell_id(ci[surv])
+        cnt = np.bincount(cid, minlength=ncell)
+        order = np.argsort(cid, kind="stable")
+        rank = np.empty(S, np.int64)
+        rank[order] = np.arange(S) - np.concatenate([[0], np.cumsum(cnt)[:-1]])[cid[order]]
+        tg = -np.ones((ncell, int(cnt.max())), np.int64)
+        tg[cid, rank] = np.arange(S)
+        jdx = tg[cell_id((ci[surv][:, None, :] + off[None]) % nc)].reshape(S, -1)
+        ii, kk = np.nonzero(jdx >= 0)
+        jj = jdx[ii, kk]
+        ii, jj = ii[jj < ii], jj[jj < ii]
+        d2 = image(C[surv[jj]] - C[surv[ii]])
+        dist = np.sqrt(np.sum(d2 * d2, axis=1))
+        ovl = dist < 2.0 * inner
+        m = ~ovl & (dist < 2.0 * bound)
+        if np.any(m):
+            ovl[m] = ellipsoids_overlap(d2[m], Ab[surv[ii[m]]], Ab[surv[jj[m]]])
+        earlier = {}
+        for a, b in zip(ii[ovl].tolist(), jj[ovl].tolist()):
+            earlier.setdefault(a, []).append(b)
+        taken = np.zeros(S, dtype=bool)
+        for t in range(S):
+            if placed >= n:
+                break
+            if any(taken[b] for b in earlier.get(t, ())):
+                continue
+            taken[t] = True
+            s = surv[t]
+            pos[placed], quat[placed], Am[placed] = C[s], Q[s], Ab[s]
+            c = int(cell_id(ci[s]))
+            if gcnt[c] >= K:
+                raise RuntimeError("grid cell overflow in ellipsoid placement")
+            grid[c, gcnt[c]] = placed
+            gcnt[c] += 1
+            placed += 1
+    return pos[:placed], quat[:placed]
+
+
 def _periodic(bc):
     return [bc[2 * a] == "periodic" for a in range(3)]
 
@@ -422,21 +583,22 @@ def fluidized_bed(precision="fp32", phi=0.15, n=(500, 200, 800), radius=10.0, se
     return cfg, parts, dict(workload=name, steps=steps, phi=phi)
 
 
-def kolmogorov_ellipsoids(n=256, fraction=0.2, precision="fp32", seed=1003, amp=1e-6):
+def kolmogorov_ellipsoids(n=512, count=None, precision="fp32", seed=1003, amp=1e-6):
     """Periodic n^3 lattice, tau = 0.55, Kolmogorov forcing of the fluid with
-    component x = amp sin(2 pi (y + 1/2) / n); prolate ellipsoids with
-    semi-axes (6, 3, 3), density ratio 1.2, uniform random orientations
-    (Shoemake), centres by random sequential addition of their bounding
-    spheres (radius 6, surface gap 1) up to a bounding-sphere volume fraction
-    `fraction`; linear contact law k_n = 1e3, e = 0.8, mu = 0.3."""
+    component x = amp sin(2 pi (y + 1/2) / n); `count` prolate ellipsoids with
+    semi-axes (6, 3, 3) (default: 50,000 at 512^3 and the same number density
+    at other sizes, 98 at 64^3), density ratio 1.2, uniform random
+    orientations (Shoemake), placed by random sequential addition with the
+    exact ellipsoid overlap test and a gap of 1 (semi-axes enlarged by 1/2);
+    linear contact law k_n = 1e3, e = 0.8, mu = 0.3."""
     cfg = base_config((n, n, n), 0.55, kolm_amp=amp, kolm_axis=1, kolm_dir=0, precision=precision,
                       kn=1e3, restitution=0.8, mu=0.3)
+    if count is None:
+        count = int(round(50000 * (n / 512.0) ** 3))
     rng = SplitMix64(seed)
-    count = int(round(fraction * n ** 3 / (4.0 / 3.0 * math.pi * 6.0 ** 3)))
-    pos = rsa_equal_spheres_periodic(rng, count, 6.0, (n, n, n))
+    pos, quat = rsa_ellipsoids_periodic(rng, count, [6.0, 3.0, 3.0], (n, n, n))
     m = len(pos)
-    quat = shoemake_quaternions(rng, m)
     parts = dict(shape=np.ones(m, np.int32), semi=np.tile([6.0, 3.0, 3.0], (m, 1)),
                  dens=np.full(m, 1.2), pos=pos, quat=quat, vel=np.zeros((m, 3)), omega=np.zeros((m, 3)),
                  fixed=np.zeros(m, np.uint8))
-    return cfg, parts, dict(workload=f"kolmogorov_{n}^3_{m}_ellipsoids", steps=200)
+    return cfg, parts, dict(workload=f"kolmogorov_{n}^3_{m}_ellipsoids", steps=500, warmup=50)
