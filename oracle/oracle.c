@@ -57,8 +57,11 @@ struct or_domain {
     double *semi, *dens, *mass, *inertia, *rb;
     double *pos, *q, *qold, *v, *w, *vp, *wp, *a, *al;
     double *fh, *mh, *fd, *md;
-    double *fh1, *mh1, *fd1, *md1; /* per-component L1 norms of the summands (parity scale): per-cell
-                                      momentum-exchange terms for F_hyd, M_hyd; pair terms for F_dem, M_dem */
+    double *fh1, *mh1, *fd1, *md1; /* per-component L1 norms of the summands: per-cell momentum-exchange
+                                      terms for F_hyd, M_hyd; pair terms for F_dem, M_dem */
+    double *fhr, *mhr, *fhg, *mhg; /* per-component rounding scales of F_hyd, M_hyd (parity bars): the
+                                      magnitudes the momentum-exchange terms are formed from, as populations
+                                      (fhr, mhr) and as deviations from the weights (fhg, mhg) */
     /* DEM lists */
     int64_t nreg, cap_reg;
     uint64_t* reg;
@@ -242,6 +245,7 @@ or_domain* or_create(const or_desc* d, int32_t np, const int32_t* shape, const d
     ALLOC3(D->vp); ALLOC3(D->wp); ALLOC3(D->a); ALLOC3(D->al); ALLOC3(D->fh); ALLOC3(D->mh);
     ALLOC3(D->fd); ALLOC3(D->md);
     ALLOC3(D->fh1); ALLOC3(D->mh1); ALLOC3(D->fd1); ALLOC3(D->md1);
+    ALLOC3(D->fhr); ALLOC3(D->mhr); ALLOC3(D->fhg); ALLOC3(D->mhg);
 #undef ALLOC3
     D->dens = (double*)xcalloc(np, sizeof(double));
     D->mass = (double*)xcalloc(np, sizeof(double));
@@ -342,6 +346,7 @@ void or_destroy(or_domain* D) {
     free(D->cF); free(D->cMi); free(D->cMj); free(D->incontact); free(D->slot_pid);
     free(D->slot_beta);
     free(D->fh1); free(D->mh1); free(D->fd1); free(D->md1);
+    free(D->fhr); free(D->mhr); free(D->fhg); free(D->mhg);
     free(D);
 }
 
@@ -568,17 +573,23 @@ static double b_weight(double beta, double tau) {
 /* Collision of one cell with PSM, Eqs. (psm1), (lbePS) with the BGK fluid
  * operator Eq. (BGK) or the TRT operator Eq. (TRT), and the solid operator
  * Omega^s; Guo forcing (G26) with the
- * (1 - B_tot) factor.  Pk receives B_k sum_i Omega^s_{i,k} c_i per slot. */
+ * (1 - B_tot) factor.  Pk receives B_k sum_i Omega^s_{i,k} c_i per slot.
+ * Mk (may be NULL) receives per slot the magnitudes that term is formed from,
+ * the bound of its rounding error up to a factor of a few machine epsilons:
+ * for component a, B_k [sum_i |c_ia| (|f_ibar| + |feq_ibar(u)| + |f_i| +
+ * |feq_i(u_k)|) + sum_i |f_i|] (the last sum for the moments behind u) in
+ * Mk[6 s + a], and the same of the deviations from the weights (f - w,
+ * f^eq - w), the quantities a shifted storage rounds, in Mk[6 s + 3 + a]. */
 static void collide_cell(const or_domain* D, const double f[19], int32_t nslot, const double* B,
-                         const double* uk, const double F[3], double fpost[19], double* Pk);
+                         const double* uk, const double F[3], double fpost[19], double* Pk, double* Mk);
 
 void or_collide_cell(const or_domain* D, const double f[19], int32_t nslot, const double* B,
                      const double* uk, const double F[3], double fpost[19], double* Pk) {
-    collide_cell(D, f, nslot, B, uk, F, fpost, Pk);
+    collide_cell(D, f, nslot, B, uk, F, fpost, Pk, NULL);
 }
 
 static void collide_cell(const or_domain* D, const double f[19], int32_t nslot, const double* B,
-                         const double* uk, const double F[3], double fpost[19], double* Pk) {
+                         const double* uk, const double F[3], double fpost[19], double* Pk, double* Mk) {
     if (W[0] == 0.0) lattice_init();
     double tau = D->d.tau;
     double rho = 0.0, m[3] = {0, 0, 0};
@@ -647,6 +658,26 @@ static void collide_cell(const or_domain* D, const double f[19], int32_t nslot, 
             P[2] += Os * CZ[i];
         }
         for (int k = 0; k < 3; ++k) Pk[3 * s + k] = B[s] * P[k];
+        if (Mk) {
+            double a64[3] = {0, 0, 0}, a32[3] = {0, 0, 0}, r64 = 0.0, r32 = 0.0;
+            for (int i = 0; i < 19; ++i) {
+                int o = OPP[i];
+                double m64 = fabs(f[o]) + fabs(feq[o]) + fabs(f[i]) + fabs(feqk[i]);
+                double m32 = fabs(f[o] - W[o]) + fabs(feq[o] - W[o]) + fabs(f[i] - W[i]) + fabs(feqk[i] - W[i]);
+                const int c[3] = {CX[i], CY[i], CZ[i]};
+                for (int k = 0; k < 3; ++k)
+                    if (c[k] != 0) {
+                        a64[k] += m64;
+                        a32[k] += m32;
+                    }
+                r64 += fabs(f[i]);
+                r32 += fabs(f[i] - W[i]);
+            }
+            for (int k = 0; k < 3; ++k) {
+                Mk[6 * s + k] = B[s] * (a64[k] + r64);
+                Mk[6 * s + 3 + k] = B[s] * (a32[k] + r32);
+            }
+        }
     }
 }
 
@@ -674,6 +705,8 @@ void or_stage_lbm(or_domain* D) {
     const int ms = D->d.max_solids;
     double* Pcell = (double*)xcalloc((size_t)(N * ms * 3), sizeof(double));
     double* Tcell = (double*)xcalloc((size_t)(N * ms * 3), sizeof(double));
+    /* rounding scales per (cell, slot): force r, torque r, force g, torque g */
+    double* Rcell = (double*)xcalloc((size_t)(N * ms * 12), sizeof(double));
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < N; ++c) {
         int x = (int)(c % nx), y = (int)((c / nx) % ny), z = (int)(c / ((int64_t)nx * ny));
@@ -696,8 +729,8 @@ void or_stage_lbm(or_domain* D) {
             }
             ++nsl;
         }
-        double P[12];
-        collide_cell(D, f, nsl, B, uk, F, fp, P);
+        double P[12], M[24];
+        collide_cell(D, f, nsl, B, uk, F, fp, P, M);
         for (int s = 0; s < nsl; ++s) {
             double T[3];
             const double* d = rjk + 3 * s;
@@ -705,6 +738,16 @@ void or_stage_lbm(or_domain* D) {
             for (int k = 0; k < 3; ++k) {
                 Pcell[(c * ms + s) * 3 + k] = P[3 * s + k];
                 Tcell[(c * ms + s) * 3 + k] = T[k];
+            }
+            /* a torque component d_a P_b - d_b P_a rounds like |d_a| M_b + |d_b| M_a */
+            double* R = Rcell + (c * ms + s) * 12;
+            for (int v = 0; v < 2; ++v) {
+                const double* m = M + 6 * s + 3 * v;
+                for (int k = 0; k < 3; ++k) {
+                    int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+                    R[6 * v + k] = m[k];
+                    R[6 * v + 3 + k] = fabs(d[k1]) * m[k2] + fabs(d[k2]) * m[k1];
+                }
             }
         }
         for (int i = 0; i < 19; ++i) {
@@ -730,7 +773,10 @@ void or_stage_lbm(or_domain* D) {
             }
         }
     }
-    for (int k = 0; k < 3 * D->np; ++k) { D->fh[k] = 0.0; D->mh[k] = 0.0; D->fh1[k] = 0.0; D->mh1[k] = 0.0; }
+    for (int k = 0; k < 3 * D->np; ++k) {
+        D->fh[k] = D->mh[k] = D->fh1[k] = D->mh1[k] = 0.0;
+        D->fhr[k] = D->mhr[k] = D->fhg[k] = D->mhg[k] = 0.0;
+    }
     for (int64_t c = 0; c < N; ++c) {
         int s = 0;
         for (int u = 0; u < ms; ++u) {
@@ -741,12 +787,18 @@ void or_stage_lbm(or_domain* D) {
                 D->mh[3 * p + k] -= Tcell[(c * ms + s) * 3 + k];
                 D->fh1[3 * p + k] += fabs(Pcell[(c * ms + s) * 3 + k]);
                 D->mh1[3 * p + k] += fabs(Tcell[(c * ms + s) * 3 + k]);
+                const double* R = Rcell + (c * ms + s) * 12;
+                D->fhr[3 * p + k] += R[k];
+                D->mhr[3 * p + k] += R[3 + k];
+                D->fhg[3 * p + k] += R[6 + k];
+                D->mhg[3 * p + k] += R[9 + k];
             }
             ++s;
         }
     }
     free(Pcell);
     free(Tcell);
+    free(Rcell);
     double* t = D->f;
     D->f = D->fn;
     D->fn = t;
@@ -1495,6 +1547,14 @@ void or_set_particles(or_domain* D, const double* pos, const double* quat, const
     if (alpha) memcpy(D->al, alpha, n3);
     if (fh) memcpy(D->fh, fh, n3);
     if (mh) memcpy(D->mh, mh, n3);
+}
+
+void or_get_rounding_scales(const or_domain* D, double* fhr, double* mhr, double* fhg, double* mhg) {
+    size_t n3 = 3 * (size_t)D->np * sizeof(double);
+    if (fhr) memcpy(fhr, D->fhr, n3);
+    if (mhr) memcpy(mhr, D->mhr, n3);
+    if (fhg) memcpy(fhg, D->fhg, n3);
+    if (mhg) memcpy(mhg, D->mhg, n3);
 }
 
 void or_get_scales(const or_domain* D, double* fh1, double* mh1, double* fd1, double* md1) {

@@ -80,6 +80,10 @@ void or_get_predicted(const or_domain* D, double* vp, double* wp);
  * |r_j - r_k| for the torque), which bounds their rounding; for F_dem / M_dem
  * the L1 norm of the pair forces and torques */
 void or_get_scales(const or_domain* D, double* fh1, double* mh1, double* fd1, double* md1);
+/* rounding scales of the last LBM-PSM step's F_hyd and M_hyd [3 np] each:
+ * the population magnitudes the momentum-exchange terms are formed from
+ * (fhr, mhr) and the same of the deviations f - w (fhg, mhg) */
+void or_get_rounding_scales(const or_domain* D, double* fhr, double* mhr, double* fhg, double* mhg);
 int64_t or_get_pairs(const or_domain* D, int64_t cap, uint64_t* keys, double* hist);
 void or_set_pairs(or_domain* D, int64_t n, const uint64_t* keys, const double* hist);
 int64_t or_get_cells(const or_domain* D, int64_t cap, uint64_t* keys);

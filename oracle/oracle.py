@@ -62,6 +62,7 @@ def lib():
     L.or_set_particles.argtypes = [P] + [P] * 8
     L.or_get_predicted.argtypes = [P, P, P]
     L.or_get_scales.argtypes = [P, P, P, P, P]
+    L.or_get_rounding_scales.argtypes = [P, P, P, P, P]
     L.or_set_predicted.argtypes = [P, P, P]
     L.or_get_pairs.argtypes = [P, C.c_int64, P, P]
     L.or_get_pairs.restype = C.c_int64
@@ -208,9 +209,18 @@ class OracleDomain:
         lib().or_set_particles(self.h, *[_ptr(a) for a in arrs])
 
     def scales(self):
-        """Per-particle sums of |summand| of F_hyd, M_hyd, F_dem, M_dem."""
-        out = {k: np.zeros((self.np, 3)) for k in ("f_hyd", "m_hyd", "f_dem", "m_dem")}
-        lib().or_get_scales(self.h, *[_ptr(out[k]) for k in ("f_hyd", "m_hyd", "f_dem", "m_dem")])
+        """Per-particle, per-component scales of the forces of the last step:
+        f_hyd, m_hyd: the rounding scale of the momentum exchange, the
+            population magnitudes each per-cell term is formed from (a
+            difference of O(w_i) populations rounds relative to them);
+        f_hyd_g, m_hyd_g: the same of the deviations f - w_i and f^eq - w_i,
+            the quantities a shifted (f - w) storage and arithmetic round;
+        f_hyd_sum, m_hyd_sum: the L1 norm of the per-cell terms themselves;
+        f_dem, m_dem: the L1 norm of the pair forces and torques."""
+        keys = ("f_hyd_sum", "m_hyd_sum", "f_dem", "m_dem")
+        out = {k: np.zeros((self.np, 3)) for k in keys + ("f_hyd", "m_hyd", "f_hyd_g", "m_hyd_g")}
+        lib().or_get_scales(self.h, *[_ptr(out[k]) for k in keys])
+        lib().or_get_rounding_scales(self.h, *[_ptr(out[k]) for k in ("f_hyd", "m_hyd", "f_hyd_g", "m_hyd_g")])
         return out
 
     def predicted(self):

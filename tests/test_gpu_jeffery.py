@@ -13,7 +13,7 @@ import math
 import numpy as np
 import pytest
 
-from tests.parity import TOL, force_err, pop_err, vec_err
+from tests.parity import TOL, hyd_errs, hyd_info, pop_err, vec_err
 from tests.test_oracle_pins import jeffery_angle, jeffery_setup
 
 pytestmark = pytest.mark.gpu
@@ -44,10 +44,9 @@ def test_jeffery_setup_matches_oracle(ps, oracle_mod):
         Pg, Po = G.particles(), O.particles()
         sc = O.scales()
         e = dict(pop=pop_err(G.populations(), O.populations()), omega=vec_err(Pg["omega"], Po["omega"]),
-                 quat=vec_err(Pg["quat"], Po["quat"]), m_hyd=force_err(Pg["m_hyd"], Po["m_hyd"], sc["m_hyd"]),
-                 f_hyd=force_err(Pg["f_hyd"], Po["f_hyd"], sc["f_hyd"]))
+                 quat=vec_err(Pg["quat"], Po["quat"]), **hyd_errs(Pg, Po, sc, "fp64"))
         worst = {k: max(worst.get(k, 0.0), v) for k, v in e.items()}
-    print("Jeffery setup, worst errors over 40 steps:", worst, "omega_z", Po["omega"][0, 2])
+    print("Jeffery setup, worst errors over 40 steps:", worst, "omega_z", Po["omega"][0, 2], hyd_info(Pg, Po, sc))
     assert Po["omega"][0, 2] < 0
     assert max(worst.values()) < TOL["fp64"]
 

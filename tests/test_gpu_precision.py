@@ -1,13 +1,15 @@
 """Precision forms on the coupled step with ellipsoids (Kolmogorov-forced
-periodic 64^3 lattice, 58 prolate ellipsoids): the GPU path in FP64, FP32,
-BF16 and FP16 storage against the FP64 oracle from the same start.  FP64 and
-FP32 hold the parity bars; the 16-bit storage errors are stated (printed) and
-held to a loose bound."""
+periodic 64^3 lattice, 98 prolate ellipsoids, the number density of 50,000
+in 512^3): the GPU path in FP64, FP32, BF16 and FP16 storage against the FP64
+oracle from the same start.  FP64 holds the parity bars over the trajectory;
+FP32 holds them for its state over the trajectory and for every output after
+one step from the oracle's state; the 16-bit storage errors are stated
+(printed) and held to a loose bound."""
 import numpy as np
 import pytest
 
 from paper_2512_04997_amd import workloads as W
-from tests.parity import TOL, force_err, pop_err, vec_err
+from tests.parity import TOL, bar_values, hyd_errs, one_step_errors, pop_err, vec_err
 
 pytestmark = pytest.mark.gpu
 
@@ -23,7 +25,7 @@ def case(oracle_mod):
     cfg, parts, _ = W.kolmogorov_ellipsoids(n=64, precision="fp64")
     O = oracle_mod.OracleDomain(cfg, parts)
     O.step(STEPS)
-    ref = dict(f=O.populations(), u=O.fields()[1], P=O.particles(), sc=O.scales())
+    ref = dict(f=O.populations(), u=O.fields()[1], P=O.particles(), sc=O.scales(), O=O)
     return psmdem, cfg, parts, ref
 
 
@@ -36,10 +38,16 @@ def test_ellipsoid_kolmogorov_precision(case, prec):
     P = G.particles()
     e["pos"] = vec_err(P["pos"], ref["P"]["pos"])
     e["vel"] = vec_err(P["vel"], ref["P"]["vel"])
-    e["f_hyd"] = force_err(P["f_hyd"], ref["P"]["f_hyd"], ref["sc"]["f_hyd"])
-    e["m_hyd"] = force_err(P["m_hyd"], ref["P"]["m_hyd"], ref["sc"]["m_hyd"])
+    e.update(hyd_errs(P, ref["P"], ref["sc"], "fp64" if prec == "fp64" else "fp32"))
     print(f"{prec} errors after {STEPS} coupled steps vs the FP64 oracle:", e)
-    if prec in TOL:
+    if prec == "fp64":
         assert max(e.values()) < TOL[prec], e
+    elif prec == "fp32":
+        # the trajectory's state holds the bar; its forces follow the diverged
+        # state and are compared after one step from the oracle's state
+        assert max(e[k] for k in ("pop", "u", "pos", "vel")) < TOL[prec], e
+        o = one_step_errors(G, ref["O"], prec)
+        print(f"{prec} one step from the oracle's state at step {STEPS}:", o)
+        assert max(bar_values(o)) < TOL[prec], o
     else:
         assert e["pop"] < 1e-2 and e["u"] < 5e-2, e

@@ -1024,3 +1024,65 @@ def test_p13_jeffery_rotation_rate(oracle_mod):
         assert abs(P["omega"][0, 0]) < 1e-6 * abs(wj) and abs(P["omega"][0, 1]) < 1e-6 * abs(wj)
     assert 0.1 < th < 0.2
     assert all(0.95 < r < 1.05 for r in ratios), ratios
+
+
+def _perturbed_forces(oracle_mod, cfg, parts, f, vp, wp, scale_f):
+    """F_hyd, M_hyd of one LBM-PSM stage of the populations scale_f(f)."""
+    D = _dom(oracle_mod, cfg, parts)
+    D.set_populations(scale_f(f))
+    D.set_predicted(vp, wp)
+    D.stage_voxelize()
+    D.stage_lbm()
+    P = D.particles()
+    return P["f_hyd"], P["m_hyd"], D.scales()
+
+
+@pytest.mark.parametrize("shifted", [False, True])
+def test_force_rounding_scales_bound_the_sensitivity(oracle_mod, shifted):
+    """The parity scales of the hydrodynamic force and torque are rounding
+    bounds: perturbing every population by a relative eps (of f, or of the
+    deviation f - w for the shifted scale) moves each component of F_hyd and
+    M_hyd by at most a few eps times its scale, while the same perturbation
+    moves some component by far more than eps times the per-cell terms' own
+    L1 norm (which is therefore no rounding bound).  Settling sphere after 40
+    steps, and a sheared ellipsoid pair (forces of every sign and size)."""
+    Wt = np.array([1 / 3] + [1 / 18] * 3 + [1 / 36] * 6 + [1 / 18] * 3 + [1 / 36] * 6)[:, None]
+    rng = np.random.default_rng(5)
+    cfg, parts, _ = W.settling_sphere()
+    cases = [(cfg, parts, 40)]
+    cfg2 = W.base_config((32, 24, 22), 0.7, bc=["periodic"] * 4 + ["moving"] * 2,
+                         wall_u=[[0.0] * 3] * 4 + [[-0.02, 0.0, 0.0], [0.02, 0.0, 0.01]])
+    p2 = dict(shape=np.array([1, 1], np.int32), semi=np.array([[5.0, 3.0, 2.5], [4.0, 4.0, 3.0]]),
+              dens=np.array([1.5, 2.0]), pos=np.array([[9.3, 12.1, 11.2], [19.6, 11.4, 10.7]]),
+              quat=W.shoemake_quaternions(W.SplitMix64(3), 2), vel=np.array([[0.01, 0.0, 0.0], [0.0, -0.005, 0.0]]),
+              omega=np.array([[0.0, 0.0, 0.002], [0.001, 0.0, 0.0]]), fixed=np.zeros(2, np.uint8))
+    cases.append((cfg2, p2, 25))
+    eps = 2.0 ** -52 if not shifted else 2.0 ** -24
+    for cfg_, parts_, steps in cases:
+        O = _dom(oracle_mod, cfg_, parts_)
+        O.step(steps)
+        f = O.populations()
+        P = O.particles()
+        vp, wp = O.predicted()
+        ref = _dom(oracle_mod, cfg_, parts_)
+        ref.set_particles(**{k: P[k] for k in ("pos", "quat", "vel", "omega", "acc", "alpha")})
+        fr, mr, sc = _perturbed_forces(oracle_mod, cfg_, dict(parts_, pos=P["pos"], quat=P["quat"]), f, vp, wp,
+                                       lambda g: g)
+        worst_bound, worst_sum = 0.0, 0.0
+        for trial in range(3):
+            r = rng.choice([-1.0, 1.0], size=f.shape)
+            if shifted:
+                pert = lambda g: Wt + (g - Wt) * (1.0 + eps * r)
+            else:
+                pert = lambda g: g * (1.0 + eps * r)
+            fp, mp, _ = _perturbed_forces(oracle_mod, cfg_, dict(parts_, pos=P["pos"], quat=P["quat"]), f, vp, wp,
+                                          pert)
+            for a, b, key in ((fp, fr, "f_hyd"), (mp, mr, "m_hyd")):
+                bound = sc[key + "_g"] if shifted else sc[key]
+                worst_bound = max(worst_bound, float(np.max(np.abs(a - b) / bound)))
+                s1 = sc[key + "_sum"]
+                worst_sum = max(worst_sum, float(np.max(np.abs(a - b) / np.where(s1 > 0, s1, np.inf))))
+        print(f"shifted={shifted}: max |dF| / (eps scale) = {worst_bound / eps:.3g}, "
+              f"against the per-cell terms' L1 norm {worst_sum / eps:.3g} eps")
+        assert worst_bound < 8.0 * eps
+        assert worst_sum > 20.0 * worst_bound
