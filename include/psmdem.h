@@ -208,7 +208,12 @@ psmdem_status psmdem_stage(psmdem_domain* d, int32_t stage);
  * the current time in the canonical layout (the in-place storage is decoded). */
 psmdem_status psmdem_read_populations(psmdem_domain* d, double* f);
 psmdem_status psmdem_write_populations(psmdem_domain* d, const double* f);
-/* rho: [n_cells], u: [3 n_cells] (with forcing, u includes the half-force shift) */
+/* Density and velocity of the populations at the current time (Sec. 2.3,
+ * Eqs. for rho and rho u; with forcing, u includes the half-force shift):
+ * rho [n_cells], u [3 n_cells] (x, y, z per cell); either may be NULL.  The
+ * moments are formed on the device, chunk by chunk, in a staging block the
+ * library allocates for the call through the domain's allocator (32 bytes
+ * per cell of a chunk of at most 2^22 cells; PSMDEM_E_NOMEM when it cannot). */
 psmdem_status psmdem_read_fields(psmdem_domain* d, double* rho, double* u);
 /* particle arrays [3n] (quat [4n]); any pointer may be NULL */
 psmdem_status psmdem_read_particles(psmdem_domain* d, double* pos, double* quat, double* vel,
@@ -334,8 +339,9 @@ psmdem_status psmdem_server_create(const psmdem_server_desc* desc, void* stream,
 /* Waits for the device and frees every job. */
 void psmdem_server_destroy(psmdem_server* s);
 /* Queues a job of `steps` coupled steps; inputs are copied.  *job receives
- * its id (> 0).  Refuses jobs the server cannot run (PSMDEM_E_INVALID) or
- * whose footprint alone exceeds the budget (PSMDEM_E_NOMEM). */
+ * its id (> 0).  Refuses, with PSMDEM_E_INVALID, jobs the server cannot run
+ * (precision, fluid off, particle or tile limits) and jobs whose footprint
+ * alone exceeds the budget (they could never be admitted). */
 psmdem_status psmdem_server_submit(psmdem_server* s, const psmdem_desc* desc, const psmdem_particles* parts,
                                    int64_t steps, int64_t* job);
 /* One serving iteration (steps 1-4 above); either output may be NULL. */

@@ -25,6 +25,7 @@ SOURCES = [
     ("voxel.hip", ["-ffp-contract=off"]),
     ("lbm.hip", []),
     ("psmdem.hip", []),
+    ("fields.hip", []),
     ("server.hip", []),
 ]
 PROBE_SOURCES = [("probe.hip", [])]

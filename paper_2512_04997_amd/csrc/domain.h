@@ -13,6 +13,7 @@
 struct psmdem_domain {
     psmdem_desc d;
     hipStream_t s = nullptr;
+    int dev = 0;        // device current at creation (the device of the stream)
     psmdem_alloc_fn alloc = nullptr;
     psmdem_free_fn freef = nullptr;
     void* actx = nullptr;
@@ -64,6 +65,7 @@ struct psmdem_domain {
     int4* items = nullptr;
     int* item_cnt = nullptr;
     long long item_cap = 0;
+    void* vpart = nullptr;
     int* scan_tmp = nullptr;
     DevCounters* ctr = nullptr;
 
@@ -96,6 +98,19 @@ struct psmdem_domain {
             bytes += n;
         }
         return ptr;
+    }
+    // a device block for the duration of one call (not part of the domain)
+    void* talloc(size_t n) {
+        n = (n + 255) & ~(size_t)255;
+        void* ptr = nullptr;
+        if (alloc) ptr = alloc(n, actx);
+        else if (hipMalloc(&ptr, n) != hipSuccess) ptr = nullptr;
+        return ptr;
+    }
+    void tfree(void* ptr, size_t n) {
+        n = (n + 255) & ~(size_t)255;
+        if (freef) freef(ptr, n, actx);
+        else if (!alloc) (void)hipFree(ptr);
     }
     ~psmdem_domain() {
         if (dry) return;
@@ -194,6 +209,7 @@ struct psmdem_domain {
         A.items = items;
         A.item_cnt = item_cnt;
         A.item_cap = item_cap;
+        A.vpart = vpart;
         A.ctr = ctr;
         return A;
     }
@@ -262,3 +278,7 @@ struct psmdem_domain {
 psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles* parts, void* stream,
                                 psmdem_alloc_fn alloc, psmdem_free_fn free_fn, void* alloc_ctx, bool dry,
                                 psmdem_domain** out, size_t* bytes);
+// waits for the domain stream and reports the device flags (unstable, then
+// capacity); psm_read_fails: a status that stops a read (the flags do not)
+psmdem_status psm_sync_flags(psmdem_domain* d);
+bool psm_read_fails(psmdem_status st);

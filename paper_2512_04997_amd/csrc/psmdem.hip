@@ -262,6 +262,7 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
     }
     psmdem_domain* D = new psmdem_domain();
     D->dry = dry;
+    if (!dry && hipGetDevice(&D->dev) != hipSuccess) D->dev = 0;
     D->d = *desc;
     D->s = (hipStream_t)stream;
     D->alloc = alloc;
@@ -454,6 +455,7 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
     t.partial = (double*)A(sizeof(double) * 6 * t.cap);
     D->tile_count = (int*)A(sizeof(int) * g.ntiles);
     D->tile_fill = (int*)A(sizeof(int) * g.ntiles);
+    if (np > 0) D->vpart = A(vox_part_bytes() * (size_t)np);
     // boundary cells sampled per step: about twice the shell of the largest
     // bounding sphere per particle (more are sampled in place, slower)
     if (np > 0 && d.sf_method == 0) {
@@ -603,7 +605,7 @@ extern "C" psmdem_status psmdem_step(psmdem_domain* d, int64_t n) {
 // Waits for the stream and reports the device flags: PSMDEM_E_UNSTABLE when
 // the state has blown up, else PSMDEM_E_CAPACITY when a device list outgrew
 // its capacity.  The flags stay set until a write_* call rewrites the state.
-static psmdem_status sync_flags(psmdem_domain* d) {
+psmdem_status psm_sync_flags(psmdem_domain* d) {
     PSM_CHECK(hipStreamSynchronize(d->s));
     DevCounters c{};
     PSM_CHECK(hipMemcpy(&c, d->ctr, sizeof c, hipMemcpyDeviceToHost));
@@ -623,7 +625,7 @@ static psmdem_status sync_flags(psmdem_domain* d) {
 
 // a status of sync_flags that stops a read (the device flags do not: the
 // outputs are still written and the flag is returned)
-static bool read_fails(psmdem_status st) { return st != PSMDEM_OK && st != PSMDEM_E_CAPACITY && st != PSMDEM_E_UNSTABLE; }
+bool psm_read_fails(psmdem_status st) { return st != PSMDEM_OK && st != PSMDEM_E_CAPACITY && st != PSMDEM_E_UNSTABLE; }
 
 // the state is being rewritten: the device flags of the old one are dropped
 static psmdem_status clear_flags(psmdem_domain* d) {
@@ -635,7 +637,7 @@ static psmdem_status clear_flags(psmdem_domain* d) {
 
 extern "C" psmdem_status psmdem_sync(psmdem_domain* d) {
     if (!d) return PSMDEM_E_INVALID;
-    return sync_flags(d);
+    return psm_sync_flags(d);
 }
 
 extern "C" psmdem_status psmdem_stage(psmdem_domain* d, int32_t stage) {
@@ -674,7 +676,7 @@ extern "C" psmdem_status psmdem_stage(psmdem_domain* d, int32_t stage) {
             return PSMDEM_E_INVALID;
     }
     if (rc) return (psmdem_status)rc;
-    return sync_flags(d);
+    return psm_sync_flags(d);
 }
 
 // ---------------------------------------------------------------------------
@@ -698,8 +700,8 @@ static void host_face(const psmdem_domain* D, int x, int y, int z, int dx, int d
 
 extern "C" psmdem_status psmdem_read_populations(psmdem_domain* d, double* fout) {
     if (!d || !fout) return PSMDEM_E_INVALID;
-    const psmdem_status st = sync_flags(d);
-    if (read_fails(st)) return st;
+    const psmdem_status st = psm_sync_flags(d);
+    if (psm_read_fails(st)) return st;
     const long long N = d->N;
     const size_t sb = storage_bytes(d->prec);
     std::vector<unsigned char> raw(19 * (size_t)N * sb);
@@ -750,35 +752,6 @@ extern "C" psmdem_status psmdem_write_populations(psmdem_domain* d, const double
     return PSMDEM_OK;
 }
 
-extern "C" psmdem_status psmdem_read_fields(psmdem_domain* d, double* rho, double* u) {
-    if (!d) return PSMDEM_E_INVALID;
-    const long long N = d->N;
-    std::vector<double> f(19 * (size_t)N);
-    const psmdem_status st = psmdem_read_populations(d, f.data());
-    if (read_fails(st)) return st;
-    for (long long c = 0; c < N; ++c) {
-        double r = 0, m[3] = {0, 0, 0};
-        for (int i = 0; i < 19; ++i) {
-            double fi = f[(long long)i * N + c];
-            r += fi;
-            m[0] += fi * CX[i];
-            m[1] += fi * CY[i];
-            m[2] += fi * CZ[i];
-        }
-        int x = (int)(c % d->d.nx), y = (int)((c / d->d.nx) % d->d.ny), z = (int)(c / ((long long)d->d.nx * d->d.ny));
-        double F[3] = {d->d.body_force[0], d->d.body_force[1], d->d.body_force[2]};
-        if (d->d.kolm_amp != 0.0) {
-            int ax = d->d.kolm_axis, coord = ax == 0 ? x : (ax == 1 ? y : z);
-            int n_ax = ax == 0 ? d->d.nx : (ax == 1 ? d->d.ny : d->d.nz);
-            F[d->d.kolm_dir] += d->d.kolm_amp * sin(2.0 * M_PI * ((double)coord + 0.5) / (double)n_ax);
-        }
-        if (rho) rho[c] = r;
-        if (u)
-            for (int k = 0; k < 3; ++k) u[3 * c + k] = (m[k] + 0.5 * F[k]) / r;
-    }
-    return st;
-}
-
 // ---------------------------------------------------------------------------
 // particles, pairs, cells, solid slots
 // ---------------------------------------------------------------------------
@@ -786,8 +759,8 @@ extern "C" psmdem_status psmdem_read_particles(psmdem_domain* d, double* pos, do
                                               double* acc, double* alpha, double* f_hyd, double* m_hyd, double* f_dem,
                                               double* m_dem) {
     if (!d) return PSMDEM_E_INVALID;
-    const psmdem_status st = sync_flags(d);
-    if (read_fails(st)) return st;
+    const psmdem_status st = psm_sync_flags(d);
+    if (psm_read_fails(st)) return st;
     size_t n3 = sizeof(double) * 3 * d->np;
     if (d->np == 0) return st;
     struct { double* h; double* dv; size_t n; } m[] = {
@@ -818,8 +791,8 @@ extern "C" psmdem_status psmdem_write_particles(psmdem_domain* d, const double* 
 
 extern "C" psmdem_status psmdem_read_predicted(psmdem_domain* d, double* vp, double* wp) {
     if (!d) return PSMDEM_E_INVALID;
-    const psmdem_status st = sync_flags(d);
-    if (read_fails(st)) return st;
+    const psmdem_status st = psm_sync_flags(d);
+    if (psm_read_fails(st)) return st;
     if (d->np == 0) return st;
     if (vp) PSM_CHECK(hipMemcpy(vp, d->p.vp, sizeof(double) * 3 * d->np, hipMemcpyDeviceToHost));
     if (wp) PSM_CHECK(hipMemcpy(wp, d->p.wp, sizeof(double) * 3 * d->np, hipMemcpyDeviceToHost));
@@ -845,8 +818,8 @@ static psmdem_status pair_count(psmdem_domain* d, int64_t* n) {
 
 extern "C" psmdem_status psmdem_read_pairs(psmdem_domain* d, int64_t cap, uint64_t* keys, double* hist, int64_t* n) {
     if (!d || !n) return PSMDEM_E_INVALID;
-    const psmdem_status st = sync_flags(d);
-    if (read_fails(st)) return st;
+    const psmdem_status st = psm_sync_flags(d);
+    if (psm_read_fails(st)) return st;
     int64_t np_ = 0;
     if (psmdem_status pc = pair_count(d, &np_)) return pc;
     *n = np_;
@@ -883,8 +856,8 @@ extern "C" psmdem_status psmdem_write_pairs(psmdem_domain* d, int64_t n, const u
 extern "C" psmdem_status psmdem_read_contacts(psmdem_domain* d, int64_t cap, uint64_t* keys, double* force, double* m_i,
                                              double* m_j, int64_t* n) {
     if (!d || !n) return PSMDEM_E_INVALID;
-    const psmdem_status st = sync_flags(d);
-    if (read_fails(st)) return st;
+    const psmdem_status st = psm_sync_flags(d);
+    if (psm_read_fails(st)) return st;
     int64_t np_ = 0;
     if (psmdem_status pc = pair_count(d, &np_)) return pc;
     np_ = std::min<int64_t>(np_, d->pair_cap);
@@ -917,8 +890,8 @@ extern "C" psmdem_status psmdem_read_contacts(psmdem_domain* d, int64_t cap, uin
 
 extern "C" psmdem_status psmdem_read_cells(psmdem_domain* d, int64_t cap, uint64_t* keys, int64_t* n) {
     if (!d || !n) return PSMDEM_E_INVALID;
-    const psmdem_status st = sync_flags(d);
-    if (read_fails(st)) return st;
+    const psmdem_status st = psm_sync_flags(d);
+    if (psm_read_fails(st)) return st;
     *n = 0;
     if (d->np == 0) return st;
     std::vector<int> start(d->ncell + 1);
@@ -939,8 +912,8 @@ extern "C" psmdem_status psmdem_read_cells(psmdem_domain* d, int64_t cap, uint64
 extern "C" psmdem_status psmdem_read_solid(psmdem_domain* d, int64_t cap, uint32_t* cell, uint32_t* pid, double* beta,
                                           int64_t* n) {
     if (!d || !n) return PSMDEM_E_INVALID;
-    const psmdem_status st = sync_flags(d);
-    if (read_fails(st)) return st;
+    const psmdem_status st = psm_sync_flags(d);
+    if (psm_read_fails(st)) return st;
     *n = 0;
     if (!d->voxelized) return st;
     const GeoArgs& g = d->geo;
@@ -1074,8 +1047,8 @@ extern "C" psmdem_status psmdem_read_state(psmdem_domain* d, void* buf, size_t c
         psm_set_error("state buffer holds %zu bytes, %zu needed", cap, need);
         return PSMDEM_E_INVALID;
     }
-    const psmdem_status st = sync_flags(d);
-    if (read_fails(st)) return st;
+    const psmdem_status st = psm_sync_flags(d);
+    if (psm_read_fails(st)) return st;
     StateHeader h{};
     memcpy(h.magic, kStateMagic, 8);
     h.layout = state_layout(d);

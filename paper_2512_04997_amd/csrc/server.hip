@@ -208,6 +208,7 @@ int upload_tables(psmdem_server* S) {
         J.dem = (D->d.dem_on && D->np > 0) ? 1 : 0;
         J.fluid = 1;
         vox[i] = D->vox_args();
+        vox[i].vpart = nullptr;  // the one-workgroup voxelisation forms its own particle records
         lbm[i] = D->lbm_args();
         const int nt = (int)D->geo.ntiles;
         std::vector<int2>& mp = D->d.max_solids <= 2 ? m2 : m4;
@@ -423,8 +424,9 @@ extern "C" psmdem_status psmdem_server_submit(psmdem_server* S, const psmdem_des
     psmdem_status rc = psmdem_footprint(desc, parts, &fp);
     if (rc != PSMDEM_OK) return rc;
     if (S->d.hbm_budget > 0 && fp > S->d.hbm_budget) {
-        psm_set_error("job footprint %lld B exceeds the budget", (long long)fp);
-        return PSMDEM_E_NOMEM;
+        psm_set_error("job footprint %lld B exceeds the budget of %lld B: it could never be admitted",
+                      (long long)fp, (long long)S->d.hbm_budget);
+        return PSMDEM_E_INVALID;
     }
     Job* J = new Job();
     J->id = S->next_id++;

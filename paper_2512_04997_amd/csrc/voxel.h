@@ -21,6 +21,8 @@ struct VoxArgs {
     int4* items;                 // [item_cap] (X, Y, Z, pid), unwrapped cell indices
     int* item_cnt;               // [item_cap] inside samples
     long long item_cap;          // items beyond it are sampled in the select kernel
+    void* vpart;                 // [np] per-step particle records of the tile kernels (vox_part_bytes
+                                 // each), formed by vox_voxelize; null: each tile forms its own
     DevCounters* ctr;
 };
 
@@ -31,3 +33,5 @@ hipError_t vox_register(const VoxArgs& A, int* scan_tmp, hipStream_t s);
 // voxelisation of registered tiles
 hipError_t vox_voxelize(const VoxArgs& A, int ctype_double, hipStream_t s);
 hipError_t vox_reduce_hydro(const VoxArgs& A, hipStream_t s);
+// bytes of one particle record (VoxArgs::vpart)
+size_t vox_part_bytes();

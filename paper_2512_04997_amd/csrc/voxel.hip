@@ -13,7 +13,8 @@
 //                  first per-tile kernel below instead)
 //   k_vox_classify per tile: cells whose samples straddle a surface, queued as
 //                  items of the step (exact inside / outside shortcuts elsewhere)
-//   k_vox_sample   a lane per queued sphere cell (a wave per other cell): its count of inside samples
+//   k_vox_sample   a lane per queued cell: its count of inside samples (spheres sample by
+//                  sample, ellipsoids row by row; a wave per cell above 12 samples per direction)
 //   k_vox_select   per tile: beta of every (cell, particle), keep the max_solids
 //                  largest (ties to the smaller pid), B_k, slots
 //   k_reduce_hydro per particle: minus the sum of its tile partials (F, M)
@@ -293,17 +294,19 @@ __global__ __launch_bounds__(VOX_RT) void k_vox_register_batch(const VoxArgs* __
     }
 }
 
-// per-particle data staged in LDS for a tile
+// per-particle data staged in LDS for a tile (8-byte words, copied as such)
 struct VoxPart {
     double c[3];
     double ax[3];
     double R[9];
     double inv[3];
     double e[3];
+    double r[3];   // ellipsoids: body-frame half-widths of a cell's sample box, h sum_r |R_rk|
     int lo[3], hi[3];
     int shape;
     int pid;
 };
+static_assert(sizeof(VoxPart) % 8 == 0, "VoxPart is copied in 8-byte words");
 
 __device__ inline bool in_box(const VoxPart& P, int x, int n, int axis, int periodic, int* X) {
     int lo = P.lo[axis], hi = P.hi[axis];
@@ -352,26 +355,48 @@ __device__ int classify(const VoxPart& P, int X, int Y, int Z, double slo, doubl
         if (minr2 > R2 + m) return 0;
         return 2;
     }
+    // Ellipsoids, over the cell's sample box (centre X + 1/2, half-width h =
+    // (ns - 1) / (2 ns) per axis, widened by 1e-9 for the rounding of the
+    // sample coordinates).  In the body frame the box's points p satisfy
+    // |p_k - pc_k| <= r_k with r_k = h sum_r |R_rk|, so
+    //   Q >= sum_k inv_k max(0, |pc_k| - r_k)^2   (every sample outside) and
+    //   Q <= sum_k inv_k (|pc_k| + r_k)^2          (every sample inside);
+    // between them, Q being convex its maximum over the box is at one of the
+    // box's eight vertices: all eight inside means every sample is inside.
+    // The margin 1e-9 lies far above the rounding of any sample's Q.
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         double dl = (double)Xc[a] - P.c[a];
         double dh = ((double)Xc[a] + 1.0) - P.c[a];
         if (dh < -P.e[a] - 1e-6 || dl > P.e[a] + 1e-6) return 0;
     }
-    // |A^-1 R^T (p - c)| >= sqrt(q(centre)) - (sqrt(3)/2) / a_min for p in the cell
-    double amin = P.ax[0] < P.ax[1] ? P.ax[0] : P.ax[1];
-    amin = amin < P.ax[2] ? amin : P.ax[2];
-    double qc = ell_q(P, ((double)X + 0.5) - P.c[0], ((double)Y + 0.5) - P.c[1], ((double)Z + 0.5) - P.c[2]);
-    if (sqrt(qc) - 0.8660254037844387 / amin > 1.0 + 1e-6) return 0;
-    bool all_in = true;
+    const double h = 0.5 * (shi - slo) + 1e-9;
+    const double d0 = ((double)X + 0.5) - P.c[0], d1 = ((double)Y + 0.5) - P.c[1], d2 = ((double)Z + 0.5) - P.c[2];
+    double pc[3];
 #pragma unroll
-    for (int corner = 0; corner < 8; ++corner) {
-        double dx = ((double)X + (double)(corner & 1)) - P.c[0];
-        double dy = ((double)Y + (double)((corner >> 1) & 1)) - P.c[1];
-        double dz = ((double)Z + (double)((corner >> 2) & 1)) - P.c[2];
-        all_in = all_in && ell_q(P, dx, dy, dz) < 1.0 - 1e-9;
+    for (int k = 0; k < 3; ++k) pc[k] = (P.R[0 + k] * d0 + P.R[3 + k] * d1) + P.R[6 + k] * d2;
+    double qmin = 0.0, qmax = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double a = fabs(pc[k]);
+        const double lo = a > P.r[k] ? a - P.r[k] : 0.0, hi = a + P.r[k];
+        qmin += lo * lo * P.inv[k];
+        qmax += hi * hi * P.inv[k];
     }
-    return all_in ? 1 : 2;
+    if (qmin > 1.0 + 1e-9) return 0;
+    if (qmax < 1.0 - 1e-9) return 1;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+        const double sx = (v & 1) ? h : -h, sy = (v & 2) ? h : -h, sz = (v & 4) ? h : -h;
+        double q = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const double pk = pc[k] + ((P.R[0 + k] * sx + P.R[3 + k] * sy) + P.R[6 + k] * sz);
+            q += pk * pk * P.inv[k];
+        }
+        if (!(q < 1.0 - 1e-9)) return 2;
+    }
+    return 1;
 }
 
 // The sphere branch of classify split at its axis loop: the x and y terms of a
@@ -522,26 +547,55 @@ __device__ inline void top_by_pid(Top4& T) {
 // pieces of the per-tile voxelisation, shared by the one-kernel form (serving
 // batches) and the three-kernel form (classify / sample / select)
 // ---------------------------------------------------------------------------
+// the voxelisation record of particle k (ns samples per direction)
+__device__ inline void make_part(const VoxArgs& A, int k, VoxPart& P) {
+    P.pid = k;
+    P.shape = A.p.shape[k];
+    for (int a = 0; a < 3; ++a) {
+        P.c[a] = A.p.pos[3 * k + a];
+        P.ax[a] = A.p.semi[3 * k + a];
+        P.inv[a] = 1.0 / (P.ax[a] * P.ax[a]);
+    }
+    quat_rbw(A.p.q + 4 * k, P.R);
+    half_extents(A, k, P.e);
+    lattice_box(A, k, P.lo, P.hi);
+    const double h = (double)(A.ns - 1) / (double)(2 * A.ns) + 1e-9;
+    for (int a = 0; a < 3; ++a) P.r[a] = h * ((fabs(P.R[a]) + fabs(P.R[3 + a])) + fabs(P.R[6 + a]));
+}
+
+// the step's records, one per particle, for the per-tile kernels
+__global__ void k_vox_parts(VoxArgs A) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= A.p.np) return;
+    VoxPart P;
+    make_part(A, k, P);
+    ((VoxPart*)A.vpart)[k] = P;
+}
+
 // the tile's registered particles staged in LDS, and the sample offsets (the
-// list from keys when given, else from global memory)
+// list from keys when given, else from global memory); the records come from
+// the step's record array when there is one (copied in 8-byte words by the
+// whole workgroup), else each is formed here
 __device__ inline void stage_particles(const VoxArgs& A, VoxPart* sp, double* off, long long s0, int count,
                                        const unsigned long long* keys = nullptr) {
     const int tid = threadIdx.x;
     if (tid < A.ns) off[tid] = (double)(2 * tid + 1) / (double)(2 * A.ns);
+    if (A.vpart) {
+        constexpr int WORDS = (int)(sizeof(VoxPart) / 8);
+        const unsigned long long* src = (const unsigned long long*)A.vpart;
+        unsigned long long* dst = (unsigned long long*)sp;
+        for (int w = tid; w < count * WORDS; w += VOX_T) {
+            const int u = w / WORDS;
+            int k = (int)((keys ? keys[u] : A.t.tile_list[s0 + u]) >> 32);
+            if (k >= A.p.np) k = 0;
+            dst[w] = src[(long long)k * WORDS + (w - u * WORDS)];
+        }
+        return;
+    }
     for (int u = tid; u < count; u += VOX_T) {
         int k = (int)((keys ? keys[u] : A.t.tile_list[s0 + u]) >> 32);
         if (k >= A.p.np) k = 0;
-        VoxPart& P = sp[u];
-        P.pid = k;
-        P.shape = A.p.shape[k];
-        for (int a = 0; a < 3; ++a) {
-            P.c[a] = A.p.pos[3 * k + a];
-            P.ax[a] = A.p.semi[3 * k + a];
-            P.inv[a] = 1.0 / (P.ax[a] * P.ax[a]);
-        }
-        quat_rbw(A.p.q + 4 * k, P.R);
-        half_extents(A, k, P.e);
-        lattice_box(A, k, P.lo, P.hi);
+        make_part(A, k, sp[u]);
     }
 }
 
@@ -969,10 +1023,101 @@ __device__ inline int sphere_count_lane_ns(int ns, double c0, double c1, double 
     }
 }
 
+// Inside samples of an ellipsoid in cell (X, Y, Z), counted by ONE LANE a
+// sample row at a time.  Along a row (fixed y and z offsets) the test value
+// is a quadratic in the x offset, Q(x) = A x^2 + 2 B x + C with
+// A = sum_k inv_k R_0k^2, B = sum_k inv_k R_0k w_k, C = sum_k inv_k w_k^2 and
+// w_k = R_1k dy + R_2k dz (p = R^T d, R = Rbw).  The samples with Q < 1 lie
+// between the roots r1 < r2 of Q = 1.  A sample farther than m from both
+// roots is decided by its side: there |Q - 1| >= A m min(m, r2 - r1) is far
+// above the rounding of any evaluation of Q (with m = 1e-5 (1 + a_max), the
+// roots computed only when the discriminant clears its own rounding by the
+// factor 1e6).  Samples within m of a root, and every sample of a row whose
+// discriminant is within that rounding bound of zero (a row grazing the
+// surface), are tested with the definition's own evaluation order.  So the
+// count is the count of the per-sample definition, bit for bit, at a few
+// flops per row instead of per sample.
+__device__ inline int ellipsoid_count_lane(const double* cen, const double* ax, const double* R, int X, int Y, int Z,
+                                           const double* off, int ns) {
+    double inv[3], A = 0.0, by = 0.0, bz = 0.0, cyy = 0.0, cyz = 0.0, czz = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        inv[k] = 1.0 / (ax[k] * ax[k]);
+        const double r0 = R[k], r1 = R[3 + k], r2 = R[6 + k];
+        A += inv[k] * r0 * r0;
+        by += inv[k] * r0 * r1;
+        bz += inv[k] * r0 * r2;
+        cyy += inv[k] * r1 * r1;
+        cyz += inv[k] * r1 * r2;
+        czz += inv[k] * r2 * r2;
+    }
+    const double iA = 1.0 / A;
+    const double amax = fmax(ax[0], fmax(ax[1], ax[2]));
+    const double fns = (double)ns;
+    const double mt = 1e-5 * (1.0 + amax) * fns;  // the margin in sample-index units
+    const double xb = (double)X - cen[0];          // sample a lies at x = xb + (a + 1/2) / ns
+    const double top = fns - 1.0;
+    // per z-sample plane, the rows that can meet the ellipsoid: those where
+    // disc(dy) = a2 dy^2 + a1 dy + a0 >= 0 (a2 < 0), widened by my = 1e-3;
+    // outside that range disc <= a2 my^2 < 0, far beyond its rounding, so
+    // every sample of such a row is outside
+    const double a2 = by * by - A * cyy;
+    const double my = 1e-3;
+    int cnt = 0;
+    // one sample with the definition's rounding and evaluation order
+    auto exact = [&](int a, double dy, double dz) -> int {
+        const double dx = ((double)X + off[a]) - cen[0];
+        const double p0 = (R[0] * dx + R[3] * dy) + R[6] * dz;
+        const double p1 = (R[1] * dx + R[4] * dy) + R[7] * dz;
+        const double p2 = (R[2] * dx + R[5] * dy) + R[8] * dz;
+        return (((p0 * p0) * inv[0] + (p1 * p1) * inv[1]) + (p2 * p2) * inv[2]) < 1.0 ? 1 : 0;
+    };
+#pragma unroll 1
+    for (int c = 0; c < ns; ++c) {
+        const double dz = ((double)Z + off[c]) - cen[2];
+        const double bzz = bz * dz, czzz = czz * dz * dz, cyzz = 2.0 * cyz * dz;
+        const double a1 = 2.0 * by * bzz - A * cyzz;
+        const double a0 = bzz * bzz - A * (czzz - 1.0);
+        const double D = a1 * a1 - 4.0 * a2 * a0;
+        if (D < -(1e-9 * (a1 * a1 + 4.0 * fabs(a2 * a0)) + 1e-12)) continue;  // the plane misses it
+        const double sD = sqrt(D > 0.0 ? D : 0.0);
+        const double y1 = (-a1 + sD) / (2.0 * a2), y2 = (-a1 - sD) / (2.0 * a2);
+        const double ylo = fmin(y1, y2) - my, yhi = fmax(y1, y2) + my;
+#pragma unroll 1
+        for (int b = 0; b < ns; ++b) {
+            const double dy = ((double)Y + off[b]) - cen[1];
+            if (dy < ylo || dy > yhi) continue;
+            const double B = by * dy + bzz;
+            const double Cm1 = (cyy * dy * dy + cyzz * dy + czzz) - 1.0;
+            const double disc = B * B - A * Cm1;
+            const double tol = 1e-6 * (B * B + A * fabs(Cm1)) + 1e-10;
+            if (disc <= -tol) continue;  // the row misses the ellipsoid
+            if (disc < tol) {            // a row grazing the surface
+                for (int a = 0; a < ns; ++a) cnt += exact(a, dy, dz);
+                continue;
+            }
+            const double sq = sqrt(disc);
+            const double t1 = ((-B - sq) * iA - xb) * fns - 0.5;
+            const double t2 = ((-B + sq) * iA - xb) * fns - 0.5;
+            // samples inside by the margin: t1 + mt < a < t2 - mt
+            const double lo = fmax(floor(t1 + mt) + 1.0, 0.0), hi = fmin(ceil(t2 - mt) - 1.0, top);
+            cnt += hi >= lo ? (int)(hi - lo) + 1 : 0;
+            // samples within the margin of a root
+            const double u0 = fmax(ceil(t1 - mt), 0.0), u1 = fmin(floor(t1 + mt), top);
+            for (double a = u0; a <= u1; a += 1.0) cnt += exact((int)a, dy, dz);
+            const double v0 = fmax(ceil(t2 - mt), 0.0), v1 = fmin(floor(t2 + mt), top);
+            for (double a = v0; a <= v1; a += 1.0)
+                if (!(fabs(a - t1) <= mt)) cnt += exact((int)a, dy, dz);
+        }
+    }
+    return cnt;
+}
+
 // 2. every boundary cell of the step.  Each wave takes 64 consecutive items,
-// one per lane: sphere cells (up to VOX_NS_REG samples per direction) are
-// counted by their own lane; the wave then counts the remaining cells of its
-// chunk (ellipsoids, finer sampling) one after the other, all lanes together.
+// one per lane: with up to VOX_NS_REG samples per direction every cell is
+// counted by its own lane (spheres sample by sample, ellipsoids row by row);
+// with finer sampling the wave counts the cells of its chunk one after the
+// other, all lanes together.
 __global__ __launch_bounds__(VOX_T) void k_vox_sample(VoxArgs A) {
     __shared__ VoxPart pw[VOX_T / 64];
     __shared__ double off[32];
@@ -994,11 +1139,15 @@ __global__ __launch_bounds__(VOX_T) void k_vox_sample(VoxArgs A) {
         const int4 it = A.items[valid ? i : n - 1];
         const int k = it.w < A.p.np ? it.w : 0;
         const int shape = A.p.shape[k];
-        const bool lane_sph = valid && shape == 0 && ns <= VOX_NS_REG;
-        if (lane_sph) {
+        const bool lane_sph = valid && ns <= VOX_NS_REG;
+        if (lane_sph && shape == 0) {
             const int cnt = sphere_count_lane_ns(ns, A.p.pos[3 * k], A.p.pos[3 * k + 1], A.p.pos[3 * k + 2],
                                                  A.p.semi[3 * k], it.x, it.y, it.z, off);
             A.item_cnt[i] = cnt;
+        } else if (lane_sph) {
+            double R[9];
+            quat_rbw(A.p.q + 4 * k, R);
+            A.item_cnt[i] = ellipsoid_count_lane(A.p.pos + 3 * k, A.p.semi + 3 * k, R, it.x, it.y, it.z, off, ns);
         }
         unsigned long long rest = __ballot(valid && !lane_sph);
         while (rest) {
@@ -1118,6 +1267,7 @@ hipError_t vox_register(const VoxArgs& A, int* scan_tmp, hipStream_t s) {
 hipError_t vox_voxelize(const VoxArgs& A, int ctype_double, hipStream_t s) {
     const unsigned nt = (unsigned)A.g.ntiles;
     const bool sort = A.g.ntiles <= VOX_SORT_IN_TILE_MAX;
+    if (A.vpart && A.p.np > 0) k_vox_parts<<<nblk(A.p.np), 256, 0, s>>>(A);
     if (A.sf_method == 0) {
         if (sort) k_vox_classify<true><<<nt, VOX_T, 0, s>>>(A);
         else k_vox_classify<false><<<nt, VOX_T, 0, s>>>(A);
@@ -1158,3 +1308,6 @@ hipError_t vox_reduce_hydro(const VoxArgs& A, hipStream_t s) {
     k_reduce_hydro<<<nblk(64LL * A.p.np), 256, 0, s>>>(A);
     return hipGetLastError();
 }
+
+size_t vox_part_bytes() { return sizeof(VoxPart); }
+

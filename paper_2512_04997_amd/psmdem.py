@@ -146,7 +146,8 @@ def lib():
     L.psmdem_version.restype = C.c_char_p
     L.psmdem_version.argtypes = []
     for name in ("psmdem_step", "psmdem_sync", "psmdem_stage", "psmdem_read_populations",
-                 "psmdem_write_populations", "psmdem_read_fields", "psmdem_read_particles",
+                 "psmdem_write_populations", "psmdem_read_fields",
+                 "psmdem_read_particles",
                  "psmdem_write_particles", "psmdem_read_predicted", "psmdem_write_predicted",
                  "psmdem_read_pairs", "psmdem_write_pairs", "psmdem_read_contacts",
                  "psmdem_read_cells", "psmdem_read_solid", "psmdem_counters", "psmdem_info",
@@ -394,6 +395,7 @@ class Domain:
         _check(lib().psmdem_write_populations(self.h, _ptr(f)))
 
     def fields(self):
+        """Density [N] and velocity [N, 3]."""
         rho = np.zeros(self.N)
         u = np.zeros(3 * self.N)
         self._rd(lib().psmdem_read_fields(self.h, _ptr(rho), _ptr(u)))

@@ -34,10 +34,15 @@ def test_ellipsoid_kolmogorov_precision(case, prec):
     ps, cfg, parts, ref = case
     G = ps.Domain(dict(cfg, precision=prec), parts)
     G.step(STEPS)
-    e = {"pop": pop_err(G.populations(), ref["f"]), "u": vec_err(G.fields()[1], ref["u"])}
+    # velocities against the protocol's floor of 1e-3 (the lattice velocity
+    # scale; the forced flow is still about 1e-4 after 100 steps, so its FP64
+    # rounding relative to max |u| alone grows past 1e-12)
+    e = {"pop": pop_err(G.populations(), ref["f"]), "u": vec_err(G.fields()[1], ref["u"], 1e-3)}
     P = G.particles()
     e["pos"] = vec_err(P["pos"], ref["P"]["pos"])
-    e["vel"] = vec_err(P["vel"], ref["P"]["vel"])
+    e["vel"] = vec_err(P["vel"], ref["P"]["vel"], 1e-3)
+    print(f"{prec}: max |u| {np.abs(ref['u']).max():.3e}, max |v| {np.abs(ref['P']['vel']).max():.3e}, "
+          f"u error against max |u| alone {vec_err(G.fields()[1], ref['u']):.3e}")
     e.update(hyd_errs(P, ref["P"], ref["sc"], "fp64" if prec == "fp64" else "fp32"))
     print(f"{prec} errors after {STEPS} coupled steps vs the FP64 oracle:", e)
     if prec == "fp64":

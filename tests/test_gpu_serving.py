@@ -172,3 +172,26 @@ def test_rejects_jobs_it_cannot_batch(ps):
     assert S.job(j)["state"] == "done"
     S.release(j)
     S.close()
+
+
+def test_rejects_a_job_larger_than_the_budget(ps):
+    """A job whose footprint alone exceeds the HBM budget is refused with
+    PSMDEM_E_INVALID at submission; one that fits is admitted and runs."""
+    small = W.base_config((32, 32, 32), 0.7, precision="fp32")
+    big = W.base_config((128, 128, 128), 0.7, precision="fp32")
+    fs, fb = ps.footprint(small), ps.footprint(big)
+    assert fb > 4 * fs
+    S = ps.Server(max_jobs=2, hbm_budget=2 * fs, precision="fp32")
+    with pytest.raises(ps.PsmdemError) as e:
+        S.submit(big, None, 5)
+    assert e.value.code == ps.E_INVALID
+    j = S.submit(small, None, 3)
+    for _ in range(20):
+        n_active, n_queued = S.iterate()
+        if n_active == 0 and n_queued == 0:
+            break
+    S.drain()
+    assert S.job(j)["state"] == "done" and S.job(j)["footprint"] == fs
+    S.release(j)
+    S.close()
+
