@@ -98,6 +98,8 @@ struct DevCounters {
     unsigned long long dropped;
     unsigned long long contacts;
     unsigned long long items;     // boundary cells queued for sampling this step
+    unsigned long long ell_work;  // ellipsoid pairs deferred to the iteration kernel this substep
+    unsigned long long blocks_done;  // blocks of the current predictor launch that finished (last one decides)
 };
 
 // ---------------------------------------------------------------------------

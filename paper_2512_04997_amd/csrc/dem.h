@@ -37,6 +37,8 @@ struct DemArgs {
                            // saved at the end of a launch for the next one (null: not kept)
     int* list_flag;        // [2] multi-launch path: the list changed in this substep (by substep parity)
     const int* list_run;   // multi-launch path: list_flag of this substep, or null (always build)
+    int* ell_list;         // [pair_cap] multi-launch path: pairs whose ellipsoid iteration is deferred to
+                           // a dense second launch (counted in ctr->ell_work), or null (no ellipsoids)
     DevCounters* ctr;
 };
 
@@ -60,10 +62,13 @@ struct PairSet {
 hipError_t dem_predict(const DemArgs& A, double dt, int write_kin, hipStream_t s);
 hipError_t dem_lists(const DemArgs& A, const PairBufs& B, int* scan_tmp, hipStream_t s);
 // multi-launch substeps that keep an unchanged list (A.list_run = A.list_flag + par)
+// (the predictor's last workgroup decides whether the substep rebuilds its list)
 hipError_t dem_predict_keep(const DemArgs& A, double dt, int write_kin, int par, hipStream_t s);
 hipError_t dem_lists_kept(const DemArgs& A, const PairBufs& B, int par, int* scan_tmp, hipStream_t s);
+// contacts and DEM sums; correct = 1 also runs each particle's corrector with
+// dt = dth after its sums (substeps whose corrector needs no hydrodynamic sums)
 hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, const double* ww, double dth,
-                        int* scan_tmp, hipStream_t s);
+                        int* scan_tmp, hipStream_t s, int correct = 0);
 hipError_t dem_correct(const DemArgs& A, double dt, hipStream_t s);
 // hydrodynamic sums of the tile partials (T) and the corrector, one launch
 hipError_t dem_hydro_correct(const DemArgs& A, const TileArgs& T, double dt, hipStream_t s);

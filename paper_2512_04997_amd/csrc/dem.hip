@@ -243,6 +243,7 @@ __device__ bool ell_line_hit(const double* c, const double* R, const double* ax,
 struct Geom {
     double delta, en[3], rci[3], rcj[3], rhoi, rhoj;
     bool sphere_law;
+    bool deferred;   // an ellipsoid pair within bounding-sphere reach left to the iteration kernel
 };
 
 __device__ void ellipsoid_pair(const DemArgs& A, int i, int j, Geom& G) {
@@ -315,9 +316,10 @@ __device__ void ellipsoid_pair(const DemArgs& A, int i, int j, Geom& G) {
 // ellipsoids), which keeps the register budget of the contact kernels small.
 template <bool ELL>
 __device__ void pair_geometry(const DemArgs& A, int i, int j, const double* ci, const double* cj, int shi, int shj,
-                              double ri, double rj, Geom& G) {
+                              double ri, double rj, Geom& G, bool defer = false) {
     const int np = A.p.np;
     G.sphere_law = false;
+    G.deferred = false;
     if (j >= np) {
         int f = j - np, a = f / 2;
         // the wall normal and the centre's coordinate along it, by selects
@@ -380,6 +382,10 @@ __device__ void pair_geometry(const DemArgs& A, int i, int j, const double* ci, 
     double rs = A.p.rb[i] + A.p.rb[j];
     if (!(r2 < rs * rs)) {
         G.delta = -1.0;
+        return;
+    }
+    if (defer) {
+        G.deferred = true;
         return;
     }
     ellipsoid_pair(A, i, j, G);
@@ -527,10 +533,13 @@ __device__ inline long long n_pairs(const DemArgs& A, const PairBufs& B) {
 // history of pair s sits at index s.
 // Returns whether the pair is in contact; out of contact, *gap (when given)
 // receives the separation -delta.
+// With deferred non-null, an ellipsoid pair that needs the iteration is not
+// evaluated: *deferred is set and the pair's outputs are left to a later
+// ph_contact call (the dense iteration kernel).
 template <bool ELL>
 __device__ bool ph_contact(const DemArgs& A, const PairBufs& B, long long s, const double* __restrict__ vv,
                            const double* __restrict__ ww, double dth, long long nprev, bool same_list = false,
-                           double* gap = nullptr) {
+                           double* gap = nullptr, bool* deferred = nullptr) {
     const int np = A.p.np;
     const unsigned long long key = B.pairs[s];
     const int i = (int)(key >> 32), j = (int)(key & 0xffffffffu);
@@ -545,7 +554,11 @@ __device__ bool ph_contact(const DemArgs& A, const PairBufs& B, long long s, con
         if (!wall) cj[k] = A.p.pos[3 * j + k];
     }
     Geom G;
-    pair_geometry<ELL>(A, i, j, ci, cj, shi, shj, ri, rj, G);
+    pair_geometry<ELL>(A, i, j, ci, cj, shi, shj, ri, rj, G, deferred != nullptr);
+    if (ELL && G.deferred) {
+        *deferred = true;
+        return false;
+    }
     double* F = A.cF + 3 * s;
     double* Mi = A.cMi + 3 * s;
     double* Mj = A.cMj + 3 * s;
@@ -906,11 +919,21 @@ __global__ void k_predict(DemArgs A, double dt, int write_kin) {
     }
 }
 
+// the substep's decision: rebuild when something changed or no list is kept
+__device__ inline void list_age_decide(const DemArgs& A, int par) {
+    const int age = __hip_atomic_load(A.fused_age, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int flag = __hip_atomic_load(&A.list_flag[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int ch = flag != 0 || age < 0;
+    A.list_flag[par] = ch;
+    *A.fused_age = ch ? 0 : age + 1;
+}
+
 // Multi-launch substeps keep the pair list while it is unchanged: the
 // predictor also compares each particle's new cells and wall candidates with
 // the stored ones (those of the last substep, so of the list) and raises
 // list_flag[par]; it clears the other parity's flag for the next substep.
 __global__ void k_predict_keep(DemArgs A, double dt, int write_kin, int par) {
+    __shared__ bool last_block;
     if (blockIdx.x == 0 && threadIdx.x == 0) A.list_flag[par ^ 1] = 0;
     GRID_LOOP(k, A.p.np) {
         const int kk = (int)k;
@@ -937,14 +960,19 @@ __global__ void k_predict_keep(DemArgs A, double dt, int write_kin, int par) {
         for (int a = 0; a < 3; ++a) ch |= ((unsigned)r.c[a][0] | ((unsigned)r.c[a][1] << 16)) != old[a];
         if (ch) atomicOr(&A.list_flag[par], 1);
     }
-}
-
-// the substep's decision: rebuild when something changed or no list is kept
-__global__ void k_list_age(DemArgs A, int par) {
-    const int age = *A.fused_age;
-    const int ch = A.list_flag[par] != 0 || age < 0;
-    A.list_flag[par] = ch;
-    *A.fused_age = ch ? 0 : age + 1;
+    // the last block to finish takes the substep's decision (list_age_decide):
+    // every block's flag update is ordered before its count by the fence
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last_block = atomicAdd(&A.ctr->blocks_done, 1ull) == (unsigned long long)gridDim.x - 1ull;
+    }
+    __syncthreads();
+    if (last_block && threadIdx.x == 0) {
+        __threadfence();
+        A.ctr->blocks_done = 0;
+        list_age_decide(A, par);
+    }
 }
 
 // one substep after a rebuild the kept list is copied into this buffer
@@ -1099,13 +1127,44 @@ __global__ __launch_bounds__(256) void k_pairemit(DemArgs A, PairBufs B) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
+// Contacts of the substep's pairs.  With ellipsoids, the pairs that need the
+// iterated equivalent spheres (ellipsoid pairs within bounding-sphere reach,
+// a small share of the candidates) are queued, one atomic per wave, and
+// evaluated by k_contacts_ell with every lane busy: in place they would hold
+// most waves for 32 iterations with a few lanes working.  Each pair writes
+// only its own outputs, so the queue order does not matter.
 template <bool ELL>
 __global__ __launch_bounds__(256) void k_contacts(DemArgs A, PairBufs B, const double* vv, const double* ww, double dth) {
     long long nprev = B.prev_n ? *B.prev_n : 0;
     nprev = nprev < A.pair_cap ? nprev : A.pair_cap;
     const long long n = n_pairs(A, B);
     const bool same = A.list_run && !*A.list_run;  // a kept list: history at the pair's own index
-    GRID_LOOP(s, n) ph_contact<ELL>(A, B, s, vv, ww, dth, nprev, same);
+    const bool defer = ELL && A.ell_list != nullptr;
+    GRID_LOOP(s, n) {
+        bool deferred = false;
+        ph_contact<ELL>(A, B, s, vv, ww, dth, nprev, same, nullptr, defer ? &deferred : nullptr);
+        if (ELL && defer) {
+            const unsigned long long m = __ballot(deferred);
+            if (m) {
+                const int lane = threadIdx.x & 63, leader = __ffsll((long long)m) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd(&A.ctr->ell_work, (unsigned long long)__popcll(m));
+                base = __shfl(base, leader, 64);
+                if (deferred) A.ell_list[base + __popcll(m & ((1ull << lane) - 1ull))] = (int)s;
+            }
+        }
+    }
+}
+
+// the queued ellipsoid pairs, one per lane (the queue is emptied by k_sum_wave)
+__global__ __launch_bounds__(64) void k_contacts_ell(DemArgs A, PairBufs B, const double* vv, const double* ww,
+                                                     double dth) {
+    long long nprev = B.prev_n ? *B.prev_n : 0;
+    nprev = nprev < A.pair_cap ? nprev : A.pair_cap;
+    long long n = (long long)A.ctr->ell_work;
+    n = n < A.pair_cap ? n : A.pair_cap;
+    const bool same = A.list_run && !*A.list_run;
+    GRID_LOOP(w, n) ph_contact<true>(A, B, (long long)A.ell_list[w], vv, ww, dth, nprev, same);
 }
 __global__ void k_colhist(DemArgs A, PairBufs B) {
     if (A.list_run && !*A.list_run) return;
@@ -1147,8 +1206,12 @@ __global__ __launch_bounds__(256) void k_colsort(DemArgs A) {
 // with their in-contact flags and forces at once; lane 0 adds the terms of
 // the pairs in contact in that order.  A pair out of contact holds zero forces,
 // whose terms leave a sum unchanged.
-__global__ __launch_bounds__(256) void k_sum_wave(DemArgs A, PairBufs B) {
+// DEM sums of every particle, one wave per particle; with correct set the
+// wave's lane 0 then runs the particle's corrector (substeps before the last,
+// whose corrector follows the hydrodynamic sums)
+__global__ __launch_bounds__(256) void k_sum_wave(DemArgs A, PairBufs B, int correct, double dt) {
     const int lane = threadIdx.x & 63;
+    if (blockIdx.x == 0 && threadIdx.x == 0) A.ctr->ell_work = 0;  // the contacts' queue, for the next substep
     const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
     const long long cap = A.pair_cap;
     for (long long w = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < A.p.np; w += nw) {
@@ -1196,12 +1259,14 @@ __global__ __launch_bounds__(256) void k_sum_wave(DemArgs A, PairBufs B) {
                 }
             }
         }
-        if (lane == 0)
+        if (lane == 0) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 A.p.fd[3 * i + c] = F[c];
                 A.p.md[3 * i + c] = M[c];
             }
+            if (correct) ph_correct(A, i, dt);
+        }
     }
 }
 __global__ void k_correct(DemArgs A, double dt) { GRID_LOOP(k, A.p.np) ph_correct(A, (int)k, dt); }
@@ -1826,7 +1891,6 @@ hipError_t dem_predict_keep(const DemArgs& A, double dt, int write_kin, int par,
 hipError_t dem_lists_kept(const DemArgs& A, const PairBufs& B, int par, int* scan_tmp, hipStream_t s) {
     if (A.p.np == 0) return hipSuccess;
     hipError_t e;
-    k_list_age<<<1, 1, 0, s>>>(A, par);
     k_list_copy<<<nblk_list(A.pair_cap), 256, 0, s>>>(A, B, par);
     k_hist<<<nblk_list(A.p.np), 256, 0, s>>>(A);
     if ((e = psm_scan(A.cell_count, A.cell_start, A.ncell, scan_tmp, s, A.list_run)) != hipSuccess) return e;
@@ -1854,16 +1918,23 @@ hipError_t dem_lists(const DemArgs& A, const PairBufs& B, int* scan_tmp, hipStre
 }
 
 hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, const double* ww, double dth,
-                        int* scan_tmp, hipStream_t s) {
+                        int* scan_tmp, hipStream_t s, int correct) {
     if (A.p.np == 0) return hipSuccess;
     hipError_t e;
-    if (A.ellipsoids) k_contacts<true><<<nblk(A.pair_cap, 128), 128, 0, s>>>(A, B, vv, ww, dth);
-    else k_contacts<false><<<nblk(A.pair_cap, 128), 128, 0, s>>>(A, B, vv, ww, dth);
+    if (A.ellipsoids) {
+        k_contacts<true><<<nblk(A.pair_cap, 128), 128, 0, s>>>(A, B, vv, ww, dth);
+        if (A.ell_list) {
+            const unsigned nb = nblk(A.pair_cap, 64);
+            k_contacts_ell<<<nb < 4096 ? nb : 4096, 64, 0, s>>>(A, B, vv, ww, dth);
+        }
+    } else {
+        k_contacts<false><<<nblk(A.pair_cap, 128), 128, 0, s>>>(A, B, vv, ww, dth);
+    }
     k_colhist<<<nblk_list(A.pair_cap), 256, 0, s>>>(A, B);
     if ((e = psm_scan(A.col_count, A.col_start, A.p.np, scan_tmp, s, A.list_run)) != hipSuccess) return e;
     k_colscatter<<<nblk_list(A.pair_cap), 256, 0, s>>>(A, B);
     k_colsort<<<nblk_list(64LL * A.p.np), 256, 0, s>>>(A);
-    k_sum_wave<<<nblk(64LL * A.p.np), 256, 0, s>>>(A, B);
+    k_sum_wave<<<nblk(64LL * A.p.np), 256, 0, s>>>(A, B, correct, dth);
     return hipGetLastError();
 }
 

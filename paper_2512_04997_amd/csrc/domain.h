@@ -54,17 +54,15 @@ struct psmdem_domain {
     double* hist[2] = {nullptr, nullptr};
     double *cF = nullptr, *cMi = nullptr, *cMj = nullptr;
     unsigned char* incontact = nullptr;
+    int* ell_list = nullptr;
     long long pair_cap = 0;
     int cur = 0;
     // voxel / tiles
     TileArgs t{};
     int* tile_count = nullptr;
     int* tile_fill = nullptr;
-    unsigned short* lane_items = nullptr;
-    int* tile_items = nullptr;
-    int4* items = nullptr;
-    int* item_cnt = nullptr;
-    long long item_cap = 0;
+    unsigned short* vbox = nullptr;
+    long long box_stride = 0;
     void* vpart = nullptr;
     int* scan_tmp = nullptr;
     DevCounters* ctr = nullptr;
@@ -166,6 +164,7 @@ struct psmdem_domain {
             for (int c = 0; c < 3; ++c) A.wall_u[f_][c] = d.wall_u[f_][c];
         A.ellipsoids = 0;
         for (int sh : h_shape) A.ellipsoids |= sh != 0;
+        A.ell_list = ell_list;
         A.ctr = ctr;
         return A;
     }
@@ -204,11 +203,8 @@ struct psmdem_domain {
         A.Rc = Rc;
         A.tau = d.tau;
         A.ms = d.max_solids;
-        A.lane_items = lane_items;
-        A.tile_items = tile_items;
-        A.items = items;
-        A.item_cnt = item_cnt;
-        A.item_cap = item_cap;
+        A.vbox = vbox;
+        A.box_stride = box_stride;
         A.vpart = vpart;
         A.ctr = ctr;
         return A;

@@ -175,18 +175,18 @@ static int coupled_step(psmdem_domain* D) {
             D->cur ^= 1;
             PairBufs B = D->pair_bufs(1);
             PSM_CHECK(dem_lists_kept(A, B, par, D->scan_tmp, D->s));
-            PSM_CHECK(dem_contacts(A, B, D->p.vp, D->p.wp, D->dt, D->scan_tmp, D->s));
+            // the corrector runs with the DEM sums, except in the last substep with
+            // the fluid on, where it follows the hydrodynamic sums
+            const bool couple = last && D->d.fluid_on;
+            PSM_CHECK(dem_contacts(A, B, D->p.vp, D->p.wp, D->dt, D->scan_tmp, D->s, couple ? 0 : 1));
             D->timed_end(tk);
-            if (last && D->d.fluid_on) {
+            if (couple) {
                 if ((rc = run_voxelize(D))) return rc;
                 if ((rc = run_lbm(D, false))) return rc;
                 tk = D->timed_begin(PSMDEM_T_HYDRO);
                 PSM_CHECK(dem_hydro_correct(A, D->t, D->dt, D->s));
-            } else {
-                tk = D->timed_begin(PSMDEM_T_DEM);
-                PSM_CHECK(dem_correct(A, D->dt, D->s));
+                D->timed_end(tk);
             }
-            D->timed_end(tk);
         }
     } else if (D->d.fluid_on) {
         if (D->np > 0) k_kin<<<nblk(D->np), 256, 0, D->s>>>(D->p, 1);
@@ -428,6 +428,9 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
     D->cMi = (double*)A(sizeof(double) * 3 * D->pair_cap);
     D->cMj = (double*)A(sizeof(double) * 3 * D->pair_cap);
     D->incontact = (unsigned char*)A(D->pair_cap);
+    bool any_ell = false;
+    for (int k = 0; k < np; ++k) any_ell = any_ell || D->h_shape[k] != 0;
+    if (any_ell) D->ell_list = (int*)A(sizeof(int) * D->pair_cap);
     D->col_count = (int*)A(sizeof(int) * std::max(np, 1));
     D->col_fill = (int*)A(sizeof(int) * std::max(np, 1));
     D->col_start = (int*)A(sizeof(int) * (np + 1));
@@ -456,15 +459,17 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
     D->tile_count = (int*)A(sizeof(int) * g.ntiles);
     D->tile_fill = (int*)A(sizeof(int) * g.ntiles);
     if (np > 0) D->vpart = A(vox_part_bytes() * (size_t)np);
-    // boundary cells sampled per step: about twice the shell of the largest
-    // bounding sphere per particle (more are sampled in place, slower)
+    // subdivision method: one count box per particle, sized for the largest
+    // lattice box (per axis at most floor(2 r_b + 2e-6) + 2 cells)
     if (np > 0 && d.sf_method == 0) {
-        D->item_cap = std::min<long long>((long long)np * (long long)ceil(8.0 * M_PI * (rbmax + 1.0) * (rbmax + 1.0)),
-                                          1LL << 30);
-        D->lane_items = (unsigned short*)A(sizeof(unsigned short) * 256 * g.ntiles);
-        D->tile_items = (int*)A(sizeof(int) * g.ntiles);
-        D->items = (int4*)A(sizeof(int4) * D->item_cap);
-        D->item_cnt = (int*)A(sizeof(int) * D->item_cap);
+        const long long side = (long long)floor(2.0 * rbmax + 2e-6) + 2;
+        if (side * side > (long long)vox_box_cells_max()) {  // (the tile limit above keeps it far below)
+            delete D;
+            psm_set_error("particles too large for the solid-fraction count boxes");
+            return PSMDEM_E_INVALID;
+        }
+        D->box_stride = side * side * side;
+        D->vbox = (unsigned short*)A(sizeof(unsigned short) * (size_t)D->box_stride * np);
     }
     long long scan_n = std::max<long long>(std::max<long long>(D->ncell, g.ntiles), np + 1);
     D->scan_tmp = (int*)A(sizeof(int) * psm_scan_tmp_ints(scan_n));

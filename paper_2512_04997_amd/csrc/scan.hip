@@ -1,6 +1,7 @@
 // scan.hip -- device-wide exclusive prefix sum of int32 counts and a fill
 // kernel.  Up to SCAN_SMALL elements one workgroup of 1024 lanes scans in
-// chunks with a running carry (one launch); longer inputs take three
+// chunks with a running carry (one launch, which also returns at once when a
+// gating flag is clear: the kept-list substeps); longer inputs take three
 // launches: per-block scan of 1024 elements (256 lanes x 4), a single-block
 // scan of the block totals, and the block-offset add.
 #include "common.h"
@@ -87,7 +88,7 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_add(int* __restrict__ out, long
         if (base + k < n) out[base + k] += add;
 }
 
-constexpr long long SCAN_SMALL = 32768;
+constexpr long long SCAN_SMALL = 131072;
 
 // One workgroup of 1024 lanes walks the input in chunks of 4096 entries, four
 // consecutive entries per lane (coalesced), with a running carry (in place

@@ -15,23 +15,23 @@ struct VoxArgs {
     double Rc;           // (3 / (4 pi))^(1/3)
     double tau;
     int ms;              // solids kept per cell
-    // boundary cells of the step (three-kernel form)
-    unsigned short* lane_items;  // [ntiles * 256] boundary cells per lane
-    int* tile_items;             // [ntiles] first item of the tile
-    int4* items;                 // [item_cap] (X, Y, Z, pid), unwrapped cell indices
-    int* item_cnt;               // [item_cap] inside samples
-    long long item_cap;          // items beyond it are sampled in the select kernel
+    // subdivision method: each particle's count box, the inside samples of every
+    // cell of its lattice box (x fastest), 16 bits per cell, box_stride cells apart
+    unsigned short* vbox;
+    long long box_stride;
     void* vpart;                 // [np] per-step particle records of the tile kernels (vox_part_bytes
                                  // each), formed by vox_voxelize; null: each tile forms its own
     DevCounters* ctr;
 };
 
 // registration: the tile lists (on lattices of up to 8192 tiles left in
-// arbitrary order within a tile, which vox_voxelize's first per-tile kernel
-// then sets, clearing the registration counters: it follows every vox_register)
+// arbitrary order within a tile, which vox_voxelize's select kernel then
+// sets, clearing the registration counters: it follows every vox_register)
 hipError_t vox_register(const VoxArgs& A, int* scan_tmp, hipStream_t s);
 // voxelisation of registered tiles
 hipError_t vox_voxelize(const VoxArgs& A, int ctype_double, hipStream_t s);
 hipError_t vox_reduce_hydro(const VoxArgs& A, hipStream_t s);
 // bytes of one particle record (VoxArgs::vpart)
 size_t vox_part_bytes();
+// cells of a count box's x-y plane the row-counting kernel holds (per z-slab)
+size_t vox_box_cells_max();

@@ -5,20 +5,21 @@
 // integer count and is evaluated with separately rounded operations.
 //
 // Pipeline per coupled step:
+//   k_vox_parts    each particle's record (centre, rotation, extents, lattice box)
 //   k_vox_count    tiles touched by each particle's lattice box (count + tile histogram)
 //   (scans)        emission offsets per particle, list offsets per tile
 //   k_vox_scatter  counting-sort scatter of (pid, emission index) into tiles
 //   (k_tile_sort)  order each tile's list by pid; inverse map emission -> position
 //                  (lattices of up to VOX_SORT_IN_TILE_MAX tiles do this in the
-//                  first per-tile kernel below instead)
-//   k_vox_classify per tile: cells whose samples straddle a surface, queued as
-//                  items of the step (exact inside / outside shortcuts elsewhere)
-//   k_vox_sample   a lane per queued cell: its count of inside samples (spheres sample by
-//                  sample, ellipsoids row by row; a wave per cell above 12 samples per direction)
-//   k_vox_select   per tile: beta of every (cell, particle), keep the max_solids
-//                  largest (ties to the smaller pid), B_k, slots
+//                  select kernel instead)
+//   k_vox_rows     subdivision method: one workgroup per particle counts the
+//                  inside samples of every cell of its lattice box, a row of
+//                  samples at a time, into the particle's count box
+//   k_vox_select   per tile: beta of every (cell, particle) (a count-box entry, or
+//                  the distance formula), keep the max_solids largest (ties to
+//                  the smaller pid), B_k, slots
 //   k_reduce_hydro per particle: minus the sum of its tile partials (F, M)
-// Serving batches run classify, sample and select of a tile in one workgroup
+// Serving batches classify, sample and select a tile in one workgroup
 // (k_voxelize_batch); both forms count the same samples.
 #include <math.h>
 
@@ -399,79 +400,6 @@ __device__ int classify(const VoxPart& P, int X, int Y, int Z, double slo, doubl
     return 1;
 }
 
-// The sphere branch of classify split at its axis loop: the x and y terms of a
-// column once, then the z term per plane; the sums round in the same order,
-// so the result is classify's.
-struct SphCol {
-    double maxr2, minr2, R2, m;
-};
-
-__device__ inline SphCol sphere_column(const VoxPart& P, int X, int Y, double slo, double shi) {
-    SphCol s;
-    s.R2 = P.ax[0] * P.ax[0];
-    s.maxr2 = 0.0;
-    s.minr2 = 0.0;
-    const int Xc[2] = {X, Y};
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        const double dl = ((double)Xc[a] + slo) - P.c[a];
-        const double dh = ((double)Xc[a] + shi) - P.c[a];
-        const double l2 = dl * dl, h2 = dh * dh;
-        s.maxr2 += l2 > h2 ? l2 : h2;
-        s.minr2 += dl > 0.0 ? l2 : (dh < 0.0 ? h2 : 0.0);
-    }
-    s.m = 1e-8 * (1.0 + s.R2);
-    return s;
-}
-
-__device__ inline int sphere_class_z(const SphCol& s, double cz, int Z, double slo, double shi) {
-    const double dl = ((double)Z + slo) - cz;
-    const double dh = ((double)Z + shi) - cz;
-    const double l2 = dl * dl, h2 = dh * dh;
-    const double maxr2 = s.maxr2 + (l2 > h2 ? l2 : h2);
-    const double minr2 = s.minr2 + (dl > 0.0 ? l2 : (dh < 0.0 ? h2 : 0.0));
-    if (maxr2 < s.R2 - s.m) return 1;
-    if (minr2 > s.R2 + s.m) return 0;
-    return 2;
-}
-
-// Boundary cells (class 2) of a lane's column, visited candidate by candidate
-// (ascending pid) with the tile's planes unrolled: f(lz, u, P, X, Y, Z) for
-// each.  The per-plane visit order (pid ascending) is that of for_each_pair.
-template <typename F>
-__device__ inline void for_each_boundary_by_candidate(const VoxArgs& A, const VoxPart* sp, int tz, int x, int y,
-                                                      bool xy_ok, unsigned long long cm0, unsigned long long cm1,
-                                                      double slo, double shi, F f) {
-    if (!xy_ok) return;
-    for (int w = 0; w < 2; ++w)
-        for (unsigned long long bits = w ? cm1 : cm0; bits; bits &= bits - 1) {
-            const int u = 64 * w + __ffsll((long long)bits) - 1;
-            const VoxPart& P = sp[u];
-            int X, Y;
-            in_box(P, x, A.g.nx, 0, A.g.periodic[0], &X);
-            in_box(P, y, A.g.ny, 1, A.g.periodic[1], &Y);
-            if (P.shape == 0) {
-                const SphCol s = sphere_column(P, X, Y, slo, shi);
-                const double cz = P.c[2];
-#pragma unroll
-                for (int lz = 0; lz < PSM_TZ; ++lz) {
-                    const int z = tz * PSM_TZ + lz;
-                    int Z;
-                    if (z < A.g.nz && in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z) && sphere_class_z(s, cz, Z, slo, shi) == 2)
-                        f(lz, u, P, X, Y, Z);
-                }
-            } else {
-#pragma unroll 1
-                for (int lz = 0; lz < PSM_TZ; ++lz) {
-                    const int z = tz * PSM_TZ + lz;
-                    int Z;
-                    if (z < A.g.nz && in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z) && classify(P, X, Y, Z, slo, shi) == 2)
-                        f(lz, u, P, X, Y, Z);
-                }
-            }
-        }
-}
-
 // one sample m (a fastest): inside test in the evaluation order of the definition
 __device__ inline bool sample_in(const VoxPart& P, int X, int Y, int Z, const double* off, int ns, int m) {
     const int a = m % ns, b = (m / ns) % ns, c = m / (ns * ns);
@@ -744,9 +672,11 @@ __device__ inline int sample_count(const VoxPart& P, int X, int Y, int Z, const 
 }
 
 // Phase C: beta per (cell, particle) in pid order, keep the largest ms, write
-// the slots.  Boundary cells take their count from lookup(j, P, X, Y, Z), j
-// running from my_off in the order of for_each_pair.
-template <typename C, typename L>
+// the slots.  BOX: the subdivision count of every (cell, particle) is
+// lookup(j, P, X, Y, Z) (the count box); else boundary cells take their count
+// from lookup(j, P, X, Y, Z), j running from my_off in the order of
+// for_each_pair, and the others are classified.
+template <typename C, bool BOX, typename L>
 __device__ inline void select_slots(const VoxArgs& A, const VoxPart* sp, long long t, int tz, int x, int y, bool xy_ok,
                                     unsigned long long cm0, unsigned long long cm1, double slo, double shi,
                                     int my_off, L lookup, unsigned long long* cnt_e, unsigned long long* cnt_d) {
@@ -774,6 +704,8 @@ __device__ inline void select_slots(const VoxArgs& A, const VoxPart* sp, long lo
                     double beta;
                     if (!subdiv) {
                         beta = beta_distance(P, X, Y, Z, A.Rc);
+                    } else if (BOX) {
+                        beta = (double)lookup(j, P, X, Y, Z) / (double)n3;
                     } else {
                         const int cl = classify(P, X, Y, Z, slo, shi);
                         if (cl == 0) continue;
@@ -898,7 +830,7 @@ __device__ void voxelize_tile(const VoxArgs& A, const long long t) {
         if (lane == 0) qcnt[it] = cnt;
     }
     __syncthreads();
-    select_slots<C>(A, sp, t, R.tz, x, y, xy_ok, cm0, cm1, slo, shi, my_off,
+    select_slots<C, false>(A, sp, t, R.tz, x, y, xy_ok, cm0, cm1, slo, shi, my_off,
                     [&](int j, const VoxPart& P, int X, int Y, int Z) {
                         if (j < VOX_QCAP) return qcnt[j];
                         int cnt = 0;
@@ -909,291 +841,157 @@ __device__ void voxelize_tile(const VoxArgs& A, const long long t) {
 }
 
 // ---------------------------------------------------------------------------
-// three-kernel form: the sampling runs as its own launch over every boundary
-// cell of the step, balanced across the GPU
+// single-domain form: count boxes per particle, then the per-tile selection
 // ---------------------------------------------------------------------------
-// 1. per tile: count the boundary cells per lane, reserve the tile's range of
-//    the step's item list, queue (X, Y, Z, pid) of each boundary cell
-template <bool SORT>
-__global__ __launch_bounds__(VOX_T) void k_vox_classify(VoxArgs A) {
-    __shared__ VoxPart sp[PSM_PMAX];
+// Inside samples of every cell of particle P's lattice box, by one workgroup,
+// a row of samples at a time.  Along a row (fixed y and z offsets dy, dz) the
+// normalised test value is a quadratic in the x offset,
+//   Q(x) = A x^2 + 2 B x + C,   inside when Q < 1,
+// with A, B, C from the inverse shape matrix (an ellipsoid: p = R^T d and
+// A = sum_k inv_k R_0k^2, B = sum_k inv_k R_0k w_k, C = sum_k inv_k w_k^2,
+// w_k = R_1k dy + R_2k dz; a sphere: A = 1/r^2, B = 0, C = (dy^2 + dz^2)/r^2).
+// The inside samples of a row lie between the roots r1 < r2 of Q = 1.  A
+// sample farther than m = 1e-5 (1 + a_max) from both roots is decided by its
+// side, since there |Q - 1| >= A m min(m, r2 - r1) lies far above the
+// rounding of any evaluation of Q (the roots are formed only when the
+// discriminant clears its own rounding bound by a factor 1e6); samples within
+// m of a root, and every sample of a row whose discriminant is within that
+// bound of zero (a row grazing the surface), are tested with the definition's
+// own evaluation order.  Per z-sample plane only the rows whose discriminant
+// can be positive are visited: as a function of dy it is the concave
+// quadratic a2 dy^2 + a1 dy + a0, and outside its roots widened by 1e-3 it is
+// below a2 1e-6 < 0, far beyond its rounding.  The counts therefore equal the
+// per-sample definition's bit for bit; a row costs a root and a few
+// comparisons instead of one test per sample.  The counts accumulate in LDS
+// (z-slabs of the box that fit) and go to the particle's count box in global
+// memory, one 16-bit count per cell, x fastest.
+#define VOX_BOX_LDS 8192
+
+__device__ inline int sample_exact(const VoxPart& P, double dx, double dy, double dz) {
+    if (P.shape == 0) {
+        const double R2 = P.ax[0] * P.ax[0];
+        return ((dx * dx + dy * dy) + dz * dz) < R2 ? 1 : 0;
+    }
+    const double p0 = (P.R[0] * dx + P.R[3] * dy) + P.R[6] * dz;
+    const double p1 = (P.R[1] * dx + P.R[4] * dy) + P.R[7] * dz;
+    const double p2 = (P.R[2] * dx + P.R[5] * dy) + P.R[8] * dz;
+    return (((p0 * p0) * P.inv[0] + (p1 * p1) * P.inv[1]) + (p2 * p2) * P.inv[2]) < 1.0 ? 1 : 0;
+}
+
+__global__ __launch_bounds__(VOX_T) void k_vox_rows(VoxArgs A) {
+    __shared__ VoxPart P;
     __shared__ double off[32];
-    __shared__ int tcnt[VOX_T / 64];
-    __shared__ int tile_base;
-    __shared__ unsigned long long ks[SORT ? VOX_T : 1];
-    const long long t = blockIdx.x;
-    if (t >= A.g.ntiles) return;
-    const unsigned long long* keys = SORT ? sort_tile_list(A, t, ks) : nullptr;
-    const TileRange R = tile_range(A, t);
-    if (R.count <= 0) return;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    stage_particles(A, sp, off, R.s0, R.count, keys);
-    __syncthreads();
-    const double slo = off[0], shi = off[A.ns - 1];  // first and last sample offset
-    const int x = R.tx * PSM_TX + lane, y = R.ty * PSM_TY + wid;
-    const bool xy_ok = x < A.g.nx && y < A.g.ny;
-    unsigned long long cm0, cm1;
-    column_masks(A, sp, R.count, x, y, xy_ok, cm0, cm1);
-    int pc[PSM_TZ];
-#pragma unroll
-    for (int lz = 0; lz < PSM_TZ; ++lz) pc[lz] = 0;
-    for_each_boundary_by_candidate(A, sp, R.tz, x, y, xy_ok, cm0, cm1, slo, shi,
-                                   [&](int lz, int, const VoxPart&, int, int, int) {
-#pragma unroll
-                                       for (int l = 0; l < PSM_TZ; ++l) pc[l] += l == lz ? 1 : 0;
-                                   });
-    int mine = 0;
-#pragma unroll
-    for (int lz = 0; lz < PSM_TZ; ++lz) mine += pc[lz];
-    A.lane_items[t * VOX_T + tid] = (unsigned short)mine;
-    int my_off, total;
-    block_offsets(mine, tcnt, my_off, total);
-    if (tid == 0) {
-        // the first item of the tile, clamped to the capacity (beyond it the
-        // select kernel samples in place)
-        const unsigned long long b = atomicAdd(&A.ctr->items, (unsigned long long)total);
-        tile_base = (int)(b < (unsigned long long)A.item_cap ? b : (unsigned long long)A.item_cap);
-        A.tile_items[t] = tile_base;
-    }
-    __syncthreads();
-    if (mine) {
-        // item index of (plane lz, candidate u): the lane's plane-major order,
-        // pid ascending within a plane
-        int j[PSM_TZ];
-        j[0] = tile_base + my_off;
-#pragma unroll
-        for (int lz = 1; lz < PSM_TZ; ++lz) j[lz] = j[lz - 1] + pc[lz - 1];
-        for_each_boundary_by_candidate(A, sp, R.tz, x, y, xy_ok, cm0, cm1, slo, shi,
-                                       [&](int lz, int, const VoxPart& P, int X, int Y, int Z) {
-                                           int g = 0;
-#pragma unroll
-                                           for (int l = 0; l < PSM_TZ; ++l)
-                                               if (l == lz) g = j[l]++;
-                                           if (g < A.item_cap) A.items[g] = make_int4(X, Y, Z, P.pid);
-                                       });
-    }
-}
-
-// Inside samples of a sphere in cell (X, Y, Z), counted by ONE LANE: the
-// squared x offsets stay in registers, the y and z ones are formed per row
-// and layer; every sample is tested with the rounding and evaluation order of
-// the definition.  No cross-lane traffic, so a wave counts 64 cells at once
-// and its loads overlap freely.
-template <int NS>
-__device__ inline int sphere_count_lane(double c0, double c1, double c2, double R, int X, int Y, int Z,
-                                        const double* off) {
-    double x2[NS];
-#pragma unroll
-    for (int a = 0; a < NS; ++a) {
-        const double dx = ((double)X + off[a]) - c0;
-        x2[a] = dx * dx;
-    }
-    const double R2 = R * R;
-    int cnt = 0;
-#pragma unroll 1
-    for (int c = 0; c < NS; ++c) {
-        const double dz = ((double)Z + off[c]) - c2;
-        const double z2 = dz * dz;
-#pragma unroll 1
-        for (int b = 0; b < NS; ++b) {
-            const double dy = ((double)Y + off[b]) - c1;
-            const double y2 = dy * dy;
-#pragma unroll
-            for (int a = 0; a < NS; ++a) cnt += ((x2[a] + y2) + z2) < R2 ? 1 : 0;
-        }
-    }
-    return cnt;
-}
-
-__device__ inline int sphere_count_lane_ns(int ns, double c0, double c1, double c2, double R, int X, int Y, int Z,
-                                           const double* off) {
-    switch (ns) {
-        case 1: return sphere_count_lane<1>(c0, c1, c2, R, X, Y, Z, off);
-        case 2: return sphere_count_lane<2>(c0, c1, c2, R, X, Y, Z, off);
-        case 3: return sphere_count_lane<3>(c0, c1, c2, R, X, Y, Z, off);
-        case 4: return sphere_count_lane<4>(c0, c1, c2, R, X, Y, Z, off);
-        case 5: return sphere_count_lane<5>(c0, c1, c2, R, X, Y, Z, off);
-        case 6: return sphere_count_lane<6>(c0, c1, c2, R, X, Y, Z, off);
-        case 7: return sphere_count_lane<7>(c0, c1, c2, R, X, Y, Z, off);
-        case 8: return sphere_count_lane<8>(c0, c1, c2, R, X, Y, Z, off);
-        case 9: return sphere_count_lane<9>(c0, c1, c2, R, X, Y, Z, off);
-        case 10: return sphere_count_lane<10>(c0, c1, c2, R, X, Y, Z, off);
-        case 11: return sphere_count_lane<11>(c0, c1, c2, R, X, Y, Z, off);
-        default: return sphere_count_lane<12>(c0, c1, c2, R, X, Y, Z, off);
-    }
-}
-
-// Inside samples of an ellipsoid in cell (X, Y, Z), counted by ONE LANE a
-// sample row at a time.  Along a row (fixed y and z offsets) the test value
-// is a quadratic in the x offset, Q(x) = A x^2 + 2 B x + C with
-// A = sum_k inv_k R_0k^2, B = sum_k inv_k R_0k w_k, C = sum_k inv_k w_k^2 and
-// w_k = R_1k dy + R_2k dz (p = R^T d, R = Rbw).  The samples with Q < 1 lie
-// between the roots r1 < r2 of Q = 1.  A sample farther than m from both
-// roots is decided by its side: there |Q - 1| >= A m min(m, r2 - r1) is far
-// above the rounding of any evaluation of Q (with m = 1e-5 (1 + a_max), the
-// roots computed only when the discriminant clears its own rounding by the
-// factor 1e6).  Samples within m of a root, and every sample of a row whose
-// discriminant is within that rounding bound of zero (a row grazing the
-// surface), are tested with the definition's own evaluation order.  So the
-// count is the count of the per-sample definition, bit for bit, at a few
-// flops per row instead of per sample.
-__device__ inline int ellipsoid_count_lane(const double* cen, const double* ax, const double* R, int X, int Y, int Z,
-                                           const double* off, int ns) {
-    double inv[3], A = 0.0, by = 0.0, bz = 0.0, cyy = 0.0, cyz = 0.0, czz = 0.0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        inv[k] = 1.0 / (ax[k] * ax[k]);
-        const double r0 = R[k], r1 = R[3 + k], r2 = R[6 + k];
-        A += inv[k] * r0 * r0;
-        by += inv[k] * r0 * r1;
-        bz += inv[k] * r0 * r2;
-        cyy += inv[k] * r1 * r1;
-        cyz += inv[k] * r1 * r2;
-        czz += inv[k] * r2 * r2;
-    }
-    const double iA = 1.0 / A;
-    const double amax = fmax(ax[0], fmax(ax[1], ax[2]));
-    const double fns = (double)ns;
-    const double mt = 1e-5 * (1.0 + amax) * fns;  // the margin in sample-index units
-    const double xb = (double)X - cen[0];          // sample a lies at x = xb + (a + 1/2) / ns
-    const double top = fns - 1.0;
-    // per z-sample plane, the rows that can meet the ellipsoid: those where
-    // disc(dy) = a2 dy^2 + a1 dy + a0 >= 0 (a2 < 0), widened by my = 1e-3;
-    // outside that range disc <= a2 my^2 < 0, far beyond its rounding, so
-    // every sample of such a row is outside
-    const double a2 = by * by - A * cyy;
-    const double my = 1e-3;
-    int cnt = 0;
-    // one sample with the definition's rounding and evaluation order
-    auto exact = [&](int a, double dy, double dz) -> int {
-        const double dx = ((double)X + off[a]) - cen[0];
-        const double p0 = (R[0] * dx + R[3] * dy) + R[6] * dz;
-        const double p1 = (R[1] * dx + R[4] * dy) + R[7] * dz;
-        const double p2 = (R[2] * dx + R[5] * dy) + R[8] * dz;
-        return (((p0 * p0) * inv[0] + (p1 * p1) * inv[1]) + (p2 * p2) * inv[2]) < 1.0 ? 1 : 0;
-    };
-#pragma unroll 1
-    for (int c = 0; c < ns; ++c) {
-        const double dz = ((double)Z + off[c]) - cen[2];
-        const double bzz = bz * dz, czzz = czz * dz * dz, cyzz = 2.0 * cyz * dz;
-        const double a1 = 2.0 * by * bzz - A * cyzz;
-        const double a0 = bzz * bzz - A * (czzz - 1.0);
-        const double D = a1 * a1 - 4.0 * a2 * a0;
-        if (D < -(1e-9 * (a1 * a1 + 4.0 * fabs(a2 * a0)) + 1e-12)) continue;  // the plane misses it
-        const double sD = sqrt(D > 0.0 ? D : 0.0);
-        const double y1 = (-a1 + sD) / (2.0 * a2), y2 = (-a1 - sD) / (2.0 * a2);
-        const double ylo = fmin(y1, y2) - my, yhi = fmax(y1, y2) + my;
-#pragma unroll 1
-        for (int b = 0; b < ns; ++b) {
-            const double dy = ((double)Y + off[b]) - cen[1];
-            if (dy < ylo || dy > yhi) continue;
-            const double B = by * dy + bzz;
-            const double Cm1 = (cyy * dy * dy + cyzz * dy + czzz) - 1.0;
-            const double disc = B * B - A * Cm1;
-            const double tol = 1e-6 * (B * B + A * fabs(Cm1)) + 1e-10;
-            if (disc <= -tol) continue;  // the row misses the ellipsoid
-            if (disc < tol) {            // a row grazing the surface
-                for (int a = 0; a < ns; ++a) cnt += exact(a, dy, dz);
-                continue;
-            }
-            const double sq = sqrt(disc);
-            const double t1 = ((-B - sq) * iA - xb) * fns - 0.5;
-            const double t2 = ((-B + sq) * iA - xb) * fns - 0.5;
-            // samples inside by the margin: t1 + mt < a < t2 - mt
-            const double lo = fmax(floor(t1 + mt) + 1.0, 0.0), hi = fmin(ceil(t2 - mt) - 1.0, top);
-            cnt += hi >= lo ? (int)(hi - lo) + 1 : 0;
-            // samples within the margin of a root
-            const double u0 = fmax(ceil(t1 - mt), 0.0), u1 = fmin(floor(t1 + mt), top);
-            for (double a = u0; a <= u1; a += 1.0) cnt += exact((int)a, dy, dz);
-            const double v0 = fmax(ceil(t2 - mt), 0.0), v1 = fmin(floor(t2 + mt), top);
-            for (double a = v0; a <= v1; a += 1.0)
-                if (!(fabs(a - t1) <= mt)) cnt += exact((int)a, dy, dz);
-        }
-    }
-    return cnt;
-}
-
-// 2. every boundary cell of the step.  Each wave takes 64 consecutive items,
-// one per lane: with up to VOX_NS_REG samples per direction every cell is
-// counted by its own lane (spheres sample by sample, ellipsoids row by row);
-// with finer sampling the wave counts the cells of its chunk one after the
-// other, all lanes together.
-__global__ __launch_bounds__(VOX_T) void k_vox_sample(VoxArgs A) {
-    __shared__ VoxPart pw[VOX_T / 64];
-    __shared__ double off[32];
-    __shared__ double tab_s[(VOX_T / 64) * 9 * 32];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    __shared__ int cnt_s[VOX_BOX_LDS];
+    const int k = blockIdx.x;
+    if (k >= A.p.np) return;
+    const int tid = threadIdx.x;
     if (tid < A.ns) off[tid] = (double)(2 * tid + 1) / (double)(2 * A.ns);
+    if (tid == 0) P = ((const VoxPart*)A.vpart)[k];
     __syncthreads();
-    long long n = (long long)A.ctr->items;
-    n = n < A.item_cap ? n : A.item_cap;
-    if (n <= 0) return;
     const int ns = A.ns;
-    const long long nchunk = (long long)gridDim.x * (VOX_T / 64);
-    double* tab = tab_s + wid * (9 * 32);
-    VoxPart& P = pw[wid];
-    for (long long base = ((long long)blockIdx.x * (VOX_T / 64) + wid) * 64; base < n; base += nchunk * 64) {
-        const long long i = base + lane;
-        const bool valid = i < n;
-        // lanes past the end re-read the last item (never stored)
-        const int4 it = A.items[valid ? i : n - 1];
-        const int k = it.w < A.p.np ? it.w : 0;
-        const int shape = A.p.shape[k];
-        const bool lane_sph = valid && ns <= VOX_NS_REG;
-        if (lane_sph && shape == 0) {
-            const int cnt = sphere_count_lane_ns(ns, A.p.pos[3 * k], A.p.pos[3 * k + 1], A.p.pos[3 * k + 2],
-                                                 A.p.semi[3 * k], it.x, it.y, it.z, off);
-            A.item_cnt[i] = cnt;
-        } else if (lane_sph) {
-            double R[9];
-            quat_rbw(A.p.q + 4 * k, R);
-            A.item_cnt[i] = ellipsoid_count_lane(A.p.pos + 3 * k, A.p.semi + 3 * k, R, it.x, it.y, it.z, off, ns);
+    const int bx = P.hi[0] - P.lo[0] + 1, by_ = P.hi[1] - P.lo[1] + 1, bz_ = P.hi[2] - P.lo[2] + 1;
+    if (bx <= 0 || by_ <= 0 || bz_ <= 0) return;  // a blown-up particle: no box
+    unsigned short* box = A.vbox + (long long)k * A.box_stride;
+    double Aq, by, bz, cyy, cyz, czz, amax;
+    if (P.shape == 0) {
+        const double i2 = 1.0 / (P.ax[0] * P.ax[0]);
+        Aq = i2; by = 0.0; bz = 0.0; cyy = i2; cyz = 0.0; czz = i2;
+        amax = P.ax[0];
+    } else {
+        Aq = by = bz = cyy = cyz = czz = 0.0;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const double r0 = P.R[q], r1 = P.R[3 + q], r2 = P.R[6 + q], iv = P.inv[q];
+            Aq += iv * r0 * r0;
+            by += iv * r0 * r1;
+            bz += iv * r0 * r2;
+            cyy += iv * r1 * r1;
+            cyz += iv * r1 * r2;
+            czz += iv * r2 * r2;
         }
-        unsigned long long rest = __ballot(valid && !lane_sph);
-        while (rest) {
-            const int l = __ffsll((long long)rest) - 1;
-            rest &= rest - 1;
-            const int X = __shfl(it.x, l, 64), Y = __shfl(it.y, l, 64), Z = __shfl(it.z, l, 64);
-            const int kk = __shfl(k, l, 64);
-            if (lane == 0) {
-                P.pid = kk;
-                P.shape = A.p.shape[kk];
-                for (int a = 0; a < 3; ++a) {
-                    P.c[a] = A.p.pos[3 * kk + a];
-                    P.ax[a] = A.p.semi[3 * kk + a];
-                    P.inv[a] = 1.0 / (P.ax[a] * P.ax[a]);
+        amax = fmax(P.ax[0], fmax(P.ax[1], P.ax[2]));
+    }
+    const double iA = 1.0 / Aq;
+    const double fns = (double)ns, mt = 1e-5 * (1.0 + amax) * fns, top = fns - 1.0;
+    const double a2 = by * by - Aq * cyy, my = 1e-3;
+    const int plane_cells = bx * by_;
+    const int pz = VOX_BOX_LDS / plane_cells;  // z-planes per slab (the box's x-y plane fits: checked at creation)
+    for (int z0 = 0; z0 < bz_; z0 += pz) {
+        const int nzs = bz_ - z0 < pz ? bz_ - z0 : pz;
+        for (int c = tid; c < nzs * plane_cells; c += VOX_T) cnt_s[c] = 0;
+        __syncthreads();
+        // work items (z-sample plane c of cell layer Z, cell row Y): the ns sample rows b
+        const int items = nzs * ns * by_;
+        for (int it = tid; it < items; it += VOX_T) {
+            const int Yr = it % by_, cz = (it / by_) % ns, Zr = it / (by_ * ns);
+            const int Z = P.lo[2] + z0 + Zr, Y = P.lo[1] + Yr;
+            const double dz = ((double)Z + off[cz]) - P.c[2];
+            const double bzz = bz * dz, czzz = czz * dz * dz, cyzz = 2.0 * cyz * dz;
+            const double a1 = 2.0 * by * bzz - Aq * cyzz;
+            const double a0 = bzz * bzz - Aq * (czzz - 1.0);
+            const double D = a1 * a1 - 4.0 * a2 * a0;
+            if (D < -(1e-9 * (a1 * a1 + 4.0 * fabs(a2 * a0)) + 1e-12)) continue;  // the plane misses it
+            const double sD = sqrt(D > 0.0 ? D : 0.0);
+            const double y1 = (-a1 + sD) / (2.0 * a2), y2 = (-a1 - sD) / (2.0 * a2);
+            const double ylo = fmin(y1, y2) - my, yhi = fmax(y1, y2) + my;
+            int* row = cnt_s + plane_cells * Zr + bx * Yr;
+            for (int b = 0; b < ns; ++b) {
+                const double dy = ((double)Y + off[b]) - P.c[1];
+                if (dy < ylo || dy > yhi) continue;
+                const double B = by * dy + bzz;
+                const double Cm1 = (cyy * dy * dy + cyzz * dy + czzz) - 1.0;
+                const double disc = B * B - Aq * Cm1;
+                const double tol = 1e-6 * (B * B + Aq * fabs(Cm1)) + 1e-10;
+                if (disc <= -tol) continue;  // the row misses it
+                if (disc < tol) {            // a row grazing the surface: every sample
+                    for (int X = P.lo[0]; X <= P.hi[0]; ++X) {
+                        int kx = 0;
+                        for (int a = 0; a < ns; ++a) kx += sample_exact(P, ((double)X + off[a]) - P.c[0], dy, dz);
+                        if (kx) atomicAdd(&row[X - P.lo[0]], kx);
+                    }
+                    continue;
                 }
-                quat_rbw(A.p.q + 4 * kk, P.R);
+                const double sq = sqrt(disc);
+                const double r1 = (-B - sq) * iA, r2 = (-B + sq) * iA;
+                int X0 = (int)floor(P.c[0] + r1) - 1, X1 = (int)floor(P.c[0] + r2) + 1;
+                X0 = X0 < P.lo[0] ? P.lo[0] : X0;
+                X1 = X1 > P.hi[0] ? P.hi[0] : X1;
+                for (int X = X0; X <= X1; ++X) {
+                    // sample a of cell X lies at x = (X - c_x) + (a + 1/2) / ns
+                    const double xb = (double)X - P.c[0];
+                    const double t1 = (r1 - xb) * fns - 0.5, t2 = (r2 - xb) * fns - 0.5;
+                    const double lo = fmax(floor(t1 + mt) + 1.0, 0.0), hi = fmin(ceil(t2 - mt) - 1.0, top);
+                    int kx = hi >= lo ? (int)(hi - lo) + 1 : 0;
+                    const double u0 = fmax(ceil(t1 - mt), 0.0), u1 = fmin(floor(t1 + mt), top);
+                    for (double a = u0; a <= u1; a += 1.0)
+                        kx += sample_exact(P, ((double)X + off[(int)a]) - P.c[0], dy, dz);
+                    const double v0 = fmax(ceil(t2 - mt), 0.0), v1 = fmin(floor(t2 + mt), top);
+                    for (double a = v0; a <= v1; a += 1.0)
+                        if (!(fabs(a - t1) <= mt)) kx += sample_exact(P, ((double)X + off[(int)a]) - P.c[0], dy, dz);
+                    if (kx) atomicAdd(&row[X - P.lo[0]], kx);
+                }
             }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            const int cnt = sample_count(P, X, Y, Z, off, ns, tab);
-            if (lane == 0) A.item_cnt[base + l] = cnt;
         }
+        __syncthreads();
+        for (int c = tid; c < nzs * plane_cells; c += VOX_T)
+            box[(long long)z0 * plane_cells + c] = (unsigned short)cnt_s[c];
+        __syncthreads();
     }
 }
 
-// 3. per tile: select the kept solids with the sampled counts (the tile's
-//    counts are staged in LDS first: one coalesced load instead of a dependent
-//    global load per boundary cell inside the selection loop)
-#define VOX_SEL_Q 1024
+// per tile: select the kept solids, the subdivision counts from the count boxes
 template <typename C, bool SORT>
 __global__ __launch_bounds__(VOX_T) void k_vox_select(VoxArgs A) {
     __shared__ VoxPart sp[PSM_PMAX];
     __shared__ double off[32];
-    __shared__ int tcnt[VOX_T / 64];
-    __shared__ int qc_s[VOX_SEL_Q];
     __shared__ unsigned long long ks[SORT ? VOX_T : 1];
     __shared__ unsigned long long cnt_e, cnt_d;
     const long long t = blockIdx.x;
     if (t >= A.g.ntiles) return;
-    const bool subdiv = A.sf_method == 0;
     const unsigned long long* keys = SORT ? sort_tile_list(A, t, ks) : nullptr;
     const TileRange R = tile_range(A, t);
     if (R.count <= 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    const int ns = A.ns, n3 = ns * ns * ns;
     if (tid == 0) { cnt_e = 0; cnt_d = 0; }
     stage_particles(A, sp, off, R.s0, R.count, keys);
     __syncthreads();
@@ -1202,23 +1000,15 @@ __global__ __launch_bounds__(VOX_T) void k_vox_select(VoxArgs A) {
     const bool xy_ok = x < A.g.nx && y < A.g.ny;
     unsigned long long cm0, cm1;
     column_masks(A, sp, R.count, x, y, xy_ok, cm0, cm1);
-    const int mine = subdiv ? (int)A.lane_items[t * VOX_T + tid] : 0;
-    int my_off, total;
-    block_offsets(mine, tcnt, my_off, total);
-    const long long tb = subdiv ? (long long)A.tile_items[t] : 0;
-    const int nq = total < VOX_SEL_Q ? total : VOX_SEL_Q;
-    for (int u = tid; u < nq; u += VOX_T) qc_s[u] = tb + u < A.item_cap ? A.item_cnt[tb + u] : 0;
-    __syncthreads();
-    select_slots<C>(A, sp, t, R.tz, x, y, xy_ok, cm0, cm1, slo, shi, my_off,
-                    [&](int j, const VoxPart& P, int X, int Y, int Z) {
-                        const long long g = tb + j;
-                        if (j < nq && g < A.item_cap) return qc_s[j];
-                        if (g < A.item_cap) return A.item_cnt[g];
-                        int cnt = 0;
-                        for (int m = 0; m < n3; ++m) cnt += sample_in(P, X, Y, Z, off, ns, m);
-                        return cnt;
-                    },
-                    &cnt_e, &cnt_d);
+    const unsigned short* vbox = A.vbox;
+    const long long stride = A.box_stride;
+    select_slots<C, true>(A, sp, t, R.tz, x, y, xy_ok, cm0, cm1, slo, shi, 0,
+                          [&](int, const VoxPart& P, int X, int Y, int Z) {
+                              const int bx = P.hi[0] - P.lo[0] + 1, by = P.hi[1] - P.lo[1] + 1;
+                              return (int)vbox[(long long)P.pid * stride + (X - P.lo[0]) +
+                                               (long long)bx * ((Y - P.lo[1]) + (long long)by * (Z - P.lo[2]))];
+                          },
+                          &cnt_e, &cnt_d);
 }
 
 // consecutive blocks of the map stay on one XCD
@@ -1267,27 +1057,18 @@ hipError_t vox_register(const VoxArgs& A, int* scan_tmp, hipStream_t s) {
 hipError_t vox_voxelize(const VoxArgs& A, int ctype_double, hipStream_t s) {
     const unsigned nt = (unsigned)A.g.ntiles;
     const bool sort = A.g.ntiles <= VOX_SORT_IN_TILE_MAX;
-    if (A.vpart && A.p.np > 0) k_vox_parts<<<nblk(A.p.np), 256, 0, s>>>(A);
-    if (A.sf_method == 0) {
-        if (sort) k_vox_classify<true><<<nt, VOX_T, 0, s>>>(A);
-        else k_vox_classify<false><<<nt, VOX_T, 0, s>>>(A);
-        // one wave per 64 items, up to 4096 workgroups; the waves stride over the rest
-        long long nb = (A.item_cap + VOX_T - 1) / VOX_T;
-        nb = nb < 4096 ? nb : 4096;
-        k_vox_sample<<<(unsigned)(nb > 0 ? nb : 1), VOX_T, 0, s>>>(A);
-    }
-    // (the subdivision method's lists were ordered by the classify kernel)
-    const bool sort_sel = A.sf_method != 0 && sort;
+    if (A.p.np > 0) k_vox_parts<<<nblk(A.p.np), 256, 0, s>>>(A);
+    if (A.sf_method == 0 && A.p.np > 0) k_vox_rows<<<(unsigned)A.p.np, VOX_T, 0, s>>>(A);
+    // (small lattices: the select kernel orders each tile's list)
     if (ctype_double) {
-        if (sort_sel) k_vox_select<double, true><<<nt, VOX_T, 0, s>>>(A);
+        if (sort) k_vox_select<double, true><<<nt, VOX_T, 0, s>>>(A);
         else k_vox_select<double, false><<<nt, VOX_T, 0, s>>>(A);
     } else {
-        if (sort_sel) k_vox_select<float, true><<<nt, VOX_T, 0, s>>>(A);
+        if (sort) k_vox_select<float, true><<<nt, VOX_T, 0, s>>>(A);
         else k_vox_select<float, false><<<nt, VOX_T, 0, s>>>(A);
     }
     return hipGetLastError();
 }
-
 hipError_t vox_register_batch(const VoxArgs* jobs, int njobs, hipStream_t s) {
     if (njobs <= 0) return hipSuccess;
     k_vox_register_batch<<<(unsigned)njobs, VOX_RT, 0, s>>>(jobs);
@@ -1310,4 +1091,5 @@ hipError_t vox_reduce_hydro(const VoxArgs& A, hipStream_t s) {
 }
 
 size_t vox_part_bytes() { return sizeof(VoxPart); }
+size_t vox_box_cells_max() { return VOX_BOX_LDS; }
 
