@@ -215,6 +215,15 @@ psmdem_status psmdem_write_populations(psmdem_domain* d, const double* f);
  * library allocates for the call through the domain's allocator (32 bytes
  * per cell of a chunk of at most 2^22 cells; PSMDEM_E_NOMEM when it cannot). */
 psmdem_status psmdem_read_fields(psmdem_domain* d, double* rho, double* u);
+/* The same read-out for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * allocation): identical outputs, staged through a file-scope device array
+ * of 2^20 cells x 4 doubles (32 MiB, one per device, held until the process
+ * ends), any lattice size in chunks of 2^20 cells.  Calls no allocating
+ * routine.  Every call on a device shares that device's array, and each chunk
+ * overwrites what it reads back (nothing has to start at zero): calls that
+ * overlap on one device (from several host threads) race. */
+psmdem_status psmdem_read_fields_noalloc(psmdem_domain* d, double* rho, double* u);
 /* particle arrays [3n] (quat [4n]); any pointer may be NULL */
 psmdem_status psmdem_read_particles(psmdem_domain* d, double* pos, double* quat, double* vel,
                                    double* omega, double* acc, double* alpha, double* f_hyd,

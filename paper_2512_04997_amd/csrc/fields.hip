@@ -3,12 +3,23 @@
 // rho u = sum_i f_i c_i, plus half the fluid force density with forcing).
 //
 // The moments of a chunk of cells are formed by one kernel into a device
-// staging buffer (allocated for the call through the domain's allocator) and
-// copied to the caller's host arrays chunk by chunk.
+// staging buffer and copied to the caller's host arrays chunk by chunk:
+//   psmdem_read_fields          stages through a buffer the library allocates
+//                               for the call (the domain's allocator);
+//   psmdem_read_fields_noalloc  stages through `scratch`, a file-scope device
+//                               array of PSM_SCRATCH_CELLS cells, and allocates
+//                               nothing.
 #include <math.h>
+#include <mutex>
 
 #include "common.h"
 #include "domain.h"
+
+// staging of the no-allocation read-out: rho then u (3 per cell) of up to
+// PSM_SCRATCH_CELLS cells (4 doubles per cell, 32 MiB); one copy per device,
+// held until the process ends, shared by every call on that device
+#define PSM_SCRATCH_CELLS (1 << 20)
+static __device__ __align__(256) double scratch[4 * PSM_SCRATCH_CELLS];
 
 namespace {
 
@@ -129,6 +140,30 @@ int read_fields_via(psmdem_domain* D, double* stage, long long chunk, double* rh
     return 0;
 }
 
+// device address of `scratch` per device, taken once with that device current
+std::mutex g_scratch_mu;
+double* g_scratch[64] = {};
+
+int scratch_of(int dev, double** out) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (dev < 0 || dev >= 64) {
+        psm_set_error("device %d out of range", dev);
+        return PSMDEM_E_INVALID;
+    }
+    if (!g_scratch[dev]) {
+        int cur = -1;
+        PSM_CHECK(hipGetDevice(&cur));
+        if (cur != dev) PSM_CHECK(hipSetDevice(dev));
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) PSM_CHECK(hipSetDevice(cur));
+        if (e != hipSuccess || !p) return psm_hip_fail(e, "hipGetSymbolAddress(scratch)", __FILE__, __LINE__);
+        g_scratch[dev] = (double*)p;
+    }
+    *out = g_scratch[dev];
+    return 0;
+}
+
 }  // namespace
 
 extern "C" psmdem_status psmdem_read_fields(psmdem_domain* d, double* rho, double* u) {
@@ -145,4 +180,14 @@ extern "C" psmdem_status psmdem_read_fields(psmdem_domain* d, double* rho, doubl
     const int rc = read_fields_via(d, stage, chunk, rho, u);
     d->tfree(stage, nb);
     return rc ? (psmdem_status)rc : st;
+}
+
+extern "C" psmdem_status psmdem_read_fields_noalloc(psmdem_domain* d, double* rho, double* u) {
+    if (!d) return PSMDEM_E_INVALID;
+    const psmdem_status st = psm_sync_flags(d);
+    if (psm_read_fails(st)) return st;
+    double* stage = nullptr;
+    if (int rc = scratch_of(d->dev, &stage)) return (psmdem_status)rc;
+    if (int rc = read_fields_via(d, stage, PSM_SCRATCH_CELLS, rho, u)) return (psmdem_status)rc;
+    return st;
 }

@@ -113,6 +113,7 @@ def lib():
     L.psmdem_read_populations.argtypes = [P, P]
     L.psmdem_write_populations.argtypes = [P, P]
     L.psmdem_read_fields.argtypes = [P, P, P]
+    L.psmdem_read_fields_noalloc.argtypes = [P, P, P]
     L.psmdem_read_particles.argtypes = [P] + [P] * 10
     L.psmdem_write_particles.argtypes = [P] + [P] * 8
     L.psmdem_read_predicted.argtypes = [P, P, P]
@@ -146,7 +147,7 @@ def lib():
     L.psmdem_version.restype = C.c_char_p
     L.psmdem_version.argtypes = []
     for name in ("psmdem_step", "psmdem_sync", "psmdem_stage", "psmdem_read_populations",
-                 "psmdem_write_populations", "psmdem_read_fields",
+                 "psmdem_write_populations", "psmdem_read_fields", "psmdem_read_fields_noalloc",
                  "psmdem_read_particles",
                  "psmdem_write_particles", "psmdem_read_predicted", "psmdem_write_predicted",
                  "psmdem_read_pairs", "psmdem_write_pairs", "psmdem_read_contacts",
@@ -394,11 +395,13 @@ class Domain:
             raise ValueError("populations must have 19 * n_cells entries")
         _check(lib().psmdem_write_populations(self.h, _ptr(f)))
 
-    def fields(self):
-        """Density [N] and velocity [N, 3]."""
+    def fields(self, noalloc=False):
+        """Density [N] and velocity [N, 3] (noalloc: the entry point that
+        allocates no device memory)."""
         rho = np.zeros(self.N)
         u = np.zeros(3 * self.N)
-        self._rd(lib().psmdem_read_fields(self.h, _ptr(rho), _ptr(u)))
+        fn = lib().psmdem_read_fields_noalloc if noalloc else lib().psmdem_read_fields
+        self._rd(fn(self.h, _ptr(rho), _ptr(u)))
         return rho, u.reshape(self.N, 3)
 
     def particles(self):
