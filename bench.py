@@ -51,7 +51,7 @@ def parse():
     p.add_argument("--spheres", type=int, default=500)
     p.add_argument("--cpu-sample-steps", type=int, default=-1,
                    help="coupled steps of the CPU oracle sample (0: skip the CPU baseline; -1: the workload's "
-                        "default, 200 on the 64^3 ellipsoid box of the same recipe, 120 on the Couette workload)")
+                        "default, 600 on the 64^3 ellipsoid box of the same recipe, 120 on the Couette workload)")
     p.add_argument("--no-timing", action="store_true", help="skip the per-kernel event timing pass")
     p.add_argument("--serve-jobs", type=int, default=32,
                    help="jobs of the ensemble-serving sample (0: skip the serving measurement)")
@@ -84,20 +84,20 @@ def lbm_source_digest():
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "lbm_couette128_fp32_traffic.txt")
-
-
-def measured_traffic(precision, n, spheres):
-    """HBM bytes per LBM pass from the committed counter summary, if it was
-    taken on this workload and on the current kernel source; else None."""
-    try:
-        rec = json.loads(open(TRAFFIC_FILE).read().split("JSON:", 1)[1].strip().splitlines()[0])
-    except (OSError, IndexError, ValueError):
-        return None
-    if (rec.get("lbm_source") != lbm_source_digest() or rec.get("precision") != precision or rec.get("n") != n
-            or rec.get("spheres") != spheres):
-        return None
-    return rec.get("bytes_per_pass")
+def measured_traffic(workload, precision):
+    """HBM bytes per LBM pass from a committed counter summary
+    (profiles/lbm_*_traffic.txt), if one was taken on this workload and
+    precision and on the current kernel source; else None."""
+    import glob
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "lbm_*_traffic.txt"))):
+        try:
+            rec = json.loads(open(path).read().split("JSON:", 1)[1].strip().splitlines()[0])
+        except (OSError, IndexError, ValueError):
+            continue
+        if (rec.get("lbm_source") == lbm_source_digest() and rec.get("precision") == precision
+                and rec.get("workload") == workload):
+            return rec.get("bytes_per_pass")
+    return None
 
 
 def _csv(path):
@@ -176,13 +176,20 @@ def lbm_sweep(n, collision="bgk"):
 def fluidized_sweep(warmup, steps, collision):
     """Coupled-step throughput of the paper's fluidized bed (500 x 200 x 800,
     D = 20, 10 substeps, distance solid fraction) against the solid fraction,
-    in FP32, FP64 and BF16 storage: one JSON line per point."""
+    in FP64, FP32 and BF16 storage: one JSON line per point.  Each point runs
+    warmup + steps + 20 timed-pass steps from the same start in every
+    precision, and FP32 and BF16 state their errors against the FP64 run at
+    the end (fluid velocity against max(|u|, 1e-3) and in relative L2;
+    particle velocities against the largest of the FP64 run; hydrodynamic
+    forces in relative L2)."""
+    import numpy as np
     import torch
     from paper_2512_04997_amd import psmdem, workloads
     torch.cuda.set_device(0)
     for phi in (0.0, 0.15, 0.30, 0.45):
         cfg, parts, meta = workloads.fluidized_bed(phi=phi)
-        for prec in ("fp32", "fp64", "bf16"):
+        ref = None
+        for prec in ("fp64", "fp32", "bf16"):
             cfg = dict(cfg, precision=prec)
             if collision:
                 cfg["collision"] = collision
@@ -203,13 +210,24 @@ def fluidized_sweep(warmup, steps, collision):
             dem_n = D.timing("dem")[1] // max(D.timing("lbm")[1], 1)
             parts_ms["dem"] = round(parts_ms["dem"] * dem_n, 4)
             ctr = D.counters()
-            print(json.dumps({"fluidized_bed": meta["workload"], "phi": phi, "precision": prec,
-                              "particles": 0 if parts is None else len(parts["pos"]), "steps": steps,
-                              "ms_per_step": round(el / steps * 1e3, 4), "mlups": round(N * steps / el / 1e6, 1),
-                              "per_step_ms": parts_ms, "contacts": ctr["n_contacts"], "pairs": ctr["n_pairs"]}),
-                  flush=True)
+            out = {"fluidized_bed": meta["workload"], "phi": phi, "precision": prec,
+                   "particles": 0 if parts is None else len(parts["pos"]), "steps": steps,
+                   "ms_per_step": round(el / steps * 1e3, 4), "mlups": round(N * steps / el / 1e6, 1),
+                   "per_step_ms": parts_ms, "contacts": ctr["n_contacts"], "pairs": ctr["n_pairs"]}
+            _, u = D.fields()
+            P = D.particles() if parts is not None else None
+            if ref is None:
+                ref = (u, P)
+                out["max_u"] = float(np.abs(u).max())
+            else:
+                u0, P0 = ref
+                out["errors_vs_fp64"] = {"u_rel_l2": _rel_l2(u, u0), "u_rel_linf": _rel_inf(u, u0, 1e-3)}
+                if P is not None:
+                    out["errors_vs_fp64"].update({"v_rel_linf": _rel_inf(P["vel"], P0["vel"]),
+                                                  "f_hyd_rel_l2": _rel_l2(P["f_hyd"], P0["f_hyd"])})
+            print(json.dumps(out), flush=True)
             D.close()
-            del D
+            del D, u, P
             torch.cuda.empty_cache()
 
 
@@ -226,7 +244,12 @@ def _rel_inf(a, b, floor=0.0):
 
 def precision_study(n, warmup=20, timed=100, check=200):
     """Same particle set and start in every population precision; speed of the
-    coupled step and of the LBM pass, and the errors against the FP64 run."""
+    coupled step and of the LBM pass, and the errors against the FP64 run at
+    step `check` (fluid velocity against max(|u|, 1e-3) and in relative L2;
+    particle velocities and rotation rates against the largest of the FP64
+    run; hydrodynamic forces and torques in relative L2).  One domain at a
+    time; the FP64 reference state is kept on the host."""
+    import numpy as np
     import torch
     from paper_2512_04997_amd import psmdem, workloads
     torch.cuda.set_device(0)
@@ -254,18 +277,20 @@ def precision_study(n, warmup=20, timed=100, check=200):
                "ms_per_step": round(dt * 1e3, 4), "mlups": round(N / dt / 1e6, 1), "lbm_ms": round(lbm_ms, 4),
                "lbm_GBs": round(N * 2 * 19 * STORAGE_BYTES[prec] / (lbm_ms * 1e-3) / 1e9, 1), "step": check}
         if ref is None:
-            ref = (u, P)
+            ref = (u.astype(np.float64), {k: P[k].copy() for k in ("vel", "omega", "f_hyd", "m_hyd")})
             out["max_u"] = float(abs(u).max())
+            out["max_v"] = float(abs(P["vel"]).max())
         else:
             u0, P0 = ref
-            out.update({"u_rel_l2": _rel_l2(u, u0), "u_rel_linf": _rel_inf(u, u0),
-                        "v_rel_linf": _rel_inf(P["vel"], P0["vel"], 1e-12),
-                        "omega_rel_linf": _rel_inf(P["omega"], P0["omega"], 1e-12),
+            out.update({"u_rel_l2": _rel_l2(u, u0), "u_rel_linf": _rel_inf(u, u0, 1e-3),
+                        "v_rel_linf": _rel_inf(P["vel"], P0["vel"]),
+                        "omega_rel_linf": _rel_inf(P["omega"], P0["omega"]),
                         "f_hyd_rel_l2": _rel_l2(P["f_hyd"], P0["f_hyd"]),
                         "m_hyd_rel_l2": _rel_l2(P["m_hyd"], P0["m_hyd"])})
         print(json.dumps(out), flush=True)
         D.close()
-        del u, P
+        del u, P, D
+        torch.cuda.empty_cache()
 
 
 def stream_probe(mib):
@@ -314,7 +339,12 @@ def serve_batched(stream, slots, precision, budget_gb=16.0):
     lat = []
     k = 0
     n_done = 0
+    shown = t0
     while n_done < len(stream):
+        if psmdem.clock() - shown > 20.0:
+            shown = psmdem.clock()
+            print(f"[bench] serving (batched): {n_done} of {len(stream)} jobs done after {shown - t0:.0f} s",
+                  file=sys.stderr, flush=True)
         now = psmdem.clock() - t0
         while k < len(stream) and stream[k][0] <= now:
             arr, cfg, parts, steps = stream[k]
@@ -343,7 +373,12 @@ def serve_one_at_a_time(stream):
     import torch
     t0 = psmdem.clock()
     lat = []
+    shown = t0
     for arr, cfg, parts, steps in stream:
+        if psmdem.clock() - shown > 20.0:
+            shown = psmdem.clock()
+            print(f"[bench] serving (one at a time): {len(lat)} of {len(stream)} jobs done after {shown - t0:.0f} s",
+                  file=sys.stderr, flush=True)
         wait = arr - (psmdem.clock() - t0)
         if wait > 0:
             time.sleep(wait)
@@ -494,7 +529,7 @@ def main():
                     "hydro_and_corrector": round(hyd_ms, 4)}
         alg_bytes = N * 2 * 19 * sb
         achieved = alg_bytes / (lbm_ms * 1e-3) / 1e9
-        traffic = measured_traffic(a.precision, n, a.spheres) if a.workload == "couette" else None
+        traffic = measured_traffic(meta["workload"], a.precision)
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "LBM collide-stream pass (one k_lbm_mixed launch over fluid and PSM tiles per step)",
@@ -513,7 +548,7 @@ def main():
     cpu = None
     cpu_steps = a.cpu_sample_steps
     if cpu_steps < 0:
-        cpu_steps = 200 if a.workload == "kolmogorov" else 120
+        cpu_steps = 600 if a.workload == "kolmogorov" else 120
     if cpu_steps > 0:
         if a.workload == "kolmogorov" and n > 64:
             # the oracle's two FP64 population arrays of 512^3 would not finish in a

@@ -89,6 +89,8 @@ struct TileArgs {
     void* slot_B;          // [ms][ntiles * 1024] B_k in the compute type
     double* partial;       // [cap][6] per (tile, particle): force then torque
     double* slot_beta;     // [ms][ntiles * 1024] beta of kept slots (double, for read-back)
+    unsigned* tile_ed;     // [2 ntiles] entries (beta > 0) and dropped entries of each tile's last
+                           // selection, summed when read; null: the step counters take atomics
 };
 
 // device error flags and counters (one 64-bit word each)
@@ -98,8 +100,6 @@ struct DevCounters {
     unsigned long long dropped;
     unsigned long long contacts;
     unsigned long long items;     // boundary cells queued for sampling this step
-    unsigned long long ell_work;  // ellipsoid pairs deferred to the iteration kernel this substep
-    unsigned long long blocks_done;  // blocks of the current predictor launch that finished (last one decides)
 };
 
 // ---------------------------------------------------------------------------

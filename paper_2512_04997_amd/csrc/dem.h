@@ -37,10 +37,25 @@ struct DemArgs {
                            // saved at the end of a launch for the next one (null: not kept)
     int* list_flag;        // [2] multi-launch path: the list changed in this substep (by substep parity)
     const int* list_run;   // multi-launch path: list_flag of this substep, or null (always build)
-    int* ell_list;         // [pair_cap] multi-launch path: pairs whose ellipsoid iteration is deferred to
-                           // a dense second launch (counted in ctr->ell_work), or null (no ellipsoids)
+    int* ell_list;         // [DEM_ELL_SEGS * ell_seg_cap] multi-launch path: pairs whose ellipsoid
+                           // iteration is deferred to a dense second launch, in DEM_ELL_SEGS segments
+                           // (a wave appends to segment wave % DEM_ELL_SEGS), or null (no ellipsoids)
+    unsigned* ell_cnt;     // [DEM_ELL_SEGS] pairs queued per segment this substep
+    long long ell_seg_cap;
     DevCounters* ctr;
 };
+
+#define DEM_ELL_SEGS 64
+#define DEM_CONTACT_GRID_MAX 2048u
+// capacity of one deferral segment for pair_cap pairs: the contact launch has
+// at most DEM_CONTACT_GRID_MAX workgroups of 128 lanes striding over the list,
+// and the waves of one segment cover at most a DEM_ELL_SEGS-th of its lanes
+inline long long dem_ell_seg_cap(long long pair_cap) {
+    const long long blocks = (pair_cap + 127) / 128 < DEM_CONTACT_GRID_MAX ? (pair_cap + 127) / 128 : DEM_CONTACT_GRID_MAX;
+    const long long lanes = 128 * (blocks > 0 ? blocks : 1);
+    const long long iters = (pair_cap + lanes - 1) / lanes;
+    return (pair_cap + lanes) / DEM_ELL_SEGS + 64 * iters + 64;
+}
 
 // the current and the previous substep's pair lists
 struct PairBufs {
@@ -62,13 +77,12 @@ struct PairSet {
 hipError_t dem_predict(const DemArgs& A, double dt, int write_kin, hipStream_t s);
 hipError_t dem_lists(const DemArgs& A, const PairBufs& B, int* scan_tmp, hipStream_t s);
 // multi-launch substeps that keep an unchanged list (A.list_run = A.list_flag + par)
-// (the predictor's last workgroup decides whether the substep rebuilds its list)
 hipError_t dem_predict_keep(const DemArgs& A, double dt, int write_kin, int par, hipStream_t s);
+// the corrector of a substep and the predictor of the next (its parity par)
+hipError_t dem_correct_predict(const DemArgs& A, double dt, int write_kin, int par, hipStream_t s);
 hipError_t dem_lists_kept(const DemArgs& A, const PairBufs& B, int par, int* scan_tmp, hipStream_t s);
-// contacts and DEM sums; correct = 1 also runs each particle's corrector with
-// dt = dth after its sums (substeps whose corrector needs no hydrodynamic sums)
 hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, const double* ww, double dth,
-                        int* scan_tmp, hipStream_t s, int correct = 0);
+                        int* scan_tmp, hipStream_t s);
 hipError_t dem_correct(const DemArgs& A, double dt, hipStream_t s);
 // hydrodynamic sums of the tile partials (T) and the corrector, one launch
 hipError_t dem_hydro_correct(const DemArgs& A, const TileArgs& T, double dt, hipStream_t s);

@@ -919,60 +919,56 @@ __global__ void k_predict(DemArgs A, double dt, int write_kin) {
     }
 }
 
-// the substep's decision: rebuild when something changed or no list is kept
-__device__ inline void list_age_decide(const DemArgs& A, int par) {
-    const int age = __hip_atomic_load(A.fused_age, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int flag = __hip_atomic_load(&A.list_flag[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int ch = flag != 0 || age < 0;
-    A.list_flag[par] = ch;
-    *A.fused_age = ch ? 0 : age + 1;
-}
-
 // Multi-launch substeps keep the pair list while it is unchanged: the
 // predictor also compares each particle's new cells and wall candidates with
 // the stored ones (those of the last substep, so of the list) and raises
-// list_flag[par]; it clears the other parity's flag for the next substep.
+// list_flag[par]; the launch clears the other parity's flag for the next
+// substep (every reader of it has finished: launches run in stream order).
+__device__ inline void predict_keep_one(const DemArgs& A, int kk, double dt, int write_kin, int par) {
+    const int* d = A.pc + 8 * kk;
+    unsigned old[4];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) old[a] = (unsigned)d[2 * a] | ((unsigned)d[2 * a + 1] << 16);
+    old[3] = (unsigned)d[7];
+    const double rbk = A.p.rb[kk];
+    AxCells r;
+    double xk[3];
+    ph_predict(A, kk, dt, write_kin, r, nullptr, xk);
+    store_cells(A, kk, r);
+    unsigned wm = 0;
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        const int a = f / 2;
+        const double wd = (f % 2 == 0) ? xk[a] : A.L[a] - xk[a];
+        wm |= (A.g.bc[f] != 0 && wd < rbk) ? 1u << f : 0u;
+    }
+    A.pc[8 * kk + 7] = (int)wm;
+    bool ch = wm != old[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ch |= ((unsigned)r.c[a][0] | ((unsigned)r.c[a][1] << 16)) != old[a];
+    if (ch) atomicOr(&A.list_flag[par], 1);
+}
+
 __global__ void k_predict_keep(DemArgs A, double dt, int write_kin, int par) {
-    __shared__ bool last_block;
+    if (blockIdx.x == 0 && threadIdx.x == 0) A.list_flag[par ^ 1] = 0;
+    GRID_LOOP(k, A.p.np) predict_keep_one(A, (int)k, dt, write_kin, par);
+}
+
+// the corrector of a substep and the predictor of the next one, per particle
+__global__ void k_correct_predict(DemArgs A, double dt, int write_kin, int par) {
     if (blockIdx.x == 0 && threadIdx.x == 0) A.list_flag[par ^ 1] = 0;
     GRID_LOOP(k, A.p.np) {
-        const int kk = (int)k;
-        const int* d = A.pc + 8 * kk;
-        unsigned old[4];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) old[a] = (unsigned)d[2 * a] | ((unsigned)d[2 * a + 1] << 16);
-        old[3] = (unsigned)d[7];
-        const double rbk = A.p.rb[kk];
-        AxCells r;
-        double xk[3];
-        ph_predict(A, kk, dt, write_kin, r, nullptr, xk);
-        store_cells(A, kk, r);
-        unsigned wm = 0;
-#pragma unroll
-        for (int f = 0; f < 6; ++f) {
-            const int a = f / 2;
-            const double wd = (f % 2 == 0) ? xk[a] : A.L[a] - xk[a];
-            wm |= (A.g.bc[f] != 0 && wd < rbk) ? 1u << f : 0u;
-        }
-        A.pc[8 * kk + 7] = (int)wm;
-        bool ch = wm != old[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) ch |= ((unsigned)r.c[a][0] | ((unsigned)r.c[a][1] << 16)) != old[a];
-        if (ch) atomicOr(&A.list_flag[par], 1);
+        ph_correct(A, (int)k, dt);
+        predict_keep_one(A, (int)k, dt, write_kin, par);
     }
-    // the last block to finish takes the substep's decision (list_age_decide):
-    // every block's flag update is ordered before its count by the fence
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        last_block = atomicAdd(&A.ctr->blocks_done, 1ull) == (unsigned long long)gridDim.x - 1ull;
-    }
-    __syncthreads();
-    if (last_block && threadIdx.x == 0) {
-        __threadfence();
-        A.ctr->blocks_done = 0;
-        list_age_decide(A, par);
-    }
+}
+
+// the substep's decision: rebuild when something changed or no list is kept
+__global__ void k_list_age(DemArgs A, int par) {
+    const int age = *A.fused_age;
+    const int ch = A.list_flag[par] != 0 || age < 0;
+    A.list_flag[par] = ch;
+    *A.fused_age = ch ? 0 : age + 1;
 }
 
 // one substep after a rebuild the kept list is copied into this buffer
@@ -1146,25 +1142,47 @@ __global__ __launch_bounds__(256) void k_contacts(DemArgs A, PairBufs B, const d
         if (ELL && defer) {
             const unsigned long long m = __ballot(deferred);
             if (m) {
+                // the wave's segment: few waves share a counter, so its atomics do not queue up
                 const int lane = threadIdx.x & 63, leader = __ffsll((long long)m) - 1;
-                unsigned long long base = 0;
-                if (lane == leader) base = atomicAdd(&A.ctr->ell_work, (unsigned long long)__popcll(m));
+                const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+                const int seg = (int)(wave % DEM_ELL_SEGS);
+                unsigned base = 0;
+                if (lane == leader) base = atomicAdd(&A.ell_cnt[seg], (unsigned)__popcll(m));
                 base = __shfl(base, leader, 64);
-                if (deferred) A.ell_list[base + __popcll(m & ((1ull << lane) - 1ull))] = (int)s;
+                if (deferred)
+                    A.ell_list[seg * A.ell_seg_cap + base + __popcll(m & ((1ull << lane) - 1ull))] = (int)s;
             }
         }
     }
 }
 
-// the queued ellipsoid pairs, one per lane (the queue is emptied by k_sum_wave)
+// the queued ellipsoid pairs, one per lane, over the segments in order (the
+// counters are cleared by k_sum_wave)
 __global__ __launch_bounds__(64) void k_contacts_ell(DemArgs A, PairBufs B, const double* vv, const double* ww,
                                                      double dth) {
+    __shared__ unsigned start[DEM_ELL_SEGS + 1];
+    if (threadIdx.x == 0) {
+        unsigned acc = 0;
+        for (int g = 0; g < DEM_ELL_SEGS; ++g) {
+            start[g] = acc;
+            acc += A.ell_cnt[g];
+        }
+        start[DEM_ELL_SEGS] = acc;
+    }
+    __syncthreads();
     long long nprev = B.prev_n ? *B.prev_n : 0;
     nprev = nprev < A.pair_cap ? nprev : A.pair_cap;
-    long long n = (long long)A.ctr->ell_work;
-    n = n < A.pair_cap ? n : A.pair_cap;
     const bool same = A.list_run && !*A.list_run;
-    GRID_LOOP(w, n) ph_contact<true>(A, B, (long long)A.ell_list[w], vv, ww, dth, nprev, same);
+    GRID_LOOP(w, (long long)start[DEM_ELL_SEGS]) {
+        int lo = 0, hi = DEM_ELL_SEGS - 1;  // the segment holding flat index w
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (start[mid] <= (unsigned)w) lo = mid;
+            else hi = mid - 1;
+        }
+        ph_contact<true>(A, B, (long long)A.ell_list[lo * A.ell_seg_cap + ((unsigned)w - start[lo])], vv, ww, dth,
+                         nprev, same);
+    }
 }
 __global__ void k_colhist(DemArgs A, PairBufs B) {
     if (A.list_run && !*A.list_run) return;
@@ -1206,12 +1224,11 @@ __global__ __launch_bounds__(256) void k_colsort(DemArgs A) {
 // with their in-contact flags and forces at once; lane 0 adds the terms of
 // the pairs in contact in that order.  A pair out of contact holds zero forces,
 // whose terms leave a sum unchanged.
-// DEM sums of every particle, one wave per particle; with correct set the
-// wave's lane 0 then runs the particle's corrector (substeps before the last,
-// whose corrector follows the hydrodynamic sums)
-__global__ __launch_bounds__(256) void k_sum_wave(DemArgs A, PairBufs B, int correct, double dt) {
+// DEM sums of every particle, one wave per particle
+__global__ __launch_bounds__(256) void k_sum_wave(DemArgs A, PairBufs B) {
     const int lane = threadIdx.x & 63;
-    if (blockIdx.x == 0 && threadIdx.x == 0) A.ctr->ell_work = 0;  // the contacts' queue, for the next substep
+    if (A.ell_cnt && blockIdx.x == 0 && threadIdx.x < DEM_ELL_SEGS)
+        A.ell_cnt[threadIdx.x] = 0;  // the contacts' deferral queue, for the next substep
     const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
     const long long cap = A.pair_cap;
     for (long long w = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < A.p.np; w += nw) {
@@ -1259,14 +1276,12 @@ __global__ __launch_bounds__(256) void k_sum_wave(DemArgs A, PairBufs B, int cor
                 }
             }
         }
-        if (lane == 0) {
+        if (lane == 0)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 A.p.fd[3 * i + c] = F[c];
                 A.p.md[3 * i + c] = M[c];
             }
-            if (correct) ph_correct(A, i, dt);
-        }
     }
 }
 __global__ void k_correct(DemArgs A, double dt) { GRID_LOOP(k, A.p.np) ph_correct(A, (int)k, dt); }
@@ -1891,6 +1906,7 @@ hipError_t dem_predict_keep(const DemArgs& A, double dt, int write_kin, int par,
 hipError_t dem_lists_kept(const DemArgs& A, const PairBufs& B, int par, int* scan_tmp, hipStream_t s) {
     if (A.p.np == 0) return hipSuccess;
     hipError_t e;
+    k_list_age<<<1, 1, 0, s>>>(A, par);
     k_list_copy<<<nblk_list(A.pair_cap), 256, 0, s>>>(A, B, par);
     k_hist<<<nblk_list(A.p.np), 256, 0, s>>>(A);
     if ((e = psm_scan(A.cell_count, A.cell_start, A.ncell, scan_tmp, s, A.list_run)) != hipSuccess) return e;
@@ -1918,29 +1934,38 @@ hipError_t dem_lists(const DemArgs& A, const PairBufs& B, int* scan_tmp, hipStre
 }
 
 hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, const double* ww, double dth,
-                        int* scan_tmp, hipStream_t s, int correct) {
+                        int* scan_tmp, hipStream_t s) {
     if (A.p.np == 0) return hipSuccess;
     hipError_t e;
+    // a grid for the pairs the list can hold, capped (the kernel strides over the rest)
+    unsigned nbc = nblk(A.pair_cap, 128);
+    nbc = nbc < DEM_CONTACT_GRID_MAX ? nbc : DEM_CONTACT_GRID_MAX;
     if (A.ellipsoids) {
-        k_contacts<true><<<nblk(A.pair_cap, 128), 128, 0, s>>>(A, B, vv, ww, dth);
+        k_contacts<true><<<nbc, 128, 0, s>>>(A, B, vv, ww, dth);
         if (A.ell_list) {
             const unsigned nb = nblk(A.pair_cap, 64);
             k_contacts_ell<<<nb < 4096 ? nb : 4096, 64, 0, s>>>(A, B, vv, ww, dth);
         }
     } else {
-        k_contacts<false><<<nblk(A.pair_cap, 128), 128, 0, s>>>(A, B, vv, ww, dth);
+        k_contacts<false><<<nbc, 128, 0, s>>>(A, B, vv, ww, dth);
     }
     k_colhist<<<nblk_list(A.pair_cap), 256, 0, s>>>(A, B);
     if ((e = psm_scan(A.col_count, A.col_start, A.p.np, scan_tmp, s, A.list_run)) != hipSuccess) return e;
     k_colscatter<<<nblk_list(A.pair_cap), 256, 0, s>>>(A, B);
     k_colsort<<<nblk_list(64LL * A.p.np), 256, 0, s>>>(A);
-    k_sum_wave<<<nblk(64LL * A.p.np), 256, 0, s>>>(A, B, correct, dth);
+    k_sum_wave<<<nblk(64LL * A.p.np), 256, 0, s>>>(A, B);
     return hipGetLastError();
 }
 
 hipError_t dem_hydro_correct(const DemArgs& A, const TileArgs& T, double dt, hipStream_t s) {
     if (A.p.np == 0) return hipSuccess;
     k_hydro_correct<<<(unsigned)((64LL * A.p.np + 255) / 256), 256, 0, s>>>(A, T, dt);
+    return hipGetLastError();
+}
+
+hipError_t dem_correct_predict(const DemArgs& A, double dt, int write_kin, int par, hipStream_t s) {
+    if (A.p.np == 0) return hipSuccess;
+    k_correct_predict<<<nblk(A.p.np), 256, 0, s>>>(A, dt, write_kin, par);
     return hipGetLastError();
 }
 

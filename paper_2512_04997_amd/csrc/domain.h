@@ -55,6 +55,8 @@ struct psmdem_domain {
     double *cF = nullptr, *cMi = nullptr, *cMj = nullptr;
     unsigned char* incontact = nullptr;
     int* ell_list = nullptr;
+    unsigned* ell_cnt = nullptr;
+    long long ell_seg_cap = 0;
     long long pair_cap = 0;
     int cur = 0;
     // voxel / tiles
@@ -69,6 +71,7 @@ struct psmdem_domain {
 
     int64_t step = 0;
     bool voxelized = false;
+    bool tile_counts = false;  // the entry counts of the last voxelisation are in t.tile_ed
 
     // timing
     bool timing = false;
@@ -165,6 +168,8 @@ struct psmdem_domain {
         A.ellipsoids = 0;
         for (int sh : h_shape) A.ellipsoids |= sh != 0;
         A.ell_list = ell_list;
+        A.ell_cnt = ell_cnt;
+        A.ell_seg_cap = ell_seg_cap;
         A.ctr = ctr;
         return A;
     }

@@ -109,6 +109,7 @@ static int run_voxelize(psmdem_domain* D) {
     PSM_CHECK(vox_voxelize(V, D->prec == 0, D->s));
     D->timed_end(tk);
     D->voxelized = true;
+    D->tile_counts = true;
     return 0;
 }
 
@@ -163,6 +164,7 @@ static int coupled_step(psmdem_domain* D) {
             D->timed_end(tk);
         }
     } else if (D->d.dem_on && D->np > 0) {
+        // a substep's corrector and the next substep's predictor share a launch
         for (int sub = 1; sub <= D->nsub; ++sub) {
             const bool last = sub == D->nsub;
             int tk = D->timed_begin(PSMDEM_T_DEM);
@@ -171,22 +173,23 @@ static int coupled_step(psmdem_domain* D) {
             const int par = (int)(D->dem_sub++ & 1);
             DemArgs A = D->dem_args();
             A.list_run = A.list_flag + par;
-            PSM_CHECK(dem_predict_keep(A, D->dt, last ? 1 : 0, par, D->s));
+            if (sub == 1) PSM_CHECK(dem_predict_keep(A, D->dt, last ? 1 : 0, par, D->s));
             D->cur ^= 1;
             PairBufs B = D->pair_bufs(1);
             PSM_CHECK(dem_lists_kept(A, B, par, D->scan_tmp, D->s));
-            // the corrector runs with the DEM sums, except in the last substep with
-            // the fluid on, where it follows the hydrodynamic sums
-            const bool couple = last && D->d.fluid_on;
-            PSM_CHECK(dem_contacts(A, B, D->p.vp, D->p.wp, D->dt, D->scan_tmp, D->s, couple ? 0 : 1));
-            D->timed_end(tk);
-            if (couple) {
+            PSM_CHECK(dem_contacts(A, B, D->p.vp, D->p.wp, D->dt, D->scan_tmp, D->s));
+            if (last && D->d.fluid_on) {
+                D->timed_end(tk);
                 if ((rc = run_voxelize(D))) return rc;
                 if ((rc = run_lbm(D, false))) return rc;
                 tk = D->timed_begin(PSMDEM_T_HYDRO);
                 PSM_CHECK(dem_hydro_correct(A, D->t, D->dt, D->s));
-                D->timed_end(tk);
+            } else if (last) {
+                PSM_CHECK(dem_correct(A, D->dt, D->s));
+            } else {
+                PSM_CHECK(dem_correct_predict(A, D->dt, sub + 1 == D->nsub ? 1 : 0, (int)(D->dem_sub & 1), D->s));
             }
+            D->timed_end(tk);
         }
     } else if (D->d.fluid_on) {
         if (D->np > 0) k_kin<<<nblk(D->np), 256, 0, D->s>>>(D->p, 1);
@@ -430,7 +433,11 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
     D->incontact = (unsigned char*)A(D->pair_cap);
     bool any_ell = false;
     for (int k = 0; k < np; ++k) any_ell = any_ell || D->h_shape[k] != 0;
-    if (any_ell) D->ell_list = (int*)A(sizeof(int) * D->pair_cap);
+    if (any_ell) {
+        D->ell_seg_cap = dem_ell_seg_cap(D->pair_cap);
+        D->ell_list = (int*)A(sizeof(int) * (size_t)(DEM_ELL_SEGS * D->ell_seg_cap));
+        D->ell_cnt = (unsigned*)A(sizeof(unsigned) * DEM_ELL_SEGS);
+    }
     D->col_count = (int*)A(sizeof(int) * std::max(np, 1));
     D->col_fill = (int*)A(sizeof(int) * std::max(np, 1));
     D->col_start = (int*)A(sizeof(int) * (np + 1));
@@ -455,6 +462,7 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
     t.slot_lp = (unsigned*)A(sizeof(unsigned) * plane);
     t.slot_B = A((D->prec == 0 ? 8 : 4) * (size_t)plane * d.max_solids);
     t.slot_beta = (double*)A(sizeof(double) * (size_t)plane * d.max_solids);
+    t.tile_ed = (unsigned*)A(sizeof(unsigned) * 2 * (size_t)g.ntiles);
     t.partial = (double*)A(sizeof(double) * 6 * t.cap);
     D->tile_count = (int*)A(sizeof(int) * g.ntiles);
     D->tile_fill = (int*)A(sizeof(int) * g.ntiles);
@@ -535,10 +543,12 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
             hipMemsetAsync(D->tile_fill, 0, sizeof(int) * g.ntiles, D->s) != hipSuccess ||
             hipMemsetAsync(D->t.vinv, 0, sizeof(int) * D->t.cap, D->s) != hipSuccess ||
             hipMemsetAsync(D->t.slot_lp, 0xff, sizeof(unsigned) * g.ntiles * (size_t)PSM_TILE, D->s) != hipSuccess ||
+            hipMemsetAsync(D->t.tile_ed, 0, sizeof(unsigned) * 2 * (size_t)g.ntiles, D->s) != hipSuccess ||
             hipMemsetAsync(D->cell_pid, 0, sizeof(int) * D->reg_cap, D->s) != hipSuccess ||
             hipMemsetAsync(D->fused_age, 0xff, sizeof(int), D->s) != hipSuccess ||
             (D->fz && hipMemsetAsync(D->fz, 0xff, sizeof(int), D->s) != hipSuccess) ||
             hipMemsetAsync(D->list_flag, 0, 2 * sizeof(int), D->s) != hipSuccess ||
+            (D->ell_cnt && hipMemsetAsync(D->ell_cnt, 0, sizeof(unsigned) * DEM_ELL_SEGS, D->s) != hipSuccess) ||
             hipStreamSynchronize(D->s) != hipSuccess)
             rc = PSMDEM_E_HIP;
     }
@@ -983,6 +993,18 @@ extern "C" psmdem_status psmdem_counters(psmdem_domain* d, psmdem_counters_t* ou
     for (long long t = 0; t < d->geo.ntiles; ++t) out->n_solid_tiles += ts[t + 1] > ts[t];
     out->n_entries = (int64_t)c.entries;
     out->n_dropped = (int64_t)c.dropped;
+    if (d->t.tile_ed && d->np > 0 && d->tile_counts) {
+        // the per-tile words of the last selection
+        std::vector<unsigned> ed(2 * (size_t)d->geo.ntiles);
+        PSM_CHECK(hipMemcpy(ed.data(), d->t.tile_ed, sizeof(unsigned) * ed.size(), hipMemcpyDeviceToHost));
+        int64_t e = 0, dr = 0;
+        for (size_t k = 0; k < ed.size(); k += 2) {
+            e += ed[k];
+            dr += ed[k + 1];
+        }
+        out->n_entries = e;
+        out->n_dropped = dr;
+    }
     out->step = d->step;
     out->flags = (int64_t)c.flags;
     return PSMDEM_OK;

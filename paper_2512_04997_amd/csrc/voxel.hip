@@ -309,7 +309,8 @@ struct VoxPart {
 };
 static_assert(sizeof(VoxPart) % 8 == 0, "VoxPart is copied in 8-byte words");
 
-__device__ inline bool in_box(const VoxPart& P, int x, int n, int axis, int periodic, int* X) {
+template <typename PT>
+__device__ inline bool in_box(const PT& P, int x, int n, int axis, int periodic, int* X) {
     int lo = P.lo[axis], hi = P.hi[axis];
     int v;
     if (periodic) {
@@ -413,7 +414,8 @@ __device__ inline bool sample_in(const VoxPart& P, int X, int Y, int Z, const do
     return ell_q(P, dx, dy, dz) < 1.0;
 }
 
-__device__ inline double beta_distance(const VoxPart& P, int X, int Y, int Z, double Rc) {
+template <typename PT>
+__device__ inline double beta_distance(const PT& P, int X, int Y, int Z, double Rc) {
     const double R = P.ax[0];
     double dx = ((double)X + 0.5) - P.c[0], dy = ((double)Y + 0.5) - P.c[1], dz = ((double)Z + 0.5) - P.c[2];
     double dist = sqrt((dx * dx + dy * dy) + dz * dz);
@@ -529,7 +531,8 @@ __device__ inline void stage_particles(const VoxArgs& A, VoxPart* sp, double* of
 
 // candidates of a lane's (x, y) column: bit u set when particle u's lattice box
 // holds x and y (ascending u = ascending pid)
-__device__ inline void column_masks(const VoxArgs& A, const VoxPart* sp, int count, int x, int y, bool xy_ok,
+template <typename PT>
+__device__ inline void column_masks(const VoxArgs& A, const PT* sp, int count, int x, int y, bool xy_ok,
                                     unsigned long long& cm0, unsigned long long& cm1) {
     cm0 = cm1 = 0;
     if (!xy_ok) return;
@@ -676,80 +679,136 @@ __device__ inline int sample_count(const VoxPart& P, int X, int Y, int Z, const 
 // lookup(j, P, X, Y, Z) (the count box); else boundary cells take their count
 // from lookup(j, P, X, Y, Z), j running from my_off in the order of
 // for_each_pair, and the others are classified.
-template <typename C, bool BOX, typename L>
-__device__ inline void select_slots(const VoxArgs& A, const VoxPart* sp, long long t, int tz, int x, int y, bool xy_ok,
+// the kept slots of one cell (T in descending beta, ties to the smaller pid),
+// ordered by pid, into slot_lp, slot_B and slot_beta
+template <typename C>
+__device__ inline void write_slots(const VoxArgs& A, Top4& T, long long cell) {
+    C* Bout = (C*)A.t.slot_B;
+    const long long plane = A.g.ntiles * (long long)PSM_TILE;
+    top_by_pid(T);
+    unsigned int lp = 0xffffffffu;
+    if (T.n > 0) lp = (lp & ~0xffu) | (unsigned)T.l0;
+    if (T.n > 1) lp = (lp & ~0xff00u) | ((unsigned)T.l1 << 8);
+    if (T.n > 2) lp = (lp & ~0xff0000u) | ((unsigned)T.l2 << 16);
+    if (T.n > 3) lp = (lp & ~0xff000000u) | ((unsigned)T.l3 << 24);
+    A.t.slot_lp[cell] = lp;
+    const double bq[PSM_SLOTS_MAX] = {T.n > 0 ? T.b0 : 0.0, T.n > 1 ? T.b1 : 0.0, T.n > 2 ? T.b2 : 0.0,
+                                      T.n > 3 ? T.b3 : 0.0};
+    // only the kept slots are written: readers stop at the first empty index of slot_lp
+#pragma unroll
+    for (int q = 0; q < PSM_SLOTS_MAX; ++q)
+        if (q < A.ms && q < T.n) {
+            const double beta = bq[q];
+            const double B = beta * (A.tau - 0.5) / ((1.0 - beta) + (A.tau - 0.5));
+            Bout[q * plane + cell] = (C)B;
+            A.t.slot_beta[q * plane + cell] = beta;
+        }
+}
+
+// the workgroup's entry and drop counts: into the tile's own words when the
+// domain keeps them (a global atomic per workgroup on one address would queue
+// every tile of the lattice behind it), else into the step's counters
+__device__ inline void add_entry_counts(const VoxArgs& A, long long t, unsigned long long my_e,
+                                        unsigned long long my_d, unsigned long long* cnt_e,
+                                        unsigned long long* cnt_d) {
+    if (my_e) atomicAdd(cnt_e, my_e);
+    if (my_d) atomicAdd(cnt_d, my_d);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (A.t.tile_ed) {
+            A.t.tile_ed[2 * t] = (unsigned)*cnt_e;
+            A.t.tile_ed[2 * t + 1] = (unsigned)*cnt_d;
+        } else {
+            if (*cnt_e) atomicAdd(&A.ctr->entries, *cnt_e);
+            if (*cnt_d) atomicAdd(&A.ctr->dropped, *cnt_d);
+        }
+    }
+}
+
+// Phase C: beta per (cell, particle) in pid order, keep the largest ms, write
+// the slots.  BOX: the subdivision count of every (cell, particle) is
+// lookup(P, X, Y, Z) (the count box); the candidates are visited once for the
+// lane's four planes together, so the four planes' count loads are in flight
+// at once.  Else boundary cells take their count from lookup(j, P, X, Y, Z), j
+// running from my_off in the order of for_each_pair, and the others are
+// classified.  Every plane sees its candidates in ascending pid, as the
+// selection's tie rule needs.
+template <typename C, bool BOX, typename PT, typename L>
+__device__ inline void select_slots(const VoxArgs& A, const PT* sp, long long t, int tz, int x, int y, bool xy_ok,
                                     unsigned long long cm0, unsigned long long cm1, double slo, double shi,
                                     int my_off, L lookup, unsigned long long* cnt_e, unsigned long long* cnt_d) {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const int ms = A.ms, n3 = A.ns * A.ns * A.ns;
     const bool subdiv = A.sf_method == 0;
-    C* Bout = (C*)A.t.slot_B;
-    const long long plane = A.g.ntiles * (long long)PSM_TILE;
     const long long base = t * (long long)PSM_TILE;
     unsigned long long my_e = 0, my_d = 0;
-    int j = my_off;
-    for (int lz = 0; lz < PSM_TZ; ++lz) {
-        const int z = tz * PSM_TZ + lz;
-        const long long l = lane + PSM_TX * (wid + PSM_TY * lz);
-        Top4 T;
-        if (xy_ok && z < A.g.nz) {
+    if constexpr (BOX) {
+        Top4 T[PSM_TZ];
+        if (xy_ok)
             for (int w = 0; w < 2; ++w)
                 for (unsigned long long bits = w ? cm1 : cm0; bits; bits &= bits - 1) {
                     const int u = 64 * w + __ffsll((long long)bits) - 1;
-                    const VoxPart& P = sp[u];
-                    int X, Y, Z;
+                    const PT& P = sp[u];
+                    int X, Y;
                     in_box(P, x, A.g.nx, 0, A.g.periodic[0], &X);
                     in_box(P, y, A.g.ny, 1, A.g.periodic[1], &Y);
-                    if (!in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z)) continue;
-                    double beta;
-                    if (!subdiv) {
-                        beta = beta_distance(P, X, Y, Z, A.Rc);
-                    } else if (BOX) {
-                        beta = (double)lookup(j, P, X, Y, Z) / (double)n3;
-                    } else {
-                        const int cl = classify(P, X, Y, Z, slo, shi);
-                        if (cl == 0) continue;
-                        if (cl == 1) {
-                            beta = 1.0;
-                        } else {
-                            const int cnt = lookup(j, P, X, Y, Z);
-                            ++j;
-                            beta = (double)cnt / (double)n3;
-                        }
-                    }
-                    if (!(beta > 0.0)) continue;
-                    ++my_e;
-                    keep_top(T, ms, beta, u, my_d);
-                }
-        }
-        top_by_pid(T);
-        unsigned int lp = 0xffffffffu;
-        if (T.n > 0) lp = (lp & ~0xffu) | (unsigned)T.l0;
-        if (T.n > 1) lp = (lp & ~0xff00u) | ((unsigned)T.l1 << 8);
-        if (T.n > 2) lp = (lp & ~0xff0000u) | ((unsigned)T.l2 << 16);
-        if (T.n > 3) lp = (lp & ~0xff000000u) | ((unsigned)T.l3 << 24);
-        if (xy_ok && z < A.g.nz) {
-            A.t.slot_lp[base + l] = lp;
-            const double bq[PSM_SLOTS_MAX] = {T.n > 0 ? T.b0 : 0.0, T.n > 1 ? T.b1 : 0.0, T.n > 2 ? T.b2 : 0.0,
-                                              T.n > 3 ? T.b3 : 0.0};
-            // only the kept slots are written: readers stop at the first
-            // empty index of slot_lp
+                    double beta[PSM_TZ];
 #pragma unroll
-            for (int q = 0; q < PSM_SLOTS_MAX; ++q)
-                if (q < ms && q < T.n) {
-                    const double beta = bq[q];
-                    const double B = beta * (A.tau - 0.5) / ((1.0 - beta) + (A.tau - 0.5));
-                    Bout[q * plane + base + l] = (C)B;
-                    A.t.slot_beta[q * plane + base + l] = beta;
+                    for (int lz = 0; lz < PSM_TZ; ++lz) {
+                        const int z = tz * PSM_TZ + lz;
+                        int Z;
+                        beta[lz] = 0.0;
+                        if (z < A.g.nz && in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z))
+                            beta[lz] = subdiv ? (double)lookup(P, X, Y, Z) / (double)n3 : beta_distance(P, X, Y, Z, A.Rc);
+                    }
+#pragma unroll
+                    for (int lz = 0; lz < PSM_TZ; ++lz)
+                        if (beta[lz] > 0.0) {
+                            ++my_e;
+                            keep_top(T[lz], ms, beta[lz], u, my_d);
+                        }
                 }
+#pragma unroll
+        for (int lz = 0; lz < PSM_TZ; ++lz)
+            if (xy_ok && tz * PSM_TZ + lz < A.g.nz) write_slots<C>(A, T[lz], base + lane + PSM_TX * (wid + PSM_TY * lz));
+        add_entry_counts(A, t, my_e, my_d, cnt_e, cnt_d);
+        return;
+    } else {
+        int j = my_off;
+        for (int lz = 0; lz < PSM_TZ; ++lz) {
+            const int z = tz * PSM_TZ + lz;
+            Top4 T;
+            if (xy_ok && z < A.g.nz) {
+                for (int w = 0; w < 2; ++w)
+                    for (unsigned long long bits = w ? cm1 : cm0; bits; bits &= bits - 1) {
+                        const int u = 64 * w + __ffsll((long long)bits) - 1;
+                        const PT& P = sp[u];
+                        int X, Y, Z;
+                        in_box(P, x, A.g.nx, 0, A.g.periodic[0], &X);
+                        in_box(P, y, A.g.ny, 1, A.g.periodic[1], &Y);
+                        if (!in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z)) continue;
+                        double beta;
+                        if (!subdiv) {
+                            beta = beta_distance(P, X, Y, Z, A.Rc);
+                        } else {
+                            const int cl = classify(P, X, Y, Z, slo, shi);
+                            if (cl == 0) continue;
+                            if (cl == 1) {
+                                beta = 1.0;
+                            } else {
+                                const int cnt = lookup(j, P, X, Y, Z);
+                                ++j;
+                                beta = (double)cnt / (double)n3;
+                            }
+                        }
+                        if (!(beta > 0.0)) continue;
+                        ++my_e;
+                        keep_top(T, ms, beta, u, my_d);
+                    }
+                write_slots<C>(A, T, base + lane + PSM_TX * (wid + PSM_TY * lz));
+            }
         }
-    }
-    if (my_e) atomicAdd(cnt_e, my_e);
-    if (my_d) atomicAdd(cnt_d, my_d);
-    __syncthreads();
-    if (tid == 0) {
-        if (*cnt_e) atomicAdd(&A.ctr->entries, *cnt_e);
-        if (*cnt_d) atomicAdd(&A.ctr->dropped, *cnt_d);
+        add_entry_counts(A, t, my_e, my_d, cnt_e, cnt_d);
     }
 }
 
@@ -830,7 +889,7 @@ __device__ void voxelize_tile(const VoxArgs& A, const long long t) {
         if (lane == 0) qcnt[it] = cnt;
     }
     __syncthreads();
-    select_slots<C, false>(A, sp, t, R.tz, x, y, xy_ok, cm0, cm1, slo, shi, my_off,
+    select_slots<C, false, VoxPart>(A, sp, t, R.tz, x, y, xy_ok, cm0, cm1, slo, shi, my_off,
                     [&](int j, const VoxPart& P, int X, int Y, int Z) {
                         if (j < VOX_QCAP) return qcnt[j];
                         int cnt = 0;
@@ -878,6 +937,88 @@ __device__ inline int sample_exact(const VoxPart& P, double dx, double dy, doubl
     return (((p0 * p0) * P.inv[0] + (p1 * p1) * P.inv[1]) + (p2 * p2) * P.inv[2]) < 1.0 ? 1 : 0;
 }
 
+// the row quadratic's coefficients of one particle (see k_vox_rows)
+struct RowQ {
+    double A, iA, by, bz, cyy, cyz, czz, a2, mt, xl, gmax, fns;
+};
+
+// Row dy, dz of the cell row `row` (LDS counts of the box's x cells): the
+// samples certainly inside are the global sample indices glo..ghi along the
+// row (g = (X - lo_x) ns + a, at x = xl + (g + 1/2) / ns; empty: glo > ghi),
+// returned for the caller to add; samples within the margin of a root, and
+// every sample of a grazing row, are tested and added here.
+__device__ inline void row_inside(const VoxPart& P, const RowQ& q, const double* off, int ns, double dy, double dz,
+                                  double bzz, double cyzz, double czzz, int* row, int& glo, int& ghi) {
+    glo = 1;
+    ghi = 0;
+    const double B = q.by * dy + bzz;
+    const double Cm1 = (q.cyy * dy * dy + cyzz * dy + czzz) - 1.0;
+    const double disc = B * B - q.A * Cm1;
+    const double tol = 1e-6 * (B * B + q.A * fabs(Cm1)) + 1e-10;
+    if (disc <= -tol) return;  // the row misses it
+    if (disc < tol) {          // a row grazing the surface: every sample
+        for (int X = P.lo[0]; X <= P.hi[0]; ++X) {
+            int kx = 0;
+            for (int a = 0; a < ns; ++a) kx += sample_exact(P, ((double)X + off[a]) - P.c[0], dy, dz);
+            if (kx) atomicAdd(&row[X - P.lo[0]], kx);
+        }
+        return;
+    }
+    const double sq = sqrt(disc);
+    const double G1 = ((-B - sq) * q.iA - q.xl) * q.fns - 0.5, G2 = ((-B + sq) * q.iA - q.xl) * q.fns - 0.5;
+    const double lo = fmax(floor(G1 + q.mt) + 1.0, 0.0), hi = fmin(ceil(G2 - q.mt) - 1.0, q.gmax);
+    if (hi >= lo) {
+        glo = (int)lo;
+        ghi = (int)hi;
+    }
+    const double u0 = fmax(ceil(G1 - q.mt), 0.0), u1 = fmin(floor(G1 + q.mt), q.gmax);
+    for (double g = u0; g <= u1; g += 1.0) {
+        const int gi = (int)g;
+        if (sample_exact(P, ((double)(P.lo[0] + gi / ns) + off[gi % ns]) - P.c[0], dy, dz))
+            atomicAdd(&row[gi / ns], 1);
+    }
+    const double v0 = fmax(ceil(G2 - q.mt), 0.0), v1 = fmin(floor(G2 + q.mt), q.gmax);
+    for (double g = v0; g <= v1; g += 1.0) {
+        if (fabs(g - G1) <= q.mt) continue;
+        const int gi = (int)g;
+        if (sample_exact(P, ((double)(P.lo[0] + gi / ns) + off[gi % ns]) - P.c[0], dy, dz))
+            atomicAdd(&row[gi / ns], 1);
+    }
+}
+
+// samples of the index range glo..ghi per cell of the row
+__device__ inline int range_in_cell(int glo, int ghi, int i, int ns) {
+    const int a0 = i * ns, a1 = a0 + ns - 1;
+    const int n = (ghi < a1 ? ghi : a1) - (glo > a0 ? glo : a0) + 1;
+    return n > 0 ? n : 0;
+}
+
+// Inside samples of every cell of particle P's lattice box, by one workgroup,
+// a row of samples at a time.  Along a row (fixed y and z offsets dy, dz) the
+// normalised test value is a quadratic in the x offset,
+//   Q(x) = A x^2 + 2 B x + C,   inside when Q < 1,
+// with A, B, C from the inverse shape matrix (an ellipsoid: p = R^T d and
+// A = sum_k inv_k R_0k^2, B = sum_k inv_k R_0k w_k, C = sum_k inv_k w_k^2,
+// w_k = R_1k dy + R_2k dz; a sphere: A = 1/r^2, B = 0, C = (dy^2 + dz^2)/r^2).
+// The inside samples of a row lie between the roots r1 < r2 of Q = 1.  A
+// sample farther than m = 1e-5 (1 + a_max) from both roots is decided by its
+// side, since there |Q - 1| >= A m min(m, r2 - r1) lies far above the
+// rounding of any evaluation of Q (the roots are formed only when the
+// discriminant clears its own rounding bound by a factor 1e6); samples within
+// m of a root, and every sample of a row whose discriminant is within that
+// bound of zero (a row grazing the surface), are tested with the definition's
+// own evaluation order.  Per z-sample plane only the rows whose discriminant
+// can be positive are visited: as a function of dy it is the concave
+// quadratic a2 dy^2 + a1 dy + a0, and outside its roots widened by 1e-3 it is
+// below a2 1e-6 < 0, far beyond its rounding.  The counts therefore equal the
+// per-sample definition's bit for bit; a row costs a root and a few integer
+// operations instead of one test per sample.  A work item is one z-sample
+// plane of one cell row: with NS (compile-time samples per direction) its NS
+// sample rows are summed per cell before one LDS add per cell, else each row
+// adds its own.  The counts accumulate in LDS (z-slabs of the box that fit)
+// and go to the particle's count box in global memory, one 16-bit count per
+// cell, x fastest.
+template <int NS>
 __global__ __launch_bounds__(VOX_T) void k_vox_rows(VoxArgs A) {
     __shared__ VoxPart P;
     __shared__ double off[32];
@@ -888,87 +1029,85 @@ __global__ __launch_bounds__(VOX_T) void k_vox_rows(VoxArgs A) {
     if (tid < A.ns) off[tid] = (double)(2 * tid + 1) / (double)(2 * A.ns);
     if (tid == 0) P = ((const VoxPart*)A.vpart)[k];
     __syncthreads();
-    const int ns = A.ns;
+    const int ns = NS > 0 ? NS : A.ns;
     const int bx = P.hi[0] - P.lo[0] + 1, by_ = P.hi[1] - P.lo[1] + 1, bz_ = P.hi[2] - P.lo[2] + 1;
     if (bx <= 0 || by_ <= 0 || bz_ <= 0) return;  // a blown-up particle: no box
     unsigned short* box = A.vbox + (long long)k * A.box_stride;
-    double Aq, by, bz, cyy, cyz, czz, amax;
+    RowQ q;
+    double amax;
     if (P.shape == 0) {
         const double i2 = 1.0 / (P.ax[0] * P.ax[0]);
-        Aq = i2; by = 0.0; bz = 0.0; cyy = i2; cyz = 0.0; czz = i2;
+        q.A = i2; q.by = 0.0; q.bz = 0.0; q.cyy = i2; q.cyz = 0.0; q.czz = i2;
         amax = P.ax[0];
     } else {
-        Aq = by = bz = cyy = cyz = czz = 0.0;
+        q.A = q.by = q.bz = q.cyy = q.cyz = q.czz = 0.0;
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            const double r0 = P.R[q], r1 = P.R[3 + q], r2 = P.R[6 + q], iv = P.inv[q];
-            Aq += iv * r0 * r0;
-            by += iv * r0 * r1;
-            bz += iv * r0 * r2;
-            cyy += iv * r1 * r1;
-            cyz += iv * r1 * r2;
-            czz += iv * r2 * r2;
+        for (int d = 0; d < 3; ++d) {
+            const double r0 = P.R[d], r1 = P.R[3 + d], r2 = P.R[6 + d], iv = P.inv[d];
+            q.A += iv * r0 * r0;
+            q.by += iv * r0 * r1;
+            q.bz += iv * r0 * r2;
+            q.cyy += iv * r1 * r1;
+            q.cyz += iv * r1 * r2;
+            q.czz += iv * r2 * r2;
         }
         amax = fmax(P.ax[0], fmax(P.ax[1], P.ax[2]));
     }
-    const double iA = 1.0 / Aq;
-    const double fns = (double)ns, mt = 1e-5 * (1.0 + amax) * fns, top = fns - 1.0;
-    const double a2 = by * by - Aq * cyy, my = 1e-3;
+    q.iA = 1.0 / q.A;
+    q.fns = (double)ns;
+    q.mt = 1e-5 * (1.0 + amax) * q.fns;
+    q.a2 = q.by * q.by - q.A * q.cyy;
+    q.xl = (double)P.lo[0] - P.c[0];
+    q.gmax = (double)(bx * ns - 1);
+    const double my = 1e-3;
     const int plane_cells = bx * by_;
     const int pz = VOX_BOX_LDS / plane_cells;  // z-planes per slab (the box's x-y plane fits: checked at creation)
     for (int z0 = 0; z0 < bz_; z0 += pz) {
         const int nzs = bz_ - z0 < pz ? bz_ - z0 : pz;
         for (int c = tid; c < nzs * plane_cells; c += VOX_T) cnt_s[c] = 0;
         __syncthreads();
-        // work items (z-sample plane c of cell layer Z, cell row Y): the ns sample rows b
         const int items = nzs * ns * by_;
         for (int it = tid; it < items; it += VOX_T) {
             const int Yr = it % by_, cz = (it / by_) % ns, Zr = it / (by_ * ns);
             const int Z = P.lo[2] + z0 + Zr, Y = P.lo[1] + Yr;
             const double dz = ((double)Z + off[cz]) - P.c[2];
-            const double bzz = bz * dz, czzz = czz * dz * dz, cyzz = 2.0 * cyz * dz;
-            const double a1 = 2.0 * by * bzz - Aq * cyzz;
-            const double a0 = bzz * bzz - Aq * (czzz - 1.0);
-            const double D = a1 * a1 - 4.0 * a2 * a0;
-            if (D < -(1e-9 * (a1 * a1 + 4.0 * fabs(a2 * a0)) + 1e-12)) continue;  // the plane misses it
+            const double bzz = q.bz * dz, czzz = q.czz * dz * dz, cyzz = 2.0 * q.cyz * dz;
+            const double a1 = 2.0 * q.by * bzz - q.A * cyzz;
+            const double a0 = bzz * bzz - q.A * (czzz - 1.0);
+            const double D = a1 * a1 - 4.0 * q.a2 * a0;
+            if (D < -(1e-9 * (a1 * a1 + 4.0 * fabs(q.a2 * a0)) + 1e-12)) continue;  // the plane misses it
             const double sD = sqrt(D > 0.0 ? D : 0.0);
-            const double y1 = (-a1 + sD) / (2.0 * a2), y2 = (-a1 - sD) / (2.0 * a2);
+            const double y1 = (-a1 + sD) / (2.0 * q.a2), y2 = (-a1 - sD) / (2.0 * q.a2);
             const double ylo = fmin(y1, y2) - my, yhi = fmax(y1, y2) + my;
             int* row = cnt_s + plane_cells * Zr + bx * Yr;
-            for (int b = 0; b < ns; ++b) {
-                const double dy = ((double)Y + off[b]) - P.c[1];
-                if (dy < ylo || dy > yhi) continue;
-                const double B = by * dy + bzz;
-                const double Cm1 = (cyy * dy * dy + cyzz * dy + czzz) - 1.0;
-                const double disc = B * B - Aq * Cm1;
-                const double tol = 1e-6 * (B * B + Aq * fabs(Cm1)) + 1e-10;
-                if (disc <= -tol) continue;  // the row misses it
-                if (disc < tol) {            // a row grazing the surface: every sample
-                    for (int X = P.lo[0]; X <= P.hi[0]; ++X) {
-                        int kx = 0;
-                        for (int a = 0; a < ns; ++a) kx += sample_exact(P, ((double)X + off[a]) - P.c[0], dy, dz);
-                        if (kx) atomicAdd(&row[X - P.lo[0]], kx);
+            if (NS > 0) {
+                int glo[NS > 0 ? NS : 1], ghi[NS > 0 ? NS : 1];
+                int i0 = 1 << 30, i1 = -1;
+#pragma unroll
+                for (int b = 0; b < NS; ++b) {
+                    glo[b] = 1;
+                    ghi[b] = 0;
+                    const double dy = ((double)Y + off[b]) - P.c[1];
+                    if (dy < ylo || dy > yhi) continue;
+                    row_inside(P, q, off, NS, dy, dz, bzz, cyzz, czzz, row, glo[b], ghi[b]);
+                    if (glo[b] <= ghi[b]) {
+                        i0 = min(i0, glo[b] / NS);
+                        i1 = max(i1, ghi[b] / NS);
                     }
-                    continue;
                 }
-                const double sq = sqrt(disc);
-                const double r1 = (-B - sq) * iA, r2 = (-B + sq) * iA;
-                int X0 = (int)floor(P.c[0] + r1) - 1, X1 = (int)floor(P.c[0] + r2) + 1;
-                X0 = X0 < P.lo[0] ? P.lo[0] : X0;
-                X1 = X1 > P.hi[0] ? P.hi[0] : X1;
-                for (int X = X0; X <= X1; ++X) {
-                    // sample a of cell X lies at x = (X - c_x) + (a + 1/2) / ns
-                    const double xb = (double)X - P.c[0];
-                    const double t1 = (r1 - xb) * fns - 0.5, t2 = (r2 - xb) * fns - 0.5;
-                    const double lo = fmax(floor(t1 + mt) + 1.0, 0.0), hi = fmin(ceil(t2 - mt) - 1.0, top);
-                    int kx = hi >= lo ? (int)(hi - lo) + 1 : 0;
-                    const double u0 = fmax(ceil(t1 - mt), 0.0), u1 = fmin(floor(t1 + mt), top);
-                    for (double a = u0; a <= u1; a += 1.0)
-                        kx += sample_exact(P, ((double)X + off[(int)a]) - P.c[0], dy, dz);
-                    const double v0 = fmax(ceil(t2 - mt), 0.0), v1 = fmin(floor(t2 + mt), top);
-                    for (double a = v0; a <= v1; a += 1.0)
-                        if (!(fabs(a - t1) <= mt)) kx += sample_exact(P, ((double)X + off[(int)a]) - P.c[0], dy, dz);
-                    if (kx) atomicAdd(&row[X - P.lo[0]], kx);
+                for (int i = i0; i <= i1; ++i) {
+                    int n = 0;
+#pragma unroll
+                    for (int b = 0; b < NS; ++b) n += range_in_cell(glo[b], ghi[b], i, NS);
+                    if (n) atomicAdd(&row[i], n);
+                }
+            } else {
+                for (int b = 0; b < ns; ++b) {
+                    const double dy = ((double)Y + off[b]) - P.c[1];
+                    if (dy < ylo || dy > yhi) continue;
+                    int glo, ghi;
+                    row_inside(P, q, off, ns, dy, dz, bzz, cyzz, czzz, row, glo, ghi);
+                    for (int i = glo / ns; glo <= ghi && i <= ghi / ns; ++i) atomicAdd(&row[i], range_in_cell(glo, ghi, i, ns));
                 }
             }
         }
@@ -979,10 +1118,18 @@ __global__ __launch_bounds__(VOX_T) void k_vox_rows(VoxArgs A) {
     }
 }
 
+// what the selection needs of a candidate (staged in LDS, a quarter of a full record)
+struct SelPart {
+    double c[3];
+    double ax[1];   // radius (the distance method)
+    int lo[3], hi[3];
+    int shape, pid;
+};
+
 // per tile: select the kept solids, the subdivision counts from the count boxes
 template <typename C, bool SORT>
 __global__ __launch_bounds__(VOX_T) void k_vox_select(VoxArgs A) {
-    __shared__ VoxPart sp[PSM_PMAX];
+    __shared__ SelPart sp[PSM_PMAX];
     __shared__ double off[32];
     __shared__ unsigned long long ks[SORT ? VOX_T : 1];
     __shared__ unsigned long long cnt_e, cnt_d;
@@ -990,10 +1137,27 @@ __global__ __launch_bounds__(VOX_T) void k_vox_select(VoxArgs A) {
     if (t >= A.g.ntiles) return;
     const unsigned long long* keys = SORT ? sort_tile_list(A, t, ks) : nullptr;
     const TileRange R = tile_range(A, t);
-    if (R.count <= 0) return;
+    if (R.count <= 0) {
+        if (threadIdx.x == 0 && A.t.tile_ed) A.t.tile_ed[2 * t] = A.t.tile_ed[2 * t + 1] = 0u;
+        return;
+    }
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     if (tid == 0) { cnt_e = 0; cnt_d = 0; }
-    stage_particles(A, sp, off, R.s0, R.count, keys);
+    if (tid < A.ns) off[tid] = (double)(2 * tid + 1) / (double)(2 * A.ns);
+    for (int u = tid; u < R.count; u += VOX_T) {
+        int k = (int)((keys ? keys[u] : A.t.tile_list[R.s0 + u]) >> 32);
+        if (k >= A.p.np) k = 0;
+        const VoxPart& V = ((const VoxPart*)A.vpart)[k];
+        SelPart& P = sp[u];
+        for (int a = 0; a < 3; ++a) {
+            P.c[a] = V.c[a];
+            P.lo[a] = V.lo[a];
+            P.hi[a] = V.hi[a];
+        }
+        P.ax[0] = V.ax[0];
+        P.shape = V.shape;
+        P.pid = V.pid;
+    }
     __syncthreads();
     const double slo = off[0], shi = off[A.ns - 1];  // first and last sample offset
     const int x = R.tx * PSM_TX + lane, y = R.ty * PSM_TY + wid;
@@ -1002,8 +1166,8 @@ __global__ __launch_bounds__(VOX_T) void k_vox_select(VoxArgs A) {
     column_masks(A, sp, R.count, x, y, xy_ok, cm0, cm1);
     const unsigned short* vbox = A.vbox;
     const long long stride = A.box_stride;
-    select_slots<C, true>(A, sp, t, R.tz, x, y, xy_ok, cm0, cm1, slo, shi, 0,
-                          [&](int, const VoxPart& P, int X, int Y, int Z) {
+    select_slots<C, true, SelPart>(A, sp, t, R.tz, x, y, xy_ok, cm0, cm1, slo, shi, 0,
+                          [&](const SelPart& P, int X, int Y, int Z) {
                               const int bx = P.hi[0] - P.lo[0] + 1, by = P.hi[1] - P.lo[1] + 1;
                               return (int)vbox[(long long)P.pid * stride + (X - P.lo[0]) +
                                                (long long)bx * ((Y - P.lo[1]) + (long long)by * (Z - P.lo[2]))];
@@ -1058,7 +1222,10 @@ hipError_t vox_voxelize(const VoxArgs& A, int ctype_double, hipStream_t s) {
     const unsigned nt = (unsigned)A.g.ntiles;
     const bool sort = A.g.ntiles <= VOX_SORT_IN_TILE_MAX;
     if (A.p.np > 0) k_vox_parts<<<nblk(A.p.np), 256, 0, s>>>(A);
-    if (A.sf_method == 0 && A.p.np > 0) k_vox_rows<<<(unsigned)A.p.np, VOX_T, 0, s>>>(A);
+    if (A.sf_method == 0 && A.p.np > 0) {
+        if (A.ns == 10) k_vox_rows<10><<<(unsigned)A.p.np, VOX_T, 0, s>>>(A);
+        else k_vox_rows<0><<<(unsigned)A.p.np, VOX_T, 0, s>>>(A);
+    }
     // (small lattices: the select kernel orders each tile's list)
     if (ctype_double) {
         if (sort) k_vox_select<double, true><<<nt, VOX_T, 0, s>>>(A);
