@@ -311,6 +311,88 @@ __device__ void ellipsoid_pair(const DemArgs& A, int i, int j, Geom& G) {
     }
 }
 
+// The same iteration with the pair on two adjacent lanes: side 0 evaluates
+// ellipsoid i, side 1 ellipsoid j, and the lanes swap the sphere centres, the
+// hit flags and the point moves they need of each other.  Every quantity both
+// lanes branch on is formed from the same operands in the same order on both,
+// so the two take each branch together and each exchange finds its partner
+// active; the results are those of ellipsoid_pair, operation for operation.
+__device__ inline double lane_swap(double v) { return __shfl_xor(v, 1, 64); }
+
+__device__ void ellipsoid_pair2(const DemArgs& A, int i, int j, int side, Geom& G) {
+    const double* ci = A.p.pos + 3 * i;
+    double dvec[3];
+    min_image(A, ci, A.p.pos + 3 * j, dvec);
+    const double cj[3] = {ci[0] - dvec[0], ci[1] - dvec[1], ci[2] - dvec[2]};
+    const int me = side ? j : i;
+    const double c[3] = {side ? cj[0] : ci[0], side ? cj[1] : ci[1], side ? cj[2] : ci[2]};
+    double R[9];
+    quat_rbw(A.p.q + 4 * me, R);
+    const double* ax = A.p.semi + 3 * me;
+    const double* ai = A.p.semi + 3 * i;
+    const double* aj = A.p.semi + 3 * j;
+    double amin = ai[0];
+    for (int k = 0; k < 3; ++k) {
+        amin = ai[k] < amin ? ai[k] : amin;
+        amin = aj[k] < amin ? aj[k] : amin;
+    }
+    double p[3];
+    {
+        double u[3] = {cj[0] - ci[0], cj[1] - ci[1], cj[2] - ci[2]};
+        double l = sqrt(dot3(u, u));
+        for (int k = 0; k < 3; ++k) u[k] /= l;
+        const double dir[3] = {side ? -u[0] : u[0], side ? -u[1] : u[1], side ? -u[2] : u[2]};
+        ell_line_hit(c, R, ax, c, dir, true, p);
+    }
+    for (int it = 0; it < 32; ++it) {
+        double rho, n[3], sc[3], so[3];
+        ell_local(c, R, ax, p, &rho, n);
+        for (int k = 0; k < 3; ++k) sc[k] = p[k] - rho * n[k];
+        for (int k = 0; k < 3; ++k) so[k] = lane_swap(sc[k]);
+        const double* si = side ? so : sc;
+        const double* sj = side ? sc : so;
+        double u[3] = {sj[0] - si[0], sj[1] - si[1], sj[2] - si[2]};
+        double l = sqrt(dot3(u, u));
+        if (!(l > 0.0)) break;
+        for (int k = 0; k < 3; ++k) u[k] /= l;
+        double np_[3];
+        const int hit = ell_line_hit(c, R, ax, sc, u, side == 0, np_) ? 1 : 0;
+        const int hit_o = __shfl_xor(hit, 1, 64);
+        if (!(hit && hit_o)) break;
+        double dp[3] = {np_[0] - p[0], np_[1] - p[1], np_[2] - p[2]};
+        const double m = sqrt(dot3(dp, dp));
+        const double mo = lane_swap(m);
+        const double conv = side ? mo + m : m + mo;
+        for (int k = 0; k < 3; ++k) p[k] = np_[k];
+        if (conv < 1e-10 * amin) break;
+    }
+    double rho, n[3], sc[3], so[3], rc[3], ro[3];
+    ell_local(c, R, ax, p, &rho, n);
+    for (int k = 0; k < 3; ++k) {
+        sc[k] = p[k] - rho * n[k];
+        rc[k] = p[k] - c[k];
+    }
+    for (int k = 0; k < 3; ++k) {
+        so[k] = lane_swap(sc[k]);
+        ro[k] = lane_swap(rc[k]);
+    }
+    const double rho_o = lane_swap(rho);
+    const double* si = side ? so : sc;
+    const double* sj = side ? sc : so;
+    G.rhoi = side ? rho_o : rho;
+    G.rhoj = side ? rho : rho_o;
+    double d[3] = {si[0] - sj[0], si[1] - sj[1], si[2] - sj[2]};
+    double l = sqrt(dot3(d, d));
+    G.delta = (G.rhoi + G.rhoj) - l;
+    for (int k = 0; k < 3; ++k) {
+        G.en[k] = d[k] / l;
+        G.rci[k] = side ? ro[k] : rc[k];
+        G.rcj[k] = side ? rc[k] : ro[k];
+    }
+    G.sphere_law = false;
+    G.deferred = false;
+}
+
 // ci, cj: centres; shi, shj: shapes; ri, rj: first semi-axes (loaded by the
 // caller).  ELL = false compiles the sphere paths only (domains without
 // ellipsoids), which keeps the register budget of the contact kernels small.
@@ -536,6 +618,10 @@ __device__ inline long long n_pairs(const DemArgs& A, const PairBufs& B) {
 // With deferred non-null, an ellipsoid pair that needs the iteration is not
 // evaluated: *deferred is set and the pair's outputs are left to a later
 // ph_contact call (the dense iteration kernel).
+__device__ bool contact_law(const DemArgs& A, const PairBufs& B, long long s, unsigned long long key, const Geom& G,
+                            const double* __restrict__ vv, const double* __restrict__ ww, double dth, long long nprev,
+                            bool same_list, double* gap);
+
 template <bool ELL>
 __device__ bool ph_contact(const DemArgs& A, const PairBufs& B, long long s, const double* __restrict__ vv,
                            const double* __restrict__ ww, double dth, long long nprev, bool same_list = false,
@@ -559,6 +645,16 @@ __device__ bool ph_contact(const DemArgs& A, const PairBufs& B, long long s, con
         *deferred = true;
         return false;
     }
+    return contact_law(A, B, s, key, G, vv, ww, dth, nprev, same_list, gap);
+}
+
+// the contact law of pair s (key = B.pairs[s]) with its geometry G
+__device__ bool contact_law(const DemArgs& A, const PairBufs& B, long long s, unsigned long long key, const Geom& G,
+                            const double* __restrict__ vv, const double* __restrict__ ww, double dth, long long nprev,
+                            bool same_list, double* gap) {
+    const int np = A.p.np;
+    const int i = (int)(key >> 32), j = (int)(key & 0xffffffffu);
+    const bool wall = j >= np;
     double* F = A.cF + 3 * s;
     double* Mi = A.cMi + 3 * s;
     double* Mj = A.cMj + 3 * s;
@@ -1156,8 +1252,8 @@ __global__ __launch_bounds__(256) void k_contacts(DemArgs A, PairBufs B, const d
     }
 }
 
-// the queued ellipsoid pairs, one per lane, over the segments in order (the
-// counters are cleared by k_sum_wave)
+// the queued ellipsoid pairs, two lanes each (ellipsoid_pair2), over the
+// segments in order (the counters are cleared by k_sum_wave)
 __global__ __launch_bounds__(64) void k_contacts_ell(DemArgs A, PairBufs B, const double* vv, const double* ww,
                                                      double dth) {
     __shared__ unsigned start[DEM_ELL_SEGS + 1];
@@ -1173,15 +1269,22 @@ __global__ __launch_bounds__(64) void k_contacts_ell(DemArgs A, PairBufs B, cons
     long long nprev = B.prev_n ? *B.prev_n : 0;
     nprev = nprev < A.pair_cap ? nprev : A.pair_cap;
     const bool same = A.list_run && !*A.list_run;
-    GRID_LOOP(w, (long long)start[DEM_ELL_SEGS]) {
+    // lanes 2q and 2q + 1 take queued pair q (the grid's stride is even, so
+    // both lanes of a pair are always in the same pass)
+    GRID_LOOP(w2, 2 * (long long)start[DEM_ELL_SEGS]) {
+        const unsigned w = (unsigned)(w2 >> 1);
+        const int side = (int)(w2 & 1);
         int lo = 0, hi = DEM_ELL_SEGS - 1;  // the segment holding flat index w
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (start[mid] <= (unsigned)w) lo = mid;
+            if (start[mid] <= w) lo = mid;
             else hi = mid - 1;
         }
-        ph_contact<true>(A, B, (long long)A.ell_list[lo * A.ell_seg_cap + ((unsigned)w - start[lo])], vv, ww, dth,
-                         nprev, same);
+        const long long s = (long long)A.ell_list[lo * A.ell_seg_cap + (w - start[lo])];
+        const unsigned long long key = B.pairs[s];
+        Geom G;
+        ellipsoid_pair2(A, (int)(key >> 32), (int)(key & 0xffffffffu), side, G);
+        if (side == 0) contact_law(A, B, s, key, G, vv, ww, dth, nprev, same, nullptr);
     }
 }
 __global__ void k_colhist(DemArgs A, PairBufs B) {
@@ -1943,7 +2046,7 @@ hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, c
     if (A.ellipsoids) {
         k_contacts<true><<<nbc, 128, 0, s>>>(A, B, vv, ww, dth);
         if (A.ell_list) {
-            const unsigned nb = nblk(A.pair_cap, 64);
+            const unsigned nb = nblk(2 * A.pair_cap, 64);
             k_contacts_ell<<<nb < 4096 ? nb : 4096, 64, 0, s>>>(A, B, vv, ww, dth);
         }
     } else {

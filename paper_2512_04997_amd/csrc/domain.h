@@ -72,6 +72,8 @@ struct psmdem_domain {
     int64_t step = 0;
     bool voxelized = false;
     bool tile_counts = false;  // the entry counts of the last voxelisation are in t.tile_ed
+    bool beta_fresh = true;    // t.slot_beta holds the last voxelisation's beta (a stepping
+                               // voxelisation leaves it to the read-back, which reselects)
 
     // timing
     bool timing = false;

@@ -104,12 +104,25 @@ static int run_voxelize(psmdem_domain* D) {
         return 0;
     }
     VoxArgs V = D->vox_args();
+    V.t.slot_beta = nullptr;  // only the read-back needs beta itself (B drives the step)
     int tk = D->timed_begin(PSMDEM_T_VOXEL);
     PSM_CHECK(vox_register(V, D->scan_tmp, D->s));
     PSM_CHECK(vox_voxelize(V, D->prec == 0, D->s));
     D->timed_end(tk);
     D->voxelized = true;
     D->tile_counts = true;
+    D->beta_fresh = false;
+    return 0;
+}
+
+// beta of the kept slots into t.slot_beta when the last voxelisation left it
+// out: the same selection again from that voxelisation's particle records
+// and count boxes, which stay until the next one
+static int fresh_beta(psmdem_domain* D) {
+    if (D->beta_fresh || !D->voxelized) return 0;
+    PSM_CHECK(vox_select(D->vox_args(), D->prec == 0, D->s));
+    PSM_CHECK(hipStreamSynchronize(D->s));
+    D->beta_fresh = true;
     return 0;
 }
 
@@ -931,6 +944,7 @@ extern "C" psmdem_status psmdem_read_solid(psmdem_domain* d, int64_t cap, uint32
     if (psm_read_fails(st)) return st;
     *n = 0;
     if (!d->voxelized) return st;
+    if (int rc = fresh_beta(d)) return (psmdem_status)rc;
     const GeoArgs& g = d->geo;
     const long long plane = g.ntiles * (long long)PSM_TILE;
     const int ms = d->d.max_solids;
@@ -1076,6 +1090,7 @@ extern "C" psmdem_status psmdem_read_state(psmdem_domain* d, void* buf, size_t c
     }
     const psmdem_status st = psm_sync_flags(d);
     if (psm_read_fails(st)) return st;
+    if (int rc = fresh_beta(d)) return (psmdem_status)rc;  // a state always holds beta
     StateHeader h{};
     memcpy(h.magic, kStateMagic, 8);
     h.layout = state_layout(d);
@@ -1116,6 +1131,7 @@ extern "C" psmdem_status psmdem_write_state(psmdem_domain* d, const void* buf, s
     d->dem_sub = h.dem_sub;
     d->cur = h.cur;
     d->voxelized = h.voxelized != 0;
+    d->beta_fresh = true;
     return PSMDEM_OK;
 }
 

@@ -295,6 +295,8 @@ int enqueue_step(psmdem_server* S) {
         if (D->d.dem_on && D->np > 0) D->cur ^= (D->nsub & 1);
         D->step++;
         D->voxelized = true;
+        D->tile_counts = false;  // the batch counts entries in the step counters
+        D->beta_fresh = true;    // and stores beta
         J->steps_done++;
     }
     return 0;

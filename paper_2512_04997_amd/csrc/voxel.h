@@ -28,8 +28,13 @@ struct VoxArgs {
 // arbitrary order within a tile, which vox_voxelize's select kernel then
 // sets, clearing the registration counters: it follows every vox_register)
 hipError_t vox_register(const VoxArgs& A, int* scan_tmp, hipStream_t s);
-// voxelisation of registered tiles
+// voxelisation of registered tiles (with A.t.slot_beta null, beta itself is
+// not stored: only the slots' local indices and B)
 hipError_t vox_voxelize(const VoxArgs& A, int ctype_double, hipStream_t s);
+// the selection alone, again, from the particle records and count boxes of the
+// last vox_voxelize (they are kept until the next one): the same slots, and
+// beta when A.t.slot_beta is set
+hipError_t vox_select(const VoxArgs& A, int ctype_double, hipStream_t s);
 hipError_t vox_reduce_hydro(const VoxArgs& A, hipStream_t s);
 // bytes of one particle record (VoxArgs::vpart)
 size_t vox_part_bytes();

@@ -701,7 +701,7 @@ __device__ inline void write_slots(const VoxArgs& A, Top4& T, long long cell) {
             const double beta = bq[q];
             const double B = beta * (A.tau - 0.5) / ((1.0 - beta) + (A.tau - 0.5));
             Bout[q * plane + cell] = (C)B;
-            A.t.slot_beta[q * plane + cell] = beta;
+            if (A.t.slot_beta) A.t.slot_beta[q * plane + cell] = beta;
         }
 }
 
@@ -1126,8 +1126,99 @@ struct SelPart {
     int shape, pid;
 };
 
+// Phase C of the subdivision method from the count boxes, on integer keys:
+// an entry of candidate u with count n > 0 is the key n * 256 + (255 - u), so
+// that a larger key is a larger beta = n / ns^3 (the division is monotone and
+// one-to-one on the counts) and, for equal counts, the smaller local index
+// (the smaller pid).  Each of the lane's four planes keeps its four largest
+// keys in a sorted list updated by max/min exchanges, which equals keeping
+// the largest ms betas with ties to the smaller pid (the first ms of the list);
+// every entry past the ms-th is counted as dropped.  beta and B are formed
+// only for the kept slots.
+template <typename C>
+__device__ inline void select_counts(const VoxArgs& A, const SelPart* sp, long long t, int tz, int x, int y,
+                                     bool xy_ok, unsigned long long cm0, unsigned long long cm1,
+                                     const unsigned short* vbox, long long stride, unsigned long long* cnt_e,
+                                     unsigned long long* cnt_d) {
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int ms = A.ms;
+    unsigned key[PSM_TZ][4];
+    int ne[PSM_TZ];
+#pragma unroll
+    for (int lz = 0; lz < PSM_TZ; ++lz) {
+        ne[lz] = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) key[lz][q] = 0u;
+    }
+    if (xy_ok)
+        for (int w = 0; w < 2; ++w)
+            for (unsigned long long bits = w ? cm1 : cm0; bits; bits &= bits - 1) {
+                const int u = 64 * w + __ffsll((long long)bits) - 1;
+                const SelPart& P = sp[u];
+                int X, Y;
+                in_box(P, x, A.g.nx, 0, A.g.periodic[0], &X);
+                in_box(P, y, A.g.ny, 1, A.g.periodic[1], &Y);
+                const int bx = P.hi[0] - P.lo[0] + 1, by = P.hi[1] - P.lo[1] + 1;
+                const unsigned short* col = vbox + (long long)P.pid * stride + (X - P.lo[0]) + bx * (Y - P.lo[1]);
+                unsigned n[PSM_TZ];
+#pragma unroll
+                for (int lz = 0; lz < PSM_TZ; ++lz) {
+                    const int z = tz * PSM_TZ + lz;
+                    int Z;
+                    n[lz] = 0u;
+                    if (z < A.g.nz && in_box(P, z, A.g.nz, 2, A.g.periodic[2], &Z))
+                        n[lz] = col[bx * by * (Z - P.lo[2])];
+                }
+#pragma unroll
+                for (int lz = 0; lz < PSM_TZ; ++lz)
+                    if (n[lz]) {
+                        ++ne[lz];
+                        unsigned v = (n[lz] << 8) | (unsigned)(255 - u);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const unsigned hi = max(key[lz][q], v);
+                            v = min(key[lz][q], v);
+                            key[lz][q] = hi;
+                        }
+                    }
+            }
+    unsigned long long my_e = 0, my_d = 0;
+    C* Bout = (C*)A.t.slot_B;
+    const long long plane = A.g.ntiles * (long long)PSM_TILE;
+    const double n3 = (double)(A.ns * A.ns * A.ns), tm = A.tau - 0.5;
+#pragma unroll
+    for (int lz = 0; lz < PSM_TZ; ++lz) {
+        if (!xy_ok || tz * PSM_TZ + lz >= A.g.nz) continue;
+        const int nk = ne[lz] < ms ? ne[lz] : ms;
+        my_e += (unsigned long long)ne[lz];
+        my_d += (unsigned long long)(ne[lz] - nk);
+        // the kept keys reordered by local index: (u << 16) | count, empty last
+        unsigned o[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            o[q] = q < nk ? ((255u - (key[lz][q] & 255u)) << 16) | (key[lz][q] >> 8) : 0xffffffffu;
+#define PSM_CX(a, b) { const unsigned lo_ = min(o[a], o[b]), hi_ = max(o[a], o[b]); o[a] = lo_; o[b] = hi_; }
+        PSM_CX(0, 1) PSM_CX(2, 3) PSM_CX(0, 2) PSM_CX(1, 3) PSM_CX(1, 2)
+#undef PSM_CX
+        const long long cell = t * (long long)PSM_TILE + lane + PSM_TX * (wid + PSM_TY * lz);
+        unsigned lp = 0xffffffffu;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q < nk) lp = (lp & ~(0xffu << (8 * q))) | ((o[q] >> 16) << (8 * q));
+        A.t.slot_lp[cell] = lp;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q < nk) {
+                const double beta = (double)(o[q] & 0xffffu) / n3;
+                Bout[q * plane + cell] = (C)(beta * tm / ((1.0 - beta) + tm));
+                if (A.t.slot_beta) A.t.slot_beta[q * plane + cell] = beta;
+            }
+    }
+    add_entry_counts(A, t, my_e, my_d, cnt_e, cnt_d);
+}
+
 // per tile: select the kept solids, the subdivision counts from the count boxes
-template <typename C, bool SORT>
+template <typename C, bool SORT, bool SUB>
 __global__ __launch_bounds__(VOX_T) void k_vox_select(VoxArgs A) {
     __shared__ SelPart sp[PSM_PMAX];
     __shared__ double off[32];
@@ -1166,6 +1257,10 @@ __global__ __launch_bounds__(VOX_T) void k_vox_select(VoxArgs A) {
     column_masks(A, sp, R.count, x, y, xy_ok, cm0, cm1);
     const unsigned short* vbox = A.vbox;
     const long long stride = A.box_stride;
+    if constexpr (SUB) {
+        select_counts<C>(A, sp, t, R.tz, x, y, xy_ok, cm0, cm1, vbox, stride, &cnt_e, &cnt_d);
+        return;
+    }
     select_slots<C, true, SelPart>(A, sp, t, R.tz, x, y, xy_ok, cm0, cm1, slo, shi, 0,
                           [&](const SelPart& P, int X, int Y, int Z) {
                               const int bx = P.hi[0] - P.lo[0] + 1, by = P.hi[1] - P.lo[1] + 1;
@@ -1219,20 +1314,35 @@ hipError_t vox_register(const VoxArgs& A, int* scan_tmp, hipStream_t s) {
 }
 
 hipError_t vox_voxelize(const VoxArgs& A, int ctype_double, hipStream_t s) {
-    const unsigned nt = (unsigned)A.g.ntiles;
-    const bool sort = A.g.ntiles <= VOX_SORT_IN_TILE_MAX;
     if (A.p.np > 0) k_vox_parts<<<nblk(A.p.np), 256, 0, s>>>(A);
     if (A.sf_method == 0 && A.p.np > 0) {
         if (A.ns == 10) k_vox_rows<10><<<(unsigned)A.p.np, VOX_T, 0, s>>>(A);
         else k_vox_rows<0><<<(unsigned)A.p.np, VOX_T, 0, s>>>(A);
     }
+    return vox_select(A, ctype_double, s);
+}
+
+hipError_t vox_select(const VoxArgs& A, int ctype_double, hipStream_t s) {
+    const unsigned nt = (unsigned)A.g.ntiles;
+    const bool sort = A.g.ntiles <= VOX_SORT_IN_TILE_MAX;
     // (small lattices: the select kernel orders each tile's list)
+    const bool sub = A.sf_method == 0;
     if (ctype_double) {
-        if (sort) k_vox_select<double, true><<<nt, VOX_T, 0, s>>>(A);
-        else k_vox_select<double, false><<<nt, VOX_T, 0, s>>>(A);
+        if (sort) {
+            if (sub) k_vox_select<double, true, true><<<nt, VOX_T, 0, s>>>(A);
+            else k_vox_select<double, true, false><<<nt, VOX_T, 0, s>>>(A);
+        } else {
+            if (sub) k_vox_select<double, false, true><<<nt, VOX_T, 0, s>>>(A);
+            else k_vox_select<double, false, false><<<nt, VOX_T, 0, s>>>(A);
+        }
     } else {
-        if (sort) k_vox_select<float, true><<<nt, VOX_T, 0, s>>>(A);
-        else k_vox_select<float, false><<<nt, VOX_T, 0, s>>>(A);
+        if (sort) {
+            if (sub) k_vox_select<float, true, true><<<nt, VOX_T, 0, s>>>(A);
+            else k_vox_select<float, true, false><<<nt, VOX_T, 0, s>>>(A);
+        } else {
+            if (sub) k_vox_select<float, false, true><<<nt, VOX_T, 0, s>>>(A);
+            else k_vox_select<float, false, false><<<nt, VOX_T, 0, s>>>(A);
+        }
     }
     return hipGetLastError();
 }
