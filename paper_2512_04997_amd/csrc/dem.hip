@@ -205,23 +205,46 @@ __device__ inline int wall_count(const DemArgs& A, int i) {
 // contact geometry (Sec. 2.1): spheres in closed form, ellipsoids by iterated
 // equivalent spheres with the local curvature radius (Eq. local-curvature)
 // ---------------------------------------------------------------------------
-__device__ void ell_local(const double* c, const double* R, const double* ax, const double* p, double* rho,
-                          double* n) {
+// An ellipsoid's constants for the iteration, formed once per evaluation: its
+// rotation R (body to world), 1 / a_k^2, and the curvature-radius weights
+// (b c / a^3, a c / b^3, a b / c^3), so that the iteration itself divides only
+// where a quotient of two iterates is needed.
+struct EllShape {
+    double R[9];
+    double ia2[3];
+    double kr[3];
+};
+
+__device__ inline void ell_shape(const double* q, const double* ax, EllShape& E) {
+    quat_rbw(q, E.R);
+    const double a = ax[0], b = ax[1], c = ax[2];
+    E.ia2[0] = 1.0 / (a * a);
+    E.ia2[1] = 1.0 / (b * b);
+    E.ia2[2] = 1.0 / (c * c);
+    E.kr[0] = b * c / (a * a * a);
+    E.kr[1] = a * c / (b * b * b);
+    E.kr[2] = a * b / (c * c * c);
+}
+
+// local curvature radius rho and unit outward normal n at surface point p
+__device__ void ell_local(const double* c, const EllShape& E, const double* p, double* rho, double* n) {
+    const double* R = E.R;
     double d[3] = {p[0] - c[0], p[1] - c[1], p[2] - c[2]};
     double xb[3];
     for (int k = 0; k < 3; ++k) xb[k] = (R[0 + k] * d[0] + R[3 + k] * d[1]) + R[6 + k] * d[2];
-    double a = ax[0], b = ax[1], cc = ax[2];
-    *rho = b * cc * xb[0] * xb[0] / (a * a * a) + a * cc * xb[1] * xb[1] / (b * b * b) +
-           a * b * xb[2] * xb[2] / (cc * cc * cc);
-    double nb[3] = {xb[0] / (a * a), xb[1] / (b * b), xb[2] / (cc * cc)};
+    *rho = (E.kr[0] * xb[0] * xb[0] + E.kr[1] * xb[1] * xb[1]) + E.kr[2] * xb[2] * xb[2];
+    double nb[3] = {xb[0] * E.ia2[0], xb[1] * E.ia2[1], xb[2] * E.ia2[2]};
     double nw[3];
     for (int r = 0; r < 3; ++r) nw[r] = (R[3 * r] * nb[0] + R[3 * r + 1] * nb[1]) + R[3 * r + 2] * nb[2];
-    double l = sqrt(dot3(nw, nw));
-    for (int r = 0; r < 3; ++r) n[r] = nw[r] / l;
+    const double il = 1.0 / sqrt(dot3(nw, nw));
+    for (int r = 0; r < 3; ++r) n[r] = nw[r] * il;
 }
 
-__device__ bool ell_line_hit(const double* c, const double* R, const double* ax, const double* s, const double* u,
-                             bool far_positive, double* p) {
+// intersection of the line s + t u with the surface: the root with the larger
+// t when far_positive, else the smaller; false on a miss
+__device__ bool ell_line_hit(const double* c, const EllShape& E, const double* s, const double* u, bool far_positive,
+                             double* p) {
+    const double* R = E.R;
     double d[3] = {s[0] - c[0], s[1] - c[1], s[2] - c[2]};
     double y0[3], ud[3];
     for (int k = 0; k < 3; ++k) {
@@ -230,15 +253,14 @@ __device__ bool ell_line_hit(const double* c, const double* R, const double* ax,
     }
     double qa = 0, qb = 0, qc = -1.0;
     for (int k = 0; k < 3; ++k) {
-        double ia = 1.0 / (ax[k] * ax[k]);
-        qa += ud[k] * ud[k] * ia;
-        qb += y0[k] * ud[k] * ia;
-        qc += y0[k] * y0[k] * ia;
+        qa += ud[k] * ud[k] * E.ia2[k];
+        qb += y0[k] * ud[k] * E.ia2[k];
+        qc += y0[k] * y0[k] * E.ia2[k];
     }
     double disc = qb * qb - qa * qc;
     if (disc < 0.0 || qa <= 0.0) return false;
     double sq = sqrt(disc);
-    double t = far_positive ? (-qb + sq) / qa : (-qb - sq) / qa;
+    double t = (far_positive ? -qb + sq : -qb - sq) / qa;
     for (int k = 0; k < 3; ++k) p[k] = s[k] + t * u[k];
     return true;
 }
@@ -254,11 +276,11 @@ __device__ void ellipsoid_pair(const DemArgs& A, int i, int j, Geom& G) {
     double dvec[3];
     min_image(A, ci, A.p.pos + 3 * j, dvec);
     double cj[3] = {ci[0] - dvec[0], ci[1] - dvec[1], ci[2] - dvec[2]};
-    double Ri[9], Rj[9];
-    quat_rbw(A.p.q + 4 * i, Ri);
-    quat_rbw(A.p.q + 4 * j, Rj);
     const double* ai = A.p.semi + 3 * i;
     const double* aj = A.p.semi + 3 * j;
+    EllShape Ei, Ej;
+    ell_shape(A.p.q + 4 * i, ai, Ei);
+    ell_shape(A.p.q + 4 * j, aj, Ej);
     double amin = ai[0];
     for (int k = 0; k < 3; ++k) {
         amin = ai[k] < amin ? ai[k] : amin;
@@ -267,16 +289,16 @@ __device__ void ellipsoid_pair(const DemArgs& A, int i, int j, Geom& G) {
     double pi[3], pj[3];
     {
         double u[3] = {cj[0] - ci[0], cj[1] - ci[1], cj[2] - ci[2]};
-        double l = sqrt(dot3(u, u));
-        for (int k = 0; k < 3; ++k) u[k] /= l;
-        ell_line_hit(ci, Ri, ai, ci, u, true, pi);
+        const double il = 1.0 / sqrt(dot3(u, u));
+        for (int k = 0; k < 3; ++k) u[k] *= il;
+        ell_line_hit(ci, Ei, ci, u, true, pi);
         double um[3] = {-u[0], -u[1], -u[2]};
-        ell_line_hit(cj, Rj, aj, cj, um, true, pj);
+        ell_line_hit(cj, Ej, cj, um, true, pj);
     }
     for (int it = 0; it < 32; ++it) {
         double rhoi, rhoj, ni[3], nj[3], si[3], sj[3];
-        ell_local(ci, Ri, ai, pi, &rhoi, ni);
-        ell_local(cj, Rj, aj, pj, &rhoj, nj);
+        ell_local(ci, Ei, pi, &rhoi, ni);
+        ell_local(cj, Ej, pj, &rhoj, nj);
         for (int k = 0; k < 3; ++k) {
             si[k] = pi[k] - rhoi * ni[k];
             sj[k] = pj[k] - rhoj * nj[k];
@@ -284,10 +306,11 @@ __device__ void ellipsoid_pair(const DemArgs& A, int i, int j, Geom& G) {
         double u[3] = {sj[0] - si[0], sj[1] - si[1], sj[2] - si[2]};
         double l = sqrt(dot3(u, u));
         if (!(l > 0.0)) break;
-        for (int k = 0; k < 3; ++k) u[k] /= l;
+        const double il = 1.0 / l;
+        for (int k = 0; k < 3; ++k) u[k] *= il;
         double npi[3], npj[3];
-        if (!ell_line_hit(ci, Ri, ai, si, u, true, npi)) break;
-        if (!ell_line_hit(cj, Rj, aj, sj, u, false, npj)) break;
+        if (!ell_line_hit(ci, Ei, si, u, true, npi)) break;
+        if (!ell_line_hit(cj, Ej, sj, u, false, npj)) break;
         double dpi[3] = {npi[0] - pi[0], npi[1] - pi[1], npi[2] - pi[2]};
         double dpj[3] = {npj[0] - pj[0], npj[1] - pj[1], npj[2] - pj[2]};
         double conv = sqrt(dot3(dpi, dpi)) + sqrt(dot3(dpj, dpj));
@@ -298,8 +321,8 @@ __device__ void ellipsoid_pair(const DemArgs& A, int i, int j, Geom& G) {
         if (conv < 1e-10 * amin) break;
     }
     double ni[3], nj[3], si[3], sj[3];
-    ell_local(ci, Ri, ai, pi, &G.rhoi, ni);
-    ell_local(cj, Rj, aj, pj, &G.rhoj, nj);
+    ell_local(ci, Ei, pi, &G.rhoi, ni);
+    ell_local(cj, Ej, pj, &G.rhoj, nj);
     for (int k = 0; k < 3; ++k) {
         si[k] = pi[k] - G.rhoi * ni[k];
         sj[k] = pj[k] - G.rhoj * nj[k];
@@ -329,9 +352,8 @@ __device__ void ellipsoid_pair2(const DemArgs& A, int i, int j, int side, Geom& 
     const double cj[3] = {ci[0] - dvec[0], ci[1] - dvec[1], ci[2] - dvec[2]};
     const int me = side ? j : i;
     const double c[3] = {side ? cj[0] : ci[0], side ? cj[1] : ci[1], side ? cj[2] : ci[2]};
-    double R[9];
-    quat_rbw(A.p.q + 4 * me, R);
-    const double* ax = A.p.semi + 3 * me;
+    EllShape E;
+    ell_shape(A.p.q + 4 * me, A.p.semi + 3 * me, E);
     const double* ai = A.p.semi + 3 * i;
     const double* aj = A.p.semi + 3 * j;
     double amin = ai[0];
@@ -342,14 +364,14 @@ __device__ void ellipsoid_pair2(const DemArgs& A, int i, int j, int side, Geom& 
     double p[3];
     {
         double u[3] = {cj[0] - ci[0], cj[1] - ci[1], cj[2] - ci[2]};
-        double l = sqrt(dot3(u, u));
-        for (int k = 0; k < 3; ++k) u[k] /= l;
+        const double il = 1.0 / sqrt(dot3(u, u));
+        for (int k = 0; k < 3; ++k) u[k] *= il;
         const double dir[3] = {side ? -u[0] : u[0], side ? -u[1] : u[1], side ? -u[2] : u[2]};
-        ell_line_hit(c, R, ax, c, dir, true, p);
+        ell_line_hit(c, E, c, dir, true, p);
     }
     for (int it = 0; it < 32; ++it) {
         double rho, n[3], sc[3], so[3];
-        ell_local(c, R, ax, p, &rho, n);
+        ell_local(c, E, p, &rho, n);
         for (int k = 0; k < 3; ++k) sc[k] = p[k] - rho * n[k];
         for (int k = 0; k < 3; ++k) so[k] = lane_swap(sc[k]);
         const double* si = side ? so : sc;
@@ -357,9 +379,10 @@ __device__ void ellipsoid_pair2(const DemArgs& A, int i, int j, int side, Geom& 
         double u[3] = {sj[0] - si[0], sj[1] - si[1], sj[2] - si[2]};
         double l = sqrt(dot3(u, u));
         if (!(l > 0.0)) break;
-        for (int k = 0; k < 3; ++k) u[k] /= l;
+        const double il = 1.0 / l;
+        for (int k = 0; k < 3; ++k) u[k] *= il;
         double np_[3];
-        const int hit = ell_line_hit(c, R, ax, sc, u, side == 0, np_) ? 1 : 0;
+        const int hit = ell_line_hit(c, E, sc, u, side == 0, np_) ? 1 : 0;
         const int hit_o = __shfl_xor(hit, 1, 64);
         if (!(hit && hit_o)) break;
         double dp[3] = {np_[0] - p[0], np_[1] - p[1], np_[2] - p[2]};
@@ -370,7 +393,7 @@ __device__ void ellipsoid_pair2(const DemArgs& A, int i, int j, int side, Geom& 
         if (conv < 1e-10 * amin) break;
     }
     double rho, n[3], sc[3], so[3], rc[3], ro[3];
-    ell_local(c, R, ax, p, &rho, n);
+    ell_local(c, E, p, &rho, n);
     for (int k = 0; k < 3; ++k) {
         sc[k] = p[k] - rho * n[k];
         rc[k] = p[k] - c[k];
@@ -427,9 +450,10 @@ __device__ void pair_geometry(const DemArgs& A, int i, int j, const double* ci, 
             G.rhoi = R;
             G.sphere_law = true;
         } else {
-            double R[9];
-            quat_rbw(A.p.q + 4 * i, R);
+            EllShape E;
             const double* ax = A.p.semi + 3 * i;
+            ell_shape(A.p.q + 4 * i, ax, E);
+            const double* R = E.R;
             double nb[3];
             for (int k = 0; k < 3; ++k) nb[k] = (R[0 + k] * n[0] + R[3 + k] * n[1]) + R[6 + k] * n[2];
             double qf = (ax[0] * ax[0] * nb[0] * nb[0] + ax[1] * ax[1] * nb[1] * nb[1]) + ax[2] * ax[2] * nb[2] * nb[2];
@@ -442,7 +466,7 @@ __device__ void pair_geometry(const DemArgs& A, int i, int j, const double* ci, 
             }
             G.delta = sq - dist;
             double nn[3];
-            ell_local(c, R, ax, p, &G.rhoi, nn);
+            ell_local(c, E, p, &G.rhoi, nn);
             for (int k = 0; k < 3; ++k) G.rci[k] = p[k] - c[k];
         }
         return;
