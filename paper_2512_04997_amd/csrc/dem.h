@@ -77,16 +77,17 @@ struct PairSet {
 hipError_t dem_predict(const DemArgs& A, double dt, int write_kin, hipStream_t s);
 // cells, rows and column lists of the current positions (one launch per phase)
 hipError_t dem_lists(const DemArgs& A, const PairBufs& B, int* scan_tmp, hipStream_t s);
-// the column lists of the rows in B (the per-particle sums read them)
+// the column lists of the rows in B (the per-particle sums read them) from the
+// column counts: the row emission forms them; rows placed otherwise (copied)
+// take dem_count_columns first
 hipError_t dem_columns(const DemArgs& A, const PairBufs& B, int* scan_tmp, hipStream_t s);
+hipError_t dem_count_columns(const DemArgs& A, const PairBufs& B, hipStream_t s);
 // multi-launch substeps that keep an unchanged list (A.list_run = A.list_flag + par)
 hipError_t dem_predict_keep(const DemArgs& A, double dt, int write_kin, int par, hipStream_t s);
 // the corrector of a substep and the predictor of the next (its parity par)
 hipError_t dem_correct_predict(const DemArgs& A, double dt, int write_kin, int par, hipStream_t s);
 // the list of a multi-launch substep: rebuilt (cells, rows, columns) when
-// list_flag[par] is set, else kept, in one cooperative launch after the age
-// update; scan_tmp holds at least DEM_LIST_PART_MIN ints
-#define DEM_LIST_PART_MIN 1024
+// list_flag[par] is set, else kept (the list kernels return at once)
 hipError_t dem_lists_kept(const DemArgs& A, const PairBufs& B, int par, int* scan_tmp, hipStream_t s);
 // contacts of the pairs in B, then the per-particle sums
 hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, const double* ww, double dth,

@@ -24,9 +24,7 @@
 
 #include "common.h"
 #include "dem.h"
-#include <hip/hip_cooperative_groups.h>
 
-#include <atomic>
 #include "serve.h"
 
 namespace {
@@ -782,7 +780,8 @@ __device__ void ph_colscatter(const DemArgs& A, const PairBufs& B, long long s) 
     const unsigned j = (unsigned)(B.pairs[s] & 0xffffffffu);
     if (j >= (unsigned)A.p.np) return;
     const int slot = atomicAdd(&A.col_fill[j], 1);
-    A.col_list[A.col_start[j] + slot] = (int)s;
+    const long long at = (long long)A.col_start[j] + slot;
+    if (at < A.pair_cap) A.col_list[at] = (int)s;
 }
 
 __device__ void ph_colsort(const DemArgs& A, int j) {
@@ -1094,9 +1093,14 @@ __global__ void k_list_age(DemArgs A, int par) {
     *A.fused_age = ch ? 0 : age + 1;
 }
 
-// one substep after a rebuild the kept list is copied into this buffer
-__global__ void k_list_copy(DemArgs A, PairBufs B, int par) {
-    if (A.list_flag[par] || *A.fused_age != 1) return;
+// a rebuild's cell histogram, or, one substep after a rebuild, the kept list
+// copied into this buffer
+__global__ void k_list_copy_hist(DemArgs A, PairBufs B, int par) {
+    if (A.list_flag[par]) {
+        GRID_LOOP(k, A.p.np) ph_hist(A, (int)k);
+        return;
+    }
+    if (*A.fused_age != 1) return;
     long long n = *B.prev_n;
     n = n < A.pair_cap ? n : A.pair_cap;
     const int* prev_prow = B.prev_n - A.p.np;
@@ -1177,32 +1181,39 @@ __device__ inline int wave_candidate(const DemArgs& A, int i, const AxCells& ri,
 
 #define PAIR_KEPT_MAX 256
 
+// Rows by groups of ROW_SEG lanes, several particles per wave: a row has a few
+// dozen candidates, so a whole wave per row would leave most lanes idle while
+// its chain of dependent loads (cells, cell lists, the partners' cells) runs.
+#define ROW_SEG 16
+
 __global__ __launch_bounds__(256) void k_paircount(DemArgs A) {
     if (A.list_run && !*A.list_run) return;
-    const int lane = threadIdx.x & 63;
-    const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
-    for (long long iw = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; iw < A.p.np; iw += nw) {
-        const int i = (int)iw;
+    const int lane = threadIdx.x & 63, sl = lane & (ROW_SEG - 1), sh = lane & ~(ROW_SEG - 1);
+    const unsigned long long seg = ((1ull << ROW_SEG) - 1ull) << sh;
+    const long long ng = (long long)gridDim.x * (blockDim.x / ROW_SEG);
+    for (long long ig = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / ROW_SEG; ig < A.p.np; ig += ng) {
+        const int i = (int)ig;
         AxCells ri;
         load_cells(A, i, ri);
         WaveCells W;
         wave_cells(A, ri, W);
         int n = 0;
-        for (int f0 = 0; f0 < W.total; f0 += 64) {
-            const int f = f0 + lane;
-            n += __popcll(__ballot(f < W.total && wave_candidate(A, i, ri, W, f) >= 0));
+        for (int f0 = 0; f0 < W.total; f0 += ROW_SEG) {
+            const int f = f0 + sl;
+            n += __popcll(__ballot(f < W.total && wave_candidate(A, i, ri, W, f) >= 0) & seg);
         }
-        if (lane == 0) A.pcount[i] = n + wall_count(A, i);
+        if (sl == 0) A.pcount[i] = n + wall_count(A, i);
     }
 }
 
-// row i's emission by one wave (kept: the wave's LDS partner buffer)
+// row i's emission by one lane group (kept: the group's LDS partner buffer)
 __device__ inline void emit_row(const DemArgs& A, const PairBufs& B, int i, int* kept) {
-    const int lane = threadIdx.x & 63;
-    const unsigned long long lanes_below = (1ull << lane) - 1ull;
+    const int lane = threadIdx.x & 63, sl = lane & (ROW_SEG - 1), sh = lane & ~(ROW_SEG - 1);
+    const unsigned long long seg = ((1ull << ROW_SEG) - 1ull) << sh;
+    const unsigned long long lanes_below = ((1ull << sl) - 1ull) << sh;
     const long long at = B.prow[i];
     const long long room = A.pair_cap - at;
-    if (lane == 0 && room < (long long)(B.prow[i + 1] - B.prow[i]))
+    if (sl == 0 && room < (long long)(B.prow[i + 1] - B.prow[i]))
         atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_PAIRS);
     if (room <= 0) return;
     unsigned long long* out = B.pairs + at;
@@ -1210,12 +1221,12 @@ __device__ inline void emit_row(const DemArgs& A, const PairBufs& B, int i, int*
     load_cells(A, i, ri);
     WaveCells W;
     wave_cells(A, ri, W);
-    // kept partners gathered in wave-private LDS
+    // kept partners gathered in the group's LDS
     int nk = 0;
-    for (int f0 = 0; f0 < W.total; f0 += 64) {
-        const int f = f0 + lane;
+    for (int f0 = 0; f0 < W.total; f0 += ROW_SEG) {
+        const int f = f0 + sl;
         const int j = f < W.total ? wave_candidate(A, i, ri, W, f) : -1;
-        const unsigned long long m = __ballot(j >= 0);
+        const unsigned long long m = __ballot(j >= 0) & seg;
         const int pos = nk + __popcll(m & lanes_below);
         if (j >= 0 && pos < PAIR_KEPT_MAX) kept[pos] = j;
         nk += __popcll(m);
@@ -1223,18 +1234,25 @@ __device__ inline void emit_row(const DemArgs& A, const PairBufs& B, int i, int*
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // every stored pair with a particle as second member counts in that particle's
+    // column (the column lists of the DEM sums)
     if (nk <= PAIR_KEPT_MAX) {
         // partners are distinct: a partner's place is the number below it
-        for (int e = lane; e < nk; e += 64) {
+        for (int e = sl; e < nk; e += ROW_SEG) {
             const int j = kept[e];
             int below = 0;
             for (int v = 0; v < nk; ++v) below += kept[v] < j ? 1 : 0;
-            if (below < room) out[below] = ((unsigned long long)i << 32) | (unsigned)j;
+            if (below < room) {
+                out[below] = ((unsigned long long)i << 32) | (unsigned)j;
+                atomicAdd(&A.col_count[j], 1);
+            }
         }
-        if (lane == 0) emit_walls(A, i, out, room, nk);
-    } else if (lane == 0) {
+        if (sl == 0) emit_walls(A, i, out, room, nk);
+    } else if (sl == 0) {
         // very long rows: the serial emission with an in-place sort
         ph_pairemit<false>(A, B, i);
+        const long long m = room < (long long)nk ? room : (long long)nk;
+        for (long long e = 0; e < m; ++e) atomicAdd(&A.col_count[(int)(out[e] & 0xffffffffu)], 1);
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1243,11 +1261,11 @@ __device__ inline void emit_row(const DemArgs& A, const PairBufs& B, int i, int*
 
 __global__ __launch_bounds__(256) void k_pairemit(DemArgs A, PairBufs B) {
     if (A.list_run && !*A.list_run) return;
-    __shared__ int kept_s[4][PAIR_KEPT_MAX];
-    int* kept = kept_s[threadIdx.x >> 6];
-    const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
-    for (long long iw = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; iw < A.p.np; iw += nw)
-        emit_row(A, B, (int)iw, kept);
+    __shared__ int kept_s[256 / ROW_SEG][PAIR_KEPT_MAX];
+    int* kept = kept_s[threadIdx.x / ROW_SEG];
+    const long long ng = (long long)gridDim.x * (blockDim.x / ROW_SEG);
+    for (long long ig = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / ROW_SEG; ig < A.p.np; ig += ng)
+        emit_row(A, B, (int)ig, kept);
 }
 // Contacts of the substep's pairs.  With ellipsoids, the pairs that need the
 // iterated equivalent spheres (ellipsoid pairs within bounding-sphere reach,
@@ -2010,159 +2028,10 @@ inline unsigned nblk(long long n, int t = 256) {
     return (unsigned)b;
 }
 
-// ---------------------------------------------------------------------------
-// The list build of a multi-launch substep in one cooperative launch: the
-// phases of the kernels above (cell histogram, scan, scatter, cell sort, pair
-// count, scan, pair emission, then the column lists of the new rows: count,
-// scan, scatter, sort) run one after another over the whole grid, separated by
-// grid barriers.  On a substep that keeps its list every workgroup returns at
-// once (or only copies the kept list into this substep's buffer), so the
-// substep pays for one launch instead of one per phase.  Every workgroup reads
-// the same two flags, which no phase writes, so all of them take the same
-// branch and meet at every barrier.
-// ---------------------------------------------------------------------------
-namespace cg = cooperative_groups;
-
-constexpr int LIST_T = 256;
-
-// sum of one int per lane over the workgroup, returned to every lane
-__device__ int list_block_sum(int v) {
-    __shared__ int ws[LIST_T / 64];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    if (lane == 0) ws[wid] = v;
-    __syncthreads();
-    int t = 0;
-#pragma unroll
-    for (int w = 0; w < LIST_T / 64; ++w) t += ws[w];
-    __syncthreads();
-    return t;
-}
-
-// exclusive scan of one int per lane over the workgroup; the total to *tot
-__device__ int list_block_scan(int v, int* tot) {
-    __shared__ int ws[LIST_T / 64];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) ws[wid] = x;
-    __syncthreads();
-    int off = 0, t = 0;
-#pragma unroll
-    for (int w = 0; w < LIST_T / 64; ++w) {
-        off += w < wid ? ws[w] : 0;
-        t += ws[w];
-    }
-    __syncthreads();
-    *tot = t;
-    return off + x - v;
-}
-
-// out[0..n) = exclusive prefix sums of in[0..n), out[n] = the total, by the
-// grid: workgroup b takes the b-th contiguous chunk, its sum goes to part[b];
-// after a barrier each workgroup scans its chunk from the sum of the parts
-// below it.  Ends with a barrier (out is complete for every workgroup).
-__device__ void list_grid_scan(cg::grid_group& grid, const int* in, int* out, long long n, int* part) {
-    const long long G = gridDim.x, b = blockIdx.x;
-    const long long chunk = (n + G - 1) / G;
-    const long long c0 = b * chunk < n ? b * chunk : n;
-    const long long c1 = c0 + chunk < n ? c0 + chunk : n;
-    int s = 0;
-    for (long long i = c0 + threadIdx.x; i < c1; i += LIST_T) s += in[i];
-    s = list_block_sum(s);
-    if (threadIdx.x == 0) part[b] = s;
-    grid.sync();
-    int o = 0;
-    for (long long u = threadIdx.x; u < b; u += LIST_T) o += part[u];
-    o = list_block_sum(o);
-    for (long long base = c0; base < c1; base += LIST_T) {
-        const long long i = base + threadIdx.x;
-        const int v = i < c1 ? in[i] : 0;
-        int tot;
-        const int ex = list_block_scan(v, &tot);
-        if (i < c1) out[i] = o + ex;
-        o += tot;
-    }
-    if (b == G - 1 && threadIdx.x == 0) out[n] = o;
-    grid.sync();
-}
-
-// one wave per particle over the grid's waves (the pair-count and emission
-// phases take a particle per wave)
-#define LIST_WAVES(iw, n)                                                                                      \
-    for (long long iw = ((long long)blockIdx.x * LIST_T + threadIdx.x) >> 6; iw < (n);                           \
-         iw += (long long)gridDim.x * (LIST_T >> 6))
-
-__global__ __launch_bounds__(LIST_T) void k_list_build(DemArgs A, PairBufs B, int par, int* part) {
-    cg::grid_group grid = cg::this_grid();
-    if (!A.list_flag[par]) {
-        // kept: one substep after a rebuild the list is copied into this buffer
-        if (*A.fused_age == 1) {
-            long long n = *B.prev_n;
-            n = n < A.pair_cap ? n : A.pair_cap;
-            const int* prev_prow = B.prev_n - A.p.np;
-            GRID_LOOP(u, n) B.pairs[u] = B.prev_pairs[u];
-            GRID_LOOP(u, (long long)A.p.np + 1) B.prow[u] = prev_prow[u];
-        }
-        return;
-    }
-    const int np = A.p.np;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    // cell lists
-    GRID_LOOP(k, np) ph_hist(A, (int)k);
-    grid.sync();
-    list_grid_scan(grid, A.cell_count, A.cell_start, A.ncell, part);
-    GRID_LOOP(k, np) ph_scatter(A, (int)k);
-    grid.sync();
-    GRID_LOOP(c, A.ncell) {
-        ph_cellsort(A, c);
-        A.cell_count[c] = 0;
-        A.cell_fill[c] = 0;
-    }
-    grid.sync();
-    // rows: counts, offsets, emission
-    LIST_WAVES(iw, np) {
-        const int i = (int)iw;
-        AxCells ri;
-        load_cells(A, i, ri);
-        WaveCells W;
-        wave_cells(A, ri, W);
-        int n = 0;
-        for (int f0 = 0; f0 < W.total; f0 += 64) {
-            const int f = f0 + lane;
-            n += __popcll(__ballot(f < W.total && wave_candidate(A, i, ri, W, f) >= 0));
-        }
-        if (lane == 0) A.pcount[i] = n + wall_count(A, i);
-    }
-    grid.sync();
-    list_grid_scan(grid, A.pcount, B.prow, np, part);
-    {
-        __shared__ int kept_s[LIST_T / 64][PAIR_KEPT_MAX];
-        int* kept = kept_s[wid];
-        LIST_WAVES(iw, np) emit_row(A, B, (int)iw, kept);
-    }
-    grid.sync();
-    // column lists of the new rows
-    const long long npairs = n_pairs(A, B);
-    GRID_LOOP(s2, npairs) ph_colhist(A, B, s2);
-    grid.sync();
-    list_grid_scan(grid, A.col_count, A.col_start, np, part);
-    GRID_LOOP(s2, npairs) ph_colscatter(A, B, s2);
-    grid.sync();
-    LIST_WAVES(jw, np) sort_column(A, (int)jw, lane);
-}
-#undef LIST_WAVES
-
 // The list kernels loop over their items with a grid stride; on the substeps
 // that keep the list they return at once, so their grids stay small (a launch
 // dispatches every workgroup even when each returns at once).
 constexpr unsigned DEM_LIST_GRID_MAX = 512;
-static_assert(DEM_LIST_GRID_MAX <= DEM_LIST_PART_MIN, "the scan parts of the list build fit scan_tmp");
 inline unsigned nblk_list(long long n) {
     const unsigned b = nblk(n);
     return b < DEM_LIST_GRID_MAX ? b : DEM_LIST_GRID_MAX;
@@ -2187,51 +2056,24 @@ hipError_t dem_predict_keep(const DemArgs& A, double dt, int write_kin, int par,
 
 // the multi-launch list build of a substep, its kernels skipped (on the
 // device) when the list is kept; A.list_run is list_flag + par
-// workgroups of the cooperative list build: all of them resident at once
-// (the occupancy of k_list_build times the compute units), at most
-// DEM_LIST_GRID_MAX; per device, found once
-static std::atomic<int> g_list_grid[64];
-
-static hipError_t list_grid(unsigned* g) {
-    int dev = 0;
-    hipError_t e;
-    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
-    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
-    int v = g_list_grid[dev].load();
-    if (v <= 0) {
-        int cus = 0, per = 0;
-        if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, reinterpret_cast<const void*>(k_list_build),
-                                                              LIST_T, 0)) != hipSuccess)
-            return e;
-        const long long n = (long long)per * cus;
-        if (n < 1) return hipErrorInvalidConfiguration;
-        v = (int)(n < DEM_LIST_GRID_MAX ? n : DEM_LIST_GRID_MAX);
-        g_list_grid[dev].store(v);
-    }
-    *g = (unsigned)v;
-    return hipSuccess;
-}
-
 hipError_t dem_lists_kept(const DemArgs& A, const PairBufs& B, int par, int* scan_tmp, hipStream_t s) {
     if (A.p.np == 0) return hipSuccess;
     hipError_t e;
-    unsigned g = 0;
-    if ((e = list_grid(&g)) != hipSuccess) return e;
     k_list_age<<<1, 1, 0, s>>>(A, par);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    DemArgs a = A;
-    PairBufs b = B;
-    int p = par;
-    int* part = scan_tmp;  // DEM_LIST_PART_MIN >= DEM_LIST_GRID_MAX ints
-    void* args[] = {&a, &b, &p, &part};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(k_list_build), dim3(g), dim3(LIST_T), args, 0, s);
+    k_list_copy_hist<<<nblk_list(A.pair_cap > A.p.np ? A.pair_cap : A.p.np), 256, 0, s>>>(A, B, par);
+    if ((e = psm_scan(A.cell_count, A.cell_start, A.ncell, scan_tmp, s, A.list_run)) != hipSuccess) return e;
+    k_scatter<<<nblk_list(A.p.np), 256, 0, s>>>(A);
+    k_cellsort<<<nblk_list(A.ncell), 256, 0, s>>>(A);
+    k_paircount<<<nblk_list(64LL * A.p.np), 256, 0, s>>>(A);
+    if ((e = psm_scan(A.pcount, B.prow, A.p.np, scan_tmp, s, A.list_run)) != hipSuccess) return e;
+    k_pairemit<<<nblk_list(64LL * A.p.np), 256, 0, s>>>(A, B);
+    return dem_columns(A, B, scan_tmp, s);
 }
 
-// the column lists of the current rows (list_run gates them as the rows)
+// the column lists of the current rows from their column counts (counted by
+// the row emission, or by dem_count_columns); list_run gates them as the rows
 hipError_t dem_columns(const DemArgs& A, const PairBufs& B, int* scan_tmp, hipStream_t s) {
     hipError_t e;
-    k_colhist<<<nblk_list(A.pair_cap), 256, 0, s>>>(A, B);
     if ((e = psm_scan(A.col_count, A.col_start, A.p.np, scan_tmp, s, A.list_run)) != hipSuccess) return e;
     k_colscatter<<<nblk_list(A.pair_cap), 256, 0, s>>>(A, B);
     k_colsort<<<nblk_list(64LL * A.p.np), 256, 0, s>>>(A);
@@ -2251,6 +2093,11 @@ hipError_t dem_lists(const DemArgs& A, const PairBufs& B, int* scan_tmp, hipStre
     if ((e = psm_scan(A.pcount, B.prow, A.p.np, scan_tmp, s)) != hipSuccess) return e;
     k_pairemit<<<nblk_list(64LL * A.p.np), 256, 0, s>>>(A, B);
     return dem_columns(A, B, scan_tmp, s);
+}
+
+hipError_t dem_count_columns(const DemArgs& A, const PairBufs& B, hipStream_t s) {
+    k_colhist<<<nblk_list(A.pair_cap), 256, 0, s>>>(A, B);
+    return hipGetLastError();
 }
 
 hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, const double* ww, double dth,

@@ -493,7 +493,7 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
         D->vbox = (unsigned short*)A(sizeof(unsigned short) * (size_t)D->box_stride * np);
     }
     long long scan_n = std::max<long long>(std::max<long long>(D->ncell, g.ntiles), np + 1);
-    D->scan_tmp = (int*)A(sizeof(int) * std::max<size_t>(psm_scan_tmp_ints(scan_n), DEM_LIST_PART_MIN));
+    D->scan_tmp = (int*)A(sizeof(int) * psm_scan_tmp_ints(scan_n));
     D->ctr = (DevCounters*)A(sizeof(DevCounters));
     D->wall_corr_d = (double*)A(sizeof(double) * 6 * 19);
     if (d.kolm_amp != 0.0) {
@@ -695,7 +695,7 @@ extern "C" psmdem_status psmdem_stage(psmdem_domain* d, int32_t stage) {
                 return psm_hip_fail(hipGetLastError(), "copy", __FILE__, __LINE__);
             DemArgs A = d->dem_args();
             PairBufs B = d->pair_bufs(1);
-            if (dem_columns(A, B, d->scan_tmp, d->s) != hipSuccess ||
+            if (dem_count_columns(A, B, d->s) != hipSuccess || dem_columns(A, B, d->scan_tmp, d->s) != hipSuccess ||
                 dem_contacts(A, B, d->p.vp, d->p.wp, d->dt, d->scan_tmp, d->s) != hipSuccess)
                 return psm_hip_fail(hipGetLastError(), "contacts", __FILE__, __LINE__);
             break;

@@ -939,7 +939,7 @@ __device__ inline int sample_exact(const VoxPart& P, double dx, double dy, doubl
 
 // the row quadratic's coefficients of one particle (see k_vox_rows)
 struct RowQ {
-    double A, iA, by, bz, cyy, cyz, czz, a2, mt, xl, gmax, fns;
+    double A, iA, by, bz, cyy, cyz, czz, a2, i2a2, mt, xl, gmax, fns;
 };
 
 // Row dy, dz of the cell row `row` (LDS counts of the box's x cells): the
@@ -970,6 +970,21 @@ __device__ inline void row_inside(const VoxPart& P, const RowQ& q, const double*
     if (hi >= lo) {
         glo = (int)lo;
         ghi = (int)hi;
+    }
+    if (q.mt < 0.5) {
+        // at most one sample index lies within the margin of each root: the nearest
+        const double g1 = rint(G1), g2 = rint(G2);
+        if (fabs(g1 - G1) <= q.mt && g1 >= 0.0 && g1 <= q.gmax) {
+            const int gi = (int)g1;
+            if (sample_exact(P, ((double)(P.lo[0] + gi / ns) + off[gi % ns]) - P.c[0], dy, dz))
+                atomicAdd(&row[gi / ns], 1);
+        }
+        if (fabs(g2 - G2) <= q.mt && g2 >= 0.0 && g2 <= q.gmax && !(fabs(g2 - G1) <= q.mt)) {
+            const int gi = (int)g2;
+            if (sample_exact(P, ((double)(P.lo[0] + gi / ns) + off[gi % ns]) - P.c[0], dy, dz))
+                atomicAdd(&row[gi / ns], 1);
+        }
+        return;
     }
     const double u0 = fmax(ceil(G1 - q.mt), 0.0), u1 = fmin(floor(G1 + q.mt), q.gmax);
     for (double g = u0; g <= u1; g += 1.0) {
@@ -1019,7 +1034,7 @@ __device__ inline int range_in_cell(int glo, int ghi, int i, int ns) {
 // and go to the particle's count box in global memory, one 16-bit count per
 // cell, x fastest.
 template <int NS>
-__global__ __launch_bounds__(VOX_T) void k_vox_rows(VoxArgs A) {
+__global__ __launch_bounds__(VOX_T, 3) void k_vox_rows(VoxArgs A) {
     __shared__ VoxPart P;
     __shared__ double off[32];
     __shared__ int cnt_s[VOX_BOX_LDS];
@@ -1057,6 +1072,7 @@ __global__ __launch_bounds__(VOX_T) void k_vox_rows(VoxArgs A) {
     q.fns = (double)ns;
     q.mt = 1e-5 * (1.0 + amax) * q.fns;
     q.a2 = q.by * q.by - q.A * q.cyy;
+    q.i2a2 = 1.0 / (2.0 * q.a2);
     q.xl = (double)P.lo[0] - P.c[0];
     q.gmax = (double)(bx * ns - 1);
     const double my = 1e-3;
@@ -1077,12 +1093,14 @@ __global__ __launch_bounds__(VOX_T) void k_vox_rows(VoxArgs A) {
             const double D = a1 * a1 - 4.0 * q.a2 * a0;
             if (D < -(1e-9 * (a1 * a1 + 4.0 * fabs(q.a2 * a0)) + 1e-12)) continue;  // the plane misses it
             const double sD = sqrt(D > 0.0 ? D : 0.0);
-            const double y1 = (-a1 + sD) / (2.0 * q.a2), y2 = (-a1 - sD) / (2.0 * q.a2);
+            const double y1 = (-a1 + sD) * q.i2a2, y2 = (-a1 - sD) * q.i2a2;
             const double ylo = fmin(y1, y2) - my, yhi = fmax(y1, y2) + my;
             int* row = cnt_s + plane_cells * Zr + bx * Yr;
             if (NS > 0) {
                 int glo[NS > 0 ? NS : 1], ghi[NS > 0 ? NS : 1];
-                int i0 = 1 << 30, i1 = -1;
+                // cells touched by some row (i0..i1), cells that every nonempty row covers
+                // whole (f0..f1: NS samples from each of the nr such rows)
+                int i0 = 1 << 30, i1 = -1, f0 = 0, f1 = 1 << 30, nr = 0;
 #pragma unroll
                 for (int b = 0; b < NS; ++b) {
                     glo[b] = 1;
@@ -1091,14 +1109,20 @@ __global__ __launch_bounds__(VOX_T) void k_vox_rows(VoxArgs A) {
                     if (dy < ylo || dy > yhi) continue;
                     row_inside(P, q, off, NS, dy, dz, bzz, cyzz, czzz, row, glo[b], ghi[b]);
                     if (glo[b] <= ghi[b]) {
+                        ++nr;
                         i0 = min(i0, glo[b] / NS);
                         i1 = max(i1, ghi[b] / NS);
+                        f0 = max(f0, (glo[b] + NS - 1) / NS);
+                        f1 = min(f1, (ghi[b] + 1) / NS - 1);
                     }
                 }
                 for (int i = i0; i <= i1; ++i) {
-                    int n = 0;
+                    int n = NS * nr;
+                    if (i < f0 || i > f1) {
+                        n = 0;
 #pragma unroll
-                    for (int b = 0; b < NS; ++b) n += range_in_cell(glo[b], ghi[b], i, NS);
+                        for (int b = 0; b < NS; ++b) n += range_in_cell(glo[b], ghi[b], i, NS);
+                    }
                     if (n) atomicAdd(&row[i], n);
                 }
             } else {
