@@ -470,7 +470,7 @@ def main():
     elif a.workload == "fluidized":
         cfg, parts, meta = workloads.fluidized_bed(precision=a.precision, phi=a.phi)
     else:
-        cfg, parts, meta = workloads.settling_bed(precision=a.precision)
+        cfg, parts, meta = workloads.settling_bed_dense(precision=a.precision)
     if a.collision:
         cfg["collision"] = a.collision
     N = cfg["n"][0] * cfg["n"][1] * cfg["n"][2]

@@ -155,11 +155,8 @@ __global__ void k_fill_int(int* __restrict__ p, int v, long long n) {
 
 size_t psm_scan_tmp_ints(long long n) { return (size_t)((n + SCAN_BLOCK - 1) / SCAN_BLOCK + 1); }
 
-hipError_t psm_scan(const int* in, int* out, long long n, int* tmp, hipStream_t s, const int* run) {
-    if (n <= SCAN_SMALL) {
-        k_scan_small<<<1, 1024, 0, s>>>(in, out, n < 0 ? 0 : n, run);
-        return hipGetLastError();
-    }
+// the three-launch form at any length
+static hipError_t scan_blocks(const int* in, int* out, long long n, int* tmp, hipStream_t s, const int* run) {
     int nb = (int)((n + SCAN_BLOCK - 1) / SCAN_BLOCK);
     if (nb < 1) nb = 1;
     k_scan_local<<<nb, SCAN_T, 0, s>>>(in, out, n, tmp, run);
@@ -168,14 +165,26 @@ hipError_t psm_scan(const int* in, int* out, long long n, int* tmp, hipStream_t 
     return hipGetLastError();
 }
 
+hipError_t psm_scan(const int* in, int* out, long long n, int* tmp, hipStream_t s, const int* run) {
+    if (n <= SCAN_SMALL) {
+        k_scan_small<<<1, 1024, 0, s>>>(in, out, n < 0 ? 0 : n, run);
+        return hipGetLastError();
+    }
+    return scan_blocks(in, out, n, tmp, s, run);
+}
+
+// (one workgroup walking a long input is slower than the three-launch form;
+// above SCAN_PAIR_ONE each input takes its own scan)
+constexpr long long SCAN_PAIR_ONE = 16384;
+
 hipError_t psm_scan2(const int* in0, int* out0, long long n0, const int* in1, int* out1, long long n1, int* tmp,
                      hipStream_t s) {
-    if (n0 <= SCAN_SMALL && n1 <= SCAN_SMALL) {
+    if (n0 <= SCAN_PAIR_ONE && n1 <= SCAN_PAIR_ONE) {
         k_scan_small2<<<2, 1024, 0, s>>>(in0, out0, n0 < 0 ? 0 : n0, in1, out1, n1 < 0 ? 0 : n1);
         return hipGetLastError();
     }
-    hipError_t e = psm_scan(in0, out0, n0, tmp, s);
-    return e != hipSuccess ? e : psm_scan(in1, out1, n1, tmp, s);
+    hipError_t e = scan_blocks(in0, out0, n0 < 0 ? 0 : n0, tmp, s, nullptr);
+    return e != hipSuccess ? e : scan_blocks(in1, out1, n1 < 0 ? 0 : n1, tmp, s, nullptr);
 }
 
 hipError_t psm_fill_int(int* p, int v, long long n, hipStream_t s) {

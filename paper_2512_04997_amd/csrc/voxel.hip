@@ -133,32 +133,34 @@ __device__ inline bool particle_tiles(const VoxArgs& A, int k, TileSet& S) {
     return far;
 }
 
-// Registration of particle k, one wave per particle: lane l takes the l-th
-// tile of the particle's box (x fastest, then y, then z), which is also the
-// order of its emission indices.
+// Registration of particle k by a group of lanes: lane l of the group takes
+// the l-th tile of the particle's box (x fastest, then y, then z), then the
+// (l + group size)-th, ...; the tile's place in that order is also its
+// emission index.
 __device__ inline long long tile_of(const VoxArgs& A, const TileSet& S, int l) {
     const int a = l % S.nx, b = (l / S.nx) % S.ny, c = l / (S.nx * S.ny);
     return S.tx[a] + (long long)A.g.ntx * (S.ty[b] + (long long)A.g.nty * S.tz[c]);
 }
 
-// tile count of particle k and one tile-histogram increment per tile (through `hist`)
-__device__ inline void reg_count_wave(const VoxArgs& A, int k, int lane, int* hist) {
+// tile count of particle k and one tile-histogram increment per tile (through
+// `hist`), by lane `lane` of a group of `gs` lanes
+__device__ inline void reg_count_wave(const VoxArgs& A, int k, int lane, int* hist, int gs = 64) {
     TileSet S;
     const bool far = particle_tiles(A, k, S);
     const int n = S.nx * S.ny * S.nz;
     if (lane == 0) A.t.vcount[k] = n;
     if (lane == 0 && far) atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_UNSTABLE);
-    for (int l = lane; l < n; l += 64) atomicAdd(&hist[tile_of(A, S, l)], 1);
+    for (int l = lane; l < n; l += gs) atomicAdd(&hist[tile_of(A, S, l)], 1);
 }
 
 // counting-sort scatter of particle k's (pid, emission) entries; `fill` counts per tile
-__device__ inline void reg_scatter_wave(const VoxArgs& A, int k, int lane, int* fill) {
+__device__ inline void reg_scatter_wave(const VoxArgs& A, int k, int lane, int* fill, int gs = 64) {
     TileSet S;
     particle_tiles(A, k, S);
     const int n = S.nx * S.ny * S.nz;
     const int e0 = A.t.voff[k];
     bool full = false;
-    for (int l = lane; l < n; l += 64) {
+    for (int l = lane; l < n; l += gs) {
         const long long t = tile_of(A, S, l);
         const int e = e0 + l;
         const int slot = atomicAdd(&fill[t], 1);
@@ -188,22 +190,26 @@ __device__ inline void reg_sort(const VoxArgs& A, long long t) {
     }
 }
 
-// one wave per particle; block 0 also clears the step's entry counters
+// VOX_REG_G lanes per particle (a particle's box touches a few tiles, most
+// often fewer than eight); block 0 also clears the step's entry counters
+#define VOX_REG_G 8
 __global__ void k_vox_count(VoxArgs A) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         A.ctr->entries = 0;
         A.ctr->dropped = 0;
         A.ctr->items = 0;
     }
-    const int k = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = (int)(g / VOX_REG_G);
     if (k >= A.p.np) return;
-    reg_count_wave(A, k, threadIdx.x & 63, A.tile_count);
+    reg_count_wave(A, k, (int)(g % VOX_REG_G), A.tile_count, VOX_REG_G);
 }
 
 __global__ void k_vox_scatter(VoxArgs A) {
-    const int k = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const long long g = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = (int)(g / VOX_REG_G);
     if (k >= A.p.np) return;
-    reg_scatter_wave(A, k, threadIdx.x & 63, A.tile_fill);
+    reg_scatter_wave(A, k, (int)(g % VOX_REG_G), A.tile_fill, VOX_REG_G);
 }
 
 #define VOX_T 256  // lanes of the per-tile voxelisation workgroups
@@ -1325,7 +1331,7 @@ inline unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) /
 // the tile counters start at zero (creation) and are cleared again where the lists are ordered
 hipError_t vox_register(const VoxArgs& A, int* scan_tmp, hipStream_t s) {
     hipError_t e;
-    const unsigned nbw = nblk(64LL * (A.p.np > 0 ? A.p.np : 1));
+    const unsigned nbw = nblk((long long)VOX_REG_G * (A.p.np > 0 ? A.p.np : 1));
     k_vox_count<<<nbw, 256, 0, s>>>(A);
     if ((e = psm_scan2(A.t.vcount, A.t.voff, A.p.np, A.tile_count, A.t.tile_start, A.g.ntiles, scan_tmp, s)) !=
         hipSuccess)

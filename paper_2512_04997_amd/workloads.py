@@ -501,6 +501,117 @@ def settling_bed(precision="fp32", n=(256, 256, 128), fraction=0.15, seed=1002, 
     return cfg, parts, dict(workload=f"settling_bed_{n[0]}x{n[1]}x{n[2]}_{len(pos)}_spheres", steps=steps)
 
 
+def rsa_polydisperse(rng, rmin, rmax, box, region_lo, region_hi, target_volume, gap=0.0, wall_gap=0.0,
+                     batch=16384, max_attempts=100_000_000):
+    """Random sequential addition of spheres whose radii are drawn with their
+    centres, in a box walled on every face, until the placed volume reaches
+    target_volume.  Candidates come in batches: `batch` radii uniform in
+    [rmin, rmax], then `batch` centres (3 uniforms each) uniform over the part of
+    [region_lo, region_hi] that keeps the sphere wall_gap inside the box.  A
+    candidate is kept when its surface clears every kept sphere's by `gap`
+    (a grid of cells at least 2 rmax + gap wide holds them), tested in draw
+    order against every earlier kept one, its own batch's included, so the
+    result is that of one candidate at a time.  Near the fraction at which the
+    addition jams, small candidates fit where large ones do not, so the kept
+    radii lean to the small end.  Returns (pos (m, 3), radii (m,))."""
+    box = np.asarray(box, np.float64)
+    lo = np.asarray(region_lo, np.float64)
+    hi = np.asarray(region_hi, np.float64)
+    nc = np.maximum(1, np.floor(box / (2.0 * rmax + gap)).astype(np.int64))
+    hc = box / nc
+    ncell = int(np.prod(nc))
+    K = 8  # a cell 2 rmax wide holds fewer than eight spheres of radius rmin / 2 or more
+    grid = -np.ones((ncell, K), np.int64)
+    gcnt = np.zeros(ncell, np.int64)
+    cap = int(target_volume / (4.0 / 3.0 * math.pi * rmin ** 3)) + 2
+    pos = np.full((cap + 1, 3), -1e9)
+    rad = np.zeros(cap + 1)
+    off = np.array([(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)])
+
+    def cell_id(c):
+        return (c[..., 2] * nc[1] + c[..., 1]) * nc[0] + c[..., 0]
+
+    def near(cells, table):
+        # entries of `table` in the 27 cells around each cell (outside the box: none)
+        nbr = cells[:, None, :] + off[None]
+        inb = np.all((nbr >= 0) & (nbr < nc), axis=2)
+        ids = table[np.where(inb, cell_id(np.clip(nbr, 0, nc - 1)), 0)]
+        return np.where(inb[:, :, None], ids, -1).reshape(len(cells), -1)
+
+    placed = attempts = 0
+    vol = 0.0
+    while vol < target_volume and attempts < max_attempts:
+        nb = batch
+        R = rmin + (rmax - rmin) * rng.uniform(nb)
+        U = rng.uniform(3 * nb).reshape(nb, 3)
+        attempts += nb
+        lo_c = np.maximum(lo[None, :], 0.0) + (R + wall_gap)[:, None]
+        hi_c = np.minimum(hi[None, :], box[None, :]) - (R + wall_gap)[:, None]
+        C = lo_c + (hi_c - lo_c) * U
+        ci = np.clip(np.floor(C / hc).astype(np.int64), 0, nc - 1)
+        # against the spheres kept before this batch
+        idx = near(ci, grid)
+        j = np.where(idx >= 0, idx, cap)
+        d = pos[j] - C[:, None, :]
+        clash = np.any((idx >= 0) & (np.sqrt(np.sum(d * d, axis=2)) < rad[j] + R[:, None] + gap), axis=1)
+        surv = np.flatnonzero(~clash)
+        S = len(surv)
+        if S == 0:
+            continue
+        # among the batch's survivors (earlier survivor jj, later ii)
+        cid = cell_id(ci[surv])
+        cnt = np.bincount(cid, minlength=ncell)
+        order = np.argsort(cid, kind="stable")
+        rank = np.empty(S, np.int64)
+        rank[order] = np.arange(S) - np.concatenate([[0], np.cumsum(cnt)[:-1]])[cid[order]]
+        tg = -np.ones((ncell, int(cnt.max())), np.int64)
+        tg[cid, rank] = np.arange(S)
+        jdx = near(ci[surv], tg)
+        ii, kk = np.nonzero(jdx >= 0)
+        jj = jdx[ii, kk]
+        ii, jj = ii[jj < ii], jj[jj < ii]
+        d2 = C[surv[jj]] - C[surv[ii]]
+        ovl = np.sqrt(np.sum(d2 * d2, axis=1)) < R[surv[ii]] + R[surv[jj]] + gap
+        earlier = {}
+        for a, b in zip(ii[ovl].tolist(), jj[ovl].tolist()):
+            earlier.setdefault(a, []).append(b)
+        taken = np.zeros(S, dtype=bool)
+        for t in range(S):
+            if vol >= target_volume:
+                break
+            if any(taken[b] for b in earlier.get(t, ())):
+                continue
+            taken[t] = True
+            s_ = surv[t]
+            c = int(cell_id(ci[s_]))
+            if gcnt[c] >= K:
+                raise RuntimeError("grid cell overflow in sphere placement")
+            pos[placed], rad[placed] = C[s_], R[s_]
+            grid[c, gcnt[c]] = placed
+            gcnt[c] += 1
+            placed += 1
+            vol += 4.0 / 3.0 * math.pi * R[s_] ** 3
+    return pos[:placed], rad[:placed]
+
+
+def settling_bed_dense(precision="fp32", n=(256, 256, 128), fraction=0.30, seed=1005, steps=2000):
+    """The DEM-heavy settling bed on the 256 x 256 x 128 lattice: polydisperse
+    spheres (radius uniform in [2, 3] per candidate) placed by random sequential
+    addition without overlap in the top 60 % of a box walled on every face,
+    until they fill `fraction` of that region (0.30: about 26,500 spheres);
+    tau = 0.6, density ratio 2.5, gravity (0, 0, -1e-5) on the particles, the
+    linear contact law of the Couette workload, n_sub = 32."""
+    bc = ["noslip"] * 6
+    cfg = base_config(tuple(n), 0.6, bc=bc, gravity=[0.0, 0.0, -1e-5], precision=precision, n_sub=32,
+                      kn=1e3, restitution=0.8, mu=0.3)
+    box = np.asarray(n, dtype=np.float64)
+    lo = np.array([0.0, 0.0, 0.4 * box[2]])
+    region = box[0] * box[1] * 0.6 * box[2]
+    pos, radii = rsa_polydisperse(SplitMix64(seed), 2.0, 3.0, box, lo, box, fraction * region)
+    parts = spheres(pos, radii, 2.5)
+    return cfg, parts, dict(workload=f"settling_bed_{n[0]}x{n[1]}x{n[2]}_{len(pos)}_spheres", steps=steps)
+
+
 # sphere counts of the fluidized-bed benchmark at the fractions the paper lists
 FLUIDIZED_COUNTS = {0.0: 0, 0.15: 2866, 0.30: 5731, 0.45: 8596}
 

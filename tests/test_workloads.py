@@ -113,3 +113,23 @@ def test_placement_tests_candidates_within_their_batch():
             m = np.arange(len(pos)) > i
             assert not np.any(W.ellipsoids_overlap(d[m], np.repeat(A[i:i + 1], m.sum(), 0), A[m]))
     assert len(p1) == 40
+
+
+def test_polydisperse_addition_in_a_walled_box():
+    """The dense settling bed's placement: no two spheres overlap (all pairs,
+    brute force), each lies inside the box and its region, the placed volume
+    reaches the requested fraction, radii stay in [2, 3], and the same seed
+    gives the same bed."""
+    box = np.array([48.0, 40.0, 36.0])
+    lo = np.array([0.0, 0.0, 0.4 * box[2]])
+    region = box[0] * box[1] * 0.6 * box[2]
+    pos, r = W.rsa_polydisperse(W.SplitMix64(7), 2.0, 3.0, box, lo, box, 0.3 * region, batch=2048)
+    d = np.sqrt(((pos[:, None, :] - pos[None, :, :]) ** 2).sum(-1))
+    np.fill_diagonal(d, np.inf)
+    assert np.all(d >= r[:, None] + r[None, :])
+    assert np.all(pos - r[:, None] >= lo) and np.all(pos + r[:, None] <= box)
+    assert np.all((r >= 2.0) & (r <= 3.0))
+    vol = (4.0 / 3.0 * np.pi * r ** 3).sum()
+    assert 0.3 * region <= vol < 0.3 * region + 4.0 / 3.0 * np.pi * 27.0
+    pos2, r2 = W.rsa_polydisperse(W.SplitMix64(7), 2.0, 3.0, box, lo, box, 0.3 * region, batch=2048)
+    assert np.array_equal(pos, pos2) and np.array_equal(r, r2)
