@@ -66,6 +66,7 @@ struct psmdem_domain {
     unsigned short* vbox = nullptr;
     long long box_stride = 0;
     void* vpart = nullptr;
+    void* tile_rec = nullptr;
     int* scan_tmp = nullptr;
     DevCounters* ctr = nullptr;
 
@@ -213,6 +214,7 @@ struct psmdem_domain {
         A.vbox = vbox;
         A.box_stride = box_stride;
         A.vpart = vpart;
+        A.tile_rec = tile_rec;
         A.ctr = ctr;
         return A;
     }

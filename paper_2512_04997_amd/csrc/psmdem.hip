@@ -480,6 +480,7 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
     D->tile_count = (int*)A(sizeof(int) * g.ntiles);
     D->tile_fill = (int*)A(sizeof(int) * g.ntiles);
     if (np > 0) D->vpart = A(vox_part_bytes() * (size_t)np);
+    if (np > 0 && vox_tile_rec_bytes(g.ntiles)) D->tile_rec = A(vox_tile_rec_bytes(g.ntiles) * (size_t)t.cap);
     // subdivision method: one count box per particle, sized for the largest
     // lattice box (per axis at most floor(2 r_b + 2e-6) + 2 cells)
     if (np > 0 && d.sf_method == 0) {

@@ -20,7 +20,9 @@ struct VoxArgs {
     unsigned short* vbox;
     long long box_stride;
     void* vpart;                 // [np] per-step particle records of the tile kernels (vox_part_bytes
-                                 // each), formed by vox_voxelize; null: each tile forms its own
+                                 // each), formed by vox_register; null: each tile forms its own
+    void* tile_rec;              // [t.cap] selection record per registration slot (vox_tile_rec_bytes
+                                 // each), written by the tile sort from vpart; null: gathered per tile
     DevCounters* ctr;
 };
 
@@ -38,5 +40,8 @@ hipError_t vox_select(const VoxArgs& A, int ctype_double, hipStream_t s);
 hipError_t vox_reduce_hydro(const VoxArgs& A, hipStream_t s);
 // bytes of one particle record (VoxArgs::vpart)
 size_t vox_part_bytes();
+// bytes of one selection record (VoxArgs::tile_rec) on a lattice of ntiles
+// tiles; 0 where the selection kernel orders the lists itself (none kept)
+size_t vox_tile_rec_bytes(long long ntiles);
 // cells of a count box's x-y plane the row-counting kernel holds (per z-slab)
 size_t vox_box_cells_max();

@@ -9,7 +9,8 @@
 //   k_vox_count    tiles touched by each particle's lattice box (count + tile histogram)
 //   (scans)        emission offsets per particle, list offsets per tile
 //   k_vox_scatter  counting-sort scatter of (pid, emission index) into tiles
-//   (k_tile_sort)  order each tile's list by pid; inverse map emission -> position
+//   (k_tile_sort)  order each tile's list by pid; inverse map emission -> position;
+//                  each entry's selection record beside it
 //                  (lattices of up to VOX_SORT_IN_TILE_MAX tiles do this in the
 //                  select kernel instead)
 //   k_vox_rows     subdivision method: one workgroup per particle counts the
@@ -219,15 +220,6 @@ __global__ void k_vox_scatter(VoxArgs A) {
 // latency in every tile workgroup.
 #define VOX_SORT_IN_TILE_MAX 8192
 
-// orders each tile's list, then clears the tile's counters for the next step
-__global__ void k_tile_sort(VoxArgs A) {
-    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= A.g.ntiles) return;
-    reg_sort(A, t);
-    A.tile_count[t] = 0;
-    A.tile_fill[t] = 0;
-}
-
 // Tile t's list ordered by (pid, emission) by the tile's workgroup, the
 // emission -> position map, and the tile's counters cleared for the next step.
 // Up to VOX_T entries rank-sort through LDS (keys are unique); longer lists
@@ -314,6 +306,50 @@ struct VoxPart {
     int pid;
 };
 static_assert(sizeof(VoxPart) % 8 == 0, "VoxPart is copied in 8-byte words");
+
+// what the selection needs of a candidate (a quarter of a full record)
+struct SelPart {
+    double c[3];
+    double ax[1];   // radius (the distance method)
+    int lo[3], hi[3];
+    int shape, pid;
+};
+static_assert(sizeof(SelPart) % 8 == 0, "SelPart is copied in 8-byte words");
+
+__device__ inline void sel_of(const VoxPart& V, SelPart& P) {
+    for (int a = 0; a < 3; ++a) {
+        P.c[a] = V.c[a];
+        P.lo[a] = V.lo[a];
+        P.hi[a] = V.hi[a];
+    }
+    P.ax[0] = V.ax[0];
+    P.shape = V.shape;
+    P.pid = V.pid;
+}
+
+// orders each tile's list, then clears the tile's counters for the next step;
+// with tile_rec, also writes each entry's selection record beside it (from the
+// step's particle records), so that the selection reads its candidates in one
+// contiguous load instead of a list load and a gather
+__global__ void k_tile_sort(VoxArgs A) {
+    long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= A.g.ntiles) return;
+    reg_sort(A, t);
+    A.tile_count[t] = 0;
+    A.tile_fill[t] = 0;
+    if (!A.tile_rec) return;
+    long long s0 = A.t.tile_start[t], s1 = A.t.tile_start[t + 1];
+    if (s1 > A.t.cap) s1 = A.t.cap;
+    SelPart* out = (SelPart*)A.tile_rec;
+    for (long long u = s0; u < s1; ++u) {
+        int k = (int)(A.t.tile_list[u] >> 32);
+        if (k >= A.p.np) k = 0;
+        SelPart P;
+        sel_of(((const VoxPart*)A.vpart)[k], P);
+        out[u] = P;
+    }
+}
+
 
 template <typename PT>
 __device__ inline bool in_box(const PT& P, int x, int n, int axis, int periodic, int* X) {
@@ -945,7 +981,7 @@ __device__ inline int sample_exact(const VoxPart& P, double dx, double dy, doubl
 
 // the row quadratic's coefficients of one particle (see k_vox_rows)
 struct RowQ {
-    double A, iA, by, bz, cyy, cyz, czz, a2, i2a2, mt, xl, gmax, fns;
+    double A, iA, by, bz, cyy, cyz, czz, a2, mt, xl, gmax, fns;
 };
 
 // Row dy, dz of the cell row `row` (LDS counts of the box's x cells): the
@@ -976,21 +1012,6 @@ __device__ inline void row_inside(const VoxPart& P, const RowQ& q, const double*
     if (hi >= lo) {
         glo = (int)lo;
         ghi = (int)hi;
-    }
-    if (q.mt < 0.5) {
-        // at most one sample index lies within the margin of each root: the nearest
-        const double g1 = rint(G1), g2 = rint(G2);
-        if (fabs(g1 - G1) <= q.mt && g1 >= 0.0 && g1 <= q.gmax) {
-            const int gi = (int)g1;
-            if (sample_exact(P, ((double)(P.lo[0] + gi / ns) + off[gi % ns]) - P.c[0], dy, dz))
-                atomicAdd(&row[gi / ns], 1);
-        }
-        if (fabs(g2 - G2) <= q.mt && g2 >= 0.0 && g2 <= q.gmax && !(fabs(g2 - G1) <= q.mt)) {
-            const int gi = (int)g2;
-            if (sample_exact(P, ((double)(P.lo[0] + gi / ns) + off[gi % ns]) - P.c[0], dy, dz))
-                atomicAdd(&row[gi / ns], 1);
-        }
-        return;
     }
     const double u0 = fmax(ceil(G1 - q.mt), 0.0), u1 = fmin(floor(G1 + q.mt), q.gmax);
     for (double g = u0; g <= u1; g += 1.0) {
@@ -1040,7 +1061,7 @@ __device__ inline int range_in_cell(int glo, int ghi, int i, int ns) {
 // and go to the particle's count box in global memory, one 16-bit count per
 // cell, x fastest.
 template <int NS>
-__global__ __launch_bounds__(VOX_T, 3) void k_vox_rows(VoxArgs A) {
+__global__ __launch_bounds__(VOX_T) void k_vox_rows(VoxArgs A) {
     __shared__ VoxPart P;
     __shared__ double off[32];
     __shared__ int cnt_s[VOX_BOX_LDS];
@@ -1078,7 +1099,6 @@ __global__ __launch_bounds__(VOX_T, 3) void k_vox_rows(VoxArgs A) {
     q.fns = (double)ns;
     q.mt = 1e-5 * (1.0 + amax) * q.fns;
     q.a2 = q.by * q.by - q.A * q.cyy;
-    q.i2a2 = 1.0 / (2.0 * q.a2);
     q.xl = (double)P.lo[0] - P.c[0];
     q.gmax = (double)(bx * ns - 1);
     const double my = 1e-3;
@@ -1099,14 +1119,12 @@ __global__ __launch_bounds__(VOX_T, 3) void k_vox_rows(VoxArgs A) {
             const double D = a1 * a1 - 4.0 * q.a2 * a0;
             if (D < -(1e-9 * (a1 * a1 + 4.0 * fabs(q.a2 * a0)) + 1e-12)) continue;  // the plane misses it
             const double sD = sqrt(D > 0.0 ? D : 0.0);
-            const double y1 = (-a1 + sD) * q.i2a2, y2 = (-a1 - sD) * q.i2a2;
+            const double y1 = (-a1 + sD) / (2.0 * q.a2), y2 = (-a1 - sD) / (2.0 * q.a2);
             const double ylo = fmin(y1, y2) - my, yhi = fmax(y1, y2) + my;
             int* row = cnt_s + plane_cells * Zr + bx * Yr;
             if (NS > 0) {
                 int glo[NS > 0 ? NS : 1], ghi[NS > 0 ? NS : 1];
-                // cells touched by some row (i0..i1), cells that every nonempty row covers
-                // whole (f0..f1: NS samples from each of the nr such rows)
-                int i0 = 1 << 30, i1 = -1, f0 = 0, f1 = 1 << 30, nr = 0;
+                int i0 = 1 << 30, i1 = -1;
 #pragma unroll
                 for (int b = 0; b < NS; ++b) {
                     glo[b] = 1;
@@ -1115,20 +1133,14 @@ __global__ __launch_bounds__(VOX_T, 3) void k_vox_rows(VoxArgs A) {
                     if (dy < ylo || dy > yhi) continue;
                     row_inside(P, q, off, NS, dy, dz, bzz, cyzz, czzz, row, glo[b], ghi[b]);
                     if (glo[b] <= ghi[b]) {
-                        ++nr;
                         i0 = min(i0, glo[b] / NS);
                         i1 = max(i1, ghi[b] / NS);
-                        f0 = max(f0, (glo[b] + NS - 1) / NS);
-                        f1 = min(f1, (ghi[b] + 1) / NS - 1);
                     }
                 }
                 for (int i = i0; i <= i1; ++i) {
-                    int n = NS * nr;
-                    if (i < f0 || i > f1) {
-                        n = 0;
+                    int n = 0;
 #pragma unroll
-                        for (int b = 0; b < NS; ++b) n += range_in_cell(glo[b], ghi[b], i, NS);
-                    }
+                    for (int b = 0; b < NS; ++b) n += range_in_cell(glo[b], ghi[b], i, NS);
                     if (n) atomicAdd(&row[i], n);
                 }
             } else {
@@ -1147,14 +1159,6 @@ __global__ __launch_bounds__(VOX_T, 3) void k_vox_rows(VoxArgs A) {
         __syncthreads();
     }
 }
-
-// what the selection needs of a candidate (staged in LDS, a quarter of a full record)
-struct SelPart {
-    double c[3];
-    double ax[1];   // radius (the distance method)
-    int lo[3], hi[3];
-    int shape, pid;
-};
 
 // Phase C of the subdivision method from the count boxes, on integer keys:
 // an entry of candidate u with count n > 0 is the key n * 256 + (255 - u), so
@@ -1265,19 +1269,18 @@ __global__ __launch_bounds__(VOX_T) void k_vox_select(VoxArgs A) {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     if (tid == 0) { cnt_e = 0; cnt_d = 0; }
     if (tid < A.ns) off[tid] = (double)(2 * tid + 1) / (double)(2 * A.ns);
-    for (int u = tid; u < R.count; u += VOX_T) {
-        int k = (int)((keys ? keys[u] : A.t.tile_list[R.s0 + u]) >> 32);
-        if (k >= A.p.np) k = 0;
-        const VoxPart& V = ((const VoxPart*)A.vpart)[k];
-        SelPart& P = sp[u];
-        for (int a = 0; a < 3; ++a) {
-            P.c[a] = V.c[a];
-            P.lo[a] = V.lo[a];
-            P.hi[a] = V.hi[a];
+    if (!SORT && A.tile_rec) {
+        // the records beside the sorted list, copied in 8-byte words
+        const unsigned long long* src = (const unsigned long long*)((const SelPart*)A.tile_rec + R.s0);
+        unsigned long long* dst = (unsigned long long*)sp;
+        const int words = R.count * (int)(sizeof(SelPart) / 8);
+        for (int w = tid; w < words; w += VOX_T) dst[w] = src[w];
+    } else {
+        for (int u = tid; u < R.count; u += VOX_T) {
+            int k = (int)((keys ? keys[u] : A.t.tile_list[R.s0 + u]) >> 32);
+            if (k >= A.p.np) k = 0;
+            sel_of(((const VoxPart*)A.vpart)[k], sp[u]);
         }
-        P.ax[0] = V.ax[0];
-        P.shape = V.shape;
-        P.pid = V.pid;
     }
     __syncthreads();
     const double slo = off[0], shi = off[A.ns - 1];  // first and last sample offset
@@ -1331,6 +1334,7 @@ inline unsigned nblk(long long n, int t = 256) { return (unsigned)((n + t - 1) /
 // the tile counters start at zero (creation) and are cleared again where the lists are ordered
 hipError_t vox_register(const VoxArgs& A, int* scan_tmp, hipStream_t s) {
     hipError_t e;
+    if (A.p.np > 0 && A.vpart) k_vox_parts<<<nblk(A.p.np), 256, 0, s>>>(A);
     const unsigned nbw = nblk((long long)VOX_REG_G * (A.p.np > 0 ? A.p.np : 1));
     k_vox_count<<<nbw, 256, 0, s>>>(A);
     if ((e = psm_scan2(A.t.vcount, A.t.voff, A.p.np, A.tile_count, A.t.tile_start, A.g.ntiles, scan_tmp, s)) !=
@@ -1344,7 +1348,6 @@ hipError_t vox_register(const VoxArgs& A, int* scan_tmp, hipStream_t s) {
 }
 
 hipError_t vox_voxelize(const VoxArgs& A, int ctype_double, hipStream_t s) {
-    if (A.p.np > 0) k_vox_parts<<<nblk(A.p.np), 256, 0, s>>>(A);
     if (A.sf_method == 0 && A.p.np > 0) {
         if (A.ns == 10) k_vox_rows<10><<<(unsigned)A.p.np, VOX_T, 0, s>>>(A);
         else k_vox_rows<0><<<(unsigned)A.p.np, VOX_T, 0, s>>>(A);
@@ -1398,5 +1401,6 @@ hipError_t vox_reduce_hydro(const VoxArgs& A, hipStream_t s) {
 }
 
 size_t vox_part_bytes() { return sizeof(VoxPart); }
+size_t vox_tile_rec_bytes(long long ntiles) { return ntiles > VOX_SORT_IN_TILE_MAX ? sizeof(SelPart) : 0; }
 size_t vox_box_cells_max() { return VOX_BOX_LDS; }
 
