@@ -84,14 +84,16 @@ hipError_t dem_columns(const DemArgs& A, const PairBufs& B, int* scan_tmp, hipSt
 hipError_t dem_count_columns(const DemArgs& A, const PairBufs& B, hipStream_t s);
 // multi-launch substeps that keep an unchanged list (A.list_run = A.list_flag + par)
 hipError_t dem_predict_keep(const DemArgs& A, double dt, int write_kin, int par, hipStream_t s);
-// the corrector of a substep and the predictor of the next (its parity par)
-hipError_t dem_correct_predict(const DemArgs& A, double dt, int write_kin, int par, hipStream_t s);
 // the list of a multi-launch substep: rebuilt (cells, rows, columns) when
 // list_flag[par] is set, else kept (the list kernels return at once)
 hipError_t dem_lists_kept(const DemArgs& A, const PairBufs& B, int par, int* scan_tmp, hipStream_t s);
-// contacts of the pairs in B, then the per-particle sums
+// contacts of the pairs in B, then (sums) the per-particle sums
 hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, const double* ww, double dth,
-                        int* scan_tmp, hipStream_t s);
+                        int* scan_tmp, hipStream_t s, bool sums = true);
+// the per-particle sums of a substep whose contacts ran without them, its
+// corrector and the next substep's predictor (its parity par)
+hipError_t dem_sum_correct_predict(const DemArgs& A, const PairBufs& B, double dt, int write_kin, int par,
+                                   hipStream_t s);
 hipError_t dem_correct(const DemArgs& A, double dt, hipStream_t s);
 // hydrodynamic sums of the tile partials (T) and the corrector, one launch
 hipError_t dem_hydro_correct(const DemArgs& A, const TileArgs& T, double dt, hipStream_t s);

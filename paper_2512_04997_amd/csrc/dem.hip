@@ -1076,12 +1076,47 @@ __global__ void k_predict_keep(DemArgs A, double dt, int write_kin, int par) {
     GRID_LOOP(k, A.p.np) predict_keep_one(A, (int)k, dt, write_kin, par);
 }
 
-// the corrector of a substep and the predictor of the next one, per particle
-__global__ void k_correct_predict(DemArgs A, double dt, int write_kin, int par) {
+// The DEM sums of a substep, its corrector and the next substep's predictor,
+// one thread per particle: the sums take the particle's column (pairs (k, i),
+// ascending k), then its row, pairs in contact only, in the order of
+// k_sum_wave; block 0 also clears the contacts' deferral queue (as k_sum_wave
+// does) and the current parity's list flag (as k_predict_keep does).
+__global__ __launch_bounds__(256) void k_sum_correct_predict(DemArgs A, PairBufs B, double dt, int write_kin,
+                                                             int par) {
     if (blockIdx.x == 0 && threadIdx.x == 0) A.list_flag[par ^ 1] = 0;
+    if (A.ell_cnt && blockIdx.x == 0 && threadIdx.x < DEM_ELL_SEGS) A.ell_cnt[threadIdx.x] = 0;
+    const long long cap = A.pair_cap;
     GRID_LOOP(k, A.p.np) {
-        ph_correct(A, (int)k, dt);
-        predict_keep_one(A, (int)k, dt, write_kin, par);
+        const int i = (int)k;
+        const long long c0 = A.col_start[i], c1 = A.col_start[i + 1];
+        const long long s0 = B.prow[i];
+        long long s1 = B.prow[i + 1];
+        s1 = s1 < cap ? s1 : cap;
+        double F[3] = {0.0, 0.0, 0.0}, M[3] = {0.0, 0.0, 0.0};
+        for (long long u = c0; u < c1; ++u) {
+            const long long s = A.col_list[u];
+            if (!A.incontact[s]) continue;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                F[c] -= A.cF[3 * s + c];
+                M[c] += A.cMj[3 * s + c];
+            }
+        }
+        for (long long s = s0; s < s1; ++s) {
+            if (!A.incontact[s]) continue;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                F[c] += A.cF[3 * s + c];
+                M[c] += A.cMi[3 * s + c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            A.p.fd[3 * i + c] = F[c];
+            A.p.md[3 * i + c] = M[c];
+        }
+        ph_correct(A, i, dt);
+        predict_keep_one(A, i, dt, write_kin, par);
     }
 }
 
@@ -2101,7 +2136,7 @@ hipError_t dem_count_columns(const DemArgs& A, const PairBufs& B, hipStream_t s)
 }
 
 hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, const double* ww, double dth,
-                        int* scan_tmp, hipStream_t s) {
+                        int* scan_tmp, hipStream_t s, bool sums) {
     if (A.p.np == 0) return hipSuccess;
     // a grid for the pairs the list can hold, capped (the kernel strides over the rest)
     unsigned nbc = nblk(A.pair_cap, 128);
@@ -2115,19 +2150,20 @@ hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, c
     } else {
         k_contacts<false><<<nbc, 128, 0, s>>>(A, B, vv, ww, dth);
     }
-    k_sum_wave<<<nblk(64LL * A.p.np), 256, 0, s>>>(A, B);
+    if (sums) k_sum_wave<<<nblk(64LL * A.p.np), 256, 0, s>>>(A, B);
+    return hipGetLastError();
+}
+
+hipError_t dem_sum_correct_predict(const DemArgs& A, const PairBufs& B, double dt, int write_kin, int par,
+                                   hipStream_t s) {
+    if (A.p.np == 0) return hipSuccess;
+    k_sum_correct_predict<<<nblk(A.p.np), 256, 0, s>>>(A, B, dt, write_kin, par);
     return hipGetLastError();
 }
 
 hipError_t dem_hydro_correct(const DemArgs& A, const TileArgs& T, double dt, hipStream_t s) {
     if (A.p.np == 0) return hipSuccess;
     k_hydro_correct<<<(unsigned)((64LL * A.p.np + 255) / 256), 256, 0, s>>>(A, T, dt);
-    return hipGetLastError();
-}
-
-hipError_t dem_correct_predict(const DemArgs& A, double dt, int write_kin, int par, hipStream_t s) {
-    if (A.p.np == 0) return hipSuccess;
-    k_correct_predict<<<nblk(A.p.np), 256, 0, s>>>(A, dt, write_kin, par);
     return hipGetLastError();
 }
 

@@ -190,7 +190,9 @@ static int coupled_step(psmdem_domain* D) {
             D->cur ^= 1;
             PairBufs B = D->pair_bufs(1);
             PSM_CHECK(dem_lists_kept(A, B, par, D->scan_tmp, D->s));
-            PSM_CHECK(dem_contacts(A, B, D->p.vp, D->p.wp, D->dt, D->scan_tmp, D->s));
+            // a substep that is followed by another runs its sums with the
+            // corrector and the next predictor
+            PSM_CHECK(dem_contacts(A, B, D->p.vp, D->p.wp, D->dt, D->scan_tmp, D->s, last));
             if (last && D->d.fluid_on) {
                 D->timed_end(tk);
                 if ((rc = run_voxelize(D))) return rc;
@@ -200,7 +202,8 @@ static int coupled_step(psmdem_domain* D) {
             } else if (last) {
                 PSM_CHECK(dem_correct(A, D->dt, D->s));
             } else {
-                PSM_CHECK(dem_correct_predict(A, D->dt, sub + 1 == D->nsub ? 1 : 0, (int)(D->dem_sub & 1), D->s));
+                PSM_CHECK(dem_sum_correct_predict(A, B, D->dt, sub + 1 == D->nsub ? 1 : 0, (int)(D->dem_sub & 1),
+                                                  D->s));
             }
             D->timed_end(tk);
         }
