@@ -2,7 +2,9 @@
 // (Sec. 2.4: subdivision and distance-based methods; Sec. 3.2.3: at most k
 // solids per fluid cell) and the per-particle hydrodynamic reduction.
 // Compiled with -ffp-contract=off: the subdivision sample test decides an
-// integer count and is evaluated with separately rounded operations.
+// integer count and is evaluated with separately rounded operations.  The row
+// counting's root arithmetic (whose results only need to lie within the
+// margins it tests against) is contracted locally.
 //
 // Pipeline per coupled step:
 //   k_vox_parts    each particle's record (centre, rotation, extents, lattice box)
@@ -993,10 +995,14 @@ __device__ inline void row_inside(const VoxPart& P, const RowQ& q, const double*
                                   double bzz, double cyzz, double czzz, int* row, int& glo, int& ghi) {
     glo = 1;
     ghi = 0;
-    const double B = q.by * dy + bzz;
-    const double Cm1 = (q.cyy * dy * dy + cyzz * dy + czzz) - 1.0;
-    const double disc = B * B - q.A * Cm1;
-    const double tol = 1e-6 * (B * B + q.A * fabs(Cm1)) + 1e-10;
+    double B, disc, tol;
+    {
+#pragma clang fp contract(fast)
+        B = q.by * dy + bzz;
+        const double Cm1 = (q.cyy * dy * dy + cyzz * dy + czzz) - 1.0;
+        disc = B * B - q.A * Cm1;
+        tol = 1e-6 * (B * B + q.A * fabs(Cm1)) + 1e-10;
+    }
     if (disc <= -tol) return;  // the row misses it
     if (disc < tol) {          // a row grazing the surface: every sample
         for (int X = P.lo[0]; X <= P.hi[0]; ++X) {
@@ -1006,8 +1012,13 @@ __device__ inline void row_inside(const VoxPart& P, const RowQ& q, const double*
         }
         return;
     }
-    const double sq = sqrt(disc);
-    const double G1 = ((-B - sq) * q.iA - q.xl) * q.fns - 0.5, G2 = ((-B + sq) * q.iA - q.xl) * q.fns - 0.5;
+    double G1, G2;
+    {
+#pragma clang fp contract(fast)
+        const double sq = sqrt(disc);
+        G1 = ((-B - sq) * q.iA - q.xl) * q.fns - 0.5;
+        G2 = ((-B + sq) * q.iA - q.xl) * q.fns - 0.5;
+    }
     const double lo = fmax(floor(G1 + q.mt) + 1.0, 0.0), hi = fmin(ceil(G2 - q.mt) - 1.0, q.gmax);
     if (hi >= lo) {
         glo = (int)lo;
@@ -1113,14 +1124,23 @@ __global__ __launch_bounds__(VOX_T) void k_vox_rows(VoxArgs A) {
             const int Yr = it % by_, cz = (it / by_) % ns, Zr = it / (by_ * ns);
             const int Z = P.lo[2] + z0 + Zr, Y = P.lo[1] + Yr;
             const double dz = ((double)Z + off[cz]) - P.c[2];
-            const double bzz = q.bz * dz, czzz = q.czz * dz * dz, cyzz = 2.0 * q.cyz * dz;
-            const double a1 = 2.0 * q.by * bzz - q.A * cyzz;
-            const double a0 = bzz * bzz - q.A * (czzz - 1.0);
-            const double D = a1 * a1 - 4.0 * q.a2 * a0;
-            if (D < -(1e-9 * (a1 * a1 + 4.0 * fabs(q.a2 * a0)) + 1e-12)) continue;  // the plane misses it
-            const double sD = sqrt(D > 0.0 ? D : 0.0);
-            const double y1 = (-a1 + sD) / (2.0 * q.a2), y2 = (-a1 - sD) / (2.0 * q.a2);
-            const double ylo = fmin(y1, y2) - my, yhi = fmax(y1, y2) + my;
+            double bzz, czzz, cyzz, ylo, yhi;
+            bool miss;
+            {
+#pragma clang fp contract(fast)
+                bzz = q.bz * dz;
+                czzz = q.czz * dz * dz;
+                cyzz = 2.0 * q.cyz * dz;
+                const double a1 = 2.0 * q.by * bzz - q.A * cyzz;
+                const double a0 = bzz * bzz - q.A * (czzz - 1.0);
+                const double D = a1 * a1 - 4.0 * q.a2 * a0;
+                miss = D < -(1e-9 * (a1 * a1 + 4.0 * fabs(q.a2 * a0)) + 1e-12);
+                const double sD = sqrt(D > 0.0 ? D : 0.0);
+                const double y1 = (-a1 + sD) / (2.0 * q.a2), y2 = (-a1 - sD) / (2.0 * q.a2);
+                ylo = fmin(y1, y2) - my;
+                yhi = fmax(y1, y2) + my;
+            }
+            if (miss) continue;  // the plane misses it
             int* row = cnt_s + plane_cells * Zr + bx * Yr;
             if (NS > 0) {
                 int glo[NS > 0 ? NS : 1], ghi[NS > 0 ? NS : 1];
