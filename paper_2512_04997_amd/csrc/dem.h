@@ -4,6 +4,7 @@
 
 // particles up to this count take the fused single-workgroup substep kernel
 #define DEM_FUSED_MAX 2048
+#define DEM_ROWS_PER_WG 64  // particles per workgroup of the multi-launch row kernel
 
 struct DemArgs {
     GeoArgs g;
@@ -18,7 +19,8 @@ struct DemArgs {
     int* cell_fill;        // [ncell]
     int* cell_pid;         // [reg_cap] particle ids per cell, ascending
     long long reg_cap;
-    int* pcount;           // [np] pairs per row
+    unsigned long long* row_lb;  // [np / DEM_ROWS_PER_WG + 2] the row kernel's ticket counter and
+                                 // per-chunk status words (cleared by the cell histogram)
     double *cF, *cMi, *cMj;         // [3 pair_cap] force on i, torque on i, torque on j
     unsigned char* incontact;       // [pair_cap]
     int *col_count, *col_fill;      // [np]
@@ -84,12 +86,15 @@ hipError_t dem_columns(const DemArgs& A, const PairBufs& B, int* scan_tmp, hipSt
 hipError_t dem_count_columns(const DemArgs& A, const PairBufs& B, hipStream_t s);
 // multi-launch substeps that keep an unchanged list (A.list_run = A.list_flag + par)
 hipError_t dem_predict_keep(const DemArgs& A, double dt, int write_kin, int par, hipStream_t s);
-// the list of a multi-launch substep: rebuilt (cells, rows, columns) when
-// list_flag[par] is set, else kept (the list kernels return at once)
+// the list of a multi-launch substep: cells and rows rebuilt when
+// list_flag[par] is set, else kept (the list kernels return at once); the
+// column lists follow with dem_columns (gated the same way)
 hipError_t dem_lists_kept(const DemArgs& A, const PairBufs& B, int par, int* scan_tmp, hipStream_t s);
 // contacts of the pairs in B, then (sums) the per-particle sums
 hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, const double* ww, double dth,
                         int* scan_tmp, hipStream_t s, bool sums = true);
+// the per-particle sums of a substep whose contacts ran without them
+hipError_t dem_sums(const DemArgs& A, const PairBufs& B, hipStream_t s);
 // the per-particle sums of a substep whose contacts ran without them, its
 // corrector and the next substep's predictor (its parity par)
 hipError_t dem_sum_correct_predict(const DemArgs& A, const PairBufs& B, double dt, int write_kin, int par,

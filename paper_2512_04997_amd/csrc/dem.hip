@@ -206,7 +206,10 @@ __device__ inline int wall_count(const DemArgs& A, int i) {
 // An ellipsoid's constants for the iteration, formed once per evaluation: its
 // rotation R (body to world), 1 / a_k^2, and the curvature-radius weights
 // (b c / a^3, a c / b^3, a b / c^3), so that the iteration itself divides only
-// where a quotient of two iterates is needed.
+// where a quotient of two iterates is needed.  The iteration's two helpers
+// contract multiply-adds (the file is otherwise compiled without): they form an
+// approximation refined until it converges or the cap is met, and the
+// contact decision on its result is not an exact predicate of the inputs.
 struct EllShape {
     double R[9];
     double ia2[3];
@@ -226,6 +229,7 @@ __device__ inline void ell_shape(const double* q, const double* ax, EllShape& E)
 
 // local curvature radius rho and unit outward normal n at surface point p
 __device__ void ell_local(const double* c, const EllShape& E, const double* p, double* rho, double* n) {
+#pragma clang fp contract(fast)
     const double* R = E.R;
     double d[3] = {p[0] - c[0], p[1] - c[1], p[2] - c[2]};
     double xb[3];
@@ -242,6 +246,7 @@ __device__ void ell_local(const double* c, const EllShape& E, const double* p, d
 // t when far_positive, else the smaller; false on a miss
 __device__ bool ell_line_hit(const double* c, const EllShape& E, const double* s, const double* u, bool far_positive,
                              double* p) {
+#pragma clang fp contract(fast)
     const double* R = E.R;
     double d[3] = {s[0] - c[0], s[1] - c[1], s[2] - c[2]};
     double y0[3], ud[3];
@@ -587,32 +592,6 @@ __device__ inline void emit_walls(const DemArgs& A, int i, unsigned long long* o
             if (n < room) out[n] = ((unsigned long long)i << 32) | (unsigned)(np + f);
             ++n;
         }
-}
-
-template <bool ALL>
-__device__ void ph_paircount(const DemArgs& A, int i) {
-    const int n = (ALL ? pairs_all(A, i, nullptr, 0) : pairs_by_cells(A, i, nullptr, 0)) + wall_count(A, i);
-    A.pcount[i] = n;
-}
-
-template <bool ALL>
-__device__ void ph_pairemit(const DemArgs& A, const PairBufs& B, int i) {
-    const long long at = B.prow[i];
-    const long long room = A.pair_cap - at;
-    if (room < (long long)(B.prow[i + 1] - B.prow[i])) atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_PAIRS);
-    if (room <= 0) return;
-    unsigned long long* out = B.pairs + at;
-    const int n = ALL ? pairs_all(A, i, out, room) : pairs_by_cells(A, i, out, room);
-    emit_walls(A, i, out, room, n);
-    if (!ALL) {
-        const int m = n < room ? n : (int)room;
-        for (int u = 1; u < m; ++u)
-            for (int v = u; v > 0 && out[v] < out[v - 1]; --v) {
-                unsigned long long t = out[v];
-                out[v] = out[v - 1];
-                out[v - 1] = t;
-            }
-    }
 }
 
 __device__ inline long long find_prev(const PairBufs& B, unsigned long long key, long long n) {
@@ -1133,6 +1112,7 @@ __global__ void k_list_age(DemArgs A, int par) {
 __global__ void k_list_copy_hist(DemArgs A, PairBufs B, int par) {
     if (A.list_flag[par]) {
         GRID_LOOP(k, A.p.np) ph_hist(A, (int)k);
+        GRID_LOOP(u, (long long)A.p.np / DEM_ROWS_PER_WG + 2) A.row_lb[u] = 0ull;  // k_rows' tickets, status
         return;
     }
     if (*A.fused_age != 1) return;
@@ -1146,6 +1126,7 @@ __global__ void k_cells(DemArgs A) { GRID_LOOP(k, A.p.np) ph_cells(A, (int)k); }
 __global__ void k_hist(DemArgs A) {
     if (A.list_run && !*A.list_run) return;
     GRID_LOOP(k, A.p.np) ph_hist(A, (int)k);
+    GRID_LOOP(u, (long long)A.p.np / DEM_ROWS_PER_WG + 2) A.row_lb[u] = 0ull;  // k_rows' tickets, status
 }
 __global__ void k_scatter(DemArgs A) {
     if (A.list_run && !*A.list_run) return;
@@ -1214,94 +1195,154 @@ __device__ inline int wave_candidate(const DemArgs& A, int i, const AxCells& ri,
     return j;
 }
 
-#define PAIR_KEPT_MAX 256
 
 // Rows by groups of ROW_SEG lanes, several particles per wave: a row has a few
 // dozen candidates, so a whole wave per row would leave most lanes idle while
 // its chain of dependent loads (cells, cell lists, the partners' cells) runs.
 #define ROW_SEG 16
 
-__global__ __launch_bounds__(256) void k_paircount(DemArgs A) {
-    if (A.list_run && !*A.list_run) return;
-    const int lane = threadIdx.x & 63, sl = lane & (ROW_SEG - 1), sh = lane & ~(ROW_SEG - 1);
-    const unsigned long long seg = ((1ull << ROW_SEG) - 1ull) << sh;
-    const long long ng = (long long)gridDim.x * (blockDim.x / ROW_SEG);
-    for (long long ig = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / ROW_SEG; ig < A.p.np; ig += ng) {
-        const int i = (int)ig;
-        AxCells ri;
-        load_cells(A, i, ri);
-        WaveCells W;
-        wave_cells(A, ri, W);
-        int n = 0;
-        for (int f0 = 0; f0 < W.total; f0 += ROW_SEG) {
-            const int f = f0 + sl;
-            n += __popcll(__ballot(f < W.total && wave_candidate(A, i, ri, W, f) >= 0) & seg);
-        }
-        if (sl == 0) A.pcount[i] = n + wall_count(A, i);
+// Rows in one pass (counts, offsets, emission).  Workgroups take chunks of
+// DEM_ROWS_PER_WG consecutive particles in the order they start (a ticket);
+// a group of ROW_SEG lanes finds a row's partners (up to ROW_KEEP kept in LDS),
+// the chunk's counts are scanned, and the rows before the chunk come from the
+// chunks before it: each publishes its own total and then its running sum in a
+// status word (decoupled look-back), so a chunk waits only on chunks that
+// started before it.  A wait past its bound raises PSM_FLAG_NEIGH (the step is
+// reported as failed) instead of hanging.  Then each row is emitted: partners
+// ascending (a partner's place is the number of partners below it), then the
+// wall candidates; a row of more than ROW_KEEP partners is gathered again by
+// one lane and ordered in place.  Every stored pair with a particle as second
+// member counts in that particle's column (the column lists of the DEM sums).
+#define ROW_KEEP 32
+static_assert(DEM_ROWS_PER_WG == 64, "the chunk scan takes one wave");
+
+__device__ inline unsigned long long row_wait(const unsigned long long* p, bool& ok) {
+    unsigned long long v = 0;
+    for (unsigned it = 0; ok; ++it) {
+        v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (v) break;
+        if (it > (1u << 22)) ok = false;
+        __builtin_amdgcn_s_sleep(1);
     }
+    return v;
 }
 
-// row i's emission by one lane group (kept: the group's LDS partner buffer)
-__device__ inline void emit_row(const DemArgs& A, const PairBufs& B, int i, int* kept) {
-    const int lane = threadIdx.x & 63, sl = lane & (ROW_SEG - 1), sh = lane & ~(ROW_SEG - 1);
+__global__ __launch_bounds__(256) void k_rows(DemArgs A, PairBufs B) {
+    if (A.list_run && !*A.list_run) return;
+    __shared__ int ticket_s;
+    __shared__ int cnt_s[DEM_ROWS_PER_WG], wall_s[DEM_ROWS_PER_WG], off_s[DEM_ROWS_PER_WG + 1];
+    __shared__ int kept_s[DEM_ROWS_PER_WG][ROW_KEEP];
+    __shared__ long long base_s;
+    const int tid = threadIdx.x, lane = tid & 63, sl = lane & (ROW_SEG - 1), sh = lane & ~(ROW_SEG - 1);
+    const int grp = tid / ROW_SEG, ngrp = 256 / ROW_SEG;
     const unsigned long long seg = ((1ull << ROW_SEG) - 1ull) << sh;
     const unsigned long long lanes_below = ((1ull << sl) - 1ull) << sh;
-    const long long at = B.prow[i];
-    const long long room = A.pair_cap - at;
-    if (sl == 0 && room < (long long)(B.prow[i + 1] - B.prow[i]))
-        atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_PAIRS);
-    if (room <= 0) return;
-    unsigned long long* out = B.pairs + at;
-    AxCells ri;
-    load_cells(A, i, ri);
-    WaveCells W;
-    wave_cells(A, ri, W);
-    // kept partners gathered in the group's LDS
-    int nk = 0;
-    for (int f0 = 0; f0 < W.total; f0 += ROW_SEG) {
-        const int f = f0 + sl;
-        const int j = f < W.total ? wave_candidate(A, i, ri, W, f) : -1;
-        const unsigned long long m = __ballot(j >= 0) & seg;
-        const int pos = nk + __popcll(m & lanes_below);
-        if (j >= 0 && pos < PAIR_KEPT_MAX) kept[pos] = j;
-        nk += __popcll(m);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // every stored pair with a particle as second member counts in that particle's
-    // column (the column lists of the DEM sums)
-    if (nk <= PAIR_KEPT_MAX) {
-        // partners are distinct: a partner's place is the number below it
-        for (int e = sl; e < nk; e += ROW_SEG) {
-            const int j = kept[e];
-            int below = 0;
-            for (int v = 0; v < nk; ++v) below += kept[v] < j ? 1 : 0;
-            if (below < room) {
-                out[below] = ((unsigned long long)i << 32) | (unsigned)j;
-                atomicAdd(&A.col_count[j], 1);
+    const int np = A.p.np;
+    unsigned long long* st = A.row_lb;  // [0] tickets, [1 + c] status of chunk c
+    if (tid == 0) ticket_s = (int)atomicAdd(&st[0], 1ull);
+    __syncthreads();
+    const int c = ticket_s;
+    const int i0 = c * DEM_ROWS_PER_WG;
+    // 1: each row's partners
+    for (int r = grp; r < DEM_ROWS_PER_WG; r += ngrp) {
+        const int i = i0 + r;
+        int nk = 0, nw = 0;
+        if (i < np) {
+            AxCells ri;
+            load_cells(A, i, ri);
+            WaveCells W;
+            wave_cells(A, ri, W);
+            for (int f0 = 0; f0 < W.total; f0 += ROW_SEG) {
+                const int f = f0 + sl;
+                const int j = f < W.total ? wave_candidate(A, i, ri, W, f) : -1;
+                const unsigned long long m = __ballot(j >= 0) & seg;
+                const int pos = nk + __popcll(m & lanes_below);
+                if (j >= 0 && pos < ROW_KEEP) kept_s[r][pos] = j;
+                nk += __popcll(m);
             }
+            nw = wall_count(A, i);
         }
-        if (sl == 0) emit_walls(A, i, out, room, nk);
-    } else if (sl == 0) {
-        // very long rows: the serial emission with an in-place sort
-        ph_pairemit<false>(A, B, i);
-        const long long m = room < (long long)nk ? room : (long long)nk;
-        for (long long e = 0; e < m; ++e) atomicAdd(&A.col_count[(int)(out[e] & 0xffffffffu)], 1);
+        if (sl == 0) {
+            cnt_s[r] = nk;
+            wall_s[r] = nw;
+        }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    __syncthreads();
+    // 2: offsets within the chunk
+    if (tid < 64) {
+        const int v = cnt_s[tid] + wall_s[tid];
+        int x = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        off_s[tid] = x - v;
+        if (tid == 63) off_s[DEM_ROWS_PER_WG] = x;
+    }
+    __syncthreads();
+    // 3: the rows of the chunks before this one
+    if (tid == 0) {
+        const unsigned long long T = (unsigned long long)off_s[DEM_ROWS_PER_WG];
+        const unsigned long long AGG = 1ull << 62, INC = 2ull << 62, VAL = AGG - 1ull;
+        long long ex = 0;
+        bool ok = true;
+        if (c > 0) {
+            __hip_atomic_store(&st[1 + c], AGG | T, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int k = c - 1; k >= 0; --k) {
+                const unsigned long long v = row_wait(&st[1 + k], ok);
+                if (!ok) break;
+                ex += (long long)(v & VAL);
+                if ((v & ~VAL) == INC) break;
+            }
+            if (!ok) atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_NEIGH);
+        }
+        __hip_atomic_store(&st[1 + c], INC | (unsigned long long)(ex + (long long)T), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        base_s = ex;
+    }
+    __syncthreads();
+    const long long base = base_s;
+    if (tid < DEM_ROWS_PER_WG && i0 + tid < np) B.prow[i0 + tid] = (int)(base + off_s[tid]);
+    if (tid == 0 && i0 + DEM_ROWS_PER_WG >= np) B.prow[np] = (int)(base + off_s[np - i0]);
+    // 4: emission
+    for (int r = grp; r < DEM_ROWS_PER_WG; r += ngrp) {
+        const int i = i0 + r;
+        if (i >= np) continue;
+        const long long at = base + off_s[r];
+        const long long room = A.pair_cap - at;
+        const int nk = cnt_s[r];
+        if (sl == 0 && room < (long long)(nk + wall_s[r])) atomicOr(&A.ctr->flags, (unsigned long long)PSM_FLAG_PAIRS);
+        if (room <= 0) continue;
+        unsigned long long* out = B.pairs + at;
+        if (nk <= ROW_KEEP) {
+            const int* kept = kept_s[r];
+            for (int e = sl; e < nk; e += ROW_SEG) {
+                const int j = kept[e];
+                int below = 0;
+                for (int v = 0; v < nk; ++v) below += kept[v] < j ? 1 : 0;
+                if (below < room) {
+                    out[below] = ((unsigned long long)i << 32) | (unsigned)j;
+                    atomicAdd(&A.col_count[j], 1);
+                }
+            }
+            if (sl == 0) emit_walls(A, i, out, room, nk);
+        } else if (sl == 0) {
+            // a long row: its partners again in cell order, ordered in place
+            const int n = pairs_by_cells(A, i, out, room);
+            emit_walls(A, i, out, room, n);
+            const int m = n < room ? n : (int)room;
+            for (int u = 1; u < m; ++u)
+                for (int v = u; v > 0 && out[v] < out[v - 1]; --v) {
+                    const unsigned long long t = out[v];
+                    out[v] = out[v - 1];
+                    out[v - 1] = t;
+                }
+            for (int e = 0; e < m; ++e) atomicAdd(&A.col_count[(int)(out[e] & 0xffffffffu)], 1);
+        }
+    }
 }
 
-__global__ __launch_bounds__(256) void k_pairemit(DemArgs A, PairBufs B) {
-    if (A.list_run && !*A.list_run) return;
-    __shared__ int kept_s[256 / ROW_SEG][PAIR_KEPT_MAX];
-    int* kept = kept_s[threadIdx.x / ROW_SEG];
-    const long long ng = (long long)gridDim.x * (blockDim.x / ROW_SEG);
-    for (long long ig = ((long long)blockIdx.x * blockDim.x + threadIdx.x) / ROW_SEG; ig < A.p.np; ig += ng)
-        emit_row(A, B, (int)ig, kept);
-}
 // Contacts of the substep's pairs.  With ellipsoids, the pairs that need the
 // iterated equivalent spheres (ellipsoid pairs within bounding-sphere reach,
 // a small share of the candidates) are queued, one atomic per wave, and
@@ -2099,10 +2140,8 @@ hipError_t dem_lists_kept(const DemArgs& A, const PairBufs& B, int par, int* sca
     if ((e = psm_scan(A.cell_count, A.cell_start, A.ncell, scan_tmp, s, A.list_run)) != hipSuccess) return e;
     k_scatter<<<nblk_list(A.p.np), 256, 0, s>>>(A);
     k_cellsort<<<nblk_list(A.ncell), 256, 0, s>>>(A);
-    k_paircount<<<nblk_list(64LL * A.p.np), 256, 0, s>>>(A);
-    if ((e = psm_scan(A.pcount, B.prow, A.p.np, scan_tmp, s, A.list_run)) != hipSuccess) return e;
-    k_pairemit<<<nblk_list(64LL * A.p.np), 256, 0, s>>>(A, B);
-    return dem_columns(A, B, scan_tmp, s);
+    k_rows<<<(unsigned)((A.p.np + DEM_ROWS_PER_WG - 1) / DEM_ROWS_PER_WG), 256, 0, s>>>(A, B);
+    return hipGetLastError();
 }
 
 // the column lists of the current rows from their column counts (counted by
@@ -2124,9 +2163,7 @@ hipError_t dem_lists(const DemArgs& A, const PairBufs& B, int* scan_tmp, hipStre
     if ((e = psm_scan(A.cell_count, A.cell_start, A.ncell, scan_tmp, s)) != hipSuccess) return e;
     k_scatter<<<nblk_list(A.p.np), 256, 0, s>>>(A);
     k_cellsort<<<nblk_list(A.ncell), 256, 0, s>>>(A);
-    k_paircount<<<nblk_list(64LL * A.p.np), 256, 0, s>>>(A);
-    if ((e = psm_scan(A.pcount, B.prow, A.p.np, scan_tmp, s)) != hipSuccess) return e;
-    k_pairemit<<<nblk_list(64LL * A.p.np), 256, 0, s>>>(A, B);
+    k_rows<<<(unsigned)((A.p.np + DEM_ROWS_PER_WG - 1) / DEM_ROWS_PER_WG), 256, 0, s>>>(A, B);
     return dem_columns(A, B, scan_tmp, s);
 }
 
@@ -2151,6 +2188,12 @@ hipError_t dem_contacts(const DemArgs& A, const PairBufs& B, const double* vv, c
         k_contacts<false><<<nbc, 128, 0, s>>>(A, B, vv, ww, dth);
     }
     if (sums) k_sum_wave<<<nblk(64LL * A.p.np), 256, 0, s>>>(A, B);
+    return hipGetLastError();
+}
+
+hipError_t dem_sums(const DemArgs& A, const PairBufs& B, hipStream_t s) {
+    if (A.p.np == 0) return hipSuccess;
+    k_sum_wave<<<nblk(64LL * A.p.np), 256, 0, s>>>(A, B);
     return hipGetLastError();
 }
 

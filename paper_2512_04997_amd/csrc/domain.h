@@ -48,7 +48,7 @@ struct psmdem_domain {
     long long dem_sub = 0;  // multi-launch substeps run (their parity indexes list_flag)
     int *col_count = nullptr, *col_fill = nullptr, *col_start = nullptr, *col_list = nullptr;
     long long reg_cap = 0;
-    int* pcount = nullptr;
+    unsigned long long* row_lb = nullptr;
     int* prow[2] = {nullptr, nullptr};
     unsigned long long* pairs[2] = {nullptr, nullptr};
     double* hist[2] = {nullptr, nullptr};
@@ -148,7 +148,7 @@ struct psmdem_domain {
         A.cell_fill = cell_fill;
         A.cell_pid = cell_pid;
         A.reg_cap = reg_cap;
-        A.pcount = pcount;
+        A.row_lb = row_lb;
         A.cF = cF;
         A.cMi = cMi;
         A.cMj = cMj;

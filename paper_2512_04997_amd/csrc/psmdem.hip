@@ -190,9 +190,11 @@ static int coupled_step(psmdem_domain* D) {
             D->cur ^= 1;
             PairBufs B = D->pair_bufs(1);
             PSM_CHECK(dem_lists_kept(A, B, par, D->scan_tmp, D->s));
+            PSM_CHECK(dem_columns(A, B, D->scan_tmp, D->s));
+            PSM_CHECK(dem_contacts(A, B, D->p.vp, D->p.wp, D->dt, D->scan_tmp, D->s, false));
             // a substep that is followed by another runs its sums with the
             // corrector and the next predictor
-            PSM_CHECK(dem_contacts(A, B, D->p.vp, D->p.wp, D->dt, D->scan_tmp, D->s, last));
+            if (last) PSM_CHECK(dem_sums(A, B, D->s));
             if (last && D->d.fluid_on) {
                 D->timed_end(tk);
                 if ((rc = run_voxelize(D))) return rc;
@@ -437,7 +439,7 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
     D->cell_start = (int*)A(sizeof(int) * (D->ncell + 1));
     D->cell_pid = (int*)A(sizeof(int) * D->reg_cap);
     D->pair_cap = d.pair_capacity > 0 ? d.pair_capacity : 32LL * np + 1024;
-    D->pcount = (int*)A(sizeof(int) * std::max(np, 1));
+    D->row_lb = (unsigned long long*)A(sizeof(unsigned long long) * (np / DEM_ROWS_PER_WG + 2));
     for (int b = 0; b < 2; ++b) {
         D->prow[b] = (int*)A(sizeof(int) * (np + 1));
         D->pairs[b] = (unsigned long long*)A(sizeof(unsigned long long) * D->pair_cap);
