@@ -67,6 +67,8 @@ struct psmdem_domain {
     long long box_stride = 0;
     void* vpart = nullptr;
     void* tile_rec = nullptr;
+    void* btab = nullptr;         // subdivision method: B per inside-sample count (compute type)
+    double* betatab = nullptr;    // and beta
     int* scan_tmp = nullptr;
     DevCounters* ctr = nullptr;
 
@@ -215,6 +217,8 @@ struct psmdem_domain {
         A.box_stride = box_stride;
         A.vpart = vpart;
         A.tile_rec = tile_rec;
+        A.btab = btab;
+        A.betatab = betatab;
         A.ctr = ctr;
         return A;
     }

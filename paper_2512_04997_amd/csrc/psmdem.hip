@@ -486,6 +486,11 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
     D->tile_fill = (int*)A(sizeof(int) * g.ntiles);
     if (np > 0) D->vpart = A(vox_part_bytes() * (size_t)np);
     if (np > 0 && vox_tile_rec_bytes(g.ntiles)) D->tile_rec = A(vox_tile_rec_bytes(g.ntiles) * (size_t)t.cap);
+    if (np > 0 && d.sf_method == 0) {
+        const size_t nt = (size_t)d.sf_subdiv * d.sf_subdiv * d.sf_subdiv + 1;
+        D->btab = A((D->prec == 0 ? 8 : 4) * nt);
+        D->betatab = (double*)A(sizeof(double) * nt);
+    }
     // subdivision method: one count box per particle, sized for the largest
     // lattice box (per axis at most floor(2 r_b + 2e-6) + 2 cells)
     if (np > 0 && d.sf_method == 0) {
@@ -574,6 +579,11 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
     if (rc) {
         delete D;
         psm_set_error("initial copies failed");
+        return PSMDEM_E_HIP;
+    }
+    if (D->btab && vox_fill_tables(D->btab, D->betatab, d.sf_subdiv, d.tau, D->prec == 0, D->s) != hipSuccess) {
+        delete D;
+        psm_set_error("init kernel failed");
         return PSMDEM_E_HIP;
     }
     if (lbm_init(D->f, D->prec, D->N, d.rho0, D->s) != hipSuccess) {

@@ -21,6 +21,9 @@ struct VoxArgs {
     long long box_stride;
     void* vpart;                 // [np] per-step particle records of the tile kernels (vox_part_bytes
                                  // each), formed by vox_register; null: each tile forms its own
+    const void* btab;            // [ns^3 + 1] subdivision method: B of each inside-sample count, in the
+                                 // compute type, and beta (betatab); null: formed per slot
+    const double* betatab;
     void* tile_rec;              // [t.cap] selection record per registration slot (vox_tile_rec_bytes
                                  // each), written by the tile sort from vpart; null: gathered per tile
     DevCounters* ctr;
@@ -38,6 +41,10 @@ hipError_t vox_voxelize(const VoxArgs& A, int ctype_double, hipStream_t s);
 // beta when A.t.slot_beta is set
 hipError_t vox_select(const VoxArgs& A, int ctype_double, hipStream_t s);
 hipError_t vox_reduce_hydro(const VoxArgs& A, hipStream_t s);
+// the subdivision method's tables of B and beta per inside-sample count (ns^3 + 1
+// entries each; btab in double when ctype_double, else float), from the same
+// expressions the selection would evaluate per slot
+hipError_t vox_fill_tables(void* btab, double* betatab, int ns, double tau, int ctype_double, hipStream_t s);
 // bytes of one particle record (VoxArgs::vpart)
 size_t vox_part_bytes();
 // bytes of one selection record (VoxArgs::tile_rec) on a lattice of ntiles

@@ -1180,6 +1180,22 @@ __global__ __launch_bounds__(VOX_T) void k_vox_rows(VoxArgs A) {
     }
 }
 
+// B of a solid fraction beta (Sec. 2.3): beta (tau - 1/2) / ((1 - beta) + (tau - 1/2)), tm = tau - 1/2
+template <typename C>
+__device__ inline C sel_B(double beta, double tm) {
+    return (C)(beta * tm / ((1.0 - beta) + tm));
+}
+
+// the tables of B and beta per inside-sample count n = 0 .. n3
+template <typename C>
+__global__ void k_fill_tables(C* btab, double* betatab, int n3, double tau) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n > n3) return;
+    const double beta = (double)n / (double)n3;
+    btab[n] = sel_B<C>(beta, tau - 0.5);
+    betatab[n] = beta;
+}
+
 // Phase C of the subdivision method from the count boxes, on integer keys:
 // an entry of candidate u with count n > 0 is the key n * 256 + (255 - u), so
 // that a larger key is a larger beta = n / ns^3 (the division is monotone and
@@ -1263,9 +1279,15 @@ __device__ inline void select_counts(const VoxArgs& A, const SelPart* sp, long l
 #pragma unroll
         for (int q = 0; q < 4; ++q)
             if (q < nk) {
-                const double beta = (double)(o[q] & 0xffffu) / n3;
-                Bout[q * plane + cell] = (C)(beta * tm / ((1.0 - beta) + tm));
-                if (A.t.slot_beta) A.t.slot_beta[q * plane + cell] = beta;
+                const unsigned n = o[q] & 0xffffu;
+                if (A.btab) {
+                    Bout[q * plane + cell] = ((const C*)A.btab)[n];
+                    if (A.t.slot_beta) A.t.slot_beta[q * plane + cell] = A.betatab[n];
+                } else {
+                    const double beta = (double)n / n3;
+                    Bout[q * plane + cell] = sel_B<C>(beta, tm);
+                    if (A.t.slot_beta) A.t.slot_beta[q * plane + cell] = beta;
+                }
             }
     }
     add_entry_counts(A, t, my_e, my_d, cnt_e, cnt_d);
@@ -1417,6 +1439,14 @@ hipError_t vox_voxelize_batch(const VoxArgs* jobs, const int2* map, long long nm
 hipError_t vox_reduce_hydro(const VoxArgs& A, hipStream_t s) {
     if (A.p.np == 0) return hipSuccess;
     k_reduce_hydro<<<nblk(64LL * A.p.np), 256, 0, s>>>(A);
+    return hipGetLastError();
+}
+
+hipError_t vox_fill_tables(void* btab, double* betatab, int ns, double tau, int ctype_double, hipStream_t s) {
+    const int n3 = ns * ns * ns;
+    const unsigned nb = (unsigned)((n3 + 1 + 255) / 256);
+    if (ctype_double) k_fill_tables<double><<<nb, 256, 0, s>>>((double*)btab, betatab, n3, tau);
+    else k_fill_tables<float><<<nb, 256, 0, s>>>((float*)btab, betatab, n3, tau);
     return hipGetLastError();
 }
 
