@@ -66,7 +66,6 @@ struct psmdem_domain {
     unsigned short* vbox = nullptr;
     long long box_stride = 0;
     void* vpart = nullptr;
-    void* tile_rec = nullptr;
     void* btab = nullptr;         // subdivision method: B per inside-sample count (compute type)
     double* betatab = nullptr;    // and beta
     int* scan_tmp = nullptr;
@@ -216,7 +215,6 @@ struct psmdem_domain {
         A.vbox = vbox;
         A.box_stride = box_stride;
         A.vpart = vpart;
-        A.tile_rec = tile_rec;
         A.btab = btab;
         A.betatab = betatab;
         A.ctr = ctr;

@@ -485,7 +485,6 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
     D->tile_count = (int*)A(sizeof(int) * g.ntiles);
     D->tile_fill = (int*)A(sizeof(int) * g.ntiles);
     if (np > 0) D->vpart = A(vox_part_bytes() * (size_t)np);
-    if (np > 0 && vox_tile_rec_bytes(g.ntiles)) D->tile_rec = A(vox_tile_rec_bytes(g.ntiles) * (size_t)t.cap);
     if (np > 0 && d.sf_method == 0) {
         const size_t nt = (size_t)d.sf_subdiv * d.sf_subdiv * d.sf_subdiv + 1;
         D->btab = A((D->prec == 0 ? 8 : 4) * nt);

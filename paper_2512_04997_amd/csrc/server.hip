@@ -209,7 +209,6 @@ int upload_tables(psmdem_server* S) {
         J.fluid = 1;
         vox[i] = D->vox_args();
         vox[i].vpart = nullptr;  // the one-workgroup voxelisation forms its own particle records
-        vox[i].tile_rec = nullptr;
         vox[i].t.tile_ed = nullptr;  // and counts its entries in the job's step counters
         lbm[i] = D->lbm_args();
         const int nt = (int)D->geo.ntiles;

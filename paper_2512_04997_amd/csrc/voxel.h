@@ -24,8 +24,6 @@ struct VoxArgs {
     const void* btab;            // [ns^3 + 1] subdivision method: B of each inside-sample count, in the
                                  // compute type, and beta (betatab); null: formed per slot
     const double* betatab;
-    void* tile_rec;              // [t.cap] selection record per registration slot (vox_tile_rec_bytes
-                                 // each), written by the tile sort from vpart; null: gathered per tile
     DevCounters* ctr;
 };
 
@@ -47,8 +45,5 @@ hipError_t vox_reduce_hydro(const VoxArgs& A, hipStream_t s);
 hipError_t vox_fill_tables(void* btab, double* betatab, int ns, double tau, int ctype_double, hipStream_t s);
 // bytes of one particle record (VoxArgs::vpart)
 size_t vox_part_bytes();
-// bytes of one selection record (VoxArgs::tile_rec) on a lattice of ntiles
-// tiles; 0 where the selection kernel orders the lists itself (none kept)
-size_t vox_tile_rec_bytes(long long ntiles);
 // cells of a count box's x-y plane the row-counting kernel holds (per z-slab)
 size_t vox_box_cells_max();

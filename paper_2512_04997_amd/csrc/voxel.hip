@@ -11,8 +11,7 @@
 //   k_vox_count    tiles touched by each particle's lattice box (count + tile histogram)
 //   (scans)        emission offsets per particle, list offsets per tile
 //   k_vox_scatter  counting-sort scatter of (pid, emission index) into tiles
-//   (k_tile_sort)  order each tile's list by pid; inverse map emission -> position;
-//                  each entry's selection record beside it
+//   (k_tile_sort)  order each tile's list by pid; inverse map emission -> position
 //                  (lattices of up to VOX_SORT_IN_TILE_MAX tiles do this in the
 //                  select kernel instead)
 //   k_vox_rows     subdivision method: one workgroup per particle counts the
@@ -121,15 +120,43 @@ __device__ inline int axis_tiles(int lo, int hi, int n, int T, int periodic, int
     return cnt;
 }
 
+// per-particle data staged in LDS for a tile (8-byte words, copied as such)
+struct VoxPart {
+    double c[3];
+    double ax[3];
+    double R[9];
+    double inv[3];
+    double e[3];
+    double r[3];   // ellipsoids: body-frame half-widths of a cell's sample box, h sum_r |R_rk|
+    int lo[3], hi[3];
+    int shape;
+    int pid;
+};
+static_assert(sizeof(VoxPart) % 8 == 0, "VoxPart is copied in 8-byte words");
+
 struct TileSet {
     int tx[VOX_AXIS_MAX], ty[VOX_AXIS_MAX], tz[VOX_AXIS_MAX];
     int nx, ny, nz;
 };
 
-// returns true for a blown-up particle (no tiles)
+// returns true for a blown-up particle (no tiles); the lattice box comes from
+// the step's particle record when there is one (formed at the start of the
+// registration), else it is formed here
 __device__ inline bool particle_tiles(const VoxArgs& A, int k, TileSet& S) {
     int lo[3], hi[3];
-    const bool far = lattice_box(A, k, lo, hi);
+    bool far;
+    if (A.vpart) {
+        const VoxPart& V = ((const VoxPart*)A.vpart)[k];
+        const int n[3] = {A.g.nx, A.g.ny, A.g.nz};
+        far = false;
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = V.lo[a];
+            hi[a] = V.hi[a];
+            far = far || !(V.c[a] >= -(double)n[a] && V.c[a] < 2.0 * (double)n[a]);
+        }
+    } else {
+        far = lattice_box(A, k, lo, hi);
+    }
     S.nx = axis_tiles(lo[0], hi[0], A.g.nx, PSM_TX, A.g.periodic[0], S.tx);
     S.ny = axis_tiles(lo[1], hi[1], A.g.ny, PSM_TY, A.g.periodic[1], S.ty);
     S.nz = axis_tiles(lo[2], hi[2], A.g.nz, PSM_TZ, A.g.periodic[2], S.tz);
@@ -295,19 +322,6 @@ __global__ __launch_bounds__(VOX_RT) void k_vox_register_batch(const VoxArgs* __
     }
 }
 
-// per-particle data staged in LDS for a tile (8-byte words, copied as such)
-struct VoxPart {
-    double c[3];
-    double ax[3];
-    double R[9];
-    double inv[3];
-    double e[3];
-    double r[3];   // ellipsoids: body-frame half-widths of a cell's sample box, h sum_r |R_rk|
-    int lo[3], hi[3];
-    int shape;
-    int pid;
-};
-static_assert(sizeof(VoxPart) % 8 == 0, "VoxPart is copied in 8-byte words");
 
 // what the selection needs of a candidate (a quarter of a full record)
 struct SelPart {
@@ -329,27 +343,13 @@ __device__ inline void sel_of(const VoxPart& V, SelPart& P) {
     P.pid = V.pid;
 }
 
-// orders each tile's list, then clears the tile's counters for the next step;
-// with tile_rec, also writes each entry's selection record beside it (from the
-// step's particle records), so that the selection reads its candidates in one
-// contiguous load instead of a list load and a gather
+// orders each tile's list, then clears the tile's counters for the next step
 __global__ void k_tile_sort(VoxArgs A) {
     long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= A.g.ntiles) return;
     reg_sort(A, t);
     A.tile_count[t] = 0;
     A.tile_fill[t] = 0;
-    if (!A.tile_rec) return;
-    long long s0 = A.t.tile_start[t], s1 = A.t.tile_start[t + 1];
-    if (s1 > A.t.cap) s1 = A.t.cap;
-    SelPart* out = (SelPart*)A.tile_rec;
-    for (long long u = s0; u < s1; ++u) {
-        int k = (int)(A.t.tile_list[u] >> 32);
-        if (k >= A.p.np) k = 0;
-        SelPart P;
-        sel_of(((const VoxPart*)A.vpart)[k], P);
-        out[u] = P;
-    }
 }
 
 
@@ -1311,18 +1311,10 @@ __global__ __launch_bounds__(VOX_T) void k_vox_select(VoxArgs A) {
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     if (tid == 0) { cnt_e = 0; cnt_d = 0; }
     if (tid < A.ns) off[tid] = (double)(2 * tid + 1) / (double)(2 * A.ns);
-    if (!SORT && A.tile_rec) {
-        // the records beside the sorted list, copied in 8-byte words
-        const unsigned long long* src = (const unsigned long long*)((const SelPart*)A.tile_rec + R.s0);
-        unsigned long long* dst = (unsigned long long*)sp;
-        const int words = R.count * (int)(sizeof(SelPart) / 8);
-        for (int w = tid; w < words; w += VOX_T) dst[w] = src[w];
-    } else {
-        for (int u = tid; u < R.count; u += VOX_T) {
-            int k = (int)((keys ? keys[u] : A.t.tile_list[R.s0 + u]) >> 32);
-            if (k >= A.p.np) k = 0;
-            sel_of(((const VoxPart*)A.vpart)[k], sp[u]);
-        }
+    for (int u = tid; u < R.count; u += VOX_T) {
+        int k = (int)((keys ? keys[u] : A.t.tile_list[R.s0 + u]) >> 32);
+        if (k >= A.p.np) k = 0;
+        sel_of(((const VoxPart*)A.vpart)[k], sp[u]);
     }
     __syncthreads();
     const double slo = off[0], shi = off[A.ns - 1];  // first and last sample offset
@@ -1451,6 +1443,5 @@ hipError_t vox_fill_tables(void* btab, double* betatab, int ns, double tau, int 
 }
 
 size_t vox_part_bytes() { return sizeof(VoxPart); }
-size_t vox_tile_rec_bytes(long long ntiles) { return ntiles > VOX_SORT_IN_TILE_MAX ? sizeof(SelPart) : 0; }
 size_t vox_box_cells_max() { return VOX_BOX_LDS; }
 
