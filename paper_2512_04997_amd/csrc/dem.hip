@@ -1517,13 +1517,56 @@ __global__ void k_correct(DemArgs A, double dt) { GRID_LOOP(k, A.p.np) ph_correc
 
 // after the LBM-PSM pass: each particle's hydrodynamic sums (one wave), then
 // its corrector (lane 0, which stored the sums)
+// the hydrodynamic sums and the corrector, HYD_G lanes per particle: the lanes
+// fetch HYD_G partials at a time into the group's LDS buffer and the group's
+// first lane adds them in emission order (a particle of the multi-launch path
+// touches a few tiles, so a whole wave per particle would idle most lanes)
+#define HYD_G 16
 __global__ __launch_bounds__(256) void k_hydro_correct(DemArgs A, TileArgs T, double dt) {
-    __shared__ double buf[4][64 * 6];
-    const int k = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    const int lane = threadIdx.x & 63;
+    __shared__ double buf[256 / HYD_G][HYD_G * 6];
+    const int k = (int)(((long long)blockIdx.x * blockDim.x + threadIdx.x) / HYD_G);
+    const int lane = threadIdx.x & 63, gl = lane & (HYD_G - 1), sh = lane & ~(HYD_G - 1);
     if (k >= A.p.np) return;
-    psm_reduce_hydro_wave(T, A.p, k, lane, buf[threadIdx.x >> 6]);
-    if (lane == 0) ph_correct(A, k, dt);
+    double* b = buf[threadIdx.x / HYD_G];
+    const int e0 = T.voff[k], e1 = T.voff[k + 1];
+    double F[3] = {0.0, 0.0, 0.0}, M[3] = {0.0, 0.0, 0.0};
+    for (int b0 = e0; b0 < e1 && b0 < T.cap; b0 += HYD_G) {
+        const int e = b0 + gl;
+        bool ok = false;
+        if (e < e1 && e < T.cap) {
+            const long long s = T.vinv[e];
+            ok = s >= 0 && s < T.cap;
+            if (ok)
+#pragma unroll
+                for (int c = 0; c < 6; ++c) b[6 * gl + c] = T.partial[6 * s + c];
+        }
+        const unsigned okm = (unsigned)((__ballot(ok) >> sh) & ((1ull << HYD_G) - 1ull));
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (gl == 0) {
+            const int m = e1 - b0 < HYD_G ? e1 - b0 : HYD_G;
+            for (int j = 0; j < m; ++j)
+                if ((okm >> j) & 1u)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        F[c] -= b[6 * j + c];
+                        M[c] -= b[6 * j + 3 + c];
+                    }
+        }
+        // the buffer is refilled only after the group's first lane has read it
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (gl == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            A.p.fh[3 * k + c] = F[c];
+            A.p.mh[3 * k + c] = M[c];
+        }
+        ph_correct(A, k, dt);
+    }
 }
 __global__ void k_initial_accel(DemArgs A) { GRID_LOOP(k, A.p.np) ph_initial_accel(A, (int)k); }
 
@@ -2206,7 +2249,7 @@ hipError_t dem_sum_correct_predict(const DemArgs& A, const PairBufs& B, double d
 
 hipError_t dem_hydro_correct(const DemArgs& A, const TileArgs& T, double dt, hipStream_t s) {
     if (A.p.np == 0) return hipSuccess;
-    k_hydro_correct<<<(unsigned)((64LL * A.p.np + 255) / 256), 256, 0, s>>>(A, T, dt);
+    k_hydro_correct<<<(unsigned)(((long long)HYD_G * A.p.np + 255) / 256), 256, 0, s>>>(A, T, dt);
     return hipGetLastError();
 }
 
