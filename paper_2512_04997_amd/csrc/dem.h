@@ -33,8 +33,9 @@ struct DemArgs {
     double wall_u[6][3];
     double gravity[3];
     int ellipsoids;        // any particle is an ellipsoid (else the sphere-only kernels run)
-    int* fused_age;        // [1] substeps the pair list has been kept (pc holds the cells it was built
-                           // from, the wall candidates in pc's last word); -1: rebuild
+    int* fused_age;        // [2] substeps the pair list has been kept (pc holds the cells it was built
+                           // from, the wall candidates in pc's last word); -1: rebuild.  The fused
+                           // kernel uses word 0, the multi-launch path one word per substep parity
     unsigned char* fz;     // [dem_fused_save_bytes()] the fused kernel's skip state of its kept list,
                            // saved at the end of a launch for the next one (null: not kept)
     int* list_flag;        // [2] multi-launch path: the list changed in this substep (by substep parity)

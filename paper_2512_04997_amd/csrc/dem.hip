@@ -1099,23 +1099,27 @@ __global__ __launch_bounds__(256) void k_sum_correct_predict(DemArgs A, PairBufs
     }
 }
 
-// the substep's decision: rebuild when something changed or no list is kept
-__global__ void k_list_age(DemArgs A, int par) {
-    const int age = *A.fused_age;
+// The substep's decision, then its list work: a rebuild (something changed,
+// or no list is kept) runs the cell histogram; one substep after a rebuild
+// the kept list is copied into this buffer.  The list age has a word per
+// substep parity: a substep reads the other parity's and writes its own, so
+// every block reads the same age.  Block 0 writes the decision into
+// list_flag[par] for the gated kernels that follow; the flag only rises to
+// the decision itself, so a block that reads it after that write decides
+// the same.
+__global__ void k_list_decide(DemArgs A, PairBufs B, int par) {
+    const int age = A.fused_age[par ^ 1];
     const int ch = A.list_flag[par] != 0 || age < 0;
-    A.list_flag[par] = ch;
-    *A.fused_age = ch ? 0 : age + 1;
-}
-
-// a rebuild's cell histogram, or, one substep after a rebuild, the kept list
-// copied into this buffer
-__global__ void k_list_copy_hist(DemArgs A, PairBufs B, int par) {
-    if (A.list_flag[par]) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        A.list_flag[par] = ch;
+        A.fused_age[par] = ch ? 0 : age + 1;
+    }
+    if (ch) {
         GRID_LOOP(k, A.p.np) ph_hist(A, (int)k);
         GRID_LOOP(u, (long long)A.p.np / DEM_ROWS_PER_WG + 2) A.row_lb[u] = 0ull;  // k_rows' tickets, status
         return;
     }
-    if (*A.fused_age != 1) return;
+    if (age != 0) return;
     long long n = *B.prev_n;
     n = n < A.pair_cap ? n : A.pair_cap;
     const int* prev_prow = B.prev_n - A.p.np;
@@ -2178,8 +2182,7 @@ hipError_t dem_predict_keep(const DemArgs& A, double dt, int write_kin, int par,
 hipError_t dem_lists_kept(const DemArgs& A, const PairBufs& B, int par, int* scan_tmp, hipStream_t s) {
     if (A.p.np == 0) return hipSuccess;
     hipError_t e;
-    k_list_age<<<1, 1, 0, s>>>(A, par);
-    k_list_copy_hist<<<nblk_list(A.pair_cap > A.p.np ? A.pair_cap : A.p.np), 256, 0, s>>>(A, B, par);
+    k_list_decide<<<nblk_list(A.pair_cap > A.p.np ? A.pair_cap : A.p.np), 256, 0, s>>>(A, B, par);
     if ((e = psm_scan(A.cell_count, A.cell_start, A.ncell, scan_tmp, s, A.list_run)) != hipSuccess) return e;
     k_scatter<<<nblk_list(A.p.np), 256, 0, s>>>(A);
     k_cellsort<<<nblk_list(A.ncell), 256, 0, s>>>(A);

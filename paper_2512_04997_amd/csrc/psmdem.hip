@@ -144,7 +144,7 @@ static int run_lbm(psmdem_domain* D, bool hydro = true) {
 // the single-workgroup DEM may keep its pair list across launches; any other
 // writer of the lists, cells or particle state makes its next launch rebuild
 static int forget_fused_list(psmdem_domain* D) {
-    if (D->np > 0) PSM_CHECK(hipMemsetAsync(D->fused_age, 0xff, sizeof(int), D->s));
+    if (D->np > 0) PSM_CHECK(hipMemsetAsync(D->fused_age, 0xff, 2 * sizeof(int), D->s));
     if (D->fz) PSM_CHECK(hipMemsetAsync(D->fz, 0xff, sizeof(int), D->s));
     return 0;
 }
@@ -430,7 +430,7 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
     P.kin = (double*)A(sizeof(double) * 9 * std::max(np, 1));
     D->reg_cap = 8LL * std::max(np, 1);
     D->pc = (int*)A(sizeof(int) * 8 * std::max(np, 1));
-    D->fused_age = (int*)A(sizeof(int));
+    D->fused_age = (int*)A(2 * sizeof(int));
     // the fused DEM kernel's saved skip state (domains it runs)
     D->fz = np > 0 && np <= DEM_FUSED_MAX ? (unsigned char*)A(dem_fused_save_bytes()) : nullptr;
     D->list_flag = (int*)A(2 * sizeof(int));
@@ -568,7 +568,7 @@ psmdem_status psm_domain_create(const psmdem_desc* desc, const psmdem_particles*
             hipMemsetAsync(D->t.slot_lp, 0xff, sizeof(unsigned) * g.ntiles * (size_t)PSM_TILE, D->s) != hipSuccess ||
             hipMemsetAsync(D->t.tile_ed, 0, sizeof(unsigned) * 2 * (size_t)g.ntiles, D->s) != hipSuccess ||
             hipMemsetAsync(D->cell_pid, 0, sizeof(int) * D->reg_cap, D->s) != hipSuccess ||
-            hipMemsetAsync(D->fused_age, 0xff, sizeof(int), D->s) != hipSuccess ||
+            hipMemsetAsync(D->fused_age, 0xff, 2 * sizeof(int), D->s) != hipSuccess ||
             (D->fz && hipMemsetAsync(D->fz, 0xff, sizeof(int), D->s) != hipSuccess) ||
             hipMemsetAsync(D->list_flag, 0, 2 * sizeof(int), D->s) != hipSuccess ||
             (D->ell_cnt && hipMemsetAsync(D->ell_cnt, 0, sizeof(unsigned) * DEM_ELL_SEGS, D->s) != hipSuccess) ||
