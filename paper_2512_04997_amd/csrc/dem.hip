@@ -1748,14 +1748,13 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
     }
     long long save_n = -1;  // the last substep's list length when its skip state is complete
     // With at most one particle per thread (and LDS column lists) each thread
-    // runs its particle's sums, corrector and next predictor back to back,
-    // every state load issued before the sums' own loads: no barrier and no
-    // further load latency between them (the same arithmetic as the
-    // stored-state path).
+    // runs its particle's sums, corrector and next predictor back to back on
+    // the state it holds in registers: no barrier and no load between them
+    // (the same arithmetic as the stored-state path).
     // Predictor of particle k for substep psub on its loaded state; returns
     // whether its cells or wall candidates differ from those the kept list
     // was built from.
-    auto predict_k = [&](int k, int psub, PredIn& st, double rbk) __attribute__((always_inline)) -> int {
+    auto predict_k = [&](int k, int psub, PredIn& st, double rbk, double* q0) __attribute__((always_inline)) -> int {
         unsigned old[4];
         if (psub == 0) {
             const int* d = A.pc + 8 * k;
@@ -1769,7 +1768,7 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
         }
         const int pl = psub == nsub - 1 ? 1 : 0;
         AxCells r;
-        double dsp, q0[4];
+        double dsp;
         pred_core(A, k, dt, pl, st, r, &dsp, q0);
         const double xk[3] = {st.x[0], st.x[1], st.x[2]};
         if (!ELL) dacc_s[k] += dsp;  // reset by the first substep, which starts fresh
@@ -1795,6 +1794,17 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
     };
     int changed_next = 0;  // predictors of the next substep run after the sums
     bool tail_done = false;  // ... in the previous substep
+    // With one particle per thread the thread's particle state stays in
+    // registers from its predictor to its corrector and on to the next
+    // predictor: every value the corrector and the predictor read back is one
+    // they wrote (the hydrodynamic force and the particle constants do not
+    // change within a launch).  Its row range is kept while the list is.
+    const bool own = np <= FUSED_T;
+    PredIn own_ps;
+    CorrConst own_cs;
+    double own_qo[4], own_rb = 0.0;
+    long long own_r0 = 0, own_r1 = 0;
+    bool own_rows = false;
     for (int sub = 0; sub < nsub; ++sub) {
         const bool last = sub == nsub - 1;
         const int c = cur ^ 1;
@@ -1812,7 +1822,16 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
             for (int k = tid; k < np; k += FUSED_T) {
                 PredIn st;
                 pred_load(A, k, st);
-                changed |= predict_k(k, sub, st, A.p.rb[k]);
+                const double rbk = A.p.rb[k];
+                double q0[4];
+                changed |= predict_k(k, sub, st, rbk, q0);
+                if (own) {
+                    own_ps = st;
+                    corr_load_const(A, k, own_cs);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) own_qo[q] = q0[q];
+                    own_rb = rbk;
+                }
             }
         } else {
             changed = changed_next;
@@ -1823,6 +1842,7 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
         // with a new list and at the start of a launch that restored none
         const bool fresh = rebuild || (sub == 0 && !restored);
         if (fresh) keys_lds = false;
+        if (rebuild) own_rows = false;
         if (!rebuild) {
             // the previous list is this list: one substep after the rebuild it
             // is copied into this buffer, later this buffer already holds it
@@ -2006,18 +2026,8 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
         save_n = (!ELL && lds_cols && keys_lds && npairs <= FUSED_PREV_LDS) ? npairs : -1;
         __syncthreads();
         // DEM sums: pairs (k, i) for ascending k, then the own row
-        const bool tail = !ELL && np <= FUSED_T && lds_cols;  // ellipsoids: registers go to the contacts
+        const bool tail = !ELL && own && lds_cols;  // ellipsoids: registers go to the contacts
         for (int i = tid; i < np; i += FUSED_T) {
-            PredIn ps;
-            CorrConst cs;
-            double qo[4], rbk = 0.0;
-            if (tail) {
-                pred_load(A, i, ps);
-                corr_load_const(A, i, cs);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) qo[q] = A.p.qold[4 * i + q];
-                rbk = A.p.rb[i];
-            }
             double F[3] = {0.0, 0.0, 0.0}, M[3] = {0.0, 0.0, 0.0};
             if (lds_cols) {
                 const int s0 = i > 0 ? cnt_s[i - 1] : 0, s1 = cnt_s[i];
@@ -2050,9 +2060,13 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
                     }
                 }
             }
-            long long s0 = B.prow[i], s1 = B.prow[i + 1];
-            s1 = s1 < A.pair_cap ? s1 : A.pair_cap;
-            for (long long s = s0; s < s1; ++s) {
+            if (!own_rows) {
+                own_r0 = B.prow[i];
+                own_r1 = B.prow[i + 1];
+                own_r1 = own_r1 < A.pair_cap ? own_r1 : A.pair_cap;
+                own_rows = own;
+            }
+            for (long long s = own_r0; s < own_r1; ++s) {
                 if (lds_cols && !inc_s[s]) continue;
 #pragma unroll
                 for (int q = 0; q < 3; ++q) {
@@ -2068,8 +2082,8 @@ __device__ __attribute__((always_inline)) void dem_fused_body(const DemArgs& A, 
             if (tail) {
                 // this thread's particle: corrector, then the next predictor
                 if (!(last && stop_before_correct))
-                    corr_core(A, i, dt, cs, F, M, qo, ps.v, ps.a, ps.w, ps.al);
-                if (!last) changed_next = predict_k(i, sub + 1, ps, rbk);
+                    corr_core(A, i, dt, own_cs, F, M, own_qo, own_ps.v, own_ps.a, own_ps.w, own_ps.al);
+                if (!last) changed_next = predict_k(i, sub + 1, own_ps, own_rb, own_qo);
             }
         }
         if (!tail) {
