@@ -609,23 +609,18 @@ __device__ inline long long n_pairs(const DemArgs& A, const PairBufs& B) {
     return n < A.pair_cap ? n : A.pair_cap;
 }
 
-// spring-dashpot with Coulomb cap and tangential history (Sec. 2.1), linear or
-// Hertz (App. A) stiffness and damping:
-// F_n = [k_n delta + gamma_n (v_j - v_i).e_n] e_n, linear gamma_n = -2 beta sqrt(k_n m*);
-// v_rel = (v_i - v_j) - (rho_i w_i + rho_j w_j) x e_n, v_t its tangential part;
-// history projected on the tangent plane then advanced by v_t dt;
-// F_t = -k_t d_t - gamma_t v_t capped at mu |F_n| with the history reset.
-// same_list: the previous list holds the same keys in the same order, so the
-// history of pair s sits at index s.
-// Returns whether the pair is in contact; out of contact, *gap (when given)
-// receives the separation -delta.
-// With deferred non-null, an ellipsoid pair that needs the iteration is not
-// evaluated: *deferred is set and the pair's outputs are left to a later
-// ph_contact call (the dense iteration kernel).
+// Spring-dashpot contact with a Coulomb limit and tangential history (Sec.
+// 2.1; Hertz coefficients App. A), defined below.  same_list: the previous
+// list holds the same keys in the same order, so the history of pair s sits
+// at index s.  Returns whether the pair is in contact; out of contact, *gap
+// (when given) receives the separation -delta.
 __device__ bool contact_law(const DemArgs& A, const PairBufs& B, long long s, unsigned long long key, const Geom& G,
                             const double* __restrict__ vv, const double* __restrict__ ww, double dth, long long nprev,
                             bool same_list, double* gap);
 
+// Geometry, then the law, of pair s.  With deferred non-null, an ellipsoid
+// pair that needs the iteration is not evaluated: *deferred is set and the
+// pair's outputs are left to the dense iteration kernel.
 template <bool ELL>
 __device__ bool ph_contact(const DemArgs& A, const PairBufs& B, long long s, const double* __restrict__ vv,
                            const double* __restrict__ ww, double dth, long long nprev, bool same_list = false,
@@ -652,100 +647,134 @@ __device__ bool ph_contact(const DemArgs& A, const PairBufs& B, long long s, con
     return contact_law(A, B, s, key, G, vv, ww, dth, nprev, same_list, gap);
 }
 
-// the contact law of pair s (key = B.pairs[s]) with its geometry G
+// Spring and dashpot coefficients of a contact in contact: the linear law's
+// constants (gamma_n = -2 beta sqrt(k_n m*)), or the Hertz law's from the
+// material and the overlap (App. A: k_n = 4/3 Y* sqrt(R* delta), k_t = 8 G*
+// sqrt(R* delta), gamma = -2 sqrt(5/6) beta sqrt(S m*) with S_n = 2 Y*
+// sqrt(R* delta), S_t = 8 G* sqrt(R* delta); a wall has infinite radius and
+// mass).
+struct LawCoeffs {
+    double kn, kt, gn, gt;
+};
+
+__device__ inline LawCoeffs law_coeffs(const DemArgs& A, const Geom& G, bool wall, double mstar) {
+    LawCoeffs c;
+    if (A.hertz) {
+        const double Rs = wall ? G.rhoi : 1.0 / (1.0 / G.rhoi + 1.0 / G.rhoj);
+        const double root = sqrt(Rs * G.delta);
+        c.kn = 4.0 / 3.0 * A.ystar * root;
+        c.kt = 8.0 * A.gstar * root;
+        const double damp = -2.0 * sqrt(5.0 / 6.0) * A.beta_e;
+        c.gn = damp * sqrt((2.0 * A.ystar * root) * mstar);
+        c.gt = damp * sqrt((8.0 * A.gstar * root) * mstar);
+    } else {
+        c.kn = A.kn;
+        c.kt = A.kt_ratio * A.kn;
+        c.gn = -2.0 * A.beta_e * sqrt(c.kn * mstar);
+        c.gt = A.gt_ratio * c.gn;
+    }
+    return c;
+}
+
+// Sliding: a tangential force above mu |F_n| is scaled down to it, and the
+// spring displacement is reset to the one that force implies.
+__device__ inline void coulomb_limit(const LawCoeffs& c, double limit, const double* ut, double* ft, double* xi) {
+    const double mag = sqrt(dot3(ft, ft));
+    if (!(mag > limit)) return;
+    const double s = limit / mag;
+    for (int k = 0; k < 3; ++k) ft[k] *= s;
+    if (c.kt > 0.0)
+        for (int k = 0; k < 3; ++k) xi[k] = -(ft[k] + c.gt * ut[k]) / c.kt;
+}
+
+// The contact law of pair s (key = B.pairs[s]) with its geometry G.  Out of
+// contact every output is zero.  In contact, with n the unit normal from i
+// towards j and d = v_i - v_j:
+//   normal force   F_n = k_n delta - gamma_n (d . n), along n;
+//   slip velocity  u = d - (rho_i w_i + rho_j w_j) x n, u_t its tangential part;
+//   spring         xi = (h - (h . n) n) + u_t dt (the stored displacement h
+//                  turned into the present tangent plane, then advanced);
+//   friction       F_t = -k_t xi - gamma_t u_t, at most mu |F_n|;
+// force on i: F_n n + F_t; moments: spheres -rho e_n x F_t on each, else the
+// contact-point arms crossed with the force.  The arithmetic of each term is
+// evaluated in the oracle's order (forces and history bit for bit on the
+// same geometry).
 __device__ bool contact_law(const DemArgs& A, const PairBufs& B, long long s, unsigned long long key, const Geom& G,
                             const double* __restrict__ vv, const double* __restrict__ ww, double dth, long long nprev,
                             bool same_list, double* gap) {
     const int np = A.p.np;
     const int i = (int)(key >> 32), j = (int)(key & 0xffffffffu);
     const bool wall = j >= np;
-    double* F = A.cF + 3 * s;
-    double* Mi = A.cMi + 3 * s;
-    double* Mj = A.cMj + 3 * s;
-    double* h = B.hist + 3 * s;
+    double* out_f = A.cF + 3 * s;
+    double* out_mi = A.cMi + 3 * s;
+    double* out_mj = A.cMj + 3 * s;
+    double* out_h = B.hist + 3 * s;
     if (!(G.delta > 0.0)) {
-        for (int k = 0; k < 3; ++k) F[k] = Mi[k] = Mj[k] = h[k] = 0.0;
+        for (int k = 0; k < 3; ++k) out_f[k] = out_mi[k] = out_mj[k] = out_h[k] = 0.0;
         A.incontact[s] = 0;
         if (gap) *gap = -G.delta;
         return false;
     }
-    double vi[3], wi[3], vj[3], wj[3];
-    const double mi = A.p.mass[i], mj = wall ? 0.0 : A.p.mass[j];
+    A.incontact[s] = 1;
+    // the partner's motion: a particle's, or the wall's (its velocity when it moves)
+    double vi[3], wi[3], vj[3] = {0.0, 0.0, 0.0}, wj[3] = {0.0, 0.0, 0.0};
     for (int k = 0; k < 3; ++k) {
         vi[k] = vv[3 * i + k];
         wi[k] = ww[3 * i + k];
-        if (!wall) {
+    }
+    double mstar;
+    if (wall) {
+        const int face = j - np;
+        if (A.g.bc[face] == 2)
+            for (int k = 0; k < 3; ++k) vj[k] = A.wall_u[face][k];
+        mstar = A.p.mass[i];
+    } else {
+        for (int k = 0; k < 3; ++k) {
             vj[k] = vv[3 * j + k];
             wj[k] = ww[3 * j + k];
         }
-    }
-    const long long ps = same_list ? s : find_prev(B, key, nprev);
-    double ho[3] = {0.0, 0.0, 0.0};
-    if (ps >= 0)
-        for (int k = 0; k < 3; ++k) ho[k] = B.prev_hist[3 * ps + k];
-    A.incontact[s] = 1;
-    double mstar;
-    if (!wall) {
+        const double mi = A.p.mass[i], mj = A.p.mass[j];
         mstar = mi * mj / (mi + mj);
-    } else {
-        int f = j - np;
-        for (int k = 0; k < 3; ++k) {
-            vj[k] = (A.g.bc[f] == 2) ? A.wall_u[f][k] : 0.0;
-            wj[k] = 0.0;
-        }
-        mstar = mi;
     }
-    double kn = A.kn, kt = A.kt_ratio * A.kn, gn, gt;
-    if (A.hertz) {
-        // Hertz (App. A): stiffness and damping from the material and the overlap
-        const double Rs = wall ? G.rhoi : 1.0 / (1.0 / G.rhoi + 1.0 / G.rhoj);
-        const double sq = sqrt(Rs * G.delta);
-        kn = 4.0 / 3.0 * A.ystar * sq;
-        kt = 8.0 * A.gstar * sq;
-        const double Sn = 2.0 * A.ystar * sq, St = 8.0 * A.gstar * sq;
-        gn = -2.0 * sqrt(5.0 / 6.0) * A.beta_e * sqrt(Sn * mstar);
-        gt = -2.0 * sqrt(5.0 / 6.0) * A.beta_e * sqrt(St * mstar);
-    } else {
-        gn = -2.0 * A.beta_e * sqrt(kn * mstar);
-        gt = A.gt_ratio * gn;
-    }
-    double dv[3] = {vj[0] - vi[0], vj[1] - vi[1], vj[2] - vi[2]};
-    double fn = kn * G.delta + gn * dot3(dv, G.en);
-    double rw[3] = {G.rhoi * wi[0] + G.rhoj * wj[0], G.rhoi * wi[1] + G.rhoj * wj[1], G.rhoi * wi[2] + G.rhoj * wj[2]};
-    double cr[3];
-    cross3(rw, G.en, cr);
-    double vrel[3] = {(vi[0] - vj[0]) - cr[0], (vi[1] - vj[1]) - cr[1], (vi[2] - vj[2]) - cr[2]};
-    double vrn = dot3(vrel, G.en);
-    double vt[3] = {vrel[0] - vrn * G.en[0], vrel[1] - vrn * G.en[1], vrel[2] - vrn * G.en[2]};
-    double hp = dot3(ho, G.en);
-    double ht[3];
-    for (int k = 0; k < 3; ++k) ht[k] = (ho[k] - hp * G.en[k]) + vt[k] * dth;
-    double ft[3];
-    for (int k = 0; k < 3; ++k) ft[k] = -kt * ht[k] - gt * vt[k];
-    double ftn = sqrt(dot3(ft, ft));
-    double cap = A.mu * fabs(fn);
-    if (ftn > cap) {
-        double sc = cap / ftn;
-        for (int k = 0; k < 3; ++k) ft[k] *= sc;
-        if (kt > 0.0)
-            for (int k = 0; k < 3; ++k) ht[k] = -(ft[k] + gt * vt[k]) / kt;
-    }
+    // the tangential displacement the pair carried out of the last substep
+    double h[3] = {0.0, 0.0, 0.0};
+    const long long at = same_list ? s : find_prev(B, key, nprev);
+    if (at >= 0)
+        for (int k = 0; k < 3; ++k) h[k] = B.prev_hist[3 * at + k];
+    const LawCoeffs c = law_coeffs(A, G, wall, mstar);
+    const double* n = G.en;
+    double d[3], lever[3], spin[3], u[3];
     for (int k = 0; k < 3; ++k) {
-        F[k] = fn * G.en[k] + ft[k];
-        h[k] = ht[k];
+        d[k] = vi[k] - vj[k];
+        lever[k] = G.rhoi * wi[k] + G.rhoj * wj[k];
+    }
+    cross3(lever, n, spin);
+    for (int k = 0; k < 3; ++k) u[k] = d[k] - spin[k];
+    const double fnorm = c.kn * G.delta - c.gn * dot3(d, n);
+    const double un = dot3(u, n), hn = dot3(h, n);
+    double ut[3], xi[3], ft[3];
+    for (int k = 0; k < 3; ++k) {
+        ut[k] = u[k] - un * n[k];
+        xi[k] = (h[k] - hn * n[k]) + ut[k] * dth;
+    }
+    for (int k = 0; k < 3; ++k) ft[k] = -c.kt * xi[k] - c.gt * ut[k];
+    coulomb_limit(c, A.mu * fabs(fnorm), ut, ft, xi);
+    for (int k = 0; k < 3; ++k) {
+        out_f[k] = fnorm * n[k] + ft[k];
+        out_h[k] = xi[k];
     }
     if (G.sphere_law) {
-        double T[3];
-        cross3(G.en, ft, T);
+        double t[3];
+        cross3(n, ft, t);
         for (int k = 0; k < 3; ++k) {
-            Mi[k] = -G.rhoi * T[k];
-            Mj[k] = (j < np) ? -G.rhoj * T[k] : 0.0;
+            out_mi[k] = -G.rhoi * t[k];
+            out_mj[k] = wall ? 0.0 : -G.rhoj * t[k];
         }
     } else {
-        double mF[3] = {-F[0], -F[1], -F[2]};
-        cross3(G.rci, F, Mi);
-        if (j < np) cross3(G.rcj, mF, Mj);
-        else Mj[0] = Mj[1] = Mj[2] = 0.0;
+        const double back[3] = {-out_f[0], -out_f[1], -out_f[2]};
+        cross3(G.rci, out_f, out_mi);
+        if (wall) out_mj[0] = out_mj[1] = out_mj[2] = 0.0;
+        else cross3(G.rcj, back, out_mj);
     }
     return true;
 }
