@@ -84,6 +84,9 @@ hipError_t dem_lists(const DemArgs& A, const PairBufs& B, int* scan_tmp, hipStre
 // column counts: the row emission forms them; rows placed otherwise (copied)
 // take dem_count_columns first
 hipError_t dem_columns(const DemArgs& A, const PairBufs& B, int* scan_tmp, hipStream_t s);
+// each cell's list of the last build in ascending particle order (the step
+// itself leaves them in arrival order; a read-back of the lists sorts them)
+hipError_t dem_sort_cells(const DemArgs& A, hipStream_t s);
 hipError_t dem_count_columns(const DemArgs& A, const PairBufs& B, hipStream_t s);
 // multi-launch substeps that keep an unchanged list (A.list_run = A.list_flag + par)
 hipError_t dem_predict_keep(const DemArgs& A, double dt, int write_kin, int par, hipStream_t s);

@@ -1161,19 +1161,17 @@ __global__ void k_hist(DemArgs A) {
     GRID_LOOP(k, A.p.np) ph_hist(A, (int)k);
     GRID_LOOP(u, (long long)A.p.np / DEM_ROWS_PER_WG + 2) A.row_lb[u] = 0ull;  // k_rows' tickets, status
 }
+// The scatter fills each cell's list in arrival order; the rows rank their
+// partners by index, so nothing on the path needs the lists ordered.  The
+// scan has consumed the cell counts: they are cleared here for the next list
+// build (the fill counters by the rows kernel).
 __global__ void k_scatter(DemArgs A) {
     if (A.list_run && !*A.list_run) return;
     GRID_LOOP(k, A.p.np) ph_scatter(A, (int)k);
+    GRID_LOOP(c, A.ncell) A.cell_count[c] = 0;
 }
-// sorts each cell's list, then clears the cell's counters for the next list build
-__global__ void k_cellsort(DemArgs A) {
-    if (A.list_run && !*A.list_run) return;
-    GRID_LOOP(c, A.ncell) {
-        ph_cellsort(A, c);
-        A.cell_count[c] = 0;
-        A.cell_fill[c] = 0;
-    }
-}
+// each cell's list in ascending particle order (for a read-back of the lists)
+__global__ void k_cellsort(DemArgs A) { GRID_LOOP(c, A.ncell) ph_cellsort(A, c); }
 // Candidate rows through the cell lists, one wave per particle i: the entries
 // of i's registration cells are flattened over the lanes; a lane keeps
 // partner j when j > i and the cell is the lowest the two share (each pair
@@ -1262,6 +1260,7 @@ __device__ inline unsigned long long row_wait(const unsigned long long* p, bool&
 
 __global__ __launch_bounds__(256) void k_rows(DemArgs A, PairBufs B) {
     if (A.list_run && !*A.list_run) return;
+    GRID_LOOP(c, A.ncell) A.cell_fill[c] = 0;  // the scatter's fill counters, for the next list build
     __shared__ int ticket_s;
     __shared__ int cnt_s[DEM_ROWS_PER_WG], wall_s[DEM_ROWS_PER_WG], off_s[DEM_ROWS_PER_WG + 1];
     __shared__ int kept_s[DEM_ROWS_PER_WG][ROW_KEEP];
@@ -2227,8 +2226,7 @@ hipError_t dem_lists_kept(const DemArgs& A, const PairBufs& B, int par, int* sca
     hipError_t e;
     k_list_decide<<<nblk_list(A.pair_cap > A.p.np ? A.pair_cap : A.p.np), 256, 0, s>>>(A, B, par);
     if ((e = psm_scan(A.cell_count, A.cell_start, A.ncell, scan_tmp, s, A.list_run)) != hipSuccess) return e;
-    k_scatter<<<nblk_list(A.p.np), 256, 0, s>>>(A);
-    k_cellsort<<<nblk_list(A.ncell), 256, 0, s>>>(A);
+    k_scatter<<<nblk_list(A.p.np > A.ncell ? A.p.np : A.ncell), 256, 0, s>>>(A);
     k_rows<<<(unsigned)((A.p.np + DEM_ROWS_PER_WG - 1) / DEM_ROWS_PER_WG), 256, 0, s>>>(A, B);
     return hipGetLastError();
 }
@@ -2250,10 +2248,15 @@ hipError_t dem_lists(const DemArgs& A, const PairBufs& B, int* scan_tmp, hipStre
     k_cells<<<nblk(A.p.np), 256, 0, s>>>(A);
     k_hist<<<nblk(A.p.np), 256, 0, s>>>(A);
     if ((e = psm_scan(A.cell_count, A.cell_start, A.ncell, scan_tmp, s)) != hipSuccess) return e;
-    k_scatter<<<nblk_list(A.p.np), 256, 0, s>>>(A);
-    k_cellsort<<<nblk_list(A.ncell), 256, 0, s>>>(A);
+    k_scatter<<<nblk_list(A.p.np > A.ncell ? A.p.np : A.ncell), 256, 0, s>>>(A);
     k_rows<<<(unsigned)((A.p.np + DEM_ROWS_PER_WG - 1) / DEM_ROWS_PER_WG), 256, 0, s>>>(A, B);
     return dem_columns(A, B, scan_tmp, s);
+}
+
+hipError_t dem_sort_cells(const DemArgs& A, hipStream_t s) {
+    if (A.p.np == 0) return hipSuccess;
+    k_cellsort<<<nblk_list(A.ncell), 256, 0, s>>>(A);
+    return hipGetLastError();
 }
 
 hipError_t dem_count_columns(const DemArgs& A, const PairBufs& B, hipStream_t s) {

@@ -938,6 +938,8 @@ extern "C" psmdem_status psmdem_read_cells(psmdem_domain* d, int64_t cap, uint64
     if (psm_read_fails(st)) return st;
     *n = 0;
     if (d->np == 0) return st;
+    PSM_CHECK(dem_sort_cells(d->dem_args(), d->s));
+    PSM_CHECK(hipStreamSynchronize(d->s));
     std::vector<int> start(d->ncell + 1);
     PSM_CHECK(hipMemcpy(start.data(), d->cell_start, sizeof(int) * (d->ncell + 1), hipMemcpyDeviceToHost));
     long long tot = std::min<long long>(start[d->ncell], d->reg_cap);
