@@ -210,6 +210,24 @@ __device__ inline int wall_count(const DemArgs& A, int i) {
 // contract multiply-adds (the file is otherwise compiled without): they form an
 // approximation refined until it converges or the cap is met, and the
 // contact decision on its result is not an exact predicate of the inputs.
+// 1/sqrt(x) and 1/x from the hardware estimates refined by two Newton steps
+// (within a few units in the last place of the rounded quotients)
+__device__ inline double rsq_nr(double x) {
+#pragma clang fp contract(fast)
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * (1.5 - h * y * y);
+    y = y * (1.5 - h * y * y);
+    return y;
+}
+__device__ inline double rcp_nr(double x) {
+#pragma clang fp contract(fast)
+    double y = __builtin_amdgcn_rcp(x);
+    y = y * (2.0 - x * y);
+    y = y * (2.0 - x * y);
+    return y;
+}
+
 struct EllShape {
     double R[9];
     double ia2[3];
@@ -238,7 +256,7 @@ __device__ void ell_local(const double* c, const EllShape& E, const double* p, d
     double nb[3] = {xb[0] * E.ia2[0], xb[1] * E.ia2[1], xb[2] * E.ia2[2]};
     double nw[3];
     for (int r = 0; r < 3; ++r) nw[r] = (R[3 * r] * nb[0] + R[3 * r + 1] * nb[1]) + R[3 * r + 2] * nb[2];
-    const double il = 1.0 / sqrt(dot3(nw, nw));
+    const double il = rsq_nr(dot3(nw, nw));
     for (int r = 0; r < 3; ++r) n[r] = nw[r] * il;
 }
 
@@ -263,7 +281,7 @@ __device__ bool ell_line_hit(const double* c, const EllShape& E, const double* s
     double disc = qb * qb - qa * qc;
     if (disc < 0.0 || qa <= 0.0) return false;
     double sq = sqrt(disc);
-    double t = (far_positive ? -qb + sq : -qb - sq) / qa;
+    double t = (far_positive ? -qb + sq : -qb - sq) * rcp_nr(qa);
     for (int k = 0; k < 3; ++k) p[k] = s[k] + t * u[k];
     return true;
 }
@@ -292,7 +310,7 @@ __device__ void ellipsoid_pair(const DemArgs& A, int i, int j, Geom& G) {
     double pi[3], pj[3];
     {
         double u[3] = {cj[0] - ci[0], cj[1] - ci[1], cj[2] - ci[2]};
-        const double il = 1.0 / sqrt(dot3(u, u));
+        const double il = rsq_nr(dot3(u, u));
         for (int k = 0; k < 3; ++k) u[k] *= il;
         ell_line_hit(ci, Ei, ci, u, true, pi);
         double um[3] = {-u[0], -u[1], -u[2]};
@@ -307,9 +325,9 @@ __device__ void ellipsoid_pair(const DemArgs& A, int i, int j, Geom& G) {
             sj[k] = pj[k] - rhoj * nj[k];
         }
         double u[3] = {sj[0] - si[0], sj[1] - si[1], sj[2] - si[2]};
-        double l = sqrt(dot3(u, u));
-        if (!(l > 0.0)) break;
-        const double il = 1.0 / l;
+        const double l2 = dot3(u, u);
+        if (!(l2 > 0.0)) break;
+        const double il = rsq_nr(l2);
         for (int k = 0; k < 3; ++k) u[k] *= il;
         double npi[3], npj[3];
         if (!ell_line_hit(ci, Ei, si, u, true, npi)) break;
@@ -367,7 +385,7 @@ __device__ void ellipsoid_pair2(const DemArgs& A, int i, int j, int side, Geom& 
     double p[3];
     {
         double u[3] = {cj[0] - ci[0], cj[1] - ci[1], cj[2] - ci[2]};
-        const double il = 1.0 / sqrt(dot3(u, u));
+        const double il = rsq_nr(dot3(u, u));
         for (int k = 0; k < 3; ++k) u[k] *= il;
         const double dir[3] = {side ? -u[0] : u[0], side ? -u[1] : u[1], side ? -u[2] : u[2]};
         ell_line_hit(c, E, c, dir, true, p);
@@ -380,9 +398,9 @@ __device__ void ellipsoid_pair2(const DemArgs& A, int i, int j, int side, Geom& 
         const double* si = side ? so : sc;
         const double* sj = side ? sc : so;
         double u[3] = {sj[0] - si[0], sj[1] - si[1], sj[2] - si[2]};
-        double l = sqrt(dot3(u, u));
-        if (!(l > 0.0)) break;
-        const double il = 1.0 / l;
+        const double l2 = dot3(u, u);
+        if (!(l2 > 0.0)) break;
+        const double il = rsq_nr(l2);
         for (int k = 0; k < 3; ++k) u[k] *= il;
         double np_[3];
         const int hit = ell_line_hit(c, E, sc, u, side == 0, np_) ? 1 : 0;
