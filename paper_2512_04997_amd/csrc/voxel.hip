@@ -981,6 +981,18 @@ __device__ inline int sample_exact(const VoxPart& P, double dx, double dy, doubl
     return (((p0 * p0) * P.inv[0] + (p1 * p1) * P.inv[1]) + (p2 * p2) * P.inv[2]) < 1.0 ? 1 : 0;
 }
 
+// sqrt(x) for x > 0 from the hardware reciprocal-square-root estimate refined
+// by two Newton steps (a few units in the last place): the row roots only
+// need to be within the margin of the exact test
+__device__ inline double sqrt_est(double x) {
+#pragma clang fp contract(fast)
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * (1.5 - h * y * y);
+    y = y * (1.5 - h * y * y);
+    return x * y;
+}
+
 // the row quadratic's coefficients of one particle (see k_vox_rows)
 struct RowQ {
     double A, iA, by, bz, cyy, cyz, czz, a2, mt, xl, gmax, fns;
@@ -1015,7 +1027,7 @@ __device__ inline void row_inside(const VoxPart& P, const RowQ& q, const double*
     double G1, G2;
     {
 #pragma clang fp contract(fast)
-        const double sq = sqrt(disc);
+        const double sq = sqrt_est(disc);  // disc >= tol > 0 here
         G1 = ((-B - sq) * q.iA - q.xl) * q.fns - 0.5;
         G2 = ((-B + sq) * q.iA - q.xl) * q.fns - 0.5;
     }
@@ -1135,7 +1147,7 @@ __global__ __launch_bounds__(VOX_T) void k_vox_rows(VoxArgs A) {
                 const double a0 = bzz * bzz - q.A * (czzz - 1.0);
                 const double D = a1 * a1 - 4.0 * q.a2 * a0;
                 miss = D < -(1e-9 * (a1 * a1 + 4.0 * fabs(q.a2 * a0)) + 1e-12);
-                const double sD = sqrt(D > 0.0 ? D : 0.0);
+                const double sD = D > 0.0 ? sqrt_est(D) : 0.0;
                 const double y1 = (-a1 + sD) / (2.0 * q.a2), y2 = (-a1 - sD) / (2.0 * q.a2);
                 ylo = fmin(y1, y2) - my;
                 yhi = fmax(y1, y2) + my;
