@@ -22,7 +22,7 @@ struct DemArgs {
     unsigned long long* row_lb;  // [np / DEM_ROWS_PER_WG + 2] the row kernel's ticket counter and
                                  // per-chunk status words (cleared by the cell histogram)
     double *cF, *cMi, *cMj;         // [3 pair_cap] force on i, torque on i, torque on j
-    unsigned char* incontact;       // [pair_cap]
+    unsigned char* incontact;       // [pair_cap] bit 0: in contact now; bit 1: at the evaluation before (or unknown)
     int *col_count, *col_fill;      // [np]
     int* col_start;                 // [np + 1]
     int* col_list;                  // [pair_cap] pair indices by second member, ascending

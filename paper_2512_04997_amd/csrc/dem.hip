@@ -727,13 +727,21 @@ __device__ bool contact_law(const DemArgs& A, const PairBufs& B, long long s, un
     double* out_mi = A.cMi + 3 * s;
     double* out_mj = A.cMj + 3 * s;
     double* out_h = B.hist + 3 * s;
+    // incontact[s]: bit 0 the pair is in contact at this evaluation, bit 1 it
+    // was at the one before on the same list, or that is not known (a new
+    // list).  A pair out of contact at both earlier evaluations on a kept list
+    // already holds zero outputs and zero history in both buffers (the history
+    // buffers alternate by substep), so it writes nothing.
+    const unsigned char prev = same_list ? A.incontact[s] : (unsigned char)2;
     if (!(G.delta > 0.0)) {
-        for (int k = 0; k < 3; ++k) out_f[k] = out_mi[k] = out_mj[k] = out_h[k] = 0.0;
-        A.incontact[s] = 0;
+        if (prev != 0) {
+            for (int k = 0; k < 3; ++k) out_f[k] = out_mi[k] = out_mj[k] = out_h[k] = 0.0;
+            A.incontact[s] = same_list ? (unsigned char)((prev & 1) << 1) : (unsigned char)2;
+        }
         if (gap) *gap = -G.delta;
         return false;
     }
-    A.incontact[s] = 1;
+    A.incontact[s] = same_list ? (unsigned char)(1 | ((prev & 1) << 1)) : (unsigned char)3;
     // the partner's motion: a particle's, or the wall's (its velocity when it moves)
     double vi[3], wi[3], vj[3] = {0.0, 0.0, 0.0}, wj[3] = {0.0, 0.0, 0.0};
     for (int k = 0; k < 3; ++k) {
@@ -1121,7 +1129,7 @@ __global__ __launch_bounds__(256) void k_sum_correct_predict(DemArgs A, PairBufs
         double F[3] = {0.0, 0.0, 0.0}, M[3] = {0.0, 0.0, 0.0};
         for (long long u = c0; u < c1; ++u) {
             const long long s = A.col_list[u];
-            if (!A.incontact[s]) continue;
+            if (!(A.incontact[s] & 1)) continue;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 F[c] -= A.cF[3 * s + c];
@@ -1129,7 +1137,7 @@ __global__ __launch_bounds__(256) void k_sum_correct_predict(DemArgs A, PairBufs
             }
         }
         for (long long s = s0; s < s1; ++s) {
-            if (!A.incontact[s]) continue;
+            if (!(A.incontact[s] & 1)) continue;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 F[c] += A.cF[3 * s + c];
@@ -1525,7 +1533,7 @@ __global__ __launch_bounds__(256) void k_sum_wave(DemArgs A, PairBufs B) {
             if (e < ne) {
                 const bool col = e < nc;
                 const long long s = col ? (long long)A.col_list[c0 + e] : s0 + (e - nc);
-                in = A.incontact[s] != 0;
+                in = (A.incontact[s] & 1) != 0;
                 if (in) {
                     const double* Mo = col ? A.cMj : A.cMi;
 #pragma unroll

@@ -917,7 +917,7 @@ extern "C" psmdem_status psmdem_read_contacts(psmdem_domain* d, int64_t cap, uin
     }
     int64_t m = 0;
     for (int64_t s = 0; s < np_; ++s) {
-        if (!ic[s]) continue;
+        if (!(ic[s] & 1)) continue;
         if (m < cap) {
             if (keys) keys[m] = k[s];
             for (int c = 0; c < 3; ++c) {
@@ -1013,7 +1013,7 @@ extern "C" psmdem_status psmdem_counters(psmdem_domain* d, psmdem_counters_t* ou
     if (npairs > 0) {
         std::vector<unsigned char> ic(npairs);
         PSM_CHECK(hipMemcpy(ic.data(), d->incontact, npairs, hipMemcpyDeviceToHost));
-        for (auto v : ic) out->n_contacts += v;
+        for (auto v : ic) out->n_contacts += v & 1;
     }
     if (d->np > 0) {
         int r = 0;
