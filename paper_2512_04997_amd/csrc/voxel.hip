@@ -995,7 +995,7 @@ __device__ inline double sqrt_est(double x) {
 
 // the row quadratic's coefficients of one particle (see k_vox_rows)
 struct RowQ {
-    double A, iA, by, bz, cyy, cyz, czz, a2, mt, xl, gmax, fns;
+    double A, iA, by, bz, cyy, cyz, czz, a2, i2a2, mt, xl, gmax, fns;
 };
 
 // Row dy, dz of the cell row `row` (LDS counts of the box's x cells): the
@@ -1122,6 +1122,7 @@ __global__ __launch_bounds__(VOX_T) void k_vox_rows(VoxArgs A) {
     q.fns = (double)ns;
     q.mt = 1e-5 * (1.0 + amax) * q.fns;
     q.a2 = q.by * q.by - q.A * q.cyy;
+    q.i2a2 = 1.0 / (2.0 * q.a2);  // a2 < 0: the shape matrix is positive definite
     q.xl = (double)P.lo[0] - P.c[0];
     q.gmax = (double)(bx * ns - 1);
     const double my = 1e-3;
@@ -1148,7 +1149,7 @@ __global__ __launch_bounds__(VOX_T) void k_vox_rows(VoxArgs A) {
                 const double D = a1 * a1 - 4.0 * q.a2 * a0;
                 miss = D < -(1e-9 * (a1 * a1 + 4.0 * fabs(q.a2 * a0)) + 1e-12);
                 const double sD = D > 0.0 ? sqrt_est(D) : 0.0;
-                const double y1 = (-a1 + sD) / (2.0 * q.a2), y2 = (-a1 - sD) / (2.0 * q.a2);
+                const double y1 = (-a1 + sD) * q.i2a2, y2 = (-a1 - sD) * q.i2a2;  // widened by my below
                 ylo = fmin(y1, y2) - my;
                 yhi = fmax(y1, y2) + my;
             }
