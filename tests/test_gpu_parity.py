@@ -383,6 +383,49 @@ def test_dem_multi_launch_path(ps, oracle_mod):
     assert O.counters()["contacts"] > 50
 
 
+def test_dem_multi_launch_contacts_form_and_break(ps, oracle_mod):
+    """Multi-launch DEM over 48 substeps in which pairs come into contact and
+    leave it again while the list is kept: a pair out of contact at its last
+    two evaluations writes nothing (its zero outputs and history are already
+    in place), so the contact set, forces and trajectory after each step must
+    still equal the oracle's, and some pairs must re-enter contact."""
+    box = (72, 64, 60)
+    rng = W.SplitMix64(91)
+    n = 2300
+    radii = 1.2 + 0.6 * rng.uniform(n)
+    pos = W.rsa_spheres(rng, n, radii, box, [True, True, False], gap=0.15)
+    m = len(pos)
+    assert m > 2048
+    parts = W.spheres(pos, radii[:m], 1.8, vel=0.03 * (rng.uniform(3 * m).reshape(m, 3) - 0.5),
+                      omega=0.02 * (rng.uniform(3 * m).reshape(m, 3) - 0.5))
+    cfg = _walled(box, 0.7, "fp64", fluid_on=False, mu=0.3, restitution=0.6, n_sub=6,
+                  gravity=[0.0, 0.0, -1e-4])
+    G, O = _pair(ps, oracle_mod, cfg, parts)
+    seen, left, reentered = set(), 0, 0
+    prev = set()
+    for step in range(8):
+        G.step(1)
+        O.step(1)
+        assert np.array_equal(G.pairs()[0], O.pairs()[0])
+        kg, Fg, _, _ = G.contacts()
+        ko, Fo, _, _ = O.contacts()
+        assert np.array_equal(kg, ko)
+        sc = O.scales()
+        Pg, Po = G.particles(), O.particles()
+        assert vec_err(Pg["pos"], Po["pos"]) < 1e-12
+        assert vec_err(Pg["vel"], Po["vel"]) < 1e-12, step
+        assert force_err(Pg["f_dem"], Po["f_dem"], sc["f_dem"]) < 1e-12, step
+        if len(ko):
+            assert np.abs(Fg - Fo).max() <= 1e-12 * max(1.0, float(np.abs(Fo).max()))
+        now = set(int(k) for k in ko)
+        left += len(prev - now)
+        reentered += len((now - prev) & seen)
+        seen |= now
+        prev = now
+    print(f"multi-launch contacts: {len(seen)} pairs touched, {left} separations, {reentered} re-entries")
+    assert left > 0 and len(seen) > 50
+
+
 @pytest.mark.parametrize("kind", ["fast", "dense_slow"])
 def test_fused_dem_list_reuse(ps, oracle_mod, kind):
     """The single-workgroup DEM keeps the pair list while no particle changes
