@@ -1110,6 +1110,8 @@ __global__ void k_predict_keep(DemArgs A, double dt, int write_kin, int par) {
     GRID_LOOP(k, A.p.np) predict_keep_one(A, (int)k, dt, write_kin, par);
 }
 
+#define SUM_CHUNK 8
+
 // The DEM sums of a substep, its corrector and the next substep's predictor,
 // one thread per particle: the sums take the particle's column (pairs (k, i),
 // ascending k), then its row, pairs in contact only, in the order of
@@ -1127,22 +1129,41 @@ __global__ __launch_bounds__(256) void k_sum_correct_predict(DemArgs A, PairBufs
         long long s1 = B.prow[i + 1];
         s1 = s1 < cap ? s1 : cap;
         double F[3] = {0.0, 0.0, 0.0}, M[3] = {0.0, 0.0, 0.0};
-        for (long long u = c0; u < c1; ++u) {
-            const long long s = A.col_list[u];
-            if (!(A.incontact[s] & 1)) continue;
+        // entries in chunks of SUM_CHUNK: the chunk's pair indices and contact
+        // flags are loaded together, then the pairs in contact are added in
+        // entry order (a flag per iteration would wait on each load in turn)
+        for (long long u0 = c0; u0 < c1; u0 += SUM_CHUNK) {
+            int sidx[SUM_CHUNK];
+            unsigned char fl[SUM_CHUNK];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                F[c] -= A.cF[3 * s + c];
-                M[c] += A.cMj[3 * s + c];
-            }
+            for (int q = 0; q < SUM_CHUNK; ++q) sidx[q] = u0 + q < c1 ? A.col_list[u0 + q] : -1;
+#pragma unroll
+            for (int q = 0; q < SUM_CHUNK; ++q) fl[q] = sidx[q] >= 0 ? A.incontact[sidx[q]] : (unsigned char)0;
+#pragma unroll
+            for (int q = 0; q < SUM_CHUNK; ++q)
+                if (fl[q] & 1) {
+                    const long long s = sidx[q];
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        F[c] -= A.cF[3 * s + c];
+                        M[c] += A.cMj[3 * s + c];
+                    }
+                }
         }
-        for (long long s = s0; s < s1; ++s) {
-            if (!(A.incontact[s] & 1)) continue;
+        for (long long t0 = s0; t0 < s1; t0 += SUM_CHUNK) {
+            unsigned char fl[SUM_CHUNK];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                F[c] += A.cF[3 * s + c];
-                M[c] += A.cMi[3 * s + c];
-            }
+            for (int q = 0; q < SUM_CHUNK; ++q) fl[q] = t0 + q < s1 ? A.incontact[t0 + q] : (unsigned char)0;
+#pragma unroll
+            for (int q = 0; q < SUM_CHUNK; ++q)
+                if (fl[q] & 1) {
+                    const long long s = t0 + q;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        F[c] += A.cF[3 * s + c];
+                        M[c] += A.cMi[3 * s + c];
+                    }
+                }
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
