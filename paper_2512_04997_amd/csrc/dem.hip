@@ -364,7 +364,14 @@ __device__ void ellipsoid_pair(const DemArgs& A, int i, int j, Geom& G) {
 // lanes branch on is formed from the same operands in the same order on both,
 // so the two take each branch together and each exchange finds its partner
 // active; the results are those of ellipsoid_pair, operation for operation.
-__device__ inline double lane_swap(double v) { return __shfl_xor(v, 1, 64); }
+// the partner lane's value (lanes 2k and 2k + 1 swap) by a DPP quad permutation
+// [1, 0, 3, 2]: a register move, no LDS round trip.  Both lanes of a pair are
+// always active together (they take the same branches).
+__device__ inline int lane_swap_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true); }
+__device__ inline double lane_swap(double v) {
+    const int lo = lane_swap_i(__double2loint(v)), hi = lane_swap_i(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
 
 __device__ void ellipsoid_pair2(const DemArgs& A, int i, int j, int side, Geom& G) {
     const double* ci = A.p.pos + 3 * i;
@@ -404,7 +411,7 @@ __device__ void ellipsoid_pair2(const DemArgs& A, int i, int j, int side, Geom& 
         for (int k = 0; k < 3; ++k) u[k] *= il;
         double np_[3];
         const int hit = ell_line_hit(c, E, sc, u, side == 0, np_) ? 1 : 0;
-        const int hit_o = __shfl_xor(hit, 1, 64);
+        const int hit_o = lane_swap_i(hit);
         if (!(hit && hit_o)) break;
         double dp[3] = {np_[0] - p[0], np_[1] - p[1], np_[2] - p[2]};
         const double m = sqrt(dot3(dp, dp));
