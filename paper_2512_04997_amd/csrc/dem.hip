@@ -220,6 +220,8 @@ __device__ inline double rsq_nr(double x) {
     y = y * (1.5 - h * y * y);
     return y;
 }
+// sqrt(x) for x >= 0 from the same estimate (0 at 0)
+__device__ inline double sqrt_nr(double x) { return x > 0.0 ? x * rsq_nr(x) : 0.0; }
 __device__ inline double rcp_nr(double x) {
 #pragma clang fp contract(fast)
     double y = __builtin_amdgcn_rcp(x);
@@ -280,7 +282,7 @@ __device__ bool ell_line_hit(const double* c, const EllShape& E, const double* s
     }
     double disc = qb * qb - qa * qc;
     if (disc < 0.0 || qa <= 0.0) return false;
-    double sq = sqrt(disc);
+    double sq = sqrt_nr(disc);
     double t = (far_positive ? -qb + sq : -qb - sq) * rcp_nr(qa);
     for (int k = 0; k < 3; ++k) p[k] = s[k] + t * u[k];
     return true;
@@ -334,7 +336,7 @@ __device__ void ellipsoid_pair(const DemArgs& A, int i, int j, Geom& G) {
         if (!ell_line_hit(cj, Ej, sj, u, false, npj)) break;
         double dpi[3] = {npi[0] - pi[0], npi[1] - pi[1], npi[2] - pi[2]};
         double dpj[3] = {npj[0] - pj[0], npj[1] - pj[1], npj[2] - pj[2]};
-        double conv = sqrt(dot3(dpi, dpi)) + sqrt(dot3(dpj, dpj));
+        double conv = sqrt_nr(dot3(dpi, dpi)) + sqrt_nr(dot3(dpj, dpj));
         for (int k = 0; k < 3; ++k) {
             pi[k] = npi[k];
             pj[k] = npj[k];
@@ -414,7 +416,7 @@ __device__ void ellipsoid_pair2(const DemArgs& A, int i, int j, int side, Geom& 
         const int hit_o = lane_swap_i(hit);
         if (!(hit && hit_o)) break;
         double dp[3] = {np_[0] - p[0], np_[1] - p[1], np_[2] - p[2]};
-        const double m = sqrt(dot3(dp, dp));
+        const double m = sqrt_nr(dot3(dp, dp));
         const double mo = lane_swap(m);
         const double conv = side ? mo + m : m + mo;
         for (int k = 0; k < 3; ++k) p[k] = np_[k];
