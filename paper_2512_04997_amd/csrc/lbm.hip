@@ -68,6 +68,16 @@ struct Conv<_Float16, float> {
     __device__ static _Float16 st(float v) { return (_Float16)v; }
 };
 
+
+// streaming stores and loads of populations (each is touched once per pass)
+template <typename S>
+__device__ inline void st_nt(S* p, S v) { __builtin_nontemporal_store(v, p); }
+template <>
+__device__ inline void st_nt<bf16_t>(bf16_t* p, bf16_t v) { __builtin_nontemporal_store(v.u, &p->u); }
+template <typename S>
+__device__ inline S ld_nt(const S* p) { return __builtin_nontemporal_load(p); }
+template <>
+__device__ inline bf16_t ld_nt<bf16_t>(const bf16_t* p) { bf16_t r; r.u = __builtin_nontemporal_load(&p->u); return r; }
 // ---------------------------------------------------------------------------
 // collision of one cell in shifted form (g = f - w), compute type C
 // ---------------------------------------------------------------------------
@@ -249,7 +259,7 @@ template <typename S, typename C, bool ODD, int I>
 __device__ inline void load_dir(const LbmArgs& A, const S* f, long long N, long long cell, const AxisNb& ax,
                                 const AxisNb& ay, const AxisNb& az, C* g) {
     if (!ODD) {
-        g[I] = Conv<S, C>::ld(f[(long long)I * N + cell]);
+        g[I] = Conv<S, C>::ld(ld_nt(&f[(long long)I * N + cell]));
     } else {
         int face;
         const int o = dir_off<-d3q19_cx(I), -d3q19_cy(I), -d3q19_cz(I)>(ax, ay, az, &face);
@@ -262,12 +272,12 @@ template <typename S, typename C, bool ODD, int I>
 __device__ inline void store_dir(const LbmArgs& A, S* f, long long N, long long cell, const AxisNb& ax,
                                  const AxisNb& ay, const AxisNb& az, const C* out) {
     if (!ODD) {
-        f[(long long)d3q19_opp(I) * N + cell] = Conv<S, C>::st(out[I]);
+        st_nt(&f[(long long)d3q19_opp(I) * N + cell], Conv<S, C>::st(out[I]));
     } else {
         int face;
         const int o = dir_off<d3q19_cx(I), d3q19_cy(I), d3q19_cz(I)>(ax, ay, az, &face);
-        if (face >= 0) f[(long long)d3q19_opp(I) * N + cell] = Conv<S, C>::st(out[I] - (C)A.wall_corr[face * 19 + I]);
-        else f[(long long)I * N + cell + o] = Conv<S, C>::st(out[I]);
+        if (face >= 0) st_nt(&f[(long long)d3q19_opp(I) * N + cell], Conv<S, C>::st(out[I] - (C)A.wall_corr[face * 19 + I]));
+        else st_nt(&f[(long long)I * N + cell + o], Conv<S, C>::st(out[I]));
     }
 }
 
@@ -319,7 +329,7 @@ __device__ inline void load_plain(const LbmArgs& A, const S* f, long long N, uns
                                   const AxisNb& ay, const AxisNb& az, C* g) {
     constexpr unsigned sz = sizeof(S);
     if (!ODD) {
-        g[I] = Conv<S, C>::ld(*plane_ptr(f, N, I, cell * sz));
+        g[I] = Conv<S, C>::ld(ld_nt(plane_ptr(f, N, I, cell * sz)));
     } else {
         constexpr int cx = d3q19_cx(I);
         const int o = plain_off<-d3q19_cx(I), -d3q19_cy(I), -d3q19_cz(I)>(ax, ay, az);
@@ -338,16 +348,16 @@ __device__ inline void store_plain(const LbmArgs& A, S* f, long long N, unsigned
                                    const AxisNb& ay, const AxisNb& az, const C* out) {
     constexpr unsigned sz = sizeof(S);
     if (!ODD) {
-        *plane_ptr(f, N, d3q19_opp(I), cell * sz) = Conv<S, C>::st(out[I]);
+        st_nt(plane_ptr(f, N, d3q19_opp(I), cell * sz), Conv<S, C>::st(out[I]));
     } else {
         constexpr int cx = d3q19_cx(I);
         const int o = plain_off<d3q19_cx(I), d3q19_cy(I), d3q19_cz(I)>(ax, ay, az);
         const bool xw = XW && ((cx < 0 && ax.wl) || (cx > 0 && ax.wh));
         if (XW && cx != 0 && xw) {
             const int face = cx < 0 ? 0 : 1;
-            *plane_ptr(f, N, d3q19_opp(I), cell * sz) = Conv<S, C>::st(out[I] - (C)A.wall_corr[face * 19 + I]);
+            st_nt(plane_ptr(f, N, d3q19_opp(I), cell * sz), Conv<S, C>::st(out[I] - (C)A.wall_corr[face * 19 + I]));
         } else {
-            *plane_ptr(f, N, I, (unsigned)((int)cell + o) * sz) = Conv<S, C>::st(out[I]);
+            st_nt(plane_ptr(f, N, I, (unsigned)((int)cell + o) * sz), Conv<S, C>::st(out[I]));
         }
     }
 }
