@@ -78,6 +78,18 @@ template <typename S>
 __device__ inline S ld_nt(const S* p) { return __builtin_nontemporal_load(p); }
 template <>
 __device__ inline bf16_t ld_nt<bf16_t>(const bf16_t* p) { bf16_t r; r.u = __builtin_nontemporal_load(&p->u); return r; }
+// NT: streaming form (lattices whose population array exceeds the last-level
+// cache), else ordinary accesses (smaller lattices stay cached between passes)
+template <bool NT, typename S>
+__device__ inline void st_pop(S* p, S v) {
+    if constexpr (NT) st_nt(p, v);
+    else *p = v;
+}
+template <bool NT, typename S>
+__device__ inline S ld_pop(const S* p) {
+    if constexpr (NT) return ld_nt(p);
+    else return *p;
+}
 // ---------------------------------------------------------------------------
 // collision of one cell in shifted form (g = f - w), compute type C
 // ---------------------------------------------------------------------------
@@ -255,11 +267,11 @@ __device__ inline int dir_off(const AxisNb& ax, const AxisNb& ay, const AxisNb& 
     return o;
 }
 
-template <typename S, typename C, bool ODD, int I>
+template <typename S, typename C, bool ODD, bool NT, int I>
 __device__ inline void load_dir(const LbmArgs& A, const S* f, long long N, long long cell, const AxisNb& ax,
                                 const AxisNb& ay, const AxisNb& az, C* g) {
     if (!ODD) {
-        g[I] = Conv<S, C>::ld(ld_nt(&f[(long long)I * N + cell]));
+        g[I] = Conv<S, C>::ld(ld_pop<NT>(&f[(long long)I * N + cell]));
     } else {
         int face;
         const int o = dir_off<-d3q19_cx(I), -d3q19_cy(I), -d3q19_cz(I)>(ax, ay, az, &face);
@@ -268,29 +280,29 @@ __device__ inline void load_dir(const LbmArgs& A, const S* f, long long N, long 
     }
 }
 
-template <typename S, typename C, bool ODD, int I>
+template <typename S, typename C, bool ODD, bool NT, int I>
 __device__ inline void store_dir(const LbmArgs& A, S* f, long long N, long long cell, const AxisNb& ax,
                                  const AxisNb& ay, const AxisNb& az, const C* out) {
     if (!ODD) {
-        st_nt(&f[(long long)d3q19_opp(I) * N + cell], Conv<S, C>::st(out[I]));
+        st_pop<NT>(&f[(long long)d3q19_opp(I) * N + cell], Conv<S, C>::st(out[I]));
     } else {
         int face;
         const int o = dir_off<d3q19_cx(I), d3q19_cy(I), d3q19_cz(I)>(ax, ay, az, &face);
-        if (face >= 0) st_nt(&f[(long long)d3q19_opp(I) * N + cell], Conv<S, C>::st(out[I] - (C)A.wall_corr[face * 19 + I]));
-        else st_nt(&f[(long long)I * N + cell + o], Conv<S, C>::st(out[I]));
+        if (face >= 0) st_pop<NT>(&f[(long long)d3q19_opp(I) * N + cell], Conv<S, C>::st(out[I] - (C)A.wall_corr[face * 19 + I]));
+        else st_pop<NT>(&f[(long long)I * N + cell + o], Conv<S, C>::st(out[I]));
     }
 }
 
-template <typename S, typename C, bool ODD, int... Is>
+template <typename S, typename C, bool ODD, bool NT, int... Is>
 __device__ inline void load_all(const LbmArgs& A, const S* f, long long N, long long cell, const AxisNb& ax,
                                 const AxisNb& ay, const AxisNb& az, C* g, std::integer_sequence<int, Is...>) {
-    (load_dir<S, C, ODD, Is>(A, f, N, cell, ax, ay, az, g), ...);
+    (load_dir<S, C, ODD, NT, Is>(A, f, N, cell, ax, ay, az, g), ...);
 }
 
-template <typename S, typename C, bool ODD, int... Is>
+template <typename S, typename C, bool ODD, bool NT, int... Is>
 __device__ inline void store_all(const LbmArgs& A, S* f, long long N, long long cell, const AxisNb& ax,
                                  const AxisNb& ay, const AxisNb& az, const C* out, std::integer_sequence<int, Is...>) {
-    (store_dir<S, C, ODD, Is>(A, f, N, cell, ax, ay, az, out), ...);
+    (store_dir<S, C, ODD, NT, Is>(A, f, N, cell, ax, ay, az, out), ...);
 }
 
 // Rows whose links cross no wall (every row of a periodic domain, and all but
@@ -324,12 +336,12 @@ __device__ inline int plain_off(const AxisNb& ax, const AxisNb& ay, const AxisNb
 // moving-wall term (faces 0 and 1 are the only ones such a row can cross).
 // Waves with no lane at an x wall take XW = false and keep one unconditional
 // access per direction.
-template <typename S, typename C, bool ODD, bool XW, int I>
+template <typename S, typename C, bool ODD, bool XW, bool NT, int I>
 __device__ inline void load_plain(const LbmArgs& A, const S* f, long long N, unsigned cell, const AxisNb& ax,
                                   const AxisNb& ay, const AxisNb& az, C* g) {
     constexpr unsigned sz = sizeof(S);
     if (!ODD) {
-        g[I] = Conv<S, C>::ld(ld_nt(plane_ptr(f, N, I, cell * sz)));
+        g[I] = Conv<S, C>::ld(ld_pop<NT>(plane_ptr(f, N, I, cell * sz)));
     } else {
         constexpr int cx = d3q19_cx(I);
         const int o = plain_off<-d3q19_cx(I), -d3q19_cy(I), -d3q19_cz(I)>(ax, ay, az);
@@ -343,36 +355,36 @@ __device__ inline void load_plain(const LbmArgs& A, const S* f, long long N, uns
     }
 }
 
-template <typename S, typename C, bool ODD, bool XW, int I>
+template <typename S, typename C, bool ODD, bool XW, bool NT, int I>
 __device__ inline void store_plain(const LbmArgs& A, S* f, long long N, unsigned cell, const AxisNb& ax,
                                    const AxisNb& ay, const AxisNb& az, const C* out) {
     constexpr unsigned sz = sizeof(S);
     if (!ODD) {
-        st_nt(plane_ptr(f, N, d3q19_opp(I), cell * sz), Conv<S, C>::st(out[I]));
+        st_pop<NT>(plane_ptr(f, N, d3q19_opp(I), cell * sz), Conv<S, C>::st(out[I]));
     } else {
         constexpr int cx = d3q19_cx(I);
         const int o = plain_off<d3q19_cx(I), d3q19_cy(I), d3q19_cz(I)>(ax, ay, az);
         const bool xw = XW && ((cx < 0 && ax.wl) || (cx > 0 && ax.wh));
         if (XW && cx != 0 && xw) {
             const int face = cx < 0 ? 0 : 1;
-            st_nt(plane_ptr(f, N, d3q19_opp(I), cell * sz), Conv<S, C>::st(out[I] - (C)A.wall_corr[face * 19 + I]));
+            st_pop<NT>(plane_ptr(f, N, d3q19_opp(I), cell * sz), Conv<S, C>::st(out[I] - (C)A.wall_corr[face * 19 + I]));
         } else {
-            st_nt(plane_ptr(f, N, I, (unsigned)((int)cell + o) * sz), Conv<S, C>::st(out[I]));
+            st_pop<NT>(plane_ptr(f, N, I, (unsigned)((int)cell + o) * sz), Conv<S, C>::st(out[I]));
         }
     }
 }
 
-template <typename S, typename C, bool ODD, bool XW, int... Is>
+template <typename S, typename C, bool ODD, bool XW, bool NT, int... Is>
 __device__ inline void load_all_plain(const LbmArgs& A, const S* f, long long N, unsigned cell, const AxisNb& ax,
                                       const AxisNb& ay, const AxisNb& az, C* g, std::integer_sequence<int, Is...>) {
-    (load_plain<S, C, ODD, XW, Is>(A, f, N, cell, ax, ay, az, g), ...);
+    (load_plain<S, C, ODD, XW, NT, Is>(A, f, N, cell, ax, ay, az, g), ...);
 }
 
-template <typename S, typename C, bool ODD, bool XW, int... Is>
+template <typename S, typename C, bool ODD, bool XW, bool NT, int... Is>
 __device__ inline void store_all_plain(const LbmArgs& A, S* f, long long N, unsigned cell, const AxisNb& ax,
                                        const AxisNb& ay, const AxisNb& az, const C* out,
                                        std::integer_sequence<int, Is...>) {
-    (store_plain<S, C, ODD, XW, Is>(A, f, N, cell, ax, ay, az, out), ...);
+    (store_plain<S, C, ODD, XW, NT, Is>(A, f, N, cell, ax, ay, az, out), ...);
 }
 
 __device__ inline unsigned long long ballot64(bool p) { return __ballot(p); }
@@ -410,7 +422,7 @@ __device__ inline void wave_add_by_id(bool has, int my, const double* P, const d
 
 // MS = 0: tiles without registered particles; MS > 0: tiles with particles
 // one tile of one domain (the body shared by the single-domain and the batched kernels)
-template <typename S, typename C, bool ODD, int MS>
+template <typename S, typename C, bool ODD, int MS, bool NT>
 __device__ void lbm_tile(const LbmArgs& A, const long long t, double* kin_s, double* acc) {
     const long long ntiles = A.g.ntiles;
     long long s0 = A.t.tile_start[t], s1 = A.t.tile_start[t + 1];
@@ -481,22 +493,22 @@ __device__ void lbm_tile(const LbmArgs& A, const long long t, double* kin_s, dou
             C Braw[MS > 0 ? MS : 1];
             const long long sl = t * (long long)PSM_TILE + lane + PSM_TX * (wid + PSM_TY * lz);
             if (MS > 0) {
-                lp = A.t.slot_lp[sl];
+                lp = ld_pop<NT>(&A.t.slot_lp[sl]);
 #pragma unroll
-                for (int k = 0; k < MS; ++k) Braw[k] = k < A.ms ? Bslot[k * plane + sl] : (C)0;
+                for (int k = 0; k < MS; ++k) Braw[k] = k < A.ms ? ld_pop<NT>(&Bslot[k * plane + sl]) : (C)0;
             }
             const AxisNb az = axis_nb(z, A.g.nz, A.g.periodic[2], A.g.nx * A.g.ny);
             const long long cell = (long long)x + (long long)A.g.nx * ((long long)y + (long long)A.g.ny * z);
             C g[19], out[19];
             const bool plain = row_plain && !az.wl && !az.wh;
             if (plain && !row_xw)
-                load_all_plain<S, C, ODD, false>(A, f, N, (unsigned)cell, ax, ay, az, g,
+                load_all_plain<S, C, ODD, false, NT>(A, f, N, (unsigned)cell, ax, ay, az, g,
                                                  std::make_integer_sequence<int, 19>{});
             else if (plain)
-                load_all_plain<S, C, ODD, true>(A, f, N, (unsigned)cell, ax, ay, az, g,
+                load_all_plain<S, C, ODD, true, NT>(A, f, N, (unsigned)cell, ax, ay, az, g,
                                                 std::make_integer_sequence<int, 19>{});
             else
-                load_all<S, C, ODD>(A, f, N, cell, ax, ay, az, g, std::make_integer_sequence<int, 19>{});
+                load_all<S, C, ODD, NT>(A, f, N, cell, ax, ay, az, g, std::make_integer_sequence<int, 19>{});
             C Fx = (C)0, Fy = (C)0, Fz = (C)0;
             if (forcing) {
                 Fx = (C)A.F[0];
@@ -541,13 +553,13 @@ __device__ void lbm_tile(const LbmArgs& A, const long long t, double* kin_s, dou
             const C rho = collide<C, MS>(g, out, omega, omega_m, forcing, Fx, Fy, Fz, nk, B, uk, Pk);
             bad = bad || !(rho > (C)0 && rho < (C)1e30);
             if (plain && !row_xw)
-                store_all_plain<S, C, ODD, false>(A, f, N, (unsigned)cell, ax, ay, az, out,
+                store_all_plain<S, C, ODD, false, NT>(A, f, N, (unsigned)cell, ax, ay, az, out,
                                                   std::make_integer_sequence<int, 19>{});
             else if (plain)
-                store_all_plain<S, C, ODD, true>(A, f, N, (unsigned)cell, ax, ay, az, out,
+                store_all_plain<S, C, ODD, true, NT>(A, f, N, (unsigned)cell, ax, ay, az, out,
                                                  std::make_integer_sequence<int, 19>{});
             else
-                store_all<S, C, ODD>(A, f, N, cell, ax, ay, az, out, std::make_integer_sequence<int, 19>{});
+                store_all<S, C, ODD, NT>(A, f, N, cell, ax, ay, az, out, std::make_integer_sequence<int, 19>{});
         }
         if (MS > 0) {
             // per-particle momentum exchange of this plane: wave sums into LDS
@@ -626,20 +638,20 @@ struct LbmMinBlocks {
     static constexpr int value = (MS == 2 && !ODD && (sizeof(S) == 2 || sizeof(S) == 4)) ? 4 : 1;
 };
 
-template <typename S, typename C, bool ODD, int MS>
+template <typename S, typename C, bool ODD, int MS, bool NT>
 __global__ __launch_bounds__(256, (LbmMinBlocks<S, ODD, MS>::value)) void k_lbm(LbmArgs A) {
     __shared__ double kin_s[MS > 0 ? PSM_PMAX * 9 : 1];
     __shared__ double acc[MS > 0 ? 4 * PSM_PMAX * 6 : 1];
     const long long t = xcd_block(A.g.ntiles);
     if (t >= A.g.ntiles) return;
-    lbm_tile<S, C, ODD, MS>(A, t, kin_s, acc);
+    lbm_tile<S, C, ODD, MS, NT>(A, t, kin_s, acc);
 }
 
 // Both tile kinds in one launch: the branch is uniform over the workgroup (a
 // tile's registration count decides it), so a pass is one kernel and the few
 // particle-free tiles of a dense suspension share the rounds of the PSM tiles
 // instead of a launch of their own.
-template <typename S, typename C, bool ODD, int MS>
+template <typename S, typename C, bool ODD, int MS, bool NT>
 __global__ __launch_bounds__(256, (LbmMinBlocks<S, ODD, MS>::value)) void k_lbm_mixed(LbmArgs A) {
     __shared__ double kin_s[PSM_PMAX * 9];
     __shared__ double acc[4 * PSM_PMAX * 6];
@@ -648,8 +660,8 @@ __global__ __launch_bounds__(256, (LbmMinBlocks<S, ODD, MS>::value)) void k_lbm_
     const long long s0 = A.t.tile_start[t];
     long long s1 = A.t.tile_start[t + 1];
     if (s1 > A.t.cap) s1 = A.t.cap;
-    if (s1 > s0) lbm_tile<S, C, ODD, MS>(A, t, kin_s, acc);
-    else lbm_tile<S, C, ODD, 0>(A, t, kin_s, acc);
+    if (s1 > s0) lbm_tile<S, C, ODD, MS, NT>(A, t, kin_s, acc);
+    else lbm_tile<S, C, ODD, 0, NT>(A, t, kin_s, acc);
 }
 
 // many domains in one launch: map[b] = (job, tile), the job's parity in dyn.odd
@@ -661,8 +673,8 @@ __global__ __launch_bounds__(256) void k_lbm_batch(const LbmArgs* __restrict__ j
     const long long b = xcd_block(nmap);
     if (b >= nmap) return;
     const int2 m = map[b];
-    if (srv_bit(dyn.odd, m.x)) lbm_tile<S, C, true, MS>(jobs[m.x], m.y, kin_s, acc);
-    else lbm_tile<S, C, false, MS>(jobs[m.x], m.y, kin_s, acc);
+    if (srv_bit(dyn.odd, m.x)) lbm_tile<S, C, true, MS, false>(jobs[m.x], m.y, kin_s, acc);
+    else lbm_tile<S, C, false, MS, false>(jobs[m.x], m.y, kin_s, acc);
 }
 
 template <typename S, typename C>
@@ -675,23 +687,37 @@ hipError_t launch_batch(const LbmArgs* jobs, const SrvDyn& dyn, const int2* map,
     return hipGetLastError();
 }
 
-template <typename S, typename C>
-hipError_t launch_step(const LbmArgs& A, int odd, hipStream_t s) {
-    const unsigned nblk = (unsigned)(8 * ((A.g.ntiles + 7) / 8));
+template <typename S, typename C, bool NT>
+void launch_pass(const LbmArgs& A, int odd, unsigned nblk, hipStream_t s) {
     // without particles no tile holds a registration: the PSM launch is skipped
     // (two slots: one launch for both tile kinds; four slots keep two launches,
     // whose PSM kernel alone already fills the register file)
     const bool psm = A.np > 0;
     if (psm && A.ms <= 2) {
-        if (odd) k_lbm_mixed<S, C, true, 2><<<nblk, 256, 0, s>>>(A);
-        else k_lbm_mixed<S, C, false, 2><<<nblk, 256, 0, s>>>(A);
+        if (odd) k_lbm_mixed<S, C, true, 2, NT><<<nblk, 256, 0, s>>>(A);
+        else k_lbm_mixed<S, C, false, 2, NT><<<nblk, 256, 0, s>>>(A);
     } else if (odd) {
-        k_lbm<S, C, true, 0><<<nblk, 256, 0, s>>>(A);
-        if (psm) k_lbm<S, C, true, 4><<<nblk, 256, 0, s>>>(A);
+        k_lbm<S, C, true, 0, NT><<<nblk, 256, 0, s>>>(A);
+        if (psm) k_lbm<S, C, true, 4, NT><<<nblk, 256, 0, s>>>(A);
     } else {
-        k_lbm<S, C, false, 0><<<nblk, 256, 0, s>>>(A);
-        if (psm) k_lbm<S, C, false, 4><<<nblk, 256, 0, s>>>(A);
+        k_lbm<S, C, false, 0, NT><<<nblk, 256, 0, s>>>(A);
+        if (psm) k_lbm<S, C, false, 4, NT><<<nblk, 256, 0, s>>>(A);
     }
+}
+
+// Streaming accesses pay where the population array does not stay in the
+// last-level cache (256 MB) from one pass to the next anyway, and where every
+// wave's 64-cell row covers whole lines of 4- or 8-byte populations (x extent
+// a multiple of 64); on rows that straddle lines, or with 2-byte populations,
+// the streamed partial lines measured slower than ordinary accesses.
+#define LBM_STREAM_BYTES (192ll << 20)
+
+template <typename S, typename C>
+hipError_t launch_step(const LbmArgs& A, int odd, hipStream_t s) {
+    const unsigned nblk = (unsigned)(8 * ((A.g.ntiles + 7) / 8));
+    const bool stream = 19ll * A.g.N * (long long)sizeof(S) > LBM_STREAM_BYTES && A.g.nx % 64 == 0 && sizeof(S) >= 4;
+    if (stream) launch_pass<S, C, true>(A, odd, nblk, s);
+    else launch_pass<S, C, false>(A, odd, nblk, s);
     return hipGetLastError();
 }
 
