@@ -1,18 +1,22 @@
 // dem.hip -- DEM substep kernels (FP64).  Compiled with -ffp-contract=off so
-// that the predicates deciding integer results (cell indices, contact flags)
-// use separately rounded operations in a fixed order.
+// that the predicates deciding integer results (cell indices, pair lists) use
+// separately rounded operations in a fixed order; only the ellipsoid
+// iteration's helpers, an approximation refined to a tolerance, contract
+// multiply-adds and use refined hardware reciprocal estimates.
 //
 // A substep (Sec. 3.2.1-3.2.2, Table 1), as per-index phases:
 //   predict      Verlet predictor of position and orientation (Eqs. advance-r ...)
 //                and the particle's DEM cells per axis (box of the particle)
 //   cell list    counting sort of (cell, pid) registrations: histogram, scan,
-//                scatter, per-cell order by pid
+//                scatter (each cell's list in arrival order; ordered by pid only
+//                for a read-back)
 //   pairs        per particle i the unique j > i sharing a cell (each j counted in
 //                the lowest shared cell), then wall candidates; rows emitted and
 //                ordered in place, so the list is sorted and unique without a
 //                global sort
 //   contacts     spring-dashpot + Coulomb per pair, history by binary search in the
-//                previous sorted list
+//                previous sorted list (at the pair's own index on a kept list;
+//                pairs out of contact at their last two evaluations write nothing)
 //   sums         per particle: pairs where it is the second member (counting-sorted
 //                columns, ascending pair index) then its own row, a fixed order
 //   correct      Verlet corrector
