@@ -350,7 +350,10 @@ __device__ inline void load_plain(const LbmArgs& A, const S* f, long long N, uns
             const int face = cx > 0 ? 0 : 1;
             g[I] = Conv<S, C>::ld(*plane_ptr(f, N, I, cell * sz)) + (C)A.wall_corr[face * 19 + I];
         } else {
-            g[I] = Conv<S, C>::ld(*plane_ptr(f, N, d3q19_opp(I), (unsigned)((int)cell + o) * sz));
+            // links without an x component read whole lines of another row:
+            // streamed like the even pass; the x-shifted ones share their
+            // boundary lines with the neighbouring waves and stay ordinary
+            g[I] = Conv<S, C>::ld(ld_pop<NT && cx == 0>(plane_ptr(f, N, d3q19_opp(I), (unsigned)((int)cell + o) * sz)));
         }
     }
 }
