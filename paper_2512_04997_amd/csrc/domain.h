@@ -217,6 +217,9 @@ struct psmdem_domain {
         A.vpart = vpart;
         A.btab = btab;
         A.betatab = betatab;
+        // the LBM pass's rule for streaming accesses (large lattices with line-aligned rows)
+        const long long sb = prec == 0 ? 8 : (prec == 1 ? 4 : 2);
+        A.stream = 19ll * N * sb > (192ll << 20) && geo.nx % 64 == 0 && sb >= 4;
         A.ctr = ctr;
         return A;
     }

@@ -24,6 +24,8 @@ struct VoxArgs {
     const void* btab;            // [ns^3 + 1] subdivision method: B of each inside-sample count, in the
                                  // compute type, and beta (betatab); null: formed per slot
     const double* betatab;
+    int stream;                  // store the slots with streaming stores (lattices that take the
+                                 // LBM pass's streaming accesses: beyond the last-level cache)
     DevCounters* ctr;
 };
 

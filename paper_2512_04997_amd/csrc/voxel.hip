@@ -1288,13 +1288,15 @@ __device__ inline void select_counts(const VoxArgs& A, const SelPart* sp, long l
 #pragma unroll
         for (int q = 0; q < 4; ++q)
             if (q < nk) lp = (lp & ~(0xffu << (8 * q))) | ((o[q] >> 16) << (8 * q));
-        __builtin_nontemporal_store(lp, &A.t.slot_lp[cell]);  // streamed: the LBM pass reads each once
+        if (A.stream) __builtin_nontemporal_store(lp, &A.t.slot_lp[cell]);  // the LBM pass reads each once
+        else A.t.slot_lp[cell] = lp;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
             if (q < nk) {
                 const unsigned n = o[q] & 0xffffu;
                 if (A.btab) {
-                    __builtin_nontemporal_store(((const C*)A.btab)[n], &Bout[q * plane + cell]);
+                    if (A.stream) __builtin_nontemporal_store(((const C*)A.btab)[n], &Bout[q * plane + cell]);
+                    else Bout[q * plane + cell] = ((const C*)A.btab)[n];
                     if (A.t.slot_beta) A.t.slot_beta[q * plane + cell] = A.betatab[n];
                 } else {
                     const double beta = (double)n / n3;
