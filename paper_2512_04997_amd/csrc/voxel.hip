@@ -1170,10 +1170,27 @@ __global__ __launch_bounds__(VOX_T) void k_vox_rows(VoxArgs A) {
                         i1 = max(i1, ghi[b] / NS);
                     }
                 }
-                for (int i = i0; i <= i1; ++i) {
-                    int n = 0;
+                // the per-cell sum over the rows on packed 16-bit lanes (two rows
+                // per operation; sample indices stay below 2^15)
+                typedef short s2_t __attribute__((ext_vector_type(2)));
+                s2_t lo2[NS > 1 ? NS / 2 : 1], hi2[NS > 1 ? NS / 2 : 1];
 #pragma unroll
-                    for (int b = 0; b < NS; ++b) n += range_in_cell(glo[b], ghi[b], i, NS);
+                for (int b = 0; b < NS / 2; ++b) {
+                    lo2[b] = s2_t{(short)glo[2 * b], (short)glo[2 * b + 1]};
+                    hi2[b] = s2_t{(short)ghi[2 * b], (short)ghi[2 * b + 1]};
+                }
+                for (int i = i0; i <= i1; ++i) {
+                    const short a0 = (short)(i * NS), a1 = (short)(i * NS + NS - 1);
+                    const s2_t va0 = s2_t{a0, a0}, va1 = s2_t{a1, a1}, one = s2_t{1, 1}, zero = s2_t{0, 0};
+                    s2_t acc = zero;
+#pragma unroll
+                    for (int b = 0; b < NS / 2; ++b) {
+                        const s2_t m = __builtin_elementwise_min(hi2[b], va1) - __builtin_elementwise_max(lo2[b], va0) + one;
+                        acc += __builtin_elementwise_max(m, zero);
+                    }
+                    int n = (int)acc.x + (int)acc.y;
+#pragma unroll
+                    for (int b = 2 * (NS / 2); b < NS; ++b) n += range_in_cell(glo[b], ghi[b], i, NS);
                     if (n) atomicAdd(&row[i], n);
                 }
             } else {
